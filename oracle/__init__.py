@@ -1,0 +1,239 @@
+"""CPU oracle for the sparse-grid hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's
+``cpu_baseline`` leg may import this package.  It never imports the product
+package and the product never imports it.
+
+Two independent implementations live here:
+
+* ``OracleGrid`` -- ctypes wrapper over ``oracle.c``: a plain single-threaded
+  C implementation of the sparse-grid semantics (root table + block pool,
+  activation on write with zero fill, ascending list generation, struct-fors
+  over the list, 7-point stencils, PIC particle transfers, the diffusion step
+  and its hand-derived adjoint), built for fp32 and for fp64.
+* ``oracle.dense`` -- a NumPy dense-array implementation for tiny grids, used
+  to pin the C oracle's sparse machinery.
+
+What pins each function (tests/test_oracle_pins.py):
+
+* activate, listgen -- brute-force mask scans, idempotence, the union
+  invariant, whole-block activation (Fig. 3), the restriction pattern.
+* lap_update, axpy, jacobi, copy, fill, inc, diffuse, diffuse_adj -- the
+  dense implementation (bit-exact in fp32 and fp64), plus closed forms:
+  inactive-neighbour counts, exactness on polynomials of degree <= 2,
+  Jacobi eigenmodes, a direct Poisson solve, linear-field diffusion fluxes.
+* diffuse_adj -- dot-product identities in a and k, and central finite
+  differences of a multi-step loss.
+* p2g, normalise, g2p -- B-spline moment identities, mass and momentum
+  conservation, the on-node (1/8, 3/4, 1/8) stencil, affine reproduction by
+  the gather, and the dense implementation.
+
+Every function has at least one such pin; none is "parity unpinned".
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_LIBS = {}
+_DTYPES = {"f32": np.float32, "f64": np.float64}
+_CREAL = {"f32": ctypes.c_float, "f64": ctypes.c_double}
+
+
+def _lib(prec: str):
+    if prec in _LIBS:
+        return _LIBS[prec]
+    if not _build.built():
+        _build.build()
+    L = ctypes.CDLL(_build.LIBS[prec])
+    R = _CREAL[prec]
+    P = ctypes.c_void_p
+    i32, i64 = ctypes.c_int, ctypes.c_int64
+    sig = {
+        "og_create": (P, [i32, i32]),
+        "og_destroy": (None, [P]),
+        "og_root_edge": (i32, [P]),
+        "og_num_slots": (i64, [P]),
+        "og_is_active": (i32, [P, i32, i32, i32]),
+        "og_activate": (i64, [P, P, i64, i32]),
+        "og_listgen": (i64, [P]),
+        "og_active_cells": (i64, [P, P]),
+        "og_get_list": (i64, [P, P]),
+        "og_read": (R, [P, i32, i32, i32, i32]),
+        "og_read_block": (None, [P, i32, ctypes.c_int32, P]),
+        "og_write_block": (None, [P, i32, ctypes.c_int32, P]),
+        "og_lap_update": (None, [P, i32, i32, R]),
+        "og_axpy": (None, [P, i32, i32, R]),
+        "og_jacobi": (None, [P, i32, i32, i32]),
+        "og_copy": (None, [P, i32, i32]),
+        "og_fill": (None, [P, i32, R]),
+        "og_inc": (None, [P, i32, R]),
+        "og_diffuse": (None, [P, i32, i32, i32, R]),
+        "og_diffuse_adj": (None, [P, i32, i32, i32, i32, i32, R]),
+        "og_advect": (None, [P, P, i64, R]),
+        "og_p2g": (i64, [P, i32, i32, i32, P, P, P, i64, R]),
+        "og_normalise": (None, [P, i32, i32, i32]),
+        "og_g2p": (None, [P, i32, P, P, i64, R]),
+        "og_bspline": (i32, [R, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIBS[prec] = L
+    return L
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def bspline_weights(X: float, precision: str = "f32"):
+    """(base, [w0, w1, w2]) of the quadratic B-spline at grid coordinate X."""
+    dt = _DTYPES[precision]
+    w = np.zeros(3, dtype=dt)
+    base = _lib(precision).og_bspline(dt(X), _ptr(w))
+    return base, w
+
+
+def advect(x: np.ndarray, v: np.ndarray, dt: float, precision: str = "f32") -> np.ndarray:
+    """Return x + dt * v (SoA [3, np]) computed by the oracle."""
+    d = _DTYPES[precision]
+    xo = np.ascontiguousarray(x, dtype=d).copy()
+    vv = np.ascontiguousarray(v, dtype=d)
+    _lib(precision).og_advect(_ptr(xo), _ptr(vv), xo.shape[1], d(dt))
+    return xo
+
+
+class OracleGrid:
+    """A sparse grid of ``n^3`` voxels (root of (n/8)^3 cells over 8^3 blocks)
+    with ``channels`` value channels, in fp32 or fp64."""
+
+    def __init__(self, n: int, channels: int, precision: str = "f32"):
+        self.n, self.channels, self.precision = n, channels, precision
+        self.R = n // 8
+        self.dtype = _DTYPES[precision]
+        self._L = _lib(precision)
+        self._g = self._L.og_create(n, channels)
+        if not self._g:
+            raise ValueError("invalid oracle grid shape")
+
+    def __del__(self):
+        g, self._g = getattr(self, "_g", None), None
+        if g:
+            self._L.og_destroy(g)
+
+    # -- activation, lists, masks -------------------------------------------
+    def activate(self, coords, kind: str = "block") -> int:
+        c = np.ascontiguousarray(np.asarray(coords, dtype=np.int32).reshape(-1, 3))
+        return int(self._L.og_activate(self._g, _ptr(c), c.shape[0], 0 if kind == "voxel" else 1))
+
+    def listgen(self) -> int:
+        return int(self._L.og_listgen(self._g))
+
+    def list(self) -> np.ndarray:
+        out = np.zeros(self.R ** 3, dtype=np.int32)
+        cnt = self._L.og_get_list(self._g, _ptr(out))
+        return out[:cnt].copy()
+
+    def active_cells(self) -> np.ndarray:
+        out = np.zeros(self.R ** 3, dtype=np.int32)
+        cnt = self._L.og_active_cells(self._g, _ptr(out))
+        return out[:cnt].copy()
+
+    def is_active(self, bi: int, bj: int, bk: int) -> bool:
+        return bool(self._L.og_is_active(self._g, bi, bj, bk))
+
+    @property
+    def num_slots(self) -> int:
+        return int(self._L.og_num_slots(self._g))
+
+    # -- values -----------------------------------------------------------------
+    def read(self, ch: int, i: int, j: int, k: int) -> float:
+        return float(self._L.og_read(self._g, ch, i, j, k))
+
+    def read_blocks(self, ch: int, cells) -> np.ndarray:
+        cells = np.asarray(cells, dtype=np.int32)
+        out = np.zeros((cells.shape[0], 512), dtype=self.dtype)
+        buf = np.zeros(512, dtype=self.dtype)
+        for t, c in enumerate(cells):
+            self._L.og_read_block(self._g, ch, int(c), _ptr(buf))
+            out[t] = buf
+        return out
+
+    def write_blocks(self, ch: int, cells, values) -> None:
+        cells = np.asarray(cells, dtype=np.int32)
+        vals = np.ascontiguousarray(values, dtype=self.dtype).reshape(cells.shape[0], 512)
+        for t, c in enumerate(cells):
+            row = np.ascontiguousarray(vals[t])
+            self._L.og_write_block(self._g, ch, int(c), _ptr(row))
+
+    def to_dense(self, ch: int) -> np.ndarray:
+        """Dense (n, n, n) copy of channel ``ch`` (zeros where inactive)."""
+        out = np.zeros((self.n,) * 3, dtype=self.dtype)
+        cells = self.active_cells()
+        vals = self.read_blocks(ch, cells)
+        R = self.R
+        for t, c in enumerate(cells):
+            bi, bj, bk = c // (R * R), (c // R) % R, c % R
+            out[bi * 8:bi * 8 + 8, bj * 8:bj * 8 + 8, bk * 8:bk * 8 + 8] = vals[t].reshape(8, 8, 8)
+        return out
+
+    # -- struct-for tasks over the current list ------------------------------
+    def lap_update(self, ch_a: int, ch_out: int, coef: float = 0.1):
+        self._L.og_lap_update(self._g, ch_a, ch_out, self.dtype(coef))
+
+    def axpy(self, ch_y: int, ch_x: int, alpha: float):
+        self._L.og_axpy(self._g, ch_y, ch_x, self.dtype(alpha))
+
+    def jacobi(self, ch_x: int, ch_b: int, ch_xn: int):
+        self._L.og_jacobi(self._g, ch_x, ch_b, ch_xn)
+
+    def copy(self, ch_dst: int, ch_src: int):
+        self._L.og_copy(self._g, ch_dst, ch_src)
+
+    def fill(self, ch: int, value: float):
+        self._L.og_fill(self._g, ch, self.dtype(value))
+
+    def inc(self, ch: int, value: float):
+        self._L.og_inc(self._g, ch, self.dtype(value))
+
+    def diffuse(self, ch_a: int, ch_k: int, ch_out: int, dt: float):
+        self._L.og_diffuse(self._g, ch_a, ch_k, ch_out, self.dtype(dt))
+
+    def diffuse_adj(self, ch_a: int, ch_k: int, ch_lamn: int, ch_lam: int, ch_gk: int, dt: float):
+        self._L.og_diffuse_adj(self._g, ch_a, ch_k, ch_lamn, ch_lam, ch_gk, self.dtype(dt))
+
+    # -- particles ------------------------------------------------------------
+    def p2g(self, ch_m: int, ch_mv: int, x, v, m, inv_dx: float, ch_abs: int = -1) -> int:
+        d = self.dtype
+        xx = np.ascontiguousarray(x, dtype=d)
+        vv = np.ascontiguousarray(v, dtype=d)
+        mm = np.ascontiguousarray(m, dtype=d)
+        return int(self._L.og_p2g(self._g, ch_m, ch_mv, ch_abs, _ptr(xx), _ptr(vv), _ptr(mm),
+                                  mm.shape[0], d(inv_dx)))
+
+    def normalise(self, ch_m: int, ch_mv: int, ch_v: int):
+        self._L.og_normalise(self._g, ch_m, ch_mv, ch_v)
+
+    def g2p(self, ch_v: int, x, inv_dx: float) -> np.ndarray:
+        d = self.dtype
+        xx = np.ascontiguousarray(x, dtype=d)
+        out = np.zeros_like(xx)
+        self._L.og_g2p(self._g, ch_v, _ptr(xx), _ptr(out), xx.shape[1], d(inv_dx))
+        return out
+
+    # -- convenience ----------------------------------------------------------
+    def load(self, blocks, channel_values: dict, channel_index: dict) -> None:
+        """Activate ``blocks`` (block coordinates, in order) and store the
+        given per-block values into the named channels."""
+        self.activate(blocks, "block")
+        R = self.R
+        b = np.asarray(blocks, dtype=np.int64)
+        cells = ((b[:, 0] * R + b[:, 1]) * R + b[:, 2]).astype(np.int32)
+        for name, vals in channel_values.items():
+            self.write_blocks(channel_index[name], cells, vals)

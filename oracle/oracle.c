@@ -1,0 +1,424 @@
+/*
+ * CPU oracle for the sparse-grid hot path -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+ * load this library.  It shares no code with the HIP path: its data structure
+ * (a root table of int32 slot indices over a growable pool of 8^3 blocks) and
+ * every loop here are written independently, straight from the paper's
+ * definitions, single-threaded and in program order.
+ *
+ * Semantics followed (paper, Section 3 "Spatially sparse programming" and
+ * Section 4 "States"):
+ *   - the domain is a root of R^3 cells over dense 8^3 leaf blocks; a block is
+ *     active or not as a whole (dense leaves are all-or-nothing, Fig. 3);
+ *   - every voxel has a value; an inactive voxel (and, by our reading, a voxel
+ *     outside the domain) reads as the ambient value 0;
+ *   - activation on write: activating an inactive block zero-fills it;
+ *     activating an active block changes nothing;
+ *   - list generation: the list of active root cells, consumed by struct-fors.
+ *     The oracle emits it in ascending linear root index;
+ *   - a struct-for visits every voxel of every listed block.
+ *
+ * Arithmetic is done in REAL (float or double, chosen at compile time) in the
+ * exact operation order documented on each function, built with
+ * -ffp-contract=off so no fused multiply-add changes the rounding.
+ * Particle-to-grid transfer accumulates in double regardless of REAL and can
+ * also return, per node and channel, the sum of absolute terms (the bound a
+ * summation-order error is measured against).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef REAL
+#define REAL float
+#endif
+
+#define BS 8
+#define BV 512
+
+typedef struct {
+    int n;            /* domain edge in voxels */
+    int R;            /* root edge in blocks */
+    int channels;
+    int64_t ncells;   /* R^3 */
+    int32_t *root;    /* slot of each root cell, -1 when inactive */
+    int64_t nslots;   /* slots in use */
+    int64_t capslots; /* slots allocated */
+    REAL **pool;      /* per channel: capslots * 512 values */
+    int32_t *list;    /* list state: active root cells */
+    int64_t count;    /* list length */
+} og_grid;
+
+/* ------------------------------------------------------------------ grid */
+
+og_grid *og_create(int n, int channels) {
+    if (n <= 0 || n % BS != 0 || channels <= 0) return NULL;
+    og_grid *g = (og_grid *)calloc(1, sizeof(og_grid));
+    g->n = n;
+    g->R = n / BS;
+    g->channels = channels;
+    g->ncells = (int64_t)g->R * g->R * g->R;
+    g->root = (int32_t *)malloc(sizeof(int32_t) * g->ncells);
+    for (int64_t c = 0; c < g->ncells; ++c) g->root[c] = -1;
+    g->list = (int32_t *)malloc(sizeof(int32_t) * g->ncells);
+    g->count = 0;
+    g->capslots = 16;
+    g->nslots = 0;
+    g->pool = (REAL **)calloc(channels, sizeof(REAL *));
+    for (int ch = 0; ch < channels; ++ch)
+        g->pool[ch] = (REAL *)calloc((size_t)g->capslots * BV, sizeof(REAL));
+    return g;
+}
+
+void og_destroy(og_grid *g) {
+    if (!g) return;
+    for (int ch = 0; ch < g->channels; ++ch) free(g->pool[ch]);
+    free(g->pool);
+    free(g->root);
+    free(g->list);
+    free(g);
+}
+
+int og_root_edge(const og_grid *g) { return g->R; }
+int64_t og_num_slots(const og_grid *g) { return g->nslots; }
+
+static int64_t cell_of_block(const og_grid *g, int bi, int bj, int bk) {
+    return ((int64_t)bi * g->R + bj) * g->R + bk;
+}
+
+static int block_in_domain(const og_grid *g, int bi, int bj, int bk) {
+    return bi >= 0 && bj >= 0 && bk >= 0 && bi < g->R && bj < g->R && bk < g->R;
+}
+
+/* Activate one block: if it is inactive, give it a fresh slot and zero every
+ * channel of that slot; otherwise nothing happens. */
+static void activate_block(og_grid *g, int bi, int bj, int bk) {
+    int64_t c = cell_of_block(g, bi, bj, bk);
+    if (g->root[c] >= 0) return;
+    if (g->nslots == g->capslots) {
+        int64_t ncap = g->capslots * 2;
+        for (int ch = 0; ch < g->channels; ++ch) {
+            g->pool[ch] = (REAL *)realloc(g->pool[ch], sizeof(REAL) * (size_t)ncap * BV);
+        }
+        g->capslots = ncap;
+    }
+    int64_t s = g->nslots++;
+    for (int ch = 0; ch < g->channels; ++ch)
+        for (int v = 0; v < BV; ++v) g->pool[ch][s * BV + v] = (REAL)0;
+    g->root[c] = (int32_t)s;
+}
+
+int og_is_active(const og_grid *g, int bi, int bj, int bk) {
+    if (!block_in_domain(g, bi, bj, bk)) return 0;
+    return g->root[cell_of_block(g, bi, bj, bk)] >= 0;
+}
+
+/* Activate coordinates in the given order.  coord_kind 0: voxel (i, j, k),
+ * whose block is activated; 1: block (bi, bj, bk).  Returns the number of
+ * coordinates that fell outside the domain (those are ignored). */
+int64_t og_activate(og_grid *g, const int32_t *ijk, int64_t n, int coord_kind) {
+    int64_t bad = 0;
+    for (int64_t t = 0; t < n; ++t) {
+        int a = ijk[3 * t], b = ijk[3 * t + 1], c = ijk[3 * t + 2];
+        if (coord_kind == 0) {
+            if (a < 0 || b < 0 || c < 0 || a >= g->n || b >= g->n || c >= g->n) { ++bad; continue; }
+            a /= BS; b /= BS; c /= BS;
+        } else if (!block_in_domain(g, a, b, c)) { ++bad; continue; }
+        activate_block(g, a, b, c);
+    }
+    return bad;
+}
+
+/* List generation: every active root cell, ascending linear index. */
+int64_t og_listgen(og_grid *g) {
+    int64_t cnt = 0;
+    for (int64_t c = 0; c < g->ncells; ++c)
+        if (g->root[c] >= 0) g->list[cnt++] = (int32_t)c;
+    g->count = cnt;
+    return cnt;
+}
+
+/* Active root cells read from the mask (ascending), without touching the
+ * list state. */
+int64_t og_active_cells(const og_grid *g, int32_t *out) {
+    int64_t cnt = 0;
+    for (int64_t c = 0; c < g->ncells; ++c)
+        if (g->root[c] >= 0) out[cnt++] = (int32_t)c;
+    return cnt;
+}
+
+int64_t og_get_list(const og_grid *g, int32_t *out) {
+    memcpy(out, g->list, sizeof(int32_t) * (size_t)g->count);
+    return g->count;
+}
+
+/* Value read with sparse semantics: 0 outside the domain or in an inactive
+ * block. */
+static REAL rd(const og_grid *g, int ch, int i, int j, int k) {
+    if (i < 0 || j < 0 || k < 0 || i >= g->n || j >= g->n || k >= g->n) return (REAL)0;
+    int32_t s = g->root[cell_of_block(g, i / BS, j / BS, k / BS)];
+    if (s < 0) return (REAL)0;
+    return g->pool[ch][(int64_t)s * BV + (i % BS) * 64 + (j % BS) * 8 + (k % BS)];
+}
+
+/* Activating write (activation on write). */
+static void wr(og_grid *g, int ch, int i, int j, int k, REAL v) {
+    activate_block(g, i / BS, j / BS, k / BS);
+    int32_t s = g->root[cell_of_block(g, i / BS, j / BS, k / BS)];
+    g->pool[ch][(int64_t)s * BV + (i % BS) * 64 + (j % BS) * 8 + (k % BS)] = v;
+}
+
+REAL og_read(const og_grid *g, int ch, int i, int j, int k) { return rd(g, ch, i, j, k); }
+
+/* Copy the 512 values of root cell `cell` (zeros if inactive). */
+void og_read_block(const og_grid *g, int ch, int32_t cell, REAL *out) {
+    int32_t s = (cell >= 0 && cell < g->ncells) ? g->root[cell] : -1;
+    for (int v = 0; v < BV; ++v) out[v] = s < 0 ? (REAL)0 : g->pool[ch][(int64_t)s * BV + v];
+}
+
+/* Store 512 values into root cell `cell`, activating it first. */
+void og_write_block(og_grid *g, int ch, int32_t cell, const REAL *vals) {
+    int bi = (int)(cell / ((int64_t)g->R * g->R)), bj = (int)((cell / g->R) % g->R), bk = (int)(cell % g->R);
+    activate_block(g, bi, bj, bk);
+    int32_t s = g->root[cell];
+    for (int v = 0; v < BV; ++v) g->pool[ch][(int64_t)s * BV + v] = vals[v];
+}
+
+/* ------------------------------------------------ struct-for over the list */
+
+/* Voxel coordinates of local voxel v of listed root cell `cell`. */
+#define FOR_EACH_LISTED_VOXEL(g, ...)                                               \
+    for (int64_t e = 0; e < (g)->count; ++e) {                                      \
+        int64_t cell_ = (g)->list[e];                                               \
+        int bi_ = (int)(cell_ / ((int64_t)(g)->R * (g)->R));                        \
+        int bj_ = (int)((cell_ / (g)->R) % (g)->R);                                 \
+        int bk_ = (int)(cell_ % (g)->R);                                            \
+        for (int li = 0; li < BS; ++li)                                             \
+            for (int lj = 0; lj < BS; ++lj)                                         \
+                for (int lk = 0; lk < BS; ++lk) {                                   \
+                    int i = bi_ * BS + li, j = bj_ * BS + lj, k = bk_ * BS + lk;    \
+                    __VA_ARGS__                                                     \
+                }                                                                   \
+    }
+
+/* Sum of the six face neighbours, in the fixed order
+ * ((((x[i-1] + x[i+1]) + x[j-1]) + x[j+1]) + x[k-1]) + x[k+1]. */
+static REAL nbsum(const og_grid *g, int ch, int i, int j, int k) {
+    REAL s = rd(g, ch, i - 1, j, k) + rd(g, ch, i + 1, j, k);
+    s = s + rd(g, ch, i, j - 1, k);
+    s = s + rd(g, ch, i, j + 1, k);
+    s = s + rd(g, ch, i, j, k - 1);
+    s = s + rd(g, ch, i, j, k + 1);
+    return s;
+}
+
+/* out = a + coef * (s - 6 a): explicit step of the 7-point Laplacian in grid
+ * units (h = 1). */
+void og_lap_update(og_grid *g, int ch_a, int ch_out, REAL coef) {
+    FOR_EACH_LISTED_VOXEL(g, {
+        REAL a = rd(g, ch_a, i, j, k);
+        REAL s = nbsum(g, ch_a, i, j, k);
+        REAL six_a = (REAL)6 * a;
+        REAL d = s - six_a;
+        REAL t = coef * d;
+        wr(g, ch_out, i, j, k, a + t);
+    })
+}
+
+/* y = y + alpha * x */
+void og_axpy(og_grid *g, int ch_y, int ch_x, REAL alpha) {
+    FOR_EACH_LISTED_VOXEL(g, {
+        REAL y = rd(g, ch_y, i, j, k);
+        REAL t = alpha * rd(g, ch_x, i, j, k);
+        wr(g, ch_y, i, j, k, y + t);
+    })
+}
+
+/* One Jacobi sweep for -lap(x) = b in grid units: xn = (s + b) * fp(1/6). */
+void og_jacobi(og_grid *g, int ch_x, int ch_b, int ch_xn) {
+    const REAL sixth = (REAL)(1.0 / 6.0);
+    FOR_EACH_LISTED_VOXEL(g, {
+        REAL s = nbsum(g, ch_x, i, j, k);
+        REAL b = rd(g, ch_b, i, j, k);
+        REAL t = s + b;
+        wr(g, ch_xn, i, j, k, t * sixth);
+    })
+}
+
+/* dst = src */
+void og_copy(og_grid *g, int ch_dst, int ch_src) {
+    FOR_EACH_LISTED_VOXEL(g, { wr(g, ch_dst, i, j, k, rd(g, ch_src, i, j, k)); })
+}
+
+/* x = value */
+void og_fill(og_grid *g, int ch, REAL value) {
+    FOR_EACH_LISTED_VOXEL(g, { wr(g, ch, i, j, k, value); })
+}
+
+/* x = x + value */
+void og_inc(og_grid *g, int ch, REAL value) {
+    FOR_EACH_LISTED_VOXEL(g, { wr(g, ch, i, j, k, rd(g, ch, i, j, k) + value); })
+}
+
+/* Explicit diffusion step with face conductance kf = (k + k_nb) / 2:
+ *   f = sum over faces (fixed order) of kf * (a_nb - a);  out = a + dt * f.
+ * Reads of inactive neighbours (a_nb, k_nb) give 0. */
+void og_diffuse(og_grid *g, int ch_a, int ch_k, int ch_out, REAL dt) {
+    static const int off[6][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+    FOR_EACH_LISTED_VOXEL(g, {
+        REAL a = rd(g, ch_a, i, j, k);
+        REAL kc = rd(g, ch_k, i, j, k);
+        REAL f = (REAL)0;
+        for (int q = 0; q < 6; ++q) {
+            int ii = i + off[q][0], jj = j + off[q][1], kk = k + off[q][2];
+            REAL kf = (REAL)0.5 * (kc + rd(g, ch_k, ii, jj, kk));
+            f = f + kf * (rd(g, ch_a, ii, jj, kk) - a);
+        }
+        wr(g, ch_out, i, j, k, a + dt * f);
+    })
+}
+
+/* Reverse-mode step of og_diffuse.  With lam' the adjoint of the step's
+ * output and a, k its inputs:
+ *   lam[i]  = lam'[i] + dt * sum_faces kf * (lam'[nb] - lam'[i])
+ *   gk[i]  += (dt * 0.5) * sum_faces (a[nb] - a[i]) * (lam'[i] - lam'[nb])
+ * (the operator is self-adjoint; inactive neighbours read 0). */
+void og_diffuse_adj(og_grid *g, int ch_a, int ch_k, int ch_lamn, int ch_lam, int ch_gk, REAL dt) {
+    static const int off[6][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+    FOR_EACH_LISTED_VOXEL(g, {
+        REAL l = rd(g, ch_lamn, i, j, k);
+        REAL a = rd(g, ch_a, i, j, k);
+        REAL kc = rd(g, ch_k, i, j, k);
+        REAL f = (REAL)0, q2 = (REAL)0;
+        for (int q = 0; q < 6; ++q) {
+            int ii = i + off[q][0], jj = j + off[q][1], kk = k + off[q][2];
+            REAL ln = rd(g, ch_lamn, ii, jj, kk);
+            REAL kf = (REAL)0.5 * (kc + rd(g, ch_k, ii, jj, kk));
+            f = f + kf * (ln - l);
+            q2 = q2 + (rd(g, ch_a, ii, jj, kk) - a) * (l - ln);
+        }
+        wr(g, ch_lam, i, j, k, l + dt * f);
+        REAL gk = rd(g, ch_gk, i, j, k);
+        wr(g, ch_gk, i, j, k, gk + (dt * (REAL)0.5) * q2);
+    })
+}
+
+/* ----------------------------------------------------------- particles */
+
+/* x += dt * v, component by component (SoA: x[c*np + p]). */
+void og_advect(REAL *x, const REAL *v, int64_t np, REAL dt) {
+    for (int c = 0; c < 3; ++c)
+        for (int64_t p = 0; p < np; ++p) x[c * np + p] = x[c * np + p] + dt * v[c * np + p];
+}
+
+/* Quadratic B-spline weights of one axis: base = floor(X - 1/2),
+ * fx = X - base, w = (0.5 (1.5 - fx)^2, 0.75 - (fx - 1)^2, 0.5 (fx - 0.5)^2). */
+static int bspline(REAL X, REAL w[3]) {
+    int base = (int)floor((double)(X - (REAL)0.5));
+    REAL fx = X - (REAL)base;
+    REAL t0 = (REAL)1.5 - fx, t1 = fx - (REAL)1, t2 = fx - (REAL)0.5;
+    w[0] = (REAL)0.5 * (t0 * t0);
+    w[1] = (REAL)0.75 - t1 * t1;
+    w[2] = (REAL)0.5 * (t2 * t2);
+    return base;
+}
+
+/* Particle-to-grid transfer of mass and momentum (PIC), particles in id
+ * order, the 27 nodes of each in (x, y, z) lexicographic order.  Each node's
+ * block is activated on write.  Node weight w = (wx * wy) * wz; terms
+ * w * m_p and (w * m_p) * v_p are formed in REAL and summed in double onto the current grid
+ * values.  When ch_abs >= 0, channels ch_abs .. ch_abs+3 receive the sum of
+ * |term| for m, mv0, mv1, mv2 (added to their current contents).
+ * Returns the number of node writes that fell outside the domain (skipped). */
+int64_t og_p2g(og_grid *g, int ch_m, int ch_mv, int ch_abs, const REAL *x, const REAL *v,
+               const REAL *m, int64_t np, REAL inv_dx) {
+    int64_t bad = 0;
+    /* pass 1: activation, in exactly the order the writes happen */
+    for (int64_t p = 0; p < np; ++p) {
+        REAL w[3][3];
+        int base[3];
+        for (int c = 0; c < 3; ++c) base[c] = bspline(x[c * np + p] * inv_dx, w[c]);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                for (int d = 0; d < 3; ++d) {
+                    int i = base[0] + a, j = base[1] + b, k = base[2] + d;
+                    if (i < 0 || j < 0 || k < 0 || i >= g->n || j >= g->n || k >= g->n) { ++bad; continue; }
+                    activate_block(g, i / BS, j / BS, k / BS);
+                }
+    }
+    /* pass 2: accumulate in double */
+    int nacc = ch_abs >= 0 ? 8 : 4;
+    size_t len = (size_t)g->nslots * BV;
+    double *acc = (double *)malloc(sizeof(double) * len * nacc);
+    for (int q = 0; q < 4; ++q) {
+        int ch = q == 0 ? ch_m : ch_mv + q - 1;
+        for (size_t t = 0; t < len; ++t) acc[q * len + t] = (double)g->pool[ch][t];
+        if (ch_abs >= 0)
+            for (size_t t = 0; t < len; ++t) acc[(4 + q) * len + t] = (double)g->pool[ch_abs + q][t];
+    }
+    for (int64_t p = 0; p < np; ++p) {
+        REAL w[3][3];
+        int base[3];
+        for (int c = 0; c < 3; ++c) base[c] = bspline(x[c * np + p] * inv_dx, w[c]);
+        REAL vp[3] = {v[p], v[np + p], v[2 * np + p]};
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                for (int d = 0; d < 3; ++d) {
+                    int i = base[0] + a, j = base[1] + b, k = base[2] + d;
+                    if (i < 0 || j < 0 || k < 0 || i >= g->n || j >= g->n || k >= g->n) continue;
+                    int32_t s = g->root[cell_of_block(g, i / BS, j / BS, k / BS)];
+                    size_t at = (size_t)s * BV + (i % BS) * 64 + (j % BS) * 8 + (k % BS);
+                    REAL wt = (w[0][a] * w[1][b]) * w[2][d];
+                    REAL term[4];
+                    term[0] = wt * m[p];
+                    for (int c = 0; c < 3; ++c) term[1 + c] = term[0] * vp[c];
+                    for (int q = 0; q < 4; ++q) {
+                        acc[q * len + at] += (double)term[q];
+                        if (ch_abs >= 0) acc[(4 + q) * len + at] += fabs((double)term[q]);
+                    }
+                }
+    }
+    for (int q = 0; q < 4; ++q) {
+        int ch = q == 0 ? ch_m : ch_mv + q - 1;
+        for (size_t t = 0; t < len; ++t) g->pool[ch][t] = (REAL)acc[q * len + t];
+        if (ch_abs >= 0)
+            for (size_t t = 0; t < len; ++t) g->pool[ch_abs + q][t] = (REAL)acc[(4 + q) * len + t];
+    }
+    free(acc);
+    return bad;
+}
+
+/* Grid velocity from momentum over the list: v = m > 0 ? mv / m : 0. */
+void og_normalise(og_grid *g, int ch_m, int ch_mv, int ch_v) {
+    FOR_EACH_LISTED_VOXEL(g, {
+        REAL mm = rd(g, ch_m, i, j, k);
+        for (int c = 0; c < 3; ++c) {
+            REAL r = mm > (REAL)0 ? rd(g, ch_mv + c, i, j, k) / mm : (REAL)0;
+            wr(g, ch_v + c, i, j, k, r);
+        }
+    })
+}
+
+/* Grid-to-particle gather of velocity: v_p = sum over the 27 nodes (same
+ * order as og_p2g) of w * v_node, accumulated in REAL starting from 0. */
+void og_g2p(const og_grid *g, int ch_v, const REAL *x, REAL *vout, int64_t np, REAL inv_dx) {
+    for (int64_t p = 0; p < np; ++p) {
+        REAL w[3][3];
+        int base[3];
+        for (int c = 0; c < 3; ++c) base[c] = bspline(x[c * np + p] * inv_dx, w[c]);
+        REAL acc[3] = {(REAL)0, (REAL)0, (REAL)0};
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                for (int d = 0; d < 3; ++d) {
+                    int i = base[0] + a, j = base[1] + b, k = base[2] + d;
+                    REAL wt = (w[0][a] * w[1][b]) * w[2][d];
+                    for (int c = 0; c < 3; ++c) acc[c] = acc[c] + wt * rd(g, ch_v + c, i, j, k);
+                }
+        for (int c = 0; c < 3; ++c) vout[c * np + p] = acc[c];
+    }
+}
+
+/* B-spline weights of one coordinate, exposed for the pins. */
+int og_bspline(REAL X, REAL *w3) { return bspline(X, w3); }
