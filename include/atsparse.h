@@ -1,0 +1,314 @@
+/*
+ * atsparse -- sparse-grid kernels with an inter-kernel optimizer, for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library implements the data-parallel hot path of the method of
+ * "AsyncTaichi: On-the-fly Inter-kernel Optimizations for Imperative and
+ * Spatially Sparse Programming" (Hu, Xu, Kuang, Durand; arXiv 2012.08141):
+ * a spatially sparse grid (a bitmasked or pointer root over dense 8^3 fp32
+ * leaf blocks, paper Section 3), the tasks that run on it (activation, list
+ * generation, struct-for stencils, particle scatter and gather), and an
+ * engine that runs a sequence of such tasks either eagerly or after the
+ * paper's inter-kernel optimizations on a state-flow graph (Sections 4-7):
+ * list generation removal, activation demotion, task fusion and dead store
+ * elimination.
+ *
+ * Conventions for every entry point
+ *   - Nothing throws across this interface.  Every call returns an
+ *     at_status; on failure at_last_error() gives a message (thread-local,
+ *     valid until the next failing call on the same thread).
+ *   - An invalid argument returns AT_E_INVALID and enqueues no device work.
+ *   - Device work is asynchronous on the hipStream_t passed in; the caller
+ *     keeps every buffer alive until that work has completed.
+ *   - The library never allocates device memory: the caller allocates each
+ *     grid's buffer (size from at_grid_footprint) and every external array.
+ *   - Layouts: a leaf block holds 512 fp32 values, voxel (i, j, k) of the
+ *     block (local coordinates 0..7) at offset i*64 + j*8 + k.  Channels are
+ *     stored structure-of-arrays: one array of capacity_blocks * 512 floats
+ *     per channel.  The linear index of root cell (bi, bj, bk) is
+ *     (bi*R + bj)*R + bk with R = n/8.  Particle arrays are SoA: x[3][np]
+ *     (component c of particle p at c*np + p), v[3][np], m[np].
+ *   - A grid handle is not thread-safe; the engine serialises its own state
+ *     with a lock, so distinct handles may be used from distinct threads.
+ */
+#ifndef ATSPARSE_H
+#define ATSPARSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+typedef int32_t at_status;
+#define AT_OK             0
+#define AT_E_INVALID     -1   /* bad argument; nothing was enqueued */
+#define AT_E_CAPACITY    -2   /* a grid's block pool ran out (sticky, see at_device_status) */
+#define AT_E_HIP         -3   /* a HIP call failed; at_last_error() has its text */
+#define AT_E_UNSUPPORTED -4   /* valid request this build does not implement */
+#define AT_E_STATE       -5   /* call not allowed in the handle's current state */
+
+/* ------------------------------------------------------------------- grids */
+typedef struct at_grid_s *at_grid;
+
+#define AT_ROOT_BITMASK 0   /* bitmasked root; every leaf preallocated, slot = cell */
+#define AT_ROOT_POINTER 1   /* pointer root over a pool of capacity_blocks leaves */
+
+typedef struct at_grid_desc {
+    int32_t n[3];             /* domain edge in voxels per axis; multiples of 8, all equal */
+    int32_t root_kind;        /* AT_ROOT_BITMASK or AT_ROOT_POINTER */
+    int32_t channels;         /* fp32 value channels, 1..64 */
+    int32_t capacity_blocks;  /* pointer root: pool size in leaves (<= R^3);
+                                 bitmask root: ignored (R^3) */
+} at_grid_desc;
+
+/* Bytes of device memory a grid with this description needs.  Host only.
+ * (Section 3, "Spatially sparse programming": root, leaves, list.) */
+at_status at_grid_footprint(const at_grid_desc *desc, size_t *bytes);
+
+/* Create a grid in the caller's device buffer `dev_buf` of `bytes` bytes
+ * (>= at_grid_footprint, 256-byte aligned).  Enqueues the buffer's
+ * initialisation on `stream`: every block inactive, every value 0, empty
+ * list.  The buffer stays owned by the caller and must outlive the handle.
+ *
+ * dev_buf == NULL (bytes ignored) creates a *planning handle*: it has no
+ * device memory; at_run_sequence / at_plan_sequence accept it and plan and
+ * record engine state for it but launch nothing, and every other call that
+ * would touch device memory returns AT_E_STATE. */
+at_status at_grid_create(const at_grid_desc *desc, void *dev_buf, size_t bytes,
+                         hipStream_t stream, at_grid *out);
+
+/* Release the host handle (the device buffer is the caller's).  Forgets the
+ * engine's state-flow information for this grid. */
+at_status at_grid_destroy(at_grid grid);
+
+/* Device pointers into the grid's buffer.  ch_base[c] (array of `channels`
+ * entries, may be NULL) receives the base of channel c (capacity_blocks*512
+ * floats, indexed by slot*512 + voxel).  *list receives the list state
+ * (int32 root cells, capacity min(R^3, capacity_blocks)), *count its int32
+ * length, *root the root table (bitmask root: uint32[ceil(R^3/32)] bits;
+ * pointer root: int32[R^3] slot or -1).  Any out-pointer may be NULL. */
+at_status at_grid_views(at_grid grid, float **ch_base, const int32_t **list,
+                        const int32_t **count, const void **root);
+
+typedef struct at_grid_info {
+    int32_t n, R, root_kind, channels, capacity_blocks, list_capacity;
+    int64_t ncells;           /* R^3 */
+    size_t bytes;             /* footprint */
+} at_grid_info;
+at_status at_grid_get_info(at_grid grid, at_grid_info *info);
+
+/* Deactivate every block: root emptied, used leaves zeroed, list emptied,
+ * pool reset.  A deactivating write to the mask state (Section 4). */
+at_status at_grid_clear(at_grid grid, hipStream_t stream);
+
+/* Sticky device-side error bits of a grid, read synchronously on `stream`
+ * (waits for the stream).  bit 0: the pointer pool overflowed
+ * (AT_E_CAPACITY); bit 1: an allocation wait exceeded its spin limit.
+ * Returns AT_OK and stores the bits; `clear` != 0 also resets them. */
+at_status at_device_status(at_grid grid, hipStream_t stream, int32_t clear, int32_t *bits);
+
+/* Number of active blocks (popcount of the mask), read synchronously. */
+at_status at_active_count(at_grid grid, hipStream_t stream, int64_t *count);
+
+/* -------------------------------------------------------- immediate tasks
+ * Each call below runs one task eagerly (optimizer off) through the engine,
+ * so the engine's state versions stay exact for later optimized windows. */
+
+#define AT_COORD_VOXEL 0
+#define AT_COORD_BLOCK 1
+
+/* Activation on write (Section 3, item 3; Fig. 3): for each of the n
+ * coordinates (device int32 [n][3]) activate the containing block.  A newly
+ * activated block reads 0 in every channel; an active block is unchanged.
+ * Coordinates outside the domain are ignored. */
+at_status at_activate(at_grid grid, const int32_t *d_ijk, int64_t n, int32_t coord_kind,
+                      hipStream_t stream);
+
+/* List generation (Section 3, item 2): write the grid's list state -- the
+ * active root cells in ascending linear order -- and its device count.  The
+ * list-clearing step is folded in (one dispatch). */
+at_status at_listgen(at_grid grid, hipStream_t stream);
+
+/* Struct-for operators over the grid's current list (Section 3, item 1).
+ * Every voxel of every listed block is updated.  Neighbour reads outside
+ * the domain or in inactive blocks give 0.  All arithmetic is fp32,
+ * round-to-nearest, without contraction, in the order given:
+ *   s = ((((x[i-1] + x[i+1]) + x[j-1]) + x[j+1]) + x[k-1]) + x[k+1]      */
+#define AT_OP_LAP_UPDATE  1  /* ch {a, out}; p {coef}: out = a + coef*(s(a) - 6*a)        */
+#define AT_OP_AXPY        2  /* ch {y, x};   p {alpha}: y = y + alpha*x                    */
+#define AT_OP_JACOBI      3  /* ch {x, b, xn}: xn = (s(x) + b) * fp32(1/6)                 */
+#define AT_OP_COPY        4  /* ch {dst, src}: dst = src                                   */
+#define AT_OP_FILL        5  /* ch {c0, c1, ... , -1} (up to 7); p {value}: c = value       */
+#define AT_OP_INC         6  /* ch {x}; p {value}: x = x + value                           */
+#define AT_OP_DIFFUSE     7  /* ch {a, k, out}; p {dt}: per face q (same order as s),
+                                kf = 0.5*(k + k_q); f = f + kf*(a_q - a); out = a + dt*f   */
+#define AT_OP_DIFFUSE_ADJ 8  /* ch {a, k, lamn, lam, gk}; p {dt}: adjoint of DIFFUSE:
+                                f = f + kf*(lamn_q - lamn); g = g + (a_q - a)*(lamn - lamn_q);
+                                lam = lamn + dt*f; gk = gk + (dt*0.5)*g                    */
+#define AT_OP_NORMALISE   9  /* ch {m, mv0, v0}: v_c = m > 0 ? mv_c / m : 0, c = 0..2 on
+                                channels mv0+c, v0+c                                       */
+
+/* ch: host array of channel indices (meaning per op above); params: host
+ * array of up to 4 floats.  check_activation != 0 keeps the per-write
+ * activation check of an eager task (activation on write); 0 is the
+ * demoted form (Section 6.3). */
+at_status at_run_stencil(at_grid grid, int32_t op, const int32_t *ch, const float *params,
+                         int32_t check_activation, hipStream_t stream);
+
+/* Particle tasks (Section 8.2 workload; PIC transfers with the quadratic
+ * B-spline: per axis base = floor(X - 0.5), fx = X - base,
+ * w = (0.5*(1.5-fx)^2, 0.75-(fx-1)^2, 0.5*(fx-0.5)^2), X = x/dx, node weight
+ * (wx*wy)*wz, nodes in (x, y, z) lexicographic order). */
+#define AT_ACT_PER_NODE  0   /* eager: check and activate at each of the 27 node writes */
+#define AT_ACT_PER_BLOCK 1   /* activate each distinct touched block once, then write unchecked */
+
+/* x += dt * v (device SoA arrays, np particles). */
+at_status at_advect(float *d_x, const float *d_v, int64_t np, float dt, hipStream_t stream);
+
+/* Scatter mass and momentum: m += w*m_p, mv_c += (w*m_p)*v_c with fp32
+ * atomics, activating node blocks on write.  ch: {m, mv0} (mv on mv0..mv0+2).
+ * Nodes outside the domain are skipped. */
+at_status at_p2g(at_grid grid, const float *d_x, const float *d_v, const float *d_m, int64_t np,
+                 float dx, const int32_t *ch, int32_t activation, hipStream_t stream);
+
+/* Gather velocity: v_p = sum over 27 nodes of w * v_node (accumulated in node
+ * order from 0).  ch: {v0} (v on v0..v0+2). */
+at_status at_g2p(at_grid grid, const float *d_x, float *d_v, int64_t np, float dx,
+                 const int32_t *ch, hipStream_t stream);
+
+/* Copy listed values between a grid and dense per-block arrays (setup and
+ * inspection, not part of the optimized path).  cells: device int32 [n]
+ * root cells; vals: device float [n][512].  at_scatter_blocks activates the
+ * cells (in order) and stores; at_gather_blocks reads (0 for inactive). */
+at_status at_scatter_blocks(at_grid grid, int32_t ch, const int32_t *d_cells, const float *d_vals,
+                            int64_t n, hipStream_t stream);
+at_status at_gather_blocks(at_grid grid, int32_t ch, const int32_t *d_cells, float *d_vals,
+                           int64_t n, hipStream_t stream);
+
+/* ---------------------------------------------------- sequences and engine
+ * A task descriptor (Section 4, "Tasks"): the kind fixes the loop type
+ * (serial, range-for or struct-for) and the states the task reads and
+ * writes; the engine derives its state-flow edges from that.  Per kind:
+ *   AT_TASK_ACTIVATE  range-for over n coordinates: grid; op = AT_COORD_*;
+ *                     ext[0] = coords (int32 [n][3])
+ *   AT_TASK_LISTGEN   serial: grid
+ *   AT_TASK_STENCIL   struct-for over grid's list: op = AT_OP_*; ch = the op's
+ *                     channels in the order documented there; param[0]
+ *   AT_TASK_ADVECT    range-for over n particles: ext[0] = x (updated),
+ *                     ext[1] = v; param[0] = dt
+ *   AT_TASK_P2G       range-for: grid (scatter target); op = AT_ACT_* (the
+ *                     eager form; the optimizer may coarsen it);
+ *                     ext[0] = x, ext[1] = v, ext[2] = m; param[0] = dx;
+ *                     ch[0] = m, ch[1] = mv0
+ *   AT_TASK_G2P       range-for: grid (gather source); ext[0] = x,
+ *                     ext[1] = v (written); param[0] = dx; ch[0] = v0
+ * Unused ch entries must be -1 and unused ext entries NULL. */
+#define AT_TASK_ACTIVATE 1
+#define AT_TASK_LISTGEN  2
+#define AT_TASK_STENCIL  3
+#define AT_TASK_ADVECT   4
+#define AT_TASK_P2G      5
+#define AT_TASK_G2P      6
+
+/* The particle arrays of this task are indexed only at the loop index, and
+ * the loop index is unique per iteration and covers the array (the paper's
+ * loop_unique hint, supplement Section 4.4).  Required for particle tasks
+ * to be fusible. */
+#define AT_TASKF_LOOP_UNIQUE 1u
+
+typedef struct at_task {
+    int32_t kind;         /* AT_TASK_* */
+    int32_t op;           /* AT_OP_* (STENCIL), AT_COORD_* (ACTIVATE), AT_ACT_* (P2G) */
+    uint32_t flags;       /* AT_TASKF_* */
+    int32_t reserved;     /* must be 0 */
+    at_grid grid;
+    at_grid grid2;        /* reserved, must be NULL */
+    int32_t ch[8];        /* channels; unused entries -1 */
+    float param[4];
+    void *ext[4];         /* device pointers of external arrays */
+    int64_t n;            /* element count of a range-for (coordinates, particles) */
+} at_task;
+
+/* Optimizer passes (Section 6), selectable one by one as in the paper's
+ * ablations.  0 = the eager pipeline. */
+#define AT_OPT_LGR   1u   /* list generation removal (6.2) */
+#define AT_OPT_AD    2u   /* activation demotion (6.3)     */
+#define AT_OPT_FUSE  4u   /* task fusion (6.4, supplement 2) */
+#define AT_OPT_DSE   8u   /* dead store elimination (6.5) */
+#define AT_OPT_ALL  15u
+
+typedef struct at_stats {
+    int64_t tasks_in;             /* descriptors received */
+    int64_t tasks_launched;       /* tasks left after optimization (fused = 1) */
+    int64_t dispatches;           /* device dispatches issued (kernels + fills) */
+    int64_t listgens_removed;
+    int64_t activations_demoted;
+    int64_t fusions;
+    int64_t stores_eliminated;
+    int64_t plan_cache_hits;
+    double optimizer_us;          /* host time spent building and optimizing the plan */
+} at_stats;
+
+/* Run a window of tasks on `stream` (Section 5, "Asynchronous launching"):
+ * build the state-flow graph (Section 4) seeded with the state owners kept
+ * from earlier windows (Section 7.1, "Partial SFG garbage collection"), run
+ * the passes selected in opt_flags to a fixpoint, and launch the result in a
+ * topological order, without host synchronisation.  Results equal those of
+ * running the tasks in the given order (order independency, Section 4.2).
+ * stats (nullable) is overwritten with this window's counters. */
+at_status at_run_sequence(const at_task *tasks, int32_t ntasks, uint32_t opt_flags,
+                          at_stats *stats, hipStream_t stream);
+
+/* One entry of an optimized plan: the input tasks it runs, in order. */
+#define AT_PLAN_MAX_MEMBERS 8
+typedef struct at_plan_entry {
+    int32_t kind;                 /* AT_TASK_* of the first member */
+    int32_t nmembers;
+    int32_t members[AT_PLAN_MAX_MEMBERS];   /* indices into the input task array */
+    int32_t check_activation;     /* 1 if activating writes keep their check */
+    int32_t activation_mode;      /* AT_ACT_* for particle scatter */
+    uint32_t dropped;             /* bit q: member q's dropped stores (DSE) */
+    int32_t fill_channels;        /* remaining channels of a FILL member 0 (bitmask of ch slots) */
+} at_plan_entry;
+
+/* Plan a window without running it or changing engine state (host only). */
+at_status at_plan_sequence(const at_task *tasks, int32_t ntasks, uint32_t opt_flags,
+                           at_plan_entry *out, int32_t capacity, int32_t *nout, at_stats *stats);
+
+/* Queue a task for the next flush (Section 7.1, execution queue); flushes by
+ * itself every `flush_period` tasks (AT_OPTION_FLUSH_PERIOD) with the
+ * engine's opt flags (AT_OPTION_OPT_FLAGS). */
+at_status at_enqueue(const at_task *task, hipStream_t stream);
+/* Optimize and launch every queued task (Section 7.1, "Flushing"). */
+at_status at_flush(at_stats *stats, hipStream_t stream);
+
+#define AT_OPTION_MAX_FUSE_PER_TASK 1   /* default 1 (supplement Section 2, criterion 4) */
+#define AT_OPTION_FLUSH_PERIOD      2   /* default 0 = flush only explicitly */
+#define AT_OPTION_OPT_FLAGS         3   /* flags for at_enqueue/at_flush, default AT_OPT_ALL */
+#define AT_OPTION_PLAN_CACHE        4   /* 1 (default) caches optimized plans */
+#define AT_OPTION_STRUCT_FOR_WORKGROUPS 5 /* persistent struct-for grid size; 0 = automatic */
+at_status at_set_option(int32_t option, int64_t value);
+at_status at_get_option(int32_t option, int64_t *value);
+
+/* Forget all engine state (versions, owners, cached plans). */
+at_status at_engine_reset(void);
+
+/* Tell the engine an external array was written outside its tasks (bumps
+ * the array's state version so no earlier result is reused). */
+at_status at_ext_modified(const void *ptr);
+
+/* Total device dispatches issued by the library since load. */
+int64_t at_dispatch_count(void);
+
+const char *at_last_error(void);
+const char *at_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ATSPARSE_H */

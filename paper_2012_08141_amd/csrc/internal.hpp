@@ -1,0 +1,98 @@
+// Internal definitions shared by the host runtime, the planner and the HIP
+// kernels.  Not part of the public interface (include/atsparse.h is).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+#include "atsparse.h"
+
+namespace ats {
+
+constexpr int kBS = 8;      // leaf block edge
+constexpr int kBV = 512;    // voxels per leaf block
+
+// Words of the per-grid device header (first 256 bytes of the grid buffer).
+enum : int { HDR_COUNT = 0, HDR_BUMP = 1, HDR_ERR = 2, HDR_SCRATCH = 3 };
+enum : int32_t { ERR_CAPACITY = 1, ERR_SPIN = 2 };
+
+// Pointer-root cell states besides a valid slot (>= 0).
+enum : int32_t { PTR_NULL = -1, PTR_LOCKED = -2, PTR_FAILED = -3 };
+
+// Device view of one grid, passed by value to kernels.
+struct GridDev {
+    int32_t R;          // root edge (blocks per axis)
+    int32_t R2;         // R * R
+    int32_t kind;       // AT_ROOT_BITMASK / AT_ROOT_POINTER
+    int32_t cap;        // leaf capacity (bitmask root: R^3)
+    int64_t ncells;     // R^3
+    uint32_t *bits;     // activity bits, one per root cell (both root kinds)
+    int32_t *ptr;       // pointer root: slot per cell; bitmask root: nullptr
+    int32_t *list;      // list state: root cells
+    int32_t *hdr;       // device header words
+    float *chan;        // channel 0 base; channel c at chan + c * ch_stride
+    int64_t ch_stride;  // floats per channel (cap * 512)
+};
+
+// One op of a fused (or elementwise) struct-for program, applied per voxel
+// in program order.
+constexpr int kMaxOps = 8;
+struct MicroOp {
+    int32_t op;       // AT_OP_*
+    int32_t ch[7];    // channels, as in the public op table
+    float p;          // parameter
+    uint32_t keep;    // FILL: bit q keeps the store to ch[q]; NORMALISE: bit c keeps v_c
+};
+struct MicroProg {
+    int32_t nops;
+    int32_t check;    // eager activation check on writes
+    MicroOp ops[kMaxOps];
+};
+
+// Particle program: any subset of gather (G2P), advection and scatter (P2G),
+// in that order, over the same particle arrays.
+enum : uint32_t { PS_G2P = 1, PS_ADVECT = 2, PS_P2G = 4 };
+struct PartProg {
+    uint32_t steps;
+    int32_t act_mode;      // AT_ACT_* for the scatter
+    int64_t np;
+    float *x;              // [3][np], updated by ADVECT
+    float *v;              // [3][np], written by G2P, read by ADVECT / P2G
+    const float *m;        // [np]
+    float dt;
+    float inv_dx_src;      // gather grid
+    float inv_dx_dst;      // scatter grid
+    int32_t ch_vsrc;       // gather: velocity channels v0..v0+2 of gsrc
+    int32_t ch_m, ch_mv;   // scatter: m and mv0..mv0+2 of gdst
+    GridDev gsrc, gdst;
+};
+
+// Kernel launchers (kernels.hip).  Each enqueues exactly one dispatch on the
+// stream and returns the launch status.
+hipError_t launch_activate(const GridDev &g, const int32_t *ijk, int64_t n, int coord_kind,
+                           hipStream_t s);
+hipError_t launch_listgen(const GridDev &g, hipStream_t s);
+hipError_t launch_stencil(const GridDev &g, int op, const int32_t *ch, float p, int check,
+                          hipStream_t s);
+hipError_t launch_micro(const GridDev &g, const MicroProg &prog, hipStream_t s);
+hipError_t launch_particles(const PartProg &prog, hipStream_t s);
+hipError_t launch_scatter_blocks(const GridDev &g, int ch, const int32_t *cells, const float *vals,
+                                 int64_t n, hipStream_t s);
+hipError_t launch_gather_blocks(const GridDev &g, int ch, const int32_t *cells, float *vals,
+                                int64_t n, hipStream_t s);
+hipError_t launch_popcount(const GridDev &g, hipStream_t s);   // into hdr[HDR_SCRATCH]
+// Persistent grid size used by struct-for kernels (workgroups).
+int struct_for_grid_size(const GridDev &g);
+void set_struct_for_grid_size(int wgs);   // 0 = automatic
+
+}  // namespace ats
+
+// Host-side grid handle.
+struct at_grid_s {
+    at_grid_desc desc;
+    ats::GridDev dev;
+    uint64_t uid;       // engine identity (never reused)
+    bool virt;          // planning handle without device memory
+    size_t bytes;
+    int32_t list_cap;
+};

@@ -1,0 +1,733 @@
+// Grid runtime, execution engine and the C ABI of libatsparse.
+//
+// The engine follows the paper's asynchronous execution engine (Section 7.1):
+// tasks of a window (one at_run_sequence call, or everything queued by
+// at_enqueue until a flush) are planned together -- state-flow graph plus the
+// passes selected by the caller -- and launched in order on the caller's
+// stream with no host synchronisation.  After each window only the
+// information carried by the latest owners of each state is kept (partial
+// SFG garbage collection), and optimized plans are cached under a hash of the
+// window's task descriptors (the IR-bank analogue of Section 7.2).
+#include <hip/hip_runtime_api.h>
+
+#include <atomic>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.hpp"
+#include "sfg.hpp"
+
+using namespace ats;
+
+namespace {
+
+thread_local std::string g_err;
+
+at_status fail(at_status code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+at_status hip_fail(hipError_t e, const char *what) {
+    return fail(AT_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+struct CacheEntry {
+    std::vector<uint8_t> fp;
+    std::vector<Node> nodes;
+    PlanCounters counters;
+};
+
+struct Engine {
+    std::recursive_mutex mu;
+    Persist persist;
+    std::unordered_map<uint64_t, CacheEntry> cache;
+    int max_fuse = 1;
+    int64_t flush_period = 0;
+    uint32_t opt_flags = AT_OPT_ALL;
+    bool plan_cache = true;
+    std::vector<at_task> queue;
+    hipStream_t queue_stream = nullptr;
+    std::atomic<int64_t> dispatches{0};
+    uint64_t next_uid = 1;
+};
+
+Engine &E() {
+    static Engine *e = new Engine();
+    return *e;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t hdr, bits, ptr, list, chan, total;
+    int64_t ncells;
+    int32_t cap, list_cap, R;
+};
+
+at_status layout_of(const at_grid_desc *d, Layout &L) {
+    if (!d) return fail(AT_E_INVALID, "null grid description");
+    if (d->n[0] <= 0 || d->n[0] % kBS != 0) return fail(AT_E_INVALID, "domain edge must be a positive multiple of 8");
+    if (d->n[1] != d->n[0] || d->n[2] != d->n[0])
+        return fail(AT_E_UNSUPPORTED, "only cubic domains are supported (n[0] == n[1] == n[2])");
+    const int64_t R = d->n[0] / kBS;
+    if (R > 1024) return fail(AT_E_INVALID, "domain edge above 8192 voxels");
+    if (d->root_kind != AT_ROOT_BITMASK && d->root_kind != AT_ROOT_POINTER) return fail(AT_E_INVALID, "unknown root kind");
+    if (d->channels < 1 || d->channels > 64) return fail(AT_E_INVALID, "channels must be in 1..64");
+    L.R = (int32_t)R;
+    L.ncells = R * R * R;
+    if (d->root_kind == AT_ROOT_BITMASK) {
+        L.cap = (int32_t)L.ncells;
+    } else {
+        if (d->capacity_blocks < 1 || d->capacity_blocks > L.ncells)
+            return fail(AT_E_INVALID, "pointer root: capacity_blocks must be in 1..R^3");
+        L.cap = d->capacity_blocks;
+    }
+    L.list_cap = (int32_t)(L.cap < L.ncells ? L.cap : L.ncells);
+    size_t off = 0;
+    L.hdr = off; off += 256;
+    L.bits = off; off += align256(((L.ncells + 31) / 32) * 4);
+    L.ptr = off; if (d->root_kind == AT_ROOT_POINTER) off += align256(L.ncells * 4);
+    L.list = off; off += align256((size_t)L.list_cap * 4);
+    L.chan = off; off += (size_t)d->channels * L.cap * kBV * sizeof(float);
+    L.total = off;
+    return AT_OK;
+}
+
+at_status check_grid(at_grid g, bool need_device) {
+    if (!g) return fail(AT_E_INVALID, "null grid handle");
+    if (need_device && g->virt) return fail(AT_E_STATE, "planning handle has no device memory");
+    return AT_OK;
+}
+
+// ------------------------------------------------------------ execution
+
+int64_t dispatches_of(const Node &) { return 1; }
+
+at_status execute_node(const Node &nd, const at_task *tasks, hipStream_t s) {
+    const at_task &t0 = tasks[nd.members[0].task];
+    const at_grid_s *g = task_grid(t0);
+    // planning handles launch nothing
+    for (const Member &m : nd.members) {
+        const at_grid_s *gm = task_grid(tasks[m.task]);
+        if (gm && gm->virt) return AT_OK;
+    }
+    hipError_t e = hipSuccess;
+    switch (t0.kind) {
+    case AT_TASK_ACTIVATE:
+        e = launch_activate(g->dev, (const int32_t *)t0.ext[0], t0.n, t0.op, s);
+        break;
+    case AT_TASK_LISTGEN:
+        e = launch_listgen(g->dev, s);
+        break;
+    case AT_TASK_STENCIL: {
+        const Member &m0 = nd.members[0];
+        const bool tiled = t0.op == AT_OP_LAP_UPDATE || t0.op == AT_OP_JACOBI || t0.op == AT_OP_DIFFUSE ||
+                           t0.op == AT_OP_DIFFUSE_ADJ;
+        if (nd.members.size() == 1 && tiled && m0.keep == ~0u) {
+            e = launch_stencil(g->dev, t0.op, t0.ch, t0.param[0], nd.check_activation ? 1 : 0, s);
+        } else {
+            MicroProg prog{};
+            prog.nops = (int32_t)nd.members.size();
+            prog.check = nd.check_activation ? 1 : 0;
+            for (size_t q = 0; q < nd.members.size(); ++q) {
+                const at_task &t = tasks[nd.members[q].task];
+                MicroOp &op = prog.ops[q];
+                op.op = t.op;
+                for (int c = 0; c < 7; ++c) op.ch[c] = t.ch[c];
+                op.p = t.param[0];
+                op.keep = nd.members[q].keep;
+            }
+            e = launch_micro(g->dev, prog, s);
+        }
+        break;
+    }
+    case AT_TASK_ADVECT:
+    case AT_TASK_P2G:
+    case AT_TASK_G2P: {
+        PartProg pp{};
+        pp.act_mode = nd.act_mode;
+        pp.np = t0.n;
+        for (const Member &m : nd.members) {
+            const at_task &t = tasks[m.task];
+            pp.x = (float *)t.ext[0];
+            if (t.kind == AT_TASK_G2P) {
+                pp.steps |= PS_G2P;
+                pp.v = (float *)t.ext[1];
+                pp.gsrc = task_grid(t)->dev;
+                pp.inv_dx_src = (float)(1.0 / (double)t.param[0]);
+                pp.ch_vsrc = t.ch[0];
+            } else if (t.kind == AT_TASK_ADVECT) {
+                pp.steps |= PS_ADVECT;
+                pp.v = (float *)t.ext[1];
+                pp.dt = t.param[0];
+            } else {
+                pp.steps |= PS_P2G;
+                pp.v = (float *)t.ext[1];
+                pp.m = (const float *)t.ext[2];
+                pp.gdst = task_grid(t)->dev;
+                pp.inv_dx_dst = (float)(1.0 / (double)t.param[0]);
+                pp.ch_m = t.ch[0];
+                pp.ch_mv = t.ch[1];
+            }
+        }
+        if (pp.np == 0) return AT_OK;
+        e = launch_particles(pp, s);
+        break;
+    }
+    default:
+        return fail(AT_E_INVALID, "cannot execute task kind %d", t0.kind);
+    }
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    E().dispatches.fetch_add(1);
+    return AT_OK;
+}
+
+void fill_stats(at_stats *st, int ntasks, const std::vector<Node> &nodes, const PlanCounters &c, int64_t disp,
+                double us, int64_t hits) {
+    if (!st) return;
+    st->tasks_in = ntasks;
+    st->tasks_launched = (int64_t)nodes.size();
+    st->dispatches = disp;
+    st->listgens_removed = c.listgens_removed;
+    st->activations_demoted = c.activations_demoted;
+    st->fusions = c.fusions;
+    st->stores_eliminated = c.stores_eliminated;
+    st->plan_cache_hits = hits;
+    st->optimizer_us = us;
+}
+
+// Plan a window (no side effects on the engine unless `commit`).
+at_status plan_window(const at_task *tasks, int ntasks, uint32_t flags, std::vector<Node> &nodes, PlanCounters &ctr,
+                      int64_t &hits) {
+    Engine &en = E();
+    for (int i = 0; i < ntasks; ++i) {
+        const std::string msg = validate_task(tasks[i]);
+        if (!msg.empty()) return fail(AT_E_INVALID, "task %d: %s", i, msg.c_str());
+    }
+    hits = 0;
+    Planner P(tasks, ntasks, flags, en.max_fuse);
+    if (flags == 0) {
+        P.build_eager();
+        nodes = std::move(P.nodes);
+        ctr = PlanCounters{};
+        return AT_OK;
+    }
+    const uint64_t key = hash_window(tasks, ntasks, flags, en.max_fuse);
+    std::vector<uint8_t> fp = Planner::fingerprint(tasks, ntasks, en.persist);
+    if (en.plan_cache) {
+        auto it = en.cache.find(key);
+        if (it != en.cache.end() && it->second.fp == fp) {
+            nodes = it->second.nodes;
+            ctr = it->second.counters;
+            hits = 1;
+            return AT_OK;
+        }
+    }
+    P.build_eager();
+    P.optimize(en.persist);
+    nodes = std::move(P.nodes);
+    ctr = P.counters;
+    if (en.plan_cache) {
+        if (en.cache.size() > 4096) en.cache.clear();
+        en.cache[key] = CacheEntry{std::move(fp), nodes, ctr};
+    }
+    return AT_OK;
+}
+
+at_status run_window(const at_task *tasks, int ntasks, uint32_t flags, at_stats *stats, hipStream_t s) {
+    Engine &en = E();
+    std::lock_guard<std::recursive_mutex> lk(en.mu);
+    if (ntasks < 0 || (ntasks > 0 && !tasks)) return fail(AT_E_INVALID, "bad task array");
+    if (flags & ~AT_OPT_ALL) return fail(AT_E_INVALID, "unknown optimizer flags");
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<Node> nodes;
+    PlanCounters ctr;
+    int64_t hits = 0;
+    at_status st = plan_window(tasks, ntasks, flags, nodes, ctr, hits);
+    if (st != AT_OK) return st;
+    const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+    const int64_t d0 = en.dispatches.load();
+    for (const Node &nd : nodes) {
+        st = execute_node(nd, tasks, s);
+        if (st != AT_OK) {
+            Planner::commit(nodes, tasks, en.persist);
+            return st;
+        }
+    }
+    Planner::commit(nodes, tasks, en.persist);
+    fill_stats(stats, ntasks, nodes, ctr, en.dispatches.load() - d0, us, hits);
+    return AT_OK;
+}
+
+at_status run_one(const at_task &t, hipStream_t s) {
+    Engine &en = E();
+    std::lock_guard<std::recursive_mutex> lk(en.mu);
+    if (!en.queue.empty()) {
+        // keep program order with queued work
+        at_status st = run_window(en.queue.data(), (int)en.queue.size(), en.opt_flags, nullptr, en.queue_stream);
+        en.queue.clear();
+        if (st != AT_OK) return st;
+    }
+    return run_window(&t, 1, 0, nullptr, s);
+}
+
+at_task blank_task(int kind, at_grid g) {
+    at_task t;
+    std::memset(&t, 0, sizeof t);
+    t.kind = kind;
+    t.grid = g;
+    for (int q = 0; q < 8; ++q) t.ch[q] = -1;
+    return t;
+}
+
+// Bump the versions of states written outside tasks (setup copies, clears).
+void bump(uint64_t uid, uint8_t kind, int32_t ch) {
+    E().persist.version[StateKey{uid, ch, kind}] += 1;
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+extern "C" {
+
+at_status at_grid_footprint(const at_grid_desc *desc, size_t *bytes) {
+    if (!bytes) return fail(AT_E_INVALID, "null output");
+    Layout L;
+    at_status st = layout_of(desc, L);
+    if (st != AT_OK) return st;
+    *bytes = L.total;
+    return AT_OK;
+}
+
+at_status at_grid_create(const at_grid_desc *desc, void *dev_buf, size_t bytes, hipStream_t stream, at_grid *out) {
+    if (!out) return fail(AT_E_INVALID, "null output handle");
+    *out = nullptr;
+    Layout L;
+    at_status st = layout_of(desc, L);
+    if (st != AT_OK) return st;
+    const bool virt = dev_buf == nullptr;
+    if (!virt) {
+        if (bytes < L.total) return fail(AT_E_INVALID, "buffer of %zu bytes below the footprint %zu", bytes, L.total);
+        if (((uintptr_t)dev_buf & 255) != 0) return fail(AT_E_INVALID, "grid buffer must be 256-byte aligned");
+    }
+    at_grid g = new at_grid_s();
+    g->desc = *desc;
+    g->virt = virt;
+    g->bytes = L.total;
+    g->list_cap = L.list_cap;
+    GridDev &d = g->dev;
+    d.R = L.R;
+    d.R2 = L.R * L.R;
+    d.kind = desc->root_kind;
+    d.cap = L.cap;
+    d.ncells = L.ncells;
+    d.ch_stride = (int64_t)L.cap * kBV;
+    if (!virt) {
+        char *b = (char *)dev_buf;
+        d.hdr = (int32_t *)(b + L.hdr);
+        d.bits = (uint32_t *)(b + L.bits);
+        d.ptr = desc->root_kind == AT_ROOT_POINTER ? (int32_t *)(b + L.ptr) : nullptr;
+        d.list = (int32_t *)(b + L.list);
+        d.chan = (float *)(b + L.chan);
+        hipError_t e = hipMemsetAsync(dev_buf, 0, L.total, stream);
+        if (e == hipSuccess && d.ptr) e = hipMemsetAsync(d.ptr, 0xff, (size_t)L.ncells * 4, stream);
+        if (e != hipSuccess) {
+            delete g;
+            return hip_fail(e, "grid initialisation");
+        }
+        E().dispatches.fetch_add(d.ptr ? 2 : 1);
+    }
+    {
+        std::lock_guard<std::recursive_mutex> lk(E().mu);
+        g->uid = E().next_uid++;
+    }
+    *out = g;
+    return AT_OK;
+}
+
+at_status at_grid_destroy(at_grid grid) {
+    if (!grid) return fail(AT_E_INVALID, "null grid handle");
+    {
+        Engine &en = E();
+        std::lock_guard<std::recursive_mutex> lk(en.mu);
+        for (const at_task &t : en.queue)
+            if (t.grid == grid) return fail(AT_E_STATE, "grid has queued tasks; flush first");
+        en.persist.forget_grid(grid->uid);
+    }
+    delete grid;
+    return AT_OK;
+}
+
+at_status at_grid_views(at_grid grid, float **ch_base, const int32_t **list, const int32_t **count, const void **root) {
+    at_status st = check_grid(grid, true);
+    if (st != AT_OK) return st;
+    if (ch_base)
+        for (int c = 0; c < grid->desc.channels; ++c) ch_base[c] = grid->dev.chan + (int64_t)c * grid->dev.ch_stride;
+    if (list) *list = grid->dev.list;
+    if (count) *count = grid->dev.hdr + HDR_COUNT;
+    if (root) *root = grid->desc.root_kind == AT_ROOT_POINTER ? (const void *)grid->dev.ptr : (const void *)grid->dev.bits;
+    return AT_OK;
+}
+
+at_status at_grid_get_info(at_grid grid, at_grid_info *info) {
+    at_status st = check_grid(grid, false);
+    if (st != AT_OK) return st;
+    if (!info) return fail(AT_E_INVALID, "null output");
+    info->n = grid->desc.n[0];
+    info->R = grid->dev.R;
+    info->root_kind = grid->desc.root_kind;
+    info->channels = grid->desc.channels;
+    info->capacity_blocks = grid->dev.cap;
+    info->list_capacity = grid->list_cap;
+    info->ncells = grid->dev.ncells;
+    info->bytes = grid->bytes;
+    return AT_OK;
+}
+
+at_status at_grid_clear(at_grid grid, hipStream_t stream) {
+    at_status st = check_grid(grid, true);
+    if (st != AT_OK) return st;
+    Engine &en = E();
+    std::lock_guard<std::recursive_mutex> lk(en.mu);
+    if (!en.queue.empty()) {
+        st = run_window(en.queue.data(), (int)en.queue.size(), en.opt_flags, nullptr, en.queue_stream);
+        en.queue.clear();
+        if (st != AT_OK) return st;
+    }
+    const GridDev &d = grid->dev;
+    hipError_t e = hipMemsetAsync(d.hdr, 0, 2 * sizeof(int32_t), stream);   // count and bump
+    if (e == hipSuccess) e = hipMemsetAsync(d.bits, 0, ((d.ncells + 31) / 32) * 4, stream);
+    if (e == hipSuccess && d.ptr) e = hipMemsetAsync(d.ptr, 0xff, (size_t)d.ncells * 4, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(d.chan, 0, (size_t)grid->desc.channels * d.ch_stride * sizeof(float), stream);
+    if (e != hipSuccess) return hip_fail(e, "grid clear");
+    en.dispatches.fetch_add(d.ptr ? 4 : 3);
+    en.persist.deactivate_grid(grid->uid);
+    for (int c = 0; c < grid->desc.channels; ++c) bump(grid->uid, ST_VALUE, c);
+    bump(grid->uid, ST_ALLOC, -1);
+    return AT_OK;
+}
+
+at_status at_device_status(at_grid grid, hipStream_t stream, int32_t clear, int32_t *bits) {
+    at_status st = check_grid(grid, true);
+    if (st != AT_OK) return st;
+    if (!bits) return fail(AT_E_INVALID, "null output");
+    hipError_t e = hipMemcpyAsync(bits, grid->dev.hdr + HDR_ERR, sizeof(int32_t), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e == hipSuccess && clear) {
+        e = hipMemsetAsync(grid->dev.hdr + HDR_ERR, 0, sizeof(int32_t), stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "device status");
+    return AT_OK;
+}
+
+at_status at_active_count(at_grid grid, hipStream_t stream, int64_t *count) {
+    at_status st = check_grid(grid, true);
+    if (st != AT_OK) return st;
+    if (!count) return fail(AT_E_INVALID, "null output");
+    hipError_t e = launch_popcount(grid->dev, stream);
+    int32_t v = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&v, grid->dev.hdr + HDR_SCRATCH, sizeof v, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "active count");
+    E().dispatches.fetch_add(1);
+    *count = v;
+    return AT_OK;
+}
+
+at_status at_activate(at_grid grid, const int32_t *d_ijk, int64_t n, int32_t coord_kind, hipStream_t stream) {
+    at_status st = check_grid(grid, true);
+    if (st != AT_OK) return st;
+    at_task t = blank_task(AT_TASK_ACTIVATE, grid);
+    t.op = coord_kind;
+    t.ext[0] = (void *)d_ijk;
+    t.n = n;
+    return run_one(t, stream);
+}
+
+at_status at_listgen(at_grid grid, hipStream_t stream) {
+    at_status st = check_grid(grid, true);
+    if (st != AT_OK) return st;
+    return run_one(blank_task(AT_TASK_LISTGEN, grid), stream);
+}
+
+at_status at_run_stencil(at_grid grid, int32_t op, const int32_t *ch, const float *params, int32_t check_activation,
+                         hipStream_t stream) {
+    at_status st = check_grid(grid, true);
+    if (st != AT_OK) return st;
+    if (!ch) return fail(AT_E_INVALID, "null channel array");
+    at_task t = blank_task(AT_TASK_STENCIL, grid);
+    t.op = op;
+    if (op == AT_OP_FILL) {
+        for (int q = 0; q < 8; ++q) {
+            t.ch[q] = ch[q];
+            if (ch[q] < 0) break;
+        }
+    } else {
+        const int nc = op == AT_OP_LAP_UPDATE || op == AT_OP_AXPY || op == AT_OP_COPY ? 2
+                     : op == AT_OP_INC ? 1 : op == AT_OP_DIFFUSE_ADJ ? 5 : 3;
+        if (op < AT_OP_LAP_UPDATE || op > AT_OP_NORMALISE) return fail(AT_E_INVALID, "unknown op %d", op);
+        for (int q = 0; q < nc; ++q) t.ch[q] = ch[q];
+    }
+    if (params) t.param[0] = params[0];
+    Engine &en = E();
+    std::lock_guard<std::recursive_mutex> lk(en.mu);
+    if (check_activation) return run_one(t, stream);
+    // demoted form requested explicitly: plan with activation demotion only
+    if (!en.queue.empty()) {
+        st = run_window(en.queue.data(), (int)en.queue.size(), en.opt_flags, nullptr, en.queue_stream);
+        en.queue.clear();
+        if (st != AT_OK) return st;
+    }
+    return run_window(&t, 1, AT_OPT_AD, nullptr, stream);
+}
+
+at_status at_advect(float *d_x, const float *d_v, int64_t np, float dt, hipStream_t stream) {
+    at_task t = blank_task(AT_TASK_ADVECT, nullptr);
+    t.ext[0] = d_x;
+    t.ext[1] = (void *)d_v;
+    t.n = np;
+    t.param[0] = dt;
+    t.flags = AT_TASKF_LOOP_UNIQUE;
+    return run_one(t, stream);
+}
+
+at_status at_p2g(at_grid grid, const float *d_x, const float *d_v, const float *d_m, int64_t np, float dx,
+                 const int32_t *ch, int32_t activation, hipStream_t stream) {
+    at_status st = check_grid(grid, true);
+    if (st != AT_OK) return st;
+    if (!ch) return fail(AT_E_INVALID, "null channel array");
+    at_task t = blank_task(AT_TASK_P2G, grid);
+    t.op = activation;
+    t.ext[0] = (void *)d_x;
+    t.ext[1] = (void *)d_v;
+    t.ext[2] = (void *)d_m;
+    t.n = np;
+    t.param[0] = dx;
+    t.ch[0] = ch[0];
+    t.ch[1] = ch[1];
+    t.flags = AT_TASKF_LOOP_UNIQUE;
+    return run_one(t, stream);
+}
+
+at_status at_g2p(at_grid grid, const float *d_x, float *d_v, int64_t np, float dx, const int32_t *ch,
+                 hipStream_t stream) {
+    at_status st = check_grid(grid, true);
+    if (st != AT_OK) return st;
+    if (!ch) return fail(AT_E_INVALID, "null channel array");
+    at_task t = blank_task(AT_TASK_G2P, grid);
+    t.ext[0] = (void *)d_x;
+    t.ext[1] = d_v;
+    t.n = np;
+    t.param[0] = dx;
+    t.ch[0] = ch[0];
+    t.flags = AT_TASKF_LOOP_UNIQUE;
+    return run_one(t, stream);
+}
+
+at_status at_scatter_blocks(at_grid grid, int32_t ch, const int32_t *d_cells, const float *d_vals, int64_t n,
+                            hipStream_t stream) {
+    at_status st = check_grid(grid, true);
+    if (st != AT_OK) return st;
+    if (ch < 0 || ch >= grid->desc.channels) return fail(AT_E_INVALID, "channel out of range");
+    if (n < 0 || (n > 0 && (!d_cells || !d_vals))) return fail(AT_E_INVALID, "bad block arrays");
+    Engine &en = E();
+    std::lock_guard<std::recursive_mutex> lk(en.mu);
+    if (!en.queue.empty()) {
+        st = run_window(en.queue.data(), (int)en.queue.size(), en.opt_flags, nullptr, en.queue_stream);
+        en.queue.clear();
+        if (st != AT_OK) return st;
+    }
+    if (n == 0) return AT_OK;
+    hipError_t e = launch_scatter_blocks(grid->dev, ch, d_cells, d_vals, n, stream);
+    if (e != hipSuccess) return hip_fail(e, "scatter blocks");
+    en.dispatches.fetch_add(1);
+    bump(grid->uid, ST_MASK, -1);
+    bump(grid->uid, ST_ALLOC, -1);
+    bump(grid->uid, ST_VALUE, ch);
+    return AT_OK;
+}
+
+at_status at_gather_blocks(at_grid grid, int32_t ch, const int32_t *d_cells, float *d_vals, int64_t n,
+                           hipStream_t stream) {
+    at_status st = check_grid(grid, true);
+    if (st != AT_OK) return st;
+    if (ch < 0 || ch >= grid->desc.channels) return fail(AT_E_INVALID, "channel out of range");
+    if (n < 0 || (n > 0 && (!d_cells || !d_vals))) return fail(AT_E_INVALID, "bad block arrays");
+    Engine &en = E();
+    std::lock_guard<std::recursive_mutex> lk(en.mu);
+    if (!en.queue.empty()) {
+        st = run_window(en.queue.data(), (int)en.queue.size(), en.opt_flags, nullptr, en.queue_stream);
+        en.queue.clear();
+        if (st != AT_OK) return st;
+    }
+    if (n == 0) return AT_OK;
+    hipError_t e = launch_gather_blocks(grid->dev, ch, d_cells, d_vals, n, stream);
+    if (e != hipSuccess) return hip_fail(e, "gather blocks");
+    en.dispatches.fetch_add(1);
+    return AT_OK;
+}
+
+at_status at_run_sequence(const at_task *tasks, int32_t ntasks, uint32_t opt_flags, at_stats *stats,
+                          hipStream_t stream) {
+    Engine &en = E();
+    std::lock_guard<std::recursive_mutex> lk(en.mu);
+    if (!en.queue.empty()) {
+        at_status st = run_window(en.queue.data(), (int)en.queue.size(), en.opt_flags, nullptr, en.queue_stream);
+        en.queue.clear();
+        if (st != AT_OK) return st;
+    }
+    return run_window(tasks, ntasks, opt_flags, stats, stream);
+}
+
+at_status at_plan_sequence(const at_task *tasks, int32_t ntasks, uint32_t opt_flags, at_plan_entry *out,
+                           int32_t capacity, int32_t *nout, at_stats *stats) {
+    Engine &en = E();
+    std::lock_guard<std::recursive_mutex> lk(en.mu);
+    if (ntasks < 0 || (ntasks > 0 && !tasks)) return fail(AT_E_INVALID, "bad task array");
+    if (opt_flags & ~AT_OPT_ALL) return fail(AT_E_INVALID, "unknown optimizer flags");
+    if (!nout || capacity < 0 || (capacity > 0 && !out)) return fail(AT_E_INVALID, "bad output array");
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<Node> nodes;
+    PlanCounters ctr;
+    int64_t hits = 0;
+    // planning must not populate the cache with a plan that was never run
+    const bool cache = en.plan_cache;
+    en.plan_cache = false;
+    at_status st = plan_window(tasks, ntasks, opt_flags, nodes, ctr, hits);
+    en.plan_cache = cache;
+    if (st != AT_OK) return st;
+    const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+    *nout = (int32_t)nodes.size();
+    if ((int32_t)nodes.size() > capacity) return fail(AT_E_INVALID, "plan has %zu entries, capacity %d", nodes.size(), capacity);
+    for (size_t i = 0; i < nodes.size(); ++i) {
+        const Node &nd = nodes[i];
+        at_plan_entry &e = out[i];
+        std::memset(&e, 0, sizeof e);
+        e.kind = tasks[nd.members[0].task].kind;
+        e.nmembers = (int32_t)nd.members.size();
+        for (size_t m = 0; m < nd.members.size() && m < AT_PLAN_MAX_MEMBERS; ++m) {
+            e.members[m] = nd.members[m].task;
+            if (nd.members[m].keep != ~0u) e.dropped |= 1u << m;
+        }
+        e.check_activation = nd.check_activation ? 1 : 0;
+        e.activation_mode = nd.act_mode;
+        e.fill_channels = (int32_t)nd.members[0].keep;
+    }
+    fill_stats(stats, ntasks, nodes, ctr, (int64_t)nodes.size(), us, hits);
+    return AT_OK;
+}
+
+at_status at_enqueue(const at_task *task, hipStream_t stream) {
+    if (!task) return fail(AT_E_INVALID, "null task");
+    const std::string msg = validate_task(*task);
+    if (!msg.empty()) return fail(AT_E_INVALID, "%s", msg.c_str());
+    Engine &en = E();
+    std::lock_guard<std::recursive_mutex> lk(en.mu);
+    if (!en.queue.empty() && stream != en.queue_stream) {
+        at_status st = run_window(en.queue.data(), (int)en.queue.size(), en.opt_flags, nullptr, en.queue_stream);
+        en.queue.clear();
+        if (st != AT_OK) return st;
+    }
+    en.queue.push_back(*task);
+    en.queue_stream = stream;
+    if (en.flush_period > 0 && (int64_t)en.queue.size() >= en.flush_period) {
+        at_status st = run_window(en.queue.data(), (int)en.queue.size(), en.opt_flags, nullptr, en.queue_stream);
+        en.queue.clear();
+        return st;
+    }
+    return AT_OK;
+}
+
+at_status at_flush(at_stats *stats, hipStream_t stream) {
+    Engine &en = E();
+    std::lock_guard<std::recursive_mutex> lk(en.mu);
+    if (en.queue.empty()) {
+        if (stats) std::memset(stats, 0, sizeof *stats);
+        return AT_OK;
+    }
+    (void)stream;
+    at_status st = run_window(en.queue.data(), (int)en.queue.size(), en.opt_flags, stats, en.queue_stream);
+    en.queue.clear();
+    return st;
+}
+
+at_status at_set_option(int32_t option, int64_t value) {
+    Engine &en = E();
+    std::lock_guard<std::recursive_mutex> lk(en.mu);
+    switch (option) {
+    case AT_OPTION_MAX_FUSE_PER_TASK:
+        if (value < 1 || value > 64) return fail(AT_E_INVALID, "max_fuse_per_task must be in 1..64");
+        en.max_fuse = (int)value;
+        en.cache.clear();
+        return AT_OK;
+    case AT_OPTION_FLUSH_PERIOD:
+        if (value < 0) return fail(AT_E_INVALID, "flush period must be >= 0");
+        en.flush_period = value;
+        return AT_OK;
+    case AT_OPTION_OPT_FLAGS:
+        if (value < 0 || (value & ~(int64_t)AT_OPT_ALL)) return fail(AT_E_INVALID, "unknown optimizer flags");
+        en.opt_flags = (uint32_t)value;
+        return AT_OK;
+    case AT_OPTION_PLAN_CACHE:
+        en.plan_cache = value != 0;
+        if (!en.plan_cache) en.cache.clear();
+        return AT_OK;
+    case AT_OPTION_STRUCT_FOR_WORKGROUPS:
+        if (value < 0 || value > (1 << 20)) return fail(AT_E_INVALID, "workgroup count out of range");
+        set_struct_for_grid_size((int)value);
+        return AT_OK;
+    default:
+        return fail(AT_E_INVALID, "unknown option %d", option);
+    }
+}
+
+at_status at_get_option(int32_t option, int64_t *value) {
+    if (!value) return fail(AT_E_INVALID, "null output");
+    Engine &en = E();
+    std::lock_guard<std::recursive_mutex> lk(en.mu);
+    switch (option) {
+    case AT_OPTION_MAX_FUSE_PER_TASK: *value = en.max_fuse; return AT_OK;
+    case AT_OPTION_FLUSH_PERIOD: *value = en.flush_period; return AT_OK;
+    case AT_OPTION_OPT_FLAGS: *value = en.opt_flags; return AT_OK;
+    case AT_OPTION_PLAN_CACHE: *value = en.plan_cache ? 1 : 0; return AT_OK;
+    default: return fail(AT_E_INVALID, "unknown option %d", option);
+    }
+}
+
+at_status at_engine_reset(void) {
+    Engine &en = E();
+    std::lock_guard<std::recursive_mutex> lk(en.mu);
+    en.persist = Persist{};
+    en.cache.clear();
+    en.queue.clear();
+    return AT_OK;
+}
+
+at_status at_ext_modified(const void *ptr) {
+    if (!ptr) return fail(AT_E_INVALID, "null pointer");
+    Engine &en = E();
+    std::lock_guard<std::recursive_mutex> lk(en.mu);
+    en.persist.version[StateKey{(uint64_t)(uintptr_t)ptr, -1, ST_EXT}] += 1;
+    return AT_OK;
+}
+
+int64_t at_dispatch_count(void) { return E().dispatches.load(); }
+
+const char *at_last_error(void) { return g_err.c_str(); }
+
+const char *at_version(void) { return "atsparse 0.1 (gfx950)"; }
+
+}  // extern "C"

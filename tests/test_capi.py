@@ -1,0 +1,114 @@
+"""The C ABI: the library loads, exports every function include/atsparse.h
+declares, its constants match the Python binding, and argument validation
+rejects bad calls without touching a device (host only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2012_08141_amd import _lib as L
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "atsparse.h")
+
+
+def test_exports_every_declared_symbol():
+    lib = L.lib()
+    names = L.declared_symbols(HEADER)
+    assert len(names) >= 25
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_constants_match_header():
+    txt = open(HEADER).read()
+    defs = dict(re.findall(r"#define\s+(AT_[A-Z0-9_]+)\s+(-?\d+)u?\b", txt))
+    assert len(defs) > 30
+    for name, val in defs.items():
+        assert hasattr(L, name), name
+        assert getattr(L, name) == int(val), name
+
+
+def test_struct_layouts():
+    # at_task: 4 int32, 2 pointers, 8 int32, 4 float, 4 pointers, int64
+    assert ctypes.sizeof(L.AtTask) == 16 + 16 + 32 + 16 + 32 + 8
+    assert ctypes.sizeof(L.AtStats) == 8 * 9
+    assert ctypes.sizeof(L.AtGridDesc) == 24
+
+
+def _desc(n, kind=L.AT_ROOT_BITMASK, ch=2, cap=0):
+    return L.AtGridDesc((n, n, n), kind, ch, cap)
+
+
+def test_footprint_layout_and_validation():
+    lib = L.lib()
+    b = ctypes.c_size_t()
+    d = _desc(64)
+    assert lib.at_grid_footprint(ctypes.byref(d), ctypes.byref(b)) == L.AT_OK
+    # header 256 + bits 256 + list 2048 + 2 channels * 512 blocks * 2 KiB
+    assert b.value == 256 + 256 + 2048 + 2 * 512 * 2048
+    d = _desc(64, L.AT_ROOT_POINTER, 3, 100)
+    assert lib.at_grid_footprint(ctypes.byref(d), ctypes.byref(b)) == L.AT_OK
+    assert b.value == 256 + 256 + 2048 + 512 + 3 * 100 * 2048
+    for bad in (_desc(60), _desc(0), _desc(64, 7), _desc(64, L.AT_ROOT_BITMASK, 0),
+                _desc(64, L.AT_ROOT_POINTER, 1, 0), _desc(64, L.AT_ROOT_POINTER, 1, 513)):
+        assert lib.at_grid_footprint(ctypes.byref(bad), ctypes.byref(b)) == L.AT_E_INVALID
+        assert lib.at_last_error()
+    nc = L.AtGridDesc((64, 64, 32), 0, 1, 0)
+    assert lib.at_grid_footprint(ctypes.byref(nc), ctypes.byref(b)) == L.AT_E_UNSUPPORTED
+
+
+def test_planning_handle_rejects_device_calls():
+    lib = L.lib()
+    d = _desc(32)
+    h = ctypes.c_void_p()
+    assert lib.at_grid_create(ctypes.byref(d), None, 0, None, ctypes.byref(h)) == L.AT_OK
+    assert lib.at_listgen(h, None) == L.AT_E_STATE
+    assert lib.at_grid_views(h, None, None, None, None) == L.AT_E_STATE
+    bits = ctypes.c_int32()
+    assert lib.at_device_status(h, None, 0, ctypes.byref(bits)) == L.AT_E_STATE
+    assert lib.at_grid_destroy(h) == L.AT_OK
+    assert lib.at_grid_destroy(None) == L.AT_E_INVALID
+
+
+def test_create_rejects_small_or_misaligned_buffers():
+    lib = L.lib()
+    d = _desc(32)
+    h = ctypes.c_void_p()
+    assert lib.at_grid_create(ctypes.byref(d), ctypes.c_void_p(0x100000), 16, None, ctypes.byref(h)) == L.AT_E_INVALID
+    assert lib.at_grid_create(ctypes.byref(d), ctypes.c_void_p(0x100010), 1 << 30, None, ctypes.byref(h)) == L.AT_E_INVALID
+
+
+def test_task_validation_enqueues_nothing():
+    lib = L.lib()
+    d = _desc(32, L.AT_ROOT_BITMASK, 2)
+    h = ctypes.c_void_p()
+    assert lib.at_grid_create(ctypes.byref(d), None, 0, None, ctypes.byref(h)) == L.AT_OK
+    before = lib.at_dispatch_count()
+    t = L.AtTask()
+    t.kind, t.op, t.grid = L.AT_TASK_STENCIL, 99, h.value
+    for q in range(8):
+        t.ch[q] = -1
+    st = L.AtStats()
+    assert lib.at_run_sequence(ctypes.byref(t), 1, L.AT_OPT_ALL, ctypes.byref(st), None) == L.AT_E_INVALID
+    t.op = L.AT_OP_JACOBI
+    t.ch[0], t.ch[1], t.ch[2] = 0, 1, 5          # channel out of range
+    assert lib.at_run_sequence(ctypes.byref(t), 1, L.AT_OPT_ALL, ctypes.byref(st), None) == L.AT_E_INVALID
+    t.ch[2] = 0                                   # output aliases the stencil input
+    assert lib.at_run_sequence(ctypes.byref(t), 1, 0, ctypes.byref(st), None) == L.AT_E_INVALID
+    assert lib.at_run_sequence(ctypes.byref(t), 1, 1 << 7, ctypes.byref(st), None) == L.AT_E_INVALID
+    t.reserved = 1
+    assert lib.at_run_sequence(ctypes.byref(t), 1, 0, ctypes.byref(st), None) == L.AT_E_INVALID
+    assert lib.at_dispatch_count() == before
+    assert lib.at_grid_destroy(h) == L.AT_OK
+
+
+def test_options_roundtrip():
+    lib = L.lib()
+    v = ctypes.c_int64()
+    assert lib.at_set_option(L.AT_OPTION_MAX_FUSE_PER_TASK, 2) == L.AT_OK
+    assert lib.at_get_option(L.AT_OPTION_MAX_FUSE_PER_TASK, ctypes.byref(v)) == L.AT_OK and v.value == 2
+    assert lib.at_set_option(L.AT_OPTION_MAX_FUSE_PER_TASK, 1) == L.AT_OK
+    assert lib.at_set_option(L.AT_OPTION_MAX_FUSE_PER_TASK, 0) == L.AT_E_INVALID
+    assert lib.at_set_option(999, 0) == L.AT_E_INVALID
+    assert lib.at_version().startswith(b"atsparse")

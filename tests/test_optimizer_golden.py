@@ -1,0 +1,91 @@
+"""Golden plans of the inter-kernel optimizer for the paper's worked examples
+(tests/golden/*.json, each citing its passage).  Host only: the grids are
+planning handles without device memory."""
+import glob
+import json
+import os
+
+import pytest
+
+from paper_2012_08141_amd import _lib as L
+from paper_2012_08141_amd import engine as E
+from paper_2012_08141_amd.grid import SparseGrid
+
+GOLDEN = sorted(glob.glob(os.path.join(os.path.dirname(__file__), "golden", "*.json")))
+
+
+class FakeArray:
+    """Stands in for a device array in planning (only its address and length
+    matter to the planner)."""
+    _next = 0x10000
+
+    def __init__(self, n, comps=1):
+        self.shape = (comps, n) if comps > 1 else (n,)
+        self._p = FakeArray._next
+        FakeArray._next += 1 << 20
+
+    def data_ptr(self):
+        return self._p
+
+
+def build(fx):
+    grids = {}
+    for name, g in fx["grids"].items():
+        grids[name] = SparseGrid(g["n"], g["channels"], g["root"], g.get("capacity", 0), device=None)
+    arrays = {}
+    for name, n in fx.get("arrays", {}).items():
+        arrays[name] = FakeArray(n, 1 if name == "m" else 3)
+    tasks = []
+    for op in fx["program"]:
+        k = op[0]
+        if k == "listgen":
+            tasks.append(E.listgen(grids[op[1]]))
+        elif k == "inc":
+            tasks.append(E.inc(grids[op[1]], op[2], op[3]))
+        elif k == "fill":
+            tasks.append(E.fill(grids[op[1]], op[2], op[3]))
+        elif k == "copy":
+            tasks.append(E.copy(grids[op[1]], op[2], op[3]))
+        elif k == "lap_update":
+            tasks.append(E.lap_update(grids[op[1]], op[2], op[3], op[4]))
+        elif k == "jacobi":
+            tasks.append(E.jacobi(grids[op[1]], op[2], op[3], op[4]))
+        elif k == "advect":
+            tasks.append(E.advect(arrays[op[1]], arrays[op[2]], op[3], unique=op[4]))
+        elif k == "p2g":
+            tasks.append(E.p2g(grids[op[1]], arrays[op[2]], arrays[op[3]], arrays[op[4]], op[5], 0, 1))
+        elif k == "g2p":
+            tasks.append(E.g2p(grids[op[1]], arrays[op[2]], arrays[op[3]], op[4], 4))
+        else:
+            raise ValueError(k)
+    return grids, tasks
+
+
+@pytest.mark.parametrize("path", GOLDEN, ids=[os.path.basename(p) for p in GOLDEN])
+def test_golden_plan(path):
+    fx = json.load(open(path))
+    assert fx["citation"]
+    E.reset()
+    grids, tasks = build(fx)
+    for case in fx["cases"]:
+        entries, st = E.plan_sequence(tasks, case["flags"])
+        plan = [e["members"] for e in entries]
+        if "plan" in case:
+            assert plan == case["plan"], (case["flags"], plan)
+        if "paper_tasks" in case:
+            assert E.paper_task_count(entries) == case["paper_tasks"]
+        for k, v in case.get("counters", {}).items():
+            assert st[k] == v, (k, st)
+        for ti, kept in case.get("fill_kept", {}).items():
+            ti = int(ti)
+            ent = [e for e in entries if e["members"][0] == ti]
+            assert ent, "task %d vanished" % ti
+            mask = ent[0]["fill_channels"]
+            chans = [c for q, c in enumerate(fx["program"][ti][2]) if (mask >> q) & 1]
+            assert chans == kept
+        for a, b in case.get("separate", []):
+            assert not any(a in m and b in m for m in plan), plan
+        # every plan entry is a topological order of the eager program:
+        # members keep program order inside a fused task
+        for m in plan:
+            assert m == sorted(m)
