@@ -88,9 +88,11 @@ at_status at_grid_destroy(at_grid grid);
 
 /* Device pointers into the grid's buffer.  ch_base[c] (array of `channels`
  * entries, may be NULL) receives the base of channel c (capacity_blocks*512
- * floats, indexed by slot*512 + voxel).  *list receives the list state
- * (int32 root cells, capacity min(R^3, capacity_blocks)), *count its int32
- * length, *root the root table (bitmask root: uint32[ceil(R^3/32)] bits;
+ * floats, indexed by slot*512 + voxel).  *list receives the list state:
+ * capacity min(R^3, capacity_blocks) records of 8 int32 -- root cell, leaf
+ * slot, and the slots of the six face neighbours (i-1, i+1, j-1, j+1, k-1,
+ * k+1; -1 inactive or outside) as of the list generation; *count its int32
+ * length; *root the root table (bitmask root: uint32[ceil(R^3/32)] bits;
  * pointer root: int32[R^3] slot or -1).  Any out-pointer may be NULL. */
 at_status at_grid_views(at_grid grid, float **ch_base, const int32_t **list,
                         const int32_t **count, const void **root);
@@ -129,8 +131,9 @@ at_status at_active_count(at_grid grid, hipStream_t stream, int64_t *count);
 at_status at_activate(at_grid grid, const int32_t *d_ijk, int64_t n, int32_t coord_kind,
                       hipStream_t stream);
 
-/* List generation (Section 3, item 2): write the grid's list state -- the
- * active root cells in ascending linear order -- and its device count.  The
+/* List generation (Section 3, item 2): write the grid's list state -- a
+ * record per active root cell, in ascending cell order, carrying the cell's
+ * leaf slot and its face neighbours' slots -- and its device count.  The
  * list-clearing step is folded in (one dispatch). */
 at_status at_listgen(at_grid grid, hipStream_t stream);
 
@@ -301,6 +304,48 @@ at_status at_engine_reset(void);
 /* Tell the engine an external array was written outside its tasks (bumps
  * the array's state version so no earlier result is reused). */
 at_status at_ext_modified(const void *ptr);
+
+/* ------------------------------------------------------------- batching
+ * Many independent Jacobi solves (the 7-point Jacobi sweep and copy of
+ * AT_OP_JACOBI / AT_OP_COPY, same arithmetic) over pointer-rooted grids of
+ * one domain size whose leaves share one pool.  The caller owns admission:
+ * it writes each grid's root row (pool slot per root cell, -1 inactive), its
+ * pool leaves (x, b), the work list (entries grid * R^3 + cell, count) and
+ * the grid's iteration window [start, end) in global iterations, through the
+ * device views below, on the same stream.  at_batch_jacobi advances every
+ * listed block whose grid is active at global iteration clock + i, for
+ * i = 0 .. iters-1, then adds iters to the device clock.  Because all
+ * per-launch state lives in device memory, the launches of one call can be
+ * captured once in a HIP graph and replayed while grids come and go. */
+typedef struct at_batch_s *at_batch;
+
+typedef struct at_batch_desc {
+    int32_t n;            /* domain edge of every grid (multiple of 8, R^3 <= 2^20) */
+    int32_t max_grids;    /* grids that can be resident at once */
+    int32_t pool_blocks;  /* shared leaf pool size */
+    int32_t reserved;     /* must be 0 */
+} at_batch_desc;
+
+typedef struct at_batch_views {
+    int64_t *clock;       /* global iteration counter (device) */
+    int32_t *count;       /* work list length (device) */
+    int64_t *window;      /* [max_grids][2] first and one-past-last active iteration */
+    int32_t *roots;       /* [max_grids][R^3] pool slot or -1 */
+    int32_t *work;        /* [pool_blocks] grid * R^3 + cell */
+    float *x, *xn, *b;    /* [pool_blocks][512] */
+} at_batch_views;
+
+at_status at_batch_footprint(const at_batch_desc *desc, size_t *bytes);
+/* Lays the batch out in the caller's buffer and enqueues its initialisation
+ * (clock 0, empty work list, all windows empty, roots -1, pool zero). */
+at_status at_batch_create(const at_batch_desc *desc, void *dev_buf, size_t bytes, hipStream_t stream,
+                          at_batch *out);
+at_status at_batch_destroy(at_batch batch);
+at_status at_batch_get_views(at_batch batch, at_batch_views *views);
+/* iters x (jacobi, copy) then the clock tick: 2*iters + 1 dispatches, no
+ * host synchronisation, no fills (safe to capture in a graph).  workgroups:
+ * persistent grid size (0 = automatic). */
+at_status at_batch_jacobi(at_batch batch, int32_t iters, int32_t workgroups, hipStream_t stream);
 
 /* Total device dispatches issued by the library since load. */
 int64_t at_dispatch_count(void);

@@ -55,6 +55,15 @@ class AtStats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class AtBatchDesc(ctypes.Structure):
+    _fields_ = [("n", c_int32), ("max_grids", c_int32), ("pool_blocks", c_int32), ("reserved", c_int32)]
+
+
+class AtBatchViews(ctypes.Structure):
+    _fields_ = [("clock", c_void_p), ("count", c_void_p), ("window", c_void_p), ("roots", c_void_p),
+                ("work", c_void_p), ("x", c_void_p), ("xn", c_void_p), ("b", c_void_p)]
+
+
 class AtPlanEntry(ctypes.Structure):
     _fields_ = [("kind", c_int32), ("nmembers", c_int32), ("members", c_int32 * AT_PLAN_MAX_MEMBERS),
                 ("check_activation", c_int32), ("activation_mode", c_int32), ("dropped", c_uint32),
@@ -88,6 +97,11 @@ _SIGS = {
     "at_get_option": (c_int32, [c_int32, ctypes.POINTER(c_int64)]),
     "at_engine_reset": (c_int32, []),
     "at_ext_modified": (c_int32, [_P]),
+    "at_batch_footprint": (c_int32, [ctypes.POINTER(AtBatchDesc), ctypes.POINTER(c_size_t)]),
+    "at_batch_create": (c_int32, [ctypes.POINTER(AtBatchDesc), _P, c_size_t, _P, ctypes.POINTER(_P)]),
+    "at_batch_destroy": (c_int32, [_P]),
+    "at_batch_get_views": (c_int32, [_P, ctypes.POINTER(AtBatchViews)]),
+    "at_batch_jacobi": (c_int32, [_P, c_int32, c_int32, _P]),
     "at_dispatch_count": (c_int64, []),
     "at_last_error": (ctypes.c_char_p, []),
     "at_version": (ctypes.c_char_p, []),

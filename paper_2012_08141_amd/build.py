@@ -15,7 +15,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 INC = ["-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
-             "-munsafe-fp-atomics", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+             "-munsafe-fp-atomics", "-mllvm", "-disable-promote-alloca-to-lds", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__",
              "-I" + os.path.join(ROCM, "include")]
 

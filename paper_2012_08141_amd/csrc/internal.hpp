@@ -28,11 +28,15 @@ struct GridDev {
     int64_t ncells;     // R^3
     uint32_t *bits;     // activity bits, one per root cell (both root kinds)
     int32_t *ptr;       // pointer root: slot per cell; bitmask root: nullptr
-    int32_t *list;      // list state: root cells
+    int32_t *list;      // list state: records {cell, slot, 6 face-neighbour slots} (8 int32 each)
     int32_t *hdr;       // device header words
     float *chan;        // channel 0 base; channel c at chan + c * ch_stride
     int64_t ch_stride;  // floats per channel (cap * 512)
+    uint64_t *scan;     // list generation look-back flags (kScanFlags entries)
 };
+
+constexpr int kScanFlags = 1024;   // = maximum workgroups of one list generation
+constexpr int kRec = 8;            // int32 words per list record
 
 // One op of a fused (or elementwise) struct-for program, applied per voxel
 // in program order.
@@ -46,6 +50,7 @@ struct MicroOp {
 struct MicroProg {
     int32_t nops;
     int32_t check;    // eager activation check on writes
+    int32_t table;    // neighbour slots from the list records (mask unchanged since listgen)
     MicroOp ops[kMaxOps];
 };
 
@@ -67,12 +72,25 @@ struct PartProg {
     GridDev gsrc, gdst;
 };
 
+// Batched Jacobi over many pointer-rooted grids sharing one leaf pool.
+struct BatchDev {
+    int32_t R, R2, ncells;   // per-grid root edge, R^2, R^3
+    int32_t max_grids;
+    int32_t pool;            // leaf pool size (blocks)
+    int64_t *clock;          // global iteration counter
+    int32_t *count;          // work list length
+    int64_t *window;         // [max_grids][2]: first and one-past-last active iteration
+    int32_t *roots;          // [max_grids][R^3]: pool slot or -1
+    int32_t *work;           // [pool]: grid * R^3 + cell
+    float *x, *xn, *b;       // [pool][512]
+};
+
 // Kernel launchers (kernels.hip).  Each enqueues exactly one dispatch on the
 // stream and returns the launch status.
 hipError_t launch_activate(const GridDev &g, const int32_t *ijk, int64_t n, int coord_kind,
                            hipStream_t s);
-hipError_t launch_listgen(const GridDev &g, hipStream_t s);
-hipError_t launch_stencil(const GridDev &g, int op, const int32_t *ch, float p, int check,
+hipError_t launch_listgen(const GridDev &g, uint64_t *flags, uint32_t epoch, hipStream_t s);
+hipError_t launch_stencil(const GridDev &g, int op, const int32_t *ch, float p, int check, int table,
                           hipStream_t s);
 hipError_t launch_micro(const GridDev &g, const MicroProg &prog, hipStream_t s);
 hipError_t launch_particles(const PartProg &prog, hipStream_t s);
@@ -81,6 +99,8 @@ hipError_t launch_scatter_blocks(const GridDev &g, int ch, const int32_t *cells,
 hipError_t launch_gather_blocks(const GridDev &g, int ch, const int32_t *cells, float *vals,
                                 int64_t n, hipStream_t s);
 hipError_t launch_popcount(const GridDev &g, hipStream_t s);   // into hdr[HDR_SCRATCH]
+// iters x (jacobi, copy) over the work list, then clock += iters (2*iters + 1 dispatches).
+hipError_t launch_batch_jacobi(const BatchDev &d, int iters, int workgroups, hipStream_t s);
 // Persistent grid size used by struct-for kernels (workgroups).
 int struct_for_grid_size(const GridDev &g);
 void set_struct_for_grid_size(int wgs);   // 0 = automatic
@@ -93,6 +113,7 @@ struct at_grid_s {
     ats::GridDev dev;
     uint64_t uid;       // engine identity (never reused)
     bool virt;          // planning handle without device memory
+    uint32_t listgen_epoch;   // distinguishes list generation launches (never 0)
     size_t bytes;
     int32_t list_cap;
 };

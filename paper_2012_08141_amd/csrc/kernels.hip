@@ -17,7 +17,6 @@ namespace ats {
 namespace {
 
 constexpr int kSFThreads = 128;          // struct-for workgroup
-constexpr int kTile = 1600;              // 10 x 10 x 16 floats (k padded to 16)
 constexpr int kSpinLimit = 1 << 22;      // bounded wait on a pointer-root allocation
 int g_sf_grid_override = 0;
 
@@ -49,12 +48,14 @@ __device__ __forceinline__ int32_t slot_of(const GridDev &g, int64_t c) {
 template <int KIND>
 __device__ __forceinline__ int32_t activate_cell(const GridDev &g, int64_t c) {
     const uint32_t m = 1u << (c & 31);
+    // A plain load may return a stale value; staleness only ever shows an
+    // active block as inactive (activity never reverts inside a kernel),
+    // which sends the thread down the atomic path below -- still correct.
     if (KIND == AT_ROOT_BITMASK) {
-        const uint32_t w = __hip_atomic_load(&g.bits[c >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (!(w & m)) atomicOr(&g.bits[c >> 5], m);
+        if (!(g.bits[c >> 5] & m)) atomicOr(&g.bits[c >> 5], m);
         return (int32_t)c;
     }
-    int32_t s = __hip_atomic_load(&g.ptr[c], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    int32_t s = g.ptr[c];
     if (s == PTR_NULL) {
         const int32_t old = atomicCAS(&g.ptr[c], PTR_NULL, PTR_LOCKED);
         if (old == PTR_NULL) {
@@ -136,58 +137,138 @@ __global__ __launch_bounds__(256) void k_activate(GridDev g, const int32_t *ijk,
 }
 
 // --------------------------------------------------------- list generation
-// One workgroup of 1024 threads.  Thread t owns a contiguous run of mask
-// words; a block-wide exclusive scan of per-thread popcounts gives every
-// thread its output offset, so the list comes out in ascending cell order
-// with no atomics.  The count is written by the last thread (the clear of
-// the previous list is folded in: the count is simply overwritten).
-__global__ __launch_bounds__(1024) void k_listgen(GridDev g) {
-    __shared__ int wsum[16];
-    const int64_t W = (g.ncells + 31) >> 5;
-    const int tid = threadIdx.x;
-    const int T = blockDim.x;
-    const int64_t per = (W + T - 1) / T;
-    const int64_t w0 = min((int64_t)tid * per, W);
-    const int64_t w1 = min(w0 + per, W);
-    const uint32_t tail = (g.ncells & 31) ? ((1u << (g.ncells & 31)) - 1u) : 0xffffffffu;
-    int cnt = 0;
-    for (int64_t w = w0; w < w1; ++w) {
-        uint32_t b = g.bits[w];
-        if (w == W - 1) b &= tail;
-        cnt += __popc(b);
-    }
-    const int incl = wave_incl_scan(cnt);
-    const int lane = tid & 63, wid = tid >> 6, nw = (T + 63) >> 6;
-    if (lane == 63) wsum[wid] = incl;
-    __syncthreads();
-    if (wid == 0) {
-        const int v = lane < nw ? wsum[lane] : 0;
-        const int iv = wave_incl_scan(v);
-        if (lane < nw) wsum[lane] = iv - v;
-    }
-    __syncthreads();
-    int pos = wsum[wid] + incl - cnt;
-    for (int64_t w = w0; w < w1; ++w) {
-        uint32_t b = g.bits[w];
-        if (w == W - 1) b &= tail;
-        while (b) {
-            const int bit = __builtin_ctz(b);
-            g.list[pos++] = (int32_t)(w * 32 + bit);
-            b &= b - 1;
-        }
-    }
-    if (tid == T - 1) g.hdr[HDR_COUNT] = pos;
+// Workgroup b (256 threads) owns words [b*256*WPT, (b+1)*256*WPT) of the
+// activity bits; thread t of it owns WPT consecutive words.  A block scan of
+// per-thread popcounts gives offsets inside the workgroup; the workgroup's
+// base offset comes from a single-pass decoupled look-back over its
+// predecessors' published aggregates (flags[b] = epoch:32 | status:2 |
+// value:30, status 1 = aggregate, 2 = inclusive prefix).  The host passes a
+// fresh epoch per launch, so stale flags of an earlier launch are never
+// mistaken for current ones and need no clearing.  Workgroups are
+// dispatched in index order and every predecessor is resident or finished,
+// so the bounded wait always ends.  The list comes out in ascending cell
+// order; the last workgroup writes the count (the list clear is folded in).
+constexpr int kScanMaxWG = 1024;
+enum : uint32_t { SCAN_AGG = 1, SCAN_INCL = 2 };
+
+__device__ __forceinline__ uint64_t scan_flag(uint32_t epoch, uint32_t status, uint32_t value) {
+    return ((uint64_t)epoch << 32) | ((uint64_t)status << 30) | (uint64_t)value;
 }
 
-// ----------------------------------------------------- 7-point stencils (LDS)
-// The block plus a one-voxel face halo is staged in an LDS tile of
-// 10 x 10 x 16 floats per stencil-read channel: plane stride 160, row stride
-// 16, local k at column k + 4 so every interior row is two aligned float4s.
-// Halo faces come from the six face-neighbour blocks (zeros when inactive or
-// outside the domain): i and j faces as float4 rows, k faces as scalars.
+// Block record written for each list entry: the root cell, its leaf slot
+// and the slots of its six face neighbours (order i-1, i+1, j-1, j+1, k-1,
+// k+1; -1 when inactive or outside the domain), as of this list generation.
+template <int KIND>
+__device__ __forceinline__ void write_record(const GridDev &g, int32_t cell, int pos) {
+    int bi, bj, bk;
+    cell_coords(g, cell, bi, bj, bk);
+    const int32_t slot = (KIND == AT_ROOT_BITMASK) ? cell : g.ptr[cell];
+    const int32_t n0 = bi > 0 ? slot_of<KIND>(g, cell - g.R2) : -1;
+    const int32_t n1 = bi < g.R - 1 ? slot_of<KIND>(g, cell + g.R2) : -1;
+    const int32_t n2 = bj > 0 ? slot_of<KIND>(g, cell - g.R) : -1;
+    const int32_t n3 = bj < g.R - 1 ? slot_of<KIND>(g, cell + g.R) : -1;
+    const int32_t n4 = bk > 0 ? slot_of<KIND>(g, cell - 1) : -1;
+    const int32_t n5 = bk < g.R - 1 ? slot_of<KIND>(g, cell + 1) : -1;
+    int4 *r = reinterpret_cast<int4 *>(g.list + (int64_t)pos * kRec);
+    r[0] = make_int4(cell, slot, n0, n1);
+    r[1] = make_int4(n2, n3, n4, n5);
+}
+
+// Thread t of workgroup b owns C consecutive root cells (C = 8 or 16: part
+// of one bit word; C >= 32: C/32 whole words), so a dense run of active
+// cells is spread over many threads and many workgroups.
+template <int KIND, int C>
+__global__ __launch_bounds__(256) void k_listgen(GridDev g, uint64_t *flags, uint32_t epoch) {
+    constexpr int WPT = C >= 32 ? C / 32 : 1;
+    __shared__ int wsum[4];
+    __shared__ int s_base;
+    const int64_t W = (g.ncells + 31) >> 5;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wid = tid >> 6;
+    const uint32_t tail = (g.ncells & 31) ? ((1u << (g.ncells & 31)) - 1u) : 0xffffffffu;
+    const int64_t c0 = ((int64_t)blockIdx.x * 256 + tid) * C;   // first cell of this thread
+    uint32_t b[WPT];
+    if (C < 32) {
+        const int64_t w = c0 >> 5;
+        uint32_t v = w < W ? g.bits[w] : 0u;
+        if (w == W - 1) v &= tail;
+        b[0] = (v >> (c0 & 31)) & ((1u << (C & 31)) - 1u);
+    } else {
+#pragma unroll
+        for (int q = 0; q < WPT; ++q) {
+            const int64_t w = (c0 >> 5) + q;
+            uint32_t v = w < W ? g.bits[w] : 0u;
+            if (w == W - 1) v &= tail;
+            b[q] = v;
+        }
+    }
+    int cnt = 0;
+#pragma unroll
+    for (int q = 0; q < WPT; ++q) cnt += __popc(b[q]);
+    const int incl = wave_incl_scan(cnt);
+    if (lane == 63) wsum[wid] = incl;
+    __syncthreads();
+    const int before = (wid > 0 ? wsum[0] : 0) + (wid > 1 ? wsum[1] : 0) + (wid > 2 ? wsum[2] : 0);
+    const int total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    if (tid == 0) {
+        const int bid = blockIdx.x;
+        int base = 0;
+        if (bid == 0) {
+            __hip_atomic_store(&flags[0], scan_flag(epoch, SCAN_INCL, (uint32_t)total), __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_store(&flags[bid], scan_flag(epoch, SCAN_AGG, (uint32_t)total), __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            int j = bid - 1;
+            for (int it = 0; j >= 0; ++it) {
+                const uint64_t f = __hip_atomic_load(&flags[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t st = (uint32_t)(f >> 30) & 3u;
+                if ((uint32_t)(f >> 32) != epoch || st == 0) {
+                    if (it >= kSpinLimit) {
+                        atomicOr(&g.hdr[HDR_ERR], ERR_SPIN);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                base += (int)(f & 0x3fffffffu);
+                if (st == SCAN_INCL) break;
+                --j;
+            }
+            __hip_atomic_store(&flags[bid], scan_flag(epoch, SCAN_INCL, (uint32_t)(base + total)), __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        s_base = base;
+        if (bid == (int)gridDim.x - 1) g.hdr[HDR_COUNT] = base + total;
+    }
+    __syncthreads();
+    int pos = s_base + before + incl - cnt;
+#pragma unroll
+    for (int q = 0; q < WPT; ++q) {
+        uint32_t v = b[q];
+        const int64_t cb = C < 32 ? c0 : c0 + 32 * q;
+        while (v) {
+            const int bit = __builtin_ctz(v);
+            write_record<KIND>(g, (int32_t)(cb + bit), pos++);
+            v &= v - 1;
+        }
+    }
+}
+
+// ------------------------------------------------------ 7-point stencils
+// One wavefront per block: lane l owns row (i, j) = (l >> 3, l & 7) of the
+// block, i.e. the 8 consecutive voxels [8l, 8l+8) as two float4.  The i+-1
+// and j+-1 neighbour rows are rows of the same block (lane +-8, +-1) or of
+// the face-neighbour block; the k-1 / k+1 values beyond the row are single
+// floats of the k-neighbour blocks.  Every lane issues all of its loads at
+// once and unconditionally (an absent neighbour loads a valid dummy address
+// and is zeroed by a select), so a block costs one dependent step (the six
+// neighbour slots, looked up by lanes 0..5 and broadcast with readlane) plus
+// one round of independent loads; there is no LDS and no barrier, and many
+// small wavefronts per CU hide the latency.
 
 struct StencilCh {
-    const float *tin[3];  // stencil-read channels (tile order)
+    const float *tin[3];  // stencil-read channels
     const float *ein;     // elementwise input (JACOBI: b; DIFFUSE_ADJ: gk)
     float *out0;          // output (LAP/DIFFUSE: out; JACOBI: xn; ADJ: lam)
     float *out1;          // DIFFUSE_ADJ: gk
@@ -197,31 +278,79 @@ template <int OP> struct NTiles { static constexpr int v = 1; };
 template <> struct NTiles<AT_OP_DIFFUSE> { static constexpr int v = 2; };
 template <> struct NTiles<AT_OP_DIFFUSE_ADJ> { static constexpr int v = 3; };
 
-// Values around the thread's four voxels: c[q] centre, f[face][q] the
+// Row values around a lane's 8 voxels: c[q] centre, f[face][q] the
 // neighbour across `face` (order i-1, i+1, j-1, j+1, k-1, k+1).
-struct Around {
-    float c[4];
-    float f[6][4];
+struct Row {
+    float c[8];
+    float f[6][8];
 };
 
-__device__ __forceinline__ void gather_around(const float *tile, int rb, Around &a) {
-    const float4 C = *reinterpret_cast<const float4 *>(tile + rb);
-    const float4 IM = *reinterpret_cast<const float4 *>(tile + rb - 160);
-    const float4 IP = *reinterpret_cast<const float4 *>(tile + rb + 160);
-    const float4 JM = *reinterpret_cast<const float4 *>(tile + rb - 16);
-    const float4 JP = *reinterpret_cast<const float4 *>(tile + rb + 16);
-    const float KL = tile[rb - 1];
-    const float KR = tile[rb + 4];
-    a.c[0] = C.x; a.c[1] = C.y; a.c[2] = C.z; a.c[3] = C.w;
-    a.f[0][0] = IM.x; a.f[0][1] = IM.y; a.f[0][2] = IM.z; a.f[0][3] = IM.w;
-    a.f[1][0] = IP.x; a.f[1][1] = IP.y; a.f[1][2] = IP.z; a.f[1][3] = IP.w;
-    a.f[2][0] = JM.x; a.f[2][1] = JM.y; a.f[2][2] = JM.z; a.f[2][3] = JM.w;
-    a.f[3][0] = JP.x; a.f[3][1] = JP.y; a.f[3][2] = JP.z; a.f[3][3] = JP.w;
-    a.f[4][0] = KL;   a.f[4][1] = C.x;  a.f[4][2] = C.y;  a.f[4][3] = C.z;
-    a.f[5][0] = C.y;  a.f[5][1] = C.z;  a.f[5][2] = C.w;  a.f[5][3] = KR;
+__device__ __forceinline__ void put8(float *d, float4 a, float4 b) {
+    d[0] = a.x; d[1] = a.y; d[2] = a.z; d[3] = a.w; d[4] = b.x; d[5] = b.y; d[6] = b.z; d[7] = b.w;
 }
 
-__device__ __forceinline__ float nbsum(const Around &a, int q) {
+// Neighbour block slots of the wave's block, uniform across the wave.
+struct Nbs {
+    int32_t s[6];
+};
+
+template <int KIND>
+__device__ __forceinline__ Nbs neighbour_slots(const GridDev &g, int32_t cell) {
+    int bi, bj, bk;
+    cell_coords(g, cell, bi, bj, bk);
+    const int lane = threadIdx.x & 63;
+    int32_t mine = -1;
+    if (lane < 6) {
+        bool ok;
+        int64_t d;
+        switch (lane) {
+        case 0: ok = bi > 0; d = -(int64_t)g.R2; break;
+        case 1: ok = bi < g.R - 1; d = g.R2; break;
+        case 2: ok = bj > 0; d = -(int64_t)g.R; break;
+        case 3: ok = bj < g.R - 1; d = g.R; break;
+        case 4: ok = bk > 0; d = -1; break;
+        default: ok = bk < g.R - 1; d = 1; break;
+        }
+        if (ok) mine = slot_of<KIND>(g, cell + d);
+    }
+    Nbs n;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) n.s[f] = __builtin_amdgcn_readlane(mine, f);
+    return n;
+}
+
+// Load the rows around this lane from channel `ch` (block slot `slot`).
+__device__ __forceinline__ void load_row(const float *ch, int32_t slot, const Nbs &n, int lane, Row &r) {
+    const int li = lane >> 3, lj = lane & 7;
+    const int64_t own = (int64_t)slot * kBV;
+    auto row_at = [&](bool inside, int in_row, int32_t nb, int nb_row, float *dst) {
+        const bool present = inside || nb >= 0;
+        const int64_t base = inside ? own + in_row * 8 : (nb >= 0 ? (int64_t)nb * kBV + nb_row * 8 : own);
+        const float4 a = *reinterpret_cast<const float4 *>(ch + base);
+        const float4 b = *reinterpret_cast<const float4 *>(ch + base + 4);
+        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+        put8(dst, present ? a : z, present ? b : z);
+    };
+    {
+        const float4 a = *reinterpret_cast<const float4 *>(ch + own + lane * 8);
+        const float4 b = *reinterpret_cast<const float4 *>(ch + own + lane * 8 + 4);
+        put8(r.c, a, b);
+    }
+    row_at(li > 0, lane - 8, n.s[0], lane + 56, r.f[0]);
+    row_at(li < 7, lane + 8, n.s[1], lane - 56, r.f[1]);
+    row_at(lj > 0, lane - 1, n.s[2], lane + 7, r.f[2]);
+    row_at(lj < 7, lane + 1, n.s[3], lane - 7, r.f[3]);
+    const float km = ch[(n.s[4] >= 0 ? (int64_t)n.s[4] * kBV : own) + lane * 8 + 7];
+    const float kp = ch[(n.s[5] >= 0 ? (int64_t)n.s[5] * kBV : own) + lane * 8 + 0];
+    r.f[4][0] = n.s[4] >= 0 ? km : 0.f;
+    r.f[5][7] = n.s[5] >= 0 ? kp : 0.f;
+#pragma unroll
+    for (int q = 1; q < 8; ++q) r.f[4][q] = r.c[q - 1];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) r.f[5][q] = r.c[q + 1];
+}
+
+__device__ __forceinline__ float nbsum(const Row &a, int q) {
     float s = a.f[0][q] + a.f[1][q];
     s = s + a.f[2][q];
     s = s + a.f[3][q];
@@ -230,119 +359,96 @@ __device__ __forceinline__ float nbsum(const Around &a, int q) {
     return s;
 }
 
-template <int OP, int KIND, bool CHECK>
-__global__ __launch_bounds__(kSFThreads) void k_stencil(GridDev g, StencilCh c, float p) {
-    constexpr int NT = NTiles<OP>::v;
-    __shared__ float4 tile4[NT * kTile / 4];
-    float *tile = reinterpret_cast<float *>(tile4);
-    const int t = threadIdx.x;
-    const int li = t >> 4, lj = (t >> 1) & 7, k0 = (t & 1) * 4;
-    const int rb = (li + 1) * 160 + (lj + 1) * 16 + 4 + k0;
+__device__ __forceinline__ void store8(float *d, const float *v) {
+    reinterpret_cast<float4 *>(d)[0] = make_float4(v[0], v[1], v[2], v[3]);
+    reinterpret_cast<float4 *>(d)[1] = make_float4(v[4], v[5], v[6], v[7]);
+}
+
+// The neighbour slots of a listed block: from its list record when the mask
+// is known unchanged since the list was generated (TABLE), else looked up in
+// the current root.
+template <int KIND, bool TABLE>
+__device__ __forceinline__ void read_record(const GridDev &g, int e, int32_t &cell, int32_t &slot, Nbs &n) {
+    const int4 *r = reinterpret_cast<const int4 *>(g.list + (int64_t)e * kRec);
+    const int4 a = r[0];
+    cell = a.x;
+    slot = a.y;
+    if (TABLE) {
+        const int4 b = r[1];
+        n.s[0] = a.z; n.s[1] = a.w; n.s[2] = b.x; n.s[3] = b.y; n.s[4] = b.z; n.s[5] = b.w;
+    } else {
+        n = neighbour_slots<KIND>(g, cell);
+    }
+}
+
+template <int OP, int KIND, bool CHECK, bool TABLE>
+__global__ __launch_bounds__(64) void k_stencil(GridDev g, StencilCh c, float p) {
+    const int lane = threadIdx.x;
     const ListRange lr = list_range(g.hdr[HDR_COUNT]);
     for (int e = lr.lo; e < lr.hi; e += lr.step) {
-        const int32_t cell = g.list[e];
-        int bi, bj, bk;
-        cell_coords(g, cell, bi, bj, bk);
-        const int32_t slot = (KIND == AT_ROOT_BITMASK) ? cell : g.ptr[cell];
-        __syncthreads();   // the previous block's tile reads are done
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const float4 v = reinterpret_cast<const float4 *>(c.tin[nt] + (int64_t)slot * kBV)[t];
-            *reinterpret_cast<float4 *>(tile + nt * kTile + rb) = v;
-        }
-        if (t < 64) {
-            const int face = t >> 4, q = t & 15, a = q >> 1, kk = (q & 1) * 4;
-            int64_t nc = -1;
-            int src, dst;
-            if (face == 0) {        // i-1: neighbour's i = 7 plane, row j = a
-                if (bi > 0) nc = cell - g.R2;
-                src = 7 * 64 + a * 8 + kk; dst = 0 * 160 + (a + 1) * 16 + 4 + kk;
-            } else if (face == 1) { // i+1: neighbour's i = 0 plane
-                if (bi < g.R - 1) nc = cell + g.R2;
-                src = 0 * 64 + a * 8 + kk; dst = 9 * 160 + (a + 1) * 16 + 4 + kk;
-            } else if (face == 2) { // j-1: neighbour's j = 7 rows, plane i = a
-                if (bj > 0) nc = cell - g.R;
-                src = a * 64 + 7 * 8 + kk; dst = (a + 1) * 160 + 0 * 16 + 4 + kk;
-            } else {                // j+1
-                if (bj < g.R - 1) nc = cell + g.R;
-                src = a * 64 + 0 * 8 + kk; dst = (a + 1) * 160 + 9 * 16 + 4 + kk;
-            }
-            const int32_t ns = nc >= 0 ? slot_of<KIND>(g, nc) : -1;
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (ns >= 0) v = *reinterpret_cast<const float4 *>(c.tin[nt] + (int64_t)ns * kBV + src);
-                *reinterpret_cast<float4 *>(tile + nt * kTile + dst) = v;
-            }
-        } else {
-            const int q = t - 64, a = q >> 3, b = q & 7;
-            const int32_t sm = bk > 0 ? slot_of<KIND>(g, cell - 1) : -1;
-            const int32_t sp = bk < g.R - 1 ? slot_of<KIND>(g, cell + 1) : -1;
-            const int row = (a + 1) * 160 + (b + 1) * 16;
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                tile[nt * kTile + row + 3] = sm >= 0 ? c.tin[nt][(int64_t)sm * kBV + a * 64 + b * 8 + 7] : 0.f;
-                tile[nt * kTile + row + 12] = sp >= 0 ? c.tin[nt][(int64_t)sp * kBV + a * 64 + b * 8 + 0] : 0.f;
-            }
-        }
-        __syncthreads();
+        int32_t cell, slot;
+        Nbs n;
+        read_record<KIND, TABLE>(g, e, cell, slot, n);
         int32_t wslot = slot;
-        if (CHECK) wslot = activate_cell<KIND>(g, cell);
-        const int64_t off = (int64_t)wslot * kBV + 4 * t;
+        if (CHECK) {
+            // activation on write of this block: one check per wavefront
+            int32_t a = 0;
+            if (lane == 0) a = activate_cell<KIND>(g, cell);
+            wslot = __builtin_amdgcn_readfirstlane(a);
+        }
+        const int64_t off = (int64_t)wslot * kBV + lane * 8;
+        const int64_t eoff = (int64_t)slot * kBV + lane * 8;
+        float r0[8], r1[8];
         if (OP == AT_OP_LAP_UPDATE) {
-            Around A;
-            gather_around(tile, rb, A);
-            float r[4];
+            Row A;
+            load_row(c.tin[0], slot, n, lane, A);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < 8; ++q) {
                 const float s = nbsum(A, q);
                 const float six_a = 6.0f * A.c[q];
                 const float d = s - six_a;
                 const float tq = p * d;
-                r[q] = A.c[q] + tq;
+                r0[q] = A.c[q] + tq;
             }
-            *reinterpret_cast<float4 *>(c.out0 + off) = make_float4(r[0], r[1], r[2], r[3]);
+            store8(c.out0 + off, r0);
         } else if (OP == AT_OP_JACOBI) {
-            Around X;
-            gather_around(tile, rb, X);
-            const float4 b = *reinterpret_cast<const float4 *>(c.ein + (int64_t)slot * kBV + 4 * t);
-            const float bb[4] = {b.x, b.y, b.z, b.w};
+            Row X;
+            load_row(c.tin[0], slot, n, lane, X);
+            float b[8];
+            put8(b, reinterpret_cast<const float4 *>(c.ein + eoff)[0], reinterpret_cast<const float4 *>(c.ein + eoff)[1]);
             const float sixth = 0x1.555556p-3f;
-            float r[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < 8; ++q) {
                 const float s = nbsum(X, q);
-                const float tq = s + bb[q];
-                r[q] = tq * sixth;
+                const float tq = s + b[q];
+                r0[q] = tq * sixth;
             }
-            *reinterpret_cast<float4 *>(c.out0 + off) = make_float4(r[0], r[1], r[2], r[3]);
+            store8(c.out0 + off, r0);
         } else if (OP == AT_OP_DIFFUSE) {
-            Around A, K;
-            gather_around(tile, rb, A);
-            gather_around(tile + kTile, rb, K);
-            float r[4];
+            Row A, K;
+            load_row(c.tin[0], slot, n, lane, A);
+            load_row(c.tin[1], slot, n, lane, K);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < 8; ++q) {
                 float f = 0.f;
 #pragma unroll
                 for (int fc = 0; fc < 6; ++fc) {
                     const float kf = 0.5f * (K.c[q] + K.f[fc][q]);
                     f = f + kf * (A.f[fc][q] - A.c[q]);
                 }
-                r[q] = A.c[q] + p * f;
+                r0[q] = A.c[q] + p * f;
             }
-            *reinterpret_cast<float4 *>(c.out0 + off) = make_float4(r[0], r[1], r[2], r[3]);
+            store8(c.out0 + off, r0);
         } else if (OP == AT_OP_DIFFUSE_ADJ) {
-            Around A, K, L;
-            gather_around(tile, rb, A);
-            gather_around(tile + kTile, rb, K);
-            gather_around(tile + 2 * kTile, rb, L);
-            const float4 gk4 = *reinterpret_cast<const float4 *>(c.ein + (int64_t)slot * kBV + 4 * t);
-            const float gk[4] = {gk4.x, gk4.y, gk4.z, gk4.w};
+            Row A, K, L;
+            load_row(c.tin[0], slot, n, lane, A);
+            load_row(c.tin[1], slot, n, lane, K);
+            load_row(c.tin[2], slot, n, lane, L);
+            float gk[8];
+            put8(gk, reinterpret_cast<const float4 *>(c.ein + eoff)[0], reinterpret_cast<const float4 *>(c.ein + eoff)[1]);
             const float half_dt = p * 0.5f;
-            float rl[4], rg[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < 8; ++q) {
                 float f = 0.f, q2 = 0.f;
 #pragma unroll
                 for (int fc = 0; fc < 6; ++fc) {
@@ -350,11 +456,11 @@ __global__ __launch_bounds__(kSFThreads) void k_stencil(GridDev g, StencilCh c, 
                     f = f + kf * (L.f[fc][q] - L.c[q]);
                     q2 = q2 + (A.f[fc][q] - A.c[q]) * (L.c[q] - L.f[fc][q]);
                 }
-                rl[q] = L.c[q] + p * f;
-                rg[q] = gk[q] + half_dt * q2;
+                r0[q] = L.c[q] + p * f;
+                r1[q] = gk[q] + half_dt * q2;
             }
-            *reinterpret_cast<float4 *>(c.out0 + off) = make_float4(rl[0], rl[1], rl[2], rl[3]);
-            *reinterpret_cast<float4 *>(c.out1 + off) = make_float4(rg[0], rg[1], rg[2], rg[3]);
+            store8(c.out0 + off, r0);
+            store8(c.out1 + off, r1);
         }
     }
 }
@@ -382,136 +488,208 @@ __device__ __forceinline__ float rd_nb(const GridDev &g, const float *base, int3
     return s >= 0 ? base[(int64_t)s * kBV + ii * 64 + jj * 8 + kk] : 0.f;
 }
 
-template <int KIND>
-__global__ __launch_bounds__(kSFThreads) void k_micro(GridDev g, MicroProg prog) {
-    const int t = threadIdx.x;
-    const int li = t >> 4, lj = (t >> 1) & 7, k0 = (t & 1) * 4;
-    bool has_stencil = false;
-    for (int o = 0; o < prog.nops; ++o) {
-        const int op = prog.ops[o].op;
-        has_stencil |= (op == AT_OP_LAP_UPDATE || op == AT_OP_JACOBI || op == AT_OP_DIFFUSE || op == AT_OP_DIFFUSE_ADJ);
-    }
+template <int KIND, bool STENCIL>
+__global__ __launch_bounds__(64) void k_micro(GridDev g, MicroProg prog) {
+    // one wavefront per block; lane l owns voxels [8l, 8l+8) = row
+    // (i, j) = (l >> 3, l & 7), handled as two float4 halves
+    const int lane = threadIdx.x;
+    const int li = lane >> 3, lj = lane & 7;
     const ListRange lr = list_range(g.hdr[HDR_COUNT]);
     for (int e = lr.lo; e < lr.hi; e += lr.step) {
-        const int32_t cell = g.list[e];
-        int32_t slot = (KIND == AT_ROOT_BITMASK) ? cell : g.ptr[cell];
+        const int4 rec0 = reinterpret_cast<const int4 *>(g.list + (int64_t)e * kRec)[0];
+        const int32_t cell = rec0.x;
+        int32_t slot = rec0.y;
         int32_t nbs[6] = {-1, -1, -1, -1, -1, -1};
-        if (has_stencil) {
-            int bi, bj, bk;
-            cell_coords(g, cell, bi, bj, bk);
-            if (bi > 0) nbs[0] = slot_of<KIND>(g, cell - g.R2);
-            if (bi < g.R - 1) nbs[1] = slot_of<KIND>(g, cell + g.R2);
-            if (bj > 0) nbs[2] = slot_of<KIND>(g, cell - g.R);
-            if (bj < g.R - 1) nbs[3] = slot_of<KIND>(g, cell + g.R);
-            if (bk > 0) nbs[4] = slot_of<KIND>(g, cell - 1);
-            if (bk < g.R - 1) nbs[5] = slot_of<KIND>(g, cell + 1);
+        if (STENCIL) {
+            Nbs n;
+            int32_t c2, s2;
+            if (prog.table) read_record<KIND, true>(g, e, c2, s2, n);
+            else n = neighbour_slots<KIND>(g, cell);
+            for (int f = 0; f < 6; ++f) nbs[f] = n.s[f];
         }
-        if (prog.check) slot = activate_cell<KIND>(g, cell);
-        const int64_t off = (int64_t)slot * kBV + 4 * t;
+        if (prog.check) {
+            int32_t a = 0;
+            if (lane == 0) a = activate_cell<KIND>(g, cell);
+            slot = __builtin_amdgcn_readfirstlane(a);
+        }
         for (int o = 0; o < prog.nops; ++o) {
             const MicroOp &op = prog.ops[o];
-            switch (op.op) {
-            case AT_OP_AXPY: {
-                float *y = chan(g, op.ch[0]) + off;
-                const float *x = chan(g, op.ch[1]) + off;
-                float4 yv = *reinterpret_cast<float4 *>(y);
-                const float4 xv = *reinterpret_cast<const float4 *>(x);
-                const float a = op.p;
-                yv.x = yv.x + a * xv.x; yv.y = yv.y + a * xv.y;
-                yv.z = yv.z + a * xv.z; yv.w = yv.w + a * xv.w;
-                *reinterpret_cast<float4 *>(y) = yv;
-                break;
-            }
-            case AT_OP_COPY:
-                *reinterpret_cast<float4 *>(chan(g, op.ch[0]) + off) =
-                    *reinterpret_cast<const float4 *>(chan(g, op.ch[1]) + off);
-                break;
-            case AT_OP_FILL:
-                for (int q = 0; q < 7; ++q)
-                    if (op.ch[q] >= 0 && ((op.keep >> q) & 1u))
-                        *reinterpret_cast<float4 *>(chan(g, op.ch[q]) + off) = make_float4(op.p, op.p, op.p, op.p);
-                break;
-            case AT_OP_INC: {
-                float4 *x = reinterpret_cast<float4 *>(chan(g, op.ch[0]) + off);
-                float4 v = *x;
-                v.x = v.x + op.p; v.y = v.y + op.p; v.z = v.z + op.p; v.w = v.w + op.p;
-                *x = v;
-                break;
-            }
-            case AT_OP_NORMALISE: {
-                const float4 m = *reinterpret_cast<const float4 *>(chan(g, op.ch[0]) + off);
-                const float mm[4] = {m.x, m.y, m.z, m.w};
-                for (int cc = 0; cc < 3; ++cc) {
-                    if (!((op.keep >> cc) & 1u)) continue;
-                    const float4 mv = *reinterpret_cast<const float4 *>(chan(g, op.ch[1] + cc) + off);
-                    const float mvv[4] = {mv.x, mv.y, mv.z, mv.w};
-                    float r[4];
-                    for (int q = 0; q < 4; ++q) r[q] = mm[q] > 0.f ? mvv[q] / mm[q] : 0.f;
-                    *reinterpret_cast<float4 *>(chan(g, op.ch[2] + cc) + off) = make_float4(r[0], r[1], r[2], r[3]);
+            for (int h = 0; h < 2; ++h) {
+                const int64_t off = (int64_t)slot * kBV + lane * 8 + 4 * h;
+                const int k0 = 4 * h;
+                switch (op.op) {
+                case AT_OP_AXPY: {
+                    float *y = chan(g, op.ch[0]) + off;
+                    const float *x = chan(g, op.ch[1]) + off;
+                    float4 yv = *reinterpret_cast<float4 *>(y);
+                    const float4 xv = *reinterpret_cast<const float4 *>(x);
+                    const float a = op.p;
+                    yv.x = yv.x + a * xv.x; yv.y = yv.y + a * xv.y;
+                    yv.z = yv.z + a * xv.z; yv.w = yv.w + a * xv.w;
+                    *reinterpret_cast<float4 *>(y) = yv;
+                    break;
                 }
-                break;
-            }
-            case AT_OP_LAP_UPDATE:
-            case AT_OP_JACOBI:
-            case AT_OP_DIFFUSE:
-            case AT_OP_DIFFUSE_ADJ: {
-                const float *A = chan(g, op.ch[0]);
-                float r0[4], r1[4];
-                for (int q = 0; q < 4; ++q) {
-                    const int lk = k0 + q;
-                    const float a = A[off + q];
-                    float nb[6];
-                    for (int fc = 0; fc < 6; ++fc) nb[fc] = rd_nb<KIND>(g, A, slot, nbs, li, lj, lk, fc);
-                    if (op.op == AT_OP_LAP_UPDATE || op.op == AT_OP_JACOBI) {
-                        float s = nb[0] + nb[1];
-                        s = s + nb[2]; s = s + nb[3]; s = s + nb[4]; s = s + nb[5];
-                        if (op.op == AT_OP_LAP_UPDATE) {
-                            const float six_a = 6.0f * a;
-                            const float d = s - six_a;
-                            const float tq = op.p * d;
-                            r0[q] = a + tq;
-                        } else {
-                            const float tq = s + chan(g, op.ch[1])[off + q];
-                            r0[q] = tq * 0x1.555556p-3f;
-                        }
-                    } else {
-                        const float *K = chan(g, op.ch[1]);
-                        const float kc = K[off + q];
-                        if (op.op == AT_OP_DIFFUSE) {
-                            float f = 0.f;
-                            for (int fc = 0; fc < 6; ++fc) {
-                                const float kf = 0.5f * (kc + rd_nb<KIND>(g, K, slot, nbs, li, lj, lk, fc));
-                                f = f + kf * (nb[fc] - a);
+                case AT_OP_COPY:
+                    *reinterpret_cast<float4 *>(chan(g, op.ch[0]) + off) =
+                        *reinterpret_cast<const float4 *>(chan(g, op.ch[1]) + off);
+                    break;
+                case AT_OP_FILL:
+                    for (int q = 0; q < 7; ++q)
+                        if (op.ch[q] >= 0 && ((op.keep >> q) & 1u))
+                            *reinterpret_cast<float4 *>(chan(g, op.ch[q]) + off) = make_float4(op.p, op.p, op.p, op.p);
+                    break;
+                case AT_OP_INC: {
+                    float4 *x = reinterpret_cast<float4 *>(chan(g, op.ch[0]) + off);
+                    float4 v = *x;
+                    v.x = v.x + op.p; v.y = v.y + op.p; v.z = v.z + op.p; v.w = v.w + op.p;
+                    *x = v;
+                    break;
+                }
+                case AT_OP_NORMALISE: {
+                    const float4 m = *reinterpret_cast<const float4 *>(chan(g, op.ch[0]) + off);
+                    const float mm[4] = {m.x, m.y, m.z, m.w};
+                    for (int cc = 0; cc < 3; ++cc) {
+                        if (!((op.keep >> cc) & 1u)) continue;
+                        const float4 mv = *reinterpret_cast<const float4 *>(chan(g, op.ch[1] + cc) + off);
+                        const float mvv[4] = {mv.x, mv.y, mv.z, mv.w};
+                        float r[4];
+                        for (int q = 0; q < 4; ++q) r[q] = mm[q] > 0.f ? mvv[q] / mm[q] : 0.f;
+                        *reinterpret_cast<float4 *>(chan(g, op.ch[2] + cc) + off) = make_float4(r[0], r[1], r[2], r[3]);
+                    }
+                    break;
+                }
+                case AT_OP_LAP_UPDATE:
+                case AT_OP_JACOBI:
+                case AT_OP_DIFFUSE:
+                case AT_OP_DIFFUSE_ADJ: {
+                    if (!STENCIL) break;
+                    const float *A = chan(g, op.ch[0]);
+                    float r0[4], r1[4];
+                    for (int q = 0; q < 4; ++q) {
+                        const int lk = k0 + q;
+                        const float a = A[off + q];
+                        float nb[6];
+                        for (int fc = 0; fc < 6; ++fc) nb[fc] = rd_nb<KIND>(g, A, slot, nbs, li, lj, lk, fc);
+                        if (op.op == AT_OP_LAP_UPDATE || op.op == AT_OP_JACOBI) {
+                            float s = nb[0] + nb[1];
+                            s = s + nb[2]; s = s + nb[3]; s = s + nb[4]; s = s + nb[5];
+                            if (op.op == AT_OP_LAP_UPDATE) {
+                                const float six_a = 6.0f * a;
+                                const float d = s - six_a;
+                                const float tq = op.p * d;
+                                r0[q] = a + tq;
+                            } else {
+                                const float tq = s + chan(g, op.ch[1])[off + q];
+                                r0[q] = tq * 0x1.555556p-3f;
                             }
-                            r0[q] = a + op.p * f;
                         } else {
-                            const float *Ln = chan(g, op.ch[2]);
-                            const float l = Ln[off + q];
-                            float f = 0.f, q2 = 0.f;
-                            for (int fc = 0; fc < 6; ++fc) {
-                                const float ln = rd_nb<KIND>(g, Ln, slot, nbs, li, lj, lk, fc);
-                                const float kf = 0.5f * (kc + rd_nb<KIND>(g, K, slot, nbs, li, lj, lk, fc));
-                                f = f + kf * (ln - l);
-                                q2 = q2 + (nb[fc] - a) * (l - ln);
+                            const float *K = chan(g, op.ch[1]);
+                            const float kc = K[off + q];
+                            if (op.op == AT_OP_DIFFUSE) {
+                                float f = 0.f;
+                                for (int fc = 0; fc < 6; ++fc) {
+                                    const float kf = 0.5f * (kc + rd_nb<KIND>(g, K, slot, nbs, li, lj, lk, fc));
+                                    f = f + kf * (nb[fc] - a);
+                                }
+                                r0[q] = a + op.p * f;
+                            } else {
+                                const float *Ln = chan(g, op.ch[2]);
+                                const float l = Ln[off + q];
+                                float f = 0.f, q2 = 0.f;
+                                for (int fc = 0; fc < 6; ++fc) {
+                                    const float ln = rd_nb<KIND>(g, Ln, slot, nbs, li, lj, lk, fc);
+                                    const float kf = 0.5f * (kc + rd_nb<KIND>(g, K, slot, nbs, li, lj, lk, fc));
+                                    f = f + kf * (ln - l);
+                                    q2 = q2 + (nb[fc] - a) * (l - ln);
+                                }
+                                r0[q] = l + op.p * f;
+                                r1[q] = chan(g, op.ch[4])[off + q] + (op.p * 0.5f) * q2;
                             }
-                            r0[q] = l + op.p * f;
-                            r1[q] = chan(g, op.ch[4])[off + q] + (op.p * 0.5f) * q2;
                         }
                     }
+                    const int outc = op.op == AT_OP_LAP_UPDATE ? op.ch[1]
+                                   : op.op == AT_OP_JACOBI ? op.ch[2]
+                                   : op.op == AT_OP_DIFFUSE ? op.ch[2] : op.ch[3];
+                    *reinterpret_cast<float4 *>(chan(g, outc) + off) = make_float4(r0[0], r0[1], r0[2], r0[3]);
+                    if (op.op == AT_OP_DIFFUSE_ADJ)
+                        *reinterpret_cast<float4 *>(chan(g, op.ch[4]) + off) = make_float4(r1[0], r1[1], r1[2], r1[3]);
+                    break;
                 }
-                const int outc = op.op == AT_OP_LAP_UPDATE ? op.ch[1]
-                               : op.op == AT_OP_JACOBI ? op.ch[2]
-                               : op.op == AT_OP_DIFFUSE ? op.ch[2] : op.ch[3];
-                *reinterpret_cast<float4 *>(chan(g, outc) + off) = make_float4(r0[0], r0[1], r0[2], r0[3]);
-                if (op.op == AT_OP_DIFFUSE_ADJ)
-                    *reinterpret_cast<float4 *>(chan(g, op.ch[4]) + off) = make_float4(r1[0], r1[1], r1[2], r1[3]);
-                break;
-            }
-            default:
-                break;
+                default:
+                    break;
+                }
             }
         }
     }
+}
+
+// ------------------------------------------------------------ batched Jacobi
+// Many independent pointer-rooted grids of one domain size share a leaf
+// pool.  The device work list holds (grid, root cell) pairs as
+// grid * R^3 + cell; grid g is active in global iteration i when
+// window[g].start <= i < window[g].end, with i = clock + it, so one captured
+// sequence of launches serves any mix of grids admitted at different times.
+// One wavefront per listed block, the same arithmetic (and operation order)
+// as the single-grid Jacobi and copy kernels.
+
+template <bool COPY>
+__global__ __launch_bounds__(64) void k_batch(BatchDev d, int it) {
+    const int lane = threadIdx.x;
+    const int64_t now = *d.clock + it;
+    const ListRange lr = list_range(*d.count);
+    for (int e = lr.lo; e < lr.hi; e += lr.step) {
+        const int32_t w = d.work[e];
+        const int gid = w / d.ncells;
+        const int32_t cell = w - gid * d.ncells;
+        if (now < d.window[2 * gid] || now >= d.window[2 * gid + 1]) continue;
+        const int32_t *root = d.roots + (int64_t)gid * d.ncells;
+        const int32_t slot = root[cell];
+        const int64_t off = (int64_t)slot * kBV + lane * 8;
+        if (COPY) {
+            const float4 a = reinterpret_cast<const float4 *>(d.xn + off)[0];
+            const float4 b = reinterpret_cast<const float4 *>(d.xn + off)[1];
+            reinterpret_cast<float4 *>(d.x + off)[0] = a;
+            reinterpret_cast<float4 *>(d.x + off)[1] = b;
+            continue;
+        }
+        const int bi = cell / d.R2, r = cell - bi * d.R2, bj = r / d.R, bk = r - bj * d.R;
+        int32_t mine = -1;
+        if (lane < 6) {
+            bool ok;
+            int32_t dc;
+            switch (lane) {
+            case 0: ok = bi > 0; dc = -d.R2; break;
+            case 1: ok = bi < d.R - 1; dc = d.R2; break;
+            case 2: ok = bj > 0; dc = -d.R; break;
+            case 3: ok = bj < d.R - 1; dc = d.R; break;
+            case 4: ok = bk > 0; dc = -1; break;
+            default: ok = bk < d.R - 1; dc = 1; break;
+            }
+            if (ok) {
+                const int32_t sn = root[cell + dc];
+                mine = sn >= 0 ? sn : -1;
+            }
+        }
+        Nbs n;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) n.s[f] = __builtin_amdgcn_readlane(mine, f);
+        Row X;
+        load_row(d.x, slot, n, lane, X);
+        float b[8], r0[8];
+        put8(b, reinterpret_cast<const float4 *>(d.b + off)[0], reinterpret_cast<const float4 *>(d.b + off)[1]);
+        const float sixth = 0x1.555556p-3f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const float sum = nbsum(X, q);
+            const float tq = sum + b[q];
+            r0[q] = tq * sixth;
+        }
+        store8(d.xn + off, r0);
+    }
+}
+
+__global__ void k_batch_tick(BatchDev d, int iters) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *d.clock += iters;
 }
 
 // ---------------------------------------------------------------- particles
@@ -692,6 +870,16 @@ int struct_for_grid_size(const GridDev &g) {
     return (int)wg;
 }
 
+// Wavefront-per-block kernels: up to 28 resident wavefronts per CU.
+int wave_grid_size(const GridDev &g) {
+    if (g_sf_grid_override > 0) return g_sf_grid_override;
+    const int64_t cap = g.cap < g.ncells ? g.cap : g.ncells;
+    int64_t wg = 256 * 28;
+    if (cap < wg) wg = ((cap + 7) / 8) * 8;
+    if (wg < 8) wg = 8;
+    return (int)wg;
+}
+
 void set_struct_for_grid_size(int wgs) { g_sf_grid_override = wgs > 0 ? ((wgs + 7) / 8) * 8 : 0; }
 
 hipError_t launch_activate(const GridDev &g, const int32_t *ijk, int64_t n, int coord_kind, hipStream_t s) {
@@ -705,45 +893,71 @@ hipError_t launch_activate(const GridDev &g, const int32_t *ijk, int64_t n, int 
     return hipGetLastError();
 }
 
-hipError_t launch_listgen(const GridDev &g, hipStream_t s) {
-    hipLaunchKernelGGL(k_listgen, dim3(1), dim3(1024), 0, s, g);
+template <int KIND>
+static void launch_listgen_k(const GridDev &g, uint64_t *flags, uint32_t epoch, hipStream_t s) {
+    int64_t C = 8;
+    while ((g.ncells + 256 * C - 1) / (256 * C) > kScanMaxWG) C *= 2;
+    const unsigned blocks = (unsigned)((g.ncells + 256 * C - 1) / (256 * C));
+    switch (C) {
+    case 8: hipLaunchKernelGGL((k_listgen<KIND, 8>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
+    case 16: hipLaunchKernelGGL((k_listgen<KIND, 16>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
+    case 32: hipLaunchKernelGGL((k_listgen<KIND, 32>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
+    case 64: hipLaunchKernelGGL((k_listgen<KIND, 64>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
+    case 128: hipLaunchKernelGGL((k_listgen<KIND, 128>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
+    case 256: hipLaunchKernelGGL((k_listgen<KIND, 256>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
+    case 512: hipLaunchKernelGGL((k_listgen<KIND, 512>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
+    case 1024: hipLaunchKernelGGL((k_listgen<KIND, 1024>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
+    case 2048: hipLaunchKernelGGL((k_listgen<KIND, 2048>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
+    default: hipLaunchKernelGGL((k_listgen<KIND, 4096>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
+    }
+}
+
+hipError_t launch_listgen(const GridDev &g, uint64_t *flags, uint32_t epoch, hipStream_t s) {
+    if (g.kind == AT_ROOT_BITMASK) launch_listgen_k<AT_ROOT_BITMASK>(g, flags, epoch, s);
+    else launch_listgen_k<AT_ROOT_POINTER>(g, flags, epoch, s);
     return hipGetLastError();
 }
 
-template <int OP, int KIND>
-static void launch_stencil_t(const GridDev &g, const StencilCh &c, float p, int check, hipStream_t s) {
-    const dim3 grid(struct_for_grid_size(g)), block(kSFThreads);
-    if (check)
-        hipLaunchKernelGGL((k_stencil<OP, KIND, true>), grid, block, 0, s, g, c, p);
+template <int OP, int KIND, bool CHECK>
+static void launch_stencil_c(const GridDev &g, const StencilCh &c, float p, int table, hipStream_t s) {
+    const dim3 grid(wave_grid_size(g)), block(64);
+    if (table)
+        hipLaunchKernelGGL((k_stencil<OP, KIND, CHECK, true>), grid, block, 0, s, g, c, p);
     else
-        hipLaunchKernelGGL((k_stencil<OP, KIND, false>), grid, block, 0, s, g, c, p);
+        hipLaunchKernelGGL((k_stencil<OP, KIND, CHECK, false>), grid, block, 0, s, g, c, p);
+}
+
+template <int OP, int KIND>
+static void launch_stencil_t(const GridDev &g, const StencilCh &c, float p, int check, int table, hipStream_t s) {
+    if (check) launch_stencil_c<OP, KIND, true>(g, c, p, table, s);
+    else launch_stencil_c<OP, KIND, false>(g, c, p, table, s);
 }
 
 template <int OP>
-static void launch_stencil_k(const GridDev &g, const StencilCh &c, float p, int check, hipStream_t s) {
-    if (g.kind == AT_ROOT_BITMASK) launch_stencil_t<OP, AT_ROOT_BITMASK>(g, c, p, check, s);
-    else launch_stencil_t<OP, AT_ROOT_POINTER>(g, c, p, check, s);
+static void launch_stencil_k(const GridDev &g, const StencilCh &c, float p, int check, int table, hipStream_t s) {
+    if (g.kind == AT_ROOT_BITMASK) launch_stencil_t<OP, AT_ROOT_BITMASK>(g, c, p, check, table, s);
+    else launch_stencil_t<OP, AT_ROOT_POINTER>(g, c, p, check, table, s);
 }
 
-hipError_t launch_stencil(const GridDev &g, int op, const int32_t *ch, float p, int check, hipStream_t s) {
+hipError_t launch_stencil(const GridDev &g, int op, const int32_t *ch, float p, int check, int table, hipStream_t s) {
     StencilCh c{};
     auto C = [&](int i) { return g.chan + (int64_t)ch[i] * g.ch_stride; };
     switch (op) {
     case AT_OP_LAP_UPDATE:
         c.tin[0] = C(0); c.out0 = C(1);
-        launch_stencil_k<AT_OP_LAP_UPDATE>(g, c, p, check, s);
+        launch_stencil_k<AT_OP_LAP_UPDATE>(g, c, p, check, table, s);
         break;
     case AT_OP_JACOBI:
         c.tin[0] = C(0); c.ein = C(1); c.out0 = C(2);
-        launch_stencil_k<AT_OP_JACOBI>(g, c, p, check, s);
+        launch_stencil_k<AT_OP_JACOBI>(g, c, p, check, table, s);
         break;
     case AT_OP_DIFFUSE:
         c.tin[0] = C(0); c.tin[1] = C(1); c.out0 = C(2);
-        launch_stencil_k<AT_OP_DIFFUSE>(g, c, p, check, s);
+        launch_stencil_k<AT_OP_DIFFUSE>(g, c, p, check, table, s);
         break;
     case AT_OP_DIFFUSE_ADJ:
         c.tin[0] = C(0); c.tin[1] = C(1); c.tin[2] = C(2); c.out0 = C(3); c.ein = C(4); c.out1 = C(4);
-        launch_stencil_k<AT_OP_DIFFUSE_ADJ>(g, c, p, check, s);
+        launch_stencil_k<AT_OP_DIFFUSE_ADJ>(g, c, p, check, table, s);
         break;
     default:
         return hipErrorInvalidValue;
@@ -752,11 +966,19 @@ hipError_t launch_stencil(const GridDev &g, int op, const int32_t *ch, float p, 
 }
 
 hipError_t launch_micro(const GridDev &g, const MicroProg &prog, hipStream_t s) {
-    const dim3 grid(struct_for_grid_size(g)), block(kSFThreads);
-    if (g.kind == AT_ROOT_BITMASK)
-        hipLaunchKernelGGL(k_micro<AT_ROOT_BITMASK>, grid, block, 0, s, g, prog);
-    else
-        hipLaunchKernelGGL(k_micro<AT_ROOT_POINTER>, grid, block, 0, s, g, prog);
+    const dim3 grid(wave_grid_size(g)), block(64);
+    bool st = false;
+    for (int o = 0; o < prog.nops; ++o) {
+        const int op = prog.ops[o].op;
+        st |= op == AT_OP_LAP_UPDATE || op == AT_OP_JACOBI || op == AT_OP_DIFFUSE || op == AT_OP_DIFFUSE_ADJ;
+    }
+    if (g.kind == AT_ROOT_BITMASK) {
+        if (st) hipLaunchKernelGGL((k_micro<AT_ROOT_BITMASK, true>), grid, block, 0, s, g, prog);
+        else hipLaunchKernelGGL((k_micro<AT_ROOT_BITMASK, false>), grid, block, 0, s, g, prog);
+    } else {
+        if (st) hipLaunchKernelGGL((k_micro<AT_ROOT_POINTER, true>), grid, block, 0, s, g, prog);
+        else hipLaunchKernelGGL((k_micro<AT_ROOT_POINTER, false>), grid, block, 0, s, g, prog);
+    }
     return hipGetLastError();
 }
 
@@ -817,6 +1039,19 @@ hipError_t launch_gather_blocks(const GridDev &g, int ch, const int32_t *cells, 
         hipLaunchKernelGGL(k_gather_blocks<AT_ROOT_BITMASK>, dim3(blocks), dim3(kSFThreads), 0, s, g, ch, cells, vals, n);
     else
         hipLaunchKernelGGL(k_gather_blocks<AT_ROOT_POINTER>, dim3(blocks), dim3(kSFThreads), 0, s, g, ch, cells, vals, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_jacobi(const BatchDev &d, int iters, int workgroups, hipStream_t s) {
+    int wgs = workgroups > 0 ? workgroups : 256 * 28;
+    wgs = ((wgs + 7) / 8) * 8;
+    if (wgs > d.pool) wgs = ((d.pool + 7) / 8) * 8;
+    if (wgs < 8) wgs = 8;
+    for (int it = 0; it < iters; ++it) {
+        hipLaunchKernelGGL(k_batch<false>, dim3(wgs), dim3(64), 0, s, d, it);
+        hipLaunchKernelGGL(k_batch<true>, dim3(wgs), dim3(64), 0, s, d, it);
+    }
+    hipLaunchKernelGGL(k_batch_tick, dim3(1), dim3(64), 0, s, d, iters);
     return hipGetLastError();
 }
 

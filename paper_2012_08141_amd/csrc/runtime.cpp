@@ -71,7 +71,7 @@ Engine &E() {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t hdr, bits, ptr, list, chan, total;
+    size_t hdr, scan, bits, ptr, list, chan, total;
     int64_t ncells;
     int32_t cap, list_cap, R;
 };
@@ -97,9 +97,10 @@ at_status layout_of(const at_grid_desc *d, Layout &L) {
     L.list_cap = (int32_t)(L.cap < L.ncells ? L.cap : L.ncells);
     size_t off = 0;
     L.hdr = off; off += 256;
+    L.scan = off; off += kScanFlags * sizeof(uint64_t);
     L.bits = off; off += align256(((L.ncells + 31) / 32) * 4);
     L.ptr = off; if (d->root_kind == AT_ROOT_POINTER) off += align256(L.ncells * 4);
-    L.list = off; off += align256((size_t)L.list_cap * 4);
+    L.list = off; off += align256((size_t)L.list_cap * kRec * sizeof(int32_t));
     L.chan = off; off += (size_t)d->channels * L.cap * kBV * sizeof(float);
     L.total = off;
     return AT_OK;
@@ -115,7 +116,7 @@ at_status check_grid(at_grid g, bool need_device) {
 
 int64_t dispatches_of(const Node &) { return 1; }
 
-at_status execute_node(const Node &nd, const at_task *tasks, hipStream_t s) {
+at_status execute_node(const Node &nd, const at_task *tasks, bool table, hipStream_t s) {
     const at_task &t0 = tasks[nd.members[0].task];
     const at_grid_s *g = task_grid(t0);
     // planning handles launch nothing
@@ -128,19 +129,23 @@ at_status execute_node(const Node &nd, const at_task *tasks, hipStream_t s) {
     case AT_TASK_ACTIVATE:
         e = launch_activate(g->dev, (const int32_t *)t0.ext[0], t0.n, t0.op, s);
         break;
-    case AT_TASK_LISTGEN:
-        e = launch_listgen(g->dev, s);
+    case AT_TASK_LISTGEN: {
+        at_grid_s *gm = const_cast<at_grid_s *>(g);
+        if (++gm->listgen_epoch == 0) gm->listgen_epoch = 1;
+        e = launch_listgen(g->dev, g->dev.scan, gm->listgen_epoch, s);
         break;
+    }
     case AT_TASK_STENCIL: {
         const Member &m0 = nd.members[0];
         const bool tiled = t0.op == AT_OP_LAP_UPDATE || t0.op == AT_OP_JACOBI || t0.op == AT_OP_DIFFUSE ||
                            t0.op == AT_OP_DIFFUSE_ADJ;
         if (nd.members.size() == 1 && tiled && m0.keep == ~0u) {
-            e = launch_stencil(g->dev, t0.op, t0.ch, t0.param[0], nd.check_activation ? 1 : 0, s);
+            e = launch_stencil(g->dev, t0.op, t0.ch, t0.param[0], nd.check_activation ? 1 : 0, table ? 1 : 0, s);
         } else {
             MicroProg prog{};
             prog.nops = (int32_t)nd.members.size();
             prog.check = nd.check_activation ? 1 : 0;
+            prog.table = table ? 1 : 0;
             for (size_t q = 0; q < nd.members.size(); ++q) {
                 const at_task &t = tasks[nd.members[q].task];
                 MicroOp &op = prog.ops[q];
@@ -259,8 +264,10 @@ at_status run_window(const at_task *tasks, int ntasks, uint32_t flags, at_stats 
     if (st != AT_OK) return st;
     const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
     const int64_t d0 = en.dispatches.load();
-    for (const Node &nd : nodes) {
-        st = execute_node(nd, tasks, s);
+    const std::vector<uint8_t> tables = neighbour_tables_valid(nodes, tasks, en.persist);
+    for (size_t i = 0; i < nodes.size(); ++i) {
+        const Node &nd = nodes[i];
+        st = execute_node(nd, tasks, tables[i] != 0, s);
         if (st != AT_OK) {
             Planner::commit(nodes, tasks, en.persist);
             return st;
@@ -327,6 +334,7 @@ at_status at_grid_create(const at_grid_desc *desc, void *dev_buf, size_t bytes, 
     g->virt = virt;
     g->bytes = L.total;
     g->list_cap = L.list_cap;
+    g->listgen_epoch = 0;
     GridDev &d = g->dev;
     d.R = L.R;
     d.R2 = L.R * L.R;
@@ -337,6 +345,7 @@ at_status at_grid_create(const at_grid_desc *desc, void *dev_buf, size_t bytes, 
     if (!virt) {
         char *b = (char *)dev_buf;
         d.hdr = (int32_t *)(b + L.hdr);
+        d.scan = (uint64_t *)(b + L.scan);
         d.bits = (uint32_t *)(b + L.bits);
         d.ptr = desc->root_kind == AT_ROOT_POINTER ? (int32_t *)(b + L.ptr) : nullptr;
         d.list = (int32_t *)(b + L.list);
@@ -721,6 +730,119 @@ at_status at_ext_modified(const void *ptr) {
     Engine &en = E();
     std::lock_guard<std::recursive_mutex> lk(en.mu);
     en.persist.version[StateKey{(uint64_t)(uintptr_t)ptr, -1, ST_EXT}] += 1;
+    return AT_OK;
+}
+
+// ----------------------------------------------------------------- batching
+
+struct at_batch_s {
+    at_batch_desc desc;
+    BatchDev dev;
+    size_t bytes;
+};
+
+namespace {
+struct BatchLayout {
+    size_t clock, count, window, roots, work, x, xn, b, total;
+};
+at_status batch_layout(const at_batch_desc *d, BatchLayout &L, int32_t &R) {
+    if (!d) return fail(AT_E_INVALID, "null batch description");
+    if (d->reserved != 0) return fail(AT_E_INVALID, "reserved field must be 0");
+    if (d->n <= 0 || d->n % kBS) return fail(AT_E_INVALID, "domain edge must be a positive multiple of 8");
+    R = d->n / kBS;
+    if ((int64_t)R * R * R > (1 << 20)) return fail(AT_E_INVALID, "batched grids are limited to R^3 <= 2^20 cells");
+    if (d->max_grids < 1 || d->pool_blocks < 1) return fail(AT_E_INVALID, "max_grids and pool_blocks must be positive");
+    if ((int64_t)d->max_grids * R * R * R >= (1LL << 31)) return fail(AT_E_INVALID, "max_grids * R^3 must fit in int32");
+    const int64_t nc = (int64_t)R * R * R;
+    size_t off = 0;
+    L.clock = off; off += 128;
+    L.count = off; off += 128;
+    L.window = off; off += align256((size_t)d->max_grids * 2 * sizeof(int64_t));
+    L.roots = off; off += align256((size_t)d->max_grids * nc * sizeof(int32_t));
+    L.work = off; off += align256((size_t)d->pool_blocks * sizeof(int32_t));
+    L.x = off; off += (size_t)d->pool_blocks * kBV * sizeof(float);
+    L.xn = off; off += (size_t)d->pool_blocks * kBV * sizeof(float);
+    L.b = off; off += (size_t)d->pool_blocks * kBV * sizeof(float);
+    L.total = off;
+    return AT_OK;
+}
+}  // namespace
+
+at_status at_batch_footprint(const at_batch_desc *desc, size_t *bytes) {
+    if (!bytes) return fail(AT_E_INVALID, "null output");
+    BatchLayout L;
+    int32_t R;
+    at_status st = batch_layout(desc, L, R);
+    if (st != AT_OK) return st;
+    *bytes = L.total;
+    return AT_OK;
+}
+
+at_status at_batch_create(const at_batch_desc *desc, void *dev_buf, size_t bytes, hipStream_t stream, at_batch *out) {
+    if (!out) return fail(AT_E_INVALID, "null output handle");
+    *out = nullptr;
+    BatchLayout L;
+    int32_t R;
+    at_status st = batch_layout(desc, L, R);
+    if (st != AT_OK) return st;
+    if (!dev_buf || bytes < L.total) return fail(AT_E_INVALID, "batch buffer missing or below the footprint");
+    if ((uintptr_t)dev_buf & 255) return fail(AT_E_INVALID, "batch buffer must be 256-byte aligned");
+    char *b = (char *)dev_buf;
+    at_batch h = new at_batch_s();
+    h->desc = *desc;
+    h->bytes = L.total;
+    BatchDev &d = h->dev;
+    d.R = R;
+    d.R2 = R * R;
+    d.ncells = R * R * R;
+    d.max_grids = desc->max_grids;
+    d.pool = desc->pool_blocks;
+    d.clock = (int64_t *)(b + L.clock);
+    d.count = (int32_t *)(b + L.count);
+    d.window = (int64_t *)(b + L.window);
+    d.roots = (int32_t *)(b + L.roots);
+    d.work = (int32_t *)(b + L.work);
+    d.x = (float *)(b + L.x);
+    d.xn = (float *)(b + L.xn);
+    d.b = (float *)(b + L.b);
+    hipError_t e = hipMemsetAsync(dev_buf, 0, L.total, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(d.roots, 0xff, (size_t)d.max_grids * d.ncells * sizeof(int32_t), stream);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "batch initialisation");
+    }
+    E().dispatches.fetch_add(2);
+    *out = h;
+    return AT_OK;
+}
+
+at_status at_batch_destroy(at_batch batch) {
+    if (!batch) return fail(AT_E_INVALID, "null batch handle");
+    delete batch;
+    return AT_OK;
+}
+
+at_status at_batch_get_views(at_batch batch, at_batch_views *v) {
+    if (!batch || !v) return fail(AT_E_INVALID, "null argument");
+    const BatchDev &d = batch->dev;
+    v->clock = d.clock;
+    v->count = d.count;
+    v->window = d.window;
+    v->roots = d.roots;
+    v->work = d.work;
+    v->x = d.x;
+    v->xn = d.xn;
+    v->b = d.b;
+    return AT_OK;
+}
+
+at_status at_batch_jacobi(at_batch batch, int32_t iters, int32_t workgroups, hipStream_t stream) {
+    if (!batch) return fail(AT_E_INVALID, "null batch handle");
+    if (iters < 0 || workgroups < 0) return fail(AT_E_INVALID, "negative iteration or workgroup count");
+    if (iters == 0) return AT_OK;
+    hipError_t e = launch_batch_jacobi(batch->dev, iters, workgroups, stream);
+    if (e != hipSuccess) return hip_fail(e, "batched jacobi launch");
+    E().dispatches.fetch_add(2 * (int64_t)iters + 1);
     return AT_OK;
 }
 

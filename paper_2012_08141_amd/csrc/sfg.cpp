@@ -747,6 +747,42 @@ void Planner::optimize(const Persist &start) {
     }
 }
 
+std::vector<uint8_t> neighbour_tables_valid(const std::vector<Node> &nodes, const at_task *tasks, const Persist &P) {
+    std::vector<uint8_t> ok(nodes.size(), 0);
+    std::unordered_map<uint64_t, uint64_t> maskv, lsrc;
+    auto mv = [&](uint64_t g) -> uint64_t & {
+        auto it = maskv.find(g);
+        if (it == maskv.end()) it = maskv.emplace(g, P.ver(MASK(g))).first;
+        return it->second;
+    };
+    auto ls = [&](uint64_t g) -> uint64_t & {
+        auto it = lsrc.find(g);
+        if (it == lsrc.end()) {
+            auto st = P.list_src.find(g);
+            it = lsrc.emplace(g, st == P.list_src.end() ? ~0ull : st->second).first;
+        }
+        return it->second;
+    };
+    std::vector<uint64_t> bumped;
+    for (size_t i = 0; i < nodes.size(); ++i) {
+        const Node &nd = nodes[i];
+        const at_task &t0 = tasks[nd.members[0].task];
+        if (nd.loop == LT_STRUCT) ok[i] = ls(nd.loop_grid) == mv(nd.loop_grid);
+        if (t0.kind == AT_TASK_LISTGEN) {
+            const uint64_t g = task_grid(t0)->uid;
+            ls(g) = mv(g);
+        }
+        bumped.clear();
+        for (const Access &a : nd.acc)
+            if ((a.mode & M_W) && a.s.kind == ST_MASK &&
+                std::find(bumped.begin(), bumped.end(), a.s.obj) == bumped.end()) {
+                bumped.push_back(a.s.obj);
+                mv(a.s.obj) += 1;
+            }
+    }
+    return ok;
+}
+
 void Planner::commit(const std::vector<Node> &nodes, const at_task *tasks, Persist &p) {
     Sim S = simulate(nodes, tasks, p);
     for (int i = 0; i < S.n; ++i) {

@@ -115,6 +115,9 @@ private:
 };
 
 void derive(Node &nd, const at_task *tasks);
+// For each node: 1 if it is a struct-for whose grid's mask is unchanged since
+// its list was generated (the neighbour slots in the list records are valid).
+std::vector<uint8_t> neighbour_tables_valid(const std::vector<Node> &nodes, const at_task *tasks, const Persist &p);
 uint64_t hash_window(const at_task *tasks, int n, uint32_t flags, int max_fuse);
 
 }  // namespace ats

@@ -95,11 +95,16 @@ class SparseGrid:
         _, _, cnt, _ = self._views()
         return int(self._slice(cnt, 4).view(torch.int32).item())
 
-    def list_cells(self) -> np.ndarray:
-        """The list state (root cells, in list order)."""
+    def list_records(self) -> np.ndarray:
+        """The list state: one record per entry, int32 [count, 8] =
+        (cell, slot, slots of the 6 face neighbours)."""
         _, lst, cnt, _ = self._views()
         c = int(self._slice(cnt, 4).view(torch.int32).item())
-        return self._slice(lst, self.list_capacity * 4).view(torch.int32)[:c].cpu().numpy()
+        return self._slice(lst, self.list_capacity * 32).view(torch.int32).view(-1, 8)[:c].cpu().numpy()
+
+    def list_cells(self) -> np.ndarray:
+        """The list state's root cells, in list order."""
+        return self.list_records()[:, 0].copy()
 
     def active_cells(self) -> np.ndarray:
         """Active root cells read from the mask, ascending."""

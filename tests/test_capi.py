@@ -45,11 +45,11 @@ def test_footprint_layout_and_validation():
     b = ctypes.c_size_t()
     d = _desc(64)
     assert lib.at_grid_footprint(ctypes.byref(d), ctypes.byref(b)) == L.AT_OK
-    # header 256 + bits 256 + list 2048 + 2 channels * 512 blocks * 2 KiB
-    assert b.value == 256 + 256 + 2048 + 2 * 512 * 2048
+    # header 256 + scan flags 8 KiB + bits 256 + list 512 records * 32 B + 2 channels * 512 blocks * 2 KiB
+    assert b.value == 256 + 8192 + 256 + 512 * 32 + 2 * 512 * 2048
     d = _desc(64, L.AT_ROOT_POINTER, 3, 100)
     assert lib.at_grid_footprint(ctypes.byref(d), ctypes.byref(b)) == L.AT_OK
-    assert b.value == 256 + 256 + 2048 + 512 + 3 * 100 * 2048
+    assert b.value == 256 + 8192 + 256 + 2048 + 3328 + 3 * 100 * 2048   # list: 100 records, 256-aligned
     for bad in (_desc(60), _desc(0), _desc(64, 7), _desc(64, L.AT_ROOT_BITMASK, 0),
                 _desc(64, L.AT_ROOT_POINTER, 1, 0), _desc(64, L.AT_ROOT_POINTER, 1, 513)):
         assert lib.at_grid_footprint(ctypes.byref(bad), ctypes.byref(b)) == L.AT_E_INVALID

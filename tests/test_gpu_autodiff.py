@@ -1,0 +1,83 @@
+"""Differentiation of sparse diffusion on the GPU (MI355X only): the
+adjoint behind torch.autograd.Function against FP64 central finite
+differences on the CPU oracle, at |g - fd| <= 1e-4 * max(|fd|, 1e-2 max|fd|)
+per component and |<g, u> - D_u| <= 1e-4 |D_u| per direction."""
+import numpy as np
+import pytest
+
+from oracle import programs as OP
+from paper_2012_08141_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _grads(w, steps, every, dt=0.1):
+    from paper_2012_08141_amd.autodiff import DiffusionProblem, diffusion_loss
+    prob = DiffusionProblem(w.n, w.blocks, dt, steps, every)
+    a0 = torch.as_tensor(w.channels["a"], device="cuda").clone().requires_grad_(True)
+    k = torch.as_tensor(w.channels["k"], device="cuda").clone().requires_grad_(True)
+    tgt = torch.as_tensor(w.channels["target"], device="cuda")
+    loss = diffusion_loss(a0, k, tgt, prob)
+    loss.backward()
+    torch.cuda.synchronize()
+    return float(loss), a0.grad.cpu().numpy().astype(np.float64), k.grad.cpu().numpy().astype(np.float64), prob
+
+
+def _check(g, ref, what):
+    scale = 1e-2 * np.abs(ref).max()
+    bad = np.abs(g - ref) > 1e-4 * np.maximum(np.abs(ref), scale)
+    assert not bad.any(), "%s: %d bad, max rel %g" % (what, int(bad.sum()),
+                                                      float((np.abs(g - ref) / np.maximum(np.abs(ref), scale)).max()))
+
+
+@pytest.mark.parametrize("steps,every", [(7, 3), (5, 5), (4, 1)])
+def test_adjoint_matches_fp64_adjoint_small(steps, every):
+    say("adjoint small", steps, every)
+    w = I.diffusion(2, n=32, r_in=0.2, r_out=0.45)
+    loss, ga, gk, prob = _grads(w, steps, every)
+    ref = OP.diffusion_grad(w.n, w.blocks, w.channels["a"].astype(np.float64), w.channels["k"].astype(np.float64),
+                            w.channels["target"].astype(np.float64), 0.1, steps, "f64")
+    assert abs(loss - ref["loss"]) <= 1e-5 * ref["loss"]
+    _check(ga, ref["grad_a0"], "grad_a0")
+    _check(gk, ref["grad_k"], "grad_k")
+
+
+def test_diffusion_workload_gradients_vs_central_differences():
+    """The differentiation workload at full size: 128^3, 355 active blocks,
+    20 steps, checkpoints every 5; FP64 central differences of the oracle's
+    loss on sampled components and random directions.  Step h = 1e-3: the
+    loss is quadratic in a0 (central differences are exact there up to
+    rounding) and smooth in k (truncation ~h^2); at h = 1e-5 the fp64
+    rounding of the 2e5-term loss (~1e-11) over 2h would exceed the bar."""
+    say("adjoint full size")
+    w = I.diffusion(0)
+    steps, dt, h = 20, 0.1, 1e-3
+    loss, ga, gk, prob = _grads(w, steps, 5)
+    a0 = w.channels["a"].astype(np.float64)
+    k = w.channels["k"].astype(np.float64)
+    tgt = w.channels["target"].astype(np.float64)
+    ref = OP.diffusion_grad(w.n, w.blocks, a0, k, tgt, dt, steps, "f64")
+    _check(ga, ref["grad_a0"], "grad_a0 vs fp64 adjoint")
+    _check(gk, ref["grad_k"], "grad_k vs fp64 adjoint")
+    L = lambda a, kk: OP.diffusion_loss(w.n, w.blocks, a, kk, tgt, dt, steps)
+    rng = np.random.default_rng(7)
+    for which, arr, g in (("a", a0, ga), ("k", k, gk)):
+        gmax = np.abs(g).max()
+        for p in rng.integers(0, arr.size, 6):
+            plus, minus = arr.copy(), arr.copy()
+            plus.flat[p] += h
+            minus.flat[p] -= h
+            fd = (L(plus, k) - L(minus, k)) / (2 * h) if which == "a" else (L(a0, plus) - L(a0, minus)) / (2 * h)
+            assert abs(g.flat[p] - fd) <= 1e-4 * max(abs(fd), 1e-2 * gmax), (which, int(p), g.flat[p], fd)
+    for _ in range(2):
+        ua = rng.standard_normal(a0.shape)
+        uk = rng.standard_normal(k.shape)
+        d = (L(a0 + h * ua, k + h * uk) - L(a0 - h * ua, k - h * uk)) / (2 * h)
+        dot = float(np.sum(ga * ua) + np.sum(gk * uk))
+        assert abs(dot - d) <= 1e-4 * abs(d), (dot, d)
+    say("  optimizer windows:", prob.windows)

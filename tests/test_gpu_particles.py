@@ -1,0 +1,144 @@
+"""Particle transfers on the GPU against the oracle (MI355X only).
+
+Bars: active sets bit-exact; one P2G within the summation bound
+|g - o| <= 1e-5 * A (A = per node and channel sum of |term|, from the
+oracle); the gather, which sums in a fixed order, within
+1e-5 * max(|o|, 0.1 * max|o|); the particle state after many steps within
+1e-5 * max(|o|, s) where s is 0.1 * max|x0| for positions and
+0.1 * max|v0| for velocities: fp32 atomics reorder the momentum sums, whose
+rounding error is set by the scattered terms (the initial particle speeds),
+not by the much smaller grid-averaged velocity that comes back.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import programs as OP
+from paper_2012_08141_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2012_08141_amd import engine as E
+    E.reset()
+    yield
+    torch.cuda.synchronize()
+
+
+def close_state(got, exp, what, scale=None):
+    exp = np.asarray(exp, np.float64)
+    got = np.asarray(got, np.float64)
+    s = 0.1 * np.abs(exp).max() if scale is None else scale
+    tol = 1e-5 * np.maximum(np.abs(exp), s)
+    bad = np.abs(got - exp) > tol
+    assert not bad.any(), "%s: %d of %d beyond tolerance (max diff %g)" % (
+        what, int(bad.sum()), bad.size, float(np.abs(got - exp).max()))
+
+
+@pytest.mark.parametrize("root", ["pointer", "bitmask"])
+@pytest.mark.parametrize("act", [0, 1])
+@pytest.mark.parametrize("n,np_", [(64, 20000), (128, 3001)])
+def test_p2g_matches_oracle_within_summation_bound(root, act, n, np_):
+    from paper_2012_08141_amd.grid import SparseGrid
+    say("p2g", root, act, n, np_)
+    p = I.random_particles(3, n, np_, 0.1, 0.6, root)
+    ref = OP.p2g_once(n, None, p.x, p.v, p.m, "f32")
+    g = SparseGrid(n, 8, root, (n // 8) ** 3 if root == "pointer" else 0)
+    x, v, m = (torch.as_tensor(a, device="cuda").contiguous() for a in (p.x, p.v, p.m))
+    import ctypes
+    from paper_2012_08141_amd import _lib as L
+    ch = (ctypes.c_int32 * 2)(0, 1)
+    L.check(L.lib().at_p2g(g.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(v.data_ptr()),
+                           ctypes.c_void_p(m.data_ptr()), np_, 1.0 / n, ch, act,
+                           torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    cells = ref["cells"]
+    assert np.array_equal(g.active_cells(), cells)
+    assert g.device_status() == 0
+    got = [g.read_blocks(0, cells)] + [g.read_blocks(1 + c, cells) for c in range(3)]
+    exp = [ref["m"]] + ref["mv"]
+    for q in range(4):
+        A = ref["abs"][q].astype(np.float64)
+        err = np.abs(got[q].astype(np.float64) - exp[q].astype(np.float64))
+        assert np.all(err <= 1e-5 * A + 1e-30), ("channel", q, float((err / np.maximum(A, 1e-30)).max()))
+    # total mass is the number of particles (weights partition unity)
+    assert abs(got[0].astype(np.float64).sum() - np_) < 1e-3 * np_
+
+
+def test_g2p_matches_oracle():
+    from paper_2012_08141_amd import engine as E
+    from paper_2012_08141_amd.grid import SparseGrid
+    say("g2p")
+    n = 64
+    w = I.random_blocks(21, n, 0.6, "pointer", channels=("v0", "v1", "v2"))
+    p = I.random_particles(4, n, 5000, 0.05, 0.95)
+    g = SparseGrid(n, 3, "pointer", (n // 8) ** 3)
+    o = oracle.OracleGrid(n, 3)
+    for q in range(3):
+        g.load_blocks(q, w.cells, w.channels["v%d" % q])
+    o.load(w.blocks, w.channels, {"v0": 0, "v1": 1, "v2": 2})
+    x = torch.as_tensor(p.x, device="cuda").contiguous()
+    v = torch.zeros_like(x)
+    E.run_sequence([E.g2p(g, x, v, 1.0 / n, 0)], 0)
+    torch.cuda.synchronize()
+    exp = o.g2p(0, p.x, float(n))
+    got = v.cpu().numpy()
+    close_state(got, exp, "g2p")
+    say("  bit-identical:", bool(np.array_equal(got, exp)))
+
+
+def _particle_run(p, steps, opt, nsteps_list=None):
+    from paper_2012_08141_amd import engine as E, programs as PR
+    from paper_2012_08141_amd.grid import SparseGrid
+    n = p.n
+    grids = [SparseGrid(n, 7, p.root_kind, (n // 8) ** 3 if p.root_kind == "pointer" else 0) for _ in range(2)]
+    x, v, m = PR.device_particles(p)
+    tasks = sum((PR.particle_step(grids, t, x, v, m, p.params["dt"], 1.0 / n) for t in range(steps)), [])
+    st = E.run_sequence(tasks, opt)
+    torch.cuda.synchronize()
+    return grids, x, v, st
+
+
+@pytest.mark.parametrize("opt", [0, 15])
+def test_particle_program_reduced(opt):
+    """Workload 3's recipe (3 boxes, N(0, 0.1^2) velocities, dt = 1e-3) with
+    100k particles in a 128^3 grid, 20 steps, eager and optimized."""
+    say("particle program opt", opt)
+    p = I.particles(0, n=128, nparticles=100_000)
+    grids, x, v, st = _particle_run(p, 20, opt)
+    assert st["dispatches"] == (140 if opt == 0 else 65)
+    ref = OP.particle_program(p.n, p.x, p.v, p.m, 20, p.params["dt"], "f32")
+    sx, sv = 0.1 * np.abs(p.x).max(), 0.1 * np.abs(p.v).max()
+    close_state(x.cpu().numpy(), ref["x"], "x", sx)
+    close_state(v.cpu().numpy(), ref["v"], "v", sv)
+    for gi in (0, 1):
+        assert np.array_equal(grids[gi].active_cells(), ref["cells%d" % gi]), gi
+        assert grids[gi].device_status() == 0
+
+
+def test_particle_full_size_one_step_and_eager_vs_optimized():
+    """Workload 3 at full size (2M particles, 256^3): one step against the
+    oracle; 20 steps optimized against eager."""
+    say("particles full size")
+    p = I.particles(0)
+    ref = OP.particle_program(p.n, p.x, p.v, p.m, 1, p.params["dt"], "f32")
+    sx, sv = 0.1 * np.abs(p.x).max(), 0.1 * np.abs(p.v).max()
+    grids, x, v, st = _particle_run(p, 1, 15)
+    close_state(x.cpu().numpy(), ref["x"], "x", sx)
+    close_state(v.cpu().numpy(), ref["v"], "v", sv)
+    assert np.array_equal(grids[0].active_cells(), ref["cells0"])
+    del grids
+    ge, xe, ve, _ = _particle_run(p, 20, 0)
+    go, xo, vo, _ = _particle_run(p, 20, 15)
+    close_state(xo.cpu().numpy(), xe.cpu().numpy(), "x eager/opt", sx)
+    close_state(vo.cpu().numpy(), ve.cpu().numpy(), "v eager/opt", sv)
+    for gi in (0, 1):
+        assert np.array_equal(ge[gi].active_cells(), go[gi].active_cells())
