@@ -1,14 +1,19 @@
-"""Benchmark: active voxel-steps/s and launches/step of the sparse Jacobi
-pipeline (512^3 domain, narrow band around 4 random spheres, 8^3 fp32
-leaves under a bitmasked root), optimized vs eager, on one GPU.
+"""Benchmark: active voxel-steps/s and launches/step, optimized vs eager
+pipeline, on one GPU.
 
-A step is one Jacobi iteration of the whole program -- listgen, jacobi
-(xn = (sum of 6 neighbours of x + b) / 6), copy (x = xn) -- over every
-active voxel.  The optimized pipeline runs the same task list through the
-inter-kernel optimizer (list generation removal, activation demotion, task
-fusion, dead store elimination).  Inputs are resident in HBM before timing;
-the timed region is K steps submitted as one engine window (plan lookup and
-launch included) bracketed by device synchronisation.
+Default workload (band512): sparse Jacobi on a 512^3 domain, a narrow band
+around 4 seeded spheres, 8^3 fp32 leaves under a bitmasked root.  A step is
+one Jacobi iteration of the whole program -- listgen, jacobi (xn = (sum of 6
+neighbours of x + b) / 6), copy (x = xn) -- over every active voxel.  The
+optimized pipeline runs the same task list through the inter-kernel
+optimizer (list generation removal, activation demotion, task fusion, dead
+store elimination).  Inputs are resident in HBM before timing; the timed
+region is K steps submitted as one engine window (plan lookup and launch
+included) bracketed by device synchronisation.
+
+Other workloads (--workload): shell (64^3 activate/lap_update/axpy),
+particles (2M-particle PIC), serving (256 Poisson-arriving 128^3 Jacobi
+requests, continuous batching) and diffusion (128^3 forward + adjoint).
 
 Prints one JSON line.
 """
@@ -26,32 +31,69 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the Jacobi stencil on band512 (seed 0), from two
+# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE), each scaled by the reading
+# for a plain 256 MiB copy in the same run.  Valid only for the kernel
+# source the counters were taken on; any change to it reports null.
+JACOBI_TRAFFIC = {"kernels_sha256": "47ee1f50c14d88e3ad31f9b92b6bb005cade0bf62f78b4046c5166a2b9445266",
+                  "bytes_per_launch": 83372710, "profile": "profiles/band512_jacobi_traffic.md"}
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--n", type=int, default=512)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=30)
-    ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (no baseline)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the sharding design is documented, not implemented); use --gpus 1", file=sys.stderr)
-        sys.exit(2)
 
-    import numpy as np
-    import torch
+def _jacobi_traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2012_08141_amd", "csrc", "kernels.hip")
+    try:
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if JACOBI_TRAFFIC["kernels_sha256"] != h:
+        return None
+    return JACOBI_TRAFFIC["bytes_per_launch"]
+METRIC = "active voxel-steps/s + launches/step, optimized vs eager pipeline, 1 GPU"
 
-    from paper_2012_08141_amd import _lib as L
+
+def _base(K, W, value, ms, config):
+    return {"metric": METRIC, "value": value, "unit": "voxel-steps/s", "n_gpus": 1, "steps": K, "warmup": W,
+            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic", "config": config}
+
+
+def settle_host():
+    """Collect once and freeze the survivors (torch's import graph, ~170k
+    objects), so a generation-2 collection inside a timed region scans only
+    new objects instead of taking ~50 ms."""
+    import gc
+    gc.collect()
+    gc.freeze()
+
+
+def _host_cpu():
+    try:
+        return subprocess.run(["bash", "-c", "lscpu | grep 'Model name' | head -1"], capture_output=True,
+                              text=True).stdout.split(":", 1)[-1].strip()
+    except Exception:
+        return "unknown"
+
+
+def time_kernel(torch, E, task_fn, reps):
+    """Average duration of back-to-back launches of one task, from HIP events
+    on the stream the launches go to."""
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tasks = [task_fn() for _ in range(reps)]
+    E.run_sequence(tasks[:2], E.OPT_AD)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    E.run_sequence(tasks, E.OPT_AD)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / reps * 1e-3
+
+
+# --------------------------------------------------------------------- band512
+def bench_band(args, torch):
     from paper_2012_08141_amd import engine as E
     from paper_2012_08141_amd import inputs, programs as PR
-
-    assert torch.cuda.is_available(), "bench needs a HIP device"
-    torch.cuda.set_device(0)
     w = inputs.band(args.seed, n=args.n)
     voxels = w.active_voxels
     K, W = args.steps, args.warmup
@@ -67,93 +109,224 @@ def main():
         t0 = time.perf_counter()
         st = E.run_sequence(timed, opt)
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        return g, st, t1 - t0
+        return g, st, time.perf_counter() - t0
 
     g_opt, st_opt, t_opt = run_pipeline(E.OPT_ALL)
     g_eag, st_eag, t_eag = run_pipeline(0)
     same = bool(torch.equal(g_opt.channel(0), g_eag.channel(0)))
-
-    # dominant kernel: the Jacobi stencil, timed alone with HIP events on the
-    # stream it is launched on (the copy kernel is timed the same way)
-    stream = torch.cuda.current_stream()
-
-    def time_kernel(task_fn, reps):
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        tasks = [task_fn() for _ in range(reps)]
-        E.run_sequence(tasks[:2], E.OPT_AD)
-        torch.cuda.synchronize()
-        ev0.record(stream)
-        E.run_sequence(tasks, E.OPT_AD)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        return ev0.elapsed_time(ev1) / reps * 1e-3   # seconds per launch
-
+    del g_eag
     reps = max(20, K)
-    t_jac = time_kernel(lambda: E.jacobi(g_opt, PR.JACOBI["x"], PR.JACOBI["b"], PR.JACOBI["xn"]), reps)
-    t_copy = time_kernel(lambda: E.copy(g_opt, PR.JACOBI["x"], PR.JACOBI["xn"]), reps)
-    jac_bytes = 12.0 * voxels        # read x, read b, write xn
-    copy_bytes = 8.0 * voxels        # read xn, write x
-    achieved = jac_bytes / t_jac / 1e9
-
-    value = voxels * K / t_opt
-    out = {
-        "metric": "active voxel-steps/s + launches/step, optimized vs eager pipeline, 1 GPU",
-        "value": value,
-        "unit": "voxel-steps/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": W,
-        "ms_per_step": t_opt / K * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "band512: sparse Jacobi, %d^3 domain, narrow band (|sdf| <= 1.5 blocks) around "
-                               "4 seeded spheres, 8^3 fp32 leaves, bitmasked root" % args.n,
-                   "seed": args.seed, "active_blocks": w.nblocks, "active_voxels": voxels,
-                   "program_per_step": "listgen, jacobi, copy", "parallelism": "single GPU"},
+    t_jac = time_kernel(torch, E, lambda: E.jacobi(g_opt, PR.JACOBI["x"], PR.JACOBI["b"], PR.JACOBI["xn"]), reps)
+    t_copy = time_kernel(torch, E, lambda: E.copy(g_opt, PR.JACOBI["x"], PR.JACOBI["xn"]), reps)
+    t_list = time_kernel(torch, E, lambda: E.listgen(g_opt), reps)
+    achieved = 12.0 * voxels / t_jac / 1e9
+    out = _base(K, W, voxels * K / t_opt, t_opt / K * 1e3,
+                {"workload": "band512: sparse Jacobi, %d^3 domain, narrow band (|sdf| <= 1.5 blocks) around "
+                             "4 seeded spheres, 8^3 fp32 leaves, bitmasked root" % args.n,
+                 "seed": args.seed, "active_blocks": w.nblocks, "active_voxels": voxels,
+                 "program_per_step": "listgen, jacobi, copy", "parallelism": "single GPU"})
+    out.update({
         "launches_per_step": {"optimized": st_opt["dispatches"] / K, "eager": st_eag["dispatches"] / K},
         "eager": {"value": voxels * K / t_eag, "ms_per_step": t_eag / K * 1e3},
         "speedup_vs_eager": t_eag / t_opt,
         "optimized_equals_eager": same,
         "optimizer_us_per_window": st_opt["optimizer_us"],
         "plan_cache_hits": st_opt["plan_cache_hits"],
-        "kernels": {"jacobi_us": t_jac * 1e6, "copy_us": t_copy * 1e6,
-                    "jacobi_GBs": achieved, "copy_GBs": copy_bytes / t_copy / 1e9,
+        "kernels": {"jacobi_us": t_jac * 1e6, "copy_us": t_copy * 1e6, "listgen_us": t_list * 1e6,
+                    "jacobi_GBs": achieved, "copy_GBs": 8.0 * voxels / t_copy / 1e9,
                     "step_GBs_algorithmic": 20.0 * voxels / (t_opt / K) / 1e9},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_stencil<JACOBI> (12 B per active voxel: x, b read; xn written)"},
-    }
-
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": _jacobi_traffic() if args.seed == 0 else None,
+                     "kernel": "k_stencil_pipe<JACOBI> (12 B per active voxel: x, b read; xn written)",
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                     "algorithmic_bytes_per_launch": 12 * voxels},
+    })
     if not args.no_cpu_baseline and not args.profile:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_iters)
+        from oracle import OracleGrid
+        og = OracleGrid(w.n, 3, "f32")
+        og.load(w.blocks, {"b": w.channels["b"]}, {"x": 0, "xn": 1, "b": 2})
+        t0 = time.perf_counter()
+        for _ in range(args.cpu_iters):
+            og.listgen()
+            og.jacobi(0, 2, 1)
+            og.copy(0, 1)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": voxels * args.cpu_iters / dt, "unit": "voxel-steps/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": "%d iterations (listgen, jacobi, copy) of the full band512 workload, "
+                                         "seed %d, single-threaded C oracle (-O2, no contraction), %.1f s"
+                                         % (args.cpu_iters, args.seed, dt),
+                               "host_cpu": _host_cpu(), "host_nproc": os.cpu_count()}
+    return out
+
+
+# ----------------------------------------------------------------------- shell
+def bench_shell(args, torch):
+    from paper_2012_08141_amd import engine as E
+    from paper_2012_08141_amd import inputs, programs as PR
+    w = inputs.shell(args.seed)
+    K, W = args.steps, args.warmup
+    coords = torch.as_tensor(w.blocks, device="cuda")
+    res = {}
+    for name, opt in (("optimized", E.OPT_ALL), ("eager", 0)):
+        g = PR.load_workload(w, PR.SHELL, 2)
+        E.run_sequence(PR.shell_setup(g, coords), opt)
+        if W:
+            E.run_sequence(sum((PR.shell_step(g, coords) for _ in range(W)), []), opt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = E.run_sequence(sum((PR.shell_step(g, coords) for _ in range(K)), []), opt)
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0, st)
+    t, st = res["optimized"]
+    out = _base(K, W, w.active_voxels * K / t, t / K * 1e3,
+                {"workload": "shell64: 64^3 spherical shell (%d blocks), per step activate, listgen, lap_update, "
+                             "listgen, axpy" % w.nblocks, "seed": args.seed})
+    out.update({"launches_per_step": {"optimized": st["dispatches"] / K, "eager": res["eager"][1]["dispatches"] / K},
+                "eager": {"value": w.active_voxels * K / res["eager"][0], "ms_per_step": res["eager"][0] / K * 1e3},
+                "speedup_vs_eager": res["eager"][0] / t})
+    return out
+
+
+# ------------------------------------------------------------------- particles
+def bench_particles(args, torch):
+    from paper_2012_08141_amd import engine as E
+    from paper_2012_08141_amd import inputs, programs as PR
+    from paper_2012_08141_amd.grid import SparseGrid
+    p = inputs.particles(args.seed)
+    K = args.steps
+    res = {}
+    for name, opt in (("optimized", E.OPT_ALL), ("eager", 0)):
+        grids = [SparseGrid(p.n, 7, "pointer", (p.n // 8) ** 3) for _ in range(2)]
+        x, v, m = PR.device_particles(p)
+        tasks = sum((PR.particle_step(grids, t, x, v, m, p.params["dt"], 1.0 / p.n) for t in range(K)), [])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = E.run_sequence(tasks, opt)
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0, st, grids)
+    t, st, grids = res["optimized"]
+    vox = sum(len(g.active_cells()) for g in grids) * 512 // 2
+    out = _base(K, 0, vox * K / t, t / K * 1e3,
+                {"workload": "particles256: 2M particles in 3 boxes, 256^3 grid, PIC P2G/normalise/G2P, two "
+                             "alternating pointer-rooted grids", "seed": args.seed, "particles": p.nparticles})
+    out.update({"particle_steps_per_s": p.nparticles * K / t,
+                "launches_per_step": {"optimized": st["dispatches"] / K, "eager": res["eager"][1]["dispatches"] / K},
+                "eager": {"value": vox * K / res["eager"][0], "ms_per_step": res["eager"][0] / K * 1e3,
+                          "particle_steps_per_s": p.nparticles * K / res["eager"][0]},
+                "speedup_vs_eager": res["eager"][0] / t, "fusions": st["fusions"],
+                "stores_eliminated": st["stores_eliminated"]})
+    return out
+
+
+# --------------------------------------------------------------------- serving
+def bench_serving(args, torch):
+    import numpy as np
+    from paper_2012_08141_amd import autotune, inputs
+    from paper_2012_08141_amd.batching import BatchArena
+    from paper_2012_08141_amd.serving import JacobiServer, make_requests, serve_eager_fifo
+    count = args.requests
+    reqs0 = make_requests(args.seed, count, np.zeros(count))
+    # tune the batched launch on the full closed batch (long windows)
+    scratch = BatchArena(128, count, sum(r.nblocks for r in reqs0))
+    for r in reqs0:
+        scratch.admit(r.cells, r.b, 1 << 40)
+    tune = autotune.tune_batch(scratch, "batch128x%d" % count)
+    del scratch
+    srv = JacobiServer(128, args.budget_mib << 20, 64, tune["iters_per_replay"], tune["workgroups"])
+    closed = srv.serve(make_requests(args.seed, count, np.zeros(count)), realtime=False)
+    cap_rps = count / closed.makespan
+    rate = args.load * cap_rps
+    arr = inputs.poisson_arrivals(args.seed, count, rate)
+    reqs = make_requests(args.seed, count, arr)
+    srv2 = JacobiServer(128, args.budget_mib << 20, 64, tune["iters_per_replay"], tune["workgroups"])
+    st = srv2.serve(reqs, realtime=True)
+    base = serve_eager_fifo(make_requests(args.seed, count, arr), realtime=True)
+    s, b = st.summary(), base.summary()
+    out = _base(count, 0, s["voxel_steps_per_s"], s["makespan_s"] * 1e3 / count,
+                {"workload": "serving: %d Jacobi requests (128^3, 32-4096 blocks log-uniform, 50 iterations), "
+                             "Poisson arrivals at %.2f x batched capacity, HBM budget %d MiB" %
+                             (count, args.load, args.budget_mib), "seed": args.seed})
+    out.update({"latency_ms": {"p50": s["p50_ms"], "p99": s["p99_ms"], "mean": s["mean_ms"]},
+                "closed_batch_voxel_steps_per_s": closed.voxel_iters / closed.makespan,
+                "arrival_rate_per_s": rate, "max_resident": s["max_resident"], "replays": s["replays"],
+                "autotune": {k: v for k, v in tune.items() if k != "candidates"},
+                "eager_fifo": {"value": b["voxel_steps_per_s"], "latency_ms": {"p50": b["p50_ms"], "p99": b["p99_ms"]}},
+                "speedup_vs_eager": s["voxel_steps_per_s"] / b["voxel_steps_per_s"]})
+    return out
+
+
+# ------------------------------------------------------------------- diffusion
+def bench_diffusion(args, torch):
+    from paper_2012_08141_amd import inputs
+    from paper_2012_08141_amd.autodiff import DiffusionProblem, diffusion_loss
+    w = inputs.diffusion(args.seed)
+    prob = DiffusionProblem(w.n, w.blocks, 0.1, 20, 5)
+    a0 = torch.as_tensor(w.channels["a"], device="cuda")
+    k = torch.as_tensor(w.channels["k"], device="cuda")
+    tgt = torch.as_tensor(w.channels["target"], device="cuda")
+    times = []
+    for _ in range(args.warmup + args.steps):
+        a = a0.clone().requires_grad_(True)
+        kk = k.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss = diffusion_loss(a, kk, tgt, prob)
+        loss.backward()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    t = sorted(times[args.warmup:])[len(times[args.warmup:]) // 2]
+    out = _base(args.steps, args.warmup, w.active_voxels * 20 / t, t * 1e3,
+                {"workload": "diffusion128: 20 diffusion steps + adjoint (checkpoints every 5) on a 128^3 shell "
+                             "(%d blocks)" % w.nblocks, "seed": args.seed})
+    out["note"] = "value counts forward steps only; one step = forward and backward of the whole 20-step loss"
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--workload", default="band512", choices=["band512", "shell", "particles", "serving", "diffusion"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=30)
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--load", type=float, default=0.8)
+    ap.add_argument("--budget-mib", type=int, default=256)
+    ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (no CPU baseline)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the run, one plain torch copy of this many MiB (the known-size kernel that "
+                         "scales rocprofv3 FETCH_SIZE / WRITE_SIZE readings)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the sharding design is documented, not implemented); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    defaults = {"band512": (100, 10), "shell": (100, 10), "particles": (20, 0), "serving": (256, 0),
+                "diffusion": (10, 2)}
+    d = defaults[args.workload]
+    args.steps = d[0] if args.steps is None else args.steps
+    args.warmup = d[1] if args.warmup is None else args.warmup
+
+    import torch
+    assert torch.cuda.is_available(), "bench needs a HIP device"
+    torch.cuda.set_device(0)
+    settle_host()
+    fn = {"band512": bench_band, "shell": bench_shell, "particles": bench_particles, "serving": bench_serving,
+          "diffusion": bench_diffusion}[args.workload]
+    out = fn(args, torch)
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib << 18
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = 4 * n
     print(json.dumps(out), flush=True)
-
-
-def cpu_baseline(w, iters):
-    """The oracle (single-threaded C) on a bounded sample of the same
-    workload: `iters` Jacobi iterations of the full 512^3 band."""
-    from oracle import OracleGrid
-    g = OracleGrid(w.n, 3, "f32")
-    g.load(w.blocks, {"b": w.channels["b"]}, {"x": 0, "xn": 1, "b": 2})
-    t0 = time.perf_counter()
-    for _ in range(iters):
-        g.listgen()
-        g.jacobi(0, 2, 1)
-        g.copy(0, 1)
-    dt = time.perf_counter() - t0
-    try:
-        model = subprocess.run(["bash", "-c", "lscpu | grep 'Model name' | head -1"], capture_output=True,
-                               text=True).stdout.split(":", 1)[-1].strip()
-    except Exception:
-        model = "unknown"
-    return {"value": w.active_voxels * iters / dt, "unit": "voxel-steps/s", "cores": 1, "kind": "oracle",
-            "sample": "%d iterations (listgen, jacobi, copy) of the full band512 workload, seed 0, "
-                      "single-threaded C oracle (-O2, no contraction), %.1f s" % (iters, dt),
-            "host_cpu": model, "host_nproc": os.cpu_count()}
 
 
 if __name__ == "__main__":

@@ -275,8 +275,9 @@ typedef struct at_plan_entry {
     int32_t members[AT_PLAN_MAX_MEMBERS];   /* indices into the input task array */
     int32_t check_activation;     /* 1 if activating writes keep their check */
     int32_t activation_mode;      /* AT_ACT_* for particle scatter */
-    uint32_t dropped;             /* bit q: member q's dropped stores (DSE) */
-    int32_t fill_channels;        /* remaining channels of a FILL member 0 (bitmask of ch slots) */
+    uint32_t dropped;             /* bit q: member q lost some stores to DSE */
+    uint32_t keep[AT_PLAN_MAX_MEMBERS];   /* per member: FILL channel slots / NORMALISE
+                                             components still stored (all ones otherwise) */
 } at_plan_entry;
 
 /* Plan a window without running it or changing engine state (host only). */
@@ -295,6 +296,12 @@ at_status at_flush(at_stats *stats, hipStream_t stream);
 #define AT_OPTION_OPT_FLAGS         3   /* flags for at_enqueue/at_flush, default AT_OPT_ALL */
 #define AT_OPTION_PLAN_CACHE        4   /* 1 (default) caches optimized plans */
 #define AT_OPTION_STRUCT_FOR_WORKGROUPS 5 /* persistent struct-for grid size; 0 = automatic */
+/* Struct-for kernel form (a tuning knob; results are identical):
+ * 0 (default) software-pipelined kernels reading the list records,
+ * 1 one block per wave iteration reading the list records,
+ * 2 one block per wave iteration with neighbour lookups in the root.
+ * Records are only read when list generation left them current. */
+#define AT_OPTION_STRUCT_FOR_KERNEL 6
 at_status at_set_option(int32_t option, int64_t value);
 at_status at_get_option(int32_t option, int64_t *value);
 

@@ -63,6 +63,7 @@ def _lib(prec: str):
         "og_listgen": (i64, [P]),
         "og_active_cells": (i64, [P, P]),
         "og_get_list": (i64, [P, P]),
+        "og_set_list": (None, [P, P, i64]),
         "og_read": (R, [P, i32, i32, i32, i32]),
         "og_read_block": (None, [P, i32, ctypes.c_int32, P]),
         "og_write_block": (None, [P, i32, ctypes.c_int32, P]),
@@ -139,6 +140,11 @@ class OracleGrid:
         out = np.zeros(self.R ** 3, dtype=np.int32)
         cnt = self._L.og_get_list(self._g, _ptr(out))
         return out[:cnt].copy()
+
+    def set_list(self, cells) -> None:
+        """Replace the list state (a struct-for then visits exactly these blocks)."""
+        c = np.ascontiguousarray(np.asarray(cells, dtype=np.int32))
+        self._L.og_set_list(self._g, _ptr(c), c.shape[0])
 
     def active_cells(self) -> np.ndarray:
         out = np.zeros(self.R ** 3, dtype=np.int32)

@@ -149,6 +149,13 @@ int64_t og_active_cells(const og_grid *g, int32_t *out) {
     return cnt;
 }
 
+/* Replace the list state (test helper: lets a test run a struct-for over a
+ * chosen subset of blocks, e.g. one block at a time). */
+void og_set_list(og_grid *g, const int32_t *cells, int64_t n) {
+    memcpy(g->list, cells, sizeof(int32_t) * (size_t)n);
+    g->count = n;
+}
+
 int64_t og_get_list(const og_grid *g, int32_t *out) {
     memcpy(out, g->list, sizeof(int32_t) * (size_t)g->count);
     return g->count;

@@ -28,6 +28,7 @@ AT_OPT_LGR, AT_OPT_AD, AT_OPT_FUSE, AT_OPT_DSE, AT_OPT_ALL = 1, 2, 4, 8, 15
 AT_PLAN_MAX_MEMBERS = 8
 AT_OPTION_MAX_FUSE_PER_TASK, AT_OPTION_FLUSH_PERIOD, AT_OPTION_OPT_FLAGS, AT_OPTION_PLAN_CACHE = 1, 2, 3, 4
 AT_OPTION_STRUCT_FOR_WORKGROUPS = 5
+AT_OPTION_STRUCT_FOR_KERNEL = 6
 
 
 class AtGridDesc(ctypes.Structure):
@@ -67,7 +68,7 @@ class AtBatchViews(ctypes.Structure):
 class AtPlanEntry(ctypes.Structure):
     _fields_ = [("kind", c_int32), ("nmembers", c_int32), ("members", c_int32 * AT_PLAN_MAX_MEMBERS),
                 ("check_activation", c_int32), ("activation_mode", c_int32), ("dropped", c_uint32),
-                ("fill_channels", c_int32)]
+                ("keep", c_uint32 * AT_PLAN_MAX_MEMBERS)]
 
 
 _P = c_void_p

@@ -1,0 +1,69 @@
+"""Autotuner for the batched Jacobi launch.
+
+Times every candidate (persistent workgroup count, iterations per captured
+graph) on the actual batch with HIP events, keeps the fastest per iteration
+-- preferring fewer iterations per replay within 3% of the best, since that
+is the admission granularity of the server -- and caches the choice per
+(device, workload signature) in a JSON file.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+CACHE = os.path.join(os.environ.get("XDG_CACHE_HOME", os.path.expanduser("~/.cache")), "atsparse", "autotune.json")
+
+
+def _load():
+    try:
+        return json.load(open(CACHE))
+    except Exception:
+        return {}
+
+
+def _store(d):
+    try:
+        os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+        json.dump(d, open(CACHE, "w"), indent=1)
+    except OSError:
+        pass
+
+
+def device_key() -> str:
+    p = torch.cuda.get_device_properties(0)
+    return "%s/%d" % (p.name, p.multi_processor_count)
+
+
+def tune_batch(arena, signature: str, workgroups=(2048, 4096, 7168, 14336), iters=(5, 10, 25),
+               reps: int = 4, use_cache: bool = True) -> dict:
+    """Pick (workgroups, iters_per_replay) for ``arena`` with its current
+    grids resident.  The arena's clock advances; callers tune on a scratch
+    arena or re-admit afterwards."""
+    key = device_key() + "|" + signature
+    cache = _load() if use_cache else {}
+    if key in cache:
+        return cache[key]
+    results = []
+    for wgs in workgroups:
+        for K in iters:
+            g = arena.capture(K, wgs)
+            g.replay()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                g.replay()
+            b.record()
+            torch.cuda.synchronize()
+            per_iter = a.elapsed_time(b) * 1e-3 / (reps * K)
+            results.append({"workgroups": wgs, "iters_per_replay": K, "s_per_iter": per_iter})
+    best = min(r["s_per_iter"] for r in results)
+    ok = [r for r in results if r["s_per_iter"] <= 1.03 * best]
+    choice = min(ok, key=lambda r: (r["iters_per_replay"], r["s_per_iter"]))
+    choice = dict(choice, candidates=results)
+    if use_cache:
+        cache[key] = choice
+        _store(cache)
+    return choice

@@ -104,6 +104,8 @@ hipError_t launch_batch_jacobi(const BatchDev &d, int iters, int workgroups, hip
 // Persistent grid size used by struct-for kernels (workgroups).
 int struct_for_grid_size(const GridDev &g);
 void set_struct_for_grid_size(int wgs);   // 0 = automatic
+int struct_for_kernel();
+void set_struct_for_kernel(int form);     // 0 pipelined, 1 direct with records, 2 direct with root lookups
 
 }  // namespace ats
 

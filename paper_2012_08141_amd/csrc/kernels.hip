@@ -19,6 +19,7 @@ namespace {
 constexpr int kSFThreads = 128;          // struct-for workgroup
 constexpr int kSpinLimit = 1 << 22;      // bounded wait on a pointer-root allocation
 int g_sf_grid_override = 0;
+int g_sf_kernel = 0;
 
 // -------------------------------------------------------------- root access
 
@@ -159,24 +160,65 @@ __device__ __forceinline__ uint64_t scan_flag(uint32_t epoch, uint32_t status, u
 // and the slots of its six face neighbours (order i-1, i+1, j-1, j+1, k-1,
 // k+1; -1 when inactive or outside the domain), as of this list generation.
 template <int KIND>
+__device__ __forceinline__ int32_t lookup_slot(const GridDev &g, int64_t c, bool ok) {
+    // unconditional load of a valid address; the select discards it
+    const int64_t cc = ok ? c : 0;
+    int32_t s;
+    if (KIND == AT_ROOT_BITMASK) s = ((g.bits[cc >> 5] >> (cc & 31)) & 1u) ? (int32_t)cc : -1;
+    else s = g.ptr[cc];
+    return ok ? (s >= 0 ? s : -1) : -1;
+}
+
+template <int KIND>
 __device__ __forceinline__ void write_record(const GridDev &g, int32_t cell, int pos) {
     int bi, bj, bk;
     cell_coords(g, cell, bi, bj, bk);
     const int32_t slot = (KIND == AT_ROOT_BITMASK) ? cell : g.ptr[cell];
-    const int32_t n0 = bi > 0 ? slot_of<KIND>(g, cell - g.R2) : -1;
-    const int32_t n1 = bi < g.R - 1 ? slot_of<KIND>(g, cell + g.R2) : -1;
-    const int32_t n2 = bj > 0 ? slot_of<KIND>(g, cell - g.R) : -1;
-    const int32_t n3 = bj < g.R - 1 ? slot_of<KIND>(g, cell + g.R) : -1;
-    const int32_t n4 = bk > 0 ? slot_of<KIND>(g, cell - 1) : -1;
-    const int32_t n5 = bk < g.R - 1 ? slot_of<KIND>(g, cell + 1) : -1;
     int4 *r = reinterpret_cast<int4 *>(g.list + (int64_t)pos * kRec);
-    r[0] = make_int4(cell, slot, n0, n1);
-    r[1] = make_int4(n2, n3, n4, n5);
+    r[0] = make_int4(cell, slot, lookup_slot<KIND>(g, cell - g.R2, bi > 0), lookup_slot<KIND>(g, cell + g.R2, bi < g.R - 1));
+    r[1] = make_int4(lookup_slot<KIND>(g, cell - g.R, bj > 0), lookup_slot<KIND>(g, cell + g.R, bj < g.R - 1),
+                     lookup_slot<KIND>(g, cell - 1, bk > 0), lookup_slot<KIND>(g, cell + 1, bk < g.R - 1));
+}
+
+// Wave-parallel decoupled look-back: lane l inspects predecessor bid-1-l;
+// the nearest predecessor with an inclusive prefix ends the walk, all
+// nearer ones must have published their aggregate.  Bounded retries.
+__device__ __forceinline__ int lookback(const GridDev &g, uint64_t *flags, uint32_t epoch, int bid) {
+    const int lane = threadIdx.x & 63;
+    int base = 0;
+    int j = bid - 1;
+    for (int it = 0; j >= 0;) {
+        const int jj = j - lane;
+        uint64_t f = scan_flag(epoch, SCAN_INCL, 0);    // before workgroup 0: prefix 0
+        if (jj >= 0) f = __hip_atomic_load(&flags[jj], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t st = ((uint32_t)(f >> 32) == epoch) ? (uint32_t)(f >> 30) & 3u : 0u;
+        const uint64_t incl = __ballot(st == SCAN_INCL);
+        const uint64_t notready = __ballot(st == 0);
+        const int L = incl ? __builtin_ctzll(incl) : 64;
+        const uint64_t need = L == 64 ? ~0ull : ((2ull << L) - 1);
+        if (notready & need) {
+            if (++it >= kSpinLimit) {
+                if (lane == 0) atomicOr(&g.hdr[HDR_ERR], ERR_SPIN);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        int v = lane <= L ? (int)(f & 0x3fffffffu) : 0;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        base += v;
+        if (L < 64) break;
+        j -= 64;
+    }
+    return base;
 }
 
 // Thread t of workgroup b owns C consecutive root cells (C = 8 or 16: part
 // of one bit word; C >= 32: C/32 whole words), so a dense run of active
-// cells is spread over many threads and many workgroups.
+// cells is spread over many threads and many workgroups.  For C <= 16 every
+// lookup of a thread's records (its cells' slots and neighbour slots) is
+// issued before any record is written.
 template <int KIND, int C>
 __global__ __launch_bounds__(256) void k_listgen(GridDev g, uint64_t *flags, uint32_t epoch) {
     constexpr int WPT = C >= 32 ? C / 32 : 1;
@@ -210,47 +252,65 @@ __global__ __launch_bounds__(256) void k_listgen(GridDev g, uint64_t *flags, uin
     __syncthreads();
     const int before = (wid > 0 ? wsum[0] : 0) + (wid > 1 ? wsum[1] : 0) + (wid > 2 ? wsum[2] : 0);
     const int total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-    if (tid == 0) {
+    if (wid == 0) {
         const int bid = blockIdx.x;
         int base = 0;
         if (bid == 0) {
-            __hip_atomic_store(&flags[0], scan_flag(epoch, SCAN_INCL, (uint32_t)total), __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0)
+                __hip_atomic_store(&flags[0], scan_flag(epoch, SCAN_INCL, (uint32_t)total), __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            __hip_atomic_store(&flags[bid], scan_flag(epoch, SCAN_AGG, (uint32_t)total), __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            int j = bid - 1;
-            for (int it = 0; j >= 0; ++it) {
-                const uint64_t f = __hip_atomic_load(&flags[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                const uint32_t st = (uint32_t)(f >> 30) & 3u;
-                if ((uint32_t)(f >> 32) != epoch || st == 0) {
-                    if (it >= kSpinLimit) {
-                        atomicOr(&g.hdr[HDR_ERR], ERR_SPIN);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                base += (int)(f & 0x3fffffffu);
-                if (st == SCAN_INCL) break;
-                --j;
-            }
-            __hip_atomic_store(&flags[bid], scan_flag(epoch, SCAN_INCL, (uint32_t)(base + total)), __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0)
+                __hip_atomic_store(&flags[bid], scan_flag(epoch, SCAN_AGG, (uint32_t)total), __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            base = lookback(g, flags, epoch, bid);
+            if (lane == 0)
+                __hip_atomic_store(&flags[bid], scan_flag(epoch, SCAN_INCL, (uint32_t)(base + total)),
+                                   __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
-        s_base = base;
-        if (bid == (int)gridDim.x - 1) g.hdr[HDR_COUNT] = base + total;
+        if (lane == 0) {
+            s_base = base;
+            if (bid == (int)gridDim.x - 1) g.hdr[HDR_COUNT] = base + total;
+        }
     }
     __syncthreads();
     int pos = s_base + before + incl - cnt;
+    if (C <= 16) {
+        // all lookups first (C cells x 7), then the records
+        int32_t sl[C], nb[C][6];
 #pragma unroll
-    for (int q = 0; q < WPT; ++q) {
-        uint32_t v = b[q];
-        const int64_t cb = C < 32 ? c0 : c0 + 32 * q;
-        while (v) {
-            const int bit = __builtin_ctz(v);
-            write_record<KIND>(g, (int32_t)(cb + bit), pos++);
-            v &= v - 1;
+        for (int q = 0; q < C; ++q) {
+            const int64_t cell = c0 + q;
+            const bool on = (b[0] >> q) & 1u;
+            const int64_t cc = on ? cell : 0;
+            int bi, bj, bk;
+            cell_coords(g, (int32_t)cc, bi, bj, bk);
+            sl[q] = KIND == AT_ROOT_BITMASK ? (int32_t)cc : g.ptr[cc];
+            nb[q][0] = lookup_slot<KIND>(g, cc - g.R2, on && bi > 0);
+            nb[q][1] = lookup_slot<KIND>(g, cc + g.R2, on && bi < g.R - 1);
+            nb[q][2] = lookup_slot<KIND>(g, cc - g.R, on && bj > 0);
+            nb[q][3] = lookup_slot<KIND>(g, cc + g.R, on && bj < g.R - 1);
+            nb[q][4] = lookup_slot<KIND>(g, cc - 1, on && bk > 0);
+            nb[q][5] = lookup_slot<KIND>(g, cc + 1, on && bk < g.R - 1);
+        }
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            if (!((b[0] >> q) & 1u)) continue;
+            int4 *r = reinterpret_cast<int4 *>(g.list + (int64_t)pos * kRec);
+            r[0] = make_int4((int32_t)(c0 + q), sl[q], nb[q][0], nb[q][1]);
+            r[1] = make_int4(nb[q][2], nb[q][3], nb[q][4], nb[q][5]);
+            ++pos;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < WPT; ++q) {
+            uint32_t v = b[q];
+            const int64_t cb = c0 + 32 * q;
+            while (v) {
+                const int bit = __builtin_ctz(v);
+                write_record<KIND>(g, (int32_t)(cb + bit), pos++);
+                v &= v - 1;
+            }
         }
     }
 }
@@ -462,6 +522,259 @@ __global__ __launch_bounds__(64) void k_stencil(GridDev g, StencilCh c, float p)
             store8(c.out0 + off, r0);
             store8(c.out1 + off, r1);
         }
+    }
+}
+
+// ------------------------------------------- pipelined stencil (list table)
+// When the list records' neighbour slots are valid (mask unchanged since the
+// list generation), the stencil runs software-pipelined: the record of the
+// next block comes through the scalar cache (the list is a read-only,
+// non-aliased kernel argument) and all of that block's vector loads are
+// issued before the current block's results are stored.  The loop body has
+// no data-dependent branch (absent neighbours load a valid dummy address and
+// are zeroed by a select), so the compiler can count outstanding loads
+// exactly and never waits for the stores that follow them.
+
+template <int NT, bool HAS_E>
+struct Blk {
+    int32_t slot;
+    float4 c0[NT], c1[NT];                 // own row
+    float4 f0[NT][4], f1[NT][4];           // i-1, i+1, j-1, j+1 rows
+    float km[NT], kp[NT];                  // k-1 / k+1 beyond the row
+    float4 e0, e1;                         // elementwise input
+};
+
+template <int NT, bool HAS_E>
+__device__ __forceinline__ void fetch_blk(const StencilCh &c, const int32_t *__restrict__ recs, int e, int lane,
+                                          Blk<NT, HAS_E> &B) {
+    const int4 *r = reinterpret_cast<const int4 *>(recs + (int64_t)e * kRec);
+    const int4 a = r[0], b = r[1];
+    const int32_t slot = a.y;
+    const int32_t nb[6] = {a.z, a.w, b.x, b.y, b.z, b.w};
+    B.slot = slot;
+    const int li = lane >> 3, lj = lane & 7;
+    const int64_t own = (int64_t)slot * kBV;
+    // row base of each of the 4 lateral neighbours (own block when inside)
+    const bool in0 = li > 0, in1 = li < 7, in2 = lj > 0, in3 = lj < 7;
+    int64_t base[4];
+    base[0] = in0 ? own + (lane - 8) * 8 : (nb[0] >= 0 ? (int64_t)nb[0] * kBV + (lane + 56) * 8 : own);
+    base[1] = in1 ? own + (lane + 8) * 8 : (nb[1] >= 0 ? (int64_t)nb[1] * kBV + (lane - 56) * 8 : own);
+    base[2] = in2 ? own + (lane - 1) * 8 : (nb[2] >= 0 ? (int64_t)nb[2] * kBV + (lane + 7) * 8 : own);
+    base[3] = in3 ? own + (lane + 1) * 8 : (nb[3] >= 0 ? (int64_t)nb[3] * kBV + (lane - 7) * 8 : own);
+    const bool pr[4] = {in0 || nb[0] >= 0, in1 || nb[1] >= 0, in2 || nb[2] >= 0, in3 || nb[3] >= 0};
+    const int64_t kmb = (nb[4] >= 0 ? (int64_t)nb[4] * kBV : own) + lane * 8 + 7;
+    const int64_t kpb = (nb[5] >= 0 ? (int64_t)nb[5] * kBV : own) + lane * 8;
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        const float *ch = c.tin[nt];
+        B.c0[nt] = *reinterpret_cast<const float4 *>(ch + own + lane * 8);
+        B.c1[nt] = *reinterpret_cast<const float4 *>(ch + own + lane * 8 + 4);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const float4 u = *reinterpret_cast<const float4 *>(ch + base[f]);
+            const float4 v = *reinterpret_cast<const float4 *>(ch + base[f] + 4);
+            B.f0[nt][f] = pr[f] ? u : z;
+            B.f1[nt][f] = pr[f] ? v : z;
+        }
+        const float km = ch[kmb], kp = ch[kpb];
+        B.km[nt] = nb[4] >= 0 ? km : 0.f;
+        B.kp[nt] = nb[5] >= 0 ? kp : 0.f;
+    }
+    if (HAS_E) {
+        B.e0 = *reinterpret_cast<const float4 *>(c.ein + own + lane * 8);
+        B.e1 = *reinterpret_cast<const float4 *>(c.ein + own + lane * 8 + 4);
+    }
+}
+
+template <int NT, bool HAS_E>
+__device__ __forceinline__ void unpack(const Blk<NT, HAS_E> &B, int nt, Row &r) {
+    put8(r.c, B.c0[nt], B.c1[nt]);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) put8(r.f[f], B.f0[nt][f], B.f1[nt][f]);
+    r.f[4][0] = B.km[nt];
+    r.f[5][7] = B.kp[nt];
+#pragma unroll
+    for (int q = 1; q < 8; ++q) r.f[4][q] = r.c[q - 1];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) r.f[5][q] = r.c[q + 1];
+}
+
+template <int OP, int KIND, bool CHECK>
+__global__ __launch_bounds__(64) void k_stencil_pipe(GridDev g, const int32_t *__restrict__ recs, StencilCh c,
+                                                     float p) {
+    constexpr int NT = NTiles<OP>::v;
+    constexpr bool HAS_E = (OP == AT_OP_JACOBI || OP == AT_OP_DIFFUSE_ADJ);
+    const int lane = threadIdx.x;
+    const ListRange lr = list_range(g.hdr[HDR_COUNT]);
+    if (lr.lo >= lr.hi) return;
+    Blk<NT, HAS_E> cur, nxt;
+    fetch_blk<NT, HAS_E>(c, recs, __builtin_amdgcn_readfirstlane(lr.lo), lane, cur);
+    for (int e = lr.lo; e < lr.hi; e += lr.step) {
+        const int en = e + lr.step < lr.hi ? e + lr.step : e;
+        fetch_blk<NT, HAS_E>(c, recs, __builtin_amdgcn_readfirstlane(en), lane, nxt);
+        int32_t wslot = cur.slot;
+        if (CHECK) {
+            const int32_t cell = recs[(int64_t)e * kRec];
+            int32_t a = 0;
+            if (lane == 0) a = activate_cell<KIND>(g, cell);
+            wslot = __builtin_amdgcn_readfirstlane(a);
+        }
+        const int64_t off = (int64_t)wslot * kBV + lane * 8;
+        float r0[8], r1[8];
+        if (OP == AT_OP_LAP_UPDATE) {
+            Row A;
+            unpack(cur, 0, A);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const float s = nbsum(A, q);
+                const float six_a = 6.0f * A.c[q];
+                const float d = s - six_a;
+                const float tq = p * d;
+                r0[q] = A.c[q] + tq;
+            }
+            store8(c.out0 + off, r0);
+        } else if (OP == AT_OP_JACOBI) {
+            Row X;
+            unpack(cur, 0, X);
+            float b[8];
+            put8(b, cur.e0, cur.e1);
+            const float sixth = 0x1.555556p-3f;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const float s = nbsum(X, q);
+                const float tq = s + b[q];
+                r0[q] = tq * sixth;
+            }
+            store8(c.out0 + off, r0);
+        } else if (OP == AT_OP_DIFFUSE) {
+            Row A, K;
+            unpack(cur, 0, A);
+            unpack(cur, 1, K);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                float f = 0.f;
+#pragma unroll
+                for (int fc = 0; fc < 6; ++fc) {
+                    const float kf = 0.5f * (K.c[q] + K.f[fc][q]);
+                    f = f + kf * (A.f[fc][q] - A.c[q]);
+                }
+                r0[q] = A.c[q] + p * f;
+            }
+            store8(c.out0 + off, r0);
+        } else if (OP == AT_OP_DIFFUSE_ADJ) {
+            Row A, K, L;
+            unpack(cur, 0, A);
+            unpack(cur, 1, K);
+            unpack(cur, 2, L);
+            float gk[8];
+            put8(gk, cur.e0, cur.e1);
+            const float half_dt = p * 0.5f;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                float f = 0.f, q2 = 0.f;
+#pragma unroll
+                for (int fc = 0; fc < 6; ++fc) {
+                    const float kf = 0.5f * (K.c[q] + K.f[fc][q]);
+                    f = f + kf * (L.f[fc][q] - L.c[q]);
+                    q2 = q2 + (A.f[fc][q] - A.c[q]) * (L.c[q] - L.f[fc][q]);
+                }
+                r0[q] = L.c[q] + p * f;
+                r1[q] = gk[q] + half_dt * q2;
+            }
+            store8(c.out0 + off, r0);
+            store8(c.out1 + off, r1);
+        }
+        cur = nxt;
+    }
+}
+
+// ------------------------------------------------- elementwise (single op)
+// Single element-wise struct-for ops, pipelined the same way: the next
+// block's inputs are loaded before this block's outputs are stored.
+template <int OP>
+struct Elem {
+    int32_t slot;
+    float4 a0, a1, b0, b1, c0, c1, d0, d1;   // up to 4 input rows
+};
+
+template <int OP>
+__device__ __forceinline__ void fetch_elem(const GridDev &g, const int32_t *__restrict__ recs, const MicroOp &op,
+                                           int e, int lane, Elem<OP> &E) {
+    const int4 a = reinterpret_cast<const int4 *>(recs + (int64_t)e * kRec)[0];
+    E.slot = a.y;
+    const int64_t off = (int64_t)a.y * kBV + lane * 8;
+    auto ld = [&](int ch, float4 &u, float4 &v) {
+        const float *p = chan(g, ch) + off;
+        u = reinterpret_cast<const float4 *>(p)[0];
+        v = reinterpret_cast<const float4 *>(p)[1];
+    };
+    if (OP == AT_OP_COPY) ld(op.ch[1], E.a0, E.a1);
+    if (OP == AT_OP_AXPY) { ld(op.ch[0], E.a0, E.a1); ld(op.ch[1], E.b0, E.b1); }
+    if (OP == AT_OP_INC) ld(op.ch[0], E.a0, E.a1);
+    if (OP == AT_OP_NORMALISE) {
+        ld(op.ch[0], E.a0, E.a1);
+        ld(op.ch[1], E.b0, E.b1);
+        ld(op.ch[1] + 1, E.c0, E.c1);
+        ld(op.ch[1] + 2, E.d0, E.d1);
+    }
+}
+
+__device__ __forceinline__ float4 f4(float a, float b, float c, float d) { return make_float4(a, b, c, d); }
+
+template <int OP, int KIND, bool CHECK>
+__global__ __launch_bounds__(64) void k_elem(GridDev g, const int32_t *__restrict__ recs, MicroOp op) {
+    const int lane = threadIdx.x;
+    const ListRange lr = list_range(g.hdr[HDR_COUNT]);
+    if (lr.lo >= lr.hi) return;
+    Elem<OP> cur, nxt;
+    fetch_elem<OP>(g, recs, op, __builtin_amdgcn_readfirstlane(lr.lo), lane, cur);
+    for (int e = lr.lo; e < lr.hi; e += lr.step) {
+        const int en = e + lr.step < lr.hi ? e + lr.step : e;
+        fetch_elem<OP>(g, recs, op, __builtin_amdgcn_readfirstlane(en), lane, nxt);
+        int32_t wslot = cur.slot;
+        if (CHECK) {
+            const int32_t cell = recs[(int64_t)e * kRec];
+            int32_t a = 0;
+            if (lane == 0) a = activate_cell<KIND>(g, cell);
+            wslot = __builtin_amdgcn_readfirstlane(a);
+        }
+        const int64_t off = (int64_t)wslot * kBV + lane * 8;
+        auto st = [&](int ch, float4 u, float4 v) {
+            float *p = chan(g, ch) + off;
+            reinterpret_cast<float4 *>(p)[0] = u;
+            reinterpret_cast<float4 *>(p)[1] = v;
+        };
+        if (OP == AT_OP_COPY) {
+            st(op.ch[0], cur.a0, cur.a1);
+        } else if (OP == AT_OP_AXPY) {
+            const float a = op.p;
+            const float4 y0 = cur.a0, y1 = cur.a1, x0 = cur.b0, x1 = cur.b1;
+            st(op.ch[0], f4(y0.x + a * x0.x, y0.y + a * x0.y, y0.z + a * x0.z, y0.w + a * x0.w),
+               f4(y1.x + a * x1.x, y1.y + a * x1.y, y1.z + a * x1.z, y1.w + a * x1.w));
+        } else if (OP == AT_OP_INC) {
+            const float a = op.p;
+            st(op.ch[0], f4(cur.a0.x + a, cur.a0.y + a, cur.a0.z + a, cur.a0.w + a),
+               f4(cur.a1.x + a, cur.a1.y + a, cur.a1.z + a, cur.a1.w + a));
+        } else if (OP == AT_OP_FILL) {
+            const float4 v = f4(op.p, op.p, op.p, op.p);
+            for (int q = 0; q < 7; ++q)
+                if (op.ch[q] >= 0 && ((op.keep >> q) & 1u)) st(op.ch[q], v, v);
+        } else if (OP == AT_OP_NORMALISE) {
+            float m[8], mv[3][8];
+            put8(m, cur.a0, cur.a1);
+            put8(mv[0], cur.b0, cur.b1);
+            put8(mv[1], cur.c0, cur.c1);
+            put8(mv[2], cur.d0, cur.d1);
+            for (int cc = 0; cc < 3; ++cc) {
+                if (!((op.keep >> cc) & 1u)) continue;
+                float r[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) r[q] = m[q] > 0.f ? mv[cc][q] / m[q] : 0.f;
+                st(op.ch[2] + cc, f4(r[0], r[1], r[2], r[3]), f4(r[4], r[5], r[6], r[7]));
+            }
+        }
+        cur = nxt;
     }
 }
 
@@ -870,17 +1183,22 @@ int struct_for_grid_size(const GridDev &g) {
     return (int)wg;
 }
 
-// Wavefront-per-block kernels: up to 28 resident wavefronts per CU.
-int wave_grid_size(const GridDev &g) {
+// Wavefront-per-block kernels.  The software-pipelined forms want several
+// blocks per wavefront (8 resident wavefronts per CU measured best on the
+// 13k-block band); the direct forms hide latency with occupancy instead.
+int wave_grid_size(const GridDev &g, bool pipelined) {
     if (g_sf_grid_override > 0) return g_sf_grid_override;
     const int64_t cap = g.cap < g.ncells ? g.cap : g.ncells;
-    int64_t wg = 256 * 28;
+    int64_t wg = pipelined ? 256 * 8 : 256 * 28;
     if (cap < wg) wg = ((cap + 7) / 8) * 8;
     if (wg < 8) wg = 8;
     return (int)wg;
 }
 
 void set_struct_for_grid_size(int wgs) { g_sf_grid_override = wgs > 0 ? ((wgs + 7) / 8) * 8 : 0; }
+
+int struct_for_kernel() { return g_sf_kernel; }
+void set_struct_for_kernel(int form) { g_sf_kernel = form; }
 
 hipError_t launch_activate(const GridDev &g, const int32_t *ijk, int64_t n, int coord_kind, hipStream_t s) {
     int64_t blocks = (n + 255) / 256;
@@ -920,8 +1238,10 @@ hipError_t launch_listgen(const GridDev &g, uint64_t *flags, uint32_t epoch, hip
 
 template <int OP, int KIND, bool CHECK>
 static void launch_stencil_c(const GridDev &g, const StencilCh &c, float p, int table, hipStream_t s) {
-    const dim3 grid(wave_grid_size(g)), block(64);
-    if (table)
+    const dim3 grid(wave_grid_size(g, table && g_sf_kernel == 0)), block(64);
+    if (table && g_sf_kernel == 0)
+        hipLaunchKernelGGL((k_stencil_pipe<OP, KIND, CHECK>), grid, block, 0, s, g, (const int32_t *)g.list, c, p);
+    else if (table && g_sf_kernel == 1)
         hipLaunchKernelGGL((k_stencil<OP, KIND, CHECK, true>), grid, block, 0, s, g, c, p);
     else
         hipLaunchKernelGGL((k_stencil<OP, KIND, CHECK, false>), grid, block, 0, s, g, c, p);
@@ -965,8 +1285,35 @@ hipError_t launch_stencil(const GridDev &g, int op, const int32_t *ch, float p, 
     return hipGetLastError();
 }
 
+template <int KIND, bool CHECK>
+static bool launch_elem_k(const GridDev &g, const MicroOp &op, dim3 grid, hipStream_t s) {
+    const int32_t *recs = g.list;
+    switch (op.op) {
+    case AT_OP_COPY: hipLaunchKernelGGL((k_elem<AT_OP_COPY, KIND, CHECK>), grid, dim3(64), 0, s, g, recs, op); return true;
+    case AT_OP_AXPY: hipLaunchKernelGGL((k_elem<AT_OP_AXPY, KIND, CHECK>), grid, dim3(64), 0, s, g, recs, op); return true;
+    case AT_OP_INC: hipLaunchKernelGGL((k_elem<AT_OP_INC, KIND, CHECK>), grid, dim3(64), 0, s, g, recs, op); return true;
+    case AT_OP_FILL: hipLaunchKernelGGL((k_elem<AT_OP_FILL, KIND, CHECK>), grid, dim3(64), 0, s, g, recs, op); return true;
+    case AT_OP_NORMALISE:
+        hipLaunchKernelGGL((k_elem<AT_OP_NORMALISE, KIND, CHECK>), grid, dim3(64), 0, s, g, recs, op);
+        return true;
+    default: return false;
+    }
+}
+
 hipError_t launch_micro(const GridDev &g, const MicroProg &prog, hipStream_t s) {
-    const dim3 grid(wave_grid_size(g)), block(64);
+    const dim3 grid(wave_grid_size(g, false)), block(64);
+    if (prog.nops == 1 && g_sf_kernel == 0) {
+        const dim3 pgrid(wave_grid_size(g, true));
+        // a single element-wise op runs the pipelined kernel
+        bool done;
+        if (g.kind == AT_ROOT_BITMASK)
+            done = prog.check ? launch_elem_k<AT_ROOT_BITMASK, true>(g, prog.ops[0], pgrid, s)
+                              : launch_elem_k<AT_ROOT_BITMASK, false>(g, prog.ops[0], pgrid, s);
+        else
+            done = prog.check ? launch_elem_k<AT_ROOT_POINTER, true>(g, prog.ops[0], pgrid, s)
+                              : launch_elem_k<AT_ROOT_POINTER, false>(g, prog.ops[0], pgrid, s);
+        if (done) return hipGetLastError();
+    }
     bool st = false;
     for (int o = 0; o < prog.nops; ++o) {
         const int op = prog.ops[o].op;

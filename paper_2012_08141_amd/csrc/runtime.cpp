@@ -629,11 +629,11 @@ at_status at_plan_sequence(const at_task *tasks, int32_t ntasks, uint32_t opt_fl
         e.nmembers = (int32_t)nd.members.size();
         for (size_t m = 0; m < nd.members.size() && m < AT_PLAN_MAX_MEMBERS; ++m) {
             e.members[m] = nd.members[m].task;
+            e.keep[m] = nd.members[m].keep;
             if (nd.members[m].keep != ~0u) e.dropped |= 1u << m;
         }
         e.check_activation = nd.check_activation ? 1 : 0;
         e.activation_mode = nd.act_mode;
-        e.fill_channels = (int32_t)nd.members[0].keep;
     }
     fill_stats(stats, ntasks, nodes, ctr, (int64_t)nodes.size(), us, hits);
     return AT_OK;
@@ -697,6 +697,10 @@ at_status at_set_option(int32_t option, int64_t value) {
     case AT_OPTION_STRUCT_FOR_WORKGROUPS:
         if (value < 0 || value > (1 << 20)) return fail(AT_E_INVALID, "workgroup count out of range");
         set_struct_for_grid_size((int)value);
+        return AT_OK;
+    case AT_OPTION_STRUCT_FOR_KERNEL:
+        if (value < 0 || value > 2) return fail(AT_E_INVALID, "struct-for kernel form must be 0, 1 or 2");
+        set_struct_for_kernel((int)value);
         return AT_OK;
     default:
         return fail(AT_E_INVALID, "unknown option %d", option);

@@ -173,7 +173,8 @@ def plan_sequence(tasks, opt_flags: int = OPT_ALL):
         e = out[i]
         entries.append({"kind": e.kind, "members": [e.members[m] for m in range(e.nmembers)],
                         "check_activation": bool(e.check_activation), "activation_mode": e.activation_mode,
-                        "dropped": e.dropped, "fill_channels": e.fill_channels})
+                        "dropped": e.dropped, "keep": [e.keep[m] for m in range(e.nmembers)],
+                        "fill_channels": e.keep[0]})
     return entries, st.as_dict()
 
 
