@@ -64,6 +64,11 @@ typedef struct at_grid_desc {
     int32_t channels;         /* fp32 value channels, 1..64 */
     int32_t capacity_blocks;  /* pointer root: pool size in leaves (<= R^3);
                                  bitmask root: ignored (R^3) */
+    int32_t particle_capacity; /* particles a scatter into this grid may bin at
+                                  once (workspace of 40 B each plus 24 B per root
+                                  cell); a scatter of more particles, or any
+                                  scatter when 0, adds straight into global
+                                  memory with atomics instead of binning */
 } at_grid_desc;
 
 /* Bytes of device memory a grid with this description needs.  Host only.
@@ -175,7 +180,11 @@ at_status at_advect(float *d_x, const float *d_v, int64_t np, float dt, hipStrea
 
 /* Scatter mass and momentum: m += w*m_p, mv_c += (w*m_p)*v_c with fp32
  * atomics, activating node blocks on write.  ch: {m, mv0} (mv on mv0..mv0+2).
- * Nodes outside the domain are skipped. */
+ * Nodes outside the domain are skipped.  When the grid's particle_capacity
+ * covers np, particles are first binned by the block of their centre node and
+ * each bin is accumulated in an on-chip tile (block plus one-node halo) that
+ * is then added to the grid: five dispatches instead of one, and the order
+ * of the fp32 additions differs (results agree within fp32 rounding). */
 at_status at_p2g(at_grid grid, const float *d_x, const float *d_v, const float *d_m, int64_t np,
                  float dx, const int32_t *ch, int32_t activation, hipStream_t stream);
 
@@ -349,7 +358,9 @@ at_status at_batch_create(const at_batch_desc *desc, void *dev_buf, size_t bytes
                           at_batch *out);
 at_status at_batch_destroy(at_batch batch);
 at_status at_batch_get_views(at_batch batch, at_batch_views *views);
-/* iters x (jacobi, copy) then the clock tick: 2*iters + 1 dispatches, no
+/* One pass that records, per work-list entry, its block's pool slot and the
+ * slots of its six face neighbours (from the roots as they are now), then
+ * iters x (jacobi, copy), then the clock tick: 2*iters + 2 dispatches, no
  * host synchronisation, no fills (safe to capture in a graph).  workgroups:
  * persistent grid size (0 = automatic). */
 at_status at_batch_jacobi(at_batch batch, int32_t iters, int32_t workgroups, hipStream_t stream);

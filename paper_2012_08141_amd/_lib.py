@@ -32,7 +32,8 @@ AT_OPTION_STRUCT_FOR_KERNEL = 6
 
 
 class AtGridDesc(ctypes.Structure):
-    _fields_ = [("n", c_int32 * 3), ("root_kind", c_int32), ("channels", c_int32), ("capacity_blocks", c_int32)]
+    _fields_ = [("n", c_int32 * 3), ("root_kind", c_int32), ("channels", c_int32), ("capacity_blocks", c_int32),
+                ("particle_capacity", c_int32)]
 
 
 class AtGridInfo(ctypes.Structure):

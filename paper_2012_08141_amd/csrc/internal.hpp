@@ -13,7 +13,7 @@ constexpr int kBS = 8;      // leaf block edge
 constexpr int kBV = 512;    // voxels per leaf block
 
 // Words of the per-grid device header (first 256 bytes of the grid buffer).
-enum : int { HDR_COUNT = 0, HDR_BUMP = 1, HDR_ERR = 2, HDR_SCRATCH = 3 };
+enum : int { HDR_COUNT = 0, HDR_BUMP = 1, HDR_ERR = 2, HDR_SCRATCH = 3, HDR_NBINS = 4 };
 enum : int32_t { ERR_CAPACITY = 1, ERR_SPIN = 2 };
 
 // Pointer-root cell states besides a valid slot (>= 0).
@@ -33,6 +33,13 @@ struct GridDev {
     float *chan;        // channel 0 base; channel c at chan + c * ch_stride
     int64_t ch_stride;  // floats per channel (cap * 512)
     uint64_t *scan;     // list generation look-back flags (kScanFlags entries)
+    // particle binning workspace (absent when pcap == 0)
+    int64_t pcap;       // particles that can be binned at once
+    int32_t *pcount;    // [R^3] particles per root cell (zero between scatters)
+    int32_t *poff;      // [R^3] first position of each cell's particles in pstage
+    int4 *pbins;        // [R^3] non-empty cells: {cell, first, count, 0}; count in hdr[HDR_NBINS]
+    int2 *pkr;          // [pcap] per particle: {root cell of its centre node or -1, rank in that cell}
+    float4 *pstage;     // [pcap][2] particle records {x0, x1, x2, v0}, {v1, v2, m, 0} grouped by cell
 };
 
 constexpr int kScanFlags = 1024;   // = maximum workgroups of one list generation
@@ -82,6 +89,7 @@ struct BatchDev {
     int64_t *window;         // [max_grids][2]: first and one-past-last active iteration
     int32_t *roots;          // [max_grids][R^3]: pool slot or -1
     int32_t *work;           // [pool]: grid * R^3 + cell
+    int4 *rec;               // [pool][2]: per work entry {slot, grid, nb0, nb1}, {nb2, nb3, nb4, nb5}
     float *x, *xn, *b;       // [pool][512]
 };
 
@@ -93,7 +101,9 @@ hipError_t launch_listgen(const GridDev &g, uint64_t *flags, uint32_t epoch, hip
 hipError_t launch_stencil(const GridDev &g, int op, const int32_t *ch, float p, int check, int table,
                           hipStream_t s);
 hipError_t launch_micro(const GridDev &g, const MicroProg &prog, hipStream_t s);
-hipError_t launch_particles(const PartProg &prog, hipStream_t s);
+// Launches one particle task (1 dispatch, or 4 when its scatter is binned;
+// the count is stored in *dispatches).
+hipError_t launch_particles(const PartProg &prog, hipStream_t s, int *dispatches);
 hipError_t launch_scatter_blocks(const GridDev &g, int ch, const int32_t *cells, const float *vals,
                                  int64_t n, hipStream_t s);
 hipError_t launch_gather_blocks(const GridDev &g, int ch, const int32_t *cells, float *vals,

@@ -943,20 +943,41 @@ __global__ __launch_bounds__(64) void k_micro(GridDev g, MicroProg prog) {
 // window[g].start <= i < window[g].end, with i = clock + it, so one captured
 // sequence of launches serves any mix of grids admitted at different times.
 // One wavefront per listed block, the same arithmetic (and operation order)
-// as the single-grid Jacobi and copy kernels.
+// as the single-grid Jacobi and copy kernels; the block's slot and its
+// neighbours' come from a record per work entry, so the sweep does no root
+// lookups.
+
+// Records of the work list, rebuilt at the start of every call from the
+// roots as they are then: {slot, grid, nb0, nb1}, {nb2, nb3, nb4, nb5}.
+__global__ __launch_bounds__(256) void k_batch_records(BatchDev d) {
+    const int n = *d.count;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const int32_t w = d.work[e];
+        const int gid = w / d.ncells;
+        const int32_t cell = w - gid * d.ncells;
+        const int32_t *root = d.roots + (int64_t)gid * d.ncells;
+        const int bi = cell / d.R2, r = cell - bi * d.R2, bj = r / d.R, bk = r - bj * d.R;
+        auto nb = [&](bool ok, int32_t c) {
+            const int32_t s = ok ? root[c] : -1;
+            return s >= 0 ? s : -1;
+        };
+        d.rec[2 * e] = make_int4(root[cell], gid, nb(bi > 0, cell - d.R2), nb(bi < d.R - 1, cell + d.R2));
+        d.rec[2 * e + 1] = make_int4(nb(bj > 0, cell - d.R), nb(bj < d.R - 1, cell + d.R), nb(bk > 0, cell - 1),
+                                     nb(bk < d.R - 1, cell + 1));
+    }
+}
 
 template <bool COPY>
 __global__ __launch_bounds__(64) void k_batch(BatchDev d, int it) {
     const int lane = threadIdx.x;
     const int64_t now = *d.clock + it;
     const ListRange lr = list_range(*d.count);
+    const int4 *__restrict__ rec = d.rec;
     for (int e = lr.lo; e < lr.hi; e += lr.step) {
-        const int32_t w = d.work[e];
-        const int gid = w / d.ncells;
-        const int32_t cell = w - gid * d.ncells;
+        const int4 r0 = rec[2 * e];
+        const int gid = r0.y;
         if (now < d.window[2 * gid] || now >= d.window[2 * gid + 1]) continue;
-        const int32_t *root = d.roots + (int64_t)gid * d.ncells;
-        const int32_t slot = root[cell];
+        const int32_t slot = r0.x;
         const int64_t off = (int64_t)slot * kBV + lane * 8;
         if (COPY) {
             const float4 a = reinterpret_cast<const float4 *>(d.xn + off)[0];
@@ -965,39 +986,21 @@ __global__ __launch_bounds__(64) void k_batch(BatchDev d, int it) {
             reinterpret_cast<float4 *>(d.x + off)[1] = b;
             continue;
         }
-        const int bi = cell / d.R2, r = cell - bi * d.R2, bj = r / d.R, bk = r - bj * d.R;
-        int32_t mine = -1;
-        if (lane < 6) {
-            bool ok;
-            int32_t dc;
-            switch (lane) {
-            case 0: ok = bi > 0; dc = -d.R2; break;
-            case 1: ok = bi < d.R - 1; dc = d.R2; break;
-            case 2: ok = bj > 0; dc = -d.R; break;
-            case 3: ok = bj < d.R - 1; dc = d.R; break;
-            case 4: ok = bk > 0; dc = -1; break;
-            default: ok = bk < d.R - 1; dc = 1; break;
-            }
-            if (ok) {
-                const int32_t sn = root[cell + dc];
-                mine = sn >= 0 ? sn : -1;
-            }
-        }
+        const int4 r1 = rec[2 * e + 1];
         Nbs n;
-#pragma unroll
-        for (int f = 0; f < 6; ++f) n.s[f] = __builtin_amdgcn_readlane(mine, f);
+        n.s[0] = r0.z; n.s[1] = r0.w; n.s[2] = r1.x; n.s[3] = r1.y; n.s[4] = r1.z; n.s[5] = r1.w;
         Row X;
         load_row(d.x, slot, n, lane, X);
-        float b[8], r0[8];
+        float b[8], r[8];
         put8(b, reinterpret_cast<const float4 *>(d.b + off)[0], reinterpret_cast<const float4 *>(d.b + off)[1]);
         const float sixth = 0x1.555556p-3f;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const float sum = nbsum(X, q);
             const float tq = sum + b[q];
-            r0[q] = tq * sixth;
+            r[q] = tq * sixth;
         }
-        store8(d.xn + off, r0);
+        store8(d.xn + off, r);
     }
 }
 
@@ -1017,7 +1020,12 @@ __device__ __forceinline__ int bspline(float X, float w[3]) {
     return base;
 }
 
-template <int KS, int KD, uint32_t STEPS, int ACT>
+// One thread per particle: optional gather (G2P), advection and scatter
+// (P2G).  With BIN the scatter only records, for each particle whose centre
+// node (base + 1 per axis) lies in the domain, that node's root cell
+// (k_bin_rank, k_bin_scan, k_bin_place and k_p2g_bins finish the scatter);
+// the others scatter directly.
+template <int KS, int KD, uint32_t STEPS, int ACT, bool BIN>
 __global__ __launch_bounds__(256) void k_particles(PartProg pp) {
     const int64_t np = pp.np;
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np;
@@ -1070,6 +1078,14 @@ __global__ __launch_bounds__(256) void k_particles(PartProg pp) {
             float w[3][3];
             int base[3];
             for (int c = 0; c < 3; ++c) base[c] = bspline(x[c] * pp.inv_dx_dst, w[c]);
+            if (BIN) {
+                const int hi = base[0] + 1, hj = base[1] + 1, hk = base[2] + 1;
+                if (hi >= 0 && hj >= 0 && hk >= 0 && hi < N && hj < N && hk < N) {
+                    g.pkr[p] = make_int2(((hi >> 3) * g.R + (hj >> 3)) * g.R + (hk >> 3), 0);
+                    continue;
+                }
+                g.pkr[p] = make_int2(-1, 0);
+            }
             const float mp = pp.m[p];
             float *M = chan(g, pp.ch_m), *MV0 = chan(g, pp.ch_mv), *MV1 = chan(g, pp.ch_mv + 1),
                   *MV2 = chan(g, pp.ch_mv + 2);
@@ -1115,6 +1131,192 @@ __global__ __launch_bounds__(256) void k_particles(PartProg pp) {
                 }
             }
         }
+    }
+}
+
+// ------------------------------------------------ binned scatter (P2G)
+// Rank of each binned particle within its cell.  Every particle lands on one
+// of the few hundred to thousand cells its grid has active, so counting with
+// one global atomic per particle would queue thousands of atomics on each
+// counter.  With LDS (root cells <= kHistCells) each workgroup (one per CU)
+// counts a contiguous range of particles in an on-chip histogram first and
+// adds each cell's total to the global count once, taking its base from the
+// returned value.
+constexpr int kHistCells = 32768;
+
+template <bool LDS>
+__global__ __launch_bounds__(1024) void k_bin_rank(GridDev g, int64_t np) {
+    const int64_t per = (np + gridDim.x - 1) / gridDim.x;
+    const int64_t p0 = blockIdx.x * per < np ? blockIdx.x * per : np;
+    const int64_t p1 = p0 + per < np ? p0 + per : np;
+    const int t = threadIdx.x;
+    if (!LDS) {
+        for (int64_t p = p0 + t; p < p1; p += blockDim.x) {
+            int2 kr = g.pkr[p];
+            if (kr.x < 0) continue;
+            kr.y = atomicAdd(&g.pcount[kr.x], 1);
+            g.pkr[p] = kr;
+        }
+        return;
+    }
+    __shared__ int32_t h[kHistCells];
+    const int nc = (int)g.ncells;
+    for (int c = t; c < nc; c += blockDim.x) h[c] = 0;
+    __syncthreads();
+    for (int64_t p = p0 + t; p < p1; p += blockDim.x) {
+        int2 kr = g.pkr[p];
+        if (kr.x < 0) continue;
+        kr.y = atomicAdd(&h[kr.x], 1);
+        g.pkr[p] = kr;
+    }
+    __syncthreads();
+    for (int c = t; c < nc; c += blockDim.x) {
+        const int k = h[c];
+        if (k) h[c] = atomicAdd(&g.pcount[c], k);
+    }
+    __syncthreads();
+    for (int64_t p = p0 + t; p < p1; p += blockDim.x) {
+        int2 kr = g.pkr[p];
+        if (kr.x < 0) continue;
+        kr.y += h[kr.x];
+        g.pkr[p] = kr;
+    }
+}
+
+// Exclusive scan of the per-cell particle counts in one workgroup: the first
+// position of each cell's particles, the list of non-empty cells (bins) and
+// their number; the counts are cleared for the next scatter.
+__global__ __launch_bounds__(1024) void k_bin_scan(GridDev g) {
+    __shared__ int wsum[16][2];
+    const int64_t n = g.ncells;
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    const int64_t per = (n + 1023) / 1024;
+    const int64_t c0 = t * per < n ? t * per : n;
+    const int64_t c1 = c0 + per < n ? c0 + per : n;
+    int cnt = 0, nb = 0;
+    for (int64_t c = c0; c < c1; ++c) {
+        const int k = g.pcount[c];
+        cnt += k;
+        nb += k > 0;
+    }
+    const int ic = wave_incl_scan(cnt), inb = wave_incl_scan(nb);
+    if (lane == 63) {
+        wsum[wid][0] = ic;
+        wsum[wid][1] = inb;
+    }
+    __syncthreads();
+    int bc = 0, bn = 0;
+    for (int w = 0; w < wid; ++w) {
+        bc += wsum[w][0];
+        bn += wsum[w][1];
+    }
+    int pos = bc + ic - cnt, bpos = bn + inb - nb;
+    for (int64_t c = c0; c < c1; ++c) {
+        const int k = g.pcount[c];
+        g.poff[c] = pos;
+        if (k > 0) g.pbins[bpos++] = make_int4((int32_t)c, pos, k, 0);
+        pos += k;
+        g.pcount[c] = 0;
+    }
+    if (t == 1023) g.hdr[HDR_NBINS] = bn + inb;
+}
+
+// Particle records grouped by cell: record poff[cell] + rank holds the
+// particle's x, v and m (read in index order, written as two float4), so a
+// bin's particles are read contiguously by the tile kernel.
+__global__ __launch_bounds__(256) void k_bin_place(PartProg pp) {
+    const GridDev &g = pp.gdst;
+    const int64_t np = pp.np;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
+        const int2 kr = g.pkr[p];
+        if (kr.x < 0) continue;
+        const int64_t pos = (int64_t)g.poff[kr.x] + kr.y;
+        g.pstage[2 * pos] = make_float4(pp.x[p], pp.x[np + p], pp.x[2 * np + p], pp.v[p]);
+        g.pstage[2 * pos + 1] = make_float4(pp.v[np + p], pp.v[2 * np + p], pp.m[p], 0.f);
+    }
+}
+
+// One workgroup per bin (root cell c): every node a particle of the bin
+// touches lies in [8c - 1, 8c + 8] per axis, a 10^3 tile held in LDS for m
+// and the three mv channels.  Particles add into the tile with LDS atomics
+// (same per-contribution arithmetic as the direct scatter); the touched
+// blocks among the 27 around c are activated (or were, per node, when
+// ACT == AT_ACT_PER_NODE) and the tile's non-zero values are added to the
+// grid with one global atomic per node and channel.
+constexpr int kTile = 10, kTile3 = 1000;
+
+template <int KD, int ACT>
+__global__ __launch_bounds__(256) void k_p2g_bins(PartProg pp) {
+    __shared__ float tile[4][kTile3];
+    __shared__ int32_t tslot[27];
+    __shared__ int32_t tflag[27];
+    const GridDev &g = pp.gdst;
+    const int N = g.R * kBS;
+    const int nbins = g.hdr[HDR_NBINS];
+    float *const M = chan(g, pp.ch_m), *const MV0 = chan(g, pp.ch_mv), *const MV1 = chan(g, pp.ch_mv + 1),
+                 *const MV2 = chan(g, pp.ch_mv + 2);
+    for (int b = blockIdx.x; b < nbins; b += gridDim.x) {
+        const int4 bin = g.pbins[b];
+        int ci, cj, ck;
+        cell_coords(g, bin.x, ci, cj, ck);
+        const int oi = ci * kBS - 1, oj = cj * kBS - 1, ok = ck * kBS - 1;
+        for (int q = threadIdx.x; q < 4 * kTile3; q += blockDim.x) (&tile[0][0])[q] = 0.f;
+        if (threadIdx.x < 27) tflag[threadIdx.x] = 0;
+        __syncthreads();
+        for (int q = threadIdx.x; q < bin.z; q += blockDim.x) {
+            const float4 ra = g.pstage[2 * ((int64_t)bin.y + q)], rb = g.pstage[2 * ((int64_t)bin.y + q) + 1];
+            const float x[3] = {ra.x, ra.y, ra.z};
+            const float v[3] = {ra.w, rb.x, rb.y};
+            const float mp = rb.z;
+            float w[3][3];
+            int base[3];
+            for (int c = 0; c < 3; ++c) base[c] = bspline(x[c] * pp.inv_dx_dst, w[c]);
+            for (int a = 0; a < 3; ++a) {
+                const int i = base[0] + a;
+                for (int bb = 0; bb < 3; ++bb) {
+                    const int j = base[1] + bb;
+                    const float wab = w[0][a] * w[1][bb];
+                    for (int d = 0; d < 3; ++d) {
+                        const int k = base[2] + d;
+                        if (i < 0 || j < 0 || k < 0 || i >= N || j >= N || k >= N) continue;
+                        if (ACT == AT_ACT_PER_NODE)
+                            activate_cell<KD>(g, ((int64_t)(i >> 3) * g.R + (j >> 3)) * g.R + (k >> 3));
+                        tflag[((i >> 3) - ci + 1) * 9 + ((j >> 3) - cj + 1) * 3 + ((k >> 3) - ck + 1)] = 1;
+                        const int n = ((i - oi) * kTile + (j - oj)) * kTile + (k - ok);
+                        const float wt = wab * w[2][d];
+                        const float tm = wt * mp;
+                        atomicAdd(&tile[0][n], tm);
+                        atomicAdd(&tile[1][n], tm * v[0]);
+                        atomicAdd(&tile[2][n], tm * v[1]);
+                        atomicAdd(&tile[3][n], tm * v[2]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 27) {
+            const int t = threadIdx.x;
+            int32_t sl = -1;
+            if (tflag[t]) {
+                const int64_t cell = ((int64_t)(ci - 1 + t / 9) * g.R + (cj - 1 + (t / 3) % 3)) * g.R + (ck - 1 + t % 3);
+                sl = activate_cell<KD>(g, cell);   // already active under per-node activation
+            }
+            tslot[t] = sl;
+        }
+        __syncthreads();
+        for (int n = threadIdx.x; n < kTile3; n += blockDim.x) {
+            const int i = oi + n / 100, j = oj + (n / 10) % 10, k = ok + n % 10;
+            if (i < 0 || j < 0 || k < 0 || i >= N || j >= N || k >= N) continue;
+            const int32_t sl = tslot[((i >> 3) - ci + 1) * 9 + ((j >> 3) - cj + 1) * 3 + ((k >> 3) - ck + 1)];
+            if (sl < 0) continue;
+            const int64_t o = (int64_t)sl * kBV + (i & 7) * 64 + (j & 7) * 8 + (k & 7);
+            const float m = tile[0][n], a0 = tile[1][n], a1 = tile[2][n], a2 = tile[3][n];
+            if (m != 0.f) unsafeAtomicAdd(M + o, m);
+            if (a0 != 0.f) unsafeAtomicAdd(MV0 + o, a0);
+            if (a1 != 0.f) unsafeAtomicAdd(MV1 + o, a1);
+            if (a2 != 0.f) unsafeAtomicAdd(MV2 + o, a2);
+        }
+        __syncthreads();
     }
 }
 
@@ -1330,28 +1532,51 @@ hipError_t launch_micro(const GridDev &g, const MicroProg &prog, hipStream_t s) 
 }
 
 template <int KS, int KD, uint32_t STEPS>
-static void launch_part_a(const PartProg &pp, dim3 grid, hipStream_t s) {
+static void launch_part_a(const PartProg &pp, dim3 grid, bool bin, hipStream_t s) {
+    constexpr bool P2G = (STEPS & PS_P2G) != 0;
+    if (P2G && bin) {
+        // cell keys (with the gather and advection), ranks, scan, place, scatter per bin
+        if (pp.act_mode == AT_ACT_PER_BLOCK)
+            hipLaunchKernelGGL((k_particles<KS, KD, STEPS, AT_ACT_PER_BLOCK, P2G>), grid, dim3(256), 0, s, pp);
+        else
+            hipLaunchKernelGGL((k_particles<KS, KD, STEPS, AT_ACT_PER_NODE, P2G>), grid, dim3(256), 0, s, pp);
+        if (pp.gdst.ncells <= kHistCells)
+            hipLaunchKernelGGL(k_bin_rank<true>, dim3(256), dim3(1024), 0, s, pp.gdst, pp.np);
+        else
+            hipLaunchKernelGGL(k_bin_rank<false>, dim3(1024), dim3(1024), 0, s, pp.gdst, pp.np);
+        hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, pp.gdst);
+        hipLaunchKernelGGL(k_bin_place, grid, dim3(256), 0, s, pp);
+        const int64_t nb = pp.gdst.ncells < 256 * 8 ? pp.gdst.ncells : 256 * 8;
+        if (pp.act_mode == AT_ACT_PER_BLOCK)
+            hipLaunchKernelGGL((k_p2g_bins<KD, AT_ACT_PER_BLOCK>), dim3((unsigned)nb), dim3(256), 0, s, pp);
+        else
+            hipLaunchKernelGGL((k_p2g_bins<KD, AT_ACT_PER_NODE>), dim3((unsigned)nb), dim3(256), 0, s, pp);
+        return;
+    }
     if (pp.act_mode == AT_ACT_PER_BLOCK)
-        hipLaunchKernelGGL((k_particles<KS, KD, STEPS, AT_ACT_PER_BLOCK>), grid, dim3(256), 0, s, pp);
+        hipLaunchKernelGGL((k_particles<KS, KD, STEPS, AT_ACT_PER_BLOCK, false>), grid, dim3(256), 0, s, pp);
     else
-        hipLaunchKernelGGL((k_particles<KS, KD, STEPS, AT_ACT_PER_NODE>), grid, dim3(256), 0, s, pp);
+        hipLaunchKernelGGL((k_particles<KS, KD, STEPS, AT_ACT_PER_NODE, false>), grid, dim3(256), 0, s, pp);
 }
 
 template <int KS, int KD>
-static bool launch_part_s(const PartProg &pp, dim3 grid, hipStream_t s) {
+static bool launch_part_s(const PartProg &pp, dim3 grid, bool bin, hipStream_t s) {
     switch (pp.steps) {
-    case PS_G2P: launch_part_a<KS, KD, PS_G2P>(pp, grid, s); return true;
-    case PS_ADVECT: launch_part_a<KS, KD, PS_ADVECT>(pp, grid, s); return true;
-    case PS_P2G: launch_part_a<KS, KD, PS_P2G>(pp, grid, s); return true;
-    case PS_G2P | PS_ADVECT: launch_part_a<KS, KD, PS_G2P | PS_ADVECT>(pp, grid, s); return true;
-    case PS_ADVECT | PS_P2G: launch_part_a<KS, KD, PS_ADVECT | PS_P2G>(pp, grid, s); return true;
-    case PS_G2P | PS_P2G: launch_part_a<KS, KD, PS_G2P | PS_P2G>(pp, grid, s); return true;
-    case PS_G2P | PS_ADVECT | PS_P2G: launch_part_a<KS, KD, PS_G2P | PS_ADVECT | PS_P2G>(pp, grid, s); return true;
+    case PS_G2P: launch_part_a<KS, KD, PS_G2P>(pp, grid, bin, s); return true;
+    case PS_ADVECT: launch_part_a<KS, KD, PS_ADVECT>(pp, grid, bin, s); return true;
+    case PS_P2G: launch_part_a<KS, KD, PS_P2G>(pp, grid, bin, s); return true;
+    case PS_G2P | PS_ADVECT: launch_part_a<KS, KD, PS_G2P | PS_ADVECT>(pp, grid, bin, s); return true;
+    case PS_ADVECT | PS_P2G: launch_part_a<KS, KD, PS_ADVECT | PS_P2G>(pp, grid, bin, s); return true;
+    case PS_G2P | PS_P2G: launch_part_a<KS, KD, PS_G2P | PS_P2G>(pp, grid, bin, s); return true;
+    case PS_G2P | PS_ADVECT | PS_P2G: launch_part_a<KS, KD, PS_G2P | PS_ADVECT | PS_P2G>(pp, grid, bin, s); return true;
     default: return false;
     }
 }
 
-hipError_t launch_particles(const PartProg &pp, hipStream_t s) {
+hipError_t launch_particles(const PartProg &pp, hipStream_t s, int *dispatches) {
+    // the scatter is binned when the destination grid has room for every particle
+    const bool bin = (pp.steps & PS_P2G) && pp.gdst.pcap >= pp.np;
+    *dispatches = bin ? 5 : 1;
     int64_t blocks = (pp.np + 255) / 256;
     if (blocks < 1) blocks = 1;
     if (blocks > 256 * 64) blocks = 256 * 64;
@@ -1361,10 +1586,10 @@ hipError_t launch_particles(const PartProg &pp, hipStream_t s) {
     const int ks = (pp.steps & PS_G2P) ? pp.gsrc.kind : pp.gdst.kind;
     const int kd = (pp.steps & PS_P2G) ? pp.gdst.kind : ks;
     bool ok;
-    if (ks == AT_ROOT_BITMASK && kd == AT_ROOT_BITMASK) ok = launch_part_s<AT_ROOT_BITMASK, AT_ROOT_BITMASK>(pp, grid, s);
-    else if (ks == AT_ROOT_BITMASK) ok = launch_part_s<AT_ROOT_BITMASK, AT_ROOT_POINTER>(pp, grid, s);
-    else if (kd == AT_ROOT_BITMASK) ok = launch_part_s<AT_ROOT_POINTER, AT_ROOT_BITMASK>(pp, grid, s);
-    else ok = launch_part_s<AT_ROOT_POINTER, AT_ROOT_POINTER>(pp, grid, s);
+    if (ks == AT_ROOT_BITMASK && kd == AT_ROOT_BITMASK) ok = launch_part_s<AT_ROOT_BITMASK, AT_ROOT_BITMASK>(pp, grid, bin, s);
+    else if (ks == AT_ROOT_BITMASK) ok = launch_part_s<AT_ROOT_BITMASK, AT_ROOT_POINTER>(pp, grid, bin, s);
+    else if (kd == AT_ROOT_BITMASK) ok = launch_part_s<AT_ROOT_POINTER, AT_ROOT_BITMASK>(pp, grid, bin, s);
+    else ok = launch_part_s<AT_ROOT_POINTER, AT_ROOT_POINTER>(pp, grid, bin, s);
     if (!ok) return hipErrorInvalidValue;
     return hipGetLastError();
 }
@@ -1394,6 +1619,7 @@ hipError_t launch_batch_jacobi(const BatchDev &d, int iters, int workgroups, hip
     wgs = ((wgs + 7) / 8) * 8;
     if (wgs > d.pool) wgs = ((d.pool + 7) / 8) * 8;
     if (wgs < 8) wgs = 8;
+    hipLaunchKernelGGL(k_batch_records, dim3(1024), dim3(256), 0, s, d);
     for (int it = 0; it < iters; ++it) {
         hipLaunchKernelGGL(k_batch<false>, dim3(wgs), dim3(64), 0, s, d, it);
         hipLaunchKernelGGL(k_batch<true>, dim3(wgs), dim3(64), 0, s, d, it);

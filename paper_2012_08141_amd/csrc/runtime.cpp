@@ -71,7 +71,8 @@ Engine &E() {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t hdr, scan, bits, ptr, list, chan, total;
+    size_t hdr, scan, bits, ptr, list, pcount, poff, pbins, pkr, pstage, chan, total;
+    int64_t pcap;
     int64_t ncells;
     int32_t cap, list_cap, R;
 };
@@ -101,6 +102,14 @@ at_status layout_of(const at_grid_desc *d, Layout &L) {
     L.bits = off; off += align256(((L.ncells + 31) / 32) * 4);
     L.ptr = off; if (d->root_kind == AT_ROOT_POINTER) off += align256(L.ncells * 4);
     L.list = off; off += align256((size_t)L.list_cap * kRec * sizeof(int32_t));
+    if (d->particle_capacity < 0) return fail(AT_E_INVALID, "particle_capacity must be >= 0");
+    L.pcap = d->particle_capacity;
+    const size_t nc = (size_t)L.ncells;
+    L.pcount = off; if (L.pcap) off += align256(nc * sizeof(int32_t));
+    L.poff = off;   if (L.pcap) off += align256(nc * sizeof(int32_t));
+    L.pbins = off;  if (L.pcap) off += align256(nc * 4 * sizeof(int32_t));
+    L.pkr = off;    if (L.pcap) off += align256((size_t)L.pcap * 2 * sizeof(int32_t));
+    L.pstage = off; if (L.pcap) off += align256((size_t)L.pcap * 8 * sizeof(float));
     L.chan = off; off += (size_t)d->channels * L.cap * kBV * sizeof(float);
     L.total = off;
     return AT_OK;
@@ -188,8 +197,11 @@ at_status execute_node(const Node &nd, const at_task *tasks, bool table, hipStre
             }
         }
         if (pp.np == 0) return AT_OK;
-        e = launch_particles(pp, s);
-        break;
+        int ndisp = 1;
+        e = launch_particles(pp, s, &ndisp);
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        E().dispatches.fetch_add(ndisp);
+        return AT_OK;
     }
     default:
         return fail(AT_E_INVALID, "cannot execute task kind %d", t0.kind);
@@ -349,6 +361,12 @@ at_status at_grid_create(const at_grid_desc *desc, void *dev_buf, size_t bytes, 
         d.bits = (uint32_t *)(b + L.bits);
         d.ptr = desc->root_kind == AT_ROOT_POINTER ? (int32_t *)(b + L.ptr) : nullptr;
         d.list = (int32_t *)(b + L.list);
+        d.pcap = L.pcap;
+        d.pcount = L.pcap ? (int32_t *)(b + L.pcount) : nullptr;
+        d.poff = L.pcap ? (int32_t *)(b + L.poff) : nullptr;
+        d.pbins = L.pcap ? (int4 *)(b + L.pbins) : nullptr;
+        d.pkr = L.pcap ? (int2 *)(b + L.pkr) : nullptr;
+        d.pstage = L.pcap ? (float4 *)(b + L.pstage) : nullptr;
         d.chan = (float *)(b + L.chan);
         hipError_t e = hipMemsetAsync(dev_buf, 0, L.total, stream);
         if (e == hipSuccess && d.ptr) e = hipMemsetAsync(d.ptr, 0xff, (size_t)L.ncells * 4, stream);
@@ -420,8 +438,9 @@ at_status at_grid_clear(at_grid grid, hipStream_t stream) {
     if (e == hipSuccess) e = hipMemsetAsync(d.bits, 0, ((d.ncells + 31) / 32) * 4, stream);
     if (e == hipSuccess && d.ptr) e = hipMemsetAsync(d.ptr, 0xff, (size_t)d.ncells * 4, stream);
     if (e == hipSuccess) e = hipMemsetAsync(d.chan, 0, (size_t)grid->desc.channels * d.ch_stride * sizeof(float), stream);
+    if (e == hipSuccess && d.pcount) e = hipMemsetAsync(d.pcount, 0, (size_t)d.ncells * sizeof(int32_t), stream);
     if (e != hipSuccess) return hip_fail(e, "grid clear");
-    en.dispatches.fetch_add(d.ptr ? 4 : 3);
+    en.dispatches.fetch_add((d.ptr ? 4 : 3) + (d.pcount ? 1 : 0));
     en.persist.deactivate_grid(grid->uid);
     for (int c = 0; c < grid->desc.channels; ++c) bump(grid->uid, ST_VALUE, c);
     bump(grid->uid, ST_ALLOC, -1);
@@ -747,7 +766,7 @@ struct at_batch_s {
 
 namespace {
 struct BatchLayout {
-    size_t clock, count, window, roots, work, x, xn, b, total;
+    size_t clock, count, window, roots, work, rec, x, xn, b, total;
 };
 at_status batch_layout(const at_batch_desc *d, BatchLayout &L, int32_t &R) {
     if (!d) return fail(AT_E_INVALID, "null batch description");
@@ -764,6 +783,7 @@ at_status batch_layout(const at_batch_desc *d, BatchLayout &L, int32_t &R) {
     L.window = off; off += align256((size_t)d->max_grids * 2 * sizeof(int64_t));
     L.roots = off; off += align256((size_t)d->max_grids * nc * sizeof(int32_t));
     L.work = off; off += align256((size_t)d->pool_blocks * sizeof(int32_t));
+    L.rec = off; off += align256((size_t)d->pool_blocks * 8 * sizeof(int32_t));
     L.x = off; off += (size_t)d->pool_blocks * kBV * sizeof(float);
     L.xn = off; off += (size_t)d->pool_blocks * kBV * sizeof(float);
     L.b = off; off += (size_t)d->pool_blocks * kBV * sizeof(float);
@@ -806,6 +826,7 @@ at_status at_batch_create(const at_batch_desc *desc, void *dev_buf, size_t bytes
     d.window = (int64_t *)(b + L.window);
     d.roots = (int32_t *)(b + L.roots);
     d.work = (int32_t *)(b + L.work);
+    d.rec = (int4 *)(b + L.rec);
     d.x = (float *)(b + L.x);
     d.xn = (float *)(b + L.xn);
     d.b = (float *)(b + L.b);
@@ -846,7 +867,7 @@ at_status at_batch_jacobi(at_batch batch, int32_t iters, int32_t workgroups, hip
     if (iters == 0) return AT_OK;
     hipError_t e = launch_batch_jacobi(batch->dev, iters, workgroups, stream);
     if (e != hipSuccess) return hip_fail(e, "batched jacobi launch");
-    E().dispatches.fetch_add(2 * (int64_t)iters + 1);
+    E().dispatches.fetch_add(2 * (int64_t)iters + 2);
     return AT_OK;
 }
 

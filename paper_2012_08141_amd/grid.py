@@ -24,8 +24,9 @@ def current_stream():
 _KINDS = {"bitmask": L.AT_ROOT_BITMASK, "pointer": L.AT_ROOT_POINTER}
 
 
-def footprint(n: int, channels: int, root_kind: str = "bitmask", capacity_blocks: int = 0) -> int:
-    d = L.AtGridDesc((n, n, n), _KINDS[root_kind], channels, capacity_blocks)
+def footprint(n: int, channels: int, root_kind: str = "bitmask", capacity_blocks: int = 0,
+              particle_capacity: int = 0) -> int:
+    d = L.AtGridDesc((n, n, n), _KINDS[root_kind], channels, capacity_blocks, particle_capacity)
     b = ctypes.c_size_t()
     L.check(L.lib().at_grid_footprint(ctypes.byref(d), ctypes.byref(b)))
     return int(b.value)
@@ -35,15 +36,17 @@ class SparseGrid:
     """An ``n^3`` sparse grid with ``channels`` fp32 channels.
 
     ``device=None`` makes a planning handle (no device memory): it can be
-    used in task sequences for planning only."""
+    used in task sequences for planning only.  ``particle_capacity`` sizes
+    the workspace that lets a particle scatter into this grid bin up to that
+    many particles (0: scatters add straight into global memory)."""
 
     def __init__(self, n: int, channels: int, root_kind: str = "bitmask", capacity_blocks: int = 0,
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, particle_capacity: int = 0):
         self.n, self.channels, self.root_kind = n, channels, root_kind
         self.R = n // 8
         self._lib = L.lib()
-        desc = L.AtGridDesc((n, n, n), _KINDS[root_kind], channels, capacity_blocks)
-        self.bytes = footprint(n, channels, root_kind, capacity_blocks)
+        desc = L.AtGridDesc((n, n, n), _KINDS[root_kind], channels, capacity_blocks, particle_capacity)
+        self.bytes = footprint(n, channels, root_kind, capacity_blocks, particle_capacity)
         self.buf = None
         h = ctypes.c_void_p()
         if device is None:

@@ -33,11 +33,11 @@ def test_struct_layouts():
     # at_task: 4 int32, 2 pointers, 8 int32, 4 float, 4 pointers, int64
     assert ctypes.sizeof(L.AtTask) == 16 + 16 + 32 + 16 + 32 + 8
     assert ctypes.sizeof(L.AtStats) == 8 * 9
-    assert ctypes.sizeof(L.AtGridDesc) == 24
+    assert ctypes.sizeof(L.AtGridDesc) == 28
 
 
 def _desc(n, kind=L.AT_ROOT_BITMASK, ch=2, cap=0):
-    return L.AtGridDesc((n, n, n), kind, ch, cap)
+    return L.AtGridDesc((n, n, n), kind, ch, cap, 0)
 
 
 def test_footprint_layout_and_validation():
@@ -54,8 +54,15 @@ def test_footprint_layout_and_validation():
                 _desc(64, L.AT_ROOT_POINTER, 1, 0), _desc(64, L.AT_ROOT_POINTER, 1, 513)):
         assert lib.at_grid_footprint(ctypes.byref(bad), ctypes.byref(b)) == L.AT_E_INVALID
         assert lib.at_last_error()
-    nc = L.AtGridDesc((64, 64, 32), 0, 1, 0)
+    nc = L.AtGridDesc((64, 64, 32), 0, 1, 0, 0)
     assert lib.at_grid_footprint(ctypes.byref(nc), ctypes.byref(b)) == L.AT_E_UNSUPPORTED
+    # particle binning workspace: 3 cell arrays (count, first, bins of 16 B) + 40 B per particle
+    d = L.AtGridDesc((64, 64, 64), L.AT_ROOT_POINTER, 3, 100, 1000)
+    assert lib.at_grid_footprint(ctypes.byref(d), ctypes.byref(b)) == L.AT_OK
+    assert b.value == (256 + 8192 + 256 + 2048 + 3328 + 2048 + 2048 + 8192 + 8192 + 32000
+                       + 3 * 100 * 2048)
+    d = L.AtGridDesc((64, 64, 64), L.AT_ROOT_POINTER, 3, 100, -1)
+    assert lib.at_grid_footprint(ctypes.byref(d), ctypes.byref(b)) == L.AT_E_INVALID
 
 
 def test_planning_handle_rejects_device_calls():
