@@ -1238,21 +1238,31 @@ __global__ __launch_bounds__(256) void k_bin_place(PartProg pp) {
 
 // One workgroup per bin (root cell c): every node a particle of the bin
 // touches lies in [8c - 1, 8c + 8] per axis, a 10^3 tile held in LDS for m
-// and the three mv channels.  Particles add into the tile with LDS atomics
-// (same per-contribution arithmetic as the direct scatter); the touched
-// blocks among the 27 around c are activated (or were, per node, when
-// ACT == AT_ACT_PER_NODE) and the tile's non-zero values are added to the
-// grid with one global atomic per node and channel.
-constexpr int kTile = 10, kTile3 = 1000;
+// and the three mv channels.  LDS float atomics are slow on this hardware,
+// so the bin's particles (in chunks of kChunk) are first counting-sorted by
+// centre node (512 per block, integer LDS atomics); each thread then walks
+// a contiguous run of the sorted particles and sums, in registers, the
+// contributions to the 27 nodes its current centre node reaches (same
+// per-contribution arithmetic as the direct scatter), adding them to the
+// tile only when the centre node changes.  The touched blocks among the 27
+// around c are activated (or were, per node, when ACT == AT_ACT_PER_NODE)
+// and the tile's non-zero values are added to the grid with one global
+// atomic per node and channel.
+constexpr int kTile = 10, kTile3 = 1000, kChunk = 4096;
 
 template <int KD, int ACT>
 __global__ __launch_bounds__(256) void k_p2g_bins(PartProg pp) {
     __shared__ float tile[4][kTile3];
     __shared__ int32_t tslot[27];
     __shared__ int32_t tflag[27];
+    __shared__ int32_t ncnt[512];        // particles per centre node, then first sorted position
+    __shared__ int32_t wsum[4];
+    __shared__ uint16_t order[kChunk];   // chunk-relative particle index, sorted by centre node
+    __shared__ int32_t lrank[kChunk];    // centre node << 16 | rank among the chunk's particles there
     const GridDev &g = pp.gdst;
     const int N = g.R * kBS;
     const int nbins = g.hdr[HDR_NBINS];
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     float *const M = chan(g, pp.ch_m), *const MV0 = chan(g, pp.ch_mv), *const MV1 = chan(g, pp.ch_mv + 1),
                  *const MV2 = chan(g, pp.ch_mv + 2);
     for (int b = blockIdx.x; b < nbins; b += gridDim.x) {
@@ -1260,42 +1270,103 @@ __global__ __launch_bounds__(256) void k_p2g_bins(PartProg pp) {
         int ci, cj, ck;
         cell_coords(g, bin.x, ci, cj, ck);
         const int oi = ci * kBS - 1, oj = cj * kBS - 1, ok = ck * kBS - 1;
-        for (int q = threadIdx.x; q < 4 * kTile3; q += blockDim.x) (&tile[0][0])[q] = 0.f;
-        if (threadIdx.x < 27) tflag[threadIdx.x] = 0;
-        __syncthreads();
-        for (int q = threadIdx.x; q < bin.z; q += blockDim.x) {
-            const float4 ra = g.pstage[2 * ((int64_t)bin.y + q)], rb = g.pstage[2 * ((int64_t)bin.y + q) + 1];
-            const float x[3] = {ra.x, ra.y, ra.z};
-            const float v[3] = {ra.w, rb.x, rb.y};
-            const float mp = rb.z;
-            float w[3][3];
-            int base[3];
-            for (int c = 0; c < 3; ++c) base[c] = bspline(x[c] * pp.inv_dx_dst, w[c]);
-            for (int a = 0; a < 3; ++a) {
-                const int i = base[0] + a;
-                for (int bb = 0; bb < 3; ++bb) {
-                    const int j = base[1] + bb;
-                    const float wab = w[0][a] * w[1][bb];
-                    for (int d = 0; d < 3; ++d) {
-                        const int k = base[2] + d;
-                        if (i < 0 || j < 0 || k < 0 || i >= N || j >= N || k >= N) continue;
-                        if (ACT == AT_ACT_PER_NODE)
-                            activate_cell<KD>(g, ((int64_t)(i >> 3) * g.R + (j >> 3)) * g.R + (k >> 3));
-                        tflag[((i >> 3) - ci + 1) * 9 + ((j >> 3) - cj + 1) * 3 + ((k >> 3) - ck + 1)] = 1;
-                        const int n = ((i - oi) * kTile + (j - oj)) * kTile + (k - ok);
-                        const float wt = wab * w[2][d];
-                        const float tm = wt * mp;
-                        atomicAdd(&tile[0][n], tm);
-                        atomicAdd(&tile[1][n], tm * v[0]);
-                        atomicAdd(&tile[2][n], tm * v[1]);
-                        atomicAdd(&tile[3][n], tm * v[2]);
+        for (int q = t; q < 4 * kTile3; q += blockDim.x) (&tile[0][0])[q] = 0.f;
+        if (t < 27) tflag[t] = 0;
+        for (int c0 = 0; c0 < bin.z; c0 += kChunk) {
+            const int n = bin.z - c0 < kChunk ? bin.z - c0 : kChunk;
+            const float4 *const rec = g.pstage + 2 * ((int64_t)bin.y + c0);
+            for (int q = t; q < 512; q += blockDim.x) ncnt[q] = 0;
+            __syncthreads();
+            // centre node (base + 1 per axis, inside block c) of each particle
+            for (int q = t; q < n; q += blockDim.x) {
+                const float4 ra = rec[2 * q];
+                const int hi = (int)floorf(ra.x * pp.inv_dx_dst - 0.5f) + 1 - ci * kBS;
+                const int hj = (int)floorf(ra.y * pp.inv_dx_dst - 0.5f) + 1 - cj * kBS;
+                const int hk = (int)floorf(ra.z * pp.inv_dx_dst - 0.5f) + 1 - ck * kBS;
+                const int node = (hi * kBS + hj) * kBS + hk;
+                lrank[q] = (node << 16) | atomicAdd(&ncnt[node], 1);
+            }
+            __syncthreads();
+            // exclusive scan of the 512 counts (two per thread)
+            const int a0 = ncnt[2 * t], a1 = ncnt[2 * t + 1];
+            const int incl = wave_incl_scan(a0 + a1);
+            if (lane == 63) wsum[wid] = incl;
+            __syncthreads();
+            int before = incl - a0 - a1;
+            for (int w = 0; w < wid; ++w) before += wsum[w];
+            ncnt[2 * t] = before;
+            ncnt[2 * t + 1] = before + a0;
+            __syncthreads();
+            for (int q = t; q < n; q += blockDim.x) {
+                const int lr = lrank[q];
+                order[ncnt[lr >> 16] + (lr & 0xffff)] = (uint16_t)q;
+            }
+            __syncthreads();
+            // a contiguous run of sorted particles per thread
+            const int k = (n + blockDim.x - 1) / blockDim.x;
+            const int p0 = t * k < n ? t * k : n;
+            const int p1 = p0 + k < n ? p0 + k : n;
+            float acc[27][4];
+            int cb[3] = {0, 0, 0};
+            bool open = false;
+            auto flush = [&]() {
+                for (int a = 0; a < 3; ++a)
+                    for (int bb = 0; bb < 3; ++bb)
+                        for (int d = 0; d < 3; ++d) {
+                            const int i = cb[0] + a, j = cb[1] + bb, kk = cb[2] + d;
+                            if (i < 0 || j < 0 || kk < 0 || i >= N || j >= N || kk >= N) continue;
+                            tflag[((i >> 3) - ci + 1) * 9 + ((j >> 3) - cj + 1) * 3 + ((kk >> 3) - ck + 1)] = 1;
+                            const int nn = ((i - oi) * kTile + (j - oj)) * kTile + (kk - ok);
+                            const float *s4 = acc[(a * 3 + bb) * 3 + d];
+                            atomicAdd(&tile[0][nn], s4[0]);
+                            atomicAdd(&tile[1][nn], s4[1]);
+                            atomicAdd(&tile[2][nn], s4[2]);
+                            atomicAdd(&tile[3][nn], s4[3]);
+                        }
+            };
+            for (int pos = p0; pos < p1; ++pos) {
+                const int q = order[pos];
+                const float4 ra = rec[2 * q], rb = rec[2 * q + 1];
+                const float x[3] = {ra.x, ra.y, ra.z};
+                const float v[3] = {ra.w, rb.x, rb.y};
+                const float mp = rb.z;
+                float w[3][3];
+                int base[3];
+                for (int c = 0; c < 3; ++c) base[c] = bspline(x[c] * pp.inv_dx_dst, w[c]);
+                if (!open || base[0] != cb[0] || base[1] != cb[1] || base[2] != cb[2]) {
+                    if (open) flush();
+#pragma unroll
+                    for (int e = 0; e < 27; ++e) acc[e][0] = acc[e][1] = acc[e][2] = acc[e][3] = 0.f;
+                    cb[0] = base[0]; cb[1] = base[1]; cb[2] = base[2];
+                    open = true;
+                }
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+#pragma unroll
+                    for (int bb = 0; bb < 3; ++bb) {
+                        const float wab = w[0][a] * w[1][bb];
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            if (ACT == AT_ACT_PER_NODE) {
+                                const int i = base[0] + a, j = base[1] + bb, kk = base[2] + d;
+                                if (i >= 0 && j >= 0 && kk >= 0 && i < N && j < N && kk < N)
+                                    activate_cell<KD>(g, ((int64_t)(i >> 3) * g.R + (j >> 3)) * g.R + (kk >> 3));
+                            }
+                            const float wt = wab * w[2][d];
+                            const float tm = wt * mp;
+                            float *s4 = acc[(a * 3 + bb) * 3 + d];
+                            s4[0] = s4[0] + tm;
+                            s4[1] = s4[1] + tm * v[0];
+                            s4[2] = s4[2] + tm * v[1];
+                            s4[3] = s4[3] + tm * v[2];
+                        }
                     }
                 }
             }
+            if (open) flush();
+            __syncthreads();
         }
-        __syncthreads();
-        if (threadIdx.x < 27) {
-            const int t = threadIdx.x;
+        if (t < 27) {
             int32_t sl = -1;
             if (tflag[t]) {
                 const int64_t cell = ((int64_t)(ci - 1 + t / 9) * g.R + (cj - 1 + (t / 3) % 3)) * g.R + (ck - 1 + t % 3);
@@ -1304,13 +1375,13 @@ __global__ __launch_bounds__(256) void k_p2g_bins(PartProg pp) {
             tslot[t] = sl;
         }
         __syncthreads();
-        for (int n = threadIdx.x; n < kTile3; n += blockDim.x) {
-            const int i = oi + n / 100, j = oj + (n / 10) % 10, k = ok + n % 10;
+        for (int nn = t; nn < kTile3; nn += blockDim.x) {
+            const int i = oi + nn / 100, j = oj + (nn / 10) % 10, k = ok + nn % 10;
             if (i < 0 || j < 0 || k < 0 || i >= N || j >= N || k >= N) continue;
             const int32_t sl = tslot[((i >> 3) - ci + 1) * 9 + ((j >> 3) - cj + 1) * 3 + ((k >> 3) - ck + 1)];
             if (sl < 0) continue;
             const int64_t o = (int64_t)sl * kBV + (i & 7) * 64 + (j & 7) * 8 + (k & 7);
-            const float m = tile[0][n], a0 = tile[1][n], a1 = tile[2][n], a2 = tile[3][n];
+            const float m = tile[0][nn], a0 = tile[1][nn], a1 = tile[2][nn], a2 = tile[3][nn];
             if (m != 0.f) unsafeAtomicAdd(M + o, m);
             if (a0 != 0.f) unsafeAtomicAdd(MV0 + o, a0);
             if (a1 != 0.f) unsafeAtomicAdd(MV1 + o, a1);
