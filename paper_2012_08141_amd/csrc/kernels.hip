@@ -1039,27 +1039,56 @@ __global__ __launch_bounds__(256) void k_particles(PartProg pp) {
             int base[3];
             for (int c = 0; c < 3; ++c) base[c] = bspline(x[c] * pp.inv_dx_src, w[c]);
             const float *V0 = chan(g, pp.ch_vsrc), *V1 = chan(g, pp.ch_vsrc + 1), *V2 = chan(g, pp.ch_vsrc + 2);
+            // slots of the (at most) 2x2x2 blocks the 27 nodes span, looked up once
+            const int blo[3] = {base[0] >> 3, base[1] >> 3, base[2] >> 3};
+            int32_t bs[2][2][2];
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b)
+                    for (int d = 0; d < 2; ++d) {
+                        const int ci = blo[0] + a, cj = blo[1] + b, ck = blo[2] + d;
+                        const bool in = ci >= 0 && cj >= 0 && ck >= 0 && ci < g.R && cj < g.R && ck < g.R;
+                        bs[a][b][d] = in ? slot_of<KS>(g, ((int64_t)ci * g.R + cj) * g.R + ck) : -1;
+                    }
+            // a row of 3 nodes along k inside one block is read as one 12-byte load per channel
+            const bool krow = (base[2] & 7) <= 5 && base[2] >= 0;
             float acc[3] = {0.f, 0.f, 0.f};
             for (int a = 0; a < 3; ++a) {
                 const int i = base[0] + a;
                 for (int b = 0; b < 3; ++b) {
                     const int j = base[1] + b;
                     const float wab = w[0][a] * w[1][b];
-                    for (int d = 0; d < 3; ++d) {
-                        const int k = base[2] + d;
-                        const float wt = wab * w[2][d];
-                        float n0 = 0.f, n1 = 0.f, n2 = 0.f;
-                        if (i >= 0 && j >= 0 && k >= 0 && i < N && j < N && k < N) {
-                            const int64_t cell = ((int64_t)(i >> 3) * g.R + (j >> 3)) * g.R + (k >> 3);
-                            const int32_t s = slot_of<KS>(g, cell);
-                            if (s >= 0) {
-                                const int64_t o = (int64_t)s * kBV + (i & 7) * 64 + (j & 7) * 8 + (k & 7);
-                                n0 = V0[o]; n1 = V1[o]; n2 = V2[o];
+                    const bool ij = i >= 0 && j >= 0 && i < N && j < N;
+                    float n[3][3];
+                    if (krow) {
+                        const int32_t s = ij ? bs[(i >> 3) - blo[0]][(j >> 3) - blo[1]][0] : -1;
+                        float3 r0 = make_float3(0.f, 0.f, 0.f), r1 = r0, r2 = r0;
+                        if (s >= 0) {
+                            const int64_t o = (int64_t)s * kBV + (i & 7) * 64 + (j & 7) * 8 + (base[2] & 7);
+                            r0 = *reinterpret_cast<const float3 *>(V0 + o);
+                            r1 = *reinterpret_cast<const float3 *>(V1 + o);
+                            r2 = *reinterpret_cast<const float3 *>(V2 + o);
+                        }
+                        n[0][0] = r0.x; n[1][0] = r0.y; n[2][0] = r0.z;
+                        n[0][1] = r1.x; n[1][1] = r1.y; n[2][1] = r1.z;
+                        n[0][2] = r2.x; n[1][2] = r2.y; n[2][2] = r2.z;
+                    } else {
+                        for (int d = 0; d < 3; ++d) {
+                            const int k = base[2] + d;
+                            n[d][0] = n[d][1] = n[d][2] = 0.f;
+                            if (ij && k >= 0 && k < N) {
+                                const int32_t s = bs[(i >> 3) - blo[0]][(j >> 3) - blo[1]][(k >> 3) - blo[2]];
+                                if (s >= 0) {
+                                    const int64_t o = (int64_t)s * kBV + (i & 7) * 64 + (j & 7) * 8 + (k & 7);
+                                    n[d][0] = V0[o]; n[d][1] = V1[o]; n[d][2] = V2[o];
+                                }
                             }
                         }
-                        acc[0] = acc[0] + wt * n0;
-                        acc[1] = acc[1] + wt * n1;
-                        acc[2] = acc[2] + wt * n2;
+                    }
+                    for (int d = 0; d < 3; ++d) {
+                        const float wt = wab * w[2][d];
+                        acc[0] = acc[0] + wt * n[d][0];
+                        acc[1] = acc[1] + wt * n[d][1];
+                        acc[2] = acc[2] + wt * n[d][2];
                     }
                 }
             }
