@@ -13,7 +13,7 @@ constexpr int kBS = 8;      // leaf block edge
 constexpr int kBV = 512;    // voxels per leaf block
 
 // Words of the per-grid device header (first 256 bytes of the grid buffer).
-enum : int { HDR_COUNT = 0, HDR_BUMP = 1, HDR_ERR = 2, HDR_SCRATCH = 3, HDR_NBINS = 4 };
+enum : int { HDR_COUNT = 0, HDR_BUMP = 1, HDR_ERR = 2, HDR_SCRATCH = 3, HDR_NBINS = 4, HDR_NAPPEND = 5 };
 enum : int32_t { ERR_CAPACITY = 1, ERR_SPIN = 2 };
 
 // Pointer-root cell states besides a valid slot (>= 0).
@@ -38,6 +38,7 @@ struct GridDev {
     int32_t *pcount;    // [R^3] particles per root cell (zero between scatters)
     int32_t *poff;      // [R^3] first position of each cell's particles in pstage
     int4 *pbins;        // [R^3] non-empty cells: {cell, first, count, 0}; count in hdr[HDR_NBINS]
+                        // (while ranking: cells appended in .x, count in hdr[HDR_NAPPEND])
     int2 *pkr;          // [pcap] per particle: {root cell of its centre node or -1, rank in that cell}
     float4 *pstage;     // [pcap][2] particle records {x0, x1, x2, v0}, {v1, v2, m, 0} grouped by cell
 };

@@ -1170,8 +1170,14 @@ __global__ __launch_bounds__(256) void k_particles(PartProg pp) {
 // counter.  With LDS (root cells <= kHistCells) each workgroup (one per CU)
 // counts a contiguous range of particles in an on-chip histogram first and
 // adds each cell's total to the global count once, taking its base from the
-// returned value.
+// returned value.  Whoever takes a cell's count from zero appends the cell to
+// the bin list, so the scan only visits non-empty cells.
 constexpr int kHistCells = 32768;
+
+__device__ __forceinline__ void append_bin(const GridDev &g, int32_t cell) {
+    const int i = atomicAdd(&g.hdr[HDR_NAPPEND], 1);
+    g.pbins[i].x = cell;
+}
 
 template <bool LDS>
 __global__ __launch_bounds__(1024) void k_bin_rank(GridDev g, int64_t np) {
@@ -1184,6 +1190,7 @@ __global__ __launch_bounds__(1024) void k_bin_rank(GridDev g, int64_t np) {
             int2 kr = g.pkr[p];
             if (kr.x < 0) continue;
             kr.y = atomicAdd(&g.pcount[kr.x], 1);
+            if (kr.y == 0) append_bin(g, kr.x);
             g.pkr[p] = kr;
         }
         return;
@@ -1201,7 +1208,10 @@ __global__ __launch_bounds__(1024) void k_bin_rank(GridDev g, int64_t np) {
     __syncthreads();
     for (int c = t; c < nc; c += blockDim.x) {
         const int k = h[c];
-        if (k) h[c] = atomicAdd(&g.pcount[c], k);
+        if (k) {
+            h[c] = atomicAdd(&g.pcount[c], k);
+            if (h[c] == 0) append_bin(g, c);
+        }
     }
     __syncthreads();
     for (int64_t p = p0 + t; p < p1; p += blockDim.x) {
@@ -1212,42 +1222,37 @@ __global__ __launch_bounds__(1024) void k_bin_rank(GridDev g, int64_t np) {
     }
 }
 
-// Exclusive scan of the per-cell particle counts in one workgroup: the first
-// position of each cell's particles, the list of non-empty cells (bins) and
-// their number; the counts are cleared for the next scatter.
+// Exclusive scan, in one workgroup, of the counts of the non-empty cells
+// (in the order they were appended): each bin's first position, the final
+// bin list {cell, first, count, 0} and its length; the counts and the append
+// counter are cleared for the next scatter.
 __global__ __launch_bounds__(1024) void k_bin_scan(GridDev g) {
-    __shared__ int wsum[16][2];
-    const int64_t n = g.ncells;
+    __shared__ int wsum[16];
+    const int n = g.hdr[HDR_NAPPEND];
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-    const int64_t per = (n + 1023) / 1024;
-    const int64_t c0 = t * per < n ? t * per : n;
-    const int64_t c1 = c0 + per < n ? c0 + per : n;
-    int cnt = 0, nb = 0;
-    for (int64_t c = c0; c < c1; ++c) {
-        const int k = g.pcount[c];
-        cnt += k;
-        nb += k > 0;
-    }
-    const int ic = wave_incl_scan(cnt), inb = wave_incl_scan(nb);
-    if (lane == 63) {
-        wsum[wid][0] = ic;
-        wsum[wid][1] = inb;
-    }
+    const int per = (n + 1023) / 1024;
+    const int i0 = t * per < n ? t * per : n;
+    const int i1 = i0 + per < n ? i0 + per : n;
+    int cnt = 0;
+    for (int i = i0; i < i1; ++i) cnt += g.pcount[g.pbins[i].x];
+    const int ic = wave_incl_scan(cnt);
+    if (lane == 63) wsum[wid] = ic;
     __syncthreads();
-    int bc = 0, bn = 0;
-    for (int w = 0; w < wid; ++w) {
-        bc += wsum[w][0];
-        bn += wsum[w][1];
-    }
-    int pos = bc + ic - cnt, bpos = bn + inb - nb;
-    for (int64_t c = c0; c < c1; ++c) {
+    int pos = ic - cnt;
+    for (int w = 0; w < wid; ++w) pos += wsum[w];
+    for (int i = i0; i < i1; ++i) {
+        const int32_t c = g.pbins[i].x;
         const int k = g.pcount[c];
         g.poff[c] = pos;
-        if (k > 0) g.pbins[bpos++] = make_int4((int32_t)c, pos, k, 0);
+        g.pbins[i] = make_int4(c, pos, k, 0);
         pos += k;
         g.pcount[c] = 0;
     }
-    if (t == 1023) g.hdr[HDR_NBINS] = bn + inb;
+    __syncthreads();
+    if (t == 0) {
+        g.hdr[HDR_NBINS] = n;
+        g.hdr[HDR_NAPPEND] = 0;
+    }
 }
 
 // Particle records grouped by cell: record poff[cell] + rank holds the

@@ -439,8 +439,9 @@ at_status at_grid_clear(at_grid grid, hipStream_t stream) {
     if (e == hipSuccess && d.ptr) e = hipMemsetAsync(d.ptr, 0xff, (size_t)d.ncells * 4, stream);
     if (e == hipSuccess) e = hipMemsetAsync(d.chan, 0, (size_t)grid->desc.channels * d.ch_stride * sizeof(float), stream);
     if (e == hipSuccess && d.pcount) e = hipMemsetAsync(d.pcount, 0, (size_t)d.ncells * sizeof(int32_t), stream);
+    if (e == hipSuccess && d.pcount) e = hipMemsetAsync(d.hdr + HDR_NBINS, 0, 2 * sizeof(int32_t), stream);
     if (e != hipSuccess) return hip_fail(e, "grid clear");
-    en.dispatches.fetch_add((d.ptr ? 4 : 3) + (d.pcount ? 1 : 0));
+    en.dispatches.fetch_add((d.ptr ? 4 : 3) + (d.pcount ? 2 : 0));
     en.persist.deactivate_grid(grid->uid);
     for (int c = 0; c < grid->desc.channels; ++c) bump(grid->uid, ST_VALUE, c);
     bump(grid->uid, ST_ALLOC, -1);
