@@ -1358,17 +1358,35 @@ __global__ __launch_bounds__(256) void k_p2g_bins(PartProg pp) {
                             atomicAdd(&tile[3][nn], s4[3]);
                         }
             };
-            for (int pos = p0; pos < p1; ++pos) {
-                const int q = order[pos];
-                const float4 ra = rec[2 * q], rb = rec[2 * q + 1];
+            // the next particle's record is loaded while the current one is summed;
+            // one extra pass (pos == p1) flushes the last run
+            const int qlast = p1 > p0 ? p1 - 1 : p0;
+            float4 na = make_float4(0.f, 0.f, 0.f, 0.f), nb = na;
+            if (p0 < p1) {
+                const int q = order[p0];
+                na = rec[2 * q];
+                nb = rec[2 * q + 1];
+            }
+            for (int pos = p0; pos <= p1; ++pos) {
+                const float4 ra = na, rb = nb;
+                if (pos < p1) {
+                    const int q = order[pos + 1 < p1 ? pos + 1 : qlast];
+                    na = rec[2 * q];
+                    nb = rec[2 * q + 1];
+                }
                 const float x[3] = {ra.x, ra.y, ra.z};
                 const float v[3] = {ra.w, rb.x, rb.y};
                 const float mp = rb.z;
                 float w[3][3];
                 int base[3];
                 for (int c = 0; c < 3; ++c) base[c] = bspline(x[c] * pp.inv_dx_dst, w[c]);
-                if (!open || base[0] != cb[0] || base[1] != cb[1] || base[2] != cb[2]) {
-                    if (open) flush();
+                const bool last = pos == p1;
+                if (open && (last || base[0] != cb[0] || base[1] != cb[1] || base[2] != cb[2])) {
+                    flush();
+                    open = false;
+                }
+                if (last) break;
+                if (!open) {
 #pragma unroll
                     for (int e = 0; e < 27; ++e) acc[e][0] = acc[e][1] = acc[e][2] = acc[e][3] = 0.f;
                     cb[0] = base[0]; cb[1] = base[1]; cb[2] = base[2];
@@ -1397,7 +1415,6 @@ __global__ __launch_bounds__(256) void k_p2g_bins(PartProg pp) {
                     }
                 }
             }
-            if (open) flush();
             __syncthreads();
         }
         if (t < 27) {
