@@ -331,7 +331,7 @@ def main():
                          "scales rocprofv3 FETCH_SIZE / WRITE_SIZE readings)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(the sharding design is documented, not implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     # warm-up windows have the timed window's shape, so the timed window

@@ -49,7 +49,7 @@ typedef int32_t at_status;
 #define AT_E_INVALID     -1   /* bad argument; nothing was enqueued */
 #define AT_E_CAPACITY    -2   /* a grid's block pool ran out (sticky, see at_device_status) */
 #define AT_E_HIP         -3   /* a HIP call failed; at_last_error() has its text */
-#define AT_E_UNSUPPORTED -4   /* valid request this build does not implement */
+#define AT_E_UNSUPPORTED -4   /* valid request the library does not implement */
 #define AT_E_STATE       -5   /* call not allowed in the handle's current state */
 
 /* ------------------------------------------------------------------- grids */

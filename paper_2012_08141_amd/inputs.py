@@ -101,7 +101,7 @@ def _select(mask_flat: np.ndarray, R: int) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# Workload 1: 64^3 spherical shell, activate/listgen/lap_update/listgen/axpy.
+# Shell workload: 64^3 spherical shell, activate/listgen/lap_update/listgen/axpy.
 # ---------------------------------------------------------------------------
 def shell(seed: int = 0, n: int = 64, r_in: float = 0.30, r_out: float = 0.40,
           root_kind: str = "bitmask") -> SparseWorkload:
@@ -120,7 +120,7 @@ def shell(seed: int = 0, n: int = 64, r_in: float = 0.30, r_out: float = 0.40,
 
 
 # ---------------------------------------------------------------------------
-# Workload 2: 512^3 narrow band around 4 random spheres, Jacobi iterations.
+# Narrow-band workload: 512^3 band around 4 random spheres, Jacobi iterations.
 # ---------------------------------------------------------------------------
 def band(seed: int = 0, n: int = 512, nspheres: int = 4, band_blocks: float = 1.5,
          root_kind: str = "bitmask") -> SparseWorkload:
@@ -144,7 +144,7 @@ def band(seed: int = 0, n: int = 512, nspheres: int = 4, band_blocks: float = 1.
 
 
 # ---------------------------------------------------------------------------
-# Workload 3: 2M particles in 3 random boxes in a 256^3 grid.
+# Particle workload: 2M particles in 3 random boxes in a 256^3 grid.
 # ---------------------------------------------------------------------------
 def particles(seed: int = 0, n: int = 256, nparticles: int = 2_000_000,
               nboxes: int = 3, root_kind: str = "pointer") -> ParticleWorkload:
@@ -169,7 +169,7 @@ def particles(seed: int = 0, n: int = 256, nparticles: int = 2_000_000,
 
 
 # ---------------------------------------------------------------------------
-# Workload 4: a stream of independent 128^3 Jacobi requests.
+# Request workload: a stream of independent 128^3 Jacobi requests.
 # ---------------------------------------------------------------------------
 def batch_request(seed: int, index: int, n: int = 128, lo: int = 32, hi: int = 4096,
                   root_kind: str = "pointer") -> SparseWorkload:
@@ -199,7 +199,7 @@ def poisson_arrivals(seed: int, count: int, rate_per_s: float) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# Workload 5: 128^3 shell diffusion with a differentiable loss.
+# Diffusion workload: 128^3 shell diffusion with a differentiable loss.
 # ---------------------------------------------------------------------------
 def diffusion(seed: int = 0, n: int = 128, r_in: float = 0.32, r_out: float = 0.38,
               root_kind: str = "bitmask") -> SparseWorkload:

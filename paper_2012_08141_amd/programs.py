@@ -34,7 +34,7 @@ def load_workload(w: inputs.SparseWorkload, channels: dict, nch: int, capacity_b
     return g
 
 
-# ---------------------------------------------------------------- workload 1
+# ------------------------------------------------------------ shell workload
 def shell_setup(g: SparseGrid, coords):
     """Setup window: activation of the shell blocks and the first list."""
     return [E.activate(g, coords), E.listgen(g)]
@@ -47,14 +47,14 @@ def shell_step(g: SparseGrid, coords, coef=0.1, alpha=0.5):
             E.listgen(g), E.axpy(g, SHELL["a"], SHELL["out"], alpha)]
 
 
-# ---------------------------------------------------------------- workload 2
+# ------------------------------------------------------ narrow-band workload
 def jacobi_step(g: SparseGrid):
     """listgen -> jacobi (xn = (sum nb x + b)/6) -> copy (x = xn)."""
     return [E.listgen(g), E.jacobi(g, JACOBI["x"], JACOBI["b"], JACOBI["xn"]),
             E.copy(g, JACOBI["x"], JACOBI["xn"])]
 
 
-# ---------------------------------------------------------------- workload 3
+# --------------------------------------------------------- particle workload
 def particle_step(grids, t: int, x, v, m, dt: float, dx: float):
     """Step t on grid G = grids[t % 2]: listgen(G) -> reset(G) -> advect ->
     p2g(G) -> listgen(G) -> normalise(G) -> g2p(G)."""
@@ -66,7 +66,7 @@ def particle_step(grids, t: int, x, v, m, dt: float, dx: float):
             E.g2p(G, x, v, dx, PART["v"])]
 
 
-# ---------------------------------------------------------------- workload 5
+# -------------------------------------------------------- diffusion workload
 def diffusion_forward_tasks(g: SparseGrid, steps: int, dt: float, src: int = 0, dst: int = 1, k: int = 2):
     """listgen, then ``steps`` diffusion steps ping-ponging between channels
     src and dst.  Returns (tasks, channel holding the result)."""

@@ -185,7 +185,7 @@ def test_normalise():
 # ------------------------------------------------------- workload programs
 @pytest.mark.parametrize("opt", [0, 15])
 def test_shell_program(opt):
-    """Workload 1 at its full size: 64^3 shell, 10 steps, eager and optimized."""
+    """The 64^3 shell workload at its full size, 10 steps, eager and optimized."""
     from paper_2012_08141_amd import engine as E, programs as PR
     say("shell program opt", opt)
     w = I.shell(0)
@@ -204,7 +204,7 @@ def test_shell_program(opt):
 
 @pytest.mark.parametrize("opt", [0, 15])
 def test_jacobi_band_reduced(opt):
-    """Workload 2's recipe on a 128^3 domain, 100 iterations."""
+    """The narrow-band recipe on a 128^3 domain, 100 iterations."""
     from paper_2012_08141_amd import engine as E, programs as PR
     say("jacobi band128 opt", opt)
     w = I.band(0, n=128)
@@ -218,7 +218,7 @@ def test_jacobi_band_reduced(opt):
 
 
 def test_jacobi_band_full_size():
-    """Workload 2 at its full size (512^3): 2 iterations against the oracle,
+    """The narrow-band workload at its full size (512^3): 2 iterations against the oracle,
     then 100 iterations eager == optimized bit for bit."""
     from paper_2012_08141_amd import engine as E, programs as PR
     say("jacobi band512 full")

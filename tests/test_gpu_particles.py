@@ -117,7 +117,7 @@ def _particle_run(p, steps, opt, binned=True):
 @pytest.mark.parametrize("binned", [False, True])
 @pytest.mark.parametrize("opt", [0, 15])
 def test_particle_program_reduced(opt, binned):
-    """Workload 3's recipe (3 boxes, N(0, 0.1^2) velocities, dt = 1e-3) with
+    """The particle recipe (3 boxes, N(0, 0.1^2) velocities, dt = 1e-3) with
     100k particles in a 128^3 grid, 20 steps, eager and optimized, direct
     and binned scatter."""
     say("particle program opt", opt, "binned" if binned else "direct")
@@ -136,7 +136,7 @@ def test_particle_program_reduced(opt, binned):
 
 
 def test_particle_full_size_one_step_and_eager_vs_optimized():
-    """Workload 3 at full size (2M particles, 256^3): one step against the
+    """The particle workload at full size (2M particles, 256^3): one step against the
     oracle; 20 steps optimized against eager."""
     say("particles full size")
     p = I.particles(0)
