@@ -262,13 +262,15 @@ def bench_serving(args, torch):
         scratch.admit(r.cells, r.b, 1 << 40)
     tune = autotune.tune_batch(scratch, "batch128x%d" % count)
     del scratch
-    srv = JacobiServer(128, args.budget_mib << 20, 64, tune["iters_per_replay"], tune["workgroups"])
+    srv = JacobiServer(128, args.budget_mib << 20, 64, tune["iters_per_replay"], tune["workgroups"],
+                       waves=tune["waves"])
     closed = srv.serve(make_requests(args.seed, count, np.zeros(count)), realtime=False)
     cap_rps = count / closed.makespan
     rate = args.load * cap_rps
     arr = inputs.poisson_arrivals(args.seed, count, rate)
     reqs = make_requests(args.seed, count, arr)
-    srv2 = JacobiServer(128, args.budget_mib << 20, 64, tune["iters_per_replay"], tune["workgroups"])
+    srv2 = JacobiServer(128, args.budget_mib << 20, 64, tune["iters_per_replay"], tune["workgroups"],
+                        waves=tune["waves"])
     st = srv2.serve(reqs, realtime=True)
     base = serve_eager_fifo(make_requests(args.seed, count, arr), realtime=True)
     s, b = st.summary(), base.summary()

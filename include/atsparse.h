@@ -311,6 +311,10 @@ at_status at_flush(at_stats *stats, hipStream_t stream);
  * 2 one block per wave iteration with neighbour lookups in the root.
  * Records are only read when list generation left them current. */
 #define AT_OPTION_STRUCT_FOR_KERNEL 6
+/* Wavefronts per workgroup of the batched Jacobi launches: 1 (default), 2
+ * or 4; each wavefront sweeps its own blocks (a tuning knob; results are
+ * identical).  Read when at_batch_jacobi enqueues (or a graph captures). */
+#define AT_OPTION_BATCH_WAVES 7
 at_status at_set_option(int32_t option, int64_t value);
 at_status at_get_option(int32_t option, int64_t *value);
 

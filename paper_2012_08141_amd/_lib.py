@@ -29,6 +29,7 @@ AT_PLAN_MAX_MEMBERS = 8
 AT_OPTION_MAX_FUSE_PER_TASK, AT_OPTION_FLUSH_PERIOD, AT_OPTION_OPT_FLAGS, AT_OPTION_PLAN_CACHE = 1, 2, 3, 4
 AT_OPTION_STRUCT_FOR_WORKGROUPS = 5
 AT_OPTION_STRUCT_FOR_KERNEL = 6
+AT_OPTION_BATCH_WAVES = 7
 
 
 class AtGridDesc(ctypes.Structure):

@@ -1,10 +1,10 @@
 """Autotuner for the batched Jacobi launch.
 
-Times every candidate (persistent workgroup count, iterations per captured
-graph) on the actual batch with HIP events, keeps the fastest per iteration
--- preferring fewer iterations per replay within 3% of the best, since that
-is the admission granularity of the server -- and caches the choice per
-(device, workload signature) in a JSON file.
+Times every candidate (wavefronts per workgroup, persistent workgroup count,
+iterations per captured graph) on the actual batch with HIP events, keeps
+the fastest per iteration -- preferring fewer iterations per replay within
+3% of the best, since that is the admission granularity of the server --
+and caches the choice per (device, workload signature) in a JSON file.
 """
 from __future__ import annotations
 
@@ -36,29 +36,32 @@ def device_key() -> str:
     return "%s/%d" % (p.name, p.multi_processor_count)
 
 
-def tune_batch(arena, signature: str, workgroups=(2048, 4096, 7168, 14336), iters=(5, 10, 25),
-               reps: int = 4, use_cache: bool = True) -> dict:
-    """Pick (workgroups, iters_per_replay) for ``arena`` with its current
-    grids resident.  The arena's clock advances; callers tune on a scratch
-    arena or re-admit afterwards."""
+def tune_batch(arena, signature: str, wavefronts=(2048, 4096, 7168, 14336), waves=(1, 2, 4),
+               iters=(5, 10, 25), reps: int = 4, use_cache: bool = True) -> dict:
+    """Pick (waves per workgroup, workgroups, iters_per_replay) for ``arena``
+    with its current grids resident; ``wavefronts`` are the total persistent
+    wavefront counts tried.  The arena's clock advances; callers tune on a
+    scratch arena or re-admit afterwards."""
     key = device_key() + "|" + signature
     cache = _load() if use_cache else {}
-    if key in cache:
+    if key in cache and "waves" in cache[key]:
         return cache[key]
     results = []
-    for wgs in workgroups:
-        for K in iters:
-            g = arena.capture(K, wgs)
-            g.replay()
-            torch.cuda.synchronize()
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
-            for _ in range(reps):
+    for total in wavefronts:
+        for w in waves:
+            wgs = total // w
+            for K in iters:
+                g = arena.capture(K, wgs, w)
                 g.replay()
-            b.record()
-            torch.cuda.synchronize()
-            per_iter = a.elapsed_time(b) * 1e-3 / (reps * K)
-            results.append({"workgroups": wgs, "iters_per_replay": K, "s_per_iter": per_iter})
+                torch.cuda.synchronize()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                for _ in range(reps):
+                    g.replay()
+                b.record()
+                torch.cuda.synchronize()
+                per_iter = a.elapsed_time(b) * 1e-3 / (reps * K)
+                results.append({"waves": w, "workgroups": wgs, "iters_per_replay": K, "s_per_iter": per_iter})
     best = min(r["s_per_iter"] for r in results)
     ok = [r for r in results if r["s_per_iter"] <= 1.03 * best]
     choice = min(ok, key=lambda r: (r["iters_per_replay"], r["s_per_iter"]))

@@ -141,15 +141,35 @@ class BatchArena:
         self.launch(iters, workgroups)
         self.clock_host += iters
 
-    def capture(self, iters: int, workgroups: int = 0):
+    def capture(self, iters: int, workgroups: int = 0, waves: int = 0):
         """A replayable graph of ``iters`` iterations (the launches read all
-        per-iteration state from device memory)."""
-        return CapturedSteps(self, iters, workgroups)
+        per-iteration state from device memory).  ``waves``: wavefronts per
+        workgroup of the captured launches (0: the library's current setting)."""
+        return CapturedSteps(self, iters, workgroups, waves)
+
+
+def _get_waves() -> int:
+    v = ctypes.c_int64()
+    L.check(L.lib().at_get_option(L.AT_OPTION_BATCH_WAVES, ctypes.byref(v)))
+    return int(v.value)
+
+
+def _set_waves(w: int):
+    L.check(L.lib().at_set_option(L.AT_OPTION_BATCH_WAVES, w))
 
 
 class CapturedSteps:
-    def __init__(self, arena: BatchArena, iters: int, workgroups: int = 0):
+    def __init__(self, arena: BatchArena, iters: int, workgroups: int = 0, waves: int = 0):
         self.arena, self.iters = arena, iters
+        prev = _get_waves()
+        if waves:
+            _set_waves(waves)
+        try:
+            self._capture(arena, iters, workgroups)
+        finally:
+            _set_waves(prev)
+
+    def _capture(self, arena, iters, workgroups):
         self.graph = torch.cuda.CUDAGraph()
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())

@@ -112,9 +112,12 @@ hipError_t launch_gather_blocks(const GridDev &g, int ch, const int32_t *cells, 
 hipError_t launch_popcount(const GridDev &g, hipStream_t s);   // into hdr[HDR_SCRATCH]
 // iters x (jacobi, copy) over the work list, then clock += iters (2*iters + 1 dispatches).
 hipError_t launch_batch_jacobi(const BatchDev &d, int iters, int workgroups, hipStream_t s);
+int batch_waves();
+void set_batch_waves(int waves);          // 1, 2 or 4 wavefronts per batched workgroup
 // Persistent grid size used by struct-for kernels (workgroups).
 int struct_for_grid_size(const GridDev &g);
 void set_struct_for_grid_size(int wgs);   // 0 = automatic
+int struct_for_grid_size_override();       // the value set (0 = automatic)
 int struct_for_kernel();
 void set_struct_for_kernel(int form);     // 0 pipelined, 1 direct with records, 2 direct with root lookups
 

@@ -20,6 +20,7 @@ constexpr int kSFThreads = 128;          // struct-for workgroup
 constexpr int kSpinLimit = 1 << 22;      // bounded wait on a pointer-root allocation
 int g_sf_grid_override = 0;
 int g_sf_kernel = 0;
+int g_batch_waves = 1;
 
 // -------------------------------------------------------------- root access
 
@@ -967,11 +968,25 @@ __global__ __launch_bounds__(256) void k_batch_records(BatchDev d) {
     }
 }
 
-template <bool COPY>
-__global__ __launch_bounds__(64) void k_batch(BatchDev d, int it) {
-    const int lane = threadIdx.x;
+// Range of work entries a wavefront walks when a workgroup holds W
+// wavefronts: the workgroup's XCD slice as in list_range, each wavefront a
+// virtual workgroup of its own.
+template <int W>
+__device__ __forceinline__ ListRange wave_range(int count) {
+    const int nx = (gridDim.x % 8 == 0) ? 8 : 1;
+    const int x = blockIdx.x % nx;
+    const int local = (blockIdx.x / nx) * W + (int)(threadIdx.x >> 6);
+    const int per = (gridDim.x / nx) * W;
+    const int lo = (int)(((int64_t)count * x) / nx);
+    const int hi = (int)(((int64_t)count * (x + 1)) / nx);
+    return {lo + local, hi, per};
+}
+
+template <bool COPY, int W>
+__global__ __launch_bounds__(64 * W) void k_batch(BatchDev d, int it) {
+    const int lane = threadIdx.x & 63;
     const int64_t now = *d.clock + it;
-    const ListRange lr = list_range(*d.count);
+    const ListRange lr = wave_range<W>(*d.count);
     const int4 *__restrict__ rec = d.rec;
     for (int e = lr.lo; e < lr.hi; e += lr.step) {
         const int4 r0 = rec[2 * e];
@@ -1522,6 +1537,9 @@ int wave_grid_size(const GridDev &g, bool pipelined) {
 void set_struct_for_grid_size(int wgs) { g_sf_grid_override = wgs > 0 ? ((wgs + 7) / 8) * 8 : 0; }
 
 int struct_for_kernel() { return g_sf_kernel; }
+int struct_for_grid_size_override() { return g_sf_grid_override; }
+int batch_waves() { return g_batch_waves; }
+void set_batch_waves(int waves) { g_batch_waves = waves; }
 void set_struct_for_kernel(int form) { g_sf_kernel = form; }
 
 hipError_t launch_activate(const GridDev &g, const int32_t *ijk, int64_t n, int coord_kind, hipStream_t s) {
@@ -1742,9 +1760,18 @@ hipError_t launch_batch_jacobi(const BatchDev &d, int iters, int workgroups, hip
     if (wgs > d.pool) wgs = ((d.pool + 7) / 8) * 8;
     if (wgs < 8) wgs = 8;
     hipLaunchKernelGGL(k_batch_records, dim3(1024), dim3(256), 0, s, d);
+    const int W = g_batch_waves;
     for (int it = 0; it < iters; ++it) {
-        hipLaunchKernelGGL(k_batch<false>, dim3(wgs), dim3(64), 0, s, d, it);
-        hipLaunchKernelGGL(k_batch<true>, dim3(wgs), dim3(64), 0, s, d, it);
+        if (W == 4) {
+            hipLaunchKernelGGL((k_batch<false, 4>), dim3(wgs), dim3(256), 0, s, d, it);
+            hipLaunchKernelGGL((k_batch<true, 4>), dim3(wgs), dim3(256), 0, s, d, it);
+        } else if (W == 2) {
+            hipLaunchKernelGGL((k_batch<false, 2>), dim3(wgs), dim3(128), 0, s, d, it);
+            hipLaunchKernelGGL((k_batch<true, 2>), dim3(wgs), dim3(128), 0, s, d, it);
+        } else {
+            hipLaunchKernelGGL((k_batch<false, 1>), dim3(wgs), dim3(64), 0, s, d, it);
+            hipLaunchKernelGGL((k_batch<true, 1>), dim3(wgs), dim3(64), 0, s, d, it);
+        }
     }
     hipLaunchKernelGGL(k_batch_tick, dim3(1), dim3(64), 0, s, d, iters);
     return hipGetLastError();

@@ -722,6 +722,10 @@ at_status at_set_option(int32_t option, int64_t value) {
         if (value < 0 || value > 2) return fail(AT_E_INVALID, "struct-for kernel form must be 0, 1 or 2");
         set_struct_for_kernel((int)value);
         return AT_OK;
+    case AT_OPTION_BATCH_WAVES:
+        if (value != 1 && value != 2 && value != 4) return fail(AT_E_INVALID, "batch waves must be 1, 2 or 4");
+        set_batch_waves((int)value);
+        return AT_OK;
     default:
         return fail(AT_E_INVALID, "unknown option %d", option);
     }
@@ -736,6 +740,9 @@ at_status at_get_option(int32_t option, int64_t *value) {
     case AT_OPTION_FLUSH_PERIOD: *value = en.flush_period; return AT_OK;
     case AT_OPTION_OPT_FLAGS: *value = en.opt_flags; return AT_OK;
     case AT_OPTION_PLAN_CACHE: *value = en.plan_cache ? 1 : 0; return AT_OK;
+    case AT_OPTION_STRUCT_FOR_WORKGROUPS: *value = struct_for_grid_size_override(); return AT_OK;
+    case AT_OPTION_STRUCT_FOR_KERNEL: *value = struct_for_kernel(); return AT_OK;
+    case AT_OPTION_BATCH_WAVES: *value = batch_waves(); return AT_OK;
     default: return fail(AT_E_INVALID, "unknown option %d", option);
     }
 }

@@ -74,12 +74,12 @@ class ServeStats:
 
 class JacobiServer:
     def __init__(self, n: int = 128, budget_bytes: int = 256 << 20, max_grids: int = 64,
-                 iters_per_replay: int = 10, workgroups: int = 0, max_inflight: int = 2):
+                 iters_per_replay: int = 10, workgroups: int = 0, max_inflight: int = 2, waves: int = 0):
         pool = max(1, budget_bytes // BatchArena.footprint(1))
         self.arena = BatchArena(n, max_grids, pool)
         self.budget = budget_bytes
         self.K = iters_per_replay
-        self.graph = self.arena.capture(self.K, workgroups)
+        self.graph = self.arena.capture(self.K, workgroups, waves)
         self.max_inflight = max_inflight
 
     def serve(self, requests, realtime: bool = True) -> ServeStats:

@@ -106,3 +106,53 @@ def test_batch_graph_replays_match_eager_launches():
         a2.step(4)
         torch.cuda.synchronize()
         assert torch.equal(a1.x, a2.x) and torch.equal(a1.xn, a2.xn)
+
+
+@pytest.mark.parametrize("waves", [2, 4])
+def test_batch_waves_per_workgroup_equal(waves):
+    """Two or four wavefronts per workgroup give the same state as one."""
+    from paper_2012_08141_amd.batching import BatchArena
+    say("batch waves", waves)
+    reqs = _requests(5, iters=30, seed=7)
+    arenas = [BatchArena(128, 8, 4096), BatchArena(128, 8, 4096)]
+    for a in arenas:
+        for r in reqs:
+            a.admit(r.cells, r.b, r.iters)
+    g1 = arenas[0].capture(5, 512, 1)
+    gw = arenas[1].capture(5, 512 // waves, waves)
+    for _ in range(6):
+        g1.replay()
+        gw.replay()
+    torch.cuda.synchronize()
+    assert torch.equal(arenas[0].x, arenas[1].x) and torch.equal(arenas[0].xn, arenas[1].xn)
+
+
+def test_autotuner_choice_is_a_candidate_and_correct():
+    """The autotuner times every (waves, workgroups, iterations per replay)
+    candidate and returns one of them; a graph captured with the choice
+    gives the result of the default launch."""
+    from paper_2012_08141_amd import autotune
+    from paper_2012_08141_amd.batching import BatchArena
+    say("autotune")
+    reqs = _requests(4, iters=1 << 30, seed=9)
+    scratch = BatchArena(128, 8, 4096)
+    for r in reqs:
+        scratch.admit(r.cells, r.b, r.iters)
+    choice = autotune.tune_batch(scratch, "test", wavefronts=(1024, 2048), waves=(1, 2), iters=(2, 4),
+                                 reps=2, use_cache=False)
+    cands = {(c["waves"], c["workgroups"], c["iters_per_replay"]) for c in choice["candidates"]}
+    assert len(cands) == 8
+    assert (choice["waves"], choice["workgroups"], choice["iters_per_replay"]) in cands
+    a1, a2 = BatchArena(128, 8, 4096), BatchArena(128, 8, 4096)
+    for a in (a1, a2):
+        for r in reqs[:2]:
+            a.admit(r.cells, r.b, 12)
+    K = choice["iters_per_replay"]
+    g = a2.capture(K, choice["workgroups"], choice["waves"])
+    done = 0
+    while done < 12:
+        g.replay()
+        a1.step(K)
+        done += K
+    torch.cuda.synchronize()
+    assert torch.equal(a1.x, a2.x)
