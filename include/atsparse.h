@@ -372,6 +372,23 @@ at_status at_batch_jacobi(at_batch batch, int32_t iters, int32_t workgroups, hip
 /* Total device dispatches issued by the library since load. */
 int64_t at_dispatch_count(void);
 
+/* Per-launch timing of engine windows (a measurement aid).  While enabled,
+ * every task the engine launches on a device grid is bracketed by a pair of
+ * HIP events recorded on the window's stream (no host synchronisation).
+ * at_timing_collect waits for the recorded events and returns, per launched
+ * kind (task kind, op of its first member, number of fused members), the
+ * launches and their total event-measured duration in microseconds, then
+ * forgets them.  Events are created on first use and reused; out may be
+ * NULL with cap 0 to discard.  Returns AT_E_CAPACITY (entries dropped) when
+ * cap is too small. */
+typedef struct at_timing_entry {
+    int32_t kind, op, members, reserved;
+    int64_t launches;
+    double total_us;
+} at_timing_entry;
+at_status at_timing_enable(int32_t on);
+at_status at_timing_collect(at_timing_entry *out, int32_t cap, int32_t *n);
+
 const char *at_last_error(void);
 const char *at_version(void);
 

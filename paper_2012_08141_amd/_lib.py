@@ -37,6 +37,11 @@ class AtGridDesc(ctypes.Structure):
                 ("particle_capacity", c_int32)]
 
 
+class AtTimingEntry(ctypes.Structure):
+    _fields_ = [("kind", c_int32), ("op", c_int32), ("members", c_int32), ("reserved", c_int32),
+                ("launches", c_int64), ("total_us", ctypes.c_double)]
+
+
 class AtGridInfo(ctypes.Structure):
     _fields_ = [("n", c_int32), ("R", c_int32), ("root_kind", c_int32), ("channels", c_int32),
                 ("capacity_blocks", c_int32), ("list_capacity", c_int32), ("ncells", c_int64),
@@ -97,6 +102,8 @@ _SIGS = {
     "at_enqueue": (c_int32, [ctypes.POINTER(AtTask), _P]),
     "at_flush": (c_int32, [ctypes.POINTER(AtStats), _P]),
     "at_set_option": (c_int32, [c_int32, c_int64]),
+    "at_timing_enable": (c_int32, [c_int32]),
+    "at_timing_collect": (c_int32, [ctypes.POINTER(AtTimingEntry), c_int32, ctypes.POINTER(c_int32)]),
     "at_get_option": (c_int32, [c_int32, ctypes.POINTER(c_int64)]),
     "at_engine_reset": (c_int32, []),
     "at_ext_modified": (c_int32, [_P]),

@@ -61,6 +61,14 @@ struct Engine {
     hipStream_t queue_stream = nullptr;
     std::atomic<int64_t> dispatches{0};
     uint64_t next_uid = 1;
+    // per-launch timing (at_timing_enable)
+    struct Timed {
+        int32_t kind, op, members;
+        hipEvent_t a, b;
+    };
+    bool timing = false;
+    std::vector<hipEvent_t> ev_free;
+    std::vector<Timed> timed;
 };
 
 Engine &E() {
@@ -263,6 +271,25 @@ at_status plan_window(const at_task *tasks, int ntasks, uint32_t flags, std::vec
     return AT_OK;
 }
 
+hipEvent_t take_event() {
+    Engine &en = E();
+    if (!en.ev_free.empty()) {
+        hipEvent_t e = en.ev_free.back();
+        en.ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+
+bool node_on_device(const Node &nd, const at_task *tasks) {
+    for (const Member &m : nd.members) {
+        const at_grid_s *g = task_grid(tasks[m.task]);
+        if (g && g->virt) return false;
+    }
+    return true;
+}
+
 at_status run_window(const at_task *tasks, int ntasks, uint32_t flags, at_stats *stats, hipStream_t s) {
     Engine &en = E();
     std::lock_guard<std::recursive_mutex> lk(en.mu);
@@ -279,7 +306,22 @@ at_status run_window(const at_task *tasks, int ntasks, uint32_t flags, at_stats 
     const std::vector<uint8_t> tables = neighbour_tables_valid(nodes, tasks, en.persist);
     for (size_t i = 0; i < nodes.size(); ++i) {
         const Node &nd = nodes[i];
+        hipEvent_t ea = nullptr;
+        if (en.timing && node_on_device(nd, tasks)) {
+            ea = take_event();
+            if (ea && hipEventRecord(ea, s) != hipSuccess) ea = nullptr;
+        }
         st = execute_node(nd, tasks, tables[i] != 0, s);
+        if (ea) {
+            hipEvent_t eb = take_event();
+            if (eb && hipEventRecord(eb, s) == hipSuccess) {
+                const at_task &t0 = tasks[nd.members[0].task];
+                en.timed.push_back({t0.kind, t0.op, (int32_t)nd.members.size(), ea, eb});
+            } else {
+                en.ev_free.push_back(ea);
+                if (eb) en.ev_free.push_back(eb);
+            }
+        }
         if (st != AT_OK) {
             Planner::commit(nodes, tasks, en.persist);
             return st;
@@ -880,6 +922,44 @@ at_status at_batch_jacobi(at_batch batch, int32_t iters, int32_t workgroups, hip
 }
 
 int64_t at_dispatch_count(void) { return E().dispatches.load(); }
+
+at_status at_timing_enable(int32_t on) {
+    Engine &en = E();
+    std::lock_guard<std::recursive_mutex> lk(en.mu);
+    en.timing = on != 0;
+    return AT_OK;
+}
+
+at_status at_timing_collect(at_timing_entry *out, int32_t cap, int32_t *n) {
+    if (cap < 0 || (cap > 0 && !out) || !n) return fail(AT_E_INVALID, "bad output array");
+    Engine &en = E();
+    std::lock_guard<std::recursive_mutex> lk(en.mu);
+    std::vector<at_timing_entry> acc;
+    hipError_t err = hipSuccess;
+    for (const Engine::Timed &t : en.timed) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(t.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.a, t.b);
+        if (e != hipSuccess) {
+            err = e;
+        } else {
+            size_t k = 0;
+            while (k < acc.size() && !(acc[k].kind == t.kind && acc[k].op == t.op && acc[k].members == t.members)) ++k;
+            if (k == acc.size()) acc.push_back(at_timing_entry{t.kind, t.op, t.members, 0, 0, 0.0});
+            acc[k].launches += 1;
+            acc[k].total_us += 1e3 * (double)ms;
+        }
+        en.ev_free.push_back(t.a);
+        en.ev_free.push_back(t.b);
+    }
+    en.timed.clear();
+    if (err != hipSuccess) return hip_fail(err, "timing events");
+    const int32_t m = (int32_t)acc.size();
+    *n = m < cap ? m : cap;
+    for (int32_t i = 0; i < *n; ++i) out[i] = acc[i];
+    if (m > cap) return fail(AT_E_CAPACITY, "%d timing entries, room for %d", m, cap);
+    return AT_OK;
+}
 
 const char *at_last_error(void) { return g_err.c_str(); }
 

@@ -214,3 +214,24 @@ def paper_task_count(entries) -> int:
     """Tasks counted the paper's way (Fig. 6): a list generation is a clear
     task plus a listgen task; this library folds the clear into one dispatch."""
     return sum(2 if e["kind"] == L.AT_TASK_LISTGEN else 1 for e in entries)
+
+
+def timing_enable(on: bool = True):
+    """Bracket every launched task of later windows with HIP events."""
+    L.check(L.lib().at_timing_enable(1 if on else 0))
+
+
+def timing_collect() -> list:
+    """Wait for the recorded events; per launched kind (task kind, op,
+    fused members): launches and mean event-measured microseconds."""
+    cap = 64
+    out = (L.AtTimingEntry * cap)()
+    n = ctypes.c_int32()
+    L.check(L.lib().at_timing_collect(out, cap, ctypes.byref(n)))
+    res = []
+    for i in range(n.value):
+        e = out[i]
+        name = OP_NAMES.get(e.op, "?") if e.kind == L.AT_TASK_STENCIL else KIND_NAMES.get(e.kind, "?")
+        res.append({"name": name, "kind": e.kind, "op": e.op, "members": e.members, "launches": e.launches,
+                    "mean_us": e.total_us / max(1, e.launches)})
+    return res

@@ -119,3 +119,24 @@ def test_options_roundtrip():
     assert lib.at_set_option(L.AT_OPTION_MAX_FUSE_PER_TASK, 0) == L.AT_E_INVALID
     assert lib.at_set_option(999, 0) == L.AT_E_INVALID
     assert lib.at_version().startswith(b"atsparse")
+
+
+def test_timing_collect_without_device_work():
+    """Planning handles launch nothing, so a timed window records no events;
+    bad arguments are rejected."""
+    from paper_2012_08141_amd import engine as E
+    from paper_2012_08141_amd.grid import SparseGrid
+    lib = L.lib()
+    g = SparseGrid(32, 2, "bitmask", device=None)
+    E.reset()
+    E.timing_enable(True)
+    try:
+        E.run_sequence([E.listgen(g), E.inc(g, 0, 1.0)], E.OPT_ALL, stream=0)
+        assert E.timing_collect() == []
+    finally:
+        E.timing_enable(False)
+    n = ctypes.c_int32()
+    assert lib.at_timing_collect(None, 1, ctypes.byref(n)) == L.AT_E_INVALID
+    assert lib.at_timing_collect(None, 0, None) == L.AT_E_INVALID
+    assert lib.at_timing_collect(None, 0, ctypes.byref(n)) == L.AT_OK and n.value == 0
+    E.reset()
