@@ -307,28 +307,42 @@ def bench_serving(args, torch):
 
 # ------------------------------------------------------------------- diffusion
 def bench_diffusion(args, torch):
+    from paper_2012_08141_amd import engine as E
     from paper_2012_08141_amd import inputs
     from paper_2012_08141_amd.autodiff import DiffusionProblem, diffusion_loss
     w = inputs.diffusion(args.seed)
-    prob = DiffusionProblem(w.n, w.blocks, 0.1, 20, 5)
     a0 = torch.as_tensor(w.channels["a"], device="cuda")
     k = torch.as_tensor(w.channels["k"], device="cuda")
     tgt = torch.as_tensor(w.channels["target"], device="cuda")
-    times = []
-    for _ in range(args.warmup + args.steps):
-        a = a0.clone().requires_grad_(True)
-        kk = k.clone().requires_grad_(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        loss = diffusion_loss(a, kk, tgt, prob)
-        loss.backward()
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-    t = sorted(times[args.warmup:])[len(times[args.warmup:]) // 2]
+    res = {}
+    for name, opt in (("optimized", E.OPT_ALL), ("eager", 0)):
+        prob = DiffusionProblem(w.n, w.blocks, 0.1, 20, 5, opt_flags=opt)
+        times, disp = [], []
+        for _ in range(args.warmup + args.steps):
+            a = a0.clone().requires_grad_(True)
+            kk = k.clone().requires_grad_(True)
+            torch.cuda.synchronize()
+            d0 = E.dispatch_count()
+            t0 = time.perf_counter()
+            loss = diffusion_loss(a, kk, tgt, prob)
+            loss.backward()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            disp.append(E.dispatch_count() - d0)
+        t = sorted(times[args.warmup:])[len(times[args.warmup:]) // 2]
+        res[name] = (t, disp[-1], a.grad.clone(), kk.grad.clone())
+        del prob
+    t, d, ga, gk = res["optimized"]
+    te, de, gae, gke = res["eager"]
     out = _base(args.steps, args.warmup, w.active_voxels * 20 / t, t * 1e3,
                 {"workload": "diffusion128: 20 diffusion steps + adjoint (checkpoints every 5) on a 128^3 shell "
                              "(%d blocks)" % w.nblocks, "seed": args.seed})
-    out["note"] = "value counts forward steps only; one step = forward and backward of the whole 20-step loss"
+    out.update({"note": "value counts forward steps only; one step = forward and backward of the whole 20-step "
+                        "loss; ms_per_step is the median over the timed repetitions",
+                "launches_per_step": {"optimized": d, "eager": de},
+                "eager": {"value": w.active_voxels * 20 / te, "ms_per_step": te * 1e3},
+                "speedup_vs_eager": te / t,
+                "gradients_equal_eager": bool(torch.equal(ga, gae) and torch.equal(gk, gke))})
     return out
 
 

@@ -174,6 +174,8 @@ at_status at_run_stencil(at_grid grid, int32_t op, const int32_t *ch, const floa
  * (wx*wy)*wz, nodes in (x, y, z) lexicographic order). */
 #define AT_ACT_PER_NODE  0   /* eager: check and activate at each of the 27 node writes */
 #define AT_ACT_PER_BLOCK 1   /* activate each distinct touched block once, then write unchecked */
+#define AT_ACT_NONE      2   /* activate nothing: contributions to nodes of inactive blocks are
+                                dropped (for callers that keep every touched block active) */
 
 /* x += dt * v (device SoA arrays, np particles). */
 at_status at_advect(float *d_x, const float *d_v, int64_t np, float dt, hipStream_t stream);

@@ -1136,7 +1136,7 @@ __global__ __launch_bounds__(256) void k_particles(PartProg pp) {
             // per-block activation: the touched nodes span at most 2 blocks per axis
             int32_t bslot[2][2][2];
             const int blo[3] = {base[0] >> 3, base[1] >> 3, base[2] >> 3};
-            if (ACT == AT_ACT_PER_BLOCK) {
+            if (ACT == AT_ACT_PER_BLOCK || ACT == AT_ACT_NONE) {
                 for (int a = 0; a < 2; ++a)
                     for (int b = 0; b < 2; ++b)
                         for (int d = 0; d < 2; ++d) {
@@ -1146,7 +1146,8 @@ __global__ __launch_bounds__(256) void k_particles(PartProg pp) {
                                               (b == 0 || ((base[1] + 2) >> 3) != blo[1]) &&
                                               (d == 0 || ((base[2] + 2) >> 3) != blo[2]);
                             if (!used || ci < 0 || cj < 0 || ck < 0 || ci >= g.R || cj >= g.R || ck >= g.R) continue;
-                            bslot[a][b][d] = activate_cell<KD>(g, ((int64_t)ci * g.R + cj) * g.R + ck);
+                            const int64_t cell = ((int64_t)ci * g.R + cj) * g.R + ck;
+                            bslot[a][b][d] = ACT == AT_ACT_NONE ? slot_of<KD>(g, cell) : activate_cell<KD>(g, cell);
                         }
             }
             for (int a = 0; a < 3; ++a) {
@@ -1158,7 +1159,7 @@ __global__ __launch_bounds__(256) void k_particles(PartProg pp) {
                         const int k = base[2] + d;
                         if (i < 0 || j < 0 || k < 0 || i >= N || j >= N || k >= N) continue;
                         int32_t s;
-                        if (ACT == AT_ACT_PER_BLOCK) {
+                        if (ACT == AT_ACT_PER_BLOCK || ACT == AT_ACT_NONE) {
                             s = bslot[(i >> 3) - blo[0]][(j >> 3) - blo[1]][(k >> 3) - blo[2]];
                         } else {
                             s = activate_cell<KD>(g, ((int64_t)(i >> 3) * g.R + (j >> 3)) * g.R + (k >> 3));
@@ -1436,7 +1437,8 @@ __global__ __launch_bounds__(256) void k_p2g_bins(PartProg pp) {
             int32_t sl = -1;
             if (tflag[t]) {
                 const int64_t cell = ((int64_t)(ci - 1 + t / 9) * g.R + (cj - 1 + (t / 3) % 3)) * g.R + (ck - 1 + t % 3);
-                sl = activate_cell<KD>(g, cell);   // already active under per-node activation
+                // already active under per-node activation; looked up only under none
+                sl = ACT == AT_ACT_NONE ? slot_of<KD>(g, cell) : activate_cell<KD>(g, cell);
             }
             tslot[t] = sl;
         }
@@ -1678,6 +1680,8 @@ static void launch_part_a(const PartProg &pp, dim3 grid, bool bin, hipStream_t s
         // cell keys (with the gather and advection), ranks, scan, place, scatter per bin
         if (pp.act_mode == AT_ACT_PER_BLOCK)
             hipLaunchKernelGGL((k_particles<KS, KD, STEPS, AT_ACT_PER_BLOCK, P2G>), grid, dim3(256), 0, s, pp);
+        else if (pp.act_mode == AT_ACT_NONE)
+            hipLaunchKernelGGL((k_particles<KS, KD, STEPS, AT_ACT_NONE, P2G>), grid, dim3(256), 0, s, pp);
         else
             hipLaunchKernelGGL((k_particles<KS, KD, STEPS, AT_ACT_PER_NODE, P2G>), grid, dim3(256), 0, s, pp);
         if (pp.gdst.ncells <= kHistCells)
@@ -1689,12 +1693,16 @@ static void launch_part_a(const PartProg &pp, dim3 grid, bool bin, hipStream_t s
         const int64_t nb = pp.gdst.ncells < 256 * 8 ? pp.gdst.ncells : 256 * 8;
         if (pp.act_mode == AT_ACT_PER_BLOCK)
             hipLaunchKernelGGL((k_p2g_bins<KD, AT_ACT_PER_BLOCK>), dim3((unsigned)nb), dim3(256), 0, s, pp);
+        else if (pp.act_mode == AT_ACT_NONE)
+            hipLaunchKernelGGL((k_p2g_bins<KD, AT_ACT_NONE>), dim3((unsigned)nb), dim3(256), 0, s, pp);
         else
             hipLaunchKernelGGL((k_p2g_bins<KD, AT_ACT_PER_NODE>), dim3((unsigned)nb), dim3(256), 0, s, pp);
         return;
     }
     if (pp.act_mode == AT_ACT_PER_BLOCK)
         hipLaunchKernelGGL((k_particles<KS, KD, STEPS, AT_ACT_PER_BLOCK, false>), grid, dim3(256), 0, s, pp);
+    else if (pp.act_mode == AT_ACT_NONE)
+        hipLaunchKernelGGL((k_particles<KS, KD, STEPS, AT_ACT_NONE, false>), grid, dim3(256), 0, s, pp);
     else
         hipLaunchKernelGGL((k_particles<KS, KD, STEPS, AT_ACT_PER_NODE, false>), grid, dim3(256), 0, s, pp);
 }

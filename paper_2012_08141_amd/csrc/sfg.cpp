@@ -118,8 +118,12 @@ void member_accesses(const at_task &t, const Member &mb, bool check, int16_t mi,
         add(EXT(t.ext[2]), M_R, P_ELEM, u);
         add(VAL(gu, t.ch[0]), M_R | M_W, P_SCATTER, 0);
         for (int q = 0; q < 3; ++q) add(VAL(gu, t.ch[1] + q), M_R | M_W, P_SCATTER, 0);
-        add(MASK(gu), M_R | M_W, P_SCATTER, F_ACTIVATING);
-        if (ptr_root) add(ALLOC(gu), M_R | M_W, P_SCATTER, F_ACTIVATING);
+        if (t.op == AT_ACT_NONE) {
+            add(MASK(gu), M_R, P_GATHER, 0);   // reads the roots, activates nothing
+        } else {
+            add(MASK(gu), M_R | M_W, P_SCATTER, F_ACTIVATING);
+            if (ptr_root) add(ALLOC(gu), M_R | M_W, P_SCATTER, F_ACTIVATING);
+        }
         break;
     }
     case AT_TASK_G2P: {
@@ -303,7 +307,8 @@ std::string validate_task(const at_task &t) {
         if (t.n < 0 || (t.n > 0 && (!t.ext[0] || !t.ext[1] || !t.ext[2]))) return "p2g: bad arrays";
         if (!chan_ok(t.ch[0], 1) || !chan_ok(t.ch[1], 3)) return "p2g: channel out of range";
         if (!(t.param[0] > 0.f)) return "p2g: dx must be positive";
-        if (t.op != AT_ACT_PER_NODE && t.op != AT_ACT_PER_BLOCK) return "p2g: bad activation mode";
+        if (t.op != AT_ACT_PER_NODE && t.op != AT_ACT_PER_BLOCK && t.op != AT_ACT_NONE)
+            return "p2g: bad activation mode";
         break;
     case AT_TASK_G2P:
         if (t.n < 0 || (t.n > 0 && (!t.ext[0] || !t.ext[1]))) return "g2p: bad arrays";

@@ -153,3 +153,43 @@ def test_particle_full_size_one_step_and_eager_vs_optimized():
     close_state(vo.cpu().numpy(), ve.cpu().numpy(), "v eager/opt", sv)
     for gi in (0, 1):
         assert np.array_equal(ge[gi].active_cells(), go[gi].active_cells())
+
+
+@pytest.mark.parametrize("binned", [False, True])
+def test_p2g_without_activation(binned):
+    """AT_ACT_NONE: on a grid whose touched blocks are already active the
+    scatter equals the activating one; on a fresh grid it activates nothing
+    and writes nothing."""
+    import ctypes
+    from paper_2012_08141_amd import _lib as L
+    from paper_2012_08141_amd.grid import SparseGrid
+    say("p2g none", "binned" if binned else "direct")
+    n, np_ = 64, 20000
+    p = I.random_particles(5, n, np_, 0.1, 0.6, "pointer")
+    ref = OP.p2g_once(n, None, p.x, p.v, p.m, "f32")
+    x, v, m = (torch.as_tensor(a, device="cuda").contiguous() for a in (p.x, p.v, p.m))
+    ch = (ctypes.c_int32 * 2)(0, 1)
+
+    def scatter(g, act):
+        L.check(L.lib().at_p2g(g.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(v.data_ptr()),
+                               ctypes.c_void_p(m.data_ptr()), np_, 1.0 / n, ch, act,
+                               torch.cuda.current_stream().cuda_stream))
+
+    cap = np_ if binned else 0
+    fresh = SparseGrid(n, 4, "pointer", (n // 8) ** 3, particle_capacity=cap)
+    scatter(fresh, L.AT_ACT_NONE)
+    torch.cuda.synchronize()
+    assert len(fresh.active_cells()) == 0 and float(fresh.channel(0).abs().sum()) == 0.0
+    pre = SparseGrid(n, 4, "pointer", (n // 8) ** 3, particle_capacity=cap)
+    pre.activate(I.cells_to_blocks(ref["cells"], n // 8))
+    act = SparseGrid(n, 4, "pointer", (n // 8) ** 3, particle_capacity=cap)
+    scatter(pre, L.AT_ACT_NONE)
+    scatter(act, L.AT_ACT_PER_BLOCK)
+    torch.cuda.synchronize()
+    cells = ref["cells"]
+    assert np.array_equal(pre.active_cells(), cells) and np.array_equal(act.active_cells(), cells)
+    for q in range(4):
+        A = ref["abs"][q].astype(np.float64)
+        for g in (pre, act):
+            err = np.abs(g.read_blocks(q, cells).astype(np.float64) - (ref["m"] if q == 0 else ref["mv"][q - 1]))
+            assert np.all(err <= 1e-5 * A + 1e-30), q

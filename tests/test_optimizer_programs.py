@@ -141,3 +141,17 @@ def test_enqueue_flush_period():
     st = E.flush()
     assert st["tasks_in"] == 0
     E.set_option(L.AT_OPTION_FLUSH_PERIOD, 0)
+
+
+def test_scatter_without_activation_leaves_the_list_current():
+    """A scatter that activates nothing (AT_ACT_NONE) does not write the
+    mask, so the list generation after it is removable; one that activates
+    (per node or per block) keeps it (Section 6.2)."""
+    G = SparseGrid(256, 7, "pointer", 4096, device=None)
+    x, v, m = FakeArray((3, 1000)), FakeArray((3, 1000)), FakeArray((1000,))
+    for act, removed in ((L.AT_ACT_NONE, 1), (L.AT_ACT_PER_BLOCK, 0), (L.AT_ACT_PER_NODE, 0)):
+        E.reset()
+        tasks = [E.listgen(G), E.p2g(G, x, v, m, 1 / 256, 0, 1, activation=act), E.listgen(G)]
+        _, st = E.plan_sequence(tasks, E.OPT_LGR)
+        assert st["listgens_removed"] == removed, act
+    E.reset()
