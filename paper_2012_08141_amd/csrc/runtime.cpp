@@ -295,6 +295,13 @@ at_status run_window(const at_task *tasks, int ntasks, uint32_t flags, at_stats 
     std::lock_guard<std::recursive_mutex> lk(en.mu);
     if (ntasks < 0 || (ntasks > 0 && !tasks)) return fail(AT_E_INVALID, "bad task array");
     if (flags & ~AT_OPT_ALL) return fail(AT_E_INVALID, "unknown optimizer flags");
+    // a window on planning handles only records engine state; its tasks
+    // without a grid (advection) must not launch on their placeholder arrays
+    bool any_virt = false, any_dev = false;
+    for (int i = 0; i < ntasks; ++i)
+        for (const at_grid_s *g : {(const at_grid_s *)tasks[i].grid, (const at_grid_s *)tasks[i].grid2})
+            if (g) (g->virt ? any_virt : any_dev) = true;
+    if (any_virt && any_dev) return fail(AT_E_INVALID, "a window mixes planning handles and device grids");
     const auto t0 = std::chrono::steady_clock::now();
     std::vector<Node> nodes;
     PlanCounters ctr;
@@ -304,7 +311,7 @@ at_status run_window(const at_task *tasks, int ntasks, uint32_t flags, at_stats 
     const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
     const int64_t d0 = en.dispatches.load();
     const std::vector<uint8_t> tables = neighbour_tables_valid(nodes, tasks, en.persist);
-    for (size_t i = 0; i < nodes.size(); ++i) {
+    for (size_t i = 0; i < nodes.size() && !any_virt; ++i) {
         const Node &nd = nodes[i];
         hipEvent_t ea = nullptr;
         if (en.timing && node_on_device(nd, tasks)) {

@@ -140,3 +140,26 @@ def test_timing_collect_without_device_work():
     assert lib.at_timing_collect(None, 0, None) == L.AT_E_INVALID
     assert lib.at_timing_collect(None, 0, ctypes.byref(n)) == L.AT_OK and n.value == 0
     E.reset()
+
+
+def test_planning_window_launches_nothing_and_mixing_is_rejected():
+    """A window on planning handles records state only, also for its tasks
+    without a grid (advection over placeholder arrays); a window mixing
+    planning handles and device grids is rejected before anything runs."""
+    from paper_2012_08141_amd import engine as E
+    from paper_2012_08141_amd.grid import SparseGrid
+
+    class Fake:
+        def __init__(self, shape, p):
+            self.shape, self._p = shape, p
+
+        def data_ptr(self):
+            return self._p
+
+    g = SparseGrid(64, 7, "pointer", 512, device=None)
+    x, v, m = Fake((3, 100), 0x1000000), Fake((3, 100), 0x2000000), Fake((100,), 0x3000000)
+    E.reset()
+    before = L.lib().at_dispatch_count()
+    st = E.run_sequence([E.listgen(g), E.advect(x, v, 1e-3), E.p2g(g, x, v, m, 1 / 64, 0, 1)], 0, stream=0)
+    assert st["dispatches"] == 0 and L.lib().at_dispatch_count() == before
+    E.reset()
