@@ -167,42 +167,64 @@ Sim simulate(const std::vector<Node> &nodes, const at_task *tasks, const Persist
     S.list_ver.assign(S.n, 0);
     S.mask_at.assign(S.n, 0);
     S.act_sig.assign(S.n, 0);
-    std::unordered_map<StateKey, int, StateKeyHash> last_writer;
-    std::unordered_map<StateKey, std::vector<int>, StateKeyHash> readers;
-    auto curv = [&](const StateKey &s) -> uint64_t & {
-        auto it = S.cur.find(s);
-        if (it == S.cur.end()) it = S.cur.emplace(s, P.ver(s)).first;
-        return it->second;
+    // dense index of the window's states: one hash lookup per access
+    std::unordered_map<StateKey, int, StateKeyHash> id;
+    id.reserve(nodes.size() * 8);
+    std::vector<StateKey> keys;
+    std::vector<uint64_t> cur;
+    std::vector<char> touched;   // versions the simulation reads or bumps (reported in S.cur)
+    std::vector<int> last_writer;
+    std::vector<std::vector<int>> readers;
+    auto sidx = [&](const StateKey &s) -> int {
+        auto it = id.find(s);
+        if (it != id.end()) return it->second;
+        const int k = (int)keys.size();
+        id.emplace(s, k);
+        keys.push_back(s);
+        cur.push_back(P.ver(s));
+        touched.push_back(0);
+        last_writer.push_back(-1);
+        readers.emplace_back();
+        return k;
     };
-    std::vector<StateKey> written;
+    std::vector<int> written;
     for (int i = 0; i < S.n; ++i) {
         const Node &nd = nodes[i];
         const at_task &t0 = tasks[nd.members[0].task];
-        if (nd.loop == LT_STRUCT) S.list_ver[i] = curv(LIST(nd.loop_grid));
-        if (t0.kind == AT_TASK_LISTGEN) S.mask_at[i] = curv(MASK(task_grid(t0)->uid));
-        if (t0.kind == AT_TASK_ACTIVATE) S.act_sig[i] = activation_sig(t0, curv(EXT(t0.ext[0])));
+        auto version_of = [&](const StateKey &s) -> uint64_t {
+            const int k = sidx(s);
+            touched[k] = 1;
+            return cur[k];
+        };
+        if (nd.loop == LT_STRUCT) S.list_ver[i] = version_of(LIST(nd.loop_grid));
+        if (t0.kind == AT_TASK_LISTGEN) S.mask_at[i] = version_of(MASK(task_grid(t0)->uid));
+        if (t0.kind == AT_TASK_ACTIVATE) S.act_sig[i] = activation_sig(t0, version_of(EXT(t0.ext[0])));
         for (const Access &a : nd.acc) {
             if (!(a.mode & M_R)) continue;
-            auto lw = last_writer.find(a.s);
-            if (lw != last_writer.end() && lw->second != i) S.set(lw->second, i);
-            auto &rv = readers[a.s];
+            const int k = sidx(a.s);
+            if (last_writer[k] >= 0 && last_writer[k] != i) S.set(last_writer[k], i);
+            auto &rv = readers[k];
             if (rv.empty() || rv.back() != i) rv.push_back(i);
         }
         written.clear();
         for (const Access &a : nd.acc) {
             if (!(a.mode & M_W)) continue;
-            if (std::find(written.begin(), written.end(), a.s) != written.end()) continue;
-            written.push_back(a.s);
-            auto lw = last_writer.find(a.s);
-            if (lw != last_writer.end() && lw->second != i) S.set(lw->second, i);
-            auto &rv = readers[a.s];
+            const int k = sidx(a.s);
+            if (std::find(written.begin(), written.end(), k) != written.end()) continue;
+            written.push_back(k);
+            if (last_writer[k] >= 0 && last_writer[k] != i) S.set(last_writer[k], i);
+            auto &rv = readers[k];
             for (int r : rv)
                 if (r != i) S.set(r, i);
             rv.clear();
-            last_writer[a.s] = i;
-            curv(a.s) += 1;
+            last_writer[k] = i;
+            cur[k] += 1;
+            touched[k] = 1;
         }
     }
+    S.cur.reserve(keys.size());
+    for (size_t k = 0; k < keys.size(); ++k)
+        if (touched[k]) S.cur.emplace(keys[k], cur[k]);
     return S;
 }
 
@@ -709,8 +731,11 @@ bool Planner::pass_fuse_round(const Persist &start) {
         std::vector<std::vector<int>> succ(nn);
         std::vector<int> indeg(nn, 0);
         for (int i = 0; i < S.n; ++i)
-            for (int j = 0; j < S.n; ++j)
-                if (S.edge(i, j)) {
+            for (int w = 0; w < S.words; ++w) {
+                uint64_t bits = S.adj[(size_t)i * S.words + w];
+                while (bits) {
+                    const int j = w * 64 + __builtin_ctzll(bits);
+                    bits &= bits - 1;
                     const int u = newid[i], v = newid[j];
                     if (u == v) continue;
                     if (std::find(succ[u].begin(), succ[u].end(), v) == succ[u].end()) {
@@ -718,6 +743,7 @@ bool Planner::pass_fuse_round(const Persist &start) {
                         indeg[v] += 1;
                     }
                 }
+            }
         std::priority_queue<std::pair<int, int>, std::vector<std::pair<int, int>>, std::greater<>> ready;
         for (int u = 0; u < nn; ++u)
             if (indeg[u] == 0) ready.push({key[u], u});
