@@ -1290,11 +1290,11 @@ __global__ __launch_bounds__(256) void k_bin_place(PartProg pp) {
 // touches lies in [8c - 1, 8c + 8] per axis, a 10^3 tile held in LDS for m
 // and the three mv channels.  LDS float atomics are slow on this hardware,
 // so the bin's particles (in chunks of kChunk) are first counting-sorted by
-// centre node (512 per block, integer LDS atomics); each thread then walks
-// a contiguous run of the sorted particles and sums, in registers, the
-// contributions to the 27 nodes its current centre node reaches (same
+// centre node (512 per block, integer LDS atomics); each thread then owns
+// whole centre nodes (two of the 512) and sums, in registers, the
+// contributions of their particles to the 27 nodes each reaches (same
 // per-contribution arithmetic as the direct scatter), adding them to the
-// tile only when the centre node changes.  The touched blocks among the 27
+// tile once per centre node.  The touched blocks among the 27
 // around c are activated (or were, per node, when ACT == AT_ACT_PER_NODE)
 // and the tile's non-zero values are added to the grid with one global
 // atomic per node and channel.
@@ -1352,10 +1352,8 @@ __global__ __launch_bounds__(256) void k_p2g_bins(PartProg pp) {
                 order[ncnt[lr >> 16] + (lr & 0xffff)] = (uint16_t)q;
             }
             __syncthreads();
-            // a contiguous run of sorted particles per thread
-            const int k = (n + blockDim.x - 1) / blockDim.x;
-            const int p0 = t * k < n ? t * k : n;
-            const int p1 = p0 + k < n ? p0 + k : n;
+            // each thread owns two centre nodes (t and t + 256) and sums all of
+            // their particles, so every centre node is added to the tile once
             float acc[27][4];
             int cb[3] = {0, 0, 0};
             bool open = false;
@@ -1374,59 +1372,63 @@ __global__ __launch_bounds__(256) void k_p2g_bins(PartProg pp) {
                             atomicAdd(&tile[3][nn], s4[3]);
                         }
             };
-            // the next particle's record is loaded while the current one is summed;
-            // one extra pass (pos == p1) flushes the last run
-            const int qlast = p1 > p0 ? p1 - 1 : p0;
-            float4 na = make_float4(0.f, 0.f, 0.f, 0.f), nb = na;
-            if (p0 < p1) {
-                const int q = order[p0];
-                na = rec[2 * q];
-                nb = rec[2 * q + 1];
-            }
-            for (int pos = p0; pos <= p1; ++pos) {
-                const float4 ra = na, rb = nb;
-                if (pos < p1) {
-                    const int q = order[pos + 1 < p1 ? pos + 1 : qlast];
+            for (int own = t; own < 512; own += blockDim.x) {
+                const int p0 = ncnt[own];
+                const int p1 = own + 1 < 512 ? ncnt[own + 1] : n;
+                // the next particle's record is loaded while the current one is summed;
+                // one extra pass (pos == p1) flushes the last run
+                const int qlast = p1 > p0 ? p1 - 1 : p0;
+                float4 na = make_float4(0.f, 0.f, 0.f, 0.f), nb = na;
+                if (p0 < p1) {
+                    const int q = order[p0];
                     na = rec[2 * q];
                     nb = rec[2 * q + 1];
                 }
-                const float x[3] = {ra.x, ra.y, ra.z};
-                const float v[3] = {ra.w, rb.x, rb.y};
-                const float mp = rb.z;
-                float w[3][3];
-                int base[3];
-                for (int c = 0; c < 3; ++c) base[c] = bspline(x[c] * pp.inv_dx_dst, w[c]);
-                const bool last = pos == p1;
-                if (open && (last || base[0] != cb[0] || base[1] != cb[1] || base[2] != cb[2])) {
-                    flush();
-                    open = false;
-                }
-                if (last) break;
-                if (!open) {
-#pragma unroll
-                    for (int e = 0; e < 27; ++e) acc[e][0] = acc[e][1] = acc[e][2] = acc[e][3] = 0.f;
-                    cb[0] = base[0]; cb[1] = base[1]; cb[2] = base[2];
-                    open = true;
-                }
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-#pragma unroll
-                    for (int bb = 0; bb < 3; ++bb) {
-                        const float wab = w[0][a] * w[1][bb];
-#pragma unroll
-                        for (int d = 0; d < 3; ++d) {
-                            if (ACT == AT_ACT_PER_NODE) {
-                                const int i = base[0] + a, j = base[1] + bb, kk = base[2] + d;
-                                if (i >= 0 && j >= 0 && kk >= 0 && i < N && j < N && kk < N)
-                                    activate_cell<KD>(g, ((int64_t)(i >> 3) * g.R + (j >> 3)) * g.R + (kk >> 3));
+                for (int pos = p0; pos <= p1; ++pos) {
+                    const float4 ra = na, rb = nb;
+                    if (pos < p1) {
+                        const int q = order[pos + 1 < p1 ? pos + 1 : qlast];
+                        na = rec[2 * q];
+                        nb = rec[2 * q + 1];
+                    }
+                    const float x[3] = {ra.x, ra.y, ra.z};
+                    const float v[3] = {ra.w, rb.x, rb.y};
+                    const float mp = rb.z;
+                    float w[3][3];
+                    int base[3];
+                    for (int c = 0; c < 3; ++c) base[c] = bspline(x[c] * pp.inv_dx_dst, w[c]);
+                    const bool last = pos == p1;
+                    if (open && (last || base[0] != cb[0] || base[1] != cb[1] || base[2] != cb[2])) {
+                        flush();
+                        open = false;
+                    }
+                    if (last) break;
+                    if (!open) {
+    #pragma unroll
+                        for (int e = 0; e < 27; ++e) acc[e][0] = acc[e][1] = acc[e][2] = acc[e][3] = 0.f;
+                        cb[0] = base[0]; cb[1] = base[1]; cb[2] = base[2];
+                        open = true;
+                    }
+    #pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+    #pragma unroll
+                        for (int bb = 0; bb < 3; ++bb) {
+                            const float wab = w[0][a] * w[1][bb];
+    #pragma unroll
+                            for (int d = 0; d < 3; ++d) {
+                                if (ACT == AT_ACT_PER_NODE) {
+                                    const int i = base[0] + a, j = base[1] + bb, kk = base[2] + d;
+                                    if (i >= 0 && j >= 0 && kk >= 0 && i < N && j < N && kk < N)
+                                        activate_cell<KD>(g, ((int64_t)(i >> 3) * g.R + (j >> 3)) * g.R + (kk >> 3));
+                                }
+                                const float wt = wab * w[2][d];
+                                const float tm = wt * mp;
+                                float *s4 = acc[(a * 3 + bb) * 3 + d];
+                                s4[0] = s4[0] + tm;
+                                s4[1] = s4[1] + tm * v[0];
+                                s4[2] = s4[2] + tm * v[1];
+                                s4[3] = s4[3] + tm * v[2];
                             }
-                            const float wt = wab * w[2][d];
-                            const float tm = wt * mp;
-                            float *s4 = acc[(a * 3 + bb) * 3 + d];
-                            s4[0] = s4[0] + tm;
-                            s4[1] = s4[1] + tm * v[0];
-                            s4[2] = s4[2] + tm * v[1];
-                            s4[3] = s4[3] + tm * v[2];
                         }
                     }
                 }
