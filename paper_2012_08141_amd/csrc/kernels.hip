@@ -1291,10 +1291,9 @@ __global__ __launch_bounds__(256) void k_bin_place(PartProg pp) {
 // and the three mv channels.  LDS float atomics are slow on this hardware,
 // so the bin's particles (in chunks of kChunk) are first counting-sorted by
 // centre node (512 per block, integer LDS atomics); each thread then owns
-// whole centre nodes (two of the 512) and sums, in registers, the
-// contributions of their particles to the 27 nodes each reaches (same
-// per-contribution arithmetic as the direct scatter), adding them to the
-// tile once per centre node.  The touched blocks among the 27
+// two k-adjacent centre nodes and sums, in registers, the contributions of
+// their particles to the 3 x 3 x 4 nodes they reach (same per-contribution
+// arithmetic as the direct scatter), adding them to the tile once.  The touched blocks among the 27
 // around c are activated (or were, per node, when ACT == AT_ACT_PER_NODE)
 // and the tile's non-zero values are added to the grid with one global
 // atomic per node and channel.
@@ -1352,86 +1351,102 @@ __global__ __launch_bounds__(256) void k_p2g_bins(PartProg pp) {
                 order[ncnt[lr >> 16] + (lr & 0xffff)] = (uint16_t)q;
             }
             __syncthreads();
-            // each thread owns two centre nodes (t and t + 256) and sums all of
-            // their particles, so every centre node is added to the tile once
-            float acc[27][4];
-            int cb[3] = {0, 0, 0};
-            bool open = false;
-            auto flush = [&]() {
-                for (int a = 0; a < 3; ++a)
-                    for (int bb = 0; bb < 3; ++bb)
-                        for (int d = 0; d < 3; ++d) {
-                            const int i = cb[0] + a, j = cb[1] + bb, kk = cb[2] + d;
-                            if (i < 0 || j < 0 || kk < 0 || i >= N || j >= N || kk >= N) continue;
+            // each thread owns two k-adjacent centre nodes (2p and 2p + 1 of the
+            // block's 512) and sums their particles in registers over a window
+            // of three k-planes of 3 x 3 nodes that slides by one plane between
+            // them, so the 18 nodes the two share are added to the tile once
+            for (int pr = t; pr < 256; pr += blockDim.x) {
+                const int li = pr >> 5, lj = (pr >> 2) & 7, lk0 = (pr & 3) * 2;
+                const int bi = ci * kBS + li - 1, bj = cj * kBS + lj - 1;   // base i, j of both
+                int kb = ck * kBS + lk0 - 1;                                // base k of the first
+                float acc[3][9][4];                                         // [k plane][a * 3 + b][channel]
+                bool touched[3] = {false, false, false};
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+#pragma unroll
+                    for (int e = 0; e < 9; ++e) acc[d][e][0] = acc[d][e][1] = acc[d][e][2] = acc[d][e][3] = 0.f;
+                auto flush_plane = [&](int d) {
+                    const int kk = kb + d;
+                    if (!touched[d] || kk < 0 || kk >= N) return;
+                    for (int a = 0; a < 3; ++a)
+                        for (int bb = 0; bb < 3; ++bb) {
+                            const int i = bi + a, j = bj + bb;
+                            if (i < 0 || j < 0 || i >= N || j >= N) continue;
                             tflag[((i >> 3) - ci + 1) * 9 + ((j >> 3) - cj + 1) * 3 + ((kk >> 3) - ck + 1)] = 1;
                             const int nn = ((i - oi) * kTile + (j - oj)) * kTile + (kk - ok);
-                            const float *s4 = acc[(a * 3 + bb) * 3 + d];
-                            atomicAdd(&tile[0][nn], s4[0]);
-                            atomicAdd(&tile[1][nn], s4[1]);
-                            atomicAdd(&tile[2][nn], s4[2]);
-                            atomicAdd(&tile[3][nn], s4[3]);
+                            const float *s4 = acc[d][a * 3 + bb];
+                            if (s4[0] != 0.f) atomicAdd(&tile[0][nn], s4[0]);
+                            if (s4[1] != 0.f) atomicAdd(&tile[1][nn], s4[1]);
+                            if (s4[2] != 0.f) atomicAdd(&tile[2][nn], s4[2]);
+                            if (s4[3] != 0.f) atomicAdd(&tile[3][nn], s4[3]);
                         }
-            };
-            for (int own = t; own < 512; own += blockDim.x) {
-                const int p0 = ncnt[own];
-                const int p1 = own + 1 < 512 ? ncnt[own + 1] : n;
-                // the next particle's record is loaded while the current one is summed;
-                // one extra pass (pos == p1) flushes the last run
-                const int qlast = p1 > p0 ? p1 - 1 : p0;
-                float4 na = make_float4(0.f, 0.f, 0.f, 0.f), nb = na;
-                if (p0 < p1) {
-                    const int q = order[p0];
-                    na = rec[2 * q];
-                    nb = rec[2 * q + 1];
-                }
-                for (int pos = p0; pos <= p1; ++pos) {
-                    const float4 ra = na, rb = nb;
-                    if (pos < p1) {
-                        const int q = order[pos + 1 < p1 ? pos + 1 : qlast];
+                };
+                for (int h = 0; h < 2; ++h) {
+                    const int own = pr * 2 + h;   // = (li * 8 + lj) * 8 + lk0 + h
+                    const int p0 = ncnt[own];
+                    const int p1 = own + 1 < 512 ? ncnt[own + 1] : n;
+                    if (p0 < p1) touched[0] = touched[1] = touched[2] = true;
+                    // the next particle's record is loaded while the current one is summed
+                    float4 na = make_float4(0.f, 0.f, 0.f, 0.f), nb = na;
+                    if (p0 < p1) {
+                        const int q = order[p0];
                         na = rec[2 * q];
                         nb = rec[2 * q + 1];
                     }
-                    const float x[3] = {ra.x, ra.y, ra.z};
-                    const float v[3] = {ra.w, rb.x, rb.y};
-                    const float mp = rb.z;
-                    float w[3][3];
-                    int base[3];
-                    for (int c = 0; c < 3; ++c) base[c] = bspline(x[c] * pp.inv_dx_dst, w[c]);
-                    const bool last = pos == p1;
-                    if (open && (last || base[0] != cb[0] || base[1] != cb[1] || base[2] != cb[2])) {
-                        flush();
-                        open = false;
-                    }
-                    if (last) break;
-                    if (!open) {
-    #pragma unroll
-                        for (int e = 0; e < 27; ++e) acc[e][0] = acc[e][1] = acc[e][2] = acc[e][3] = 0.f;
-                        cb[0] = base[0]; cb[1] = base[1]; cb[2] = base[2];
-                        open = true;
-                    }
-    #pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-    #pragma unroll
-                        for (int bb = 0; bb < 3; ++bb) {
-                            const float wab = w[0][a] * w[1][bb];
-    #pragma unroll
-                            for (int d = 0; d < 3; ++d) {
-                                if (ACT == AT_ACT_PER_NODE) {
-                                    const int i = base[0] + a, j = base[1] + bb, kk = base[2] + d;
-                                    if (i >= 0 && j >= 0 && kk >= 0 && i < N && j < N && kk < N)
-                                        activate_cell<KD>(g, ((int64_t)(i >> 3) * g.R + (j >> 3)) * g.R + (kk >> 3));
+                    for (int pos = p0; pos < p1; ++pos) {
+                        const float4 ra = na, rb = nb;
+                        const int q = order[pos + 1 < p1 ? pos + 1 : pos];
+                        na = rec[2 * q];
+                        nb = rec[2 * q + 1];
+                        const float x[3] = {ra.x, ra.y, ra.z};
+                        const float v[3] = {ra.w, rb.x, rb.y};
+                        const float mp = rb.z;
+                        float w[3][3];
+                        int base[3];
+                        for (int c = 0; c < 3; ++c) base[c] = bspline(x[c] * pp.inv_dx_dst, w[c]);
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+#pragma unroll
+                            for (int bb = 0; bb < 3; ++bb) {
+                                const float wab = w[0][a] * w[1][bb];
+#pragma unroll
+                                for (int d = 0; d < 3; ++d) {
+                                    if (ACT == AT_ACT_PER_NODE) {
+                                        const int i = base[0] + a, j = base[1] + bb, kk = base[2] + d;
+                                        if (i >= 0 && j >= 0 && kk >= 0 && i < N && j < N && kk < N)
+                                            activate_cell<KD>(g, ((int64_t)(i >> 3) * g.R + (j >> 3)) * g.R + (kk >> 3));
+                                    }
+                                    const float wt = wab * w[2][d];
+                                    const float tm = wt * mp;
+                                    float *s4 = acc[d][a * 3 + bb];
+                                    s4[0] = s4[0] + tm;
+                                    s4[1] = s4[1] + tm * v[0];
+                                    s4[2] = s4[2] + tm * v[1];
+                                    s4[3] = s4[3] + tm * v[2];
                                 }
-                                const float wt = wab * w[2][d];
-                                const float tm = wt * mp;
-                                float *s4 = acc[(a * 3 + bb) * 3 + d];
-                                s4[0] = s4[0] + tm;
-                                s4[1] = s4[1] + tm * v[0];
-                                s4[2] = s4[2] + tm * v[1];
-                                s4[3] = s4[3] + tm * v[2];
                             }
                         }
                     }
+                    if (h == 0) {
+                        // the first centre node's lowest plane is complete; slide
+                        flush_plane(0);
+#pragma unroll
+                        for (int e = 0; e < 9; ++e)
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) {
+                                acc[0][e][c] = acc[1][e][c];
+                                acc[1][e][c] = acc[2][e][c];
+                                acc[2][e][c] = 0.f;
+                            }
+                        touched[0] = touched[1];
+                        touched[1] = touched[2];
+                        touched[2] = false;
+                        kb += 1;
+                    }
                 }
+                flush_plane(0);
+                flush_plane(1);
+                flush_plane(2);
             }
             __syncthreads();
         }
