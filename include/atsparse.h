@@ -65,7 +65,7 @@ typedef struct at_grid_desc {
     int32_t capacity_blocks;  /* pointer root: pool size in leaves (<= R^3);
                                  bitmask root: ignored (R^3) */
     int32_t particle_capacity; /* particles a scatter into this grid may bin at
-                                  once (workspace of 40 B each plus 24 B per root
+                                  once (workspace of 44 B each plus 24 B per root
                                   cell); a scatter of more particles, or any
                                   scatter when 0, adds straight into global
                                   memory with atomics instead of binning */
@@ -317,6 +317,14 @@ at_status at_flush(at_stats *stats, hipStream_t stream);
  * or 4; each wavefront sweeps its own blocks (a tuning knob; results are
  * identical).  Read when at_batch_jacobi enqueues (or a graph captures). */
 #define AT_OPTION_BATCH_WAVES 7
+/* Gathers through scatter bins: 1 (default) or 0.  A G2P whose source
+ * grid's last binned scatter (since the grid was created or cleared) had the
+ * same particle count gathers per bin from an LDS tile instead of per
+ * particle from the grid; results are bit-identical either way.  A fused
+ * node whose gather goes through bins runs its other steps (advection,
+ * scatter) as one more dispatch in particle order.  Read when a node
+ * executes. */
+#define AT_OPTION_G2P_BINS 8
 at_status at_set_option(int32_t option, int64_t value);
 at_status at_get_option(int32_t option, int64_t *value);
 

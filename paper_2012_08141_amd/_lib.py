@@ -30,6 +30,7 @@ AT_OPTION_MAX_FUSE_PER_TASK, AT_OPTION_FLUSH_PERIOD, AT_OPTION_OPT_FLAGS, AT_OPT
 AT_OPTION_STRUCT_FOR_WORKGROUPS = 5
 AT_OPTION_STRUCT_FOR_KERNEL = 6
 AT_OPTION_BATCH_WAVES = 7
+AT_OPTION_G2P_BINS = 8
 
 
 class AtGridDesc(ctypes.Structure):

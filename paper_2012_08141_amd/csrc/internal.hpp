@@ -13,7 +13,11 @@ constexpr int kBS = 8;      // leaf block edge
 constexpr int kBV = 512;    // voxels per leaf block
 
 // Words of the per-grid device header (first 256 bytes of the grid buffer).
-enum : int { HDR_COUNT = 0, HDR_BUMP = 1, HDR_ERR = 2, HDR_SCRATCH = 3, HDR_NBINS = 4, HDR_NAPPEND = 5 };
+enum : int {
+    HDR_COUNT = 0, HDR_BUMP = 1, HDR_ERR = 2, HDR_SCRATCH = 3, HDR_NBINS = 4, HDR_NAPPEND = 5,
+    HDR_NOUT_ACC = 6,   // outliers listed so far by the scatter's first pass
+    HDR_NOUT = 7        // outliers of the last binned scatter (pout[0..NOUT))
+};
 enum : int32_t { ERR_CAPACITY = 1, ERR_SPIN = 2 };
 
 // Pointer-root cell states besides a valid slot (>= 0).
@@ -40,7 +44,8 @@ struct GridDev {
     int4 *pbins;        // [R^3] non-empty cells: {cell, first, count, 0}; count in hdr[HDR_NBINS]
                         // (while ranking: cells appended in .x, count in hdr[HDR_NAPPEND])
     int2 *pkr;          // [pcap] per particle: {root cell of its centre node or -1, rank in that cell}
-    float4 *pstage;     // [pcap][2] particle records {x0, x1, x2, v0}, {v1, v2, m, 0} grouped by cell
+    float4 *pstage;     // [pcap][2] particle records {x0, x1, x2, v0}, {v1, v2, m, index} grouped by cell
+    int32_t *pout;      // [pcap] particles whose centre node lies outside the domain (scattered directly)
 };
 
 constexpr int kScanFlags = 1024;   // = maximum workgroups of one list generation
@@ -77,6 +82,7 @@ struct PartProg {
     float inv_dx_dst;      // scatter grid
     int32_t ch_vsrc;       // gather: velocity channels v0..v0+2 of gsrc
     int32_t ch_m, ch_mv;   // scatter: m and mv0..mv0+2 of gdst
+    int32_t g2p_bins;      // gather through gsrc's bins (its last binned scatter had np particles)
     GridDev gsrc, gdst;
 };
 
@@ -132,4 +138,5 @@ struct at_grid_s {
     uint32_t listgen_epoch;   // distinguishes list generation launches (never 0)
     size_t bytes;
     int32_t list_cap;
+    int64_t bins_np;    // particles of the last binned scatter into this grid (0: none since clear)
 };

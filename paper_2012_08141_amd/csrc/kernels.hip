@@ -1035,11 +1035,170 @@ __device__ __forceinline__ int bspline(float X, float w[3]) {
     return base;
 }
 
+// Edge of the node tile around one root cell (the block plus one node each
+// side: every node a particle binned to the cell touches), its node count,
+// and the particles the binned scatter sorts at once.
+constexpr int kTile = 10, kTile3 = 1000, kChunk = 4096;
+
+// s[x * 4 + y * 2 + z] chosen with selects: an array indexed at run time
+// would be placed in scratch memory.
+__device__ __forceinline__ int32_t pick8(const int32_t s[8], bool x, bool y, bool z) {
+    const int32_t a0 = z ? s[1] : s[0], a1 = z ? s[3] : s[2], a2 = z ? s[5] : s[4], a3 = z ? s[7] : s[6];
+    const int32_t b0 = y ? a1 : a0, b1 = y ? a3 : a2;
+    return x ? b1 : b0;
+}
+
+// Gather (G2P) of one particle straight from the grid: v = sum over its 27
+// nodes, in (a, b, d) order, of w * node value (0 outside the domain or in an
+// inactive block).
+template <int KS>
+__device__ __forceinline__ void gather_direct(const PartProg &pp, const float x[3], float v[3]) {
+    const GridDev &g = pp.gsrc;
+    const int N = g.R * kBS;
+    float w[3][3];
+    int base[3];
+    for (int c = 0; c < 3; ++c) base[c] = bspline(x[c] * pp.inv_dx_src, w[c]);
+    const float *V0 = chan(g, pp.ch_vsrc), *V1 = chan(g, pp.ch_vsrc + 1), *V2 = chan(g, pp.ch_vsrc + 2);
+    // slots of the (at most) 2x2x2 blocks the 27 nodes span, looked up once
+    const int blo[3] = {base[0] >> 3, base[1] >> 3, base[2] >> 3};
+    int32_t bs[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int ci = blo[0] + (e >> 2), cj = blo[1] + ((e >> 1) & 1), ck = blo[2] + (e & 1);
+        const bool in = ci >= 0 && cj >= 0 && ck >= 0 && ci < g.R && cj < g.R && ck < g.R;
+        bs[e] = in ? slot_of<KS>(g, ((int64_t)ci * g.R + cj) * g.R + ck) : -1;
+    }
+    // a row of 3 nodes along k inside one block is read as one 12-byte load per channel
+    const bool krow = (base[2] & 7) <= 5 && base[2] >= 0;
+    float acc[3] = {0.f, 0.f, 0.f};
+    for (int a = 0; a < 3; ++a) {
+        const int i = base[0] + a;
+        for (int b = 0; b < 3; ++b) {
+            const int j = base[1] + b;
+            const float wab = w[0][a] * w[1][b];
+            const bool ij = i >= 0 && j >= 0 && i < N && j < N;
+            float n[3][3];
+            if (krow) {
+                const int32_t s = ij ? pick8(bs, (i >> 3) != blo[0], (j >> 3) != blo[1], false) : -1;
+                float3 r0 = make_float3(0.f, 0.f, 0.f), r1 = r0, r2 = r0;
+                if (s >= 0) {
+                    const int64_t o = (int64_t)s * kBV + (i & 7) * 64 + (j & 7) * 8 + (base[2] & 7);
+                    r0 = *reinterpret_cast<const float3 *>(V0 + o);
+                    r1 = *reinterpret_cast<const float3 *>(V1 + o);
+                    r2 = *reinterpret_cast<const float3 *>(V2 + o);
+                }
+                n[0][0] = r0.x; n[1][0] = r0.y; n[2][0] = r0.z;
+                n[0][1] = r1.x; n[1][1] = r1.y; n[2][1] = r1.z;
+                n[0][2] = r2.x; n[1][2] = r2.y; n[2][2] = r2.z;
+            } else {
+                for (int d = 0; d < 3; ++d) {
+                    const int k = base[2] + d;
+                    n[d][0] = n[d][1] = n[d][2] = 0.f;
+                    if (ij && k >= 0 && k < N) {
+                        const int32_t s = pick8(bs, (i >> 3) != blo[0], (j >> 3) != blo[1], (k >> 3) != blo[2]);
+                        if (s >= 0) {
+                            const int64_t o = (int64_t)s * kBV + (i & 7) * 64 + (j & 7) * 8 + (k & 7);
+                            n[d][0] = V0[o]; n[d][1] = V1[o]; n[d][2] = V2[o];
+                        }
+                    }
+                }
+            }
+            for (int d = 0; d < 3; ++d) {
+                const float wt = wab * w[2][d];
+                acc[0] = acc[0] + wt * n[d][0];
+                acc[1] = acc[1] + wt * n[d][1];
+                acc[2] = acc[2] + wt * n[d][2];
+            }
+        }
+    }
+    v[0] = acc[0]; v[1] = acc[1]; v[2] = acc[2];
+}
+
+// Scatter (P2G) of one particle straight into the grid with fp32 atomics:
+// m += w*m_p, mv_c += (w*m_p)*v_c at each of its 27 nodes inside the domain,
+// activating per node, per touched block, or not at all (ACT).
+template <int KD, int ACT>
+__device__ __forceinline__ void scatter_direct(const PartProg &pp, const int base[3], const float w[3][3],
+                                               const float v[3], float mp) {
+    const GridDev &g = pp.gdst;
+    const int N = g.R * kBS;
+    float *M = chan(g, pp.ch_m), *MV0 = chan(g, pp.ch_mv), *MV1 = chan(g, pp.ch_mv + 1), *MV2 = chan(g, pp.ch_mv + 2);
+    // per-block activation: the touched nodes span at most 2 blocks per axis
+    int32_t bslot[8];
+    const int blo[3] = {base[0] >> 3, base[1] >> 3, base[2] >> 3};
+    if (ACT == AT_ACT_PER_BLOCK || ACT == AT_ACT_NONE) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int a = e >> 2, b = (e >> 1) & 1, d = e & 1;
+            const int ci = blo[0] + a, cj = blo[1] + b, ck = blo[2] + d;
+            bslot[e] = -1;
+            const bool used = (a == 0 || ((base[0] + 2) >> 3) != blo[0]) &&
+                              (b == 0 || ((base[1] + 2) >> 3) != blo[1]) &&
+                              (d == 0 || ((base[2] + 2) >> 3) != blo[2]);
+            if (!used || ci < 0 || cj < 0 || ck < 0 || ci >= g.R || cj >= g.R || ck >= g.R) continue;
+            const int64_t cell = ((int64_t)ci * g.R + cj) * g.R + ck;
+            bslot[e] = ACT == AT_ACT_NONE ? slot_of<KD>(g, cell) : activate_cell<KD>(g, cell);
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        const int i = base[0] + a;
+        for (int b = 0; b < 3; ++b) {
+            const int j = base[1] + b;
+            const float wab = w[0][a] * w[1][b];
+            for (int d = 0; d < 3; ++d) {
+                const int k = base[2] + d;
+                if (i < 0 || j < 0 || k < 0 || i >= N || j >= N || k >= N) continue;
+                int32_t s;
+                if (ACT == AT_ACT_PER_BLOCK || ACT == AT_ACT_NONE) {
+                    s = pick8(bslot, (i >> 3) != blo[0], (j >> 3) != blo[1], (k >> 3) != blo[2]);
+                } else {
+                    s = activate_cell<KD>(g, ((int64_t)(i >> 3) * g.R + (j >> 3)) * g.R + (k >> 3));
+                }
+                if (s < 0) continue;
+                const int64_t o = (int64_t)s * kBV + (i & 7) * 64 + (j & 7) * 8 + (k & 7);
+                const float wt = wab * w[2][d];
+                const float tm = wt * mp;
+                unsafeAtomicAdd(M + o, tm);
+                unsafeAtomicAdd(MV0 + o, tm * v[0]);
+                unsafeAtomicAdd(MV1 + o, tm * v[1]);
+                unsafeAtomicAdd(MV2 + o, tm * v[2]);
+            }
+        }
+    }
+}
+
+// What follows the gather for particle p: advection, then the scatter (or,
+// with BIN, its first pass: the root cell of the centre node, base + 1 per
+// axis; a particle whose centre node lies outside the domain scatters
+// directly and is listed as an outlier of the destination's bins).
+template <int KD, uint32_t STEPS, int ACT, bool BIN>
+__device__ __forceinline__ void after_gather(const PartProg &pp, int64_t p, float x[3], const float v[3]) {
+    const int64_t np = pp.np;
+    if (STEPS & PS_ADVECT) {
+        for (int c = 0; c < 3; ++c) x[c] = x[c] + pp.dt * v[c];
+        pp.x[p] = x[0]; pp.x[np + p] = x[1]; pp.x[2 * np + p] = x[2];
+    }
+    if (STEPS & PS_P2G) {
+        const GridDev &g = pp.gdst;
+        const int N = g.R * kBS;
+        float w[3][3];
+        int base[3];
+        for (int c = 0; c < 3; ++c) base[c] = bspline(x[c] * pp.inv_dx_dst, w[c]);
+        if (BIN) {
+            const int hi = base[0] + 1, hj = base[1] + 1, hk = base[2] + 1;
+            if (hi >= 0 && hj >= 0 && hk >= 0 && hi < N && hj < N && hk < N) {
+                g.pkr[p] = make_int2(((hi >> 3) * g.R + (hj >> 3)) * g.R + (hk >> 3), 0);
+                return;
+            }
+            g.pkr[p] = make_int2(-1, 0);
+            g.pout[atomicAdd(&g.hdr[HDR_NOUT_ACC], 1)] = (int32_t)p;
+        }
+        scatter_direct<KD, ACT>(pp, base, w, v, pp.m[p]);
+    }
+}
+
 // One thread per particle: optional gather (G2P), advection and scatter
-// (P2G).  With BIN the scatter only records, for each particle whose centre
-// node (base + 1 per axis) lies in the domain, that node's root cell
-// (k_bin_rank, k_bin_scan, k_bin_place and k_p2g_bins finish the scatter);
-// the others scatter directly.
+// (P2G), in index order.
 template <int KS, int KD, uint32_t STEPS, int ACT, bool BIN>
 __global__ __launch_bounds__(256) void k_particles(PartProg pp) {
     const int64_t np = pp.np;
@@ -1048,134 +1207,104 @@ __global__ __launch_bounds__(256) void k_particles(PartProg pp) {
         float x[3] = {pp.x[p], pp.x[np + p], pp.x[2 * np + p]};
         float v[3];
         if (STEPS & PS_G2P) {
-            const GridDev &g = pp.gsrc;
-            const int N = g.R * kBS;
-            float w[3][3];
-            int base[3];
-            for (int c = 0; c < 3; ++c) base[c] = bspline(x[c] * pp.inv_dx_src, w[c]);
-            const float *V0 = chan(g, pp.ch_vsrc), *V1 = chan(g, pp.ch_vsrc + 1), *V2 = chan(g, pp.ch_vsrc + 2);
-            // slots of the (at most) 2x2x2 blocks the 27 nodes span, looked up once
-            const int blo[3] = {base[0] >> 3, base[1] >> 3, base[2] >> 3};
-            int32_t bs[2][2][2];
-            for (int a = 0; a < 2; ++a)
-                for (int b = 0; b < 2; ++b)
-                    for (int d = 0; d < 2; ++d) {
-                        const int ci = blo[0] + a, cj = blo[1] + b, ck = blo[2] + d;
-                        const bool in = ci >= 0 && cj >= 0 && ck >= 0 && ci < g.R && cj < g.R && ck < g.R;
-                        bs[a][b][d] = in ? slot_of<KS>(g, ((int64_t)ci * g.R + cj) * g.R + ck) : -1;
-                    }
-            // a row of 3 nodes along k inside one block is read as one 12-byte load per channel
-            const bool krow = (base[2] & 7) <= 5 && base[2] >= 0;
-            float acc[3] = {0.f, 0.f, 0.f};
-            for (int a = 0; a < 3; ++a) {
-                const int i = base[0] + a;
-                for (int b = 0; b < 3; ++b) {
-                    const int j = base[1] + b;
-                    const float wab = w[0][a] * w[1][b];
-                    const bool ij = i >= 0 && j >= 0 && i < N && j < N;
-                    float n[3][3];
-                    if (krow) {
-                        const int32_t s = ij ? bs[(i >> 3) - blo[0]][(j >> 3) - blo[1]][0] : -1;
-                        float3 r0 = make_float3(0.f, 0.f, 0.f), r1 = r0, r2 = r0;
-                        if (s >= 0) {
-                            const int64_t o = (int64_t)s * kBV + (i & 7) * 64 + (j & 7) * 8 + (base[2] & 7);
-                            r0 = *reinterpret_cast<const float3 *>(V0 + o);
-                            r1 = *reinterpret_cast<const float3 *>(V1 + o);
-                            r2 = *reinterpret_cast<const float3 *>(V2 + o);
-                        }
-                        n[0][0] = r0.x; n[1][0] = r0.y; n[2][0] = r0.z;
-                        n[0][1] = r1.x; n[1][1] = r1.y; n[2][1] = r1.z;
-                        n[0][2] = r2.x; n[1][2] = r2.y; n[2][2] = r2.z;
-                    } else {
-                        for (int d = 0; d < 3; ++d) {
-                            const int k = base[2] + d;
-                            n[d][0] = n[d][1] = n[d][2] = 0.f;
-                            if (ij && k >= 0 && k < N) {
-                                const int32_t s = bs[(i >> 3) - blo[0]][(j >> 3) - blo[1]][(k >> 3) - blo[2]];
-                                if (s >= 0) {
-                                    const int64_t o = (int64_t)s * kBV + (i & 7) * 64 + (j & 7) * 8 + (k & 7);
-                                    n[d][0] = V0[o]; n[d][1] = V1[o]; n[d][2] = V2[o];
-                                }
-                            }
-                        }
-                    }
-                    for (int d = 0; d < 3; ++d) {
-                        const float wt = wab * w[2][d];
-                        acc[0] = acc[0] + wt * n[d][0];
-                        acc[1] = acc[1] + wt * n[d][1];
-                        acc[2] = acc[2] + wt * n[d][2];
-                    }
-                }
-            }
-            v[0] = acc[0]; v[1] = acc[1]; v[2] = acc[2];
+            gather_direct<KS>(pp, x, v);
             pp.v[p] = v[0]; pp.v[np + p] = v[1]; pp.v[2 * np + p] = v[2];
         } else {
             v[0] = pp.v[p]; v[1] = pp.v[np + p]; v[2] = pp.v[2 * np + p];
         }
-        if (STEPS & PS_ADVECT) {
-            for (int c = 0; c < 3; ++c) x[c] = x[c] + pp.dt * v[c];
-            pp.x[p] = x[0]; pp.x[np + p] = x[1]; pp.x[2 * np + p] = x[2];
+        after_gather<KD, STEPS, ACT, BIN>(pp, p, x, v);
+    }
+}
+
+// Gather through the bins of the source grid's last binned scatter (the
+// runtime uses them only when that scatter had the same particle count, so
+// the bins hold every particle index once; the source's outliers are listed
+// apart).  One workgroup per bin loads the 10^3 tile of the three velocity
+// channels around the bin's block (0 outside the domain or in an inactive
+// block) into LDS; each of the bin's particles reads its current position
+// and, when its 27 nodes lie in the tile, gathers from LDS in the same
+// (a, b, d) order and arithmetic as gather_direct, so the result is
+// bit-identical.  A particle that has left the tile since it was binned, and
+// every outlier, gathers directly.  Only v is written: particles come in bin
+// order, so the steps that follow a gather in a fused node (advection, the
+// scatter's first pass) run as a second, index-ordered pass, where their
+// writes stay coalesced.
+template <int KS>
+__global__ __launch_bounds__(256) void k_g2p_bins(PartProg pp) {
+    __shared__ float vt[3][kTile3];
+    __shared__ int32_t bsl[27];
+    const GridDev &S = pp.gsrc;
+    const int N = S.R * kBS;
+    const int64_t np = pp.np;
+    const int t = threadIdx.x;
+    const int nb = S.hdr[HDR_NBINS];
+    const int nout = S.hdr[HDR_NOUT];
+    const int nob = (nout + (int)blockDim.x - 1) / (int)blockDim.x;
+    const float *V0 = chan(S, pp.ch_vsrc), *V1 = chan(S, pp.ch_vsrc + 1), *V2 = chan(S, pp.ch_vsrc + 2);
+    for (int b = blockIdx.x; b < nb + nob; b += gridDim.x) {
+        if (b >= nb) {
+            const int q = (b - nb) * (int)blockDim.x + t;
+            if (q < nout) {
+                const int64_t p = S.pout[q];
+                const float x[3] = {pp.x[p], pp.x[np + p], pp.x[2 * np + p]};
+                float v[3];
+                gather_direct<KS>(pp, x, v);
+                pp.v[p] = v[0]; pp.v[np + p] = v[1]; pp.v[2 * np + p] = v[2];
+            }
+            continue;
         }
-        if (STEPS & PS_P2G) {
-            const GridDev &g = pp.gdst;
-            const int N = g.R * kBS;
+        const int4 bin = S.pbins[b];
+        int ci, cj, ck;
+        cell_coords(S, bin.x, ci, cj, ck);
+        const int oi = ci * kBS - 1, oj = cj * kBS - 1, ok = ck * kBS - 1;
+        if (t < 27) {
+            const int bi = ci - 1 + t / 9, bj = cj - 1 + (t / 3) % 3, bk = ck - 1 + t % 3;
+            const bool in = bi >= 0 && bj >= 0 && bk >= 0 && bi < S.R && bj < S.R && bk < S.R;
+            bsl[t] = in ? slot_of<KS>(S, ((int64_t)bi * S.R + bj) * S.R + bk) : -1;
+        }
+        __syncthreads();
+        for (int nn = t; nn < kTile3; nn += blockDim.x) {
+            const int i = oi + nn / 100, j = oj + (nn / 10) % 10, k = ok + nn % 10;
+            float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+            if (i >= 0 && j >= 0 && k >= 0 && i < N && j < N && k < N) {
+                const int32_t sl = bsl[((i >> 3) - ci + 1) * 9 + ((j >> 3) - cj + 1) * 3 + ((k >> 3) - ck + 1)];
+                if (sl >= 0) {
+                    const int64_t o = (int64_t)sl * kBV + (i & 7) * 64 + (j & 7) * 8 + (k & 7);
+                    a0 = V0[o]; a1 = V1[o]; a2 = V2[o];
+                }
+            }
+            vt[0][nn] = a0; vt[1][nn] = a1; vt[2][nn] = a2;
+        }
+        __syncthreads();
+        for (int q = t; q < bin.z; q += blockDim.x) {
+            const int64_t p = __float_as_int(S.pstage[2 * ((int64_t)bin.y + q) + 1].w);
+            const float x[3] = {pp.x[p], pp.x[np + p], pp.x[2 * np + p]};
             float w[3][3];
             int base[3];
-            for (int c = 0; c < 3; ++c) base[c] = bspline(x[c] * pp.inv_dx_dst, w[c]);
-            if (BIN) {
-                const int hi = base[0] + 1, hj = base[1] + 1, hk = base[2] + 1;
-                if (hi >= 0 && hj >= 0 && hk >= 0 && hi < N && hj < N && hk < N) {
-                    g.pkr[p] = make_int2(((hi >> 3) * g.R + (hj >> 3)) * g.R + (hk >> 3), 0);
-                    continue;
-                }
-                g.pkr[p] = make_int2(-1, 0);
-            }
-            const float mp = pp.m[p];
-            float *M = chan(g, pp.ch_m), *MV0 = chan(g, pp.ch_mv), *MV1 = chan(g, pp.ch_mv + 1),
-                  *MV2 = chan(g, pp.ch_mv + 2);
-            // per-block activation: the touched nodes span at most 2 blocks per axis
-            int32_t bslot[2][2][2];
-            const int blo[3] = {base[0] >> 3, base[1] >> 3, base[2] >> 3};
-            if (ACT == AT_ACT_PER_BLOCK || ACT == AT_ACT_NONE) {
-                for (int a = 0; a < 2; ++a)
-                    for (int b = 0; b < 2; ++b)
-                        for (int d = 0; d < 2; ++d) {
-                            const int ci = blo[0] + a, cj = blo[1] + b, ck = blo[2] + d;
-                            bslot[a][b][d] = -1;
-                            const bool used = (a == 0 || ((base[0] + 2) >> 3) != blo[0]) &&
-                                              (b == 0 || ((base[1] + 2) >> 3) != blo[1]) &&
-                                              (d == 0 || ((base[2] + 2) >> 3) != blo[2]);
-                            if (!used || ci < 0 || cj < 0 || ck < 0 || ci >= g.R || cj >= g.R || ck >= g.R) continue;
-                            const int64_t cell = ((int64_t)ci * g.R + cj) * g.R + ck;
-                            bslot[a][b][d] = ACT == AT_ACT_NONE ? slot_of<KD>(g, cell) : activate_cell<KD>(g, cell);
+            for (int c = 0; c < 3; ++c) base[c] = bspline(x[c] * pp.inv_dx_src, w[c]);
+            const int ri = base[0] - oi, rj = base[1] - oj, rk = base[2] - ok;
+            float v[3];
+            if ((unsigned)ri < 8u && (unsigned)rj < 8u && (unsigned)rk < 8u) {
+                float acc[3] = {0.f, 0.f, 0.f};
+                for (int a = 0; a < 3; ++a) {
+                    for (int bb = 0; bb < 3; ++bb) {
+                        const float wab = w[0][a] * w[1][bb];
+                        const int row = ((ri + a) * kTile + (rj + bb)) * kTile + rk;
+                        for (int d = 0; d < 3; ++d) {
+                            const float wt = wab * w[2][d];
+                            acc[0] = acc[0] + wt * vt[0][row + d];
+                            acc[1] = acc[1] + wt * vt[1][row + d];
+                            acc[2] = acc[2] + wt * vt[2][row + d];
                         }
-            }
-            for (int a = 0; a < 3; ++a) {
-                const int i = base[0] + a;
-                for (int b = 0; b < 3; ++b) {
-                    const int j = base[1] + b;
-                    const float wab = w[0][a] * w[1][b];
-                    for (int d = 0; d < 3; ++d) {
-                        const int k = base[2] + d;
-                        if (i < 0 || j < 0 || k < 0 || i >= N || j >= N || k >= N) continue;
-                        int32_t s;
-                        if (ACT == AT_ACT_PER_BLOCK || ACT == AT_ACT_NONE) {
-                            s = bslot[(i >> 3) - blo[0]][(j >> 3) - blo[1]][(k >> 3) - blo[2]];
-                        } else {
-                            s = activate_cell<KD>(g, ((int64_t)(i >> 3) * g.R + (j >> 3)) * g.R + (k >> 3));
-                        }
-                        if (s < 0) continue;
-                        const int64_t o = (int64_t)s * kBV + (i & 7) * 64 + (j & 7) * 8 + (k & 7);
-                        const float wt = wab * w[2][d];
-                        const float tm = wt * mp;
-                        unsafeAtomicAdd(M + o, tm);
-                        unsafeAtomicAdd(MV0 + o, tm * v[0]);
-                        unsafeAtomicAdd(MV1 + o, tm * v[1]);
-                        unsafeAtomicAdd(MV2 + o, tm * v[2]);
                     }
                 }
+                v[0] = acc[0]; v[1] = acc[1]; v[2] = acc[2];
+            } else {
+                gather_direct<KS>(pp, x, v);
             }
+            pp.v[p] = v[0]; pp.v[np + p] = v[1]; pp.v[2 * np + p] = v[2];
         }
+        __syncthreads();
     }
 }
 
@@ -1268,12 +1397,14 @@ __global__ __launch_bounds__(1024) void k_bin_scan(GridDev g) {
     if (t == 0) {
         g.hdr[HDR_NBINS] = n;
         g.hdr[HDR_NAPPEND] = 0;
+        g.hdr[HDR_NOUT] = g.hdr[HDR_NOUT_ACC];
+        g.hdr[HDR_NOUT_ACC] = 0;
     }
 }
 
 // Particle records grouped by cell: record poff[cell] + rank holds the
-// particle's x, v and m (read in index order, written as two float4), so a
-// bin's particles are read contiguously by the tile kernel.
+// particle's x, v, m and index (read in index order, written as two float4),
+// so a bin's particles are read contiguously by the tile kernels.
 __global__ __launch_bounds__(256) void k_bin_place(PartProg pp) {
     const GridDev &g = pp.gdst;
     const int64_t np = pp.np;
@@ -1282,26 +1413,28 @@ __global__ __launch_bounds__(256) void k_bin_place(PartProg pp) {
         if (kr.x < 0) continue;
         const int64_t pos = (int64_t)g.poff[kr.x] + kr.y;
         g.pstage[2 * pos] = make_float4(pp.x[p], pp.x[np + p], pp.x[2 * np + p], pp.v[p]);
-        g.pstage[2 * pos + 1] = make_float4(pp.v[np + p], pp.v[2 * np + p], pp.m[p], 0.f);
+        g.pstage[2 * pos + 1] = make_float4(pp.v[np + p], pp.v[2 * np + p], pp.m[p], __int_as_float((int32_t)p));
     }
 }
 
 // One workgroup per bin (root cell c): every node a particle of the bin
-// touches lies in [8c - 1, 8c + 8] per axis, a 10^3 tile held in LDS for m
-// and the three mv channels.  LDS float atomics are slow on this hardware,
-// so the bin's particles (in chunks of kChunk) are first counting-sorted by
-// centre node (512 per block, integer LDS atomics); each thread then owns
-// two k-adjacent centre nodes and sums, in registers, the contributions of
-// their particles to the 3 x 3 x 4 nodes they reach (same per-contribution
-// arithmetic as the direct scatter), adding them to the tile once.  The touched blocks among the 27
-// around c are activated (or were, per node, when ACT == AT_ACT_PER_NODE)
-// and the tile's non-zero values are added to the grid with one global
-// atomic per node and channel.
-constexpr int kTile = 10, kTile3 = 1000, kChunk = 4096;
+// touches lies in [8c - 1, 8c + 8] per axis, a 10^3 tile held in LDS with
+// the four channels (m, mv) of a node side by side.  The bin's particles (in
+// chunks of kChunk) are first counting-sorted by centre node (512 per
+// block, integer LDS atomics).  Each thread then owns one centre node per
+// round (two rounds of 256) and sums, in registers, the contributions of its
+// particles to the 27 nodes around it (same per-contribution arithmetic as
+// the direct scatter).  The sums reach the tile in 27 phases, one per node
+// offset, separated by barriers: within a phase distinct centre nodes add to
+// distinct tile nodes, so each add is a plain LDS read and write (LDS float
+// atomics are slow on this hardware) and the tile's summation order is
+// fixed.  The touched blocks among the 27 around c are activated (or were,
+// per node, when ACT == AT_ACT_PER_NODE) and the tile's non-zero values are
+// added to the grid with one global atomic per node and channel.
 
 template <int KD, int ACT>
-__global__ __launch_bounds__(256) void k_p2g_bins(PartProg pp) {
-    __shared__ float tile[4][kTile3];
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_p2g_bins(PartProg pp) {
+    __shared__ float4 tile[kTile3];
     __shared__ int32_t tslot[27];
     __shared__ int32_t tflag[27];
     __shared__ int32_t ncnt[512];        // particles per centre node, then first sorted position
@@ -1319,7 +1452,7 @@ __global__ __launch_bounds__(256) void k_p2g_bins(PartProg pp) {
         int ci, cj, ck;
         cell_coords(g, bin.x, ci, cj, ck);
         const int oi = ci * kBS - 1, oj = cj * kBS - 1, ok = ck * kBS - 1;
-        for (int q = t; q < 4 * kTile3; q += blockDim.x) (&tile[0][0])[q] = 0.f;
+        for (int q = t; q < kTile3; q += blockDim.x) tile[q] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (t < 27) tflag[t] = 0;
         for (int c0 = 0; c0 < bin.z; c0 += kChunk) {
             const int n = bin.z - c0 < kChunk ? bin.z - c0 : kChunk;
@@ -1351,102 +1484,74 @@ __global__ __launch_bounds__(256) void k_p2g_bins(PartProg pp) {
                 order[ncnt[lr >> 16] + (lr & 0xffff)] = (uint16_t)q;
             }
             __syncthreads();
-            // each thread owns two k-adjacent centre nodes (2p and 2p + 1 of the
-            // block's 512) and sums their particles in registers over a window
-            // of three k-planes of 3 x 3 nodes that slides by one plane between
-            // them, so the 18 nodes the two share are added to the tile once
-            for (int pr = t; pr < 256; pr += blockDim.x) {
-                const int li = pr >> 5, lj = (pr >> 2) & 7, lk0 = (pr & 3) * 2;
-                const int bi = ci * kBS + li - 1, bj = cj * kBS + lj - 1;   // base i, j of both
-                int kb = ck * kBS + lk0 - 1;                                // base k of the first
-                float acc[3][9][4];                                         // [k plane][a * 3 + b][channel]
-                bool touched[3] = {false, false, false};
+            for (int round = 0; round < 2; ++round) {
+                const int own = round * 256 + t;   // = (li * 8 + lj) * 8 + lk
+                const int li = own >> 6, lj = (own >> 3) & 7, lk = own & 7;
+                const int p0 = ncnt[own];
+                const int p1 = own + 1 < 512 ? ncnt[own + 1] : n;
+                float acc[27][4];
 #pragma unroll
-                for (int d = 0; d < 3; ++d)
+                for (int e = 0; e < 27; ++e) acc[e][0] = acc[e][1] = acc[e][2] = acc[e][3] = 0.f;
+                // the next particle's record is loaded while the current one is summed
+                float4 na = make_float4(0.f, 0.f, 0.f, 0.f), nb = na;
+                if (p0 < p1) {
+                    const int q = order[p0];
+                    na = rec[2 * q];
+                    nb = rec[2 * q + 1];
+                }
+                for (int pos = p0; pos < p1; ++pos) {
+                    const float4 ra = na, rb = nb;
+                    const int q = order[pos + 1 < p1 ? pos + 1 : pos];
+                    na = rec[2 * q];
+                    nb = rec[2 * q + 1];
+                    const float x[3] = {ra.x, ra.y, ra.z};
+                    const float v[3] = {ra.w, rb.x, rb.y};
+                    const float mp = rb.z;
+                    float w[3][3];
+                    int base[3];
+                    for (int c = 0; c < 3; ++c) base[c] = bspline(x[c] * pp.inv_dx_dst, w[c]);
 #pragma unroll
-                    for (int e = 0; e < 9; ++e) acc[d][e][0] = acc[d][e][1] = acc[d][e][2] = acc[d][e][3] = 0.f;
-                auto flush_plane = [&](int d) {
-                    const int kk = kb + d;
-                    if (!touched[d] || kk < 0 || kk >= N) return;
-                    for (int a = 0; a < 3; ++a)
+                    for (int a = 0; a < 3; ++a) {
+#pragma unroll
                         for (int bb = 0; bb < 3; ++bb) {
-                            const int i = bi + a, j = bj + bb;
-                            if (i < 0 || j < 0 || i >= N || j >= N) continue;
-                            tflag[((i >> 3) - ci + 1) * 9 + ((j >> 3) - cj + 1) * 3 + ((kk >> 3) - ck + 1)] = 1;
-                            const int nn = ((i - oi) * kTile + (j - oj)) * kTile + (kk - ok);
-                            const float *s4 = acc[d][a * 3 + bb];
-                            if (s4[0] != 0.f) atomicAdd(&tile[0][nn], s4[0]);
-                            if (s4[1] != 0.f) atomicAdd(&tile[1][nn], s4[1]);
-                            if (s4[2] != 0.f) atomicAdd(&tile[2][nn], s4[2]);
-                            if (s4[3] != 0.f) atomicAdd(&tile[3][nn], s4[3]);
-                        }
-                };
-                for (int h = 0; h < 2; ++h) {
-                    const int own = pr * 2 + h;   // = (li * 8 + lj) * 8 + lk0 + h
-                    const int p0 = ncnt[own];
-                    const int p1 = own + 1 < 512 ? ncnt[own + 1] : n;
-                    if (p0 < p1) touched[0] = touched[1] = touched[2] = true;
-                    // the next particle's record is loaded while the current one is summed
-                    float4 na = make_float4(0.f, 0.f, 0.f, 0.f), nb = na;
-                    if (p0 < p1) {
-                        const int q = order[p0];
-                        na = rec[2 * q];
-                        nb = rec[2 * q + 1];
-                    }
-                    for (int pos = p0; pos < p1; ++pos) {
-                        const float4 ra = na, rb = nb;
-                        const int q = order[pos + 1 < p1 ? pos + 1 : pos];
-                        na = rec[2 * q];
-                        nb = rec[2 * q + 1];
-                        const float x[3] = {ra.x, ra.y, ra.z};
-                        const float v[3] = {ra.w, rb.x, rb.y};
-                        const float mp = rb.z;
-                        float w[3][3];
-                        int base[3];
-                        for (int c = 0; c < 3; ++c) base[c] = bspline(x[c] * pp.inv_dx_dst, w[c]);
+                            const float wab = w[0][a] * w[1][bb];
 #pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-#pragma unroll
-                            for (int bb = 0; bb < 3; ++bb) {
-                                const float wab = w[0][a] * w[1][bb];
-#pragma unroll
-                                for (int d = 0; d < 3; ++d) {
-                                    if (ACT == AT_ACT_PER_NODE) {
-                                        const int i = base[0] + a, j = base[1] + bb, kk = base[2] + d;
-                                        if (i >= 0 && j >= 0 && kk >= 0 && i < N && j < N && kk < N)
-                                            activate_cell<KD>(g, ((int64_t)(i >> 3) * g.R + (j >> 3)) * g.R + (kk >> 3));
-                                    }
-                                    const float wt = wab * w[2][d];
-                                    const float tm = wt * mp;
-                                    float *s4 = acc[d][a * 3 + bb];
-                                    s4[0] = s4[0] + tm;
-                                    s4[1] = s4[1] + tm * v[0];
-                                    s4[2] = s4[2] + tm * v[1];
-                                    s4[3] = s4[3] + tm * v[2];
+                            for (int d = 0; d < 3; ++d) {
+                                if (ACT == AT_ACT_PER_NODE) {
+                                    const int i = base[0] + a, j = base[1] + bb, kk = base[2] + d;
+                                    if (i >= 0 && j >= 0 && kk >= 0 && i < N && j < N && kk < N)
+                                        activate_cell<KD>(g, ((int64_t)(i >> 3) * g.R + (j >> 3)) * g.R + (kk >> 3));
                                 }
+                                const float wt = wab * w[2][d];
+                                const float tm = wt * mp;
+                                float *s4 = acc[(a * 3 + bb) * 3 + d];
+                                s4[0] = s4[0] + tm;
+                                s4[1] = s4[1] + tm * v[0];
+                                s4[2] = s4[2] + tm * v[1];
+                                s4[3] = s4[3] + tm * v[2];
                             }
                         }
-                    }
-                    if (h == 0) {
-                        // the first centre node's lowest plane is complete; slide
-                        flush_plane(0);
-#pragma unroll
-                        for (int e = 0; e < 9; ++e)
-#pragma unroll
-                            for (int c = 0; c < 4; ++c) {
-                                acc[0][e][c] = acc[1][e][c];
-                                acc[1][e][c] = acc[2][e][c];
-                                acc[2][e][c] = 0.f;
-                            }
-                        touched[0] = touched[1];
-                        touched[1] = touched[2];
-                        touched[2] = false;
-                        kb += 1;
                     }
                 }
-                flush_plane(0);
-                flush_plane(1);
-                flush_plane(2);
+                // node offset e = (a * 3 + b) * 3 + d reaches tile node
+                // (li + a, lj + b, lk + d), global node (8c - 1) + that
+                const bool any = p0 < p1;
+#pragma unroll
+                for (int e = 0; e < 27; ++e) {
+                    __syncthreads();
+                    const int a = e / 9, bb = (e / 3) % 3, d = e % 3;
+                    const int i = oi + li + a, j = oj + lj + bb, kk = ok + lk + d;
+                    if (any && i >= 0 && j >= 0 && kk >= 0 && i < N && j < N && kk < N) {
+                        const int nn = ((li + a) * kTile + (lj + bb)) * kTile + (lk + d);
+                        float4 cur = tile[nn];
+                        cur.x = cur.x + acc[e][0];
+                        cur.y = cur.y + acc[e][1];
+                        cur.z = cur.z + acc[e][2];
+                        cur.w = cur.w + acc[e][3];
+                        tile[nn] = cur;
+                        tflag[((i >> 3) - ci + 1) * 9 + ((j >> 3) - cj + 1) * 3 + ((kk >> 3) - ck + 1)] = 1;
+                    }
+                }
             }
             __syncthreads();
         }
@@ -1466,11 +1571,11 @@ __global__ __launch_bounds__(256) void k_p2g_bins(PartProg pp) {
             const int32_t sl = tslot[((i >> 3) - ci + 1) * 9 + ((j >> 3) - cj + 1) * 3 + ((k >> 3) - ck + 1)];
             if (sl < 0) continue;
             const int64_t o = (int64_t)sl * kBV + (i & 7) * 64 + (j & 7) * 8 + (k & 7);
-            const float m = tile[0][nn], a0 = tile[1][nn], a1 = tile[2][nn], a2 = tile[3][nn];
-            if (m != 0.f) unsafeAtomicAdd(M + o, m);
-            if (a0 != 0.f) unsafeAtomicAdd(MV0 + o, a0);
-            if (a1 != 0.f) unsafeAtomicAdd(MV1 + o, a1);
-            if (a2 != 0.f) unsafeAtomicAdd(MV2 + o, a2);
+            const float4 tv = tile[nn];
+            if (tv.x != 0.f) unsafeAtomicAdd(M + o, tv.x);
+            if (tv.y != 0.f) unsafeAtomicAdd(MV0 + o, tv.y);
+            if (tv.z != 0.f) unsafeAtomicAdd(MV1 + o, tv.z);
+            if (tv.w != 0.f) unsafeAtomicAdd(MV2 + o, tv.w);
         }
         __syncthreads();
     }
@@ -1690,17 +1795,35 @@ hipError_t launch_micro(const GridDev &g, const MicroProg &prog, hipStream_t s) 
     return hipGetLastError();
 }
 
+// The per-particle part of a particle node: one index-ordered pass
+// (k_particles) or, for a gather through the source grid's bins, the gather
+// per source bin (k_g2p_bins) and then, when the node has more steps, an
+// index-ordered pass for them.
+template <int KS, int KD, uint32_t STEPS, int ACT, bool BIN>
+static void launch_part_first(const PartProg &pp, dim3 grid, hipStream_t s) {
+    if constexpr ((STEPS & PS_G2P) != 0) {
+        if (pp.g2p_bins) {
+            const int64_t nb = pp.gsrc.ncells < 256 * 8 ? pp.gsrc.ncells : 256 * 8;
+            hipLaunchKernelGGL(k_g2p_bins<KS>, dim3((unsigned)nb), dim3(256), 0, s, pp);
+            constexpr uint32_t REST = STEPS & ~(uint32_t)PS_G2P;
+            if constexpr (REST != 0) hipLaunchKernelGGL((k_particles<KS, KD, REST, ACT, BIN>), grid, dim3(256), 0, s, pp);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_particles<KS, KD, STEPS, ACT, BIN>), grid, dim3(256), 0, s, pp);
+}
+
 template <int KS, int KD, uint32_t STEPS>
 static void launch_part_a(const PartProg &pp, dim3 grid, bool bin, hipStream_t s) {
     constexpr bool P2G = (STEPS & PS_P2G) != 0;
     if (P2G && bin) {
         // cell keys (with the gather and advection), ranks, scan, place, scatter per bin
         if (pp.act_mode == AT_ACT_PER_BLOCK)
-            hipLaunchKernelGGL((k_particles<KS, KD, STEPS, AT_ACT_PER_BLOCK, P2G>), grid, dim3(256), 0, s, pp);
+            launch_part_first<KS, KD, STEPS, AT_ACT_PER_BLOCK, P2G>(pp, grid, s);
         else if (pp.act_mode == AT_ACT_NONE)
-            hipLaunchKernelGGL((k_particles<KS, KD, STEPS, AT_ACT_NONE, P2G>), grid, dim3(256), 0, s, pp);
+            launch_part_first<KS, KD, STEPS, AT_ACT_NONE, P2G>(pp, grid, s);
         else
-            hipLaunchKernelGGL((k_particles<KS, KD, STEPS, AT_ACT_PER_NODE, P2G>), grid, dim3(256), 0, s, pp);
+            launch_part_first<KS, KD, STEPS, AT_ACT_PER_NODE, P2G>(pp, grid, s);
         if (pp.gdst.ncells <= kHistCells)
             hipLaunchKernelGGL(k_bin_rank<true>, dim3(256), dim3(1024), 0, s, pp.gdst, pp.np);
         else
@@ -1717,11 +1840,11 @@ static void launch_part_a(const PartProg &pp, dim3 grid, bool bin, hipStream_t s
         return;
     }
     if (pp.act_mode == AT_ACT_PER_BLOCK)
-        hipLaunchKernelGGL((k_particles<KS, KD, STEPS, AT_ACT_PER_BLOCK, false>), grid, dim3(256), 0, s, pp);
+        launch_part_first<KS, KD, STEPS, AT_ACT_PER_BLOCK, false>(pp, grid, s);
     else if (pp.act_mode == AT_ACT_NONE)
-        hipLaunchKernelGGL((k_particles<KS, KD, STEPS, AT_ACT_NONE, false>), grid, dim3(256), 0, s, pp);
+        launch_part_first<KS, KD, STEPS, AT_ACT_NONE, false>(pp, grid, s);
     else
-        hipLaunchKernelGGL((k_particles<KS, KD, STEPS, AT_ACT_PER_NODE, false>), grid, dim3(256), 0, s, pp);
+        launch_part_first<KS, KD, STEPS, AT_ACT_PER_NODE, false>(pp, grid, s);
 }
 
 template <int KS, int KD>
@@ -1741,7 +1864,8 @@ static bool launch_part_s(const PartProg &pp, dim3 grid, bool bin, hipStream_t s
 hipError_t launch_particles(const PartProg &pp, hipStream_t s, int *dispatches) {
     // the scatter is binned when the destination grid has room for every particle
     const bool bin = (pp.steps & PS_P2G) && pp.gdst.pcap >= pp.np;
-    *dispatches = bin ? 5 : 1;
+    const bool split = pp.g2p_bins && (pp.steps & PS_G2P) && (pp.steps & ~(uint32_t)PS_G2P);
+    *dispatches = (bin ? 5 : 1) + (split ? 1 : 0);
     int64_t blocks = (pp.np + 255) / 256;
     if (blocks < 1) blocks = 1;
     if (blocks > 256 * 64) blocks = 256 * 64;

@@ -57,6 +57,7 @@ struct Engine {
     int64_t flush_period = 0;
     uint32_t opt_flags = AT_OPT_ALL;
     bool plan_cache = true;
+    bool g2p_bins = true;   // gathers may use the source grid's bins
     std::vector<at_task> queue;
     hipStream_t queue_stream = nullptr;
     std::atomic<int64_t> dispatches{0};
@@ -79,7 +80,7 @@ Engine &E() {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t hdr, scan, bits, ptr, list, pcount, poff, pbins, pkr, pstage, chan, total;
+    size_t hdr, scan, bits, ptr, list, pcount, poff, pbins, pkr, pstage, pout, chan, total;
     int64_t pcap;
     int64_t ncells;
     int32_t cap, list_cap, R;
@@ -118,6 +119,7 @@ at_status layout_of(const at_grid_desc *d, Layout &L) {
     L.pbins = off;  if (L.pcap) off += align256(nc * 4 * sizeof(int32_t));
     L.pkr = off;    if (L.pcap) off += align256((size_t)L.pcap * 2 * sizeof(int32_t));
     L.pstage = off; if (L.pcap) off += align256((size_t)L.pcap * 8 * sizeof(float));
+    L.pout = off;   if (L.pcap) off += align256((size_t)L.pcap * sizeof(int32_t));
     L.chan = off; off += (size_t)d->channels * L.cap * kBV * sizeof(float);
     L.total = off;
     return AT_OK;
@@ -205,9 +207,22 @@ at_status execute_node(const Node &nd, const at_task *tasks, bool table, hipStre
             }
         }
         if (pp.np == 0) return AT_OK;
+        // The gather may go through the source grid's bins when its last
+        // binned scatter had exactly these many particles (the bins then
+        // hold each index once) and the same node does not bin into that
+        // grid again while reading them.
+        at_grid_s *src = nullptr, *dst = nullptr;
+        for (const Member &m : nd.members) {
+            const at_task &t = tasks[m.task];
+            if (t.kind == AT_TASK_G2P) src = const_cast<at_grid_s *>(task_grid(t));
+            if (t.kind == AT_TASK_P2G) dst = const_cast<at_grid_s *>(task_grid(t));
+        }
+        const bool bin_dst = dst && dst->dev.pcap >= pp.np;
+        pp.g2p_bins = src && src->bins_np == pp.np && !(bin_dst && dst == src) && E().g2p_bins ? 1 : 0;
         int ndisp = 1;
         e = launch_particles(pp, s, &ndisp);
         if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        if (bin_dst) dst->bins_np = pp.np;
         E().dispatches.fetch_add(ndisp);
         return AT_OK;
     }
@@ -416,6 +431,7 @@ at_status at_grid_create(const at_grid_desc *desc, void *dev_buf, size_t bytes, 
         d.pbins = L.pcap ? (int4 *)(b + L.pbins) : nullptr;
         d.pkr = L.pcap ? (int2 *)(b + L.pkr) : nullptr;
         d.pstage = L.pcap ? (float4 *)(b + L.pstage) : nullptr;
+        d.pout = L.pcap ? (int32_t *)(b + L.pout) : nullptr;
         d.chan = (float *)(b + L.chan);
         hipError_t e = hipMemsetAsync(dev_buf, 0, L.total, stream);
         if (e == hipSuccess && d.ptr) e = hipMemsetAsync(d.ptr, 0xff, (size_t)L.ncells * 4, stream);
@@ -488,9 +504,10 @@ at_status at_grid_clear(at_grid grid, hipStream_t stream) {
     if (e == hipSuccess && d.ptr) e = hipMemsetAsync(d.ptr, 0xff, (size_t)d.ncells * 4, stream);
     if (e == hipSuccess) e = hipMemsetAsync(d.chan, 0, (size_t)grid->desc.channels * d.ch_stride * sizeof(float), stream);
     if (e == hipSuccess && d.pcount) e = hipMemsetAsync(d.pcount, 0, (size_t)d.ncells * sizeof(int32_t), stream);
-    if (e == hipSuccess && d.pcount) e = hipMemsetAsync(d.hdr + HDR_NBINS, 0, 2 * sizeof(int32_t), stream);
+    if (e == hipSuccess && d.pcount) e = hipMemsetAsync(d.hdr + HDR_NBINS, 0, 4 * sizeof(int32_t), stream);
     if (e != hipSuccess) return hip_fail(e, "grid clear");
     en.dispatches.fetch_add((d.ptr ? 4 : 3) + (d.pcount ? 2 : 0));
+    grid->bins_np = 0;
     en.persist.deactivate_grid(grid->uid);
     for (int c = 0; c < grid->desc.channels; ++c) bump(grid->uid, ST_VALUE, c);
     bump(grid->uid, ST_ALLOC, -1);
@@ -775,6 +792,10 @@ at_status at_set_option(int32_t option, int64_t value) {
         if (value != 1 && value != 2 && value != 4) return fail(AT_E_INVALID, "batch waves must be 1, 2 or 4");
         set_batch_waves((int)value);
         return AT_OK;
+    case AT_OPTION_G2P_BINS:
+        if (value != 0 && value != 1) return fail(AT_E_INVALID, "g2p bins must be 0 or 1");
+        en.g2p_bins = value != 0;
+        return AT_OK;
     default:
         return fail(AT_E_INVALID, "unknown option %d", option);
     }
@@ -792,6 +813,7 @@ at_status at_get_option(int32_t option, int64_t *value) {
     case AT_OPTION_STRUCT_FOR_WORKGROUPS: *value = struct_for_grid_size_override(); return AT_OK;
     case AT_OPTION_STRUCT_FOR_KERNEL: *value = struct_for_kernel(); return AT_OK;
     case AT_OPTION_BATCH_WAVES: *value = batch_waves(); return AT_OK;
+    case AT_OPTION_G2P_BINS: *value = en.g2p_bins ? 1 : 0; return AT_OK;
     default: return fail(AT_E_INVALID, "unknown option %d", option);
     }
 }

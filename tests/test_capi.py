@@ -56,10 +56,11 @@ def test_footprint_layout_and_validation():
         assert lib.at_last_error()
     nc = L.AtGridDesc((64, 64, 32), 0, 1, 0, 0)
     assert lib.at_grid_footprint(ctypes.byref(nc), ctypes.byref(b)) == L.AT_E_UNSUPPORTED
-    # particle binning workspace: 3 cell arrays (count, first, bins of 16 B) + 40 B per particle
+    # particle binning workspace: 3 cell arrays (count, first, bins of 16 B) + 44 B per particle
+    # (key and rank 8 B, record 32 B, outlier list 4 B)
     d = L.AtGridDesc((64, 64, 64), L.AT_ROOT_POINTER, 3, 100, 1000)
     assert lib.at_grid_footprint(ctypes.byref(d), ctypes.byref(b)) == L.AT_OK
-    assert b.value == (256 + 8192 + 256 + 2048 + 3328 + 2048 + 2048 + 8192 + 8192 + 32000
+    assert b.value == (256 + 8192 + 256 + 2048 + 3328 + 2048 + 2048 + 8192 + 8192 + 32000 + 4096
                        + 3 * 100 * 2048)
     d = L.AtGridDesc((64, 64, 64), L.AT_ROOT_POINTER, 3, 100, -1)
     assert lib.at_grid_footprint(ctypes.byref(d), ctypes.byref(b)) == L.AT_E_INVALID

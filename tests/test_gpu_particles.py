@@ -101,6 +101,55 @@ def test_g2p_matches_oracle():
     say("  bit-identical:", bool(np.array_equal(got, exp)))
 
 
+@pytest.mark.parametrize("root", ["pointer", "bitmask"])
+@pytest.mark.parametrize("n,np_,lo,hi,shift", [(64, 20000, 0.1, 0.6, 0.0), (32, 5000, -0.03, 1.03, 0.0),
+                                               (64, 20000, 0.1, 0.6, 0.02)])
+def test_g2p_through_bins_is_bit_identical(root, n, np_, lo, hi, shift):
+    """A gather after a binned scatter of as many particles goes through the
+    scatter's bins: it must equal the per-particle gather bit for bit and
+    meet the gather bar against the oracle, also with particles whose centre
+    node lies outside the domain (listed apart by the scatter) and after the
+    particles have moved (shift, in units of the domain: many leave their
+    bin's tile and gather directly).  A gather of another particle count
+    does not use the bins."""
+    from paper_2012_08141_amd import _lib as L, engine as E
+    from paper_2012_08141_amd.grid import SparseGrid
+    say("g2p bins", root, n, np_, lo, hi, shift)
+    p = I.random_particles(6, n, np_, lo, hi, root)
+    g = SparseGrid(n, 7, root, (n // 8) ** 3 if root == "pointer" else 0, particle_capacity=np_)
+    x, v, m = (torch.as_tensor(a, device="cuda").contiguous() for a in (p.x, p.v, p.m))
+    E.run_sequence([E.p2g(g, x, v, m, 1.0 / n, 0, 1)], 0)
+    if shift:
+        E.run_sequence([E.advect(x, torch.full_like(x, shift), 1.0)], 0)
+    cells = g.active_cells()
+    rng = np.random.default_rng([7, n, np_])
+    vals = [rng.uniform(-1, 1, (len(cells), 512)).astype(np.float32) for _ in range(3)]
+    for q in range(3):
+        g.load_blocks(4 + q, cells, vals[q])
+    o = oracle.OracleGrid(n, 3)
+    o.load(I.cells_to_blocks(cells, n // 8), {"v%d" % q: vals[q] for q in range(3)}, {"v0": 0, "v1": 1, "v2": 2})
+    xs = x.cpu().numpy()
+    exp = o.g2p(0, xs, float(n))
+    got = {}
+    try:
+        for on in (1, 0):
+            E.set_option(L.AT_OPTION_G2P_BINS, on)
+            out = torch.zeros_like(x)
+            E.run_sequence([E.g2p(g, x, out, 1.0 / n, 4)], 0)
+            torch.cuda.synchronize()
+            got[on] = out.cpu().numpy()
+    finally:
+        E.set_option(L.AT_OPTION_G2P_BINS, 1)
+    assert np.array_equal(got[1], got[0])
+    close_state(got[1], exp, "g2p through bins")
+    half = x[:, : np_ // 2].contiguous()
+    out = torch.zeros_like(half)
+    E.run_sequence([E.g2p(g, half, out, 1.0 / n, 4)], 0)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), got[0][:, : np_ // 2])
+    assert g.device_status() == 0
+
+
 def _particle_run(p, steps, opt, binned=True):
     from paper_2012_08141_amd import engine as E, programs as PR
     from paper_2012_08141_amd.grid import SparseGrid
@@ -124,8 +173,11 @@ def test_particle_program_reduced(opt, binned):
     p = I.particles(0, n=128, nparticles=100_000)
     grids, x, v, st = _particle_run(p, 20, opt, binned)
     assert st["tasks_launched"] == (140 if opt == 0 else 65)
-    # a binned scatter is 5 dispatches (keys, ranks, scan, place, tiles); one per step
-    assert st["dispatches"] == st["tasks_launched"] + (4 * 20 if binned else 0)
+    # a binned scatter is 5 dispatches (keys, ranks, scan, place, tiles), one per
+    # step; from the second step on, the gather goes through the bins of the
+    # previous step's scatter, and where it is fused with advection and the
+    # scatter (optimized) those run as one more index-ordered dispatch
+    assert st["dispatches"] == st["tasks_launched"] + (4 * 20 if binned else 0) + (19 if binned and opt else 0)
     ref = OP.particle_program(p.n, p.x, p.v, p.m, 20, p.params["dt"], "f32")
     sx, sv = 0.1 * np.abs(p.x).max(), 0.1 * np.abs(p.v).max()
     close_state(x.cpu().numpy(), ref["x"], "x", sx)
