@@ -83,6 +83,7 @@ struct PartProg {
     int32_t ch_vsrc;       // gather: velocity channels v0..v0+2 of gsrc
     int32_t ch_m, ch_mv;   // scatter: m and mv0..mv0+2 of gdst
     int32_t g2p_bins;      // gather through gsrc's bins (its last binned scatter had np particles)
+    int32_t g2p_rec_x;     // and take positions from its records (they hold the current x)
     GridDev gsrc, gdst;
 };
 
@@ -139,4 +140,7 @@ struct at_grid_s {
     size_t bytes;
     int32_t list_cap;
     int64_t bins_np;    // particles of the last binned scatter into this grid (0: none since clear)
+    const void *bins_x; // its position array,
+    uint64_t bins_window;   // the window it ran in
+    int64_t bins_writes;    // and the advections of bins_x in that window up to it
 };

@@ -1219,16 +1219,20 @@ __global__ __launch_bounds__(256) void k_particles(PartProg pp) {
 // Gather through the bins of the source grid's last binned scatter (the
 // runtime uses them only when that scatter had the same particle count, so
 // the bins hold every particle index once; the source's outliers are listed
-// apart).  One workgroup per bin loads the 10^3 tile of the three velocity
-// channels around the bin's block (0 outside the domain or in an inactive
-// block) into LDS; each of the bin's particles reads its current position
-// and, when its 27 nodes lie in the tile, gathers from LDS in the same
+// apart).  Four workgroups per bin (a quarter of its particles each) load
+// the 10^3 tile of the three velocity channels around the bin's block (0
+// outside the domain or in an inactive block) into LDS; each particle takes
+// its current position (from its record when the runtime knows the records
+// are current, else from x) and, when its 27 nodes lie in the tile, gathers
+// from LDS in the same
 // (a, b, d) order and arithmetic as gather_direct, so the result is
 // bit-identical.  A particle that has left the tile since it was binned, and
 // every outlier, gathers directly.  Only v is written: particles come in bin
 // order, so the steps that follow a gather in a fused node (advection, the
 // scatter's first pass) run as a second, index-ordered pass, where their
 // writes stay coalesced.
+constexpr int kG2PSplit = 4;   // workgroups per bin (each takes a quarter of its particles)
+
 template <int KS>
 __global__ __launch_bounds__(256) void k_g2p_bins(PartProg pp) {
     __shared__ float vt[3][kTile3];
@@ -1241,9 +1245,10 @@ __global__ __launch_bounds__(256) void k_g2p_bins(PartProg pp) {
     const int nout = S.hdr[HDR_NOUT];
     const int nob = (nout + (int)blockDim.x - 1) / (int)blockDim.x;
     const float *V0 = chan(S, pp.ch_vsrc), *V1 = chan(S, pp.ch_vsrc + 1), *V2 = chan(S, pp.ch_vsrc + 2);
-    for (int b = blockIdx.x; b < nb + nob; b += gridDim.x) {
-        if (b >= nb) {
-            const int q = (b - nb) * (int)blockDim.x + t;
+    const int nit = nb * kG2PSplit;
+    for (int it = blockIdx.x; it < nit + nob; it += gridDim.x) {
+        if (it >= nit) {
+            const int q = (it - nit) * (int)blockDim.x + t;
             if (q < nout) {
                 const int64_t p = S.pout[q];
                 const float x[3] = {pp.x[p], pp.x[np + p], pp.x[2 * np + p]};
@@ -1253,7 +1258,11 @@ __global__ __launch_bounds__(256) void k_g2p_bins(PartProg pp) {
             }
             continue;
         }
-        const int4 bin = S.pbins[b];
+        const int4 bin = S.pbins[it / kG2PSplit];
+        const int per = (bin.z + kG2PSplit - 1) / kG2PSplit;
+        const int q0 = (it % kG2PSplit) * per;
+        const int q1 = q0 + per < bin.z ? q0 + per : bin.z;
+        if (q0 >= q1) continue;
         int ci, cj, ck;
         cell_coords(S, bin.x, ci, cj, ck);
         const int oi = ci * kBS - 1, oj = cj * kBS - 1, ok = ck * kBS - 1;
@@ -1276,9 +1285,15 @@ __global__ __launch_bounds__(256) void k_g2p_bins(PartProg pp) {
             vt[0][nn] = a0; vt[1][nn] = a1; vt[2][nn] = a2;
         }
         __syncthreads();
-        for (int q = t; q < bin.z; q += blockDim.x) {
+        for (int q = q0 + t; q < q1; q += blockDim.x) {
             const int64_t p = __float_as_int(S.pstage[2 * ((int64_t)bin.y + q) + 1].w);
-            const float x[3] = {pp.x[p], pp.x[np + p], pp.x[2 * np + p]};
+            float x[3];
+            if (pp.g2p_rec_x) {
+                const float4 ra = S.pstage[2 * ((int64_t)bin.y + q)];
+                x[0] = ra.x; x[1] = ra.y; x[2] = ra.z;
+            } else {
+                x[0] = pp.x[p]; x[1] = pp.x[np + p]; x[2] = pp.x[2 * np + p];
+            }
             float w[3][3];
             int base[3];
             for (int c = 0; c < 3; ++c) base[c] = bspline(x[c] * pp.inv_dx_src, w[c]);
@@ -1803,7 +1818,7 @@ template <int KS, int KD, uint32_t STEPS, int ACT, bool BIN>
 static void launch_part_first(const PartProg &pp, dim3 grid, hipStream_t s) {
     if constexpr ((STEPS & PS_G2P) != 0) {
         if (pp.g2p_bins) {
-            const int64_t nb = pp.gsrc.ncells < 256 * 8 ? pp.gsrc.ncells : 256 * 8;
+            const int64_t nb = pp.gsrc.ncells * kG2PSplit < 256 * 8 ? pp.gsrc.ncells * kG2PSplit : 256 * 8;
             hipLaunchKernelGGL(k_g2p_bins<KS>, dim3((unsigned)nb), dim3(256), 0, s, pp);
             constexpr uint32_t REST = STEPS & ~(uint32_t)PS_G2P;
             if constexpr (REST != 0) hipLaunchKernelGGL((k_particles<KS, KD, REST, ACT, BIN>), grid, dim3(256), 0, s, pp);

@@ -58,6 +58,11 @@ struct Engine {
     uint32_t opt_flags = AT_OPT_ALL;
     bool plan_cache = true;
     bool g2p_bins = true;   // gathers may use the source grid's bins
+    // Inside one window only its own nodes touch external arrays, so a
+    // binned scatter's particle records still hold the current positions
+    // when the same window has not advected those positions since.
+    uint64_t window_seq = 0;                                // bumped per executed window
+    std::unordered_map<const void *, int64_t> pos_writes;   // advections per position array, this window
     std::vector<at_task> queue;
     hipStream_t queue_stream = nullptr;
     std::atomic<int64_t> dispatches{0};
@@ -217,12 +222,26 @@ at_status execute_node(const Node &nd, const at_task *tasks, bool table, hipStre
             if (t.kind == AT_TASK_G2P) src = const_cast<at_grid_s *>(task_grid(t));
             if (t.kind == AT_TASK_P2G) dst = const_cast<at_grid_s *>(task_grid(t));
         }
+        Engine &en = E();
         const bool bin_dst = dst && dst->dev.pcap >= pp.np;
-        pp.g2p_bins = src && src->bins_np == pp.np && !(bin_dst && dst == src) && E().g2p_bins ? 1 : 0;
+        pp.g2p_bins = src && src->bins_np == pp.np && !(bin_dst && dst == src) && en.g2p_bins ? 1 : 0;
+        // the records' positions are current when they were written in this
+        // window from this array and nothing has advected it since
+        const auto pw = en.pos_writes.find(pp.x);
+        const int64_t writes = pw == en.pos_writes.end() ? 0 : pw->second;
+        pp.g2p_rec_x = pp.g2p_bins && src->bins_window == en.window_seq && src->bins_x == pp.x &&
+                       src->bins_writes == writes ? 1 : 0;
         int ndisp = 1;
         e = launch_particles(pp, s, &ndisp);
         if (e != hipSuccess) return hip_fail(e, "kernel launch");
-        if (bin_dst) dst->bins_np = pp.np;
+        const int64_t after = writes + ((pp.steps & PS_ADVECT) ? 1 : 0);
+        if (pp.steps & PS_ADVECT) en.pos_writes[pp.x] = after;
+        if (bin_dst) {
+            dst->bins_np = pp.np;
+            dst->bins_x = pp.x;
+            dst->bins_window = en.window_seq;
+            dst->bins_writes = after;
+        }
         E().dispatches.fetch_add(ndisp);
         return AT_OK;
     }
@@ -326,6 +345,8 @@ at_status run_window(const at_task *tasks, int ntasks, uint32_t flags, at_stats 
     const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
     const int64_t d0 = en.dispatches.load();
     const std::vector<uint8_t> tables = neighbour_tables_valid(nodes, tasks, en.persist);
+    ++en.window_seq;
+    en.pos_writes.clear();
     for (size_t i = 0; i < nodes.size() && !any_virt; ++i) {
         const Node &nd = nodes[i];
         hipEvent_t ea = nullptr;

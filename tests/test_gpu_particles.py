@@ -150,6 +150,39 @@ def test_g2p_through_bins_is_bit_identical(root, n, np_, lo, hi, shift):
     assert g.device_status() == 0
 
 
+@pytest.mark.parametrize("root", ["pointer", "bitmask"])
+@pytest.mark.parametrize("shift", [0.0, 0.02])
+def test_g2p_through_bins_in_one_window(root, shift):
+    """Scatter, (advection,) normalisation and gather in one window: without
+    advection the gather takes positions from the scatter's records, after
+    it from x (records stale).  Both must agree with the gather that does not
+    use bins (the scatter's fp32 atomics make the node values differ in the
+    last bits between runs, so the bar is the gather bar)."""
+    from paper_2012_08141_amd import _lib as L, engine as E
+    from paper_2012_08141_amd.grid import SparseGrid
+    say("g2p bins one window", root, shift)
+    n, np_ = 64, 20000
+    p = I.random_particles(8, n, np_, 0.1, 0.6, root)
+    got = {}
+    try:
+        for on in (1, 0):
+            E.set_option(L.AT_OPTION_G2P_BINS, on)
+            g = SparseGrid(n, 7, root, (n // 8) ** 3 if root == "pointer" else 0, particle_capacity=np_)
+            x, v, m = (torch.as_tensor(a, device="cuda").contiguous() for a in (p.x, p.v, p.m))
+            out = torch.zeros_like(x)
+            tasks = [E.p2g(g, x, v, m, 1.0 / n, 0, 1)]
+            if shift:
+                tasks.append(E.advect(x, torch.full_like(x, shift), 1.0))
+            tasks += [E.listgen(g), E.normalise(g, 0, 1, 4), E.g2p(g, x, out, 1.0 / n, 4)]
+            E.run_sequence(tasks, 0)
+            torch.cuda.synchronize()
+            got[on] = out.cpu().numpy()
+            assert g.device_status() == 0
+    finally:
+        E.set_option(L.AT_OPTION_G2P_BINS, 1)
+    close_state(got[1], got[0], "g2p bins vs direct, one window")
+
+
 def _particle_run(p, steps, opt, binned=True):
     from paper_2012_08141_amd import engine as E, programs as PR
     from paper_2012_08141_amd.grid import SparseGrid
