@@ -82,8 +82,12 @@ struct PartProg {
     float inv_dx_dst;      // scatter grid
     int32_t ch_vsrc;       // gather: velocity channels v0..v0+2 of gsrc
     int32_t ch_m, ch_mv;   // scatter: m and mv0..mv0+2 of gdst
-    int32_t g2p_bins;      // gather through gsrc's bins (its last binned scatter had np particles)
-    int32_t g2p_rec_x;     // and take positions from its records (they hold the current x)
+    int32_t g2p_bins;      // gather through the bins in gbin_g (gsrc's last binned scatter had np particles)
+    int32_t g2p_rec_x;     // and take positions from their records (they hold the current x)
+    int32_t p2g_reuse;     // scatter over the bins in gbin_s as they are (no binning); the gather
+                           // of the same node updates their records first
+    GridDev gbin_g;        // workspace holding the bins the gather goes through
+    GridDev gbin_s;        // workspace holding the bins the scatter uses (gdst unless reusing)
     GridDev gsrc, gdst;
 };
 
@@ -139,8 +143,21 @@ struct at_grid_s {
     uint32_t listgen_epoch;   // distinguishes list generation launches (never 0)
     size_t bytes;
     int32_t list_cap;
-    int64_t bins_np;    // particles of the last binned scatter into this grid (0: none since clear)
-    const void *bins_x; // its position array,
-    uint64_t bins_window;   // the window it ran in
-    int64_t bins_writes;    // and the advections of bins_x in that window up to it
+    // The last binned scatter into this grid: its particle count (0: none
+    // since clear), position array, the window it ran in and the advections
+    // of that array in the window up to it, and the grid whose workspace
+    // holds its bins (this grid, or the source of a reused binning) with that
+    // workspace's generation at the time.
+    int64_t bins_np;
+    const void *bins_x;
+    uint64_t bins_window;
+    int64_t bins_writes;
+    uint64_t bins_owner;
+    uint64_t bins_owner_gen;
+    // This grid's own workspace: its generation (bumped when a scatter bins
+    // into it and when the grid is cleared) and how many scatters have reused
+    // its bins since they were made.
+    uint64_t ws_gen;
+    int32_t bins_age;
+    float bins_inv_dx;      // 1/dx the particles were binned with
 };

@@ -1035,10 +1035,11 @@ __device__ __forceinline__ int bspline(float X, float w[3]) {
     return base;
 }
 
-// Edge of the node tile around one root cell (the block plus one node each
-// side: every node a particle binned to the cell touches), its node count,
-// and the particles the binned scatter sorts at once.
-constexpr int kTile = 10, kTile3 = 1000, kChunk = 4096;
+// The binned gather works on the nodes [8c - 2, 8c + 9] per axis around root
+// cell c (kTile^3 = kTile3): every node touched by a particle whose centre
+// node lies in [8c - 1, 8c + 8], i.e. in the block or one node beyond it (a
+// particle binned to c that has moved by up to one node since).
+constexpr int kTile = 12, kTile3 = 1728;
 
 // s[x * 4 + y * 2 + z] chosen with selects: an array indexed at run time
 // would be placed in scratch memory.
@@ -1218,19 +1219,20 @@ __global__ __launch_bounds__(256) void k_particles(PartProg pp) {
 
 // Gather through the bins of the source grid's last binned scatter (the
 // runtime uses them only when that scatter had the same particle count, so
-// the bins hold every particle index once; the source's outliers are listed
-// apart).  Four workgroups per bin (a quarter of its particles each) load
-// the 10^3 tile of the three velocity channels around the bin's block (0
-// outside the domain or in an inactive block) into LDS; each particle takes
-// its current position (from its record when the runtime knows the records
-// are current, else from x) and, when its 27 nodes lie in the tile, gathers
-// from LDS in the same
-// (a, b, d) order and arithmetic as gather_direct, so the result is
-// bit-identical.  A particle that has left the tile since it was binned, and
-// every outlier, gathers directly.  Only v is written: particles come in bin
-// order, so the steps that follow a gather in a fused node (advection, the
-// scatter's first pass) run as a second, index-ordered pass, where their
-// writes stay coalesced.
+// the bins hold every particle index once; the scatter's outliers are
+// listed apart).  The bins may sit in another grid's workspace (gbin_g)
+// when that scatter reused them.  Four workgroups per bin (a quarter of its
+// particles each) load the tile of the three velocity channels around the
+// bin's block (0 outside the domain or in an inactive block) into LDS; each
+// particle takes its current position (from its record when the runtime
+// knows the records are current, else from x) and, when its 27 nodes lie in
+// the tile, gathers from LDS in the same (a, b, d) order and arithmetic as
+// gather_direct, so the result is bit-identical.  A particle that has left
+// the tile, and every outlier, gathers directly.  When the node's scatter
+// reuses these bins, the records are rewritten with the particle's new
+// velocity and (advected) position.  Otherwise only v is written: particles
+// come in bin order, so the steps that follow a gather in a fused node run
+// as a second, index-ordered pass, where their writes stay coalesced.
 constexpr int kG2PSplit = 4;   // workgroups per bin (each takes a quarter of its particles)
 
 template <int KS>
@@ -1238,19 +1240,21 @@ __global__ __launch_bounds__(256) void k_g2p_bins(PartProg pp) {
     __shared__ float vt[3][kTile3];
     __shared__ int32_t bsl[27];
     const GridDev &S = pp.gsrc;
+    const GridDev &W = pp.gbin_g;
     const int N = S.R * kBS;
     const int64_t np = pp.np;
     const int t = threadIdx.x;
-    const int nb = S.hdr[HDR_NBINS];
-    const int nout = S.hdr[HDR_NOUT];
+    const int nb = W.hdr[HDR_NBINS];
+    const int nout = W.hdr[HDR_NOUT];
     const int nob = (nout + (int)blockDim.x - 1) / (int)blockDim.x;
+    const bool advect = (pp.steps & PS_ADVECT) != 0;
     const float *V0 = chan(S, pp.ch_vsrc), *V1 = chan(S, pp.ch_vsrc + 1), *V2 = chan(S, pp.ch_vsrc + 2);
     const int nit = nb * kG2PSplit;
     for (int it = blockIdx.x; it < nit + nob; it += gridDim.x) {
         if (it >= nit) {
             const int q = (it - nit) * (int)blockDim.x + t;
             if (q < nout) {
-                const int64_t p = S.pout[q];
+                const int64_t p = W.pout[q];
                 const float x[3] = {pp.x[p], pp.x[np + p], pp.x[2 * np + p]};
                 float v[3];
                 gather_direct<KS>(pp, x, v);
@@ -1258,14 +1262,14 @@ __global__ __launch_bounds__(256) void k_g2p_bins(PartProg pp) {
             }
             continue;
         }
-        const int4 bin = S.pbins[it / kG2PSplit];
+        const int4 bin = W.pbins[it / kG2PSplit];
         const int per = (bin.z + kG2PSplit - 1) / kG2PSplit;
         const int q0 = (it % kG2PSplit) * per;
         const int q1 = q0 + per < bin.z ? q0 + per : bin.z;
         if (q0 >= q1) continue;
         int ci, cj, ck;
-        cell_coords(S, bin.x, ci, cj, ck);
-        const int oi = ci * kBS - 1, oj = cj * kBS - 1, ok = ck * kBS - 1;
+        cell_coords(W, bin.x, ci, cj, ck);
+        const int oi = ci * kBS - 2, oj = cj * kBS - 2, ok = ck * kBS - 2;
         if (t < 27) {
             const int bi = ci - 1 + t / 9, bj = cj - 1 + (t / 3) % 3, bk = ck - 1 + t % 3;
             const bool in = bi >= 0 && bj >= 0 && bk >= 0 && bi < S.R && bj < S.R && bk < S.R;
@@ -1273,7 +1277,7 @@ __global__ __launch_bounds__(256) void k_g2p_bins(PartProg pp) {
         }
         __syncthreads();
         for (int nn = t; nn < kTile3; nn += blockDim.x) {
-            const int i = oi + nn / 100, j = oj + (nn / 10) % 10, k = ok + nn % 10;
+            const int i = oi + nn / (kTile * kTile), j = oj + (nn / kTile) % kTile, k = ok + nn % kTile;
             float a0 = 0.f, a1 = 0.f, a2 = 0.f;
             if (i >= 0 && j >= 0 && k >= 0 && i < N && j < N && k < N) {
                 const int32_t sl = bsl[((i >> 3) - ci + 1) * 9 + ((j >> 3) - cj + 1) * 3 + ((k >> 3) - ck + 1)];
@@ -1285,11 +1289,13 @@ __global__ __launch_bounds__(256) void k_g2p_bins(PartProg pp) {
             vt[0][nn] = a0; vt[1][nn] = a1; vt[2][nn] = a2;
         }
         __syncthreads();
+        float4 *const rec = W.pstage + 2 * (int64_t)bin.y;
         for (int q = q0 + t; q < q1; q += blockDim.x) {
-            const int64_t p = __float_as_int(S.pstage[2 * ((int64_t)bin.y + q) + 1].w);
+            const float4 rb = rec[2 * q + 1];
+            const int64_t p = __float_as_int(rb.w);
             float x[3];
             if (pp.g2p_rec_x) {
-                const float4 ra = S.pstage[2 * ((int64_t)bin.y + q)];
+                const float4 ra = rec[2 * q];
                 x[0] = ra.x; x[1] = ra.y; x[2] = ra.z;
             } else {
                 x[0] = pp.x[p]; x[1] = pp.x[np + p]; x[2] = pp.x[2 * np + p];
@@ -1299,7 +1305,7 @@ __global__ __launch_bounds__(256) void k_g2p_bins(PartProg pp) {
             for (int c = 0; c < 3; ++c) base[c] = bspline(x[c] * pp.inv_dx_src, w[c]);
             const int ri = base[0] - oi, rj = base[1] - oj, rk = base[2] - ok;
             float v[3];
-            if ((unsigned)ri < 8u && (unsigned)rj < 8u && (unsigned)rk < 8u) {
+            if ((unsigned)ri < kTile - 2u && (unsigned)rj < kTile - 2u && (unsigned)rk < kTile - 2u) {
                 float acc[3] = {0.f, 0.f, 0.f};
                 for (int a = 0; a < 3; ++a) {
                     for (int bb = 0; bb < 3; ++bb) {
@@ -1318,6 +1324,13 @@ __global__ __launch_bounds__(256) void k_g2p_bins(PartProg pp) {
                 gather_direct<KS>(pp, x, v);
             }
             pp.v[p] = v[0]; pp.v[np + p] = v[1]; pp.v[2 * np + p] = v[2];
+            if (pp.p2g_reuse) {
+                // the same arithmetic as the index-ordered advection
+                if (advect)
+                    for (int c = 0; c < 3; ++c) x[c] = x[c] + pp.dt * v[c];
+                rec[2 * q] = make_float4(x[0], x[1], x[2], v[0]);
+                rec[2 * q + 1] = make_float4(v[1], v[2], rb.z, rb.w);
+            }
         }
         __syncthreads();
     }
@@ -1432,91 +1445,177 @@ __global__ __launch_bounds__(256) void k_bin_place(PartProg pp) {
     }
 }
 
-// One workgroup per bin (root cell c): every node a particle of the bin
-// touches lies in [8c - 1, 8c + 8] per axis, a 10^3 tile held in LDS with
-// the four channels (m, mv) of a node side by side.  The bin's particles (in
-// chunks of kChunk) are first counting-sorted by centre node (512 per
-// block, integer LDS atomics).  Each thread then owns one centre node per
-// round (two rounds of 256) and sums, in registers, the contributions of its
-// particles to the 27 nodes around it (same per-contribution arithmetic as
-// the direct scatter).  The sums reach the tile in 27 phases, one per node
-// offset, separated by barriers: within a phase distinct centre nodes add to
+// Sort key of a centre node at offset (a, b, c) in [0, 9]^3 from 8 x cell - 1
+// (the bin's block is [1, 8]^3): the 512 nodes inside the block first, in
+// (a, b, c) order, then the 488 around it (the two a-faces, then the two
+// b-faces, then the two c-faces of what is left).  centre_of_key inverts it.
+__device__ __forceinline__ int centre_key(int a, int b, int c) {
+    const bool ia = a >= 1 && a <= 8, ib = b >= 1 && b <= 8, ic = c >= 1 && c <= 8;
+    if (ia && ib && ic) return ((a - 1) * 8 + (b - 1)) * 8 + (c - 1);
+    if (!ia) return 512 + (a == 9 ? 100 : 0) + b * 10 + c;
+    if (!ib) return 712 + (a - 1) * 20 + (b == 9 ? 10 : 0) + c;
+    return 872 + (a - 1) * 16 + (b - 1) * 2 + (c == 9 ? 1 : 0);
+}
+
+__device__ __forceinline__ void centre_of_key(int key, int &a, int &b, int &c) {
+    if (key < 512) {
+        a = 1 + (key >> 6); b = 1 + ((key >> 3) & 7); c = 1 + (key & 7);
+        return;
+    }
+    int h = key - 512;
+    if (h < 200) {
+        a = h < 100 ? 0 : 9; b = (h % 100) / 10; c = h % 10;
+        return;
+    }
+    h -= 200;
+    if (h < 160) {
+        a = 1 + h / 20; b = (h % 20) < 10 ? 0 : 9; c = h % 10;
+        return;
+    }
+    h -= 160;
+    a = 1 + h / 16; b = 1 + (h % 16) / 2; c = (h & 1) ? 9 : 0;
+}
+
+// One workgroup per bin (root cell c) of the bins in gbin_s (the
+// destination's own, just made, or reused ones whose records the node's
+// gather has brought up to date).  The nodes a bin's particles touch form a
+// tile held in LDS with the four channels (m, mv) of a node side by side:
+// [8c - 1, 8c + 8] per axis for bins just made (every centre node lies in
+// the block), [8c - 2, 8c + 9] when WIDE, for reused bins, whose particles
+// may have moved one node past the block (one further, they scatter
+// directly).  The bin's particles (in chunks) are first counting-sorted by
+// centre node (integer LDS atomics).  Each thread then owns one centre node
+// per round (rounds of 256; a round with no particles in the workgroup is
+// skipped) and sums, in registers, the contributions of its particles to the
+// 27 nodes around it (same per-contribution arithmetic as the direct
+// scatter).  The sums reach the tile in 27 phases, one per node offset,
+// separated by barriers: within a phase distinct centre nodes add to
 // distinct tile nodes, so each add is a plain LDS read and write (LDS float
 // atomics are slow on this hardware) and the tile's summation order is
 // fixed.  The touched blocks among the 27 around c are activated (or were,
 // per node, when ACT == AT_ACT_PER_NODE) and the tile's non-zero values are
-// added to the grid with one global atomic per node and channel.
+// added to the grid with one global atomic per node and channel.  When
+// reusing, workgroups past the bins scatter the outliers listed with the
+// bins directly, from the particle arrays.
 
-template <int KD, int ACT>
+template <int KD, int ACT, bool WIDE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_p2g_bins(PartProg pp) {
-    __shared__ float4 tile[kTile3];
+    constexpr int TE = WIDE ? 12 : 10, T3 = TE * TE * TE;   // tile edge and nodes
+    constexpr int HALO = WIDE ? 2 : 1;                       // tile origin 8c - HALO
+    constexpr int NC = WIDE ? 10 : 8;                        // centre-node range edge, from 8c - HALO + 1
+    constexpr int KEYS = WIDE ? 1024 : 512, KPT = KEYS / 256; // sort keys (padded), per thread
+    constexpr int CHUNK = WIDE ? 3072 : 4096;
+    __shared__ float4 tile[T3];
     __shared__ int32_t tslot[27];
     __shared__ int32_t tflag[27];
-    __shared__ int32_t ncnt[512];        // particles per centre node, then first sorted position
+    __shared__ int32_t ncnt[KEYS];       // particles per centre-node key, then first sorted position
     __shared__ int32_t wsum[4];
-    __shared__ uint16_t order[kChunk];   // chunk-relative particle index, sorted by centre node
-    __shared__ int32_t lrank[kChunk];    // centre node << 16 | rank among the chunk's particles there
+    __shared__ int32_t nplaced;          // particles of the chunk summed in the tile
+    __shared__ uint16_t order[CHUNK];    // chunk-relative particle index, sorted by centre node
+    __shared__ int32_t lrank[CHUNK];     // key << 16 | rank among the chunk's particles there; -1 direct
     const GridDev &g = pp.gdst;
+    const GridDev &W = pp.gbin_s;
     const int N = g.R * kBS;
-    const int nbins = g.hdr[HDR_NBINS];
+    const int nbins = W.hdr[HDR_NBINS];
+    const int nout = pp.p2g_reuse ? W.hdr[HDR_NOUT] : 0;
+    const int nob = (nout + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int64_t np = pp.np;
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     float *const M = chan(g, pp.ch_m), *const MV0 = chan(g, pp.ch_mv), *const MV1 = chan(g, pp.ch_mv + 1),
                  *const MV2 = chan(g, pp.ch_mv + 2);
-    for (int b = blockIdx.x; b < nbins; b += gridDim.x) {
-        const int4 bin = g.pbins[b];
+    for (int b = blockIdx.x; b < nbins + nob; b += gridDim.x) {
+        if (b >= nbins) {
+            const int q = (b - nbins) * (int)blockDim.x + t;
+            if (q < nout) {
+                const int64_t p = W.pout[q];
+                const float x[3] = {pp.x[p], pp.x[np + p], pp.x[2 * np + p]};
+                const float v[3] = {pp.v[p], pp.v[np + p], pp.v[2 * np + p]};
+                float w[3][3];
+                int base[3];
+                for (int c = 0; c < 3; ++c) base[c] = bspline(x[c] * pp.inv_dx_dst, w[c]);
+                scatter_direct<KD, ACT>(pp, base, w, v, pp.m[p]);
+            }
+            continue;
+        }
+        const int4 bin = W.pbins[b];
         int ci, cj, ck;
-        cell_coords(g, bin.x, ci, cj, ck);
-        const int oi = ci * kBS - 1, oj = cj * kBS - 1, ok = ck * kBS - 1;
-        for (int q = t; q < kTile3; q += blockDim.x) tile[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        cell_coords(W, bin.x, ci, cj, ck);
+        const int oi = ci * kBS - HALO, oj = cj * kBS - HALO, ok = ck * kBS - HALO;
+        for (int q = t; q < T3; q += blockDim.x) tile[q] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (t < 27) tflag[t] = 0;
-        for (int c0 = 0; c0 < bin.z; c0 += kChunk) {
-            const int n = bin.z - c0 < kChunk ? bin.z - c0 : kChunk;
-            const float4 *const rec = g.pstage + 2 * ((int64_t)bin.y + c0);
-            for (int q = t; q < 512; q += blockDim.x) ncnt[q] = 0;
+        for (int c0 = 0; c0 < bin.z; c0 += CHUNK) {
+            const int n = bin.z - c0 < CHUNK ? bin.z - c0 : CHUNK;
+            const float4 *const rec = W.pstage + 2 * ((int64_t)bin.y + c0);
+            for (int q = t; q < KEYS; q += blockDim.x) ncnt[q] = 0;
             __syncthreads();
-            // centre node (base + 1 per axis, inside block c) of each particle
+            // centre node (base + 1 per axis) of each particle, as an offset
+            // in [0, NC) from 8c - HALO + 1 when it fits the tile
             for (int q = t; q < n; q += blockDim.x) {
                 const float4 ra = rec[2 * q];
-                const int hi = (int)floorf(ra.x * pp.inv_dx_dst - 0.5f) + 1 - ci * kBS;
-                const int hj = (int)floorf(ra.y * pp.inv_dx_dst - 0.5f) + 1 - cj * kBS;
-                const int hk = (int)floorf(ra.z * pp.inv_dx_dst - 0.5f) + 1 - ck * kBS;
-                const int node = (hi * kBS + hj) * kBS + hk;
-                lrank[q] = (node << 16) | atomicAdd(&ncnt[node], 1);
+                const int ha = (int)floorf(ra.x * pp.inv_dx_dst - 0.5f) + HALO - ci * kBS;
+                const int hb = (int)floorf(ra.y * pp.inv_dx_dst - 0.5f) + HALO - cj * kBS;
+                const int hc = (int)floorf(ra.z * pp.inv_dx_dst - 0.5f) + HALO - ck * kBS;
+                if ((unsigned)ha < (unsigned)NC && (unsigned)hb < (unsigned)NC && (unsigned)hc < (unsigned)NC) {
+                    const int key = WIDE ? centre_key(ha, hb, hc) : (ha * 8 + hb) * 8 + hc;
+                    lrank[q] = (key << 16) | atomicAdd(&ncnt[key], 1);
+                } else {
+                    lrank[q] = -1;
+                    const float4 rb = rec[2 * q + 1];
+                    const float x[3] = {ra.x, ra.y, ra.z};
+                    const float v[3] = {ra.w, rb.x, rb.y};
+                    float w[3][3];
+                    int base[3];
+                    for (int c = 0; c < 3; ++c) base[c] = bspline(x[c] * pp.inv_dx_dst, w[c]);
+                    scatter_direct<KD, ACT>(pp, base, w, v, rb.z);
+                }
             }
             __syncthreads();
-            // exclusive scan of the 512 counts (two per thread)
-            const int a0 = ncnt[2 * t], a1 = ncnt[2 * t + 1];
-            const int incl = wave_incl_scan(a0 + a1);
+            // exclusive scan of the counts (KPT consecutive keys per thread)
+            int cnt[KPT], tot = 0;
+#pragma unroll
+            for (int e = 0; e < KPT; ++e) tot += (cnt[e] = ncnt[KPT * t + e]);
+            const int incl = wave_incl_scan(tot);
             if (lane == 63) wsum[wid] = incl;
             __syncthreads();
-            int before = incl - a0 - a1;
+            int before = incl - tot;
             for (int w = 0; w < wid; ++w) before += wsum[w];
-            ncnt[2 * t] = before;
-            ncnt[2 * t + 1] = before + a0;
+#pragma unroll
+            for (int e = 0; e < KPT; ++e) {
+                ncnt[KPT * t + e] = before;
+                before += cnt[e];
+            }
+            if (t == 255) nplaced = before;
             __syncthreads();
             for (int q = t; q < n; q += blockDim.x) {
                 const int lr = lrank[q];
-                order[ncnt[lr >> 16] + (lr & 0xffff)] = (uint16_t)q;
+                if (lr >= 0) order[ncnt[lr >> 16] + (lr & 0xffff)] = (uint16_t)q;
             }
             __syncthreads();
-            for (int round = 0; round < 2; ++round) {
-                const int own = round * 256 + t;   // = (li * 8 + lj) * 8 + lk
-                const int li = own >> 6, lj = (own >> 3) & 7, lk = own & 7;
+            for (int round = 0; round < KPT; ++round) {
+                const int own = round * 256 + t;   // centre-node key
                 const int p0 = ncnt[own];
-                const int p1 = own + 1 < 512 ? ncnt[own + 1] : n;
+                const int pe = own < KEYS - 1 ? ncnt[own + 1] : nplaced;
+                const bool any = p0 < pe;
+                if (!__syncthreads_or(any)) continue;
+                int la = 0, lb = 0, lc = 0;
+                if (WIDE) {
+                    if (own < 1000) centre_of_key(own, la, lb, lc);
+                } else {
+                    la = own >> 6; lb = (own >> 3) & 7; lc = own & 7;
+                }
                 float acc[27][4];
 #pragma unroll
                 for (int e = 0; e < 27; ++e) acc[e][0] = acc[e][1] = acc[e][2] = acc[e][3] = 0.f;
                 // the next particle's record is loaded while the current one is summed
                 float4 na = make_float4(0.f, 0.f, 0.f, 0.f), nb = na;
-                if (p0 < p1) {
+                if (any) {
                     const int q = order[p0];
                     na = rec[2 * q];
                     nb = rec[2 * q + 1];
                 }
-                for (int pos = p0; pos < p1; ++pos) {
+                for (int pos = p0; pos < pe; ++pos) {
                     const float4 ra = na, rb = nb;
-                    const int q = order[pos + 1 < p1 ? pos + 1 : pos];
+                    const int q = order[pos + 1 < pe ? pos + 1 : pos];
                     na = rec[2 * q];
                     nb = rec[2 * q + 1];
                     const float x[3] = {ra.x, ra.y, ra.z};
@@ -1548,16 +1647,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                         }
                     }
                 }
-                // node offset e = (a * 3 + b) * 3 + d reaches tile node
-                // (li + a, lj + b, lk + d), global node (8c - 1) + that
-                const bool any = p0 < p1;
+                // node offset e = (a * 3 + b) * 3 + d of centre (la, lb, lc)
+                // is tile node (la + a, lb + b, lc + d)
 #pragma unroll
                 for (int e = 0; e < 27; ++e) {
                     __syncthreads();
                     const int a = e / 9, bb = (e / 3) % 3, d = e % 3;
-                    const int i = oi + li + a, j = oj + lj + bb, kk = ok + lk + d;
+                    const int i = oi + la + a, j = oj + lb + bb, kk = ok + lc + d;
                     if (any && i >= 0 && j >= 0 && kk >= 0 && i < N && j < N && kk < N) {
-                        const int nn = ((li + a) * kTile + (lj + bb)) * kTile + (lk + d);
+                        const int nn = ((la + a) * TE + (lb + bb)) * TE + (lc + d);
                         float4 cur = tile[nn];
                         cur.x = cur.x + acc[e][0];
                         cur.y = cur.y + acc[e][1];
@@ -1580,8 +1678,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             tslot[t] = sl;
         }
         __syncthreads();
-        for (int nn = t; nn < kTile3; nn += blockDim.x) {
-            const int i = oi + nn / 100, j = oj + (nn / 10) % 10, k = ok + nn % 10;
+        for (int nn = t; nn < T3; nn += blockDim.x) {
+            const int i = oi + nn / (TE * TE), j = oj + (nn / TE) % TE, k = ok + nn % TE;
             if (i < 0 || j < 0 || k < 0 || i >= N || j >= N || k >= N) continue;
             const int32_t sl = tslot[((i >> 3) - ci + 1) * 9 + ((j >> 3) - cj + 1) * 3 + ((k >> 3) - ck + 1)];
             if (sl < 0) continue;
@@ -1818,7 +1916,7 @@ template <int KS, int KD, uint32_t STEPS, int ACT, bool BIN>
 static void launch_part_first(const PartProg &pp, dim3 grid, hipStream_t s) {
     if constexpr ((STEPS & PS_G2P) != 0) {
         if (pp.g2p_bins) {
-            const int64_t nb = pp.gsrc.ncells * kG2PSplit < 256 * 8 ? pp.gsrc.ncells * kG2PSplit : 256 * 8;
+            const int64_t nb = pp.gbin_g.ncells * kG2PSplit < 256 * 8 ? pp.gbin_g.ncells * kG2PSplit : 256 * 8;
             hipLaunchKernelGGL(k_g2p_bins<KS>, dim3((unsigned)nb), dim3(256), 0, s, pp);
             constexpr uint32_t REST = STEPS & ~(uint32_t)PS_G2P;
             if constexpr (REST != 0) hipLaunchKernelGGL((k_particles<KS, KD, REST, ACT, BIN>), grid, dim3(256), 0, s, pp);
@@ -1828,9 +1926,33 @@ static void launch_part_first(const PartProg &pp, dim3 grid, hipStream_t s) {
     hipLaunchKernelGGL((k_particles<KS, KD, STEPS, ACT, BIN>), grid, dim3(256), 0, s, pp);
 }
 
+// Tiles over bins just made (narrow) or reused (wide).
+template <int KD, bool WIDE>
+static void launch_p2g_tiles(const PartProg &pp, hipStream_t s) {
+    const int64_t nb = pp.gbin_s.ncells < 256 * 8 ? pp.gbin_s.ncells : 256 * 8;
+    if (pp.act_mode == AT_ACT_PER_BLOCK)
+        hipLaunchKernelGGL((k_p2g_bins<KD, AT_ACT_PER_BLOCK, WIDE>), dim3((unsigned)nb), dim3(256), 0, s, pp);
+    else if (pp.act_mode == AT_ACT_NONE)
+        hipLaunchKernelGGL((k_p2g_bins<KD, AT_ACT_NONE, WIDE>), dim3((unsigned)nb), dim3(256), 0, s, pp);
+    else
+        hipLaunchKernelGGL((k_p2g_bins<KD, AT_ACT_PER_NODE, WIDE>), dim3((unsigned)nb), dim3(256), 0, s, pp);
+}
+
 template <int KS, int KD, uint32_t STEPS>
 static void launch_part_a(const PartProg &pp, dim3 grid, bool bin, hipStream_t s) {
     constexpr bool P2G = (STEPS & PS_P2G) != 0;
+    if constexpr ((STEPS & PS_G2P) != 0 && P2G) {
+        if (bin && pp.p2g_reuse) {
+            // gather through the bins (rewriting their records), advection
+            // in particle order, scatter over the same bins
+            const int64_t nb = pp.gbin_g.ncells * kG2PSplit < 256 * 8 ? pp.gbin_g.ncells * kG2PSplit : 256 * 8;
+            hipLaunchKernelGGL(k_g2p_bins<KS>, dim3((unsigned)nb), dim3(256), 0, s, pp);
+            if constexpr ((STEPS & PS_ADVECT) != 0)
+                hipLaunchKernelGGL((k_particles<KS, KD, PS_ADVECT, AT_ACT_PER_NODE, false>), grid, dim3(256), 0, s, pp);
+            launch_p2g_tiles<KD, true>(pp, s);
+            return;
+        }
+    }
     if (P2G && bin) {
         // cell keys (with the gather and advection), ranks, scan, place, scatter per bin
         if (pp.act_mode == AT_ACT_PER_BLOCK)
@@ -1845,13 +1967,7 @@ static void launch_part_a(const PartProg &pp, dim3 grid, bool bin, hipStream_t s
             hipLaunchKernelGGL(k_bin_rank<false>, dim3(1024), dim3(1024), 0, s, pp.gdst, pp.np);
         hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, pp.gdst);
         hipLaunchKernelGGL(k_bin_place, grid, dim3(256), 0, s, pp);
-        const int64_t nb = pp.gdst.ncells < 256 * 8 ? pp.gdst.ncells : 256 * 8;
-        if (pp.act_mode == AT_ACT_PER_BLOCK)
-            hipLaunchKernelGGL((k_p2g_bins<KD, AT_ACT_PER_BLOCK>), dim3((unsigned)nb), dim3(256), 0, s, pp);
-        else if (pp.act_mode == AT_ACT_NONE)
-            hipLaunchKernelGGL((k_p2g_bins<KD, AT_ACT_NONE>), dim3((unsigned)nb), dim3(256), 0, s, pp);
-        else
-            hipLaunchKernelGGL((k_p2g_bins<KD, AT_ACT_PER_NODE>), dim3((unsigned)nb), dim3(256), 0, s, pp);
+        launch_p2g_tiles<KD, false>(pp, s);
         return;
     }
     if (pp.act_mode == AT_ACT_PER_BLOCK)
@@ -1880,7 +1996,10 @@ hipError_t launch_particles(const PartProg &pp, hipStream_t s, int *dispatches) 
     // the scatter is binned when the destination grid has room for every particle
     const bool bin = (pp.steps & PS_P2G) && pp.gdst.pcap >= pp.np;
     const bool split = pp.g2p_bins && (pp.steps & PS_G2P) && (pp.steps & ~(uint32_t)PS_G2P);
-    *dispatches = (bin ? 5 : 1) + (split ? 1 : 0);
+    if (bin && pp.p2g_reuse && (pp.steps & PS_G2P))
+        *dispatches = (pp.steps & PS_ADVECT) ? 3 : 2;
+    else
+        *dispatches = (bin ? 5 : 1) + (split ? 1 : 0);
     int64_t blocks = (pp.np + 255) / 256;
     if (blocks < 1) blocks = 1;
     if (blocks > 256 * 64) blocks = 256 * 64;

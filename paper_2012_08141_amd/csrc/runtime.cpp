@@ -58,6 +58,8 @@ struct Engine {
     uint32_t opt_flags = AT_OPT_ALL;
     bool plan_cache = true;
     bool g2p_bins = true;   // gathers may use the source grid's bins
+    int32_t bin_reuse = 8;  // scatters that may reuse a binning before the particles are binned again
+    std::unordered_map<uint64_t, at_grid_s *> live;   // device grids by uid
     // Inside one window only its own nodes touch external arrays, so a
     // binned scatter's particle records still hold the current positions
     // when the same window has not advected those positions since.
@@ -80,6 +82,12 @@ struct Engine {
 Engine &E() {
     static Engine *e = new Engine();
     return *e;
+}
+
+at_grid_s *live_grid(uint64_t uid) {
+    Engine &en = E();
+    const auto it = en.live.find(uid);
+    return it == en.live.end() ? nullptr : it->second;
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -212,10 +220,6 @@ at_status execute_node(const Node &nd, const at_task *tasks, bool table, hipStre
             }
         }
         if (pp.np == 0) return AT_OK;
-        // The gather may go through the source grid's bins when its last
-        // binned scatter had exactly these many particles (the bins then
-        // hold each index once) and the same node does not bin into that
-        // grid again while reading them.
         at_grid_s *src = nullptr, *dst = nullptr;
         for (const Member &m : nd.members) {
             const at_task &t = tasks[m.task];
@@ -224,13 +228,29 @@ at_status execute_node(const Node &nd, const at_task *tasks, bool table, hipStre
         }
         Engine &en = E();
         const bool bin_dst = dst && dst->dev.pcap >= pp.np;
-        pp.g2p_bins = src && src->bins_np == pp.np && !(bin_dst && dst == src) && en.g2p_bins ? 1 : 0;
+        // The gather may go through the bins of the source grid's last
+        // binned scatter when it had exactly these many particles (the bins
+        // then hold each index once) and the workspace holding them has not
+        // been rebinned or cleared since.
+        at_grid_s *own = src && src->bins_np == pp.np ? live_grid(src->bins_owner) : nullptr;
+        if (own && (own->ws_gen != src->bins_owner_gen || own->dev.R != src->dev.R)) own = nullptr;
+        // (a scatter of the same node that bins into that workspace runs in
+        // later dispatches, after the gather has read it)
+        pp.g2p_bins = own && en.g2p_bins ? 1 : 0;
         // the records' positions are current when they were written in this
         // window from this array and nothing has advected it since
         const auto pw = en.pos_writes.find(pp.x);
         const int64_t writes = pw == en.pos_writes.end() ? 0 : pw->second;
         pp.g2p_rec_x = pp.g2p_bins && src->bins_window == en.window_seq && src->bins_x == pp.x &&
                        src->bins_writes == writes ? 1 : 0;
+        if (pp.g2p_bins) pp.gbin_g = own->dev;
+        // A gather-advect-scatter node whose gather goes through current
+        // records may scatter over the same bins (the gather updates the
+        // records first), up to bin_reuse times before the particles are
+        // binned again.
+        pp.p2g_reuse = bin_dst && pp.g2p_rec_x && dst != src && own->bins_age < en.bin_reuse &&
+                       own->dev.R == dst->dev.R && own->bins_inv_dx == pp.inv_dx_dst ? 1 : 0;
+        pp.gbin_s = pp.p2g_reuse ? own->dev : (dst ? dst->dev : GridDev{});
         int ndisp = 1;
         e = launch_particles(pp, s, &ndisp);
         if (e != hipSuccess) return hip_fail(e, "kernel launch");
@@ -241,6 +261,17 @@ at_status execute_node(const Node &nd, const at_task *tasks, bool table, hipStre
             dst->bins_x = pp.x;
             dst->bins_window = en.window_seq;
             dst->bins_writes = after;
+            if (pp.p2g_reuse) {
+                own->bins_age += 1;
+                dst->bins_owner = own->uid;
+                dst->bins_owner_gen = own->ws_gen;
+            } else {
+                dst->ws_gen += 1;
+                dst->bins_age = 0;
+                dst->bins_inv_dx = pp.inv_dx_dst;
+                dst->bins_owner = dst->uid;
+                dst->bins_owner_gen = dst->ws_gen;
+            }
         }
         E().dispatches.fetch_add(ndisp);
         return AT_OK;
@@ -465,6 +496,7 @@ at_status at_grid_create(const at_grid_desc *desc, void *dev_buf, size_t bytes, 
     {
         std::lock_guard<std::recursive_mutex> lk(E().mu);
         g->uid = E().next_uid++;
+        E().live[g->uid] = g;
     }
     *out = g;
     return AT_OK;
@@ -478,6 +510,7 @@ at_status at_grid_destroy(at_grid grid) {
         for (const at_task &t : en.queue)
             if (t.grid == grid) return fail(AT_E_STATE, "grid has queued tasks; flush first");
         en.persist.forget_grid(grid->uid);
+        en.live.erase(grid->uid);
     }
     delete grid;
     return AT_OK;
@@ -529,6 +562,7 @@ at_status at_grid_clear(at_grid grid, hipStream_t stream) {
     if (e != hipSuccess) return hip_fail(e, "grid clear");
     en.dispatches.fetch_add((d.ptr ? 4 : 3) + (d.pcount ? 2 : 0));
     grid->bins_np = 0;
+    grid->ws_gen += 1;
     en.persist.deactivate_grid(grid->uid);
     for (int c = 0; c < grid->desc.channels; ++c) bump(grid->uid, ST_VALUE, c);
     bump(grid->uid, ST_ALLOC, -1);
@@ -817,6 +851,10 @@ at_status at_set_option(int32_t option, int64_t value) {
         if (value != 0 && value != 1) return fail(AT_E_INVALID, "g2p bins must be 0 or 1");
         en.g2p_bins = value != 0;
         return AT_OK;
+    case AT_OPTION_BIN_REUSE:
+        if (value < 0 || value > 1024) return fail(AT_E_INVALID, "bin reuse must be in 0..1024");
+        en.bin_reuse = (int32_t)value;
+        return AT_OK;
     default:
         return fail(AT_E_INVALID, "unknown option %d", option);
     }
@@ -835,6 +873,7 @@ at_status at_get_option(int32_t option, int64_t *value) {
     case AT_OPTION_STRUCT_FOR_KERNEL: *value = struct_for_kernel(); return AT_OK;
     case AT_OPTION_BATCH_WAVES: *value = batch_waves(); return AT_OK;
     case AT_OPTION_G2P_BINS: *value = en.g2p_bins ? 1 : 0; return AT_OK;
+    case AT_OPTION_BIN_REUSE: *value = en.bin_reuse; return AT_OK;
     default: return fail(AT_E_INVALID, "unknown option %d", option);
     }
 }

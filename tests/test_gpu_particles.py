@@ -33,6 +33,14 @@ def gpu():
     torch.cuda.synchronize()
 
 
+@pytest.fixture
+def bin_reuse():
+    from paper_2012_08141_amd import _lib as L, engine as E
+    default = E.get_option(L.AT_OPTION_BIN_REUSE)
+    yield lambda k: E.set_option(L.AT_OPTION_BIN_REUSE, k)
+    E.set_option(L.AT_OPTION_BIN_REUSE, default)
+
+
 def close_state(got, exp, what, scale=None):
     exp = np.asarray(exp, np.float64)
     got = np.asarray(got, np.float64)
@@ -183,6 +191,23 @@ def test_g2p_through_bins_in_one_window(root, shift):
     close_state(got[1], got[0], "g2p bins vs direct, one window")
 
 
+def _binning_extra(steps, reuse):
+    """Dispatches beyond one per node of the optimized particle program with
+    a particle workspace.  Step 0 bins afresh: keys (with the advection),
+    ranks, scan, place, tiles.  Each later step's fused gather-advect-scatter
+    node gathers through the previous scatter's bins and then either scatters
+    over the same bins (gather, advection, tiles) while they have been reused
+    fewer than `reuse` times, or bins afresh (gather, advection with keys,
+    ranks, scan, place, tiles)."""
+    extra, age = 4, 0
+    for _ in range(1, steps):
+        if age < reuse:
+            extra, age = extra + 2, age + 1
+        else:
+            extra, age = extra + 5, 0
+    return extra
+
+
 def _particle_run(p, steps, opt, binned=True):
     from paper_2012_08141_amd import engine as E, programs as PR
     from paper_2012_08141_amd.grid import SparseGrid
@@ -196,21 +221,24 @@ def _particle_run(p, steps, opt, binned=True):
     return grids, x, v, st
 
 
-@pytest.mark.parametrize("binned", [False, True])
+@pytest.mark.parametrize("binned,reuse", [(False, 0), (True, 0), (True, 8)])
 @pytest.mark.parametrize("opt", [0, 15])
-def test_particle_program_reduced(opt, binned):
+def test_particle_program_reduced(opt, binned, reuse, bin_reuse):
     """The particle recipe (3 boxes, N(0, 0.1^2) velocities, dt = 1e-3) with
     100k particles in a 128^3 grid, 20 steps, eager and optimized, direct
-    and binned scatter."""
-    say("particle program opt", opt, "binned" if binned else "direct")
+    and binned scatter, binning every scatter or reusing bins."""
+    say("particle program opt", opt, "binned" if binned else "direct", "reuse", reuse)
+    bin_reuse(reuse)
     p = I.particles(0, n=128, nparticles=100_000)
     grids, x, v, st = _particle_run(p, 20, opt, binned)
     assert st["tasks_launched"] == (140 if opt == 0 else 65)
-    # a binned scatter is 5 dispatches (keys, ranks, scan, place, tiles), one per
-    # step; from the second step on, the gather goes through the bins of the
-    # previous step's scatter, and where it is fused with advection and the
-    # scatter (optimized) those run as one more index-ordered dispatch
-    assert st["dispatches"] == st["tasks_launched"] + (4 * 20 if binned else 0) + (19 if binned and opt else 0)
+    if not binned:
+        assert st["dispatches"] == st["tasks_launched"]
+    elif opt == 0:
+        # every scatter bins (5 dispatches); the separate gathers go through bins
+        assert st["dispatches"] == st["tasks_launched"] + 4 * 20
+    else:
+        assert st["dispatches"] == st["tasks_launched"] + _binning_extra(20, reuse)
     ref = OP.particle_program(p.n, p.x, p.v, p.m, 20, p.params["dt"], "f32")
     sx, sv = 0.1 * np.abs(p.x).max(), 0.1 * np.abs(p.v).max()
     close_state(x.cpu().numpy(), ref["x"], "x", sx)
@@ -218,6 +246,34 @@ def test_particle_program_reduced(opt, binned):
     for gi in (0, 1):
         assert np.array_equal(grids[gi].active_cells(), ref["cells%d" % gi]), gi
         assert grids[gi].device_status() == 0
+
+
+@pytest.mark.parametrize("reuse", [3, 8])
+def test_particle_program_bin_reuse_with_drift(reuse, bin_reuse):
+    """Velocities ten times the recipe's and dt = 2e-3 on a 128^3 grid move a
+    particle about a quarter node per step, so bins reused for several steps
+    hold particles that have moved one node past their block (still summed in
+    the tile) and further (scattered directly).  The state after 12 steps
+    against the oracle, and the same run binning every scatter."""
+    import dataclasses
+    say("particle program bin reuse with drift", reuse)
+    p0 = I.particles(0, n=128, nparticles=100_000)
+    p = dataclasses.replace(p0, v=(p0.v * 10).astype(np.float32), params=dict(p0.params, dt=2e-3))
+    steps = 12
+    ref = OP.particle_program(p.n, p.x, p.v, p.m, steps, p.params["dt"], "f32")
+    sx, sv = 0.1 * np.abs(p.x).max(), 0.1 * np.abs(p.v).max()
+    out = {}
+    for k in (reuse, 0):
+        bin_reuse(k)
+        grids, x, v, st = _particle_run(p, steps, 15)
+        assert st["dispatches"] == st["tasks_launched"] + _binning_extra(steps, k)
+        close_state(x.cpu().numpy(), ref["x"], "x", sx)
+        close_state(v.cpu().numpy(), ref["v"], "v", sv)
+        for gi in (0, 1):
+            assert np.array_equal(grids[gi].active_cells(), ref["cells%d" % gi]), gi
+            assert grids[gi].device_status() == 0
+        out[k] = v.cpu().numpy()
+    close_state(out[reuse], out[0], "v reuse / rebin", sv)
 
 
 def test_particle_full_size_one_step_and_eager_vs_optimized():
