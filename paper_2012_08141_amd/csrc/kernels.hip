@@ -1503,16 +1503,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     constexpr int TE = WIDE ? 12 : 10, T3 = TE * TE * TE;   // tile edge and nodes
     constexpr int HALO = WIDE ? 2 : 1;                       // tile origin 8c - HALO
     constexpr int NC = WIDE ? 10 : 8;                        // centre-node range edge, from 8c - HALO + 1
-    constexpr int KEYS = WIDE ? 1024 : 512, KPT = KEYS / 256; // sort keys (padded), per thread
-    constexpr int CHUNK = WIDE ? 3072 : 4096;
+    constexpr int KEYS = WIDE ? 1024 : 512, KPT = KEYS / 256; // sort keys (wide: 1000 padded), per thread
+    constexpr int CHUNK = 4096;
     __shared__ float4 tile[T3];
     __shared__ int32_t tslot[27];
     __shared__ int32_t tflag[27];
-    __shared__ int32_t ncnt[KEYS];       // particles per centre-node key, then first sorted position
+    __shared__ int32_t ncnt[KEYS];       // particles per centre-node key; then first, then one-past-last position
     __shared__ int32_t wsum[4];
-    __shared__ int32_t nplaced;          // particles of the chunk summed in the tile
+    __shared__ int32_t nhalo;            // wide: non-empty keys outside the block
+    __shared__ int16_t hkeys[WIDE ? 488 : 1];
     __shared__ uint16_t order[CHUNK];    // chunk-relative particle index, sorted by centre node
-    __shared__ int32_t lrank[CHUNK];     // key << 16 | rank among the chunk's particles there; -1 direct
+    // narrow: key << 16 | rank among the chunk's particles there (-1: direct);
+    // wide tiles have no room for it and place by a second pass of keys
+    __shared__ int32_t lrank[WIDE ? 1 : CHUNK];
     const GridDev &g = pp.gdst;
     const GridDev &W = pp.gbin_s;
     const int N = g.R * kBS;
@@ -1543,23 +1546,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         const int oi = ci * kBS - HALO, oj = cj * kBS - HALO, ok = ck * kBS - HALO;
         for (int q = t; q < T3; q += blockDim.x) tile[q] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (t < 27) tflag[t] = 0;
+        // sort key of particle q's centre node (base + 1 per axis, as an
+        // offset in [0, NC) from 8c - HALO + 1), or -1 when it does not fit
+        // the tile
+        auto key_of = [&](const float4 &ra) {
+            const int ha = (int)floorf(ra.x * pp.inv_dx_dst - 0.5f) + HALO - ci * kBS;
+            const int hb = (int)floorf(ra.y * pp.inv_dx_dst - 0.5f) + HALO - cj * kBS;
+            const int hc = (int)floorf(ra.z * pp.inv_dx_dst - 0.5f) + HALO - ck * kBS;
+            if ((unsigned)ha >= (unsigned)NC || (unsigned)hb >= (unsigned)NC || (unsigned)hc >= (unsigned)NC) return -1;
+            return WIDE ? centre_key(ha, hb, hc) : (ha * 8 + hb) * 8 + hc;
+        };
         for (int c0 = 0; c0 < bin.z; c0 += CHUNK) {
             const int n = bin.z - c0 < CHUNK ? bin.z - c0 : CHUNK;
             const float4 *const rec = W.pstage + 2 * ((int64_t)bin.y + c0);
             for (int q = t; q < KEYS; q += blockDim.x) ncnt[q] = 0;
+            if (t == 0) nhalo = 0;
             __syncthreads();
-            // centre node (base + 1 per axis) of each particle, as an offset
-            // in [0, NC) from 8c - HALO + 1 when it fits the tile
+            // count per centre node; a particle that does not fit the tile
+            // scatters directly
             for (int q = t; q < n; q += blockDim.x) {
                 const float4 ra = rec[2 * q];
-                const int ha = (int)floorf(ra.x * pp.inv_dx_dst - 0.5f) + HALO - ci * kBS;
-                const int hb = (int)floorf(ra.y * pp.inv_dx_dst - 0.5f) + HALO - cj * kBS;
-                const int hc = (int)floorf(ra.z * pp.inv_dx_dst - 0.5f) + HALO - ck * kBS;
-                if ((unsigned)ha < (unsigned)NC && (unsigned)hb < (unsigned)NC && (unsigned)hc < (unsigned)NC) {
-                    const int key = WIDE ? centre_key(ha, hb, hc) : (ha * 8 + hb) * 8 + hc;
-                    lrank[q] = (key << 16) | atomicAdd(&ncnt[key], 1);
+                const int key = key_of(ra);
+                if (key >= 0) {
+                    if constexpr (WIDE)
+                        atomicAdd(&ncnt[key], 1);
+                    else
+                        lrank[q] = (key << 16) | atomicAdd(&ncnt[key], 1);
                 } else {
-                    lrank[q] = -1;
+                    if constexpr (!WIDE) lrank[q] = -1;
                     const float4 rb = rec[2 * q + 1];
                     const float x[3] = {ra.x, ra.y, ra.z};
                     const float v[3] = {ra.w, rb.x, rb.y};
@@ -1570,7 +1584,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                 }
             }
             __syncthreads();
-            // exclusive scan of the counts (KPT consecutive keys per thread)
+            // scan of the counts (KPT consecutive keys per thread): narrow
+            // keeps each key's end, wide its start (placement advances it to
+            // the end) and lists the non-empty keys outside the block
             int cnt[KPT], tot = 0;
 #pragma unroll
             for (int e = 0; e < KPT; ++e) tot += (cnt[e] = ncnt[KPT * t + e]);
@@ -1581,27 +1597,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             for (int w = 0; w < wid; ++w) before += wsum[w];
 #pragma unroll
             for (int e = 0; e < KPT; ++e) {
-                ncnt[KPT * t + e] = before;
+                ncnt[KPT * t + e] = WIDE ? before : before + cnt[e];
                 before += cnt[e];
-            }
-            if (t == 255) nplaced = before;
-            __syncthreads();
-            for (int q = t; q < n; q += blockDim.x) {
-                const int lr = lrank[q];
-                if (lr >= 0) order[ncnt[lr >> 16] + (lr & 0xffff)] = (uint16_t)q;
+                if (WIDE && KPT * t + e >= 512 && cnt[e] > 0) hkeys[atomicAdd(&nhalo, 1)] = (int16_t)(KPT * t + e);
             }
             __syncthreads();
-            for (int round = 0; round < KPT; ++round) {
-                const int own = round * 256 + t;   // centre-node key
-                const int p0 = ncnt[own];
-                const int pe = own < KEYS - 1 ? ncnt[own + 1] : nplaced;
+            if constexpr (WIDE) {
+                for (int q = t; q < n; q += blockDim.x) {
+                    const int key = key_of(rec[2 * q]);
+                    if (key >= 0) order[atomicAdd(&ncnt[key], 1)] = (uint16_t)q;
+                }
+            } else {
+                for (int q = t; q < n; q += blockDim.x) {
+                    const int lr = lrank[q];
+                    if (lr < 0) continue;
+                    const int key = lr >> 16;
+                    order[(key > 0 ? ncnt[key - 1] : 0) + (lr & 0xffff)] = (uint16_t)q;
+                }
+            }
+            __syncthreads();
+            // one round: each thread sums the particles of centre-node key
+            // `own` (none when own < 0) and adds the sums to the tile
+            auto round = [&](int own) {
+                const int p0 = own > 0 ? ncnt[own - 1] : 0;
+                const int pe = own >= 0 ? ncnt[own] : 0;
                 const bool any = p0 < pe;
-                if (!__syncthreads_or(any)) continue;
                 int la = 0, lb = 0, lc = 0;
-                if (WIDE) {
-                    if (own < 1000) centre_of_key(own, la, lb, lc);
-                } else {
-                    la = own >> 6; lb = (own >> 3) & 7; lc = own & 7;
+                if (any) {
+                    if (WIDE) {
+                        centre_of_key(own, la, lb, lc);
+                    } else {
+                        la = own >> 6; lb = (own >> 3) & 7; lc = own & 7;
+                    }
                 }
                 float acc[27][4];
 #pragma unroll
@@ -1665,7 +1692,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                         tflag[((i >> 3) - ci + 1) * 9 + ((j >> 3) - cj + 1) * 3 + ((kk >> 3) - ck + 1)] = 1;
                     }
                 }
-            }
+            };
+            // the block's 512 centre nodes, then the listed ones around it
+            for (int r = 0; r < 2; ++r)
+                if (__syncthreads_or(ncnt[r * 256 + t] > (r * 256 + t > 0 ? ncnt[r * 256 + t - 1] : 0)))
+                    round(r * 256 + t);
+            if (WIDE)
+                for (int h0 = 0; h0 < nhalo; h0 += 256) round(h0 + t < nhalo ? hkeys[h0 + t] : -1);
             __syncthreads();
         }
         if (t < 27) {
