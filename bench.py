@@ -35,8 +35,8 @@ HBM_PEAK_GBS = 8000.0
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE), each scaled by the reading
 # for a plain 256 MiB copy in the same run.  Valid only for the kernel
 # source the counters were taken on; any change to it reports null.
-JACOBI_TRAFFIC = {"kernels_sha256": "4b1a1163fc5dfa73bbe85e71a5059f27274d1ff548ece518ddf659e7ce39610e",
-                  "bytes_per_launch": 83376625, "profile": "profiles/band512_jacobi_traffic.md"}
+JACOBI_TRAFFIC = {"kernels_sha256": "78caf51892b164196515e573068510094f72b4dd9f2c0807a63414a3ace5d077",
+                  "bytes_per_launch": 83377446, "profile": "profiles/band512_jacobi_traffic.md"}
 
 
 def _jacobi_traffic():
