@@ -49,6 +49,26 @@ class DiffusionProblem:
         self.grid.load_blocks(0, self.cells, z)          # activates the blocks
         E.run_sequence([E.listgen(self.grid)], self.opt)
         self.windows = 0
+        # the windows' tasks never change: pack them once
+        fwd = []
+        for s in range(self.nseg):
+            nxt = self.ck[s + 1] if s + 1 < self.nseg else None
+            t, self.last = self._segment_tasks(s, self.seg_len(s), nxt)
+            fwd += t
+        self.fwd = E.prepare(fwd)
+        g = self.grid
+        self.bwd_init = E.prepare([E.listgen(g), E.fill(g, [self.GK], 0.0)])
+        self.bwd = []
+        lamn, lam = self.LA, self.LB
+        for s in reversed(range(self.nseg)):
+            L = self.seg_len(s)
+            tasks, _ = self._segment_tasks(s, L - 1) if L > 1 else ([E.listgen(g)], None)
+            states = [self.ck[s]] + [self.seg[i] for i in range(1, L)]
+            for i in reversed(range(L)):
+                tasks.append(E.diffuse_adj(g, states[i], self.K, lamn, lam, self.GK, self.dt))
+                lamn, lam = lam, lamn
+            self.bwd.append(E.prepare(tasks))
+        self.lam_out = lamn
 
     # ---- helpers --------------------------------------------------------------
     def _put(self, ch: int, t: torch.Tensor):
@@ -77,32 +97,22 @@ class DiffusionProblem:
 
     # ---- forward / backward -------------------------------------------------
     def forward(self, a0: torch.Tensor, k: torch.Tensor) -> torch.Tensor:
-        """a_T on the active blocks ([nb, 512]); stores the checkpoints."""
+        """a_T on the active blocks ([nb, 512], a new tensor); stores the
+        checkpoints."""
         self._put(self.ck[0], a0)
         self._put(self.K, k)
-        tasks, last = [], None
-        for s in range(self.nseg):
-            nxt = self.ck[s + 1] if s + 1 < self.nseg else None
-            t, last = self._segment_tasks(s, self.seg_len(s), nxt)
-            tasks += t
-        self._run(tasks)
-        return self._get(last).clone()
+        self._run(self.fwd)
+        return self._get(self.last)
 
     def backward(self, lam_T: torch.Tensor):
-        """(grad_a0, grad_k) for adjoint seed lam_T = dL/da_T."""
-        g = self.grid
+        """(grad_a0, grad_k) for adjoint seed lam_T = dL/da_T (new tensors).
+        Per segment, in reverse: recompute its states from the checkpoint,
+        then run the adjoint steps back through them."""
         self._put(self.LA, lam_T)
-        self._run([E.listgen(g), E.fill(g, [self.GK], 0.0)])
-        lamn, lam = self.LA, self.LB
-        for s in reversed(range(self.nseg)):
-            L = self.seg_len(s)
-            tasks, _ = self._segment_tasks(s, L - 1) if L > 1 else ([E.listgen(g)], None)
-            states = [self.ck[s]] + [self.seg[i] for i in range(1, L)]
-            for i in reversed(range(L)):
-                tasks.append(E.diffuse_adj(g, states[i], self.K, lamn, lam, self.GK, self.dt))
-                lamn, lam = lam, lamn
-            self._run(tasks)
-        return self._get(lamn).clone(), self._get(self.GK).clone()
+        self._run(self.bwd_init)
+        for w in self.bwd:
+            self._run(w)
+        return self._get(self.lam_out), self._get(self.GK)
 
 
 class DiffusionLoss(torch.autograd.Function):

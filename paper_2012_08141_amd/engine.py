@@ -149,11 +149,29 @@ def _array(tasks):
     return arr
 
 
+class Prepared:
+    """A window's task descriptors packed once, for windows that run the same
+    tasks again (the arrays and grids they point at stay alive with it)."""
+
+    def __init__(self, tasks):
+        self.arr = _array(tasks)
+        self.n = len(tasks)
+        self.keep = [t.keep for t in tasks]
+
+
+def prepare(tasks) -> Prepared:
+    return Prepared(tasks)
+
+
 def run_sequence(tasks, opt_flags: int = OPT_ALL, stream=None) -> dict:
-    """Plan and launch a window of tasks; returns the window's counters."""
-    arr = _array(tasks)
+    """Plan and launch a window of tasks (a list, or a Prepared window);
+    returns the window's counters."""
+    if isinstance(tasks, Prepared):
+        arr, n = tasks.arr, tasks.n
+    else:
+        arr, n = _array(tasks), len(tasks)
     st = L.AtStats()
-    L.check(L.lib().at_run_sequence(arr, len(tasks), opt_flags, ctypes.byref(st),
+    L.check(L.lib().at_run_sequence(arr, n, opt_flags, ctypes.byref(st),
                                     stream if stream is not None else current_stream()))
     return st.as_dict()
 
