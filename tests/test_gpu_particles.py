@@ -276,6 +276,46 @@ def test_particle_program_bin_reuse_with_drift(reuse, bin_reuse):
     close_state(out[reuse], out[0], "v reuse / rebin", sv)
 
 
+@pytest.mark.parametrize("how", ["clear", "destroy"])
+def test_reused_bins_are_not_used_after_their_workspace_goes(how, bin_reuse):
+    """Two steps of the particle program in one window: the second step's
+    scatter into grid 1 reuses the bins held in grid 0's workspace.  Once
+    grid 0 is cleared (its workspace generation moves on) or destroyed (it
+    leaves the engine's registry), a gather from grid 1 must not use those
+    bins: it equals the per-particle gather bit for bit."""
+    import gc
+    from paper_2012_08141_amd import _lib as L, engine as E, programs as PR
+    from paper_2012_08141_amd.grid import SparseGrid
+    say("reused bins after", how)
+    bin_reuse(8)
+    p = I.particles(0, n=128, nparticles=50_000)
+    n = p.n
+    grids = [SparseGrid(n, 7, "pointer", (n // 8) ** 3, particle_capacity=p.nparticles) for _ in range(2)]
+    x, v, m = PR.device_particles(p)
+    tasks = sum((PR.particle_step(grids, t, x, v, m, p.params["dt"], 1.0 / n) for t in range(2)), [])
+    st = E.run_sequence(tasks, E.OPT_ALL)
+    torch.cuda.synchronize()
+    assert st["dispatches"] == st["tasks_launched"] + _binning_extra(2, 8)   # the second scatter reused
+    g1 = grids[1]
+    want = torch.zeros_like(x)
+    try:
+        E.set_option(L.AT_OPTION_G2P_BINS, 0)
+        E.run_sequence([E.g2p(g1, x, want, 1.0 / n, PR.PART["v"])], 0)
+    finally:
+        E.set_option(L.AT_OPTION_G2P_BINS, 1)
+    if how == "clear":
+        grids[0].clear()
+    else:
+        grids[0] = None
+        del tasks          # the tasks hold the grid too
+        gc.collect()
+    got = torch.zeros_like(x)
+    E.run_sequence([E.g2p(g1, x, got, 1.0 / n, PR.PART["v"])], 0)
+    torch.cuda.synchronize()
+    assert torch.equal(got, want)
+    assert g1.device_status() == 0
+
+
 def test_particle_full_size_one_step_and_eager_vs_optimized():
     """The particle workload at full size (2M particles, 256^3): one step against the
     oracle; 20 steps optimized against eager."""
