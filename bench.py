@@ -231,6 +231,7 @@ def bench_shell(args, torch):
 
 # ------------------------------------------------------------------- particles
 def bench_particles(args, torch):
+    from paper_2012_08141_amd import _lib as L
     from paper_2012_08141_amd import engine as E
     from paper_2012_08141_amd import inputs, programs as PR
     from paper_2012_08141_amd.grid import SparseGrid
@@ -261,7 +262,10 @@ def bench_particles(args, torch):
     out.update({"particle_steps_per_s": p.nparticles * K / t,
                 "launches_per_step": {"optimized": st["dispatches"] / K, "eager": res["eager"][1]["dispatches"] / K},
                 "tasks_per_step": {"optimized": st["tasks_launched"] / K, "eager": res["eager"][1]["tasks_launched"] / K},
-                "scatter": "binned: keys, LDS-histogram ranks, scan, place, LDS tile per bin (5 dispatches)",
+                "scatter": "binned: keys, LDS-histogram ranks, scan, place, LDS tile per bin (5 dispatches); a fused "
+                           "gather-advect-scatter node reuses the previous binning for up to %d scatters (gather "
+                           "rewriting the records, advection, tiles: 3 dispatches)" % E.get_option(L.AT_OPTION_BIN_REUSE),
+                "gather": "through the previous scatter's bins (LDS velocity tile per quarter bin)",
                 "eager": {"value": vox * K / res["eager"][0], "ms_per_step": res["eager"][0] / K * 1e3,
                           "particle_steps_per_s": p.nparticles * K / res["eager"][0]},
                 "speedup_vs_eager": res["eager"][0] / t, "fusions": st["fusions"],
