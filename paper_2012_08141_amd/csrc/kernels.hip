@@ -1487,8 +1487,9 @@ __device__ __forceinline__ void centre_of_key(int key, int &a, int &b, int &c) {
 // centre node (integer LDS atomics).  Each thread then owns one centre node
 // per round (rounds of 256; a round with no particles in the workgroup is
 // skipped) and sums, in registers, the contributions of its particles to the
-// 27 nodes around it (same per-contribution arithmetic as the direct
-// scatter).  The sums reach the tile in 27 phases, one per node offset,
+// 27 nodes around it (the direct scatter's contributions, with the mass
+// folded into the k-weights and fused multiply-adds: rounding differs within
+// the scatter's summation bound).  The sums reach the tile in 27 phases, one per node offset,
 // separated by barriers: within a phase distinct centre nodes add to
 // distinct tile nodes, so each add is a plain LDS read and write (LDS float
 // atomics are slow on this hardware) and the tile's summation order is
@@ -1651,6 +1652,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                     float w[3][3];
                     int base[3];
                     for (int c = 0; c < 3; ++c) base[c] = bspline(x[c] * pp.inv_dx_dst, w[c]);
+                    // the mass folded into the k-weights and fused multiply-adds:
+                    // these sums only have to meet the scatter's summation bound,
+                    // and they are what bounds this kernel (vector ALU)
+                    const float wkm[3] = {w[2][0] * mp, w[2][1] * mp, w[2][2] * mp};
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
 #pragma unroll
@@ -1663,13 +1668,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                                     if (i >= 0 && j >= 0 && kk >= 0 && i < N && j < N && kk < N)
                                         activate_cell<KD>(g, ((int64_t)(i >> 3) * g.R + (j >> 3)) * g.R + (kk >> 3));
                                 }
-                                const float wt = wab * w[2][d];
-                                const float tm = wt * mp;
+                                const float tm = wab * wkm[d];
                                 float *s4 = acc[(a * 3 + bb) * 3 + d];
                                 s4[0] = s4[0] + tm;
-                                s4[1] = s4[1] + tm * v[0];
-                                s4[2] = s4[2] + tm * v[1];
-                                s4[3] = s4[3] + tm * v[2];
+                                s4[1] = __builtin_fmaf(tm, v[0], s4[1]);
+                                s4[2] = __builtin_fmaf(tm, v[1], s4[2]);
+                                s4[3] = __builtin_fmaf(tm, v[2], s4[3]);
                             }
                         }
                     }
