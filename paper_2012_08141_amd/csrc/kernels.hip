@@ -1512,6 +1512,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     __shared__ int32_t ncnt[KEYS];       // particles per centre-node key; then first, then one-past-last position
     __shared__ int32_t wsum[4];
     __shared__ int32_t nhalo;            // wide: non-empty keys outside the block
+    __shared__ int32_t chist[64];        // block centre nodes per particle count (capped), then first rank
+    __shared__ int16_t byload[512];      // block centre nodes by decreasing particle count
     __shared__ int16_t hkeys[WIDE ? 488 : 1];
     __shared__ uint16_t order[CHUNK];    // chunk-relative particle index, sorted by centre node
     // narrow: key << 16 | rank among the chunk's particles there (-1: direct);
@@ -1697,10 +1699,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                     }
                 }
             };
-            // the block's 512 centre nodes, then the listed ones around it
-            for (int r = 0; r < 2; ++r)
-                if (__syncthreads_or(ncnt[r * 256 + t] > (r * 256 + t > 0 ? ncnt[r * 256 + t - 1] : 0)))
-                    round(r * 256 + t);
+            // the block's 512 centre nodes go to threads by decreasing
+            // particle count (any assignment keeps a phase's targets
+            // distinct), so a wave's lanes run loops of similar length; then
+            // the listed nodes around the block
+            if (t < 64) chist[t] = 0;
+            __syncthreads();
+            int load[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int key = 2 * t + h;
+                load[h] = min(ncnt[key] - (key > 0 ? ncnt[key - 1] : 0), 63);
+                atomicAdd(&chist[load[h]], 1);
+            }
+            __syncthreads();
+            if (t == 0) {
+                int run = 0;
+                for (int q = 63; q >= 0; --q) {
+                    const int c = chist[q];
+                    chist[q] = run;
+                    run += c;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int h = 0; h < 2; ++h) byload[atomicAdd(&chist[load[h]], 1)] = (int16_t)(2 * t + h);
+            __syncthreads();
+            for (int r = 0; r < 2; ++r) {
+                const int own = byload[r * 256 + t];
+                if (__syncthreads_or(ncnt[own] > (own > 0 ? ncnt[own - 1] : 0))) round(own);
+            }
             if (WIDE)
                 for (int h0 = 0; h0 < nhalo; h0 += 256) round(h0 + t < nhalo ? hkeys[h0 + t] : -1);
             __syncthreads();
