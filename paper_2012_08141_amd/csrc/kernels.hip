@@ -1237,7 +1237,7 @@ constexpr int kG2PSplit = 4;   // workgroups per bin (each takes a quarter of it
 
 template <int KS>
 __global__ __launch_bounds__(256) void k_g2p_bins(PartProg pp) {
-    __shared__ float vt[3][kTile3];
+    __shared__ float4 vt[kTile3];   // the three velocity channels of a node side by side
     __shared__ int32_t bsl[27];
     const GridDev &S = pp.gsrc;
     const GridDev &W = pp.gbin_g;
@@ -1286,7 +1286,7 @@ __global__ __launch_bounds__(256) void k_g2p_bins(PartProg pp) {
                     a0 = V0[o]; a1 = V1[o]; a2 = V2[o];
                 }
             }
-            vt[0][nn] = a0; vt[1][nn] = a1; vt[2][nn] = a2;
+            vt[nn] = make_float4(a0, a1, a2, 0.f);
         }
         __syncthreads();
         float4 *const rec = W.pstage + 2 * (int64_t)bin.y;
@@ -1313,9 +1313,10 @@ __global__ __launch_bounds__(256) void k_g2p_bins(PartProg pp) {
                         const int row = ((ri + a) * kTile + (rj + bb)) * kTile + rk;
                         for (int d = 0; d < 3; ++d) {
                             const float wt = wab * w[2][d];
-                            acc[0] = acc[0] + wt * vt[0][row + d];
-                            acc[1] = acc[1] + wt * vt[1][row + d];
-                            acc[2] = acc[2] + wt * vt[2][row + d];
+                            const float4 nv = vt[row + d];
+                            acc[0] = acc[0] + wt * nv.x;
+                            acc[1] = acc[1] + wt * nv.y;
+                            acc[2] = acc[2] + wt * nv.z;
                         }
                     }
                 }
