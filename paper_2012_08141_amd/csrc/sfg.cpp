@@ -659,75 +659,97 @@ bool executable_pair(const Node &A, const Node &B, const at_task *tasks) {
 // than max_fuse_per_task times this round.  Fusions are applied one at a
 // time; after each the graph is rebuilt from a topological order of the
 // contracted graph.
+// Fusion in greedy order: the first fusible pair (a, b) of the current graph
+// (smallest a, then smallest b) is contracted, and the search starts again.
+// One simulation serves several contractions when the result provably equals
+// that one-at-a-time order: after picking (a1, b1), a node strictly between
+// them with any fusible partner ends the batch (only the contracted graph can
+// tell whether it still fuses), while a pair (a2, b2) with a2 > b1 is the one
+// the contracted graph would pick next -- contracting (a1, b1) adds paths
+// only through the merged node, which no path starting after b1 can reach,
+// and leaves every other node's accesses, list version and fusion count as
+// they were.  Pairs picked this way have disjoint, ordered spans, so
+// contracting them together keeps the graph acyclic.  The nodes before the
+// batch's first pair had no fusible partner and keep their places (the
+// re-sort breaks ties in the old order), so the next search resumes there.
+// With more than one fusion per task and round, a merged node may fuse
+// again, so the batch holds one pair and every search starts at the front.
 bool Planner::pass_fuse_round(const Persist &start) {
     std::vector<int> fused(nodes.size(), 0);
     bool any = false;
+    int from = 0;
     for (;;) {
         Sim S = simulate(nodes, tasks_, start);
         std::vector<uint64_t> reach = closure(S);
-        int fa = -1, fb = -1;
-        for (int a = 0; a < S.n && fa < 0; ++a) {
-            if (fused[a] >= max_fuse_) continue;
-            const Node &A = nodes[a];
-            if (A.loop == LT_SERIAL) continue;
-            for (int b = a + 1; b < S.n; ++b) {
-                if (fused[b] >= max_fuse_) continue;
-                const Node &B = nodes[b];
-                if (B.loop != A.loop) continue;
-                if (A.loop == LT_STRUCT && (A.loop_grid != B.loop_grid || S.list_ver[a] != S.list_ver[b])) continue;
-                if (A.loop == LT_RANGE && A.range != B.range) continue;
-                if (!executable_pair(A, B, tasks_)) continue;
-                // criterion 1
-                bool ok = true;
-                if (S.edge(a, b)) {
-                    for (int c = a + 1; c < b && ok; ++c)
-                        if (bit(reach, S.words, a, c) && bit(reach, S.words, c, b)) ok = false;
-                } else if (bit(reach, S.words, a, b)) {
-                    ok = false;
-                }
-                if (!ok) continue;
-                // criterion 3
-                for (const Access &x : A.acc) {
-                    for (const Access &y : B.acc) {
-                        if (!(x.s == y.s) || !((x.mode | y.mode) & M_W)) continue;
-                        if (x.pattern != P_ELEM || y.pattern != P_ELEM || !(x.flags & F_UNIQUE) || !(y.flags & F_UNIQUE)) {
-                            ok = false;
-                            break;
-                        }
-                    }
-                    if (!ok) break;
-                }
-                if (!ok) continue;
-                fa = a;
-                fb = b;
-                break;
+        auto fusible = [&](int a, int b) {
+            const Node &A = nodes[a], &B = nodes[b];
+            if (B.loop != A.loop) return false;
+            if (A.loop == LT_STRUCT && (A.loop_grid != B.loop_grid || S.list_ver[a] != S.list_ver[b])) return false;
+            if (A.loop == LT_RANGE && A.range != B.range) return false;
+            if (!executable_pair(A, B, tasks_)) return false;
+            // criterion 1
+            if (S.edge(a, b)) {
+                for (int c = a + 1; c < b; ++c)
+                    if (bit(reach, S.words, a, c) && bit(reach, S.words, c, b)) return false;
+            } else if (bit(reach, S.words, a, b)) {
+                return false;
             }
+            // criterion 3
+            for (const Access &x : A.acc)
+                for (const Access &y : B.acc) {
+                    if (!(x.s == y.s) || !((x.mode | y.mode) & M_W)) continue;
+                    if (x.pattern != P_ELEM || y.pattern != P_ELEM || !(x.flags & F_UNIQUE) || !(y.flags & F_UNIQUE))
+                        return false;
+                }
+            return true;
+        };
+        std::vector<std::pair<int, int>> batch;
+        std::vector<char> taken(S.n, 0);
+        int span_hi = -1;
+        for (int a = from; a < S.n; ++a) {
+            if (taken[a] || fused[a] >= max_fuse_ || nodes[a].loop == LT_SERIAL) continue;
+            int pick = -1;
+            for (int b = a + 1; b < S.n && pick < 0; ++b)
+                if (!taken[b] && fused[b] < max_fuse_ && fusible(a, b)) pick = b;
+            if (pick < 0) continue;
+            if (a < span_hi) break;
+            batch.push_back({a, pick});
+            taken[a] = taken[pick] = 1;
+            span_hi = pick;
+            if (max_fuse_ != 1) break;
         }
-        if (fa < 0) break;
-        // contract fa and fb, then re-sort topologically
-        Node AB = nodes[fa];
-        for (const Member &m : nodes[fb].members) AB.members.push_back(m);
-        if (node_has_kind(nodes[fb], tasks_, AT_TASK_P2G)) AB.act_mode = nodes[fb].act_mode;
-        derive(AB, tasks_);
-        const int nn = S.n - 1;
+        if (batch.empty()) break;
+        if (max_fuse_ == 1) from = batch.front().first;
+        // contract every pair (b into a), then re-sort topologically, ties
+        // in the old order
+        std::vector<int> into(S.n, -1);
+        for (const auto &pr : batch) into[pr.second] = pr.first;
+        const int nn = S.n - (int)batch.size();
         std::vector<int> newid(S.n);
         std::vector<Node> pool;
-        std::vector<int> key;
+        std::vector<int> key, fcnt;
         pool.reserve(nn);
-        std::vector<int> fcnt;
+        std::vector<int> partner(S.n, -1);
+        for (const auto &pr : batch) partner[pr.first] = pr.second;
         for (int i = 0; i < S.n; ++i) {
-            if (i == fb) continue;
+            if (into[i] >= 0) continue;
             newid[i] = (int)pool.size();
-            if (i == fa) {
-                pool.push_back(AB);
-                fcnt.push_back(std::max(fused[fa], fused[fb]) + 1);
+            if (partner[i] >= 0) {
+                const int fb = partner[i];
+                Node AB = nodes[i];
+                for (const Member &m : nodes[fb].members) AB.members.push_back(m);
+                if (node_has_kind(nodes[fb], tasks_, AT_TASK_P2G)) AB.act_mode = nodes[fb].act_mode;
+                derive(AB, tasks_);
+                pool.push_back(std::move(AB));
+                fcnt.push_back(std::max(fused[i], fused[fb]) + 1);
             } else {
                 pool.push_back(std::move(nodes[i]));
                 fcnt.push_back(fused[i]);
             }
             key.push_back(i);
         }
-        newid[fb] = newid[fa];
+        for (int i = 0; i < S.n; ++i)
+            if (into[i] >= 0) newid[i] = newid[into[i]];
         std::vector<std::vector<int>> succ(nn);
         std::vector<int> indeg(nn, 0);
         for (int i = 0; i < S.n; ++i)
@@ -758,10 +780,10 @@ bool Planner::pass_fuse_round(const Persist &start) {
             for (int v : succ[u])
                 if (--indeg[v] == 0) ready.push({key[v], v});
         }
-        // criterion 1 guarantees the contracted graph is acyclic
+        // criterion 1 and the ordered spans guarantee the contracted graph is acyclic
         nodes.swap(order);
         fused.swap(ofused);
-        counters.fusions += 1;
+        counters.fusions += (int64_t)batch.size();
         any = true;
     }
     return any;
