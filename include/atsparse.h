@@ -335,6 +335,11 @@ at_status at_flush(at_stats *stats, hipStream_t stream);
  * directly).  Three dispatches instead of six; results agree within fp32
  * rounding of the scatter's sums.  Read when a node executes. */
 #define AT_OPTION_BIN_REUSE 9
+/* Fusion search: 1 (default) lets one simulation of the state-flow graph
+ * serve several fusions where that provably gives the plan that fusing one
+ * pair at a time (0) gives; the plans are the same, only planning time
+ * differs.  Clears the plan cache. */
+#define AT_OPTION_FUSE_BATCH 10
 at_status at_set_option(int32_t option, int64_t value);
 at_status at_get_option(int32_t option, int64_t *value);
 

@@ -32,6 +32,7 @@ AT_OPTION_STRUCT_FOR_KERNEL = 6
 AT_OPTION_BATCH_WAVES = 7
 AT_OPTION_G2P_BINS = 8
 AT_OPTION_BIN_REUSE = 9
+AT_OPTION_FUSE_BATCH = 10
 
 
 class AtGridDesc(ctypes.Structure):

@@ -59,6 +59,7 @@ struct Engine {
     bool plan_cache = true;
     bool g2p_bins = true;   // gathers may use the source grid's bins
     int32_t bin_reuse = 8;  // scatters that may reuse a binning before the particles are binned again
+    bool fuse_batch = true; // one graph simulation may serve several fusions (same plans)
     std::unordered_map<uint64_t, at_grid_s *> live;   // device grids by uid
     // Inside one window only its own nodes touch external arrays, so a
     // binned scatter's particle records still hold the current positions
@@ -307,7 +308,7 @@ at_status plan_window(const at_task *tasks, int ntasks, uint32_t flags, std::vec
         if (!msg.empty()) return fail(AT_E_INVALID, "task %d: %s", i, msg.c_str());
     }
     hits = 0;
-    Planner P(tasks, ntasks, flags, en.max_fuse);
+    Planner P(tasks, ntasks, flags, en.max_fuse, en.fuse_batch);
     if (flags == 0) {
         P.build_eager();
         nodes = std::move(P.nodes);
@@ -855,6 +856,11 @@ at_status at_set_option(int32_t option, int64_t value) {
         if (value < 0 || value > 1024) return fail(AT_E_INVALID, "bin reuse must be in 0..1024");
         en.bin_reuse = (int32_t)value;
         return AT_OK;
+    case AT_OPTION_FUSE_BATCH:
+        if (value != 0 && value != 1) return fail(AT_E_INVALID, "fuse batch must be 0 or 1");
+        en.fuse_batch = value != 0;
+        en.cache.clear();
+        return AT_OK;
     default:
         return fail(AT_E_INVALID, "unknown option %d", option);
     }
@@ -874,6 +880,7 @@ at_status at_get_option(int32_t option, int64_t *value) {
     case AT_OPTION_BATCH_WAVES: *value = batch_waves(); return AT_OK;
     case AT_OPTION_G2P_BINS: *value = en.g2p_bins ? 1 : 0; return AT_OK;
     case AT_OPTION_BIN_REUSE: *value = en.bin_reuse; return AT_OK;
+    case AT_OPTION_FUSE_BATCH: *value = en.fuse_batch ? 1 : 0; return AT_OK;
     default: return fail(AT_E_INVALID, "unknown option %d", option);
     }
 }

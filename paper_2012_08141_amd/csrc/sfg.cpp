@@ -378,8 +378,8 @@ uint64_t hash_window(const at_task *tasks, int n, uint32_t flags, int max_fuse) 
 
 // ------------------------------------------------------------------ planner
 
-Planner::Planner(const at_task *tasks, int n, uint32_t flags, int max_fuse)
-    : tasks_(tasks), n_(n), flags_(flags), max_fuse_(max_fuse < 1 ? 1 : max_fuse) {}
+Planner::Planner(const at_task *tasks, int n, uint32_t flags, int max_fuse, bool batch_fusions)
+    : tasks_(tasks), n_(n), flags_(flags), max_fuse_(max_fuse < 1 ? 1 : max_fuse), batch_(batch_fusions) {}
 
 void Planner::build_eager() {
     nodes.clear();
@@ -716,10 +716,10 @@ bool Planner::pass_fuse_round(const Persist &start) {
             batch.push_back({a, pick});
             taken[a] = taken[pick] = 1;
             span_hi = pick;
-            if (max_fuse_ != 1) break;
+            if (max_fuse_ != 1 || !batch_) break;
         }
         if (batch.empty()) break;
-        if (max_fuse_ == 1) from = batch.front().first;
+        if (max_fuse_ == 1 && batch_) from = batch.front().first;
         // contract every pair (b into a), then re-sort topologically, ties
         // in the old order
         std::vector<int> into(S.n, -1);

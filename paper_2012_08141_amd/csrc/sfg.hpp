@@ -90,7 +90,10 @@ std::string validate_task(const at_task &t);
 
 class Planner {
 public:
-    Planner(const at_task *tasks, int n, uint32_t flags, int max_fuse);
+    // batch_fusions: let one graph simulation serve several fusions where
+    // that gives the same plan as fusing one pair at a time (false: one at
+    // a time, the reference the batched planner is tested against)
+    Planner(const at_task *tasks, int n, uint32_t flags, int max_fuse, bool batch_fusions = true);
     // Eager plan: one node per task, activation checks kept.
     void build_eager();
     // Run the selected passes to a fixpoint against `start`.
@@ -108,6 +111,7 @@ private:
     int n_;
     uint32_t flags_;
     int max_fuse_;
+    bool batch_;
     bool pass_ad(const Persist &start);
     bool pass_lgr(const Persist &start);
     bool pass_dse(const Persist &start);
