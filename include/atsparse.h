@@ -168,7 +168,7 @@ at_status at_listgen(at_grid grid, hipStream_t stream);
 at_status at_run_stencil(at_grid grid, int32_t op, const int32_t *ch, const float *params,
                          int32_t check_activation, hipStream_t stream);
 
-/* Particle tasks (Section 8.2 workload; PIC transfers with the quadratic
+/* Particle tasks (Section 8.3 workload; PIC transfers with the quadratic
  * B-spline: per axis base = floor(X - 0.5), fx = X - base,
  * w = (0.5*(1.5-fx)^2, 0.75-(fx-1)^2, 0.5*(fx-0.5)^2), X = x/dx, node weight
  * (wx*wy)*wz, nodes in (x, y, z) lexicographic order). */
@@ -180,18 +180,25 @@ at_status at_run_stencil(at_grid grid, int32_t op, const int32_t *ch, const floa
 /* x += dt * v (device SoA arrays, np particles). */
 at_status at_advect(float *d_x, const float *d_v, int64_t np, float dt, hipStream_t stream);
 
-/* Scatter mass and momentum: m += w*m_p, mv_c += (w*m_p)*v_c with fp32
- * atomics, activating node blocks on write.  ch: {m, mv0} (mv on mv0..mv0+2).
- * Nodes outside the domain are skipped.  When the grid's particle_capacity
- * covers np, particles are first binned by the block of their centre node and
- * each bin is accumulated in an on-chip tile (block plus one-node halo) that
- * is then added to the grid: five dispatches instead of one, and the order
- * of the fp32 additions differs (results agree within fp32 rounding). */
+/* Scatter mass and momentum (Section 8.3's P2G, quadratic B-spline weights
+ * w over the 27 nodes around each particle): m += w*m_p,
+ * mv_c += (w*m_p)*v_c with fp32 atomics, activating node blocks on write.
+ * ch: {m, mv0} (mv on mv0..mv0+2).  Nodes outside the domain are skipped.
+ * When the grid's particle_capacity covers np, particles are first binned by
+ * the block of their centre node and each bin is accumulated in an on-chip
+ * tile (block plus halo) that is then added to the grid: five dispatches
+ * instead of one, and the rounding of the fp32 sums differs (results agree
+ * within the summation bound).  Binned scatters leave the bins in the grid's
+ * workspace for later gathers from the grid (AT_OPTION_G2P_BINS) and fused
+ * scatters of the same particles (AT_OPTION_BIN_REUSE). */
 at_status at_p2g(at_grid grid, const float *d_x, const float *d_v, const float *d_m, int64_t np,
                  float dx, const int32_t *ch, int32_t activation, hipStream_t stream);
 
-/* Gather velocity: v_p = sum over 27 nodes of w * v_node (accumulated in node
- * order from 0).  ch: {v0} (v on v0..v0+2). */
+/* Gather velocity (Section 8.3's G2P): v_p = sum over 27 nodes of w * v_node
+ * (accumulated in node order from 0; 0 outside the domain or in inactive
+ * blocks).  ch: {v0} (v on v0..v0+2).  After a binned scatter of as many
+ * particles into this grid, the gather runs through those bins (one LDS tile
+ * per bin) with bit-identical results. */
 at_status at_g2p(at_grid grid, const float *d_x, float *d_v, int64_t np, float dx,
                  const int32_t *ch, hipStream_t stream);
 
@@ -268,7 +275,7 @@ typedef struct at_stats {
     double optimizer_us;          /* host time spent building and optimizing the plan */
 } at_stats;
 
-/* Run a window of tasks on `stream` (Section 5, "Asynchronous launching"):
+/* Run a window of tasks on `stream` (Section 5, lazy and asynchronous kernel launches):
  * build the state-flow graph (Section 4) seeded with the state owners kept
  * from earlier windows (Section 7.1, "Partial SFG garbage collection"), run
  * the passes selected in opt_flags to a fixpoint, and launch the result in a

@@ -229,7 +229,7 @@ def dispatch_count() -> int:
 
 
 def paper_task_count(entries) -> int:
-    """Tasks counted the paper's way (Fig. 6): a list generation is a clear
+    """Tasks counted the paper's way (Section 6.1, Fig. 7): a list generation is a clear
     task plus a listgen task; this library folds the clear into one dispatch."""
     return sum(2 if e["kind"] == L.AT_TASK_LISTGEN else 1 for e in entries)
 

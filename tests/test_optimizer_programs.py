@@ -11,7 +11,7 @@ The optimized counts follow from Section 6: activation demotion removes the
 repeated activation and the loop-index checks, which leaves the masks
 unmodified so list generation removal deletes the listgens; lap_update ->
 axpy and jacobi -> copy are not fusible (criterion 3); G2P, advection and
-P2G of consecutive substeps fuse (Section 8.2); and since list generation
+P2G of consecutive substeps fuse (Section 8.3); and since list generation
 removal gives a grid's reset two steps later the same list version as its
 normalise, those two element-wise struct-fors fuse as well."""
 import pytest
