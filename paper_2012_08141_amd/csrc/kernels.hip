@@ -219,11 +219,17 @@ __device__ __forceinline__ int lookback(const GridDev &g, uint64_t *flags, uint3
 // of one bit word; C >= 32: C/32 whole words), so a dense run of active
 // cells is spread over many threads and many workgroups.  For C <= 16 every
 // lookup of a thread's records (its cells' slots and neighbour slots) is
-// issued before any record is written.
-template <int KIND, int C>
+// issued before any record is written.  With PREFIX (small roots: the bits
+// before any workgroup's range are at most kPrefixWords words) each
+// workgroup counts the active cells before its range itself, from the bits,
+// instead of the look-back: no workgroup waits for another.
+constexpr int64_t kPrefixWords = 8192;
+
+template <int KIND, int C, bool PREFIX>
 __global__ __launch_bounds__(256) void k_listgen(GridDev g, uint64_t *flags, uint32_t epoch) {
     constexpr int WPT = C >= 32 ? C / 32 : 1;
     __shared__ int wsum[4];
+    __shared__ int wpre[4];
     __shared__ int s_base;
     const int64_t W = (g.ncells + 31) >> 5;
     const int tid = threadIdx.x;
@@ -248,12 +254,27 @@ __global__ __launch_bounds__(256) void k_listgen(GridDev g, uint64_t *flags, uin
     int cnt = 0;
 #pragma unroll
     for (int q = 0; q < WPT; ++q) cnt += __popc(b[q]);
+    // PREFIX: active cells in the (whole) words before this workgroup's range
+    int pre = 0;
+    if (PREFIX) {
+        const int64_t wend = ((int64_t)blockIdx.x * 256 * C) >> 5;
+        for (int64_t w = tid; w < wend; w += 256) pre += __popc(g.bits[w]);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) pre += __shfl_xor(pre, o, 64);
+        if (lane == 0) wpre[wid] = pre;
+    }
     const int incl = wave_incl_scan(cnt);
     if (lane == 63) wsum[wid] = incl;
     __syncthreads();
     const int before = (wid > 0 ? wsum[0] : 0) + (wid > 1 ? wsum[1] : 0) + (wid > 2 ? wsum[2] : 0);
     const int total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-    if (wid == 0) {
+    if (PREFIX) {
+        if (tid == 0) {
+            const int base = wpre[0] + wpre[1] + wpre[2] + wpre[3];
+            s_base = base;
+            if (blockIdx.x == gridDim.x - 1) g.hdr[HDR_COUNT] = base + total;
+        }
+    } else if (wid == 0) {
         const int bid = blockIdx.x;
         int base = 0;
         if (bid == 0) {
@@ -1861,17 +1882,21 @@ static void launch_listgen_k(const GridDev &g, uint64_t *flags, uint32_t epoch, 
     int64_t C = 8;
     while ((g.ncells + 256 * C - 1) / (256 * C) > kScanMaxWG) C *= 2;
     const unsigned blocks = (unsigned)((g.ncells + 256 * C - 1) / (256 * C));
+    if (C == 8 && (g.ncells + 31) / 32 <= kPrefixWords) {
+        hipLaunchKernelGGL((k_listgen<KIND, 8, true>), dim3(blocks), dim3(256), 0, s, g, flags, epoch);
+        return;
+    }
     switch (C) {
-    case 8: hipLaunchKernelGGL((k_listgen<KIND, 8>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
-    case 16: hipLaunchKernelGGL((k_listgen<KIND, 16>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
-    case 32: hipLaunchKernelGGL((k_listgen<KIND, 32>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
-    case 64: hipLaunchKernelGGL((k_listgen<KIND, 64>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
-    case 128: hipLaunchKernelGGL((k_listgen<KIND, 128>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
-    case 256: hipLaunchKernelGGL((k_listgen<KIND, 256>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
-    case 512: hipLaunchKernelGGL((k_listgen<KIND, 512>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
-    case 1024: hipLaunchKernelGGL((k_listgen<KIND, 1024>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
-    case 2048: hipLaunchKernelGGL((k_listgen<KIND, 2048>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
-    default: hipLaunchKernelGGL((k_listgen<KIND, 4096>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
+    case 8: hipLaunchKernelGGL((k_listgen<KIND, 8, false>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
+    case 16: hipLaunchKernelGGL((k_listgen<KIND, 16, false>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
+    case 32: hipLaunchKernelGGL((k_listgen<KIND, 32, false>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
+    case 64: hipLaunchKernelGGL((k_listgen<KIND, 64, false>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
+    case 128: hipLaunchKernelGGL((k_listgen<KIND, 128, false>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
+    case 256: hipLaunchKernelGGL((k_listgen<KIND, 256, false>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
+    case 512: hipLaunchKernelGGL((k_listgen<KIND, 512, false>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
+    case 1024: hipLaunchKernelGGL((k_listgen<KIND, 1024, false>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
+    case 2048: hipLaunchKernelGGL((k_listgen<KIND, 2048, false>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
+    default: hipLaunchKernelGGL((k_listgen<KIND, 4096, false>), dim3(blocks), dim3(256), 0, s, g, flags, epoch); break;
     }
 }
 
