@@ -248,17 +248,18 @@ def test_particle_program_reduced(opt, binned, reuse, bin_reuse):
         assert grids[gi].device_status() == 0
 
 
+@pytest.mark.parametrize("root", ["pointer", "bitmask"])
 @pytest.mark.parametrize("reuse", [3, 8])
-def test_particle_program_bin_reuse_with_drift(reuse, bin_reuse):
+def test_particle_program_bin_reuse_with_drift(reuse, root, bin_reuse):
     """Velocities ten times the recipe's and dt = 2e-3 on a 128^3 grid move a
     particle about a quarter node per step, so bins reused for several steps
     hold particles that have moved one node past their block (still summed in
     the tile) and further (scattered directly).  The state after 12 steps
     against the oracle, and the same run binning every scatter."""
     import dataclasses
-    say("particle program bin reuse with drift", reuse)
+    say("particle program bin reuse with drift", reuse, root)
     p0 = I.particles(0, n=128, nparticles=100_000)
-    p = dataclasses.replace(p0, v=(p0.v * 10).astype(np.float32), params=dict(p0.params, dt=2e-3))
+    p = dataclasses.replace(p0, v=(p0.v * 10).astype(np.float32), params=dict(p0.params, dt=2e-3), root_kind=root)
     steps = 12
     ref = OP.particle_program(p.n, p.x, p.v, p.m, steps, p.params["dt"], "f32")
     sx, sv = 0.1 * np.abs(p.x).max(), 0.1 * np.abs(p.v).max()
