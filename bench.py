@@ -367,7 +367,7 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--workload", default="band512", choices=["band512", "shell", "particles", "serving", "diffusion"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=30)
+    ap.add_argument("--cpu-iters", type=int, default=90)
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--load", type=float, default=0.8)
     ap.add_argument("--budget-mib", type=int, default=256)
