@@ -14,11 +14,15 @@ except ImportError:      # planning handles work without torch
     torch = None
 
 
+_HAS_DEVICE = None
+
+
 def current_stream():
     """hipStream_t of torch's current stream (0 without a device)."""
-    if torch is not None and torch.cuda.is_available():
-        return torch.cuda.current_stream().cuda_stream
-    return None
+    global _HAS_DEVICE
+    if _HAS_DEVICE is None:
+        _HAS_DEVICE = torch is not None and torch.cuda.is_available()
+    return torch.cuda.current_stream().cuda_stream if _HAS_DEVICE else None
 
 
 _KINDS = {"bitmask": L.AT_ROOT_BITMASK, "pointer": L.AT_ROOT_POINTER}
