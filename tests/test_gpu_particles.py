@@ -317,17 +317,20 @@ def test_reused_bins_are_not_used_after_their_workspace_goes(how, bin_reuse):
     assert g1.device_status() == 0
 
 
-def test_particle_full_size_one_step_and_eager_vs_optimized():
-    """The particle workload at full size (2M particles, 256^3): one step against the
-    oracle; 20 steps optimized against eager."""
+def test_particle_full_size_three_steps_and_eager_vs_optimized():
+    """The particle workload at full size (2M particles, 256^3): three optimized steps
+    against the oracle (the second and third scatter over reused bins); 20 steps
+    optimized against eager."""
     say("particles full size")
     p = I.particles(0)
-    ref = OP.particle_program(p.n, p.x, p.v, p.m, 1, p.params["dt"], "f32")
+    ref = OP.particle_program(p.n, p.x, p.v, p.m, 3, p.params["dt"], "f32")
     sx, sv = 0.1 * np.abs(p.x).max(), 0.1 * np.abs(p.v).max()
-    grids, x, v, st = _particle_run(p, 1, 15)
+    grids, x, v, st = _particle_run(p, 3, 15)
+    assert st["dispatches"] == st["tasks_launched"] + _binning_extra(3, 8)
     close_state(x.cpu().numpy(), ref["x"], "x", sx)
     close_state(v.cpu().numpy(), ref["v"], "v", sv)
-    assert np.array_equal(grids[0].active_cells(), ref["cells0"])
+    for gi in (0, 1):
+        assert np.array_equal(grids[gi].active_cells(), ref["cells%d" % gi]), gi
     del grids
     ge, xe, ve, _ = _particle_run(p, 20, 0)
     go, xo, vo, _ = _particle_run(p, 20, 15)
