@@ -398,7 +398,10 @@ at_status at_batch_get_views(at_batch batch, at_batch_views *views);
  * slots of its six face neighbours (from the roots as they are now), then
  * iters x (jacobi, copy), then the clock tick: 2*iters + 2 dispatches, no
  * host synchronisation, no fills (safe to capture in a graph).  workgroups:
- * persistent grid size (0 = automatic). */
+ * persistent grid size (0 = automatic).  The work list must hold at most
+ * pool_blocks entries, each naming a grid below max_grids and a cell below
+ * R^3, and the slots in the roots must lie below pool_blocks: the device
+ * cannot check these.  An entry whose root cell holds no block is skipped. */
 at_status at_batch_jacobi(at_batch batch, int32_t iters, int32_t workgroups, hipStream_t stream);
 
 /* Total device dispatches issued by the library since load. */

@@ -1014,6 +1014,7 @@ __global__ __launch_bounds__(64 * W) void k_batch(BatchDev d, int it) {
         const int gid = r0.y;
         if (now < d.window[2 * gid] || now >= d.window[2 * gid + 1]) continue;
         const int32_t slot = r0.x;
+        if (slot < 0) continue;
         const int64_t off = (int64_t)slot * kBV + lane * 8;
         if (COPY) {
             const float4 a = reinterpret_cast<const float4 *>(d.xn + off)[0];
