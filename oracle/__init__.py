@@ -24,6 +24,9 @@ What pins each function (tests/test_oracle_pins.py):
   Jacobi eigenmodes, a direct Poisson solve, linear-field diffusion fluxes.
 * diffuse_adj -- dot-product identities in a and k, and central finite
   differences of a multi-step loss.
+* restrict_to, prolong_from -- the dense implementation (bit-exact), the
+  parent-block active set, constants, and the adjoint identity between the
+  two transfers.
 * p2g, normalise, g2p -- B-spline moment identities, mass and momentum
   conservation, the on-node (1/8, 3/4, 1/8) stencil, affine reproduction by
   the gather, and the dense implementation.
@@ -78,6 +81,8 @@ def _lib(prec: str):
         "og_advect": (None, [P, P, i64, R]),
         "og_p2g": (i64, [P, i32, i32, i32, P, P, P, i64, R]),
         "og_normalise": (None, [P, i32, i32, i32]),
+        "og_restrict": (None, [P, P, i32, i32, R]),
+        "og_prolong": (None, [P, P, i32, i32]),
         "og_g2p": (None, [P, i32, P, P, i64, R]),
         "og_bspline": (i32, [R, P]),
     }
@@ -213,6 +218,19 @@ class OracleGrid:
 
     def diffuse_adj(self, ch_a: int, ch_k: int, ch_lamn: int, ch_lam: int, ch_gk: int, dt: float):
         self._L.og_diffuse_adj(self._g, ch_a, ch_k, ch_lamn, ch_lam, ch_gk, self.dtype(dt))
+
+    # -- two-level transfers (struct-fors over this, the fine grid) -----------
+    def restrict_to(self, coarse: "OracleGrid", ch_x: int, ch_y: int, w: float = 0.125):
+        """coarse.y[I/2] += w * x[I] over this grid's list, activating coarse blocks."""
+        if coarse.n * 2 != self.n or coarse.precision != self.precision:
+            raise ValueError("coarse grid must have half the domain edge and the same precision")
+        self._L.og_restrict(self._g, coarse._g, ch_x, ch_y, self.dtype(w))
+
+    def prolong_from(self, coarse: "OracleGrid", ch_y: int, ch_x: int):
+        """x[I] += coarse.y[I/2] over this grid's list."""
+        if coarse.n * 2 != self.n or coarse.precision != self.precision:
+            raise ValueError("coarse grid must have half the domain edge and the same precision")
+        self._L.og_prolong(coarse._g, self._g, ch_y, ch_x)
 
     # -- particles ------------------------------------------------------------
     def p2g(self, ch_m: int, ch_mv: int, x, v, m, inv_dx: float, ch_abs: int = -1) -> int:

@@ -107,6 +107,34 @@ class DenseGrid:
     def inc(self, ch, value):
         self._store(ch, self._field(ch) + self.dtype.type(value))
 
+    # -- two-level transfers (this grid is the fine one) ----------------------------
+    def restrict_to(self, coarse, ch_x, ch_y, w):
+        """coarse.y[I//2] += w * x[I] over this grid's listed blocks: the coarse
+        parents of the listed blocks are activated (zero-filled if new), then
+        each coarse voxel adds its 8 children one at a time in ascending order
+        of their index inside the fine block."""
+        T = self.dtype.type
+        R = self.R
+        listed = np.zeros(R ** 3, dtype=bool)
+        listed[self.list] = True
+        listed = listed.reshape((R,) * 3)
+        for bi, bj, bk in np.argwhere(listed):
+            coarse._activate_block(bi // 2, bj // 2, bk // 2)
+        x = self._field(ch_x)
+        under = np.repeat(np.repeat(np.repeat(listed, 4, 0), 4, 1), 4, 2)   # coarse voxels fed by a listed block
+        y = coarse._field(ch_y)
+        for a in (0, 1):
+            for b in (0, 1):
+                for c in (0, 1):
+                    y = np.where(under, y + T(w) * x[a::2, b::2, c::2], y)
+        coarse.vals[ch_y] = np.where(under, y, coarse.vals[ch_y])
+
+    def prolong_from(self, coarse, ch_y, ch_x):
+        """x[I] += coarse.y[I//2] over this grid's listed blocks."""
+        y = coarse._field(ch_y)
+        up = np.repeat(np.repeat(np.repeat(y, 2, 0), 2, 1), 2, 2)
+        self._store(ch_x, self._field(ch_x) + up)
+
     def diffuse(self, ch_a, ch_k, ch_out, dt):
         T = self.dtype.type
         a, k = self._field(ch_a), self._field(ch_k)

@@ -210,6 +210,35 @@ void og_write_block(og_grid *g, int ch, int32_t cell, const REAL *vals) {
                 }                                                                   \
     }
 
+/* ------------------------------------------ two-level transfers (Sec. 6.3)
+ * A coarse grid has half the fine domain edge; fine voxel (i, j, k) lies
+ * under coarse voxel (i/2, j/2, k/2).  Both transfers are struct-fors over
+ * the FINE grid's list. */
+
+/* Restriction (the downsample pattern of Section 6.3, in 3D): for every
+ * listed fine voxel, in list order and ascending voxel order inside a block,
+ * y[i/2, j/2, k/2] = y + w * x[i, j, k], writing the coarse grid with
+ * activation on write (a coarse block is zero-filled when it is first
+ * activated). */
+void og_restrict(const og_grid *fine, og_grid *coarse, int ch_x, int ch_y, REAL w) {
+    FOR_EACH_LISTED_VOXEL(fine, {
+        REAL y = rd(coarse, ch_y, i / 2, j / 2, k / 2);
+        REAL t = w * rd(fine, ch_x, i, j, k);
+        wr(coarse, ch_y, i / 2, j / 2, k / 2, y + t);
+    })
+}
+
+/* Prolongation by injection: for every listed fine voxel,
+ * x[i, j, k] = x + y[i/2, j/2, k/2] (an inactive coarse voxel reads 0; the
+ * coarse grid is not written). */
+void og_prolong(const og_grid *coarse, og_grid *fine, int ch_y, int ch_x) {
+    FOR_EACH_LISTED_VOXEL(fine, {
+        REAL x = rd(fine, ch_x, i, j, k);
+        REAL y = rd(coarse, ch_y, i / 2, j / 2, k / 2);
+        wr(fine, ch_x, i, j, k, x + y);
+    })
+}
+
 /* Sum of the six face neighbours, in the fixed order
  * ((((x[i-1] + x[i+1]) + x[j-1]) + x[j+1]) + x[k-1]) + x[k+1]. */
 static REAL nbsum(const og_grid *g, int ch, int i, int j, int k) {

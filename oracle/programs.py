@@ -155,3 +155,58 @@ def diffusion_grad(n, blocks, a0, k, target, dt, steps, precision="f64"):
         g.diffuse_adj(0, 1, 2, 3, 4, dt)
         lam = g.read_blocks(3, cells)
     return {"loss": loss, "grad_a0": lam, "grad_k": g.read_blocks(4, cells), "aT": aT}
+
+
+# ---------------------------------------------------------------------------
+# Multigrid V-cycle (the MGPCG pattern of Section 8.4 / Fig. 12: restriction,
+# smoothing and prolongation over a sparse grid hierarchy).  Level l has domain
+# edge n >> l and channels x, b, t; the coarse levels start empty and get their
+# blocks from the restriction's activation on write.
+MG_X, MG_B, MG_T = 0, 1, 2
+
+
+def mg_smooth(g, omega):
+    """Damped Jacobi: t = J(x); t = t - x; x = x + omega * t (each a struct-for
+    preceded by a list generation, as written)."""
+    g.listgen(); g.jacobi(MG_X, MG_B, MG_T)
+    g.listgen(); g.axpy(MG_T, MG_X, -1.0)
+    g.listgen(); g.axpy(MG_X, MG_T, omega)
+
+
+def mg_vcycle(G, pre=2, post=2, coarse_iters=8, omega=0.75, w_restrict=1.5):
+    """One V-cycle over the grids G (finest first).  The scaled residual
+    t = J(x) - x (= r / 6) is restricted with y[I/2] += w * t[I] and the
+    coarse correction is prolonged by injection, x[I] += x_c[I/2].  With
+    injection P, the Galerkin coarse operator P^T A P is 4 times the 7-point
+    operator on the coarse grid, so the coarse right-hand side is
+    P^T r / 4 = (6 / 4) * sum of the children's t: w = 1.5."""
+    L = len(G)
+    for l in range(L - 1):
+        g, c = G[l], G[l + 1]
+        for _ in range(pre):
+            mg_smooth(g, omega)
+        g.listgen(); g.jacobi(MG_X, MG_B, MG_T)
+        g.listgen(); g.axpy(MG_T, MG_X, -1.0)
+        c.listgen(); c.fill(MG_X, 0.0)
+        c.listgen(); c.fill(MG_B, 0.0)
+        g.listgen(); g.restrict_to(c, MG_T, MG_B, w_restrict)
+    for _ in range(coarse_iters):
+        mg_smooth(G[L - 1], omega)
+    for l in range(L - 2, -1, -1):
+        g, c = G[l], G[l + 1]
+        g.listgen(); g.prolong_from(c, MG_X, MG_X)
+        for _ in range(post):
+            mg_smooth(g, omega)
+
+
+def multigrid_program(n, blocks, b, cycles, levels=3, precision="f32", **kw):
+    """``cycles`` V-cycles on the Poisson system of ``jacobi_program``
+    (6 x - sum of neighbours = b on the active voxels, x = 0 at start).
+    Returns x on the finest level's blocks and every level's active cells."""
+    G = [OracleGrid(n >> l, 3, precision) for l in range(levels)]
+    G[0].load(blocks, {"b": b}, {"x": MG_X, "b": MG_B})
+    for _ in range(cycles):
+        mg_vcycle(G, **kw)
+    cells = G[0].active_cells()
+    return {"cells": cells, "x": G[0].read_blocks(MG_X, cells),
+            "level_cells": [g.active_cells() for g in G], "grids": G}

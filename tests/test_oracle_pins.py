@@ -405,3 +405,119 @@ def test_particle_program_invariants():
         prev[gi] = cells
     for gi in (0, 1):
         assert abs(r["grid%d" % gi][P.CH_M].sum() - 4000) < 1e-8
+
+
+# ------------------------------------------------- two-level transfers (MG)
+def _coarse_pair(n, prec, seed):
+    """A fine grid with random blocks (only some listed) and a coarse grid
+    (half the edge) that already holds a few blocks, as oracle and dense."""
+    f = I.random_blocks(seed, n, 0.35, channels=("c0", "c1", "c2"))
+    c = I.random_blocks(seed + 7, n // 2, 0.3, channels=("c0", "c1", "c2"))
+    names = {"c0": 0, "c1": 1, "c2": 2}
+    of, df = _pair(n, 3, prec)
+    oc, dc = _pair(n // 2, 3, prec)
+    of.load(f.blocks, f.channels, names); df.load(f.blocks, f.channels, names)
+    oc.load(c.blocks, c.channels, names); dc.load(c.blocks, c.channels, names)
+    of.listgen(); df.listgen()
+    extra = I.random_blocks(seed + 50, n, 0.15).blocks      # active but not listed
+    of.activate(extra); df.activate(extra)
+    return of, df, oc, dc
+
+
+@pytest.mark.parametrize("n,seed", [(32, 0), (48, 1)])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_restrict_prolong_match_dense(n, seed, prec):
+    """Restriction (with activation of the coarse parents) and prolongation
+    of the oracle equal the dense implementation bit for bit, on both grids,
+    including coarse blocks that were active before."""
+    of, df, oc, dc = _coarse_pair(n, prec, seed)
+    of.restrict_to(oc, 0, 1, 0.375); df.restrict_to(dc, 0, 1, 0.375)
+    assert np.array_equal(oc.active_cells(), dc.active_cells())
+    for q in range(3):
+        assert np.array_equal(oc.to_dense(q), dc.to_dense(q)), q
+    of.prolong_from(oc, 1, 2); df.prolong_from(dc, 1, 2)
+    for q in range(3):
+        assert np.array_equal(of.to_dense(q), df.to_dense(q)), q
+
+
+def test_restrict_constant_field_and_parent_blocks():
+    """Restricting a constant with w = 1/8 gives the constant exactly on the
+    coarse voxels whose 8 children lie in listed blocks and 0 on the rest of
+    the newly activated coarse blocks; the coarse active set is exactly the
+    parents (block index // 2) of the listed fine blocks."""
+    n = 32
+    w = I.random_blocks(4, n, 0.3, channels=("x",))
+    fine = oracle.OracleGrid(n, 1)
+    fine.load(w.blocks, {"x": np.full((len(w.blocks), 512), 2.5)}, {"x": 0})
+    fine.listgen()
+    coarse = oracle.OracleGrid(n // 2, 1)
+    fine.restrict_to(coarse, 0, 0, 0.125)
+    R = n // 2 // 8
+    parents = sorted({((bi // 2) * R + bj // 2) * R + bk // 2 for bi, bj, bk in w.blocks})
+    assert list(coarse.active_cells()) == parents
+    expect = np.zeros((n // 2,) * 3, np.float32)
+    for bi, bj, bk in w.blocks:
+        expect[bi * 4:bi * 4 + 4, bj * 4:bj * 4 + 4, bk * 4:bk * 4 + 4] = 2.5
+    assert np.array_equal(coarse.to_dense(0), expect)
+
+
+def test_restriction_is_weighted_transpose_of_prolongation():
+    """<R x, y> = w <x, P y> in fp64 (R: y[I/2] += w x[I] into a zero coarse
+    channel; P: x[I] += y[I/2] into a zero fine channel), for random x and y;
+    a wrong index or a swapped operand in either transfer breaks it."""
+    n = 32
+    rng = np.random.default_rng(5)
+    f = I.random_blocks(9, n, 0.4, channels=("x",))
+    fine = oracle.OracleGrid(n, 2, "f64")
+    fine.load(f.blocks, {"x": rng.standard_normal((len(f.blocks), 512))}, {"x": 0})
+    fine.listgen()
+    coarse = oracle.OracleGrid(n // 2, 2, "f64")
+    fine.restrict_to(coarse, 0, 0, 0.3)
+    cc = coarse.active_cells()
+    coarse.write_blocks(1, cc, rng.standard_normal((len(cc), 512)))
+    fine.prolong_from(coarse, 1, 1)
+    lhs = float(np.sum(coarse.to_dense(0) * coarse.to_dense(1)))
+    rhs = 0.3 * float(np.sum(fine.to_dense(0) * fine.to_dense(1)))
+    assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs))
+
+
+def _direct_poisson(n, blocks, b):
+    """Dense solve of 6 x_i - sum_nb x_nb = b_i over the active voxels (zero
+    outside), returned per block in ascending cell order."""
+    R = n // 8
+    cells = (blocks[:, 0] * R + blocks[:, 1]) * R + blocks[:, 2]
+    index, coords = {}, []
+    for bi, bj, bk in blocks:
+        for v in range(512):
+            c = (bi * 8 + v // 64, bj * 8 + (v // 8) % 8, bk * 8 + v % 8)
+            index[c] = len(coords)
+            coords.append(c)
+    A = np.zeros((len(coords), len(coords)))
+    for r_, (x, y, z) in enumerate(coords):
+        A[r_, r_] = 6
+        for d in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+            c = (x + d[0], y + d[1], z + d[2])
+            if c in index:
+                A[r_, index[c]] = -1
+    xs = np.linalg.solve(A, b.ravel()).reshape(len(blocks), 512)
+    return xs[np.argsort(cells)]
+
+
+def test_multigrid_vcycles_converge_to_direct_solve():
+    """Three-level V-cycles (damped Jacobi smoothing, restriction of the
+    residual, injection prolongation) reduce the error against a direct
+    solve of the Poisson system every cycle and reach it to 1e-8 in fp64;
+    the coarse levels hold exactly the ancestors of the fine blocks."""
+    n = 32
+    blocks = np.array([[0, 0, 0], [0, 0, 1], [1, 0, 0], [1, 1, 1], [2, 1, 1], [3, 2, 1]], np.int32)
+    b = np.random.default_rng(3).standard_normal((len(blocks), 512))
+    xs = _direct_poisson(n, blocks, b)
+    errs = [np.abs(P.multigrid_program(n, blocks, b, c, levels=3, precision="f64")["x"] - xs).max()
+            for c in (1, 2, 4, 8, 32)]
+    assert all(e1 < e0 for e0, e1 in zip(errs, errs[1:])), errs
+    assert errs[-1] < 1e-8, errs
+    res = P.multigrid_program(n, blocks, b, 1, levels=3, precision="f64")
+    for l in (1, 2):
+        Rl = (n >> l) // 8
+        anc = sorted({((bi >> l) * Rl + (bj >> l)) * Rl + (bk >> l) for bi, bj, bk in blocks})
+        assert list(res["level_cells"][l]) == anc
