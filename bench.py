@@ -13,7 +13,8 @@ included) bracketed by device synchronisation.
 
 Other workloads (--workload): shell (64^3 activate/lap_update/axpy),
 particles (2M-particle PIC), serving (256 Poisson-arriving 128^3 Jacobi
-requests, continuous batching) and diffusion (128^3 forward + adjoint).
+requests, continuous batching), diffusion (128^3 forward + adjoint) and
+multigrid (V-cycles over a 256^3 band and its coarse levels).
 
 Prints one JSON line.
 """
@@ -358,6 +359,52 @@ def bench_diffusion(args, torch):
     return out
 
 
+# ------------------------------------------------------------------- multigrid
+def bench_multigrid(args, torch):
+    from paper_2012_08141_amd import engine as E
+    from paper_2012_08141_amd import inputs, programs as PR
+    w = inputs.band(args.seed, n=256)
+    K, W = args.steps, args.warmup
+    nl = 4
+    res = {}
+    for name, opt in (("optimized", E.OPT_ALL), ("eager", 0)):
+        E.reset()
+        lv = PR.mg_levels(w, nl)
+        # the first window builds the coarse levels; windows of the timed
+        # window's shape then leave its plan in the engine's plan cache
+        if W:
+            E.run_sequence(sum((PR.mg_vcycle(lv) for _ in range(W)), []), opt)
+        steps = sum((PR.mg_vcycle(lv) for _ in range(K)), [])
+        timed = E.prepare(steps)
+        cold = E.run_sequence(timed, opt)["optimizer_us"]
+        plan, _ = E.plan_sequence(steps, opt)
+        E.run_sequence(timed, opt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = E.run_sequence(timed, opt)
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0, st, plan, cold)
+        del lv
+    t, st, plan, cold = res["optimized"]
+    te, ste, plane, _ = res["eager"]
+    lists = {k: sum(1 for e in p if e["kind"] == 2) for k, p in (("optimized", plan), ("eager", plane))}
+    out = _base(K, W, w.active_voxels * K / t, t / K * 1e3,
+                {"workload": "multigrid256: V-cycles on a 256^3 narrow band (%d blocks; %d levels down to 32^3), "
+                             "per cycle 2+2 damped-Jacobi sweeps per level, 8 on the coarsest, residual "
+                             "restriction and injection prolongation; a step is one V-cycle" % (w.nblocks, nl),
+                 "seed": args.seed})
+    out.update({"launches_per_step": {"optimized": st["dispatches"] / K, "eager": ste["dispatches"] / K},
+                "list_generations_per_step": {"optimized": lists["optimized"] / K, "eager": lists["eager"] / K},
+                "paper_task_count_per_step": {"optimized": E.paper_task_count(plan) / K,
+                                              "eager": E.paper_task_count(plane) / K},
+                "activations_demoted": st["activations_demoted"],
+                "optimizer_us": {"timed_window": st["optimizer_us"], "cold_plan": cold,
+                                 "plan_cache_hits": st["plan_cache_hits"]},
+                "eager": {"value": w.active_voxels * K / te, "ms_per_step": te / K * 1e3},
+                "speedup_vs_eager": te / t})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -365,7 +412,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--n", type=int, default=512)
-    ap.add_argument("--workload", default="band512", choices=["band512", "shell", "particles", "serving", "diffusion"])
+    ap.add_argument("--workload", default="band512", choices=["band512", "shell", "particles", "serving", "diffusion",
+                                                           "multigrid"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=90)
     ap.add_argument("--requests", type=int, default=256)
@@ -384,7 +432,7 @@ def main():
     # finds its plan in the engine's plan cache (the cold planning time is
     # reported beside the result)
     defaults = {"band512": (100, 100), "shell": (100, 100), "particles": (20, 40), "serving": (256, 0),
-                "diffusion": (10, 2)}
+                "diffusion": (10, 2), "multigrid": (20, 5)}
     d = defaults[args.workload]
     args.steps = d[0] if args.steps is None else args.steps
     args.warmup = d[1] if args.warmup is None else args.warmup
@@ -394,7 +442,7 @@ def main():
     torch.cuda.set_device(0)
     settle_host()
     fn = {"band512": bench_band, "shell": bench_shell, "particles": bench_particles, "serving": bench_serving,
-          "diffusion": bench_diffusion}[args.workload]
+          "diffusion": bench_diffusion, "multigrid": bench_multigrid}[args.workload]
     out = fn(args, torch)
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib << 18

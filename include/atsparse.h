@@ -228,13 +228,29 @@ at_status at_gather_blocks(at_grid grid, int32_t ch, const int32_t *d_cells, flo
  *                     ch[0] = m, ch[1] = mv0
  *   AT_TASK_G2P       range-for: grid (gather source); ext[0] = x,
  *                     ext[1] = v (written); param[0] = dx; ch[0] = v0
- * Unused ch entries must be -1 and unused ext entries NULL. */
+ *   AT_TASK_RESTRICT  struct-for over grid (the fine level); grid2 = the
+ *                     coarse level (half the domain edge): for every listed
+ *                     fine voxel I, coarse[ch[1]][I/2] += param[0] * fine[ch[0]][I],
+ *                     activating the coarse blocks written (activation on
+ *                     write).  The 8 children of a coarse voxel are added one
+ *                     at a time in ascending order of their index inside
+ *                     their (common) fine block.  The downsample pattern of
+ *                     Section 6.3 (Fig. 5), in 3D.
+ *   AT_TASK_PROLONG   struct-for over grid (fine); grid2 = coarse: for every
+ *                     listed fine voxel I, fine[ch[1]][I] += coarse[ch[0]][I/2]
+ *                     (an inactive coarse voxel reads 0; the coarse grid is
+ *                     not written).  With RESTRICT, the transfers of the
+ *                     multigrid solver of Section 8.4.
+ * Unused ch entries must be -1 and unused ext entries NULL; grid2 is NULL
+ * except for the two-level tasks. */
 #define AT_TASK_ACTIVATE 1
 #define AT_TASK_LISTGEN  2
 #define AT_TASK_STENCIL  3
 #define AT_TASK_ADVECT   4
 #define AT_TASK_P2G      5
 #define AT_TASK_G2P      6
+#define AT_TASK_RESTRICT 7
+#define AT_TASK_PROLONG  8
 
 /* The particle arrays of this task are indexed only at the loop index, and
  * the loop index is unique per iteration and covers the array (the paper's
@@ -248,7 +264,7 @@ typedef struct at_task {
     uint32_t flags;       /* AT_TASKF_* */
     int32_t reserved;     /* must be 0 */
     at_grid grid;
-    at_grid grid2;        /* reserved, must be NULL */
+    at_grid grid2;        /* coarse level of RESTRICT / PROLONG; NULL otherwise */
     int32_t ch[8];        /* channels; unused entries -1 */
     float param[4];
     void *ext[4];         /* device pointers of external arrays */

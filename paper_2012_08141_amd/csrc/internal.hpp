@@ -113,6 +113,11 @@ hipError_t launch_listgen(const GridDev &g, uint64_t *flags, uint32_t epoch, hip
 hipError_t launch_stencil(const GridDev &g, int op, const int32_t *ch, float p, int check, int table,
                           hipStream_t s);
 hipError_t launch_micro(const GridDev &g, const MicroProg &prog, hipStream_t s);
+// Restriction (restrict_op; coarse[chc][I/2] += w * fine[chf][I]) or
+// prolongation (fine[chf][I] += coarse[chc][I/2]) over the fine grid's list;
+// check: activation on write of the blocks written.
+hipError_t launch_transfer(bool restrict_op, const GridDev &f, const GridDev &c, int chf, int chc, float w,
+                           int check, hipStream_t s);
 // Launches one particle task (1 dispatch, or 4 when its scatter is binned;
 // the count is stored in *dispatches).
 hipError_t launch_particles(const PartProg &prog, hipStream_t s, int *dispatches);

@@ -958,6 +958,87 @@ __global__ __launch_bounds__(64) void k_micro(GridDev g, MicroProg prog) {
     }
 }
 
+// ---------------------------------------------------- two-level transfers
+// A coarse grid has half the fine domain edge, so fine block (bi, bj, bk)
+// lies under coarse block (bi/2, bj/2, bk/2), in its octant
+// (bi&1, bj&1, bk&1) of 4^3 voxels.  One wavefront per listed fine block.
+
+// Restriction y[I/2] += w * x[I].  Lane l owns coarse voxel (l>>4, (l>>2)&3,
+// l&3) of the octant and adds its 8 children (two float2 loads per child
+// row pair) one at a time, in ascending order of their index in the fine
+// block.  The fine blocks under one coarse block write disjoint octants and a
+// fine block is listed once, so the read-modify-write needs no atomics; the
+// coarse block is activated by lane 0 first (CHECK) or looked up.
+template <int KF, int KC, bool CHECK>
+__global__ __launch_bounds__(64) void k_restrict(GridDev f, GridDev c, const float *__restrict__ x, float *y,
+                                                 float w) {
+    const int lane = threadIdx.x;
+    const ListRange lr = list_range(f.hdr[HDR_COUNT]);
+    const int ci = lane >> 4, cj = (lane >> 2) & 3, ck = lane & 3;
+    for (int e = lr.lo; e < lr.hi; e += lr.step) {
+        const int4 r = reinterpret_cast<const int4 *>(f.list + (int64_t)e * kRec)[0];
+        int bi, bj, bk;
+        cell_coords(f, r.x, bi, bj, bk);
+        const int64_t cc = ((int64_t)(bi >> 1) * c.R + (bj >> 1)) * c.R + (bk >> 1);
+        int32_t cs;
+        if (CHECK) {
+            int32_t a = 0;
+            if (lane == 0) a = activate_cell<KC>(c, cc);
+            cs = __builtin_amdgcn_readfirstlane(a);
+        } else {
+            cs = __builtin_amdgcn_readfirstlane(slot_of<KC>(c, cc));
+        }
+        if (cs < 0) continue;
+        const float *xp = x + (int64_t)r.y * kBV + (2 * ci) * 64 + (2 * cj) * 8 + 2 * ck;
+        float *yp = y + (int64_t)cs * kBV + ((bi & 1) * 4 + ci) * 64 + ((bj & 1) * 4 + cj) * 8 + (bk & 1) * 4 + ck;
+        float2 ch[4];
+#pragma unroll
+        for (int ab = 0; ab < 4; ++ab) ch[ab] = *reinterpret_cast<const float2 *>(xp + (ab >> 1) * 64 + (ab & 1) * 8);
+        float acc = *yp;
+#pragma unroll
+        for (int ab = 0; ab < 4; ++ab) {
+            const float t0 = w * ch[ab].x;
+            acc = acc + t0;
+            const float t1 = w * ch[ab].y;
+            acc = acc + t1;
+        }
+        *yp = acc;
+    }
+}
+
+// Prolongation by injection x[I] += y[I/2].  Lane l owns fine row
+// (l>>3, l&7, 0..7), which reads 4 consecutive coarse voxels (one float4);
+// an inactive coarse block reads as zeros.
+template <int KF, int KC, bool CHECK>
+__global__ __launch_bounds__(64) void k_prolong(GridDev f, GridDev c, const float *__restrict__ y, float *x) {
+    const int lane = threadIdx.x;
+    const ListRange lr = list_range(f.hdr[HDR_COUNT]);
+    const int li = lane >> 3, lj = lane & 7;
+    for (int e = lr.lo; e < lr.hi; e += lr.step) {
+        const int4 r = reinterpret_cast<const int4 *>(f.list + (int64_t)e * kRec)[0];
+        int bi, bj, bk;
+        cell_coords(f, r.x, bi, bj, bk);
+        const int64_t cc = ((int64_t)(bi >> 1) * c.R + (bj >> 1)) * c.R + (bk >> 1);
+        const int32_t cs = __builtin_amdgcn_readfirstlane(slot_of<KC>(c, cc));
+        int32_t fs = r.y;
+        if (CHECK) {
+            int32_t a = 0;
+            if (lane == 0) a = activate_cell<KF>(f, r.x);
+            fs = __builtin_amdgcn_readfirstlane(a);
+            if (fs < 0) continue;
+        }
+        float4 yv = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (cs >= 0)
+            yv = *reinterpret_cast<const float4 *>(y + (int64_t)cs * kBV + ((bi & 1) * 4 + (li >> 1)) * 64 +
+                                                   ((bj & 1) * 4 + (lj >> 1)) * 8 + (bk & 1) * 4);
+        float *xp = x + (int64_t)fs * kBV + lane * 8;
+        const float4 a = reinterpret_cast<const float4 *>(xp)[0];
+        const float4 b = reinterpret_cast<const float4 *>(xp)[1];
+        reinterpret_cast<float4 *>(xp)[0] = make_float4(a.x + yv.x, a.y + yv.x, a.z + yv.y, a.w + yv.y);
+        reinterpret_cast<float4 *>(xp)[1] = make_float4(b.x + yv.z, b.y + yv.z, b.z + yv.w, b.w + yv.w);
+    }
+}
+
 // ------------------------------------------------------------ batched Jacobi
 // Many independent pointer-rooted grids of one domain size share a leaf
 // pool.  The device work list holds (grid, root cell) pairs as
@@ -2126,6 +2207,31 @@ hipError_t launch_gather_blocks(const GridDev &g, int ch, const int32_t *cells, 
         hipLaunchKernelGGL(k_gather_blocks<AT_ROOT_BITMASK>, dim3(blocks), dim3(kSFThreads), 0, s, g, ch, cells, vals, n);
     else
         hipLaunchKernelGGL(k_gather_blocks<AT_ROOT_POINTER>, dim3(blocks), dim3(kSFThreads), 0, s, g, ch, cells, vals, n);
+    return hipGetLastError();
+}
+
+template <int KF, int KC>
+static void launch_transfer_k(bool restrict_op, const GridDev &f, const GridDev &c, int chf, int chc, float w,
+                              bool check, hipStream_t s) {
+    const dim3 grid(wave_grid_size(f, false)), block(64);
+    float *xf = f.chan + (int64_t)chf * f.ch_stride;
+    float *yc = c.chan + (int64_t)chc * c.ch_stride;
+    if (restrict_op) {
+        if (check) hipLaunchKernelGGL((k_restrict<KF, KC, true>), grid, block, 0, s, f, c, xf, yc, w);
+        else hipLaunchKernelGGL((k_restrict<KF, KC, false>), grid, block, 0, s, f, c, xf, yc, w);
+    } else {
+        if (check) hipLaunchKernelGGL((k_prolong<KF, KC, true>), grid, block, 0, s, f, c, yc, xf);
+        else hipLaunchKernelGGL((k_prolong<KF, KC, false>), grid, block, 0, s, f, c, yc, xf);
+    }
+}
+
+hipError_t launch_transfer(bool restrict_op, const GridDev &f, const GridDev &c, int chf, int chc, float w,
+                           int check, hipStream_t s) {
+    const bool fb = f.kind == AT_ROOT_BITMASK, cb = c.kind == AT_ROOT_BITMASK;
+    if (fb && cb) launch_transfer_k<AT_ROOT_BITMASK, AT_ROOT_BITMASK>(restrict_op, f, c, chf, chc, w, check, s);
+    else if (fb) launch_transfer_k<AT_ROOT_BITMASK, AT_ROOT_POINTER>(restrict_op, f, c, chf, chc, w, check, s);
+    else if (cb) launch_transfer_k<AT_ROOT_POINTER, AT_ROOT_BITMASK>(restrict_op, f, c, chf, chc, w, check, s);
+    else launch_transfer_k<AT_ROOT_POINTER, AT_ROOT_POINTER>(restrict_op, f, c, chf, chc, w, check, s);
     return hipGetLastError();
 }
 

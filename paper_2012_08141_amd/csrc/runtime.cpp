@@ -191,6 +191,14 @@ at_status execute_node(const Node &nd, const at_task *tasks, bool table, hipStre
         }
         break;
     }
+    case AT_TASK_RESTRICT:
+    case AT_TASK_PROLONG: {
+        const at_grid_s *c = reinterpret_cast<const at_grid_s *>(t0.grid2);
+        const bool r = t0.kind == AT_TASK_RESTRICT;
+        e = launch_transfer(r, g->dev, c->dev, r ? t0.ch[0] : t0.ch[1], r ? t0.ch[1] : t0.ch[0], t0.param[0],
+                            nd.check_activation ? 1 : 0, s);
+        break;
+    }
     case AT_TASK_ADVECT:
     case AT_TASK_P2G:
     case AT_TASK_G2P: {

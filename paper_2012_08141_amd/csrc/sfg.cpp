@@ -134,6 +134,33 @@ void member_accesses(const at_task &t, const Member &mb, bool check, int16_t mi,
         add(EXT(t.ext[1]), M_W, P_ELEM, u | F_FULL);
         break;
     }
+    case AT_TASK_RESTRICT: {
+        // fine values at the loop index; coarse values at I/2 (8 iterations
+        // per coarse voxel); the coarse mask is written when activating
+        const at_grid_s *c = reinterpret_cast<const at_grid_s *>(t.grid2);
+        add(LIST(gu), M_R, P_ELEM, 0);
+        add(VAL(gu, t.ch[0]), M_R, P_ELEM, U);
+        add(VAL(c->uid, t.ch[1]), M_R | M_W, P_SCATTER, 0);
+        if (check) {
+            add(MASK(c->uid), M_R | M_W, P_SCATTER, F_ACTIVATING);
+            if (c->desc.root_kind == AT_ROOT_POINTER) add(ALLOC(c->uid), M_R | M_W, P_SCATTER, F_ACTIVATING);
+        } else {
+            add(MASK(c->uid), M_R, P_GATHER, 0);
+        }
+        break;
+    }
+    case AT_TASK_PROLONG: {
+        const at_grid_s *c = reinterpret_cast<const at_grid_s *>(t.grid2);
+        add(LIST(gu), M_R, P_ELEM, 0);
+        add(VAL(c->uid, t.ch[0]), M_R, P_GATHER, 0);
+        add(MASK(c->uid), M_R, P_GATHER, 0);
+        add(VAL(gu, t.ch[1]), M_R | M_W, P_ELEM, U);
+        if (check) {
+            add(MASK(gu), M_R | M_W, P_ELEM, F_ACTIVATING | U);
+            if (ptr_root) add(ALLOC(gu), M_R | M_W, P_ELEM, F_ACTIVATING | U);
+        }
+        break;
+    }
     default: break;
     }
 }
@@ -149,6 +176,14 @@ struct Sim {
     bool edge(int i, int j) const { return (adj[(size_t)i * words + (j >> 6)] >> (j & 63)) & 1ull; }
     void set(int i, int j) { adj[(size_t)i * words + (j >> 6)] |= 1ull << (j & 63); }
 };
+
+// Identity of a restriction's activation: the coarse parents of the blocks
+// of one version of the fine grid's list.
+uint64_t restrict_sig(const at_task &t, uint64_t list_ver) {
+    uint64_t h = mix(0x52ull, reinterpret_cast<const at_grid_s *>(t.grid)->uid);
+    h = mix(h, reinterpret_cast<const at_grid_s *>(t.grid2)->uid);
+    return mix(h, list_ver);
+}
 
 uint64_t activation_sig(const at_task &t, uint64_t ext_ver) {
     const at_grid_s *g = task_grid(t);
@@ -199,6 +234,7 @@ Sim simulate(const std::vector<Node> &nodes, const at_task *tasks, const Persist
         if (nd.loop == LT_STRUCT) S.list_ver[i] = version_of(LIST(nd.loop_grid));
         if (t0.kind == AT_TASK_LISTGEN) S.mask_at[i] = version_of(MASK(task_grid(t0)->uid));
         if (t0.kind == AT_TASK_ACTIVATE) S.act_sig[i] = activation_sig(t0, version_of(EXT(t0.ext[0])));
+        if (t0.kind == AT_TASK_RESTRICT) S.act_sig[i] = restrict_sig(t0, S.list_ver[i]);
         for (const Access &a : nd.acc) {
             if (!(a.mode & M_R)) continue;
             const int k = sidx(a.s);
@@ -284,11 +320,12 @@ void Persist::deactivate_grid(uint64_t uid) {
 const at_grid_s *task_grid(const at_task &t) { return reinterpret_cast<const at_grid_s *>(t.grid); }
 
 std::string validate_task(const at_task &t) {
-    if (t.reserved != 0 || t.grid2 != nullptr) return "reserved task fields must be zero";
+    const bool two_level = t.kind == AT_TASK_RESTRICT || t.kind == AT_TASK_PROLONG;
+    if (t.reserved != 0 || (t.grid2 != nullptr && !two_level)) return "reserved task fields must be zero";
     const at_grid_s *g = task_grid(t);
     const bool needs_grid = t.kind == AT_TASK_ACTIVATE || t.kind == AT_TASK_LISTGEN || t.kind == AT_TASK_STENCIL ||
-                            t.kind == AT_TASK_P2G || t.kind == AT_TASK_G2P;
-    if (t.kind < AT_TASK_ACTIVATE || t.kind > AT_TASK_G2P) return "unknown task kind";
+                            t.kind == AT_TASK_P2G || t.kind == AT_TASK_G2P || two_level;
+    if (t.kind < AT_TASK_ACTIVATE || t.kind > AT_TASK_PROLONG) return "unknown task kind";
     if (needs_grid && !g) return "task needs a grid";
     auto chan_ok = [&](int c, int span) { return g && c >= 0 && c + span <= g->desc.channels; };
     switch (t.kind) {
@@ -337,6 +374,20 @@ std::string validate_task(const at_task &t) {
         if (!chan_ok(t.ch[0], 3)) return "g2p: channel out of range";
         if (!(t.param[0] > 0.f)) return "g2p: dx must be positive";
         break;
+    case AT_TASK_RESTRICT:
+    case AT_TASK_PROLONG: {
+        const at_grid_s *c = reinterpret_cast<const at_grid_s *>(t.grid2);
+        if (!c) return "two-level task needs the coarse grid in grid2";
+        if (c == g) return "two-level task: the coarse grid must differ from the fine grid";
+        if (c->desc.n[0] * 2 != g->desc.n[0] || c->virt != g->virt)
+            return "two-level task: the coarse grid must have half the fine domain edge (and the same handle kind)";
+        const int fch = t.kind == AT_TASK_RESTRICT ? t.ch[0] : t.ch[1];
+        const int cch = t.kind == AT_TASK_RESTRICT ? t.ch[1] : t.ch[0];
+        if (!chan_ok(fch, 1) || cch < 0 || cch >= c->desc.channels) return "two-level task: channel out of range";
+        for (int q = 2; q < 8; ++q)
+            if (t.ch[q] != -1) return "two-level task: unused channels must be -1";
+        break;
+    }
     }
     return "";
 }
@@ -345,7 +396,9 @@ void derive(Node &nd, const at_task *tasks) {
     const at_task &t0 = tasks[nd.members[0].task];
     const at_grid_s *g = task_grid(t0);
     switch (t0.kind) {
-    case AT_TASK_STENCIL: nd.loop = LT_STRUCT; nd.loop_grid = g->uid; nd.range = 0; break;
+    case AT_TASK_STENCIL:
+    case AT_TASK_RESTRICT:
+    case AT_TASK_PROLONG: nd.loop = LT_STRUCT; nd.loop_grid = g->uid; nd.range = 0; break;
     case AT_TASK_LISTGEN: nd.loop = LT_SERIAL; nd.loop_grid = 0; nd.range = 0; break;
     default: nd.loop = LT_RANGE; nd.loop_grid = 0; nd.range = t0.n; break;
     }
@@ -406,7 +459,10 @@ void Planner::build_eager() {
 bool Planner::pass_ad(const Persist &start) {
     bool changed = false;
     for (Node &nd : nodes) {
-        if (nd.loop == LT_STRUCT && nd.check_activation) {
+        // a struct-for writing its own grid at the loop index only touches
+        // listed (active) blocks; a restriction writes another grid and is
+        // demoted by its signature below
+        if (nd.loop == LT_STRUCT && nd.check_activation && !node_has_kind(nd, tasks_, AT_TASK_RESTRICT)) {
             nd.check_activation = false;
             counters.activations_demoted += (int64_t)nd.members.size();
             derive(nd, tasks_);
@@ -437,6 +493,24 @@ bool Planner::pass_ad(const Persist &start) {
                 continue;
             }
             it->second.insert(S.act_sig[i]);
+        }
+        if (t0.kind == AT_TASK_RESTRICT && nodes[i].check_activation) {
+            // the same list version of the fine grid was already restricted
+            // into this coarse grid: every parent block is active
+            const uint64_t cu = reinterpret_cast<const at_grid_s *>(t0.grid2)->uid;
+            auto it = sigs.find(cu);
+            if (it == sigs.end()) {
+                auto st = start.act_sigs.find(cu);
+                it = sigs.emplace(cu, st == start.act_sigs.end() ? std::unordered_set<uint64_t>() : st->second).first;
+            }
+            if (it->second.count(S.act_sig[i])) {
+                nodes[i].check_activation = false;
+                derive(nodes[i], tasks_);
+                counters.activations_demoted += 1;
+                changed = true;
+            } else {
+                it->second.insert(S.act_sig[i]);
+            }
         }
         kept.push_back(std::move(nodes[i]));
     }
@@ -842,6 +916,8 @@ void Planner::commit(const std::vector<Node> &nodes, const at_task *tasks, Persi
         const at_task &t0 = tasks[nodes[i].members[0].task];
         if (t0.kind == AT_TASK_LISTGEN) p.list_src[task_grid(t0)->uid] = S.mask_at[i];
         if (t0.kind == AT_TASK_ACTIVATE) p.act_sigs[task_grid(t0)->uid].insert(S.act_sig[i]);
+        if (t0.kind == AT_TASK_RESTRICT)
+            p.act_sigs[reinterpret_cast<const at_grid_s *>(t0.grid2)->uid].insert(S.act_sig[i]);
     }
     for (const auto &kv : S.cur) p.version[kv.first] = kv.second;
 }
@@ -864,6 +940,18 @@ std::vector<uint8_t> Planner::fingerprint(const at_task *tasks, int n, const Per
             const uint64_t ver = ev != extv.end() ? ev->second : p.ver(EXT(t.ext[0]));
             auto it = p.act_sigs.find(g->uid);
             fp.push_back(it != p.act_sigs.end() && it->second.count(activation_sig(t, ver)));
+        }
+        if (t.kind == AT_TASK_RESTRICT) {
+            // only the list version at the window's start can match a known
+            // signature: versions made inside the window are new
+            const at_grid_s *c = reinterpret_cast<const at_grid_s *>(t.grid2);
+            auto it = p.act_sigs.find(c->uid);
+            fp.push_back(it != p.act_sigs.end() && it->second.count(restrict_sig(t, p.ver(LIST(g->uid)))));
+            if (!seen.count(c->uid)) {
+                seen[c->uid] = 1;
+                auto ls = p.list_src.find(c->uid);
+                fp.push_back(ls != p.list_src.end() && ls->second == p.ver(MASK(c->uid)));
+            }
         }
         // external arrays written inside the window
         if (t.kind == AT_TASK_ADVECT) {

@@ -17,7 +17,8 @@ OPT_NONE = 0
 OPT_LGR, OPT_AD, OPT_FUSE, OPT_DSE, OPT_ALL = L.AT_OPT_LGR, L.AT_OPT_AD, L.AT_OPT_FUSE, L.AT_OPT_DSE, L.AT_OPT_ALL
 
 KIND_NAMES = {L.AT_TASK_ACTIVATE: "activate", L.AT_TASK_LISTGEN: "listgen", L.AT_TASK_STENCIL: "struct_for",
-              L.AT_TASK_ADVECT: "advect", L.AT_TASK_P2G: "p2g", L.AT_TASK_G2P: "g2p"}
+              L.AT_TASK_ADVECT: "advect", L.AT_TASK_P2G: "p2g", L.AT_TASK_G2P: "g2p",
+              L.AT_TASK_RESTRICT: "restrict", L.AT_TASK_PROLONG: "prolong"}
 OP_NAMES = {L.AT_OP_LAP_UPDATE: "lap_update", L.AT_OP_AXPY: "axpy", L.AT_OP_JACOBI: "jacobi",
             L.AT_OP_COPY: "copy", L.AT_OP_FILL: "fill", L.AT_OP_INC: "inc", L.AT_OP_DIFFUSE: "diffuse",
             L.AT_OP_DIFFUSE_ADJ: "diffuse_adj", L.AT_OP_NORMALISE: "normalise"}
@@ -106,6 +107,27 @@ def diffuse_adj(grid, a, k, lamn, lam, gk, dt):
 
 def normalise(grid, m, mv0, v0):
     return struct_for(grid, L.AT_OP_NORMALISE, [m, mv0, v0])
+
+
+# ---- two-level transfers (struct-fors over the fine grid) ----------------------
+def restrict(fine, coarse, src, dst, weight) -> Task:
+    """coarse[dst][I/2] += weight * fine[src][I] over the fine grid's list,
+    activating the coarse blocks written (coarse: half the domain edge)."""
+    T = _task(L.AT_TASK_RESTRICT, fine)
+    T.c.grid2 = coarse.handle.value
+    T.c.ch[0], T.c.ch[1] = src, dst
+    T.c.param[0] = weight
+    T.keep.append(coarse)
+    return T
+
+
+def prolong(coarse, fine, src, dst) -> Task:
+    """fine[dst][I] += coarse[src][I/2] over the fine grid's list."""
+    T = _task(L.AT_TASK_PROLONG, fine)
+    T.c.grid2 = coarse.handle.value
+    T.c.ch[0], T.c.ch[1] = src, dst
+    T.keep.append(coarse)
+    return T
 
 
 # ---- particle tasks ------------------------------------------------------------

@@ -82,3 +82,60 @@ def device_particles(p: inputs.ParticleWorkload):
     v = torch.as_tensor(p.v, device="cuda").contiguous()
     m = torch.as_tensor(p.m, device="cuda").contiguous()
     return x, v, m
+
+
+# ------------------------------------------------------- multigrid V-cycle
+MG = {"x": 0, "b": 1, "t": 2}
+
+
+def mg_smooth(g: SparseGrid, omega: float):
+    """Damped Jacobi: t = J(x); t = t - x; x = x + omega t, each struct-for
+    preceded by its list generation."""
+    return [E.listgen(g), E.jacobi(g, MG["x"], MG["b"], MG["t"]),
+            E.listgen(g), E.axpy(g, MG["t"], MG["x"], -1.0),
+            E.listgen(g), E.axpy(g, MG["x"], MG["t"], omega)]
+
+
+def mg_vcycle(levels, pre: int = 2, post: int = 2, coarse_iters: int = 8, omega: float = 0.75,
+              w_restrict: float = 1.5):
+    """One V-cycle over ``levels`` (finest first, each half the previous
+    domain edge): pre-smoothing, the scaled residual t = J(x) - x restricted
+    into the cleared coarse right-hand side (coarse[b][I/2] += w t[I]), the
+    coarsest level smoothed, then injection prolongation x[I] += x_c[I/2] and
+    post-smoothing on the way up.  The coarse levels' blocks come from the
+    restriction's activation on write."""
+    tasks = []
+    L = len(levels)
+    for l in range(L - 1):
+        g, c = levels[l], levels[l + 1]
+        for _ in range(pre):
+            tasks += mg_smooth(g, omega)
+        tasks += [E.listgen(g), E.jacobi(g, MG["x"], MG["b"], MG["t"]),
+                  E.listgen(g), E.axpy(g, MG["t"], MG["x"], -1.0),
+                  E.listgen(c), E.fill(c, [MG["x"]], 0.0),
+                  E.listgen(c), E.fill(c, [MG["b"]], 0.0),
+                  E.listgen(g), E.restrict(g, c, MG["t"], MG["b"], w_restrict)]
+    for _ in range(coarse_iters):
+        tasks += mg_smooth(levels[L - 1], omega)
+    for l in range(L - 2, -1, -1):
+        g, c = levels[l], levels[l + 1]
+        tasks += [E.listgen(g), E.prolong(c, g, MG["x"], MG["x"])]
+        for _ in range(post):
+            tasks += mg_smooth(g, omega)
+    return tasks
+
+
+def mg_levels(w: inputs.SparseWorkload, nlevels: int, stream=None):
+    """The level grids of a V-cycle solve: the finest holds the workload's
+    blocks and right-hand side ``b``; coarser levels start empty with room for
+    every ancestor block (pointer roots when the finest has one)."""
+    fine = SparseGrid(w.n, 3, w.root_kind, w.nblocks if w.root_kind == "pointer" else 0, stream=stream)
+    fine.load_blocks(MG["b"], w.cells, w.channels["b"], stream=stream)
+    levels = [fine]
+    blocks = np.asarray(w.blocks, dtype=np.int64)
+    for l in range(1, nlevels):
+        n = w.n >> l
+        anc = np.unique(blocks >> l, axis=0)
+        cap = len(anc) if w.root_kind == "pointer" else 0
+        levels.append(SparseGrid(n, 3, w.root_kind, cap, stream=stream))
+    return levels
