@@ -36,8 +36,8 @@ HBM_PEAK_GBS = 8000.0
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE), each scaled by the reading
 # for a plain 256 MiB copy in the same run.  Valid only for the kernel
 # source the counters were taken on; any change to it reports null.
-JACOBI_TRAFFIC = {"kernels_sha256": "914d9b182c8b604848274b6155a2f405b1801f0f26924261a54a6915812e6544",
-                  "bytes_per_launch": 83368916, "profile": "profiles/band512_jacobi_traffic.md"}
+JACOBI_TRAFFIC = {"kernels_sha256": "035d10b151dcbf8e04956196aeed27f63196d632c36b89fcb46d2ba2dd09abba",
+                  "bytes_per_launch": 83366464, "profile": "profiles/band512_jacobi_traffic.md"}
 
 
 def _jacobi_traffic():

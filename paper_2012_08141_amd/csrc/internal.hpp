@@ -113,6 +113,13 @@ hipError_t launch_listgen(const GridDev &g, uint64_t *flags, uint32_t epoch, hip
 hipError_t launch_stencil(const GridDev &g, int op, const int32_t *ch, float p, int check, int table,
                           hipStream_t s);
 hipError_t launch_micro(const GridDev &g, const MicroProg &prog, hipStream_t s);
+// A fused node whose first member is a single-output stencil op (LAP_UPDATE,
+// JACOBI, DIFFUSE, channels ch) and whose other members are element-wise ops
+// accepted by tail_op_supported (tail); neighbour slots from the list
+// records, no activation check.
+bool tail_op_supported(int op);
+hipError_t launch_stencil_tail(const GridDev &g, int op, const int32_t *ch, float p, const MicroProg &tail,
+                               hipStream_t s);
 // Restriction (restrict_op; coarse[chc][I/2] += w * fine[chf][I]) or
 // prolongation (fine[chf][I] += coarse[chc][I/2]) over the fine grid's list;
 // check: activation on write of the blocks written.

@@ -622,6 +622,73 @@ __device__ __forceinline__ void unpack(const Blk<NT, HAS_E> &B, int nt, Row &r) 
     for (int q = 0; q < 7; ++q) r.f[5][q] = r.c[q + 1];
 }
 
+// The values of a pipelined block for its op: r0 (and, for DIFFUSE_ADJ,
+// r1) at the lane's 8 voxels; cin = the centre row of the first stencil
+// input.
+template <int OP, int NT, bool HAS_E>
+__device__ __forceinline__ void pipe_compute(const Blk<NT, HAS_E> &cur, float p, float r0[8], float r1[8],
+                                             float cin[8]) {
+    put8(cin, cur.c0[0], cur.c1[0]);
+    if (OP == AT_OP_LAP_UPDATE) {
+        Row A;
+        unpack(cur, 0, A);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const float s = nbsum(A, q);
+            const float six_a = 6.0f * A.c[q];
+            const float d = s - six_a;
+            const float tq = p * d;
+            r0[q] = A.c[q] + tq;
+        }
+    } else if (OP == AT_OP_JACOBI) {
+        Row X;
+        unpack(cur, 0, X);
+        float b[8];
+        put8(b, cur.e0, cur.e1);
+        const float sixth = 0x1.555556p-3f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const float s = nbsum(X, q);
+            const float tq = s + b[q];
+            r0[q] = tq * sixth;
+        }
+    } else if (OP == AT_OP_DIFFUSE) {
+        Row A, K;
+        unpack(cur, 0, A);
+        unpack(cur, 1, K);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            float f = 0.f;
+#pragma unroll
+            for (int fc = 0; fc < 6; ++fc) {
+                const float kf = 0.5f * (K.c[q] + K.f[fc][q]);
+                f = f + kf * (A.f[fc][q] - A.c[q]);
+            }
+            r0[q] = A.c[q] + p * f;
+        }
+    } else if (OP == AT_OP_DIFFUSE_ADJ) {
+        Row A, K, L;
+        unpack(cur, 0, A);
+        unpack(cur, 1, K);
+        unpack(cur, 2, L);
+        float gk[8];
+        put8(gk, cur.e0, cur.e1);
+        const float half_dt = p * 0.5f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            float f = 0.f, q2 = 0.f;
+#pragma unroll
+            for (int fc = 0; fc < 6; ++fc) {
+                const float kf = 0.5f * (K.c[q] + K.f[fc][q]);
+                f = f + kf * (L.f[fc][q] - L.c[q]);
+                q2 = q2 + (A.f[fc][q] - A.c[q]) * (L.c[q] - L.f[fc][q]);
+            }
+            r0[q] = L.c[q] + p * f;
+            r1[q] = gk[q] + half_dt * q2;
+        }
+    }
+}
+
 template <int OP, int KIND, bool CHECK>
 __global__ __launch_bounds__(64) void k_stencil_pipe(GridDev g, const int32_t *__restrict__ recs, StencilCh c,
                                                      float p) {
@@ -707,6 +774,90 @@ __global__ __launch_bounds__(64) void k_stencil_pipe(GridDev g, const int32_t *_
             store8(c.out0 + off, r0);
             store8(c.out1 + off, r1);
         }
+        cur = nxt;
+    }
+}
+
+// A fused struct-for whose first member is a single-output stencil op
+// (LAP_UPDATE, JACOBI, DIFFUSE) followed by element-wise ops (AXPY, INC,
+// COPY, FILL): the stencil runs pipelined as above and the element-wise ops
+// are applied per voxel, in program order, to the lane's 8 voxels.  The
+// stencil's output stays in registers until the end and the centre row of its
+// first input is reused; other channels are read and written at the voxel
+// (a thread sees its own earlier stores).  No activation check: fused nodes
+// with one run the general interpreter.
+template <int OP, int KIND>
+__global__ __launch_bounds__(64) void k_stencil_tail(GridDev g, const int32_t *__restrict__ recs, StencilCh c,
+                                                     float p, MicroProg tail, int out_ch, int in_ch) {
+    constexpr int NT = NTiles<OP>::v;
+    constexpr bool HAS_E = (OP == AT_OP_JACOBI || OP == AT_OP_DIFFUSE_ADJ);
+    const int lane = threadIdx.x;
+    const ListRange lr = list_range(g.hdr[HDR_COUNT]);
+    if (lr.lo >= lr.hi) return;
+    Blk<NT, HAS_E> cur, nxt;
+    fetch_blk<NT, HAS_E>(c, recs, __builtin_amdgcn_readfirstlane(lr.lo), lane, cur);
+    for (int e = lr.lo; e < lr.hi; e += lr.step) {
+        const int en = e + lr.step < lr.hi ? e + lr.step : e;
+        fetch_blk<NT, HAS_E>(c, recs, __builtin_amdgcn_readfirstlane(en), lane, nxt);
+        const int64_t off = (int64_t)cur.slot * kBV + lane * 8;
+        float r0[8], r1[8], cin[8];
+        pipe_compute<OP, NT, HAS_E>(cur, p, r0, r1, cin);
+        auto get = [&](int ch, float v[8]) {
+            if (ch == out_ch) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) v[q] = r0[q];
+            } else if (ch == in_ch) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) v[q] = cin[q];
+            } else {
+                const float *src = chan(g, ch) + off;
+                put8(v, reinterpret_cast<const float4 *>(src)[0], reinterpret_cast<const float4 *>(src)[1]);
+            }
+        };
+        auto set = [&](int ch, const float v[8]) {
+            if (ch == out_ch) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) r0[q] = v[q];
+            } else {
+                store8(chan(g, ch) + off, v);
+                if (ch == in_ch) {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) cin[q] = v[q];
+                }
+            }
+        };
+        for (int o = 0; o < tail.nops; ++o) {
+            const MicroOp &op = tail.ops[o];
+            float y[8], x[8];
+            switch (op.op) {
+            case AT_OP_AXPY:
+                get(op.ch[0], y);
+                get(op.ch[1], x);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) y[q] = y[q] + op.p * x[q];
+                set(op.ch[0], y);
+                break;
+            case AT_OP_INC:
+                get(op.ch[0], y);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) y[q] = y[q] + op.p;
+                set(op.ch[0], y);
+                break;
+            case AT_OP_COPY:
+                get(op.ch[1], y);
+                set(op.ch[0], y);
+                break;
+            case AT_OP_FILL:
+#pragma unroll
+                for (int q = 0; q < 8; ++q) y[q] = op.p;
+                for (int k = 0; k < 7; ++k)
+                    if (op.ch[k] >= 0 && ((op.keep >> k) & 1u)) set(op.ch[k], y);
+                break;
+            default:
+                break;
+            }
+        }
+        store8(c.out0 + off, r0);
         cur = nxt;
     }
 }
@@ -2050,6 +2201,45 @@ static bool launch_elem_k(const GridDev &g, const MicroOp &op, dim3 grid, hipStr
         return true;
     default: return false;
     }
+}
+
+bool tail_op_supported(int op) {
+    return op == AT_OP_AXPY || op == AT_OP_INC || op == AT_OP_COPY || op == AT_OP_FILL;
+}
+
+template <int OP>
+static void launch_tail_k(const GridDev &g, const StencilCh &c, float p, const MicroProg &tail, int out_ch,
+                          int in_ch, hipStream_t s) {
+    const dim3 grid(wave_grid_size(g, true)), block(64);
+    if (g.kind == AT_ROOT_BITMASK)
+        hipLaunchKernelGGL((k_stencil_tail<OP, AT_ROOT_BITMASK>), grid, block, 0, s, g, (const int32_t *)g.list, c, p,
+                           tail, out_ch, in_ch);
+    else
+        hipLaunchKernelGGL((k_stencil_tail<OP, AT_ROOT_POINTER>), grid, block, 0, s, g, (const int32_t *)g.list, c, p,
+                           tail, out_ch, in_ch);
+}
+
+hipError_t launch_stencil_tail(const GridDev &g, int op, const int32_t *ch, float p, const MicroProg &tail,
+                               hipStream_t s) {
+    StencilCh c{};
+    auto C = [&](int i) { return g.chan + (int64_t)ch[i] * g.ch_stride; };
+    switch (op) {
+    case AT_OP_LAP_UPDATE:
+        c.tin[0] = C(0); c.out0 = C(1);
+        launch_tail_k<AT_OP_LAP_UPDATE>(g, c, p, tail, ch[1], ch[0], s);
+        break;
+    case AT_OP_JACOBI:
+        c.tin[0] = C(0); c.ein = C(1); c.out0 = C(2);
+        launch_tail_k<AT_OP_JACOBI>(g, c, p, tail, ch[2], ch[0], s);
+        break;
+    case AT_OP_DIFFUSE:
+        c.tin[0] = C(0); c.tin[1] = C(1); c.out0 = C(2);
+        launch_tail_k<AT_OP_DIFFUSE>(g, c, p, tail, ch[2], ch[0], s);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_micro(const GridDev &g, const MicroProg &prog, hipStream_t s) {

@@ -172,8 +172,24 @@ at_status execute_node(const Node &nd, const at_task *tasks, bool table, hipStre
         const Member &m0 = nd.members[0];
         const bool tiled = t0.op == AT_OP_LAP_UPDATE || t0.op == AT_OP_JACOBI || t0.op == AT_OP_DIFFUSE ||
                            t0.op == AT_OP_DIFFUSE_ADJ;
+        bool tail = nd.members.size() > 1 && tiled && t0.op != AT_OP_DIFFUSE_ADJ && m0.keep == ~0u &&
+                    !nd.check_activation && table && struct_for_kernel() == 0 &&
+                    nd.members.size() - 1 <= (size_t)kMaxOps;
+        for (size_t q = 1; tail && q < nd.members.size(); ++q) tail = tail_op_supported(tasks[nd.members[q].task].op);
         if (nd.members.size() == 1 && tiled && m0.keep == ~0u) {
             e = launch_stencil(g->dev, t0.op, t0.ch, t0.param[0], nd.check_activation ? 1 : 0, table ? 1 : 0, s);
+        } else if (tail) {
+            MicroProg prog{};
+            prog.nops = (int32_t)nd.members.size() - 1;
+            for (size_t q = 1; q < nd.members.size(); ++q) {
+                const at_task &t = tasks[nd.members[q].task];
+                MicroOp &op = prog.ops[q - 1];
+                op.op = t.op;
+                for (int c = 0; c < 7; ++c) op.ch[c] = t.ch[c];
+                op.p = t.param[0];
+                op.keep = nd.members[q].keep;
+            }
+            e = launch_stencil_tail(g->dev, t0.op, t0.ch, t0.param[0], prog, s);
         } else {
             MicroProg prog{};
             prog.nops = (int32_t)nd.members.size();
