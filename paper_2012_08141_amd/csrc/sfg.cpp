@@ -417,6 +417,8 @@ uint64_t hash_window(const at_task *tasks, int n, uint32_t flags, int max_fuse) 
         h = mix(h, (uint64_t)(uint32_t)t.kind | ((uint64_t)(uint32_t)t.op << 32));
         h = mix(h, t.flags);
         h = mix(h, g ? g->uid : 0);
+        const at_grid_s *g2 = reinterpret_cast<const at_grid_s *>(t.grid2);
+        h = mix(h, g2 ? g2->uid : 0);
         for (int q = 0; q < 8; ++q) h = mix(h, (uint64_t)(uint32_t)t.ch[q]);
         for (int q = 0; q < 4; ++q) {
             uint32_t b;

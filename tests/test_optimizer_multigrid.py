@@ -113,3 +113,25 @@ def test_two_level_task_validation():
     t = E.restrict(f, c, 0, 1, 0.5)
     t.c.grid2 = None
     assert status(t) == L.AT_E_INVALID
+
+
+def test_plan_cache_tells_coarse_grids_apart():
+    """Two windows that differ only in the coarse grid of a restriction get
+    their own plans, even from start states that look alike to the cache:
+    restricting into c1 modifies c1's mask, so the list generation of c1 after
+    it stays; restricting into c2 leaves c1's list current and removes it."""
+    f = SparseGrid(64, 3, "bitmask", device=None)
+    c1 = SparseGrid(32, 3, "bitmask", device=None)
+    c2 = SparseGrid(32, 3, "bitmask", device=None)
+    fresh = [E.listgen(f), E.listgen(c1), E.listgen(c2)]
+
+    def window(c):
+        return [E.listgen(c1), E.listgen(c2), E.restrict(f, c, 0, 1, 0.5), E.listgen(c1), E.inc(c1, 0, 1.0)]
+
+    E.run_sequence(fresh, E.OPT_ALL)
+    st2 = E.run_sequence(window(c2), E.OPT_ALL)            # records state only
+    assert st2["tasks_launched"] == 2 and st2["listgens_removed"] == 3
+    E.run_sequence(fresh, E.OPT_ALL)
+    st1 = E.run_sequence(window(c1), E.OPT_ALL)
+    assert st1["plan_cache_hits"] == 0
+    assert st1["tasks_launched"] == 3 and st1["listgens_removed"] == 2
