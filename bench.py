@@ -36,8 +36,8 @@ HBM_PEAK_GBS = 8000.0
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE), each scaled by the reading
 # for a plain 256 MiB copy in the same run.  Valid only for the kernel
 # source the counters were taken on; any change to it reports null.
-JACOBI_TRAFFIC = {"kernels_sha256": "035d10b151dcbf8e04956196aeed27f63196d632c36b89fcb46d2ba2dd09abba",
-                  "bytes_per_launch": 83366464, "profile": "profiles/band512_jacobi_traffic.md"}
+JACOBI_TRAFFIC = {"kernels_sha256": "22b5ef38115e196b64e1258667d19d86c2c814e42439c501a1d893b92c92ec8a",
+                  "bytes_per_launch": 83363495, "profile": "profiles/band512_jacobi_traffic.md"}
 
 
 def _jacobi_traffic():
@@ -85,12 +85,13 @@ def _host_cpu():
 def time_kernel(torch, E, task_fn, reps, windows=3):
     """Average duration of back-to-back launches of one task, from HIP events
     on the stream the launches go to: the median over `windows` windows of
-    `reps` launches.  An untimed run of the same window first puts its plan
-    in the engine's plan cache, so no host planning falls between the
-    events."""
+    `reps` launches.  Two untimed runs of the same window first put its plan
+    in the engine's plan cache and its HIP graph in the graph cache, so no
+    host planning or graph capture falls between the events."""
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     tasks = E.prepare([task_fn() for _ in range(reps)])
+    E.run_sequence(tasks, E.OPT_AD)
     E.run_sequence(tasks, E.OPT_AD)
     torch.cuda.synchronize()
     per = []
@@ -118,6 +119,8 @@ def bench_band(args, torch):
         warm = E.prepare(sum((PR.jacobi_step(g) for _ in range(W)), []))
         timed = E.prepare(sum((PR.jacobi_step(g) for _ in range(K)), []))
         cold = E.run_sequence(warm, opt) if W else None
+        if W:
+            E.run_sequence(warm, opt)                     # plan cached: captures the window's graph
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         st = E.run_sequence(timed, opt)
@@ -361,17 +364,27 @@ def bench_diffusion(args, torch):
 
 # ------------------------------------------------------------------- multigrid
 def bench_multigrid(args, torch):
+    from paper_2012_08141_amd import _lib as L
     from paper_2012_08141_amd import engine as E
     from paper_2012_08141_amd import inputs, programs as PR
     w = inputs.band(args.seed, n=256)
     K, W = args.steps, args.warmup
     nl = 4
+
+    def timed_run(window, opt):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = E.run_sequence(window, opt)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, st
+
     res = {}
     for name, opt in (("optimized", E.OPT_ALL), ("eager", 0)):
         E.reset()
         lv = PR.mg_levels(w, nl)
         # the first window builds the coarse levels; windows of the timed
-        # window's shape then leave its plan in the engine's plan cache
+        # window's shape then leave its plan in the engine's plan cache (and,
+        # optimized, its HIP graph in the graph cache)
         if W:
             E.run_sequence(sum((PR.mg_vcycle(lv) for _ in range(W)), []), opt)
         steps = sum((PR.mg_vcycle(lv) for _ in range(K)), [])
@@ -379,14 +392,16 @@ def bench_multigrid(args, torch):
         cold = E.run_sequence(timed, opt)["optimizer_us"]
         plan, _ = E.plan_sequence(steps, opt)
         E.run_sequence(timed, opt)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st = E.run_sequence(timed, opt)
-        torch.cuda.synchronize()
-        res[name] = (time.perf_counter() - t0, st, plan, cold)
+        t, st = timed_run(timed, opt)
+        nog = None
+        if opt:
+            E.set_option(L.AT_OPTION_GRAPHS, 0)
+            nog = timed_run(timed, opt)[0]
+            E.set_option(L.AT_OPTION_GRAPHS, 1)
+        res[name] = (t, st, plan, cold, nog)
         del lv
-    t, st, plan, cold = res["optimized"]
-    te, ste, plane, _ = res["eager"]
+    t, st, plan, cold, nog = res["optimized"]
+    te, ste, plane, _, _ = res["eager"]
     lists = {k: sum(1 for e in p if e["kind"] == 2) for k, p in (("optimized", plan), ("eager", plane))}
     out = _base(K, W, w.active_voxels * K / t, t / K * 1e3,
                 {"workload": "multigrid256: V-cycles on a 256^3 narrow band (%d blocks; %d levels down to 32^3), "
@@ -401,6 +416,7 @@ def bench_multigrid(args, torch):
                 "optimizer_us": {"timed_window": st["optimizer_us"], "cold_plan": cold,
                                  "plan_cache_hits": st["plan_cache_hits"]},
                 "eager": {"value": w.active_voxels * K / te, "ms_per_step": te / K * 1e3},
+                "optimized_without_graphs": {"value": w.active_voxels * K / nog, "ms_per_step": nog / K * 1e3},
                 "speedup_vs_eager": te / t})
     return out
 

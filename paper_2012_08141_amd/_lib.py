@@ -34,6 +34,8 @@ AT_OPTION_BATCH_WAVES = 7
 AT_OPTION_G2P_BINS = 8
 AT_OPTION_BIN_REUSE = 9
 AT_OPTION_FUSE_BATCH = 10
+AT_OPTION_GRAPHS = 11
+AT_OPTION_GRAPHS_CACHED = 12
 
 
 class AtGridDesc(ctypes.Structure):

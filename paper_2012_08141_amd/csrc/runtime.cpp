@@ -10,6 +10,7 @@
 // window's task descriptors (the IR-bank analogue of Section 7.2).
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cstdarg>
@@ -78,6 +79,15 @@ struct Engine {
     bool timing = false;
     std::vector<hipEvent_t> ev_free;
     std::vector<Timed> timed;
+    // HIP graphs of repeated optimized windows (see run_window)
+    struct Graph {
+        hipGraphExec_t exec;
+        int64_t dispatches;
+        std::vector<uint64_t> uids;   // grids whose memory the launches use
+    };
+    bool graphs = true;
+    std::unordered_map<uint64_t, Graph> graph_cache;
+    hipStream_t capture_stream = nullptr;
 };
 
 Engine &E() {
@@ -380,6 +390,103 @@ bool node_on_device(const Node &nd, const at_task *tasks) {
     return true;
 }
 
+// Windows whose plan came from the plan cache and whose launches depend on
+// nothing but the tasks and the plan -- struct-fors and two-level transfers
+// (no list generation, whose launch carries a per-launch epoch; no
+// activation; no particle task, whose binning state the host decides per
+// launch) -- are captured once into a HIP graph on a side stream and
+// replayed on the caller's stream afterwards: one host call instead of one
+// per launch.  Windows of fewer than kGraphMinLaunches launches run directly:
+// measured on the 20-step diffusion windows, a graph launch of a handful of
+// kernels costs the host more than launching them.  The key covers the
+// window, its plan, the neighbour-table choice of every node and the
+// kernel-selection options.
+constexpr size_t kGraphMinLaunches = 16;   // below this, direct launches cost the host less than a graph launch
+
+bool graph_eligible(const std::vector<Node> &nodes, const at_task *tasks) {
+    if (nodes.size() < kGraphMinLaunches) return false;
+    for (const Node &nd : nodes)
+        for (const Member &m : nd.members) {
+            const int k = tasks[m.task].kind;
+            if (k != AT_TASK_STENCIL && k != AT_TASK_RESTRICT && k != AT_TASK_PROLONG) return false;
+        }
+    return true;
+}
+
+uint64_t graph_key(const at_task *tasks, int ntasks, uint32_t flags, const std::vector<Node> &nodes,
+                   const std::vector<uint8_t> &tables) {
+    auto mixk = [](uint64_t h, uint64_t v) {
+        h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+        return h * 0xff51afd7ed558ccdull;
+    };
+    uint64_t h = hash_window(tasks, ntasks, flags, E().max_fuse);
+    for (size_t i = 0; i < nodes.size(); ++i) {
+        const Node &nd = nodes[i];
+        h = mixk(h, 0x4e0d3ull ^ nd.members.size());
+        for (const Member &m : nd.members) h = mixk(mixk(h, (uint64_t)m.task), m.keep);
+        h = mixk(h, (uint64_t)nd.check_activation | ((uint64_t)(uint32_t)nd.act_mode << 8) |
+                        ((uint64_t)tables[i] << 40));
+    }
+    h = mixk(h, (uint64_t)(uint32_t)struct_for_kernel());
+    return mixk(h, (uint64_t)(uint32_t)struct_for_grid_size_override());
+}
+
+void drop_graphs(bool sync) {
+    Engine &en = E();
+    if (en.graph_cache.empty()) return;
+    if (sync) (void)hipDeviceSynchronize();
+    for (auto &kv : en.graph_cache) (void)hipGraphExecDestroy(kv.second.exec);
+    en.graph_cache.clear();
+}
+
+// Replays (or captures, then launches) the window's graph; false when the
+// window is not eligible or capture failed (the caller then launches
+// directly, nothing having run).
+bool run_as_graph(const std::vector<Node> &nodes, const at_task *tasks, int ntasks, uint32_t flags,
+                  const std::vector<uint8_t> &tables, hipStream_t s, at_status &st) {
+    Engine &en = E();
+    st = AT_OK;
+    if (!en.graphs || en.timing || !graph_eligible(nodes, tasks)) return false;
+    const uint64_t key = graph_key(tasks, ntasks, flags, nodes, tables);
+    auto it = en.graph_cache.find(key);
+    if (it == en.graph_cache.end()) {
+        if (!en.capture_stream && hipStreamCreateWithFlags(&en.capture_stream, hipStreamNonBlocking) != hipSuccess) {
+            en.capture_stream = nullptr;
+            return false;
+        }
+        if (en.graph_cache.size() >= 64) drop_graphs(true);
+        hipStream_t cs = en.capture_stream;
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+        const int64_t d0 = en.dispatches.load();
+        at_status est = AT_OK;
+        for (size_t i = 0; i < nodes.size() && est == AT_OK; ++i) est = execute_node(nodes[i], tasks, tables[i] != 0, cs);
+        hipGraph_t graph = nullptr;
+        const hipError_t ee = hipStreamEndCapture(cs, &graph);
+        const int64_t nd = en.dispatches.load() - d0;
+        en.dispatches.fetch_sub(nd);   // counted when the graph runs
+        hipGraphExec_t exec = nullptr;
+        const bool ok = est == AT_OK && ee == hipSuccess && graph &&
+                        hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+        if (graph) (void)hipGraphDestroy(graph);
+        if (!ok) {
+            (void)hipGetLastError();
+            return false;
+        }
+        Engine::Graph G{exec, nd, {}};
+        for (int i = 0; i < ntasks; ++i)
+            for (const at_grid_s *g : {(const at_grid_s *)tasks[i].grid, (const at_grid_s *)tasks[i].grid2})
+                if (g && std::find(G.uids.begin(), G.uids.end(), g->uid) == G.uids.end()) G.uids.push_back(g->uid);
+        it = en.graph_cache.emplace(key, std::move(G)).first;
+    }
+    const hipError_t e = hipGraphLaunch(it->second.exec, s);
+    if (e != hipSuccess) {
+        st = hip_fail(e, "graph launch");
+        return true;
+    }
+    en.dispatches.fetch_add(it->second.dispatches);
+    return true;
+}
+
 at_status run_window(const at_task *tasks, int ntasks, uint32_t flags, at_stats *stats, hipStream_t s) {
     Engine &en = E();
     std::lock_guard<std::recursive_mutex> lk(en.mu);
@@ -403,6 +510,12 @@ at_status run_window(const at_task *tasks, int ntasks, uint32_t flags, at_stats 
     const std::vector<uint8_t> tables = neighbour_tables_valid(nodes, tasks, en.persist);
     ++en.window_seq;
     en.pos_writes.clear();
+    if (!any_virt && hits > 0 && run_as_graph(nodes, tasks, ntasks, flags, tables, s, st)) {
+        Planner::commit(nodes, tasks, en.persist);
+        if (st != AT_OK) return st;
+        fill_stats(stats, ntasks, nodes, ctr, en.dispatches.load() - d0, us, hits);
+        return AT_OK;
+    }
     for (size_t i = 0; i < nodes.size() && !any_virt; ++i) {
         const Node &nd = nodes[i];
         hipEvent_t ea = nullptr;
@@ -533,9 +646,18 @@ at_status at_grid_destroy(at_grid grid) {
         Engine &en = E();
         std::lock_guard<std::recursive_mutex> lk(en.mu);
         for (const at_task &t : en.queue)
-            if (t.grid == grid) return fail(AT_E_STATE, "grid has queued tasks; flush first");
+            if (t.grid == grid || t.grid2 == grid) return fail(AT_E_STATE, "grid has queued tasks; flush first");
         en.persist.forget_grid(grid->uid);
         en.live.erase(grid->uid);
+        for (auto it = en.graph_cache.begin(); it != en.graph_cache.end();) {
+            const auto &u = it->second.uids;
+            if (std::find(u.begin(), u.end(), grid->uid) != u.end()) {
+                (void)hipGraphExecDestroy(it->second.exec);   // freed once any launch in flight completes
+                it = en.graph_cache.erase(it);
+            } else {
+                ++it;
+            }
+        }
     }
     delete grid;
     return AT_OK;
@@ -885,6 +1007,12 @@ at_status at_set_option(int32_t option, int64_t value) {
         en.fuse_batch = value != 0;
         en.cache.clear();
         return AT_OK;
+    case AT_OPTION_GRAPHS_CACHED: return fail(AT_E_INVALID, "the number of cached graphs is read-only");
+    case AT_OPTION_GRAPHS:
+        if (value != 0 && value != 1) return fail(AT_E_INVALID, "graphs must be 0 or 1");
+        en.graphs = value != 0;
+        if (!en.graphs) drop_graphs(true);
+        return AT_OK;
     default:
         return fail(AT_E_INVALID, "unknown option %d", option);
     }
@@ -905,6 +1033,8 @@ at_status at_get_option(int32_t option, int64_t *value) {
     case AT_OPTION_G2P_BINS: *value = en.g2p_bins ? 1 : 0; return AT_OK;
     case AT_OPTION_BIN_REUSE: *value = en.bin_reuse; return AT_OK;
     case AT_OPTION_FUSE_BATCH: *value = en.fuse_batch ? 1 : 0; return AT_OK;
+    case AT_OPTION_GRAPHS: *value = en.graphs ? 1 : 0; return AT_OK;
+    case AT_OPTION_GRAPHS_CACHED: *value = (int64_t)en.graph_cache.size(); return AT_OK;
     default: return fail(AT_E_INVALID, "unknown option %d", option);
     }
 }
@@ -915,6 +1045,7 @@ at_status at_engine_reset(void) {
     en.persist = Persist{};
     en.cache.clear();
     en.queue.clear();
+    drop_graphs(true);
     return AT_OK;
 }
 

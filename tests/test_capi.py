@@ -119,7 +119,8 @@ def test_options_roundtrip():
     assert lib.at_set_option(L.AT_OPTION_MAX_FUSE_PER_TASK, 1) == L.AT_OK
     assert lib.at_set_option(L.AT_OPTION_MAX_FUSE_PER_TASK, 0) == L.AT_E_INVALID
     assert lib.at_set_option(999, 0) == L.AT_E_INVALID
-    for opt, good, bad in ((L.AT_OPTION_G2P_BINS, (0, 1), (2, -1)), (L.AT_OPTION_BIN_REUSE, (0, 3, 8), (-1, 1025))):
+    for opt, good, bad in ((L.AT_OPTION_G2P_BINS, (0, 1), (2, -1)), (L.AT_OPTION_BIN_REUSE, (0, 3, 8), (-1, 1025)),
+                           (L.AT_OPTION_GRAPHS, (0, 1), (2, -1))):
         assert lib.at_get_option(opt, ctypes.byref(v)) == L.AT_OK
         default = v.value
         for x in good:
@@ -128,6 +129,8 @@ def test_options_roundtrip():
         for x in bad:
             assert lib.at_set_option(opt, x) == L.AT_E_INVALID
         assert lib.at_set_option(opt, default) == L.AT_OK
+    assert lib.at_get_option(L.AT_OPTION_GRAPHS_CACHED, ctypes.byref(v)) == L.AT_OK and v.value >= 0
+    assert lib.at_set_option(L.AT_OPTION_GRAPHS_CACHED, 0) == L.AT_E_INVALID
     assert lib.at_version().startswith(b"atsparse")
 
 
