@@ -363,13 +363,13 @@ at_status at_flush(at_stats *stats, hipStream_t stream);
  * pair at a time (0) gives; the plans are the same, only planning time
  * differs.  Clears the plan cache. */
 #define AT_OPTION_FUSE_BATCH 10
-/* HIP graphs: 1 (default) captures a window whose plan came from the plan
- * cache, which launches at least 16 nodes and which holds only struct-fors
- * and two-level transfers (no list generation, activation or particle task)
- * into a HIP graph on an internal stream the first time, and replays it on
- * the window's stream afterwards;
- * same launches, same results, one host call.  Graphs are dropped when a
- * grid they use is destroyed, on at_engine_reset and when set to 0. */
+/* HIP graphs: 1 captures a window whose plan came from the plan cache,
+ * which launches at least 16 nodes and which holds only struct-fors and
+ * two-level transfers (no list generation, activation or particle task) into
+ * a HIP graph on an internal stream the first time, and replays it on the
+ * window's stream afterwards (default 0: launches are issued directly);
+ * same launches, same results, one host call.  Cached graphs are dropped
+ * when a grid they use is destroyed and on at_engine_reset. */
 #define AT_OPTION_GRAPHS 11
 /* Read-only: the number of window graphs currently cached. */
 #define AT_OPTION_GRAPHS_CACHED 12

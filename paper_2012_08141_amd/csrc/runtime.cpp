@@ -85,7 +85,7 @@ struct Engine {
         int64_t dispatches;
         std::vector<uint64_t> uids;   // grids whose memory the launches use
     };
-    bool graphs = true;
+    bool graphs = false;
     std::unordered_map<uint64_t, Graph> graph_cache;
     hipStream_t capture_stream = nullptr;
 };
@@ -1010,8 +1010,7 @@ at_status at_set_option(int32_t option, int64_t value) {
     case AT_OPTION_GRAPHS_CACHED: return fail(AT_E_INVALID, "the number of cached graphs is read-only");
     case AT_OPTION_GRAPHS:
         if (value != 0 && value != 1) return fail(AT_E_INVALID, "graphs must be 0 or 1");
-        en.graphs = value != 0;
-        if (!en.graphs) drop_graphs(true);
+        en.graphs = value != 0;   // cached graphs stay until reset or their grids go
         return AT_OK;
     default:
         return fail(AT_E_INVALID, "unknown option %d", option);

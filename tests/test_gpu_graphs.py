@@ -26,7 +26,7 @@ def graphs_default():
     from paper_2012_08141_amd import engine as E
     E.reset()
     yield
-    E.set_option(L.AT_OPTION_GRAPHS, 1)
+    E.set_option(L.AT_OPTION_GRAPHS, 0)
     E.reset()
     torch.cuda.synchronize()
 
@@ -79,6 +79,7 @@ def test_graph_dropped_with_its_grid():
     from paper_2012_08141_amd import engine as E, programs as PR
     say("graph replay: grid destroyed and replaced")
     w = I.band(4, n=64)
+    E.set_option(L.AT_OPTION_GRAPHS, 1)
     results = []
     for trial in range(2):
         g = PR.load_workload(w, PR.JACOBI, 3)
