@@ -126,14 +126,15 @@ def test_restrict_into_empty_pointer_grid_fills_its_pool():
     E.reset()
 
 
+@pytest.mark.parametrize("root", ["bitmask", "pointer"])
 @pytest.mark.parametrize("opt", [0, 15])
-def test_vcycle_program(opt):
-    """Two 3-level V-cycles on a 64^3 narrow band, eager and optimized, against
-    the oracle's V-cycle program; the optimized window launches far fewer
-    tasks and demotes the second cycle's restrictions."""
+def test_vcycle_program(opt, root):
+    """Two 3-level V-cycles on a 64^3 narrow band, eager and optimized, on both
+    root kinds, against the oracle's V-cycle program; the optimized window
+    launches far fewer tasks and demotes the second cycle's restrictions."""
     from paper_2012_08141_amd import engine as E, programs as PR
-    say("vcycle opt", opt)
-    w = I.band(3, n=64)
+    say("vcycle opt", opt, root)
+    w = I.band(3, n=64, root_kind=root)
     E.reset()
     levels = PR.mg_levels(w, 3)
     tasks = PR.mg_vcycle(levels) + PR.mg_vcycle(levels)

@@ -255,26 +255,37 @@ def test_fused_elementwise_program():
     assert np.array_equal(g.read_blocks(0, cells), o.read_blocks(0, cells))
 
 
+HEADS = {
+    "jacobi": (lambda E, g: E.jacobi(g, 0, 1, 2), lambda o: o.jacobi(0, 1, 2)),
+    "lap_update": (lambda E, g: E.lap_update(g, 0, 2, 0.1), lambda o: o.lap_update(0, 2, 0.1)),
+    "diffuse": (lambda E, g: E.diffuse(g, 0, 1, 2, 0.1), lambda o: o.diffuse(0, 1, 2, 0.1)),
+}
+
+
 @pytest.mark.parametrize("root", ["bitmask", "pointer"])
-def test_fused_stencil_with_elementwise_tail(root):
-    """A Jacobi sweep fused with the element-wise tasks after it (the tail
-    reads the sweep's output, its stencil input and other channels, and writes
-    them) equals the oracle running the tasks one by one, bit for bit."""
+@pytest.mark.parametrize("head", list(HEADS))
+def test_fused_stencil_with_elementwise_tail(root, head):
+    """A single-output stencil fused with the element-wise tasks after it (the
+    tail reads the stencil's output, its stencil input and other channels,
+    and writes them) equals the oracle running the tasks one by one, bit for
+    bit."""
     from paper_2012_08141_amd import engine as E
-    say("fused stencil + tail", root)
+    say("fused stencil + tail", head, root)
     w = I.random_blocks(17, 64, 0.3, root, channels=("c0", "c1", "c2", "c3", "c4", "c5"))
+    w.channels["c1"] = np.abs(w.channels["c1"]) + 0.5       # a positive conductance for diffuse
     names = {"c%d" % q: q for q in range(6)}
     g, o = grid_pair(w, 6, names)
     E.reset()
     E.run_sequence([E.listgen(g)], E.OPT_ALL)
-    tasks = [E.jacobi(g, 0, 1, 2), E.axpy(g, 2, 0, -1.0), E.inc(g, 3, 0.5), E.copy(g, 4, 2),
+    mk, ref = HEADS[head]
+    tasks = [mk(E, g), E.axpy(g, 2, 0, -1.0), E.inc(g, 3, 0.5), E.copy(g, 4, 2),
              E.axpy(g, 3, 1, 2.0), E.fill(g, [5], 1.5), E.axpy(g, 2, 3, 0.25)]
     plan, _ = E.plan_sequence(tasks, E.OPT_ALL)
     assert len(plan) == 1 and len(plan[0]["members"]) == len(tasks)
     st = E.run_sequence(tasks, E.OPT_ALL)
     assert st["dispatches"] == 1
     o.listgen()
-    o.jacobi(0, 1, 2); o.axpy(2, 0, -1.0); o.inc(3, 0.5); o.copy(4, 2); o.axpy(3, 1, 2.0); o.fill(5, 1.5)
+    ref(o); o.axpy(2, 0, -1.0); o.inc(3, 0.5); o.copy(4, 2); o.axpy(3, 1, 2.0); o.fill(5, 1.5)
     o.axpy(2, 3, 0.25)
     torch.cuda.synchronize()
     cells = o.active_cells()
