@@ -176,3 +176,26 @@ def test_vcycle_full_size():
     torch.cuda.synchronize()
     assert torch.equal(le[0].channel(0), lo[0].channel(0))
     E.reset()
+
+
+def test_cleared_coarse_level_is_rebuilt():
+    """Clearing a coarse level (a deactivating write) drops what the engine knew
+    about restrictions into it: the next V-cycle activates its blocks again.
+    Optimized equals eager bit for bit before and after the clear."""
+    from paper_2012_08141_amd import engine as E, programs as PR
+    say("vcycle with a cleared coarse level")
+    w = I.band(5, n=64)
+    E.reset()
+    lo, le = PR.mg_levels(w, 3), PR.mg_levels(w, 3)
+    for phase in range(2):
+        E.run_sequence(PR.mg_vcycle(lo) + PR.mg_vcycle(lo), E.OPT_ALL)
+        E.run_sequence(PR.mg_vcycle(le) + PR.mg_vcycle(le), 0)
+        torch.cuda.synchronize()
+        if phase == 1:
+            # the cleared level got its blocks back from the restriction
+            assert np.array_equal(lo[1].active_cells(), le[1].active_cells())
+            assert len(lo[1].active_cells()) > 0
+        for l in range(3):
+            assert torch.equal(lo[l].channel(0), le[l].channel(0)), (phase, l)
+        lo[1].clear(); le[1].clear()
+    E.reset()
