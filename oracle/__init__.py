@@ -24,6 +24,9 @@ What pins each function (tests/test_oracle_pins.py):
   Jacobi eigenmodes, a direct Poisson solve, linear-field diffusion fluxes.
 * diffuse_adj -- dot-product identities in a and k, and central finite
   differences of a multi-step loss.
+* advect_sl -- the dense implementation (bit-exact), zero velocity (a copy),
+  whole-voxel velocities (exact shifts with zeros entering), reproduction of
+  linear fields, and one block's values carried into a neighbour block.
 * restrict_to, prolong_from -- the dense implementation (bit-exact), the
   parent-block active set, constants, and the adjoint identity between the
   two transfers.
@@ -82,6 +85,7 @@ def _lib(prec: str):
         "og_p2g": (i64, [P, i32, i32, i32, P, P, P, i64, R]),
         "og_normalise": (None, [P, i32, i32, i32]),
         "og_restrict": (None, [P, P, i32, i32, R]),
+        "og_advect_sl": (None, [P, i32, i32, i32, R]),
         "og_prolong": (None, [P, P, i32, i32]),
         "og_g2p": (None, [P, i32, P, P, i64, R]),
         "og_bspline": (i32, [R, P]),
@@ -218,6 +222,10 @@ class OracleGrid:
 
     def diffuse_adj(self, ch_a: int, ch_k: int, ch_lamn: int, ch_lam: int, ch_gk: int, dt: float):
         self._L.og_diffuse_adj(self._g, ch_a, ch_k, ch_lamn, ch_lam, ch_gk, self.dtype(dt))
+
+    def advect_sl(self, ch_q: int, ch_v: int, ch_out: int, dt: float):
+        """out[I] = q at I - dt * v(I), trilinear (v in ch_v .. ch_v + 2)."""
+        self._L.og_advect_sl(self._g, ch_q, ch_v, ch_out, self.dtype(dt))
 
     # -- two-level transfers (struct-fors over this, the fine grid) -----------
     def restrict_to(self, coarse: "OracleGrid", ch_x: int, ch_y: int, w: float = 0.125):

@@ -107,6 +107,31 @@ class DenseGrid:
     def inc(self, ch, value):
         self._store(ch, self._field(ch) + self.dtype.type(value))
 
+    def advect_sl(self, ch_q, ch_v, ch_out, dt):
+        """out[I] = q(I - dt v(I)) trilinear, with whole-array gathers: the
+        corner indices are clipped into a zero-padded copy of q."""
+        T = self.dtype.type
+        n = self.n
+        q = self._field(ch_q)
+        pad = np.zeros((n + 6,) * 3, dtype=self.dtype)
+        pad[3:n + 3, 3:n + 3, 3:n + 3] = q
+        idx = np.indices((n, n, n)).astype(self.dtype)
+        base, w = [], []
+        for d in range(3):
+            p = idx[d] - T(dt) * self._field(ch_v + d)
+            p = np.minimum(np.maximum(p, T(-2)), T(n + 1)).astype(self.dtype)
+            b = np.floor(p).astype(self.dtype)
+            f = (p - b).astype(self.dtype)
+            base.append(b.astype(np.int64) + 3)
+            w.append(((T(1) - f).astype(self.dtype), f))
+        s = np.zeros((n, n, n), dtype=self.dtype)
+        for a in (0, 1):
+            for b in (0, 1):
+                for c in (0, 1):
+                    wt = ((w[0][a] * w[1][b]).astype(self.dtype) * w[2][c]).astype(self.dtype)
+                    s = (s + wt * pad[base[0] + a, base[1] + b, base[2] + c]).astype(self.dtype)
+        self._store(ch_out, s)
+
     # -- two-level transfers (this grid is the fine one) ----------------------------
     def restrict_to(self, coarse, ch_x, ch_y, w):
         """coarse.y[I//2] += w * x[I] over this grid's listed blocks: the coarse

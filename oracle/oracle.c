@@ -210,6 +210,47 @@ void og_write_block(og_grid *g, int ch, int32_t cell, const REAL *vals) {
                 }                                                                   \
     }
 
+/* Semi-Lagrangian advection, the building block of the MacCormack benchmark
+ * (Section 8.1) and of the supplement's simple advection microbenchmark:
+ * every listed voxel I takes q at the back-traced point p = I - dt * v(I)
+ * (grid units, one Euler step; v in channels ch_v .. ch_v + 2), trilinearly
+ * interpolated from the 8 voxels around p.  Reads outside the domain or in
+ * inactive blocks give 0.  Fixed order: corners (a, b, c) in {0, 1}^3
+ * lexicographic, weight (wx[a] * wy[b]) * wz[c], s = s + w * q.  A point
+ * further than 2 voxels outside the domain is moved to 2 voxels outside (all
+ * its corners read 0 either way), which keeps the corner indices in range. */
+static REAL clamp_coord(REAL p, int n) {
+    if (p < (REAL)-2) return (REAL)-2;
+    if (p > (REAL)(n + 1)) return (REAL)(n + 1);
+    return p;
+}
+
+void og_advect_sl(og_grid *g, int ch_q, int ch_v, int ch_out, REAL dt) {
+    FOR_EACH_LISTED_VOXEL(g, {
+        REAL p[3];
+        p[0] = clamp_coord((REAL)i - dt * rd(g, ch_v, i, j, k), g->n);
+        p[1] = clamp_coord((REAL)j - dt * rd(g, ch_v + 1, i, j, k), g->n);
+        p[2] = clamp_coord((REAL)k - dt * rd(g, ch_v + 2, i, j, k), g->n);
+        int base[3];
+        REAL w[3][2];
+        for (int d = 0; d < 3; ++d) {
+            REAL b = (REAL)floor((double)p[d]);
+            REAL f = p[d] - b;
+            base[d] = (int)b;
+            w[d][0] = (REAL)1 - f;
+            w[d][1] = f;
+        }
+        REAL s = (REAL)0;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int c = 0; c < 2; ++c) {
+                    REAL wt = (w[0][a] * w[1][b]) * w[2][c];
+                    s = s + wt * rd(g, ch_q, base[0] + a, base[1] + b, base[2] + c);
+                }
+        wr(g, ch_out, i, j, k, s);
+    })
+}
+
 /* ------------------------------------------ two-level transfers (Sec. 6.3)
  * A coarse grid has half the fine domain edge; fine voxel (i, j, k) lies
  * under coarse voxel (i/2, j/2, k/2).  Both transfers are struct-fors over
