@@ -14,7 +14,8 @@ included) bracketed by device synchronisation.
 Other workloads (--workload): shell (64^3 activate/lap_update/axpy),
 particles (2M-particle PIC), serving (256 Poisson-arriving 128^3 Jacobi
 requests, continuous batching), diffusion (128^3 forward + adjoint) and
-multigrid (V-cycles over a 256^3 band and its coarse levels).
+multigrid (V-cycles over a 256^3 band and its coarse levels) and advection
+(three scalar fields on a 256^3 tube).
 
 Prints one JSON line.
 """
@@ -368,6 +369,43 @@ def bench_diffusion(args, torch):
     return out
 
 
+# ------------------------------------------------------------------- advection
+def bench_advection(args, torch):
+    from paper_2012_08141_amd import engine as E
+    from paper_2012_08141_amd import inputs, programs as PR
+    w = inputs.tube(args.seed)
+    dt = w.params["dt"]
+    K, W = args.steps, args.warmup
+    names = {"q0": 0, "q1": 1, "q2": 2, "v0": 3, "v1": 4, "v2": 5}
+    res = {}
+    for name, opt in (("optimized", E.OPT_ALL), ("eager", 0)):
+        E.reset()
+        g = PR.load_workload(w, names, 9)
+        step = E.prepare(PR.advection_step(g, dt))     # one engine window per step
+        for _ in range(max(W, 2)):
+            E.run_sequence(step, opt)
+        torch.cuda.synchronize()
+        d0 = E.dispatch_count()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            E.run_sequence(step, opt)
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0, E.dispatch_count() - d0, E.plan_sequence(PR.advection_step(g, dt), opt)[0])
+        del step, g
+    t, d, plan = res["optimized"]
+    te, de, plane = res["eager"]
+    out = _base(K, W, w.active_voxels * K / t, t / K * 1e3,
+                {"workload": "advection256: semi-Lagrangian advection of 3 scalar fields by a swirling velocity on a "
+                             "256^3 tube (r 0.32-0.45, %d blocks); per step and field listgen, advect, listgen, "
+                             "copy, one engine window per step" % w.nblocks, "seed": args.seed})
+    out.update({"launches_per_step": {"optimized": d / K, "eager": de / K},
+                "paper_task_count_per_step": {"optimized": E.paper_task_count(plan),
+                                              "eager": E.paper_task_count(plane)},
+                "eager": {"value": w.active_voxels * K / te, "ms_per_step": te / K * 1e3},
+                "speedup_vs_eager": te / t})
+    return out
+
+
 # ------------------------------------------------------------------- multigrid
 def bench_multigrid(args, torch):
     from paper_2012_08141_amd import _lib as L
@@ -435,7 +473,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--workload", default="band512", choices=["band512", "shell", "particles", "serving", "diffusion",
-                                                           "multigrid"])
+                                                           "multigrid", "advection"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=90)
     ap.add_argument("--requests", type=int, default=256)
@@ -454,7 +492,7 @@ def main():
     # finds its plan in the engine's plan cache (the cold planning time is
     # reported beside the result)
     defaults = {"band512": (100, 100), "shell": (100, 100), "particles": (20, 40), "serving": (256, 0),
-                "diffusion": (40, 5), "multigrid": (20, 5)}
+                "diffusion": (40, 5), "multigrid": (20, 5), "advection": (50, 5)}
     d = defaults[args.workload]
     args.steps = d[0] if args.steps is None else args.steps
     args.warmup = d[1] if args.warmup is None else args.warmup
@@ -464,7 +502,8 @@ def main():
     torch.cuda.set_device(0)
     settle_host()
     fn = {"band512": bench_band, "shell": bench_shell, "particles": bench_particles, "serving": bench_serving,
-          "diffusion": bench_diffusion, "multigrid": bench_multigrid}[args.workload]
+          "diffusion": bench_diffusion, "multigrid": bench_multigrid,
+          "advection": bench_advection}[args.workload]
     out = fn(args, torch)
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib << 18

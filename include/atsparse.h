@@ -160,6 +160,13 @@ at_status at_listgen(at_grid grid, hipStream_t stream);
                                 lam = lamn + dt*f; gk = gk + (dt*0.5)*g                    */
 #define AT_OP_NORMALISE   9  /* ch {m, mv0, v0}: v_c = m > 0 ? mv_c / m : 0, c = 0..2 on
                                 channels mv0+c, v0+c                                       */
+#define AT_OP_ADVECT     10  /* ch {q, v0, out}; p {dt}: semi-Lagrangian advection (the
+                                building block of the MacCormack benchmark, Section 8.1):
+                                out[I] = q at p = I - dt*v(I) (grid units; v on channels
+                                v0..v0+2), trilinear over the 8 voxels around p, corners
+                                (a,b,c) lexicographic, weight (wx*wy)*wz, s = s + w*q;
+                                reads outside the domain or in inactive blocks give 0; a
+                                point more than 2 voxels outside is moved to 2 outside    */
 
 /* ch: host array of channel indices (meaning per op above); params: host
  * array of up to 4 floats.  check_activation != 0 keeps the per-write

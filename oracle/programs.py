@@ -210,3 +210,21 @@ def multigrid_program(n, blocks, b, cycles, levels=3, precision="f32", **kw):
     cells = G[0].active_cells()
     return {"cells": cells, "x": G[0].read_blocks(MG_X, cells),
             "level_cells": [g.active_cells() for g in G], "grids": G}
+
+
+
+# ---------------------------------------------------------------------------
+def advection_program(n, blocks, channels, dt, steps, precision="f32"):
+    """Per step and scalar field c: listgen -> advect_sl (tmp_c = q_c at
+    I - dt v(I)) -> listgen -> copy (q_c = tmp_c).  Channels: q0..q2 = 0..2,
+    v0..v2 = 3..5, tmp0..tmp2 = 6..8.  Returns the three fields."""
+    g = OracleGrid(n, 9, precision)
+    g.load(blocks, channels, {"q0": 0, "q1": 1, "q2": 2, "v0": 3, "v1": 4, "v2": 5})
+    for _ in range(steps):
+        for c in range(3):
+            g.listgen()
+            g.advect_sl(c, 3, 6 + c, dt)
+            g.listgen()
+            g.copy(c, 6 + c)
+    cells = g.active_cells()
+    return {"cells": cells, "q": [g.read_blocks(c, cells) for c in range(3)]}

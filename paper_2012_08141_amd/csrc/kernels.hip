@@ -974,6 +974,22 @@ __device__ __forceinline__ float rd_nb(const GridDev &g, const float *base, int3
     return s >= 0 ? base[(int64_t)s * kBV + ii * 64 + jj * 8 + kk] : 0.f;
 }
 
+// Value of channel `base` at voxel (x, y, z) of an n^3 domain with sparse
+// semantics (0 outside the domain or in an inactive block); the wave's own
+// block is resolved without a root lookup.
+template <int KIND>
+__device__ __forceinline__ float sample_voxel(const GridDev &g, const float *base, int64_t own_cell, int32_t own_slot,
+                                              int x, int y, int z, int n) {
+    if (x < 0 || y < 0 || z < 0 || x >= n || y >= n || z >= n) return 0.f;
+    const int64_t c = ((int64_t)(x >> 3) * g.R + (y >> 3)) * g.R + (z >> 3);
+    const int32_t s = c == own_cell ? own_slot : slot_of<KIND>(g, c);
+    return s >= 0 ? base[(int64_t)s * kBV + (x & 7) * 64 + (y & 7) * 8 + (z & 7)] : 0.f;
+}
+
+__device__ __forceinline__ float clamp_coord(float p, int n) {
+    return p < -2.f ? -2.f : (p > (float)(n + 1) ? (float)(n + 1) : p);
+}
+
 template <int KIND, bool STENCIL>
 __global__ __launch_bounds__(64) void k_micro(GridDev g, MicroProg prog) {
     // one wavefront per block; lane l owns voxels [8l, 8l+8) = row
@@ -1042,6 +1058,39 @@ __global__ __launch_bounds__(64) void k_micro(GridDev g, MicroProg prog) {
                         for (int q = 0; q < 4; ++q) r[q] = mm[q] > 0.f ? mvv[q] / mm[q] : 0.f;
                         *reinterpret_cast<float4 *>(chan(g, op.ch[2] + cc) + off) = make_float4(r[0], r[1], r[2], r[3]);
                     }
+                    break;
+                }
+                case AT_OP_ADVECT: {
+                    // semi-Lagrangian: q at I - dt v(I), trilinear, fixed corner order
+                    const float *Q = chan(g, op.ch[0]);
+                    const int n = g.R * 8;
+                    int bi, bj, bk;
+                    cell_coords(g, cell, bi, bj, bk);
+                    float r[4];
+                    for (int q = 0; q < 4; ++q) {
+                        const int I[3] = {bi * 8 + li, bj * 8 + lj, bk * 8 + k0 + q};
+                        float w[3][2];
+                        int b0[3];
+                        for (int d = 0; d < 3; ++d) {
+                            const float vd = chan(g, op.ch[1] + d)[off + q];
+                            const float pd = clamp_coord((float)I[d] - op.p * vd, n);
+                            const float bd = floorf(pd);
+                            const float f = pd - bd;
+                            b0[d] = (int)bd;
+                            w[d][0] = 1.0f - f;
+                            w[d][1] = f;
+                        }
+                        float acc = 0.f;
+                        for (int a = 0; a < 2; ++a)
+                            for (int b = 0; b < 2; ++b)
+                                for (int c = 0; c < 2; ++c) {
+                                    const float wt = (w[0][a] * w[1][b]) * w[2][c];
+                                    acc = acc + wt * sample_voxel<KIND>(g, Q, cell, slot, b0[0] + a, b0[1] + b,
+                                                                        b0[2] + c, n);
+                                }
+                        r[q] = acc;
+                    }
+                    *reinterpret_cast<float4 *>(chan(g, op.ch[2]) + off) = make_float4(r[0], r[1], r[2], r[3]);
                     break;
                 }
                 case AT_OP_LAP_UPDATE:

@@ -40,6 +40,7 @@ int op_nch(int op) {
     case AT_OP_DIFFUSE: return 3;
     case AT_OP_DIFFUSE_ADJ: return 5;
     case AT_OP_NORMALISE: return 3;
+    case AT_OP_ADVECT: return 3;
     default: return -1;
     }
 }
@@ -87,6 +88,12 @@ void member_accesses(const at_task &t, const Member &mb, bool check, int16_t mi,
         case AT_OP_DIFFUSE_ADJ:
             rd(c[0], true); rd(c[1], true); rd(c[2], true);
             wr(c[3], true, false); wr(c[4], false, true);
+            break;
+        case AT_OP_ADVECT:
+            // q at back-traced points (any offset), v at the voxel
+            rd(c[0], true);
+            for (int q = 0; q < 3; ++q) rd(c[1] + q, false);
+            wr(c[2], true, false);
             break;
         case AT_OP_NORMALISE:
             rd(c[0], false);
@@ -346,6 +353,10 @@ std::string validate_task(const at_task &t) {
                 }
             if (cnt == 0) return "fill: no channel";
             if (t.ch[7] >= 0) return "fill: at most 7 channels";
+        } else if (t.op == AT_OP_ADVECT) {
+            if (!chan_ok(t.ch[0], 1) || !chan_ok(t.ch[1], 3) || !chan_ok(t.ch[2], 1)) return "advect: channel out of range";
+            if (t.ch[2] == t.ch[0] || (t.ch[2] >= t.ch[1] && t.ch[2] < t.ch[1] + 3))
+                return "advect: the output aliases an input";
         } else if (t.op == AT_OP_NORMALISE) {
             if (!chan_ok(t.ch[0], 1) || !chan_ok(t.ch[1], 3) || !chan_ok(t.ch[2], 3)) return "normalise: channel out of range";
         } else {

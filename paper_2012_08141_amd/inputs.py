@@ -248,3 +248,34 @@ def random_particles(seed: int, n: int, nparticles: int, lo: float = 0.1, hi: fl
     m = np.ones(nparticles, dtype=np.float32)
     return ParticleWorkload("randp%d" % n, n, root_kind, x, v, m,
                             {"dt": 1e-3, "dx": 1.0 / n, "steps": 4})
+
+
+# ---------------------------------------------------------------------------
+# Advection workload: a tube domain (the paper's MacCormack benchmark setup:
+# 256^3 cells, tube of inner radius 0.32 and outer radius 0.45) carrying three
+# scalar fields and a swirling velocity field.
+# ---------------------------------------------------------------------------
+def tube(seed: int = 0, n: int = 256, r_in: float = 0.32, r_out: float = 0.45,
+         root_kind: str = "bitmask") -> SparseWorkload:
+    """Blocks whose centre lies at a distance in [r_in, r_out] from the axis
+    x = y = 0.5; scalar fields ``q0``, ``q1``, ``q2`` ~ U(0, 1); velocity (in
+    voxels per unit time) v = s * (-(y - 0.5), x - 0.5, w) * n at voxel
+    centres, with s ~ U(2, 4) and w ~ U(-0.5, 0.5) from the seed, so that a
+    step of dt = 1 / n moves a voxel by at most about 2 voxels."""
+    rng = np.random.default_rng([6, seed])
+    R = n // BLOCK
+    c = _block_centres(R)
+    d = np.hypot(c[:, 0] - 0.5, c[:, 1] - 0.5)
+    blocks = _select((d >= r_in) & (d <= r_out), R)
+    s = rng.uniform(2.0, 4.0)
+    wz = rng.uniform(-0.5, 0.5)
+    ch = {}
+    for name in ("q0", "q1", "q2"):
+        ch[name] = rng.uniform(0.0, 1.0, (blocks.shape[0], BLOCK_VOXELS)).astype(np.float32)
+    li, lj, _ = np.meshgrid(np.arange(BLOCK), np.arange(BLOCK), np.arange(BLOCK), indexing="ij")
+    x = ((blocks[:, 0:1] * BLOCK + li.reshape(1, -1)) + 0.5) / n
+    y = ((blocks[:, 1:2] * BLOCK + lj.reshape(1, -1)) + 0.5) / n
+    ch["v0"] = (s * -(y - 0.5) * n).astype(np.float32)
+    ch["v1"] = (s * (x - 0.5) * n).astype(np.float32)
+    ch["v2"] = np.full_like(ch["v0"], s * wz * n)
+    return SparseWorkload("tube%d" % n, n, root_kind, blocks, ch, {"dt": 1.0 / n, "speed": s, "axial": wz})

@@ -139,3 +139,18 @@ def mg_levels(w: inputs.SparseWorkload, nlevels: int, stream=None):
         cap = len(anc) if w.root_kind == "pointer" else 0
         levels.append(SparseGrid(n, 3, w.root_kind, cap, stream=stream))
     return levels
+
+
+# ---------------------------------------------------------- advection workload
+ADV = {"q": 0, "v": 3, "tmp": 6}            # q0..q2; v0..v2; tmp0..tmp2  (9 channels)
+
+
+def advection_step(g: SparseGrid, dt: float):
+    """Per scalar field c, as separate kernels (the multi-kernel structure of
+    the paper's advection benchmark): listgen -> advect (tmp_c = q_c at the
+    back-traced point) -> listgen -> copy (q_c = tmp_c)."""
+    tasks = []
+    for c in range(3):
+        tasks += [E.listgen(g), E.advect_sl(g, ADV["q"] + c, ADV["v"], ADV["tmp"] + c, dt),
+                  E.listgen(g), E.copy(g, ADV["q"] + c, ADV["tmp"] + c)]
+    return tasks

@@ -1,0 +1,97 @@
+"""Semi-Lagrangian advection on the device against the oracle.
+
+The advection op (the building block of the paper's MacCormack benchmark,
+Section 8.1) samples q trilinearly at the back-traced point of every voxel,
+in a fixed corner order, so it matches the oracle bit for bit: alone, with
+and without the activation check, on both root kinds, with back-traced
+points in other, inactive or absent blocks; and as the three-field program,
+whose optimized form fuses the three advections and the three copies into
+two launches per step."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import programs as OP
+from paper_2012_08141_amd import _lib as L
+from paper_2012_08141_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2012_08141_amd import engine as E
+    E.reset()
+    yield
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("root", ["bitmask", "pointer"])
+@pytest.mark.parametrize("check", [True, False])
+def test_advect_op(root, check):
+    from paper_2012_08141_amd.grid import SparseGrid
+    say("advect op", root, check)
+    n = 64
+    w = I.random_blocks(31, n, 0.3, root, channels=("q", "v0", "v1", "v2", "o"))
+    for c in ("v0", "v1", "v2"):
+        w.channels[c] = (w.channels[c] * 9.0).astype(np.float32)      # back-traces up to ~8 voxels
+    names = {"q": 0, "v0": 1, "v1": 2, "v2": 3, "o": 4}
+    g = SparseGrid(n, 5, root, w.R ** 3 if root == "pointer" else 0)
+    o = oracle.OracleGrid(n, 5)
+    for name, vals in w.channels.items():
+        g.load_blocks(names[name], w.cells, vals)
+    o.load(w.blocks, w.channels, names)
+    g.listgen(); o.listgen()
+    extra = I.random_blocks(32, n, 0.1, root).blocks
+    g.activate(extra); o.activate(extra)
+    g.run_stencil(L.AT_OP_ADVECT, [0, 1, 4], 0.6, check)
+    o.advect_sl(0, 1, 4, 0.6)
+    torch.cuda.synchronize()
+    cells = o.active_cells()
+    assert np.array_equal(g.active_cells(), cells)
+    for q in range(5):
+        assert np.array_equal(g.read_blocks(q, cells), o.read_blocks(q, cells)), q
+
+
+@pytest.mark.parametrize("opt", [0, 15])
+def test_advection_program(opt):
+    """Three steps of the three-field program on a 64^3 tube, one window per
+    step, eager and optimized, bit-exact against the oracle."""
+    from paper_2012_08141_amd import engine as E, programs as PR
+    say("advection program opt", opt)
+    w = I.tube(1, n=64)
+    dt = w.params["dt"]
+    E.reset()
+    g = PR.load_workload(w, {"q0": 0, "q1": 1, "q2": 2, "v0": 3, "v1": 4, "v2": 5}, 9)
+    step = E.prepare(PR.advection_step(g, dt))
+    disp = [E.run_sequence(step, opt)["dispatches"] for _ in range(3)]
+    assert disp[-1] == (12 if opt == 0 else 2)
+    ref = OP.advection_program(w.n, w.blocks, w.channels, dt, 3)
+    torch.cuda.synchronize()
+    for c in range(3):
+        assert np.array_equal(g.read_blocks(c, ref["cells"]), ref["q"][c]), c
+    E.reset()
+
+
+def test_advection_full_size():
+    """The advection workload at its benchmark size (256^3 tube, 10,112 blocks):
+    one optimized step against the oracle."""
+    from paper_2012_08141_amd import engine as E, programs as PR
+    say("advection tube256 full")
+    w = I.tube(0)
+    dt = w.params["dt"]
+    E.reset()
+    g = PR.load_workload(w, {"q0": 0, "q1": 1, "q2": 2, "v0": 3, "v1": 4, "v2": 5}, 9)
+    E.run_sequence(PR.advection_step(g, dt), E.OPT_ALL)
+    ref = OP.advection_program(w.n, w.blocks, w.channels, dt, 1)
+    torch.cuda.synchronize()
+    for c in range(3):
+        assert np.array_equal(g.read_blocks(c, ref["cells"]), ref["q"][c]), c
+    E.reset()

@@ -1,0 +1,53 @@
+"""The optimizer on the three-field advection program (paper Section 8.1),
+on host-only planning handles: per step and field, listgen -> advect ->
+listgen -> copy.  List generation removal deletes the list generations, and
+fusion joins the three advections (independent tasks over the same list that
+share only the velocity they read) and the three copies: 12 launches become
+2.  An advection and the copy into the field it reads at other voxels never
+fuse (criterion 3)."""
+import pytest
+
+from paper_2012_08141_amd import _lib as L
+from paper_2012_08141_amd import engine as E
+from paper_2012_08141_amd import programs as PR
+from paper_2012_08141_amd.grid import SparseGrid
+
+
+@pytest.fixture(autouse=True)
+def fresh_engine():
+    E.reset()
+    yield
+    E.reset()
+
+
+def test_three_field_step_fuses_to_two_launches():
+    g = SparseGrid(256, 9, "bitmask", device=None)
+    E.run_sequence([E.listgen(g)], E.OPT_ALL)
+    step = PR.advection_step(g, 1.0 / 256)
+    eager, _ = E.plan_sequence(step, 0)
+    assert len(eager) == 12 and E.paper_task_count(eager) == 18
+    opt, st = E.plan_sequence(step, E.OPT_ALL)
+    assert [e["members"] for e in opt] == [[1, 5, 9], [3, 7, 11]]
+    assert st["listgens_removed"] == 6
+
+
+def test_advection_and_copy_into_its_source_do_not_fuse():
+    g = SparseGrid(64, 9, "bitmask", device=None)
+    E.run_sequence([E.listgen(g)], E.OPT_ALL)
+    opt, _ = E.plan_sequence([E.advect_sl(g, 0, 3, 6, 0.1), E.copy(g, 0, 6)], E.OPT_ALL)
+    assert len(opt) == 2
+
+
+def test_advect_validation():
+    lib = L.lib()
+    import ctypes
+    g = SparseGrid(64, 6, "bitmask", device=None)
+    st = L.AtStats()
+
+    def status(t):
+        return lib.at_run_sequence(ctypes.byref(t.c), 1, E.OPT_ALL, ctypes.byref(st), None)
+
+    assert status(E.advect_sl(g, 0, 1, 4, 0.1)) == L.AT_OK
+    assert status(E.advect_sl(g, 0, 1, 0, 0.1)) == L.AT_E_INVALID       # out aliases q
+    assert status(E.advect_sl(g, 0, 1, 2, 0.1)) == L.AT_E_INVALID       # out aliases a velocity
+    assert status(E.advect_sl(g, 0, 4, 1, 0.1)) == L.AT_E_INVALID       # velocity needs 3 channels
