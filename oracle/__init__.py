@@ -24,6 +24,8 @@ What pins each function (tests/test_oracle_pins.py):
   Jacobi eigenmodes, a direct Poisson solve, linear-field diffusion fluxes.
 * diffuse_adj -- dot-product identities in a and k, and central finite
   differences of a multi-step loss.
+* maccormack -- the dense implementation (bit-exact), zero velocity (q back),
+  exactness on affine fields (no correction), and the clamp bounds.
 * advect_sl -- the dense implementation (bit-exact), zero velocity (a copy),
   whole-voxel velocities (exact shifts with zeros entering), reproduction of
   linear fields, and one block's values carried into a neighbour block.
@@ -86,6 +88,7 @@ def _lib(prec: str):
         "og_normalise": (None, [P, i32, i32, i32]),
         "og_restrict": (None, [P, P, i32, i32, R]),
         "og_advect_sl": (None, [P, i32, i32, i32, R]),
+        "og_maccormack": (None, [P, i32, i32, i32, i32, i32, R]),
         "og_prolong": (None, [P, P, i32, i32]),
         "og_g2p": (None, [P, i32, P, P, i64, R]),
         "og_bspline": (i32, [R, P]),
@@ -226,6 +229,10 @@ class OracleGrid:
     def advect_sl(self, ch_q: int, ch_v: int, ch_out: int, dt: float):
         """out[I] = q at I - dt * v(I), trilinear (v in ch_v .. ch_v + 2)."""
         self._L.og_advect_sl(self._g, ch_q, ch_v, ch_out, self.dtype(dt))
+
+    def maccormack(self, ch_q: int, ch_v: int, ch_fwd: int, ch_bwd: int, ch_out: int, dt: float):
+        """out = clamp(fwd + 0.5 (q - bwd)) to q's corner range at I - dt v(I)."""
+        self._L.og_maccormack(self._g, ch_q, ch_v, ch_fwd, ch_bwd, ch_out, self.dtype(dt))
 
     # -- two-level transfers (struct-fors over this, the fine grid) -----------
     def restrict_to(self, coarse: "OracleGrid", ch_x: int, ch_y: int, w: float = 0.125):

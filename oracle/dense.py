@@ -132,6 +132,26 @@ class DenseGrid:
                     s = (s + wt * pad[base[0] + a, base[1] + b, base[2] + c]).astype(self.dtype)
         self._store(ch_out, s)
 
+    def maccormack(self, ch_q, ch_v, ch_fwd, ch_bwd, ch_out, dt):
+        """clamp(fwd + 0.5 (q - bwd)) to the range of q over the 8 corners of the
+        forward back-traced point, whole-array."""
+        T = self.dtype.type
+        n = self.n
+        q = self._field(ch_q)
+        pad = np.zeros((n + 6,) * 3, dtype=self.dtype)
+        pad[3:n + 3, 3:n + 3, 3:n + 3] = q
+        idx = np.indices((n, n, n)).astype(self.dtype)
+        base = []
+        for d in range(3):
+            p = idx[d] - T(dt) * self._field(ch_v + d)
+            p = np.minimum(np.maximum(p, T(-2)), T(n + 1)).astype(self.dtype)
+            base.append(np.floor(p).astype(np.int64) + 3)
+        corners = [pad[base[0] + a, base[1] + b, base[2] + c] for a in (0, 1) for b in (0, 1) for c in (0, 1)]
+        lo = np.min(np.stack(corners), axis=0)
+        hi = np.max(np.stack(corners), axis=0)
+        val = (self._field(ch_fwd) + (T(0.5) * (q - self._field(ch_bwd))).astype(self.dtype)).astype(self.dtype)
+        self._store(ch_out, np.minimum(np.maximum(val, lo), hi))
+
     # -- two-level transfers (this grid is the fine one) ----------------------------
     def restrict_to(self, coarse, ch_x, ch_y, w):
         """coarse.y[I//2] += w * x[I] over this grid's listed blocks: the coarse

@@ -251,6 +251,36 @@ void og_advect_sl(og_grid *g, int ch_q, int ch_v, int ch_out, REAL dt) {
     })
 }
 
+/* MacCormack correction with clamping (Section 8.1, after Selle et al.'s
+ * unconditionally stable MacCormack method): given the forward
+ * semi-Lagrangian result fwd = SL(q, v, dt) and the backward one
+ * bwd = SL(fwd, v, -dt), every listed voxel I gets
+ *   val = fwd[I] + 0.5 * (q[I] - bwd[I]),
+ * clamped to the range of q over the 8 corners around the forward
+ * back-traced point I - dt * v(I) (corner reads with sparse semantics; the
+ * same clamping of far points as og_advect_sl).  Order: d = q - bwd,
+ * h = 0.5 * d, val = fwd + h; min and max in corner order. */
+void og_maccormack(og_grid *g, int ch_q, int ch_v, int ch_fwd, int ch_bwd, int ch_out, REAL dt) {
+    FOR_EACH_LISTED_VOXEL(g, {
+        int base[3];
+        base[0] = (int)floor((double)clamp_coord((REAL)i - dt * rd(g, ch_v, i, j, k), g->n));
+        base[1] = (int)floor((double)clamp_coord((REAL)j - dt * rd(g, ch_v + 1, i, j, k), g->n));
+        base[2] = (int)floor((double)clamp_coord((REAL)k - dt * rd(g, ch_v + 2, i, j, k), g->n));
+        REAL lo = (REAL)0, hi = (REAL)0;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int c = 0; c < 2; ++c) {
+                    REAL x = rd(g, ch_q, base[0] + a, base[1] + b, base[2] + c);
+                    if (a + b + c == 0) { lo = x; hi = x; }
+                    else { lo = x < lo ? x : lo; hi = x > hi ? x : hi; }
+                }
+        REAL d = rd(g, ch_q, i, j, k) - rd(g, ch_bwd, i, j, k);
+        REAL h = (REAL)0.5 * d;
+        REAL val = rd(g, ch_fwd, i, j, k) + h;
+        wr(g, ch_out, i, j, k, val < lo ? lo : (val > hi ? hi : val));
+    })
+}
+
 /* ------------------------------------------ two-level transfers (Sec. 6.3)
  * A coarse grid has half the fine domain edge; fine voxel (i, j, k) lies
  * under coarse voxel (i/2, j/2, k/2).  Both transfers are struct-fors over

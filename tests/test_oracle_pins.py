@@ -597,3 +597,66 @@ def test_advect_reproduces_linear_fields():
     got = g.to_dense(4)
     assert inside.sum() > 1000
     assert np.allclose(got[inside], expect[inside], rtol=0, atol=1e-12)
+
+
+# ------------------------------------------------------ MacCormack correction
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_maccormack_matches_dense_and_stays_in_range(prec):
+    """The MacCormack correction of the oracle equals the dense implementation
+    bit for bit, and every result lies within the range of q over the corners
+    of its forward back-traced point (the clamp)."""
+    n = 32
+    w = I.random_blocks(7, n, 0.5, channels=("q", "v0", "v1", "v2", "f", "b", "o"))
+    for c in ("v0", "v1", "v2"):
+        w.channels[c] = (w.channels[c] * 4.0).astype(np.float32)
+    names = {"q": 0, "v0": 1, "v1": 2, "v2": 3, "f": 4, "b": 5, "o": 6}
+    o, d = _pair(n, 7, prec)
+    o.load(w.blocks, w.channels, names); d.load(w.blocks, w.channels, names)
+    o.listgen(); d.listgen()
+    for g in (o, d):
+        g.advect_sl(0, 1, 4, 0.8)
+        g.advect_sl(4, 1, 5, -0.8)
+        g.maccormack(0, 1, 4, 5, 6, 0.8)
+    for q in range(7):
+        assert np.array_equal(o.to_dense(q), d.to_dense(q)), q
+    # clamp bound, recomputed from the back-trace here
+    qd = o.to_dense(0).astype(np.float64)
+    pad = np.zeros((n + 6,) * 3); pad[3:n + 3, 3:n + 3, 3:n + 3] = qd
+    i = np.indices((n, n, n))
+    base = [np.floor(np.clip(i[k] - np.float32(0.8) * o.to_dense(1 + k), -2, n + 1)).astype(np.int64) + 3
+            for k in range(3)]
+    cs = np.stack([pad[base[0] + a, base[1] + b, base[2] + c] for a in (0, 1) for b in (0, 1) for c in (0, 1)])
+    act = d.listed_voxels()
+    out = o.to_dense(6).astype(np.float64)
+    assert np.all(out[act] >= cs.min(0)[act]) and np.all(out[act] <= cs.max(0)[act])
+
+
+def test_maccormack_zero_velocity_and_affine_fields():
+    """v = 0 gives q back exactly; on an affine field the forward and backward
+    semi-Lagrangian steps are exact, so the correction vanishes and the result
+    is the forward value, to fp64 rounding, wherever the back-and-forth
+    traces stay in the domain."""
+    n = 16
+    rng = np.random.default_rng(8)
+    q = rng.standard_normal((n, n, n))
+    g2 = oracle.OracleGrid(n, 7, "f64")
+    R = n // 8
+    blocks = np.array([[a, b, c] for a in range(R) for b in range(R) for c in range(R)], np.int32)
+    per = lambda f: np.stack([f[a * 8:a * 8 + 8, b * 8:b * 8 + 8, c * 8:c * 8 + 8].ravel() for a, b, c in blocks])
+    z = np.zeros((n, n, n))
+    g2.load(blocks, {"q": per(q), "v0": per(z), "v1": per(z), "v2": per(z)}, {"q": 0, "v0": 1, "v1": 2, "v2": 3})
+    g2.listgen()
+    g2.advect_sl(0, 1, 4, 0.7); g2.advect_sl(4, 1, 5, -0.7); g2.maccormack(0, 1, 4, 5, 6, 0.7)
+    assert np.array_equal(g2.to_dense(6), q)
+    i, j, k = np.indices((n, n, n)).astype(np.float64)
+    qa = 0.4 * i + 0.1 * j - 0.3 * k + 2.0
+    va = np.stack([0.6 + 0.0 * i, -0.45 + 0.0 * i, 0.3 + 0.0 * i])
+    g3 = oracle.OracleGrid(n, 7, "f64")
+    g3.load(blocks, {"q": per(qa), "v0": per(va[0]), "v1": per(va[1]), "v2": per(va[2])},
+            {"q": 0, "v0": 1, "v1": 2, "v2": 3})
+    g3.listgen()
+    g3.advect_sl(0, 1, 4, 1.0); g3.advect_sl(4, 1, 5, -1.0); g3.maccormack(0, 1, 4, 5, 6, 1.0)
+    inner = np.zeros((n, n, n), bool)
+    inner[2:n - 2, 2:n - 2, 2:n - 2] = True
+    assert np.allclose(g3.to_dense(6)[inner], g3.to_dense(4)[inner], rtol=0, atol=1e-12)
+    assert np.allclose(g3.to_dense(5)[inner], qa[inner], rtol=0, atol=1e-12)
