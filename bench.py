@@ -370,18 +370,19 @@ def bench_diffusion(args, torch):
 
 
 # ------------------------------------------------------------------- advection
-def bench_advection(args, torch):
+def bench_advection(args, torch, mac=False):
     from paper_2012_08141_amd import engine as E
     from paper_2012_08141_amd import inputs, programs as PR
     w = inputs.tube(args.seed)
     dt = w.params["dt"]
     K, W = args.steps, args.warmup
     names = {"q0": 0, "q1": 1, "q2": 2, "v0": 3, "v1": 4, "v2": 5}
+    step_fn, nch = (PR.maccormack_step, 15) if mac else (PR.advection_step, 9)
     res = {}
     for name, opt in (("optimized", E.OPT_ALL), ("eager", 0)):
         E.reset()
-        g = PR.load_workload(w, names, 9)
-        step = E.prepare(PR.advection_step(g, dt))     # one engine window per step
+        g = PR.load_workload(w, names, nch)
+        step = E.prepare(step_fn(g, dt))               # one engine window per step
         for _ in range(max(W, 2)):
             E.run_sequence(step, opt)
         torch.cuda.synchronize()
@@ -390,14 +391,16 @@ def bench_advection(args, torch):
         for _ in range(K):
             E.run_sequence(step, opt)
         torch.cuda.synchronize()
-        res[name] = (time.perf_counter() - t0, E.dispatch_count() - d0, E.plan_sequence(PR.advection_step(g, dt), opt)[0])
+        res[name] = (time.perf_counter() - t0, E.dispatch_count() - d0, E.plan_sequence(step_fn(g, dt), opt)[0])
         del step, g
     t, d, plan = res["optimized"]
     te, de, plane = res["eager"]
     out = _base(K, W, w.active_voxels * K / t, t / K * 1e3,
-                {"workload": "advection256: semi-Lagrangian advection of 3 scalar fields by a swirling velocity on a "
-                             "256^3 tube (r 0.32-0.45, %d blocks); per step and field listgen, advect, listgen, "
-                             "copy, one engine window per step" % w.nblocks, "seed": args.seed})
+                {"workload": ("maccormack256: MacCormack advection (forward and backward semi-Lagrangian steps, "
+                              "clamped correction, copy back; each after a listgen)" if mac else
+                              "advection256: semi-Lagrangian advection (listgen, advect, listgen, copy)") +
+                             " of 3 scalar fields by a swirling velocity on a 256^3 tube (r 0.32-0.45, %d blocks), "
+                             "one engine window per step" % w.nblocks, "seed": args.seed})
     out.update({"launches_per_step": {"optimized": d / K, "eager": de / K},
                 "paper_task_count_per_step": {"optimized": E.paper_task_count(plan),
                                               "eager": E.paper_task_count(plane)},
@@ -473,7 +476,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--workload", default="band512", choices=["band512", "shell", "particles", "serving", "diffusion",
-                                                           "multigrid", "advection"])
+                                                           "multigrid", "advection", "maccormack"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=90)
     ap.add_argument("--requests", type=int, default=256)
@@ -492,7 +495,8 @@ def main():
     # finds its plan in the engine's plan cache (the cold planning time is
     # reported beside the result)
     defaults = {"band512": (100, 100), "shell": (100, 100), "particles": (20, 40), "serving": (256, 0),
-                "diffusion": (40, 5), "multigrid": (20, 5), "advection": (50, 5)}
+                "diffusion": (40, 5), "multigrid": (20, 5), "advection": (50, 5),
+                "maccormack": (30, 5)}
     d = defaults[args.workload]
     args.steps = d[0] if args.steps is None else args.steps
     args.warmup = d[1] if args.warmup is None else args.warmup
@@ -503,7 +507,8 @@ def main():
     settle_host()
     fn = {"band512": bench_band, "shell": bench_shell, "particles": bench_particles, "serving": bench_serving,
           "diffusion": bench_diffusion, "multigrid": bench_multigrid,
-          "advection": bench_advection}[args.workload]
+          "advection": bench_advection,
+          "maccormack": lambda a, t: bench_advection(a, t, mac=True)}[args.workload]
     out = fn(args, torch)
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib << 18

@@ -167,6 +167,12 @@ at_status at_listgen(at_grid grid, hipStream_t stream);
                                 (a,b,c) lexicographic, weight (wx*wy)*wz, s = s + w*q;
                                 reads outside the domain or in inactive blocks give 0; a
                                 point more than 2 voxels outside is moved to 2 outside    */
+#define AT_OP_MACCORMACK 11  /* ch {q, v0, fwd, bwd, out}; p {dt}: MacCormack correction
+                                (Section 8.1): val = fwd + 0.5*(q - bwd) (d = q - bwd,
+                                h = 0.5*d, val = fwd + h), clamped to the range of q over
+                                the 8 corners around I - dt*v(I) (sparse reads; far points
+                                moved as for AT_OP_ADVECT), fwd = ADVECT(q, dt) and
+                                bwd = ADVECT(fwd, -dt)                                     */
 
 /* ch: host array of channel indices (meaning per op above); params: host
  * array of up to 4 floats.  check_activation != 0 keeps the per-write

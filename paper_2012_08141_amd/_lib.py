@@ -22,6 +22,7 @@ AT_COORD_VOXEL, AT_COORD_BLOCK = 0, 1
 AT_OP_LAP_UPDATE, AT_OP_AXPY, AT_OP_JACOBI, AT_OP_COPY, AT_OP_FILL, AT_OP_INC = 1, 2, 3, 4, 5, 6
 AT_OP_DIFFUSE, AT_OP_DIFFUSE_ADJ, AT_OP_NORMALISE = 7, 8, 9
 AT_OP_ADVECT = 10
+AT_OP_MACCORMACK = 11
 AT_ACT_PER_NODE, AT_ACT_PER_BLOCK, AT_ACT_NONE = 0, 1, 2
 AT_TASK_ACTIVATE, AT_TASK_LISTGEN, AT_TASK_STENCIL, AT_TASK_ADVECT, AT_TASK_P2G, AT_TASK_G2P = 1, 2, 3, 4, 5, 6
 AT_TASK_RESTRICT, AT_TASK_PROLONG = 7, 8

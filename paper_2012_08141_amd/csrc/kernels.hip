@@ -1093,6 +1093,42 @@ __global__ __launch_bounds__(64) void k_micro(GridDev g, MicroProg prog) {
                     *reinterpret_cast<float4 *>(chan(g, op.ch[2]) + off) = make_float4(r[0], r[1], r[2], r[3]);
                     break;
                 }
+                case AT_OP_MACCORMACK: {
+                    // fwd + 0.5 (q - bwd), clamped to q's corner range at I - dt v(I)
+                    const float *Q = chan(g, op.ch[0]);
+                    const int n = g.R * 8;
+                    int bi, bj, bk;
+                    cell_coords(g, cell, bi, bj, bk);
+                    float r[4];
+                    for (int q = 0; q < 4; ++q) {
+                        const int I[3] = {bi * 8 + li, bj * 8 + lj, bk * 8 + k0 + q};
+                        int b0[3];
+                        for (int d = 0; d < 3; ++d) {
+                            const float vd = chan(g, op.ch[1] + d)[off + q];
+                            b0[d] = (int)floorf(clamp_coord((float)I[d] - op.p * vd, n));
+                        }
+                        float lo = 0.f, hi = 0.f;
+                        for (int a = 0; a < 2; ++a)
+                            for (int b = 0; b < 2; ++b)
+                                for (int c = 0; c < 2; ++c) {
+                                    const float x = sample_voxel<KIND>(g, Q, cell, slot, b0[0] + a, b0[1] + b,
+                                                                       b0[2] + c, n);
+                                    if (a + b + c == 0) {
+                                        lo = x;
+                                        hi = x;
+                                    } else {
+                                        lo = x < lo ? x : lo;
+                                        hi = x > hi ? x : hi;
+                                    }
+                                }
+                        const float dq = Q[off + q] - chan(g, op.ch[3])[off + q];
+                        const float h2 = 0.5f * dq;
+                        const float val = chan(g, op.ch[2])[off + q] + h2;
+                        r[q] = val < lo ? lo : (val > hi ? hi : val);
+                    }
+                    *reinterpret_cast<float4 *>(chan(g, op.ch[4]) + off) = make_float4(r[0], r[1], r[2], r[3]);
+                    break;
+                }
                 case AT_OP_LAP_UPDATE:
                 case AT_OP_JACOBI:
                 case AT_OP_DIFFUSE:

@@ -774,8 +774,8 @@ at_status at_run_stencil(at_grid grid, int32_t op, const int32_t *ch, const floa
         }
     } else {
         const int nc = op == AT_OP_LAP_UPDATE || op == AT_OP_AXPY || op == AT_OP_COPY ? 2
-                     : op == AT_OP_INC ? 1 : op == AT_OP_DIFFUSE_ADJ ? 5 : 3;
-        if (op < AT_OP_LAP_UPDATE || op > AT_OP_ADVECT) return fail(AT_E_INVALID, "unknown op %d", op);
+                     : op == AT_OP_INC ? 1 : op == AT_OP_DIFFUSE_ADJ || op == AT_OP_MACCORMACK ? 5 : 3;
+        if (op < AT_OP_LAP_UPDATE || op > AT_OP_MACCORMACK) return fail(AT_E_INVALID, "unknown op %d", op);
         for (int q = 0; q < nc; ++q) t.ch[q] = ch[q];
     }
     if (params) t.param[0] = params[0];

@@ -41,6 +41,7 @@ int op_nch(int op) {
     case AT_OP_DIFFUSE_ADJ: return 5;
     case AT_OP_NORMALISE: return 3;
     case AT_OP_ADVECT: return 3;
+    case AT_OP_MACCORMACK: return 5;
     default: return -1;
     }
 }
@@ -94,6 +95,14 @@ void member_accesses(const at_task &t, const Member &mb, bool check, int16_t mi,
             rd(c[0], true);
             for (int q = 0; q < 3; ++q) rd(c[1] + q, false);
             wr(c[2], true, false);
+            break;
+        case AT_OP_MACCORMACK:
+            // q at the corners of the back-traced point and at the voxel
+            rd(c[0], true);
+            for (int q = 0; q < 3; ++q) rd(c[1] + q, false);
+            rd(c[2], false);
+            rd(c[3], false);
+            wr(c[4], true, false);
             break;
         case AT_OP_NORMALISE:
             rd(c[0], false);
@@ -357,6 +366,13 @@ std::string validate_task(const at_task &t) {
             if (!chan_ok(t.ch[0], 1) || !chan_ok(t.ch[1], 3) || !chan_ok(t.ch[2], 1)) return "advect: channel out of range";
             if (t.ch[2] == t.ch[0] || (t.ch[2] >= t.ch[1] && t.ch[2] < t.ch[1] + 3))
                 return "advect: the output aliases an input";
+        } else if (t.op == AT_OP_MACCORMACK) {
+            if (!chan_ok(t.ch[0], 1) || !chan_ok(t.ch[1], 3) || !chan_ok(t.ch[2], 1) || !chan_ok(t.ch[3], 1) ||
+                !chan_ok(t.ch[4], 1))
+                return "maccormack: channel out of range";
+            const int o = t.ch[4];
+            if (o == t.ch[0] || o == t.ch[2] || o == t.ch[3] || (o >= t.ch[1] && o < t.ch[1] + 3))
+                return "maccormack: the output aliases an input";
         } else if (t.op == AT_OP_NORMALISE) {
             if (!chan_ok(t.ch[0], 1) || !chan_ok(t.ch[1], 3) || !chan_ok(t.ch[2], 3)) return "normalise: channel out of range";
         } else {

@@ -21,7 +21,8 @@ KIND_NAMES = {L.AT_TASK_ACTIVATE: "activate", L.AT_TASK_LISTGEN: "listgen", L.AT
               L.AT_TASK_RESTRICT: "restrict", L.AT_TASK_PROLONG: "prolong"}
 OP_NAMES = {L.AT_OP_LAP_UPDATE: "lap_update", L.AT_OP_AXPY: "axpy", L.AT_OP_JACOBI: "jacobi",
             L.AT_OP_COPY: "copy", L.AT_OP_FILL: "fill", L.AT_OP_INC: "inc", L.AT_OP_DIFFUSE: "diffuse",
-            L.AT_OP_DIFFUSE_ADJ: "diffuse_adj", L.AT_OP_NORMALISE: "normalise", L.AT_OP_ADVECT: "advect_sl"}
+            L.AT_OP_DIFFUSE_ADJ: "diffuse_adj", L.AT_OP_NORMALISE: "normalise", L.AT_OP_ADVECT: "advect_sl",
+            L.AT_OP_MACCORMACK: "maccormack"}
 
 
 @dataclass
@@ -113,6 +114,12 @@ def advect_sl(grid, q, v0, out, dt):
     """Semi-Lagrangian advection: out = q at I - dt * v(I), trilinear
     (v on channels v0 .. v0 + 2)."""
     return struct_for(grid, L.AT_OP_ADVECT, [q, v0, out], dt)
+
+
+def maccormack(grid, q, v0, fwd, bwd, out, dt):
+    """MacCormack correction: out = fwd + 0.5 (q - bwd), clamped to the range
+    of q around the forward back-traced point."""
+    return struct_for(grid, L.AT_OP_MACCORMACK, [q, v0, fwd, bwd, out], dt)
 
 
 # ---- two-level transfers (struct-fors over the fine grid) ----------------------

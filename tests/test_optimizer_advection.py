@@ -51,3 +51,17 @@ def test_advect_validation():
     assert status(E.advect_sl(g, 0, 1, 0, 0.1)) == L.AT_E_INVALID       # out aliases q
     assert status(E.advect_sl(g, 0, 1, 2, 0.1)) == L.AT_E_INVALID       # out aliases a velocity
     assert status(E.advect_sl(g, 0, 4, 1, 0.1)) == L.AT_E_INVALID       # velocity needs 3 channels
+
+
+def test_maccormack_step_plan():
+    """The three-field MacCormack step (per field: forward and backward
+    advection, correction, copy back, each after a list generation) plans to 5
+    launches instead of 24 (paper-style 36)."""
+    g = SparseGrid(256, 15, "bitmask", device=None)
+    E.run_sequence([E.listgen(g)], E.OPT_ALL)
+    step = PR.maccormack_step(g, 1.0 / 256)
+    eager, _ = E.plan_sequence(step, 0)
+    assert len(eager) == 24 and E.paper_task_count(eager) == 36
+    opt, _ = E.plan_sequence(step, E.OPT_ALL)
+    assert len(opt) == 5
+    assert sorted(m for e in opt for m in e["members"]) == [i for i in range(24) if i % 2 == 1]
