@@ -37,8 +37,8 @@ HBM_PEAK_GBS = 8000.0
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE), each scaled by the reading
 # for a plain 256 MiB copy in the same run.  Valid only for the kernel
 # source the counters were taken on; any change to it reports null.
-JACOBI_TRAFFIC = {"kernels_sha256": "69c5dc5ff763f8079f4af3568735f4830a8bf49eb66481c7741622cf681c2dd3",
-                  "bytes_per_launch": 83359707, "profile": "profiles/band512_jacobi_traffic.md"}
+JACOBI_TRAFFIC = {"kernels_sha256": "48d96d81e736e6dff7c3afb77291b71c07020d75bbe780e376d30554a8110697",
+                  "bytes_per_launch": 83354792, "profile": "profiles/band512_jacobi_traffic.md"}
 
 
 def _jacobi_traffic():
