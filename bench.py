@@ -401,7 +401,20 @@ def bench_advection(args, torch, mac=False):
                               "advection256: semi-Lagrangian advection (listgen, advect, listgen, copy)") +
                              " of 3 scalar fields by a swirling velocity on a 256^3 tube (r 0.32-0.45, %d blocks), "
                              "one engine window per step" % w.nblocks, "seed": args.seed})
+    # per-pass ablations of the step's plan (launches per step, as in the
+    # paper's ablation tables), planned from the steady state
+    abl = {}
+    E.reset()
+    ga = PR.load_workload(w, names, nch)
+    sa = step_fn(ga, dt)
+    E.run_sequence(sa, E.OPT_ALL)
+    for key, fl in (("no_lgr", E.OPT_ALL & ~E.OPT_LGR), ("no_ad", E.OPT_ALL & ~E.OPT_AD),
+                    ("no_fusion", E.OPT_ALL & ~E.OPT_FUSE), ("no_dse", E.OPT_ALL & ~E.OPT_DSE)):
+        pl = E.plan_sequence(sa, fl)[0]
+        abl[key] = {"launches_per_step": len(pl), "paper_task_count": E.paper_task_count(pl)}
+    del sa, ga
     out.update({"launches_per_step": {"optimized": d / K, "eager": de / K},
+                "ablations": abl,
                 "paper_task_count_per_step": {"optimized": E.paper_task_count(plan),
                                               "eager": E.paper_task_count(plane)},
                 "eager": {"value": w.active_voxels * K / te, "ms_per_step": te / K * 1e3},

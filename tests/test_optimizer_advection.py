@@ -65,3 +65,18 @@ def test_maccormack_step_plan():
     opt, _ = E.plan_sequence(step, E.OPT_ALL)
     assert len(opt) == 5
     assert sorted(m for e in opt for m in e["members"]) == [i for i in range(24) if i % 2 == 1]
+
+
+def test_maccormack_ablations_follow_the_paper():
+    """The paper's MacCormack ablation: fusion gives most of the cut, and
+    disabling list generation removal transitively disables fusion (the
+    kept list generations sit between the tasks); activation demotion is needed
+    for list generation removal (the struct-fors' checks write the mask)."""
+    g = SparseGrid(256, 15, "bitmask", device=None)
+    E.run_sequence([E.listgen(g)], E.OPT_ALL)
+    step = PR.maccormack_step(g, 1.0 / 256)
+    E.run_sequence(step, E.OPT_ALL)
+    count = {k: len(E.plan_sequence(step, fl)[0]) for k, fl in (
+        ("all", E.OPT_ALL), ("no_lgr", E.OPT_ALL & ~E.OPT_LGR), ("no_ad", E.OPT_ALL & ~E.OPT_AD),
+        ("no_fusion", E.OPT_ALL & ~E.OPT_FUSE), ("no_dse", E.OPT_ALL & ~E.OPT_DSE), ("eager", 0))}
+    assert count == {"all": 5, "no_lgr": 24, "no_ad": 23, "no_fusion": 12, "no_dse": 5, "eager": 24}
