@@ -87,8 +87,8 @@ def _lib(prec: str):
         "og_p2g": (i64, [P, i32, i32, i32, P, P, P, i64, R]),
         "og_normalise": (None, [P, i32, i32, i32]),
         "og_restrict": (None, [P, P, i32, i32, R]),
-        "og_advect_sl": (None, [P, i32, i32, i32, R]),
-        "og_maccormack": (None, [P, i32, i32, i32, i32, i32, R]),
+        "og_advect_sl": (None, [P, i32, i32, i32, R, i32]),
+        "og_maccormack": (None, [P, i32, i32, i32, i32, i32, R, i32]),
         "og_prolong": (None, [P, P, i32, i32]),
         "og_g2p": (None, [P, i32, P, P, i64, R]),
         "og_bspline": (i32, [R, P]),
@@ -226,13 +226,16 @@ class OracleGrid:
     def diffuse_adj(self, ch_a: int, ch_k: int, ch_lamn: int, ch_lam: int, ch_gk: int, dt: float):
         self._L.og_diffuse_adj(self._g, ch_a, ch_k, ch_lamn, ch_lam, ch_gk, self.dtype(dt))
 
-    def advect_sl(self, ch_q: int, ch_v: int, ch_out: int, dt: float):
-        """out[I] = q at I - dt * v(I), trilinear (v in ch_v .. ch_v + 2)."""
-        self._L.og_advect_sl(self._g, ch_q, ch_v, ch_out, self.dtype(dt))
+    def advect_sl(self, ch_q: int, ch_v: int, ch_out: int, dt: float, rk3: bool = False):
+        """out[I] = q at the back-traced point of I (Euler, or RK3), trilinear
+        (v in ch_v .. ch_v + 2)."""
+        self._L.og_advect_sl(self._g, ch_q, ch_v, ch_out, self.dtype(dt), 1 if rk3 else 0)
 
-    def maccormack(self, ch_q: int, ch_v: int, ch_fwd: int, ch_bwd: int, ch_out: int, dt: float):
-        """out = clamp(fwd + 0.5 (q - bwd)) to q's corner range at I - dt v(I)."""
-        self._L.og_maccormack(self._g, ch_q, ch_v, ch_fwd, ch_bwd, ch_out, self.dtype(dt))
+    def maccormack(self, ch_q: int, ch_v: int, ch_fwd: int, ch_bwd: int, ch_out: int, dt: float,
+                   rk3: bool = False):
+        """out = clamp(fwd + 0.5 (q - bwd)) to q's corner range at the forward
+        back-traced point (Euler, or RK3)."""
+        self._L.og_maccormack(self._g, ch_q, ch_v, ch_fwd, ch_bwd, ch_out, self.dtype(dt), 1 if rk3 else 0)
 
     # -- two-level transfers (struct-fors over this, the fine grid) -----------
     def restrict_to(self, coarse: "OracleGrid", ch_x: int, ch_y: int, w: float = 0.125):

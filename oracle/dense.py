@@ -107,45 +107,65 @@ class DenseGrid:
     def inc(self, ch, value):
         self._store(ch, self._field(ch) + self.dtype.type(value))
 
-    def advect_sl(self, ch_q, ch_v, ch_out, dt):
-        """out[I] = q(I - dt v(I)) trilinear, with whole-array gathers: the
-        corner indices are clipped into a zero-padded copy of q."""
+    def _sample(self, f, p):
+        """Trilinear sample of field f (n^3, zero outside) at points p (3, n, n, n),
+        fixed corner order, each step rounded to the grid's dtype."""
         T = self.dtype.type
         n = self.n
-        q = self._field(ch_q)
         pad = np.zeros((n + 6,) * 3, dtype=self.dtype)
-        pad[3:n + 3, 3:n + 3, 3:n + 3] = q
-        idx = np.indices((n, n, n)).astype(self.dtype)
+        pad[3:n + 3, 3:n + 3, 3:n + 3] = f
         base, w = [], []
         for d in range(3):
-            p = idx[d] - T(dt) * self._field(ch_v + d)
-            p = np.minimum(np.maximum(p, T(-2)), T(n + 1)).astype(self.dtype)
-            b = np.floor(p).astype(self.dtype)
-            f = (p - b).astype(self.dtype)
-            base.append(b.astype(np.int64) + 3)
-            w.append(((T(1) - f).astype(self.dtype), f))
+            pd = np.minimum(np.maximum(p[d], T(-2)), T(n + 1)).astype(self.dtype)
+            bd = np.floor(pd).astype(self.dtype)
+            fd = (pd - bd).astype(self.dtype)
+            base.append(bd.astype(np.int64) + 3)
+            w.append(((T(1) - fd).astype(self.dtype), fd))
         s = np.zeros((n, n, n), dtype=self.dtype)
         for a in (0, 1):
             for b in (0, 1):
                 for c in (0, 1):
                     wt = ((w[0][a] * w[1][b]).astype(self.dtype) * w[2][c]).astype(self.dtype)
                     s = (s + wt * pad[base[0] + a, base[1] + b, base[2] + c]).astype(self.dtype)
-        self._store(ch_out, s)
+        return s, base
 
-    def maccormack(self, ch_q, ch_v, ch_fwd, ch_bwd, ch_out, dt):
+    def _backtrace(self, ch_v, dt, rk3):
+        T = self.dtype.type
+        n = self.n
+        I = np.indices((n, n, n)).astype(self.dtype)
+        v1 = [self._field(ch_v + d) for d in range(3)]
+        if not rk3:
+            return [(I[d] - T(dt) * v1[d]).astype(self.dtype) for d in range(3)]
+        h1, h2 = T(0.5) * T(dt), T(0.75) * T(dt)
+        p1 = np.stack([(I[d] - h1 * v1[d]).astype(self.dtype) for d in range(3)])
+        v2 = [self._sample(self._field(ch_v + d), p1)[0] for d in range(3)]
+        p2 = np.stack([(I[d] - h2 * v2[d]).astype(self.dtype) for d in range(3)])
+        v3 = [self._sample(self._field(ch_v + d), p2)[0] for d in range(3)]
+        c1, c2, c3 = T(2.0 / 9.0), T(1.0 / 3.0), T(4.0 / 9.0)
+        out = []
+        for d in range(3):
+            sv = (c1 * v1[d]).astype(self.dtype)
+            sv = (sv + c2 * v2[d]).astype(self.dtype)
+            sv = (sv + c3 * v3[d]).astype(self.dtype)
+            out.append((I[d] - T(dt) * sv).astype(self.dtype))
+        return out
+
+    def advect_sl(self, ch_q, ch_v, ch_out, dt, rk3=False):
+        """out[I] = q at the back-traced point of I (Euler or RK3), trilinear,
+        with whole-array gathers into a zero-padded copy of q."""
+        p = np.stack(self._backtrace(ch_v, dt, rk3))
+        self._store(ch_out, self._sample(self._field(ch_q), p)[0])
+
+    def maccormack(self, ch_q, ch_v, ch_fwd, ch_bwd, ch_out, dt, rk3=False):
         """clamp(fwd + 0.5 (q - bwd)) to the range of q over the 8 corners of the
         forward back-traced point, whole-array."""
         T = self.dtype.type
         n = self.n
         q = self._field(ch_q)
+        p = np.stack(self._backtrace(ch_v, dt, rk3))
+        _, base = self._sample(q, p)
         pad = np.zeros((n + 6,) * 3, dtype=self.dtype)
         pad[3:n + 3, 3:n + 3, 3:n + 3] = q
-        idx = np.indices((n, n, n)).astype(self.dtype)
-        base = []
-        for d in range(3):
-            p = idx[d] - T(dt) * self._field(ch_v + d)
-            p = np.minimum(np.maximum(p, T(-2)), T(n + 1)).astype(self.dtype)
-            base.append(np.floor(p).astype(np.int64) + 3)
         corners = [pad[base[0] + a, base[1] + b, base[2] + c] for a in (0, 1) for b in (0, 1) for c in (0, 1)]
         lo = np.min(np.stack(corners), axis=0)
         hi = np.max(np.stack(corners), axis=0)

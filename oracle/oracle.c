@@ -214,8 +214,8 @@ void og_write_block(og_grid *g, int ch, int32_t cell, const REAL *vals) {
  * (Section 8.1) and of the supplement's simple advection microbenchmark:
  * every listed voxel I takes q at the back-traced point p = I - dt * v(I)
  * (grid units, one Euler step; v in channels ch_v .. ch_v + 2), trilinearly
- * interpolated from the 8 voxels around p.  Reads outside the domain or in
- * inactive blocks give 0.  Fixed order: corners (a, b, c) in {0, 1}^3
+ * interpolated from the 8 voxels around p (or the RK3 back-trace below).
+ * Reads outside the domain or in inactive blocks give 0.  Fixed order: corners (a, b, c) in {0, 1}^3
  * lexicographic, weight (wx[a] * wy[b]) * wz[c], s = s + w * q.  A point
  * further than 2 voxels outside the domain is moved to 2 voxels outside (all
  * its corners read 0 either way), which keeps the corner indices in range. */
@@ -225,29 +225,62 @@ static REAL clamp_coord(REAL p, int n) {
     return p;
 }
 
-void og_advect_sl(og_grid *g, int ch_q, int ch_v, int ch_out, REAL dt) {
+/* Trilinear sample of channel ch at point p (sparse reads, fixed corner order,
+ * weight (wx * wy) * wz, s = s + w * q).  p is clamped as described above. */
+static REAL sample_at(const og_grid *g, int ch, const REAL p_in[3]) {
+    int base[3];
+    REAL w[3][2];
+    for (int d = 0; d < 3; ++d) {
+        REAL p = clamp_coord(p_in[d], g->n);
+        REAL b = (REAL)floor((double)p);
+        REAL f = p - b;
+        base[d] = (int)b;
+        w[d][0] = (REAL)1 - f;
+        w[d][1] = f;
+    }
+    REAL s = (REAL)0;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 2; ++c) {
+                REAL wt = (w[0][a] * w[1][b]) * w[2][c];
+                s = s + wt * rd(g, ch, base[0] + a, base[1] + b, base[2] + c);
+            }
+    return s;
+}
+
+/* Back-traced point of voxel (i, j, k) over dt: one Euler step
+ * p = I - dt * v(I), or (rk3) the three-stage Runge-Kutta back-trace
+ *   v1 = v(I), p1 = I - (0.5 dt) v1, v2 = v(p1), p2 = I - (0.75 dt) v2,
+ *   v3 = v(p2), p = I - dt * (2/9 v1 + 1/3 v2 + 4/9 v3)
+ * with v sampled trilinearly; per component in that order. */
+static void backtrace(const og_grid *g, int ch_v, int i, int j, int k, REAL dt, int rk3, REAL p[3]) {
+    const REAL I[3] = {(REAL)i, (REAL)j, (REAL)k};
+    REAL v1[3];
+    for (int d = 0; d < 3; ++d) v1[d] = rd(g, ch_v + d, i, j, k);
+    if (!rk3) {
+        for (int d = 0; d < 3; ++d) p[d] = I[d] - dt * v1[d];
+        return;
+    }
+    const REAL h1 = (REAL)0.5 * dt, h2 = (REAL)0.75 * dt;
+    REAL p1[3], v2[3], p2[3], v3[3];
+    for (int d = 0; d < 3; ++d) p1[d] = I[d] - h1 * v1[d];
+    for (int d = 0; d < 3; ++d) v2[d] = sample_at(g, ch_v + d, p1);
+    for (int d = 0; d < 3; ++d) p2[d] = I[d] - h2 * v2[d];
+    for (int d = 0; d < 3; ++d) v3[d] = sample_at(g, ch_v + d, p2);
+    const REAL c1 = (REAL)(2.0 / 9.0), c2 = (REAL)(1.0 / 3.0), c3 = (REAL)(4.0 / 9.0);
+    for (int d = 0; d < 3; ++d) {
+        REAL sv = c1 * v1[d];
+        sv = sv + c2 * v2[d];
+        sv = sv + c3 * v3[d];
+        p[d] = I[d] - dt * sv;
+    }
+}
+
+void og_advect_sl(og_grid *g, int ch_q, int ch_v, int ch_out, REAL dt, int rk3) {
     FOR_EACH_LISTED_VOXEL(g, {
         REAL p[3];
-        p[0] = clamp_coord((REAL)i - dt * rd(g, ch_v, i, j, k), g->n);
-        p[1] = clamp_coord((REAL)j - dt * rd(g, ch_v + 1, i, j, k), g->n);
-        p[2] = clamp_coord((REAL)k - dt * rd(g, ch_v + 2, i, j, k), g->n);
-        int base[3];
-        REAL w[3][2];
-        for (int d = 0; d < 3; ++d) {
-            REAL b = (REAL)floor((double)p[d]);
-            REAL f = p[d] - b;
-            base[d] = (int)b;
-            w[d][0] = (REAL)1 - f;
-            w[d][1] = f;
-        }
-        REAL s = (REAL)0;
-        for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b)
-                for (int c = 0; c < 2; ++c) {
-                    REAL wt = (w[0][a] * w[1][b]) * w[2][c];
-                    s = s + wt * rd(g, ch_q, base[0] + a, base[1] + b, base[2] + c);
-                }
-        wr(g, ch_out, i, j, k, s);
+        backtrace(g, ch_v, i, j, k, dt, rk3, p);
+        wr(g, ch_out, i, j, k, sample_at(g, ch_q, p));
     })
 }
 
@@ -260,12 +293,12 @@ void og_advect_sl(og_grid *g, int ch_q, int ch_v, int ch_out, REAL dt) {
  * back-traced point I - dt * v(I) (corner reads with sparse semantics; the
  * same clamping of far points as og_advect_sl).  Order: d = q - bwd,
  * h = 0.5 * d, val = fwd + h; min and max in corner order. */
-void og_maccormack(og_grid *g, int ch_q, int ch_v, int ch_fwd, int ch_bwd, int ch_out, REAL dt) {
+void og_maccormack(og_grid *g, int ch_q, int ch_v, int ch_fwd, int ch_bwd, int ch_out, REAL dt, int rk3) {
     FOR_EACH_LISTED_VOXEL(g, {
+        REAL p[3];
+        backtrace(g, ch_v, i, j, k, dt, rk3, p);
         int base[3];
-        base[0] = (int)floor((double)clamp_coord((REAL)i - dt * rd(g, ch_v, i, j, k), g->n));
-        base[1] = (int)floor((double)clamp_coord((REAL)j - dt * rd(g, ch_v + 1, i, j, k), g->n));
-        base[2] = (int)floor((double)clamp_coord((REAL)k - dt * rd(g, ch_v + 2, i, j, k), g->n));
+        for (int d = 0; d < 3; ++d) base[d] = (int)floor((double)clamp_coord(p[d], g->n));
         REAL lo = (REAL)0, hi = (REAL)0;
         for (int a = 0; a < 2; ++a)
             for (int b = 0; b < 2; ++b)
