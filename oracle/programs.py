@@ -231,7 +231,7 @@ def advection_program(n, blocks, channels, dt, steps, precision="f32"):
 
 
 
-def maccormack_program(n, blocks, channels, dt, steps, precision="f32"):
+def maccormack_program(n, blocks, channels, dt, steps, precision="f32", rk3=False):
     """Per step and field c: listgen, advect_sl (fwd), listgen, advect_sl (bwd,
     -dt), listgen, maccormack, listgen, copy.  Channels: q 0..2, v 3..5, fwd
     6..8, bwd 9..11, out 12..14.  Returns the three fields."""
@@ -239,9 +239,9 @@ def maccormack_program(n, blocks, channels, dt, steps, precision="f32"):
     g.load(blocks, channels, {"q0": 0, "q1": 1, "q2": 2, "v0": 3, "v1": 4, "v2": 5})
     for _ in range(steps):
         for c in range(3):
-            g.listgen(); g.advect_sl(c, 3, 6 + c, dt)
-            g.listgen(); g.advect_sl(6 + c, 3, 9 + c, -dt)
-            g.listgen(); g.maccormack(c, 3, 6 + c, 9 + c, 12 + c, dt)
+            g.listgen(); g.advect_sl(c, 3, 6 + c, dt, rk3)
+            g.listgen(); g.advect_sl(6 + c, 3, 9 + c, -dt, rk3)
+            g.listgen(); g.maccormack(c, 3, 6 + c, 9 + c, 12 + c, dt, rk3)
             g.listgen(); g.copy(c, 12 + c)
     cells = g.active_cells()
     return {"cells": cells, "q": [g.read_blocks(c, cells) for c in range(3)]}

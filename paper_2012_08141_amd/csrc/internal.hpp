@@ -59,6 +59,7 @@ struct MicroOp {
     int32_t ch[7];    // channels, as in the public op table
     float p;          // parameter
     uint32_t keep;    // FILL: bit q keeps the store to ch[q]; NORMALISE: bit c keeps v_c
+    float p1;         // second parameter (ADVECT / MACCORMACK: 1 = RK3 back-trace)
 };
 struct MicroProg {
     int32_t nops;

@@ -990,6 +990,59 @@ __device__ __forceinline__ float clamp_coord(float p, int n) {
     return p < -2.f ? -2.f : (p > (float)(n + 1) ? (float)(n + 1) : p);
 }
 
+// Trilinear sample of channel `base` at point p (clamped as for the
+// advection), fixed corner order, weight (wx * wy) * wz, s = s + w * q.
+template <int KIND>
+__device__ __forceinline__ float sample_point(const GridDev &g, const float *base, int64_t own_cell, int32_t own_slot,
+                                              const float p[3], int n) {
+    float w[3][2];
+    int b0[3];
+    for (int d = 0; d < 3; ++d) {
+        const float pd = clamp_coord(p[d], n);
+        const float bd = floorf(pd);
+        const float f = pd - bd;
+        b0[d] = (int)bd;
+        w[d][0] = 1.0f - f;
+        w[d][1] = f;
+    }
+    float acc = 0.f;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 2; ++c) {
+                const float wt = (w[0][a] * w[1][b]) * w[2][c];
+                acc = acc + wt * sample_voxel<KIND>(g, base, own_cell, own_slot, b0[0] + a, b0[1] + b, b0[2] + c, n);
+            }
+    return acc;
+}
+
+// Back-traced point of voxel I over dt: one Euler step, or (rk3) the
+// three-stage Runge-Kutta back-trace with v sampled trilinearly at
+// p1 = I - (0.5 dt) v1 and p2 = I - (0.75 dt) v2, then
+// p = I - dt (2/9 v1 + 1/3 v2 + 4/9 v3); v1 is v at the voxel (offset off).
+template <int KIND>
+__device__ __forceinline__ void backtrace_point(const GridDev &g, int v0, int64_t own_cell, int32_t own_slot,
+                                                int64_t off, const int I[3], float dt, bool rk3, int n, float p[3]) {
+    float v1[3];
+    for (int d = 0; d < 3; ++d) v1[d] = chan(g, v0 + d)[off];
+    if (!rk3) {
+        for (int d = 0; d < 3; ++d) p[d] = (float)I[d] - dt * v1[d];
+        return;
+    }
+    const float h1 = 0.5f * dt, h2 = 0.75f * dt;
+    float p1[3], v2[3], p2[3], v3[3];
+    for (int d = 0; d < 3; ++d) p1[d] = (float)I[d] - h1 * v1[d];
+    for (int d = 0; d < 3; ++d) v2[d] = sample_point<KIND>(g, chan(g, v0 + d), own_cell, own_slot, p1, n);
+    for (int d = 0; d < 3; ++d) p2[d] = (float)I[d] - h2 * v2[d];
+    for (int d = 0; d < 3; ++d) v3[d] = sample_point<KIND>(g, chan(g, v0 + d), own_cell, own_slot, p2, n);
+    const float c1 = (float)(2.0 / 9.0), c2 = (float)(1.0 / 3.0), c3 = (float)(4.0 / 9.0);
+    for (int d = 0; d < 3; ++d) {
+        float sv = c1 * v1[d];
+        sv = sv + c2 * v2[d];
+        sv = sv + c3 * v3[d];
+        p[d] = (float)I[d] - dt * sv;
+    }
+}
+
 template <int KIND, bool STENCIL>
 __global__ __launch_bounds__(64) void k_micro(GridDev g, MicroProg prog) {
     // one wavefront per block; lane l owns voxels [8l, 8l+8) = row
@@ -1061,7 +1114,7 @@ __global__ __launch_bounds__(64) void k_micro(GridDev g, MicroProg prog) {
                     break;
                 }
                 case AT_OP_ADVECT: {
-                    // semi-Lagrangian: q at I - dt v(I), trilinear, fixed corner order
+                    // semi-Lagrangian: q at the back-traced point, trilinear
                     const float *Q = chan(g, op.ch[0]);
                     const int n = g.R * 8;
                     int bi, bj, bk;
@@ -1069,32 +1122,15 @@ __global__ __launch_bounds__(64) void k_micro(GridDev g, MicroProg prog) {
                     float r[4];
                     for (int q = 0; q < 4; ++q) {
                         const int I[3] = {bi * 8 + li, bj * 8 + lj, bk * 8 + k0 + q};
-                        float w[3][2];
-                        int b0[3];
-                        for (int d = 0; d < 3; ++d) {
-                            const float vd = chan(g, op.ch[1] + d)[off + q];
-                            const float pd = clamp_coord((float)I[d] - op.p * vd, n);
-                            const float bd = floorf(pd);
-                            const float f = pd - bd;
-                            b0[d] = (int)bd;
-                            w[d][0] = 1.0f - f;
-                            w[d][1] = f;
-                        }
-                        float acc = 0.f;
-                        for (int a = 0; a < 2; ++a)
-                            for (int b = 0; b < 2; ++b)
-                                for (int c = 0; c < 2; ++c) {
-                                    const float wt = (w[0][a] * w[1][b]) * w[2][c];
-                                    acc = acc + wt * sample_voxel<KIND>(g, Q, cell, slot, b0[0] + a, b0[1] + b,
-                                                                        b0[2] + c, n);
-                                }
-                        r[q] = acc;
+                        float pt[3];
+                        backtrace_point<KIND>(g, op.ch[1], cell, slot, off + q, I, op.p, op.p1 != 0.f, n, pt);
+                        r[q] = sample_point<KIND>(g, Q, cell, slot, pt, n);
                     }
                     *reinterpret_cast<float4 *>(chan(g, op.ch[2]) + off) = make_float4(r[0], r[1], r[2], r[3]);
                     break;
                 }
                 case AT_OP_MACCORMACK: {
-                    // fwd + 0.5 (q - bwd), clamped to q's corner range at I - dt v(I)
+                    // fwd + 0.5 (q - bwd), clamped to q's corner range at the back-traced point
                     const float *Q = chan(g, op.ch[0]);
                     const int n = g.R * 8;
                     int bi, bj, bk;
@@ -1102,11 +1138,10 @@ __global__ __launch_bounds__(64) void k_micro(GridDev g, MicroProg prog) {
                     float r[4];
                     for (int q = 0; q < 4; ++q) {
                         const int I[3] = {bi * 8 + li, bj * 8 + lj, bk * 8 + k0 + q};
+                        float pt[3];
+                        backtrace_point<KIND>(g, op.ch[1], cell, slot, off + q, I, op.p, op.p1 != 0.f, n, pt);
                         int b0[3];
-                        for (int d = 0; d < 3; ++d) {
-                            const float vd = chan(g, op.ch[1] + d)[off + q];
-                            b0[d] = (int)floorf(clamp_coord((float)I[d] - op.p * vd, n));
-                        }
+                        for (int d = 0; d < 3; ++d) b0[d] = (int)floorf(clamp_coord(pt[d], n));
                         float lo = 0.f, hi = 0.f;
                         for (int a = 0; a < 2; ++a)
                             for (int b = 0; b < 2; ++b)

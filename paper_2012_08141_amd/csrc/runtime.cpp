@@ -198,6 +198,7 @@ at_status execute_node(const Node &nd, const at_task *tasks, bool table, hipStre
                 for (int c = 0; c < 7; ++c) op.ch[c] = t.ch[c];
                 op.p = t.param[0];
                 op.keep = nd.members[q].keep;
+                op.p1 = t.param[1];
             }
             e = launch_stencil_tail(g->dev, t0.op, t0.ch, t0.param[0], prog, s);
         } else {
@@ -212,6 +213,7 @@ at_status execute_node(const Node &nd, const at_task *tasks, bool table, hipStre
                 for (int c = 0; c < 7; ++c) op.ch[c] = t.ch[c];
                 op.p = t.param[0];
                 op.keep = nd.members[q].keep;
+                op.p1 = t.param[1];
             }
             e = launch_micro(g->dev, prog, s);
         }

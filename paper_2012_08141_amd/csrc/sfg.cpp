@@ -91,15 +91,16 @@ void member_accesses(const at_task &t, const Member &mb, bool check, int16_t mi,
             wr(c[3], true, false); wr(c[4], false, true);
             break;
         case AT_OP_ADVECT:
-            // q at back-traced points (any offset), v at the voxel
+            // q at back-traced points (any offset); v at the voxel, and along
+            // the path with the RK3 back-trace
             rd(c[0], true);
-            for (int q = 0; q < 3; ++q) rd(c[1] + q, false);
+            for (int q = 0; q < 3; ++q) rd(c[1] + q, t.param[1] != 0.f);
             wr(c[2], true, false);
             break;
         case AT_OP_MACCORMACK:
             // q at the corners of the back-traced point and at the voxel
             rd(c[0], true);
-            for (int q = 0; q < 3; ++q) rd(c[1] + q, false);
+            for (int q = 0; q < 3; ++q) rd(c[1] + q, t.param[1] != 0.f);
             rd(c[2], false);
             rd(c[3], false);
             wr(c[4], true, false);
@@ -362,6 +363,8 @@ std::string validate_task(const at_task &t) {
                 }
             if (cnt == 0) return "fill: no channel";
             if (t.ch[7] >= 0) return "fill: at most 7 channels";
+        } else if ((t.op == AT_OP_ADVECT || t.op == AT_OP_MACCORMACK) && t.param[1] != 0.f && t.param[1] != 1.f) {
+            return "advect: param[1] (back-trace) must be 0 (Euler) or 1 (RK3)";
         } else if (t.op == AT_OP_ADVECT) {
             if (!chan_ok(t.ch[0], 1) || !chan_ok(t.ch[1], 3) || !chan_ok(t.ch[2], 1)) return "advect: channel out of range";
             if (t.ch[2] == t.ch[0] || (t.ch[2] >= t.ch[1] && t.ch[2] < t.ch[1] + 3))

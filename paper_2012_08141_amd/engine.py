@@ -110,16 +110,20 @@ def normalise(grid, m, mv0, v0):
     return struct_for(grid, L.AT_OP_NORMALISE, [m, mv0, v0])
 
 
-def advect_sl(grid, q, v0, out, dt):
-    """Semi-Lagrangian advection: out = q at I - dt * v(I), trilinear
-    (v on channels v0 .. v0 + 2)."""
-    return struct_for(grid, L.AT_OP_ADVECT, [q, v0, out], dt)
+def advect_sl(grid, q, v0, out, dt, rk3=False):
+    """Semi-Lagrangian advection: out = q at the back-traced point of I (one
+    Euler step, or the RK3 back-trace), trilinear (v on channels v0 .. v0 + 2)."""
+    T = struct_for(grid, L.AT_OP_ADVECT, [q, v0, out], dt)
+    T.c.param[1] = 1.0 if rk3 else 0.0
+    return T
 
 
-def maccormack(grid, q, v0, fwd, bwd, out, dt):
+def maccormack(grid, q, v0, fwd, bwd, out, dt, rk3=False):
     """MacCormack correction: out = fwd + 0.5 (q - bwd), clamped to the range
-    of q around the forward back-traced point."""
-    return struct_for(grid, L.AT_OP_MACCORMACK, [q, v0, fwd, bwd, out], dt)
+    of q around the forward back-traced point (Euler or RK3)."""
+    T = struct_for(grid, L.AT_OP_MACCORMACK, [q, v0, fwd, bwd, out], dt)
+    T.c.param[1] = 1.0 if rk3 else 0.0
+    return T
 
 
 # ---- two-level transfers (struct-fors over the fine grid) ----------------------

@@ -159,16 +159,16 @@ def advection_step(g: SparseGrid, dt: float):
 MAC = {"q": 0, "v": 3, "fwd": 6, "bwd": 9, "out": 12}   # 15 channels
 
 
-def maccormack_step(g: SparseGrid, dt: float):
+def maccormack_step(g: SparseGrid, dt: float, rk3: bool = False):
     """Per scalar field c (the multi-kernel structure of the paper's MacCormack
     benchmark): fwd = advect(q, dt), bwd = advect(fwd, -dt), out = MacCormack
     correction of q with clamping, q = out; each struct-for preceded by its list
-    generation."""
+    generation; rk3 selects the RK3 back-trace (the paper's setup)."""
     tasks = []
     for c in range(3):
         q, f, b, o = MAC["q"] + c, MAC["fwd"] + c, MAC["bwd"] + c, MAC["out"] + c
-        tasks += [E.listgen(g), E.advect_sl(g, q, MAC["v"], f, dt),
-                  E.listgen(g), E.advect_sl(g, f, MAC["v"], b, -dt),
-                  E.listgen(g), E.maccormack(g, q, MAC["v"], f, b, o, dt),
+        tasks += [E.listgen(g), E.advect_sl(g, q, MAC["v"], f, dt, rk3),
+                  E.listgen(g), E.advect_sl(g, f, MAC["v"], b, -dt, rk3),
+                  E.listgen(g), E.maccormack(g, q, MAC["v"], f, b, o, dt, rk3),
                   E.listgen(g), E.copy(g, q, o)]
     return tasks

@@ -35,9 +35,11 @@ def gpu():
 
 @pytest.mark.parametrize("root", ["bitmask", "pointer"])
 @pytest.mark.parametrize("check", [True, False])
-def test_advect_op(root, check):
+@pytest.mark.parametrize("rk3", [False, True])
+def test_advect_op(root, check, rk3):
+    from paper_2012_08141_amd import engine as E
     from paper_2012_08141_amd.grid import SparseGrid
-    say("advect op", root, check)
+    say("advect op", root, check, "rk3" if rk3 else "euler")
     n = 64
     w = I.random_blocks(31, n, 0.3, root, channels=("q", "v0", "v1", "v2", "o"))
     for c in ("v0", "v1", "v2"):
@@ -51,8 +53,11 @@ def test_advect_op(root, check):
     g.listgen(); o.listgen()
     extra = I.random_blocks(32, n, 0.1, root).blocks
     g.activate(extra); o.activate(extra)
-    g.run_stencil(L.AT_OP_ADVECT, [0, 1, 4], 0.6, check)
-    o.advect_sl(0, 1, 4, 0.6)
+    if rk3:
+        E.run_sequence([E.advect_sl(g, 0, 1, 4, 0.6, rk3=True)], 15 if not check else 0)
+    else:
+        g.run_stencil(L.AT_OP_ADVECT, [0, 1, 4], 0.6, check)
+    o.advect_sl(0, 1, 4, 0.6, rk3)
     torch.cuda.synchronize()
     cells = o.active_cells()
     assert np.array_equal(g.active_cells(), cells)
@@ -125,19 +130,21 @@ def test_maccormack_op(root):
 
 
 @pytest.mark.parametrize("opt", [0, 15])
-def test_maccormack_program(opt):
+@pytest.mark.parametrize("rk3", [False, True])
+def test_maccormack_program(opt, rk3):
     """Two MacCormack steps of three fields on a 64^3 tube, eager and optimized
-    (5 launches per step instead of 24), bit-exact against the oracle."""
+    (5 launches per step instead of 24), Euler and RK3 back-traces, bit-exact
+    against the oracle."""
     from paper_2012_08141_amd import engine as E, programs as PR
-    say("maccormack program opt", opt)
+    say("maccormack program opt", opt, "rk3" if rk3 else "euler")
     w = I.tube(2, n=64)
     dt = w.params["dt"]
     E.reset()
     g = PR.load_workload(w, {"q0": 0, "q1": 1, "q2": 2, "v0": 3, "v1": 4, "v2": 5}, 15)
-    step = E.prepare(PR.maccormack_step(g, dt))
+    step = E.prepare(PR.maccormack_step(g, dt, rk3))
     disp = [E.run_sequence(step, opt)["dispatches"] for _ in range(2)]
     assert disp[-1] == (24 if opt == 0 else 5)
-    ref = OP.maccormack_program(w.n, w.blocks, w.channels, dt, 2)
+    ref = OP.maccormack_program(w.n, w.blocks, w.channels, dt, 2, rk3=rk3)
     torch.cuda.synchronize()
     for c in range(3):
         assert np.array_equal(g.read_blocks(c, ref["cells"]), ref["q"][c]), c
