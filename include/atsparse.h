@@ -160,17 +160,22 @@ at_status at_listgen(at_grid grid, hipStream_t stream);
                                 lam = lamn + dt*f; gk = gk + (dt*0.5)*g                    */
 #define AT_OP_NORMALISE   9  /* ch {m, mv0, v0}: v_c = m > 0 ? mv_c / m : 0, c = 0..2 on
                                 channels mv0+c, v0+c                                       */
-#define AT_OP_ADVECT     10  /* ch {q, v0, out}; p {dt}: semi-Lagrangian advection (the
-                                building block of the MacCormack benchmark, Section 8.1):
-                                out[I] = q at p = I - dt*v(I) (grid units; v on channels
-                                v0..v0+2), trilinear over the 8 voxels around p, corners
+#define AT_OP_ADVECT     10  /* ch {q, v0, out}; p {dt, rk3}: semi-Lagrangian advection
+                                (the building block of the MacCormack benchmark, Section
+                                8.1): out[I] = q at the back-traced point p (grid units; v
+                                on channels v0..v0+2): p = I - dt*v(I) with rk3 = 0, or with
+                                rk3 = 1 the RK3 back-trace v1 = v(I), p1 = I - (0.5dt)v1,
+                                v2 = v(p1), p2 = I - (0.75dt)v2, v3 = v(p2),
+                                p = I - dt*(2/9 v1 + 1/3 v2 + 4/9 v3) (v sampled like q);
+                                q trilinear over the 8 voxels around p, corners
                                 (a,b,c) lexicographic, weight (wx*wy)*wz, s = s + w*q;
                                 reads outside the domain or in inactive blocks give 0; a
                                 point more than 2 voxels outside is moved to 2 outside    */
-#define AT_OP_MACCORMACK 11  /* ch {q, v0, fwd, bwd, out}; p {dt}: MacCormack correction
-                                (Section 8.1): val = fwd + 0.5*(q - bwd) (d = q - bwd,
-                                h = 0.5*d, val = fwd + h), clamped to the range of q over
-                                the 8 corners around I - dt*v(I) (sparse reads; far points
+#define AT_OP_MACCORMACK 11  /* ch {q, v0, fwd, bwd, out}; p {dt, rk3}: MacCormack
+                                correction (Section 8.1): val = fwd + 0.5*(q - bwd)
+                                (d = q - bwd, h = 0.5*d, val = fwd + h), clamped to the
+                                range of q over the 8 corners around the back-traced point
+                                of I (as for AT_OP_ADVECT; sparse reads; far points
                                 moved as for AT_OP_ADVECT), fwd = ADVECT(q, dt) and
                                 bwd = ADVECT(fwd, -dt)                                     */
 
