@@ -34,12 +34,23 @@ What pins each function (tests/test_oracle_pins.py):
   two transfers.
 * p2g, normalise, g2p -- B-spline moment identities, mass and momentum
   conservation, the on-node (1/8, 3/4, 1/8) stencil, affine reproduction by
-  the gather, and the dense implementation.
+  the gather, and the dense implementation; with one uniform particle
+  velocity u, normalise gives u wherever there is mass and the gather
+  returns u; normalise inverts momentum formation exactly on powers of two
+  (tests/test_oracle_laws.py).
+* advect (particles) -- exact dyadic displacements, +dt then -dt restoring x,
+  and a uniform-velocity PIC program moving every particle by T dt u.
+* inc -- exact on integer fields, +c then -c restoring them, only the listed
+  blocks of its channel touched.
+
+tests/test_oracle_laws.py also compiles copies of oracle.c with planted
+mistakes and checks that those pins fail on each.
 
 Every function has at least one such pin; none is "parity unpinned".
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 
@@ -57,7 +68,13 @@ def _lib(prec: str):
         return _LIBS[prec]
     if not _build.built():
         _build.build()
-    L = ctypes.CDLL(_build.LIBS[prec])
+    _LIBS[prec] = _load(_build.LIBS[prec], prec)
+    return _LIBS[prec]
+
+
+def _load(path: str, prec: str):
+    """Open one build of oracle.c and declare its signatures."""
+    L = ctypes.CDLL(path)
     R = _CREAL[prec]
     P = ctypes.c_void_p
     i32, i64 = ctypes.c_int, ctypes.c_int64
@@ -97,8 +114,20 @@ def _lib(prec: str):
         fn = getattr(L, name)
         fn.restype = res
         fn.argtypes = args
-    _LIBS[prec] = L
     return L
+
+
+@contextlib.contextmanager
+def substituted(path: str, prec: str):
+    """Within the block, grids and functions of precision ``prec`` use the
+    oracle build at ``path`` (a copy of oracle.c with a planted mistake,
+    compiled by a test, so the test can show that its pin catches it)."""
+    prev = _lib(prec)
+    _LIBS[prec] = _load(path, prec)
+    try:
+        yield
+    finally:
+        _LIBS[prec] = prev
 
 
 def _ptr(a: np.ndarray):

@@ -15,14 +15,33 @@ LIBS = {"f32": os.path.join(HERE, "liboracle_f32.so"),
 REALS = {"f32": "float", "f64": "double"}
 
 
+def _gcc(src: str, out: str, prec: str, verbose: bool = False) -> None:
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+           "-std=c99", "-Wall", "-DREAL=%s" % REALS[prec], src, "-o", out + ".tmp", "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(out + ".tmp", out)
+
+
 def build(verbose: bool = False) -> None:
     for prec, out in LIBS.items():
-        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-               "-std=c99", "-Wall", "-DREAL=%s" % REALS[prec], SRC, "-o", out + ".tmp", "-lm"]
-        if verbose:
-            print(" ".join(cmd))
-        subprocess.run(cmd, check=True)
-        os.replace(out + ".tmp", out)
+        _gcc(SRC, out, prec, verbose)
+
+
+def build_planted(old: str, new: str, workdir: str, prec: str) -> str:
+    """Compile a copy of oracle.c in which the one occurrence of ``old`` is
+    replaced by ``new`` (a deliberate mistake), into ``workdir``; returns the
+    library's path.  Used by tests that show a pin fails on a wrong oracle."""
+    text = open(SRC).read()
+    if text.count(old) != 1:
+        raise ValueError("planted mistake must replace exactly one occurrence of %r" % old)
+    src = os.path.join(workdir, "planted.c")
+    with open(src, "w") as f:
+        f.write(text.replace(old, new))
+    out = os.path.join(workdir, "liboracle_planted_%s.so" % prec)
+    _gcc(src, out, prec)
+    return out
 
 
 def built() -> bool:

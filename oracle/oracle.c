@@ -211,7 +211,7 @@ void og_write_block(og_grid *g, int ch, int32_t cell, const REAL *vals) {
     }
 
 /* Semi-Lagrangian advection, the building block of the MacCormack benchmark
- * (Section 8.1) and of the supplement's simple advection microbenchmark:
+ * (Section 8.2) and of the supplement's simple advection microbenchmark:
  * every listed voxel I takes q at the back-traced point p = I - dt * v(I)
  * (grid units, one Euler step; v in channels ch_v .. ch_v + 2), trilinearly
  * interpolated from the 8 voxels around p (or the RK3 back-trace below).
@@ -284,7 +284,7 @@ void og_advect_sl(og_grid *g, int ch_q, int ch_v, int ch_out, REAL dt, int rk3) 
     })
 }
 
-/* MacCormack correction with clamping (Section 8.1, after Selle et al.'s
+/* MacCormack correction with clamping (Section 8.2, after Selle et al.'s
  * unconditionally stable MacCormack method): given the forward
  * semi-Lagrangian result fwd = SL(q, v, dt) and the backward one
  * bwd = SL(fwd, v, -dt), every listed voxel I gets
