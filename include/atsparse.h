@@ -76,7 +76,10 @@ typedef struct at_grid_desc {
 at_status at_grid_footprint(const at_grid_desc *desc, size_t *bytes);
 
 /* Create a grid in the caller's device buffer `dev_buf` of `bytes` bytes
- * (>= at_grid_footprint, 256-byte aligned).  Enqueues the buffer's
+ * (Section 3.2: a root over dense leaf blocks, every block inactive and
+ * reading the ambient value 0 until activated; Section 4: the grid carries
+ * the value, mask, list and allocator states the optimizer tracks).
+ * `bytes` >= at_grid_footprint, 256-byte aligned.  Enqueues the buffer's
  * initialisation on `stream`: every block inactive, every value 0, empty
  * list.  The buffer stays owned by the caller and must outlive the handle.
  *
@@ -88,10 +91,16 @@ at_status at_grid_create(const at_grid_desc *desc, void *dev_buf, size_t bytes,
                          hipStream_t stream, at_grid *out);
 
 /* Release the host handle (the device buffer is the caller's).  Forgets the
- * engine's state-flow information for this grid. */
+ * engine's state-flow information for this grid: the states it owned leave
+ * the graph, as the engine's garbage collection drops states nothing can
+ * reach (Section 7.1).  Returns AT_E_INVALID for a NULL handle and
+ * AT_E_STATE while tasks on the grid wait in the engine queue (flush first). */
 at_status at_grid_destroy(at_grid grid);
 
-/* Device pointers into the grid's buffer.  ch_base[c] (array of `channels`
+/* Device pointers into the grid's buffer: where the value and list states
+ * of Section 4 live, for callers that read or fill them directly (a write
+ * through these pointers is invisible to the optimizer's state versions).
+ * ch_base[c] (array of `channels`
  * entries, may be NULL) receives the base of channel c (capacity_blocks*512
  * floats, indexed by slot*512 + voxel).  *list receives the list state:
  * capacity min(R^3, capacity_blocks) records of 8 int32 -- root cell, leaf
@@ -114,7 +123,9 @@ at_status at_grid_get_info(at_grid grid, at_grid_info *info);
 at_status at_grid_clear(at_grid grid, hipStream_t stream);
 
 /* Sticky device-side error bits of a grid, read synchronously on `stream`
- * (waits for the stream).  bit 0: the pointer pool overflowed
+ * (waits for the stream).  Activation allocates leaves from the grid's pool
+ * (Section 3.2, pointer nodes); the pool's fixed capacity is this library's,
+ * so running out is reported here instead of growing memory.  bit 0: the pointer pool overflowed
  * (AT_E_CAPACITY); bit 1: an allocation wait exceeded its spin limit.
  * Returns AT_OK and stores the bits; `clear` != 0 also resets them. */
 at_status at_device_status(at_grid grid, hipStream_t stream, int32_t clear, int32_t *bits);
@@ -162,7 +173,7 @@ at_status at_listgen(at_grid grid, hipStream_t stream);
                                 channels mv0+c, v0+c                                       */
 #define AT_OP_ADVECT     10  /* ch {q, v0, out}; p {dt, rk3}: semi-Lagrangian advection
                                 (the building block of the MacCormack benchmark, Section
-                                8.1): out[I] = q at the back-traced point p (grid units; v
+                                8.2): out[I] = q at the back-traced point p (grid units; v
                                 on channels v0..v0+2): p = I - dt*v(I) with rk3 = 0, or with
                                 rk3 = 1 the RK3 back-trace v1 = v(I), p1 = I - (0.5dt)v1,
                                 v2 = v(p1), p2 = I - (0.75dt)v2, v3 = v(p2),
@@ -172,7 +183,7 @@ at_status at_listgen(at_grid grid, hipStream_t stream);
                                 reads outside the domain or in inactive blocks give 0; a
                                 point more than 2 voxels outside is moved to 2 outside    */
 #define AT_OP_MACCORMACK 11  /* ch {q, v0, fwd, bwd, out}; p {dt, rk3}: MacCormack
-                                correction (Section 8.1): val = fwd + 0.5*(q - bwd)
+                                correction (Section 8.2): val = fwd + 0.5*(q - bwd)
                                 (d = q - bwd, h = 0.5*d, val = fwd + h), clamped to the
                                 range of q over the 8 corners around the back-traced point
                                 of I (as for AT_OP_ADVECT; sparse reads; far points
@@ -468,6 +479,9 @@ typedef struct at_timing_entry {
 at_status at_timing_enable(int32_t on);
 at_status at_timing_collect(at_timing_entry *out, int32_t cap, int32_t *n);
 
+/* Text of the last failing call on this thread (thread-local; valid until
+ * the next failing call on the same thread; "" if none).  Not a step of the
+ * paper's method: the error channel of a C interface that never throws. */
 const char *at_last_error(void);
 const char *at_version(void);
 

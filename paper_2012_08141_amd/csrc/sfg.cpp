@@ -378,6 +378,10 @@ std::string validate_task(const at_task &t) {
                 return "maccormack: the output aliases an input";
         } else if (t.op == AT_OP_NORMALISE) {
             if (!chan_ok(t.ch[0], 1) || !chan_ok(t.ch[1], 3) || !chan_ok(t.ch[2], 3)) return "normalise: channel out of range";
+            // v may replace mv in place (each component reads its own mv before writing);
+            // any other overlap would make one component read another's result
+            if ((t.ch[0] >= t.ch[2] && t.ch[0] < t.ch[2] + 3) || (t.ch[2] != t.ch[1] && t.ch[2] > t.ch[1] - 3 && t.ch[2] < t.ch[1] + 3))
+                return "normalise: the velocity channels overlap the mass or part of the momentum channels";
         } else {
             for (int q = 0; q < nc; ++q)
                 if (!chan_ok(t.ch[q], 1)) return "stencil: channel out of range";

@@ -111,6 +111,28 @@ def test_task_validation_enqueues_nothing():
     assert lib.at_grid_destroy(h) == L.AT_OK
 
 
+def test_normalise_rejects_overlapping_channels():
+    """v = mv / m per component: v may replace mv in place, but velocity
+    channels overlapping the mass or only part of the momentum would make a
+    component read another component's result (the single-op kernel loads all
+    inputs first, the fused one per component), so they are rejected."""
+    lib = L.lib()
+    d = _desc(32, L.AT_ROOT_BITMASK, 8)
+    h = ctypes.c_void_p()
+    assert lib.at_grid_create(ctypes.byref(d), None, 0, None, ctypes.byref(h)) == L.AT_OK
+    st = L.AtStats()
+    t = L.AtTask()
+    t.kind, t.op, t.grid = L.AT_TASK_STENCIL, L.AT_OP_NORMALISE, h.value
+    for q in range(8):
+        t.ch[q] = -1
+    for (m, mv, v), ok in (((0, 1, 4), True), ((0, 1, 1), True), ((0, 1, 2), False), ((0, 1, 3), False),
+                           ((0, 2, 1), False), ((3, 0, 2), False), ((4, 1, 5), True)):
+        t.ch[0], t.ch[1], t.ch[2] = m, mv, v
+        r = lib.at_run_sequence(ctypes.byref(t), 1, 0, ctypes.byref(st), None)
+        assert (r == L.AT_OK) == ok, (m, mv, v, r)
+    assert lib.at_grid_destroy(h) == L.AT_OK
+
+
 def test_options_roundtrip():
     lib = L.lib()
     v = ctypes.c_int64()

@@ -1,7 +1,7 @@
 """Semi-Lagrangian advection on the device against the oracle.
 
 The advection op (the building block of the paper's MacCormack benchmark,
-Section 8.1) samples q trilinearly at the back-traced point of every voxel,
+Section 8.2) samples q trilinearly at the back-traced point of every voxel,
 in a fixed corner order, so it matches the oracle bit for bit: alone, with
 and without the activation check, on both root kinds, with back-traced
 points in other, inactive or absent blocks; and as the three-field program,

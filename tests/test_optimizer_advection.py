@@ -1,4 +1,4 @@
-"""The optimizer on the three-field advection program (paper Section 8.1),
+"""The optimizer on the three-field advection program (paper Section 8.2),
 on host-only planning handles: per step and field, listgen -> advect ->
 listgen -> copy.  List generation removal deletes the list generations, and
 fusion joins the three advections (independent tasks over the same list that

@@ -71,7 +71,7 @@ def test_activation_whole_dense_block():
 
 
 def test_downsample_activation_pattern():
-    """Section 6.2 restriction pattern y[i//2] += x[i]: writing at half
+    """Section 6.3 restriction pattern y[i//2] += x[i]: writing at half
     coordinates activates exactly the blocks containing them."""
     n = 32
     x = I.random_blocks(4, n, 0.4)
