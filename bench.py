@@ -83,6 +83,75 @@ def _host_cpu():
         return "unknown"
 
 
+def roofline(achieved_gbs, kernel, alg_bytes, traffic=None, bound="hbm"):
+    """The roofline object of a bench line: algorithmic GB/s of the dominant
+    launch against MI355X's 8 TB/s HBM peak."""
+    return {"bound": bound, "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
+            "algorithmic_bytes_per_launch": alg_bytes,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)"}
+
+
+def cpu_leg(step, min_s, max_calls):
+    """Run one oracle step repeatedly, pinned to a single core of this host,
+    until ``min_s`` seconds have passed (at most ``max_calls`` calls).
+    Returns (calls, seconds, core)."""
+    prev = os.sched_getaffinity(0)
+    core = min(prev)
+    os.sched_setaffinity(0, {core})
+    try:
+        calls, t0 = 0, time.perf_counter()
+        while calls < max_calls:
+            step(calls)
+            calls += 1
+            if time.perf_counter() - t0 >= min_s:
+                break
+        return calls, time.perf_counter() - t0, core
+    finally:
+        os.sched_setaffinity(0, prev)
+
+
+def cpu_baseline(value, unit, sample, seconds, core):
+    return {"value": value, "unit": unit, "cores": 1, "kind": "oracle",
+            "sample": "%s; single-threaded C oracle (-O2, no contraction) pinned to core %d, %.1f s"
+                      % (sample, core, seconds),
+            "host_cpu": _host_cpu(), "host_nproc": os.cpu_count()}
+
+
+def window_kernel_means(E, tasks, opt, reps):
+    """Per launched kind of a window (task kind, op, fused members): mean
+    duration in us between HIP events recorded around each launch on its
+    stream, over ``reps`` runs of the window (its plan already cached)."""
+    E.timing_enable(True)
+    try:
+        for _ in range(reps):
+            E.run_sequence(tasks, opt)
+        res = E.timing_collect()
+    finally:
+        E.timing_enable(False)
+    return res
+
+
+def time_group(torch, E, group_fn, reps, opt, windows=3):
+    """Like time_kernel, for a group of tasks that the optimizer turns into
+    one launch: a window of ``reps`` groups planned with ``opt``.  Returns
+    (seconds per group, launches per group)."""
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tasks = E.prepare(sum((group_fn() for _ in range(reps)), []))
+    E.run_sequence(tasks, opt)
+    st = E.run_sequence(tasks, opt)
+    torch.cuda.synchronize()
+    per = []
+    for _ in range(windows):
+        ev0.record(stream)
+        E.run_sequence(tasks, opt)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        per.append(ev0.elapsed_time(ev1) / reps * 1e-3)
+    return sorted(per)[len(per) // 2], st["dispatches"] / reps
+
+
 def time_kernel(torch, E, task_fn, reps, windows=3):
     """Average duration of back-to-back launches of one task, from HIP events
     on the stream the launches go to: the median over `windows` windows of
@@ -119,14 +188,16 @@ def bench_band(args, torch):
         # windows packed once, as an application re-running a window does
         warm = E.prepare(sum((PR.jacobi_step(g) for _ in range(W)), []))
         timed = E.prepare(sum((PR.jacobi_step(g) for _ in range(K)), []))
-        cold = E.run_sequence(warm, opt) if W else None
         if W:
-            E.run_sequence(warm, opt)                     # plan cached (and, with graph replay on, captured)
+            E.run_sequence(warm, opt)
+        # whatever --warmup says, one untimed window of the timed shape: its
+        # plan is then in the engine's plan cache when the timed window runs
+        cold = E.run_sequence(timed, opt)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         st = E.run_sequence(timed, opt)
         torch.cuda.synchronize()
-        st["cold_optimizer_us"] = cold["optimizer_us"] if cold else None
+        st["cold_optimizer_us"] = cold["optimizer_us"]
         return g, st, time.perf_counter() - t0
 
     g_opt, st_opt, t_opt = run_pipeline(E.OPT_ALL)
@@ -170,8 +241,9 @@ def bench_band(args, torch):
         "optimized_equals_eager": same,
         "ablations": ablations,
         "optimizer_us_per_window": st_opt["optimizer_us"],
-        "optimizer_us_cold_window": st_opt["cold_optimizer_us"],
+        "optimizer_us_first_window_of_timed_shape": st_opt["cold_optimizer_us"],
         "plan_cache_hits": st_opt["plan_cache_hits"],
+        "timed_window_plan_cached": st_opt["plan_cache_hits"] > 0,
         "kernels": {"back_to_back": {"jacobi_us": t_jac * 1e6, "copy_us": t_copy * 1e6, "listgen_us": t_list * 1e6,
                                      "jacobi_GBs": achieved, "copy_GBs": 8.0 * voxels / t_copy / 1e9},
                     "timed_window_bracketed": {"jacobi_us": t_jac_window * 1e6, "copy_us": t_copy_window * 1e6,
@@ -190,18 +262,15 @@ def bench_band(args, torch):
         from oracle import OracleGrid
         og = OracleGrid(w.n, 3, "f32")
         og.load(w.blocks, {"b": w.channels["b"]}, {"x": 0, "xn": 1, "b": 2})
-        t0 = time.perf_counter()
-        for _ in range(args.cpu_iters):
+
+        def it(_):
             og.listgen()
             og.jacobi(0, 2, 1)
             og.copy(0, 1)
-        dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": voxels * args.cpu_iters / dt, "unit": "voxel-steps/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": "%d iterations (listgen, jacobi, copy) of the full band512 workload, "
-                                         "seed %d, single-threaded C oracle (-O2, no contraction), %.1f s"
-                                         % (args.cpu_iters, args.seed, dt),
-                               "host_cpu": _host_cpu(), "host_nproc": os.cpu_count()}
+        calls, dt, core = cpu_leg(it, 1e9, args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(voxels * calls / dt, "voxel-steps/s",
+                                           "%d iterations (listgen, jacobi, copy) of the full band512 workload, "
+                                           "seed %d" % (calls, args.seed), dt, core)
     return out
 
 
@@ -230,7 +299,27 @@ def bench_shell(args, torch):
                              "listgen, axpy" % w.nblocks, "seed": args.seed})
     out.update({"launches_per_step": {"optimized": st["dispatches"] / K, "eager": res["eager"][1]["dispatches"] / K},
                 "eager": {"value": w.active_voxels * K / res["eager"][0], "ms_per_step": res["eager"][0] / K * 1e3},
-                "speedup_vs_eager": res["eager"][0] / t})
+                "speedup_vs_eager": res["eager"][0] / t, "plan_cache_hits": st["plan_cache_hits"]})
+    # the optimized step launches lap_update (a read, out written: 8 B per
+    # voxel) and axpy (a, out read, a written: 12 B); the longer is the
+    # dominant launch.  The working set (a few hundred KiB) stays in L2, so
+    # the HBM fraction is context only: this workload is bound by launches.
+    g = PR.load_workload(w, PR.SHELL, 2)
+    E.run_sequence(PR.shell_setup(g, coords), E.OPT_ALL)
+    t_lap = time_kernel(torch, E, lambda: E.lap_update(g, PR.SHELL["a"], PR.SHELL["out"], 0.1), 100)
+    t_axpy = time_kernel(torch, E, lambda: E.axpy(g, PR.SHELL["a"], PR.SHELL["out"], 0.5), 100)
+    name, tk, per = max((("k_stencil_pipe<LAP_UPDATE>", t_lap, 8), ("k_elem<AXPY>", t_axpy, 12)), key=lambda e: e[1])
+    out["kernels"] = {"lap_update_us": t_lap * 1e6, "axpy_us": t_axpy * 1e6}
+    out["roofline"] = roofline(per * w.active_voxels / tk / 1e9,
+                               "%s (%d B per active voxel), mean of 100 back-to-back launches between two HIP events "
+                               "on the launch stream, median of 3 windows; L2-resident working set" % (name, per),
+                               per * w.active_voxels)
+    if not args.no_cpu_baseline and not args.profile:
+        from oracle import programs as OP
+        calls, dt, core = cpu_leg(lambda _: OP.shell_program(w.n, w.blocks, w.channels["a"], 100), 5.0, 100)
+        out["cpu_baseline"] = cpu_baseline(w.active_voxels * 100 * calls / dt, "voxel-steps/s",
+                                           "%d runs of the 100-step shell64 program (setup included), seed %d"
+                                           % (calls, args.seed), dt, core)
     return out
 
 
@@ -258,8 +347,8 @@ def bench_particles(args, torch):
         t0 = time.perf_counter()
         st = E.run_sequence(tasks, opt)
         torch.cuda.synchronize()
-        res[name] = (time.perf_counter() - t0, st, grids)
-    t, st, grids = res["optimized"]
+        res[name] = (time.perf_counter() - t0, st, grids, (x, v, m))
+    t, st, grids, _ = res["optimized"]
     vox = sum(len(g.active_cells()) for g in grids) * 512 // 2
     out = _base(K, W, vox * K / t, t / K * 1e3,
                 {"workload": "particles256: 2M particles in 3 boxes, 256^3 grid, PIC P2G/normalise/G2P, two "
@@ -280,6 +369,41 @@ def bench_particles(args, torch):
                                      "launches_per_step": res[name][1]["dispatches"] / K,
                                      "ms_per_step": res[name][0] / K * 1e3}
                               for name, _ in runs[2:]}})
+    # dominant launch: the fused gather-advect-scatter node (G2P from the
+    # previous grid, x += dt v, P2G into this one; three or five dispatches
+    # depending on bin reuse), timed between HIP events around each launch
+    # over two more windows of the timed shape (plan cached)
+    x, v, m = res["optimized"][3]
+    tasks = E.prepare(sum((PR.particle_step(grids, t_, x, v, m, p.params["dt"], 1.0 / p.n)
+                           for t_ in range(W + K, W + 2 * K)), []))
+    E.run_sequence(tasks, E.OPT_ALL)
+    ents = window_kernel_means(E, tasks, E.OPT_ALL, 2)
+    dom = max(ents, key=lambda e: e["launches"] * e["mean_us"])
+    out["kernels"] = {"%s/%d" % (e["name"], e["members"]): {"launches": e["launches"], "mean_us": e["mean_us"]}
+                      for e in ents}
+    # 48 B per particle (x and v read and written) + the gathered grid
+    # velocity (12 B per active voxel) + the scattered mass and momentum
+    # (16 B per active voxel)
+    alg = 48 * p.nparticles + 28 * vox
+    if dom["kind"] == L.AT_TASK_G2P and dom["members"] == 3:
+        out["roofline"] = roofline(alg / (dom["mean_us"] * 1e-6) / 1e9,
+                                   "fused G2P2G node (gather, advect, binned scatter): 48 B per particle + 28 B per "
+                                   "active voxel; mean over %d launches, each between its own HIP events (adds "
+                                   "about 2 us); HBM fraction is context: the node is bound by the tile sums and "
+                                   "atomics" % dom["launches"], alg)
+    if not args.no_cpu_baseline and not args.profile:
+        from oracle import programs as OP
+        steps = 2
+        rr = {}
+
+        def run(_):
+            rr["r"] = OP.particle_program(p.n, p.x, p.v, p.m, steps, p.params["dt"], "f32")
+        calls, dt, core = cpu_leg(run, 1e9, 1)
+        cvox = (len(rr["r"]["cells0"]) + len(rr["r"]["cells1"])) * 512 // 2
+        out["cpu_baseline"] = cpu_baseline(cvox * steps / dt, "voxel-steps/s",
+                                           "the first %d steps of the full particles256 workload (2M particles), "
+                                           "seed %d" % (steps, args.seed), dt, core)
+        out["cpu_baseline"]["particle_steps_per_s"] = p.nparticles * steps / dt
     return out
 
 
@@ -319,6 +443,28 @@ def bench_serving(args, torch):
                 "autotune": {k: v for k, v in tune.items() if k != "candidates"},
                 "eager_fifo": {"value": b["voxel_steps_per_s"], "latency_ms": {"p50": b["p50_ms"], "p99": b["p99_ms"]}},
                 "speedup_vs_eager": s["voxel_steps_per_s"] / b["voxel_steps_per_s"]})
+    # dominant launches: one batched iteration (the Jacobi and the copy
+    # launch over the whole work list, 20 B per voxel) over the closed batch
+    # of all requests, as the autotuner timed it between HIP events around
+    # replays of its captured graph
+    tot_vox = sum(r.nblocks for r in reqs0) * 512
+    out["roofline"] = roofline(20.0 * tot_vox / tune["s_per_iter"] / 1e9,
+                               "one batched Jacobi iteration (k_batch jacobi + copy launches, 20 B per active voxel) "
+                               "over all %d requests resident (%d blocks); mean per iteration over replays of the "
+                               "captured graph between two HIP events" % (count, tot_vox // 512), 20 * tot_vox)
+    if not args.no_cpu_baseline and not args.profile:
+        from oracle import programs as OP
+        done = []
+
+        def one(i):
+            r = reqs0[i]
+            blocks = np.stack(np.unravel_index(r.cells, (16, 16, 16)), axis=1).astype(np.int32)
+            OP.jacobi_program(128, blocks, r.b, r.iters)
+            done.append(r.voxel_iters)
+        calls, dt, core = cpu_leg(one, 10.0, count)
+        out["cpu_baseline"] = cpu_baseline(sum(done) / dt, "voxel-steps/s",
+                                           "the first %d requests of the stream solved one at a time (50 iterations "
+                                           "of listgen, jacobi, copy each), seed %d" % (calls, args.seed), dt, core)
     return out
 
 
@@ -366,11 +512,33 @@ def bench_diffusion(args, torch):
                 "eager": {"value": w.active_voxels * 20 / te, "ms_per_step": te * 1e3},
                 "speedup_vs_eager": te / t,
                 "gradients_equal_eager": bool(torch.equal(ga, gae) and torch.equal(gk, gke))})
+    # dominant launch: the adjoint step (a, k, lam', gk read; lam, gk
+    # written: 24 B per active voxel); the forward step moves 12 B
+    pr = DiffusionProblem(w.n, w.blocks, 0.1, 20, 5, opt_flags=E.OPT_ALL)
+    G = pr.grid
+    t_adj = time_kernel(torch, E, lambda: E.diffuse_adj(G, pr.ck[0], pr.K, pr.LA, pr.LB, pr.GK, 0.1), 100)
+    t_fwd = time_kernel(torch, E, lambda: E.diffuse(G, pr.ck[0], pr.K, pr.seg[1], 0.1), 100)
+    out["kernels"] = {"diffuse_adj_us": t_adj * 1e6, "diffuse_us": t_fwd * 1e6}
+    out["roofline"] = roofline(24.0 * w.active_voxels / t_adj / 1e9,
+                               "k_stencil_pipe<DIFFUSE_ADJ> (24 B per active voxel), mean of 100 back-to-back "
+                               "launches between two HIP events on the launch stream, median of 3 windows; the "
+                               "working set (under 8 MiB) stays in cache, so the HBM fraction is context",
+                               24 * w.active_voxels)
+    del pr
+    if not args.no_cpu_baseline and not args.profile:
+        from oracle import programs as OP
+        calls, dt, core = cpu_leg(lambda _: OP.diffusion_grad(w.n, w.blocks, w.channels["a"], w.channels["k"],
+                                                              w.channels["target"], 0.1, 20, "f32"), 5.0, 50)
+        out["cpu_baseline"] = cpu_baseline(w.active_voxels * 20 * calls / dt, "voxel-steps/s",
+                                           "%d forward + adjoint passes of the full diffusion128 loss (20 steps, "
+                                           "all states stored), seed %d; value counts forward steps" % (calls, args.seed),
+                                           dt, core)
     return out
 
 
 # ------------------------------------------------------------------- advection
 def bench_advection(args, torch, mac=False):
+    from paper_2012_08141_amd import _lib as L
     from paper_2012_08141_amd import engine as E
     from paper_2012_08141_amd import inputs, programs as PR
     w = inputs.tube(args.seed)
@@ -420,6 +588,37 @@ def bench_advection(args, torch, mac=False):
                                               "eager": E.paper_task_count(plane)},
                 "eager": {"value": w.active_voxels * K / te, "ms_per_step": te / K * 1e3},
                 "speedup_vs_eager": te / t})
+    # dominant launch of the optimized step, timed between HIP events around
+    # each launch over further windows (plan cached).  Algorithmic bytes per
+    # active voxel of a fused node: each field's q read and output written
+    # (advection: 8 B; MacCormack correction: q, fwd, bwd read, out written,
+    # 16 B; copy 8 B), plus the shared velocity (12 B) when the node samples it
+    E.reset()
+    g = PR.load_workload(w, names, nch)
+    step = E.prepare(step_fn(g, dt))
+    for _ in range(2):
+        E.run_sequence(step, E.OPT_ALL)
+    ents = window_kernel_means(E, step, E.OPT_ALL, 5)
+    dom = max(ents, key=lambda e: e["launches"] * e["mean_us"])
+    per_field = {L.AT_OP_ADVECT: 8, L.AT_OP_MACCORMACK: 16, L.AT_OP_COPY: 8}
+    out["kernels"] = {"%s/%d" % (e["name"], e["members"]): {"launches": e["launches"], "mean_us": e["mean_us"]}
+                      for e in ents}
+    if dom["kind"] == L.AT_TASK_STENCIL and dom["op"] in per_field:
+        per = per_field[dom["op"]] * dom["members"] + (12 if dom["op"] != L.AT_OP_COPY else 0)
+        out["roofline"] = roofline(per * w.active_voxels / (dom["mean_us"] * 1e-6) / 1e9,
+                                   "%s node fusing %d fields (%d B per active voxel); mean over %d launches, each "
+                                   "between its own HIP events (adds about 2 us per launch)"
+                                   % (dom["name"], dom["members"], per, dom["launches"]), per * w.active_voxels)
+    del step, g
+    if not args.no_cpu_baseline and not args.profile:
+        from oracle import programs as OP
+        fn = ((lambda: OP.maccormack_program(w.n, w.blocks, w.channels, dt, 1, rk3=True)) if mac else
+              (lambda: OP.advection_program(w.n, w.blocks, w.channels, dt, 1)))
+        calls, dt_cpu, core = cpu_leg(lambda _: fn(), 5.0, 10)
+        out["cpu_baseline"] = cpu_baseline(w.active_voxels * calls / dt_cpu, "voxel-steps/s",
+                                           "%d one-step runs of the full %s program (3 fields, setup included), "
+                                           "seed %d" % (calls, "maccormack256" if mac else "advection256", args.seed),
+                                           dt_cpu, core)
     return out
 
 
@@ -479,6 +678,29 @@ def bench_multigrid(args, torch):
                 "eager": {"value": w.active_voxels * K / te, "ms_per_step": te / K * 1e3},
                 "optimized_with_graph_replay": {"value": w.active_voxels * K / wg, "ms_per_step": wg / K * 1e3},
                 "speedup_vs_eager": te / t})
+    # dominant launch: the fine level's smoothing stencil, which the
+    # optimizer fuses with the update after it (t = J(x); t -= x) into one
+    # k_stencil_tail launch: x, b read, t written (12 B per fine voxel)
+    E.reset()
+    lv = PR.mg_levels(w, nl)
+    g0 = lv[0]
+    t_fused, lpg = time_group(torch, E, lambda: [E.listgen(g0), E.jacobi(g0, PR.MG["x"], PR.MG["b"], PR.MG["t"]),
+                                                 E.listgen(g0), E.axpy(g0, PR.MG["t"], PR.MG["x"], -1.0)],
+                              100, E.OPT_ALL & ~E.OPT_DSE)    # (DSE would drop all but the last group's stores)
+    out["kernels"] = {"fine_jacobi_tail_us": t_fused * 1e6, "launches_per_group": lpg}
+    if lpg == 1:
+        out["roofline"] = roofline(12.0 * w.active_voxels / t_fused / 1e9,
+                                   "k_stencil_tail (fine-level jacobi fused with t -= x; 12 B per fine active voxel), "
+                                   "mean of 100 back-to-back launches between two HIP events on the launch stream, "
+                                   "median of 3 windows", 12 * w.active_voxels)
+    del lv, g0
+    if not args.no_cpu_baseline and not args.profile:
+        from oracle import programs as OP
+        calls, dt, core = cpu_leg(lambda _: OP.multigrid_program(w.n, w.blocks, w.channels["b"], 2, levels=nl),
+                                  5.0, 10)
+        out["cpu_baseline"] = cpu_baseline(w.active_voxels * 2 * calls / dt, "voxel-steps/s",
+                                           "%d solves of 2 V-cycles (%d levels) of the full multigrid256 workload, "
+                                           "seed %d; value counts fine voxel-cycles" % (calls, nl, args.seed), dt, core)
     return out
 
 

@@ -156,3 +156,43 @@ def test_autotuner_choice_is_a_candidate_and_correct():
         done += K
     torch.cuda.synchronize()
     assert torch.equal(a1.x, a2.x)
+
+
+def test_full_size_requests_alone_mix_and_oracle():
+    """The serving workload at full size: the first 8 requests of the seed-0
+    stream (100 to 3,107 blocks) and its largest (request 246, 4,083 blocks),
+    50 iterations each, admitted at different replay boundaries of one
+    captured graph.  Each result equals the request solved alone (bit for
+    bit) and the oracle's in-order Jacobi program (within the stencil bar)."""
+    from paper_2012_08141_amd.batching import BatchArena
+    from paper_2012_08141_amd.serving import make_requests, solve_alone
+    say("batch full-size requests")
+    ids = list(range(8)) + [246]
+    allr = make_requests(0, 247, np.zeros(247))
+    reqs = [allr[i] for i in ids]
+    assert max(r.nblocks for r in reqs) == 4083 and all(r.iters == 50 for r in reqs)
+    arena = BatchArena(128, max_grids=16, pool_blocks=sum(r.nblocks for r in reqs))
+    graph = arena.capture(5)
+    pending, live, results = list(reqs), {}, {}
+    while pending or live:
+        if pending:                          # one admission per replay boundary
+            r = pending.pop(0)
+            r.gid = arena.admit(r.cells, r.b, r.iters)
+            r.end_clock = arena.clock_host + r.iters
+            live[r.rid] = r
+        for r in [r for r in live.values() if r.end_clock <= arena.clock_host]:
+            results[r.rid] = arena.retire(r.gid)
+            del live[r.rid]
+        if live:
+            graph.replay()
+    torch.cuda.synchronize()
+    for r in reqs:
+        say("  request", r.rid, r.nblocks, "blocks")
+        got = results[r.rid].cpu().numpy()
+        alone = solve_alone(r, 128, 0).cpu().numpy()
+        assert np.array_equal(got, alone), r.rid
+        ref = OP.jacobi_program(128, I.cells_to_blocks(r.cells, 16), r.b, r.iters)
+        assert np.array_equal(ref["cells"], r.cells)
+        exp = ref["x"]
+        tol = 1e-6 * np.maximum(np.abs(exp), 1e-3 * np.abs(exp).max())
+        assert np.all(np.abs(got - exp) <= tol), r.rid

@@ -87,6 +87,40 @@ def test_activate_and_listgen(root, n, frac, seed):
     assert np.array_equal(g.list_cells(), o.list())
 
 
+@pytest.mark.parametrize("root,n,frac", [("bitmask", 576, 0.05), ("pointer", 576, 0.05), ("pointer", 1024, 0.03),
+                                         ("pointer", 1296, 0.01), ("pointer", 2048, 0.004)])
+def test_listgen_look_back_on_large_roots(root, n, frac):
+    """Roots of more than 262,144 cells take the single-pass look-back scan
+    across workgroups (8 to 64 cells per thread, up to 1,024 workgroups).
+    About frac of the blocks at random plus one dense run of 20,000
+    consecutive cells (whole workgroups with every cell active); the list
+    and count must equal the oracle's ascending scan bit for bit (Section 3.2)."""
+    from paper_2012_08141_amd.grid import SparseGrid
+    say("listgen look-back", root, n, frac)
+    R = n // 8
+    assert R ** 3 > 262144
+    rng = np.random.default_rng([n, 17])
+    cells = np.flatnonzero(rng.uniform(size=R ** 3) < frac)
+    start = R ** 3 // 3
+    cells = np.union1d(cells, np.arange(start, start + 20000))
+    coords = np.stack(np.unravel_index(cells, (R, R, R)), axis=1).astype(np.int32)
+    rng.shuffle(coords)
+    g = SparseGrid(n, 1, root, len(cells) if root == "pointer" else 0)
+    o = oracle.OracleGrid(n, 1)
+    g.activate(coords)
+    g.listgen()
+    o.activate(coords)
+    o.listgen()
+    torch.cuda.synchronize()
+    assert g.device_status() == 0
+    assert g.list_count() == len(cells)
+    assert np.array_equal(g.list_cells(), o.list())
+    g.listgen()                          # a second generation (new epoch) over the same flags
+    assert np.array_equal(g.list_cells(), o.list())
+    assert g.device_status() == 0
+    del g
+
+
 def test_empty_grid_and_empty_activation():
     from paper_2012_08141_amd.grid import SparseGrid
     say("empty grids")
@@ -218,16 +252,17 @@ def test_jacobi_band_reduced(opt):
 
 
 def test_jacobi_band_full_size():
-    """The narrow-band workload at its full size (512^3): 2 iterations against the oracle,
-    then 100 iterations eager == optimized bit for bit."""
+    """The narrow-band workload at its full size (512^3): 12 iterations against the oracle
+    (x and xn, every voxel), then 100 iterations eager == optimized bit for bit."""
     from paper_2012_08141_amd import engine as E, programs as PR
     say("jacobi band512 full")
     w = I.band(0)
-    ref = OP.jacobi_program(w.n, w.blocks, w.channels["b"], 2)
+    ref = OP.jacobi_program(w.n, w.blocks, w.channels["b"], 12)
     g = PR.load_workload(w, PR.JACOBI, 3)
-    E.run_sequence(sum((PR.jacobi_step(g) for _ in range(2)), []), E.OPT_ALL)
+    E.run_sequence(sum((PR.jacobi_step(g) for _ in range(12)), []), E.OPT_ALL)
     torch.cuda.synchronize()
     close_stencil(g.read_blocks(0, ref["cells"]), ref["x"], "x")
+    close_stencil(g.read_blocks(1, ref["cells"]), ref["xn"], "xn")
     ge = PR.load_workload(w, PR.JACOBI, 3)
     go = PR.load_workload(w, PR.JACOBI, 3)
     E.run_sequence(sum((PR.jacobi_step(ge) for _ in range(100)), []), 0)
