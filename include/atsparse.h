@@ -223,6 +223,27 @@ at_status at_advect(float *d_x, const float *d_v, int64_t np, float dt, hipStrea
 at_status at_p2g(at_grid grid, const float *d_x, const float *d_v, const float *d_m, int64_t np,
                  float dx, const int32_t *ch, int32_t activation, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): at_p2g that
+ * always bins, through the library's own static binning workspace instead of
+ * the grid's (so it also bins on grids created with particle_capacity 0).
+ * Allocates nothing and calls no allocating routine; the workspace is one
+ * file-scope device array of about 50 MiB per device, held until the process
+ * ends.  Limits: np <= AT_STATIC_MAX_PARTICLES and R^3 <= AT_STATIC_MAX_CELLS
+ * (a domain edge of at most 512), else AT_E_INVALID with nothing enqueued.
+ * Same arguments, activation modes and result as at_p2g's binned scatter
+ * (within the same summation bound); six dispatches: a clear of the
+ * workspace's counts, then the five of the binned scatter.  Every call on a
+ * device shares that device's workspace and leaves its contents behind:
+ * calls that overlap on one device (on different streams, or from different
+ * host threads without ordering) race and give wrong sums.  The bins are
+ * not kept for later gathers or fused scatters (those use the grid's own
+ * workspace). */
+#define AT_STATIC_MAX_PARTICLES 1048576
+#define AT_STATIC_MAX_CELLS     262144
+at_status at_p2g_static(at_grid grid, const float *d_x, const float *d_v, const float *d_m, int64_t np,
+                        float dx, const int32_t *ch, int32_t activation, hipStream_t stream);
+
 /* Gather velocity (Section 8.3's G2P): v_p = sum over 27 nodes of w * v_node
  * (accumulated in node order from 0; 0 outside the domain or in inactive
  * blocks).  ch: {v0} (v on v0..v0+2).  After a binned scatter of as many

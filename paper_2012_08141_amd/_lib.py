@@ -38,6 +38,7 @@ AT_OPTION_BIN_REUSE = 9
 AT_OPTION_FUSE_BATCH = 10
 AT_OPTION_GRAPHS = 11
 AT_OPTION_GRAPHS_CACHED = 12
+AT_STATIC_MAX_PARTICLES, AT_STATIC_MAX_CELLS = 1048576, 262144
 
 
 class AtGridDesc(ctypes.Structure):
@@ -101,6 +102,7 @@ _SIGS = {
     "at_run_stencil": (c_int32, [_P, c_int32, ctypes.POINTER(c_int32), ctypes.POINTER(c_float), c_int32, _P]),
     "at_advect": (c_int32, [_P, _P, c_int64, c_float, _P]),
     "at_p2g": (c_int32, [_P, _P, _P, _P, c_int64, c_float, ctypes.POINTER(c_int32), c_int32, _P]),
+    "at_p2g_static": (c_int32, [_P, _P, _P, _P, c_int64, c_float, ctypes.POINTER(c_int32), c_int32, _P]),
     "at_g2p": (c_int32, [_P, _P, _P, c_int64, c_float, ctypes.POINTER(c_int32), _P]),
     "at_scatter_blocks": (c_int32, [_P, c_int32, _P, _P, c_int64, _P]),
     "at_gather_blocks": (c_int32, [_P, c_int32, _P, _P, c_int64, _P]),

@@ -138,6 +138,14 @@ hipError_t launch_popcount(const GridDev &g, hipStream_t s);   // into hdr[HDR_S
 hipError_t launch_batch_jacobi(const BatchDev &d, int iters, int workgroups, hipStream_t s);
 int batch_waves();
 void set_batch_waves(int waves);          // 1, 2 or 4 wavefronts per batched workgroup
+// Binning workspace in the library's static device array (the scatter that
+// allocates nothing): points g's workspace fields there and enqueues the
+// clear of its counts (1 dispatch).  hipErrorInvalidValue when np or the
+// grid's root cells exceed the array's limits.
+constexpr int64_t kStaticParticles = AT_STATIC_MAX_PARTICLES;
+constexpr int64_t kStaticCells = AT_STATIC_MAX_CELLS;
+hipError_t static_bin_workspace(GridDev &g, int64_t np, hipStream_t s);
+size_t static_workspace_bytes();
 // Persistent grid size used by struct-for kernels (workgroups).
 int struct_for_grid_size(const GridDev &g);
 void set_struct_for_grid_size(int wgs);   // 0 = automatic

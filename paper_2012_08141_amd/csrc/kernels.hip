@@ -11,6 +11,8 @@
 // coalesced dwordx4 access per wavefront pair.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "internal.hpp"
 
 namespace ats {
@@ -2184,6 +2186,19 @@ __global__ __launch_bounds__(1024) void k_popcount(GridDev g) {
     }
 }
 
+// Clears what the binning kernels expect to find at zero before a scatter
+// that bins through the static workspace: the per-cell counts of the cells
+// it may touch and the grid's append and outlier counters (a plain kernel,
+// not a memset, so that the clear can sit in a captured graph).
+__global__ __launch_bounds__(256) void k_static_clear(int32_t *pcount, int64_t n, int32_t *hdr) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        pcount[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        hdr[HDR_NAPPEND] = 0;
+        hdr[HDR_NOUT_ACC] = 0;
+    }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
@@ -2570,6 +2585,66 @@ hipError_t launch_batch_jacobi(const BatchDev &d, int iters, int workgroups, hip
 
 hipError_t launch_popcount(const GridDev &g, hipStream_t s) {
     hipLaunchKernelGGL(k_popcount, dim3(1), dim3(1024), 0, s, g);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------- static binning workspace
+// The binning workspace of a scatter that must not allocate: one file-scope
+// device array, which every device that loads this library holds for the
+// life of the process.  Segments, each 256-byte aligned: per-cell counts,
+// first positions and bins (kStaticCells each), per-particle keys, records
+// and outlier indices (kStaticParticles each).
+constexpr size_t kStaticSegCount = 0;
+constexpr size_t kStaticSegOff = kStaticSegCount + (size_t)kStaticCells * sizeof(int32_t);
+constexpr size_t kStaticSegBins = kStaticSegOff + (size_t)kStaticCells * sizeof(int32_t);
+constexpr size_t kStaticSegKr = kStaticSegBins + (size_t)kStaticCells * sizeof(int4);
+constexpr size_t kStaticSegStage = kStaticSegKr + (size_t)kStaticParticles * sizeof(int2);
+constexpr size_t kStaticSegOut = kStaticSegStage + 2 * (size_t)kStaticParticles * sizeof(float4);
+constexpr size_t kStaticBytes = kStaticSegOut + (size_t)kStaticParticles * sizeof(int32_t);
+static_assert(kStaticSegOff % 256 == 0 && kStaticSegBins % 256 == 0 && kStaticSegKr % 256 == 0 &&
+              kStaticSegStage % 256 == 0 && kStaticSegOut % 256 == 0, "segments must stay 256-byte aligned");
+
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};   // device address of `scratch`, per device
+}  // namespace
+
+size_t static_workspace_bytes() { return kStaticBytes; }
+
+hipError_t static_bin_workspace(GridDev &g, int64_t np, hipStream_t s) {
+    if (np < 0 || np > kStaticParticles || g.ncells > kStaticCells) return hipErrorInvalidValue;
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    unsigned char *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            // the array's own name is a host-side stand-in: its device
+            // address comes from the runtime, once per device
+            void *p = nullptr;
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return e;
+            if (!p) return hipErrorInvalidSymbol;
+            g_scratch_ptr[dev] = (unsigned char *)p;
+        }
+        base = g_scratch_ptr[dev];
+    }
+    g.pcap = kStaticParticles;
+    g.pcount = (int32_t *)(base + kStaticSegCount);
+    g.poff = (int32_t *)(base + kStaticSegOff);
+    g.pbins = (int4 *)(base + kStaticSegBins);
+    g.pkr = (int2 *)(base + kStaticSegKr);
+    g.pstage = (float4 *)(base + kStaticSegStage);
+    g.pout = (int32_t *)(base + kStaticSegOut);
+    int64_t blocks = (g.ncells + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_static_clear, dim3((unsigned)blocks), dim3(256), 0, s, g.pcount, g.ncells, g.hdr);
     return hipGetLastError();
 }
 

@@ -61,6 +61,7 @@ struct Engine {
     bool g2p_bins = true;   // gathers may use the source grid's bins
     int32_t bin_reuse = 8;  // scatters that may reuse a binning before the particles are binned again
     bool fuse_batch = true; // one graph simulation may serve several fusions (same plans)
+    bool static_ws = false; // the scatter being run bins through the static workspace (at_p2g_static)
     std::unordered_map<uint64_t, at_grid_s *> live;   // device grids by uid
     // Inside one window only its own nodes touch external arrays, so a
     // binned scatter's particle records still hold the current positions
@@ -264,6 +265,23 @@ at_status execute_node(const Node &nd, const at_task *tasks, bool table, hipStre
             if (t.kind == AT_TASK_P2G) dst = const_cast<at_grid_s *>(task_grid(t));
         }
         Engine &en = E();
+        int ndisp = 1;
+        if (en.static_ws && dst) {
+            // bins in the library's static array instead of the grid's workspace
+            GridDev wsd = dst->dev;
+            e = static_bin_workspace(wsd, pp.np, s);
+            if (e != hipSuccess) return hip_fail(e, "static binning workspace");
+            E().dispatches.fetch_add(1);
+            pp.gdst = wsd;
+            pp.gbin_s = wsd;
+            e = launch_particles(pp, s, &ndisp);
+            if (e != hipSuccess) return hip_fail(e, "kernel launch");
+            // the grid's own workspace no longer holds its latest bins
+            dst->bins_np = 0;
+            dst->ws_gen += 1;
+            E().dispatches.fetch_add(ndisp);
+            return AT_OK;
+        }
         const bool bin_dst = dst && dst->dev.pcap >= pp.np;
         // The gather may go through the bins of the source grid's last
         // binned scatter when it had exactly these many particles (the bins
@@ -288,7 +306,6 @@ at_status execute_node(const Node &nd, const at_task *tasks, bool table, hipStre
         pp.p2g_reuse = bin_dst && pp.g2p_rec_x && dst != src && own->bins_age < en.bin_reuse &&
                        own->dev.R == dst->dev.R && own->bins_inv_dx == pp.inv_dx_dst ? 1 : 0;
         pp.gbin_s = pp.p2g_reuse ? own->dev : (dst ? dst->dev : GridDev{});
-        int ndisp = 1;
         e = launch_particles(pp, s, &ndisp);
         if (e != hipSuccess) return hip_fail(e, "kernel launch");
         const int64_t after = writes + ((pp.steps & PS_ADVECT) ? 1 : 0);
@@ -819,6 +836,41 @@ at_status at_p2g(at_grid grid, const float *d_x, const float *d_v, const float *
     t.ch[1] = ch[1];
     t.flags = AT_TASKF_LOOP_UNIQUE;
     return run_one(t, stream);
+}
+
+at_status at_p2g_static(at_grid grid, const float *d_x, const float *d_v, const float *d_m, int64_t np, float dx,
+                        const int32_t *ch, int32_t activation, hipStream_t stream) {
+    at_status st = check_grid(grid, true);
+    if (st != AT_OK) return st;
+    if (!ch) return fail(AT_E_INVALID, "null channel array");
+    if (np < 0) return fail(AT_E_INVALID, "negative particle count");
+    if (np > AT_STATIC_MAX_PARTICLES)
+        return fail(AT_E_INVALID, "%lld particles exceed the static workspace's limit of %d", (long long)np,
+                    AT_STATIC_MAX_PARTICLES);
+    if (grid->dev.ncells > AT_STATIC_MAX_CELLS)
+        return fail(AT_E_INVALID, "%lld root cells exceed the static workspace's limit of %d",
+                    (long long)grid->dev.ncells, AT_STATIC_MAX_CELLS);
+    at_task t = blank_task(AT_TASK_P2G, grid);
+    t.op = activation;
+    t.ext[0] = (void *)d_x;
+    t.ext[1] = (void *)d_v;
+    t.ext[2] = (void *)d_m;
+    t.n = np;
+    t.param[0] = dx;
+    t.ch[0] = ch[0];
+    t.ch[1] = ch[1];
+    t.flags = AT_TASKF_LOOP_UNIQUE;
+    Engine &en = E();
+    std::lock_guard<std::recursive_mutex> lk(en.mu);
+    if (!en.queue.empty()) {
+        st = run_window(en.queue.data(), (int)en.queue.size(), en.opt_flags, nullptr, en.queue_stream);
+        en.queue.clear();
+        if (st != AT_OK) return st;
+    }
+    en.static_ws = true;
+    st = run_window(&t, 1, 0, nullptr, stream);
+    en.static_ws = false;
+    return st;
 }
 
 at_status at_g2p(at_grid grid, const float *d_x, float *d_v, int64_t np, float dx, const int32_t *ch,

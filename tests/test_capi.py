@@ -198,3 +198,14 @@ def test_planning_window_launches_nothing_and_mixing_is_rejected():
     st = E.run_sequence([E.listgen(g), E.advect(x, v, 1e-3), E.p2g(g, x, v, m, 1 / 64, 0, 1)], 0, stream=0)
     assert st["dispatches"] == 0 and L.lib().at_dispatch_count() == before
     E.reset()
+
+
+def test_static_scatter_validates_on_the_host():
+    lib = L.lib()
+    ch = (ctypes.c_int32 * 2)(0, 1)
+    assert lib.at_p2g_static(None, None, None, None, 0, 1.0, ch, 0, None) == L.AT_E_INVALID
+    d = _desc(32, L.AT_ROOT_POINTER, 4, 64)
+    h = ctypes.c_void_p()
+    assert lib.at_grid_create(ctypes.byref(d), None, 0, None, ctypes.byref(h)) == L.AT_OK
+    assert lib.at_p2g_static(h, None, None, None, 0, 1.0, ch, 0, None) == L.AT_E_STATE
+    assert lib.at_grid_destroy(h) == L.AT_OK
