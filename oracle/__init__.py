@@ -10,7 +10,8 @@ Two independent implementations live here:
   C implementation of the sparse-grid semantics (root table + block pool,
   activation on write with zero fill, ascending list generation, struct-fors
   over the list, 7-point stencils, PIC particle transfers, the diffusion step
-  and its hand-derived adjoint), built for fp32 and for fp64.
+  and its hand-derived adjoint, MLS-MPM transfers with fixed-corotated
+  stress), built for fp32 and for fp64.
 * ``oracle.dense`` -- a NumPy dense-array implementation for tiny grids, used
   to pin the C oracle's sparse machinery.
 
@@ -43,8 +44,16 @@ What pins each function (tests/test_oracle_pins.py):
 * inc -- exact on integer fields, +c then -c restoring them, only the listed
   blocks of its channel touched.
 
-tests/test_oracle_laws.py also compiles copies of oracle.c with planted
-mistakes and checks that those pins fail on each.
+* polar, fcr_stress, mpm_p2g, mpm_grid, mpm_g2p (MLS-MPM, Section 8.3) --
+  rotations from the polar decomposition against numpy's SVD; stress zero on
+  rotations, symmetric, frame indifferent and in closed form on uniform
+  scalings; affine fields reproduced by the gather (v and C); mass, momentum
+  and APIC angular momentum conserved by the scatter; free fall under
+  gravity, the floor wall, and a uniformly stretched block at rest inside
+  with its faces pulled inward (tests/test_oracle_mpm.py).
+
+tests/test_oracle_laws.py and tests/test_oracle_mpm.py also compile copies
+of oracle.c with planted mistakes and check that those pins fail on each.
 
 Every function has at least one such pin; none is "parity unpinned".
 """
@@ -109,6 +118,11 @@ def _load(path: str, prec: str):
         "og_prolong": (None, [P, P, i32, i32]),
         "og_g2p": (None, [P, i32, P, P, i64, R]),
         "og_bspline": (i32, [R, P]),
+        "og_polar": (i32, [P, P]),
+        "og_fcr_stress": (None, [P, R, R, P]),
+        "og_mpm_p2g": (i64, [P, i32, i32, i32, P, P, P, P, i64, R, R, R, R, R, R]),
+        "og_mpm_grid": (None, [P, i32, i32, i32, R, R, i32]),
+        "og_mpm_g2p": (None, [P, i32, P, P, P, i64, R]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -149,6 +163,25 @@ def advect(x: np.ndarray, v: np.ndarray, dt: float, precision: str = "f32") -> n
     vv = np.ascontiguousarray(v, dtype=d)
     _lib(precision).og_advect(_ptr(xo), _ptr(vv), xo.shape[1], d(dt))
     return xo
+
+
+def polar(F, precision: str = "f64"):
+    """(R, iterations) of the polar decomposition F = R S of one 3x3 matrix
+    (iterations -1 when det F <= 0)."""
+    d = _DTYPES[precision]
+    f = np.ascontiguousarray(np.asarray(F, dtype=d).reshape(9))
+    r = np.zeros(9, dtype=d)
+    it = _lib(precision).og_polar(_ptr(f), _ptr(r))
+    return r.reshape(3, 3), int(it)
+
+
+def fcr_stress(F, mu: float, lam: float, precision: str = "f64"):
+    """Kirchhoff stress of the fixed-corotated model at one 3x3 F."""
+    d = _DTYPES[precision]
+    f = np.ascontiguousarray(np.asarray(F, dtype=d).reshape(9))
+    t = np.zeros(9, dtype=d)
+    _lib(precision).og_fcr_stress(_ptr(f), d(mu), d(lam), _ptr(t))
+    return t.reshape(3, 3)
 
 
 class OracleGrid:
@@ -297,6 +330,32 @@ class OracleGrid:
         out = np.zeros_like(xx)
         self._L.og_g2p(self._g, ch_v, _ptr(xx), _ptr(out), xx.shape[1], d(inv_dx))
         return out
+
+    # -- MLS-MPM (Section 8.3) --------------------------------------------------
+    def mpm_p2g(self, ch_m: int, ch_mv: int, x, v, C, F, inv_dx: float, dt: float, mass: float, vol: float,
+                mu: float, lam: float, ch_abs: int = -1):
+        """Scatter of mass and APIC momentum with the fixed-corotated stress;
+        returns (updated F [9, np], node writes skipped outside the domain)."""
+        d = self.dtype
+        xx = np.ascontiguousarray(x, dtype=d)
+        vv = np.ascontiguousarray(v, dtype=d)
+        cc = np.ascontiguousarray(C, dtype=d)
+        ff = np.ascontiguousarray(F, dtype=d).copy()
+        bad = self._L.og_mpm_p2g(self._g, ch_m, ch_mv, ch_abs, _ptr(xx), _ptr(vv), _ptr(cc), _ptr(ff),
+                                 xx.shape[1], d(inv_dx), d(dt), d(mass), d(vol), d(mu), d(lam))
+        return ff, int(bad)
+
+    def mpm_grid(self, ch_m: int, ch_mv: int, ch_v: int, dt: float, gravity: float, bound: int):
+        self._L.og_mpm_grid(self._g, ch_m, ch_mv, ch_v, self.dtype(dt), self.dtype(gravity), bound)
+
+    def mpm_g2p(self, ch_v: int, x, inv_dx: float):
+        """(v [3, np], C [9, np]) gathered at the particles."""
+        d = self.dtype
+        xx = np.ascontiguousarray(x, dtype=d)
+        v = np.zeros_like(xx)
+        C = np.zeros((9, xx.shape[1]), dtype=d)
+        self._L.og_mpm_g2p(self._g, ch_v, _ptr(xx), _ptr(v), _ptr(C), xx.shape[1], d(inv_dx))
+        return v, C
 
     # -- convenience ----------------------------------------------------------
     def load(self, blocks, channel_values: dict, channel_index: dict) -> None:

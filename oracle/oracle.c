@@ -562,3 +562,215 @@ void og_g2p(const og_grid *g, int ch_v, const REAL *x, REAL *vout, int64_t np, R
 
 /* B-spline weights of one coordinate, exposed for the pins. */
 int og_bspline(REAL X, REAL *w3) { return bspline(X, w3); }
+
+/* ------------------------------------------------------------- MLS-MPM
+ * The particle-grid program of the paper's MLS-MPM benchmark (Section 8.3,
+ * the falling cube of fixed-corotated particles), following the moving
+ * least squares MPM it cites with APIC transfers: each particle carries a
+ * position x, a velocity v, the affine velocity matrix C and the
+ * deformation gradient F.  3x3 matrices are row-major, stored per particle
+ * as SoA rows: M[(3 r + c) * np + p].  Node offsets and weights follow
+ * og_p2g (quadratic B-spline, nodes in (x, y, z) lexicographic order); the
+ * offset of node (a, b, d) from the particle in physical units is
+ * dpos = ((a, b, d) - fx) * dx with fx = X - base per axis. */
+
+static REAL det3(const REAL *A) {
+    return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+           A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+
+/* Rotation R of the polar decomposition F = R S (S symmetric positive
+ * definite), for det F > 0: Newton's iteration R <- (R + R^-T) / 2 from
+ * R = F until no entry moves by more than a few units of rounding (at most
+ * 100 iterations).  R^-T is the cofactor matrix over the determinant.
+ * Returns the iterations taken, or -1 when det F <= 0. */
+int og_polar(const REAL *F, REAL *R) {
+    REAL X[9];
+    for (int q = 0; q < 9; ++q) X[q] = F[q];
+    if (!(det3(X) > (REAL)0)) return -1;
+    const REAL tol = sizeof(REAL) == 8 ? (REAL)1e-15 : (REAL)2e-7;
+    for (int it = 1; it <= 100; ++it) {
+        REAL d = det3(X);
+        REAL cof[9];
+        cof[0] = X[4] * X[8] - X[5] * X[7];
+        cof[1] = X[5] * X[6] - X[3] * X[8];
+        cof[2] = X[3] * X[7] - X[4] * X[6];
+        cof[3] = X[2] * X[7] - X[1] * X[8];
+        cof[4] = X[0] * X[8] - X[2] * X[6];
+        cof[5] = X[1] * X[6] - X[0] * X[7];
+        cof[6] = X[1] * X[5] - X[2] * X[4];
+        cof[7] = X[2] * X[3] - X[0] * X[5];
+        cof[8] = X[0] * X[4] - X[1] * X[3];
+        REAL moved = 0;
+        for (int q = 0; q < 9; ++q) {
+            REAL nx = (REAL)0.5 * (X[q] + cof[q] / d);
+            REAL step = (REAL)fabs((double)(nx - X[q]));
+            if (step > moved) moved = step;
+            X[q] = nx;
+        }
+        if (moved <= tol) {
+            for (int q = 0; q < 9; ++q) R[q] = X[q];
+            return it;
+        }
+    }
+    for (int q = 0; q < 9; ++q) R[q] = X[q];
+    return 100;
+}
+
+/* Kirchhoff stress of the fixed-corotated model at F:
+ * tau = 2 mu (F - R) F^T + lambda (J - 1) J I, J = det F, R from og_polar. */
+void og_fcr_stress(const REAL *F, REAL mu, REAL lam, REAL *tau) {
+    REAL R[9];
+    og_polar(F, R);
+    REAL J = det3(F);
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            REAL s = 0;
+            for (int k = 0; k < 3; ++k) s = s + (F[3 * r + k] - R[3 * r + k]) * F[3 * c + k];
+            tau[3 * r + c] = (REAL)2 * mu * s + (r == c ? lam * (J - (REAL)1) * J : (REAL)0);
+        }
+}
+
+/* MLS-MPM particle-to-grid transfer, particles in id order.  Per particle:
+ *   F <- (I + dt C) F                          (stored back into F)
+ *   A  = -(dt * vol * 4 * inv_dx^2) tau(F) + mass * C
+ *   node (a, b, d) receives  m  += w * mass
+ *                            mv += w * (mass * v + A dpos)
+ * with w and dpos as above.  Activation, accumulation in double and the
+ * optional |term| sums (ch_abs .. ch_abs + 3) as in og_p2g.  Returns the
+ * number of node writes outside the domain (skipped). */
+int64_t og_mpm_p2g(og_grid *g, int ch_m, int ch_mv, int ch_abs, const REAL *x, const REAL *v,
+                   const REAL *C, REAL *F, int64_t np, REAL inv_dx, REAL dt, REAL mass, REAL vol,
+                   REAL mu, REAL lam) {
+    int64_t bad = 0;
+    for (int64_t p = 0; p < np; ++p) {
+        REAL w[3][3];
+        int base[3];
+        for (int c = 0; c < 3; ++c) base[c] = bspline(x[c * np + p] * inv_dx, w[c]);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                for (int d = 0; d < 3; ++d) {
+                    int i = base[0] + a, j = base[1] + b, k = base[2] + d;
+                    if (i < 0 || j < 0 || k < 0 || i >= g->n || j >= g->n || k >= g->n) { ++bad; continue; }
+                    activate_block(g, i / BS, j / BS, k / BS);
+                }
+    }
+    int nacc = ch_abs >= 0 ? 8 : 4;
+    size_t len = (size_t)g->nslots * BV;
+    double *acc = (double *)malloc(sizeof(double) * len * nacc);
+    for (int q = 0; q < 4; ++q) {
+        int ch = q == 0 ? ch_m : ch_mv + q - 1;
+        for (size_t t = 0; t < len; ++t) acc[q * len + t] = (double)g->pool[ch][t];
+        if (ch_abs >= 0)
+            for (size_t t = 0; t < len; ++t) acc[(4 + q) * len + t] = (double)g->pool[ch_abs + q][t];
+    }
+    const REAL dx = (REAL)1 / inv_dx;
+    const REAL kstress = dt * vol * (REAL)4 * inv_dx * inv_dx;
+    for (int64_t p = 0; p < np; ++p) {
+        REAL Cp[9], Fo[9], Fn[9], tau[9], A[9];
+        for (int q = 0; q < 9; ++q) {
+            Cp[q] = C[q * np + p];
+            Fo[q] = F[q * np + p];
+        }
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) {
+                REAL s = 0;
+                for (int k = 0; k < 3; ++k) s = s + ((r == k ? (REAL)1 : (REAL)0) + dt * Cp[3 * r + k]) * Fo[3 * k + c];
+                Fn[3 * r + c] = s;
+            }
+        for (int q = 0; q < 9; ++q) F[q * np + p] = Fn[q];
+        og_fcr_stress(Fn, mu, lam, tau);
+        for (int q = 0; q < 9; ++q) A[q] = -(kstress * tau[q]) + mass * Cp[q];
+        REAL w[3][3], fx[3];
+        int base[3];
+        for (int c = 0; c < 3; ++c) {
+            REAL X = x[c * np + p] * inv_dx;
+            base[c] = bspline(X, w[c]);
+            fx[c] = X - (REAL)base[c];
+        }
+        REAL mvp[3] = {mass * v[p], mass * v[np + p], mass * v[2 * np + p]};
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                for (int d = 0; d < 3; ++d) {
+                    int i = base[0] + a, j = base[1] + b, k = base[2] + d;
+                    if (i < 0 || j < 0 || k < 0 || i >= g->n || j >= g->n || k >= g->n) continue;
+                    int32_t s = g->root[cell_of_block(g, i / BS, j / BS, k / BS)];
+                    size_t at = (size_t)s * BV + (i % BS) * 64 + (j % BS) * 8 + (k % BS);
+                    REAL wt = (w[0][a] * w[1][b]) * w[2][d];
+                    REAL dpos[3] = {((REAL)a - fx[0]) * dx, ((REAL)b - fx[1]) * dx, ((REAL)d - fx[2]) * dx};
+                    REAL term[4];
+                    term[0] = wt * mass;
+                    for (int c = 0; c < 3; ++c) {
+                        REAL ad = A[3 * c] * dpos[0] + A[3 * c + 1] * dpos[1] + A[3 * c + 2] * dpos[2];
+                        term[1 + c] = wt * (mvp[c] + ad);
+                    }
+                    for (int q = 0; q < 4; ++q) {
+                        acc[q * len + at] += (double)term[q];
+                        if (ch_abs >= 0) acc[(4 + q) * len + at] += fabs((double)term[q]);
+                    }
+                }
+    }
+    for (int q = 0; q < 4; ++q) {
+        int ch = q == 0 ? ch_m : ch_mv + q - 1;
+        for (size_t t = 0; t < len; ++t) g->pool[ch][t] = (REAL)acc[q * len + t];
+        if (ch_abs >= 0)
+            for (size_t t = 0; t < len; ++t) g->pool[ch_abs + q][t] = (REAL)acc[(4 + q) * len + t];
+    }
+    free(acc);
+    return bad;
+}
+
+/* MLS-MPM grid update over the list: where m > 0, v = mv / m, then
+ * v_z -= dt * gravity (z, axis 2, is up), then the walls: along each axis a
+ * node within `bound` nodes of the low side (index < bound) loses a
+ * negative velocity component and one beyond n - bound a positive one.
+ * Where m == 0, v = 0. */
+void og_mpm_grid(og_grid *g, int ch_m, int ch_mv, int ch_v, REAL dt, REAL gravity, int bound) {
+    FOR_EACH_LISTED_VOXEL(g, {
+        REAL mm = rd(g, ch_m, i, j, k);
+        REAL vv[3] = {(REAL)0, (REAL)0, (REAL)0};
+        if (mm > (REAL)0) {
+            for (int c = 0; c < 3; ++c) vv[c] = rd(g, ch_mv + c, i, j, k) / mm;
+            vv[2] = vv[2] - dt * gravity;
+            int idx[3] = {i, j, k};
+            for (int c = 0; c < 3; ++c) {
+                if (idx[c] < bound && vv[c] < (REAL)0) vv[c] = (REAL)0;
+                if (idx[c] > g->n - bound && vv[c] > (REAL)0) vv[c] = (REAL)0;
+            }
+        }
+        for (int c = 0; c < 3; ++c) wr(g, ch_v + c, i, j, k, vv[c]);
+    })
+}
+
+/* MLS-MPM grid-to-particle gather: v_p = sum of w * v_node and
+ * C_p = 4 inv_dx^2 * sum of w * v_node dpos^T over the 27 nodes, both
+ * accumulated in REAL from 0 in node order (C as B_rc += (w * v_r) * dpos_c,
+ * then scaled).  Nodes outside the domain or in inactive blocks read 0. */
+void og_mpm_g2p(const og_grid *g, int ch_v, const REAL *x, REAL *vout, REAL *Cout, int64_t np, REAL inv_dx) {
+    const REAL dx = (REAL)1 / inv_dx;
+    const REAL kc = (REAL)4 * inv_dx * inv_dx;
+    for (int64_t p = 0; p < np; ++p) {
+        REAL w[3][3], fx[3];
+        int base[3];
+        for (int c = 0; c < 3; ++c) {
+            REAL X = x[c * np + p] * inv_dx;
+            base[c] = bspline(X, w[c]);
+            fx[c] = X - (REAL)base[c];
+        }
+        REAL av[3] = {0, 0, 0}, B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                for (int d = 0; d < 3; ++d) {
+                    int i = base[0] + a, j = base[1] + b, k = base[2] + d;
+                    REAL wt = (w[0][a] * w[1][b]) * w[2][d];
+                    REAL off[3] = {((REAL)a - fx[0]) * dx, ((REAL)b - fx[1]) * dx, ((REAL)d - fx[2]) * dx};
+                    for (int r = 0; r < 3; ++r) {
+                        REAL wv = wt * rd(g, ch_v + r, i, j, k);
+                        av[r] = av[r] + wv;
+                        for (int c = 0; c < 3; ++c) B[3 * r + c] = B[3 * r + c] + wv * off[c];
+                    }
+                }
+        for (int r = 0; r < 3; ++r) vout[r * np + p] = av[r];
+        for (int q = 0; q < 9; ++q) Cout[q * np + p] = kc * B[q];
+    }
+}

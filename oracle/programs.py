@@ -245,3 +245,48 @@ def maccormack_program(n, blocks, channels, dt, steps, precision="f32", rk3=Fals
             g.listgen(); g.copy(c, 12 + c)
     cells = g.active_cells()
     return {"cells": cells, "q": [g.read_blocks(c, cells) for c in range(3)]}
+
+
+# ---------------------------------------------------------------------------
+# MLS-MPM (Section 8.3): substep t uses grid G = grids[t % 2] (the paper's two
+# grids swapped before each substep); channels m, mv (3), v (3), and with
+# with_abs the per-node sums of |term| (4) of the last scatter into G.
+MPM_M, MPM_MV, MPM_V, MPM_ABS = 0, 1, 4, 7
+
+
+def mpm_program(n, x, v, C, F, steps, dt, mass, vol, mu, lam, gravity, bound, precision="f64",
+                with_abs=False):
+    """Per substep: listgen(G) -> fill(G: m, mv = 0) -> mpm_p2g(G) (F updated,
+    activating) -> listgen(G) -> mpm_grid(G) (v, gravity, walls) ->
+    mpm_g2p(G) (v and C gathered) -> advect (x += dt v).  Returns the final
+    particle state and both grids' cells and channels."""
+    inv_dx = float(n)
+    nch = 11 if with_abs else 7
+    grids = [OracleGrid(n, nch, precision), OracleGrid(n, nch, precision)]
+    d = np.float32 if precision == "f32" else np.float64
+    x = np.ascontiguousarray(x, dtype=d).copy()
+    v = np.ascontiguousarray(v, dtype=d).copy()
+    C = np.ascontiguousarray(C, dtype=d).copy()
+    F = np.ascontiguousarray(F, dtype=d).copy()
+    for t in range(steps):
+        G = grids[t % 2]
+        G.listgen()
+        for ch in range(MPM_MV + 3):
+            G.fill(ch, 0.0)
+        if with_abs:
+            for ch in range(MPM_ABS, MPM_ABS + 4):
+                G.fill(ch, 0.0)
+        F, bad = G.mpm_p2g(MPM_M, MPM_MV, x, v, C, F, inv_dx, dt, mass, vol, mu, lam,
+                           MPM_ABS if with_abs else -1)
+        if bad:
+            raise RuntimeError("particle left the domain")
+        G.listgen()
+        G.mpm_grid(MPM_M, MPM_MV, MPM_V, dt, gravity, bound)
+        v, C = G.mpm_g2p(MPM_V, x, inv_dx)
+        x = advect(x, v, dt, precision)
+    out = {"x": x, "v": v, "C": C, "F": F}
+    for gi, G in enumerate(grids):
+        cells = G.active_cells()
+        out["cells%d" % gi] = cells
+        out["grid%d" % gi] = {ch: G.read_blocks(ch, cells) for ch in range(nch)}
+    return out

@@ -279,3 +279,76 @@ def tube(seed: int = 0, n: int = 256, r_in: float = 0.32, r_out: float = 0.45,
     ch["v1"] = (s * (x - 0.5) * n).astype(np.float32)
     ch["v2"] = np.full_like(ch["v0"], s * wz * n)
     return SparseWorkload("tube%d" % n, n, root_kind, blocks, ch, {"dt": 1.0 / n, "speed": s, "axial": wz})
+
+
+# ---------------------------------------------------------------------------
+# MLS-MPM workload: the falling cube of the paper's Section 8.3 benchmark
+# (supplement Section 4.3).
+# ---------------------------------------------------------------------------
+@dataclass
+class MpmWorkload:
+    """Particles with APIC affine velocity C and deformation gradient F
+    (SoA float32: x, v [3, np]; C, F [9, np], row-major 3x3 per particle)."""
+    name: str
+    n: int
+    root_kind: str
+    x: np.ndarray
+    v: np.ndarray
+    C: np.ndarray
+    F: np.ndarray
+    params: dict = field(default_factory=dict)
+
+    @property
+    def nparticles(self) -> int:
+        return int(self.x.shape[1])
+
+
+def mpm_cube(seed: int = 0, n: int = 256, side: float = 0.5, z_bottom: float = 49.0 / 1024.0,
+             jitter: float = 0.25, root_kind: str = "bitmask", E: float = 2e4, nu: float = 0.4,
+             rho: float = 1e3, gravity: float = 9.8, dt: float = 1e-4, v_sigma: float = 0.0,
+             c_sigma: float = 0.0, f_sigma: float = 0.0) -> MpmWorkload:
+    """A cube of edge ``side`` filled with a lattice of particles two per cell
+    per axis (spacing dx/2, dx = 1/n), centred in x and y, the lowest layer's
+    centres at ``z_bottom`` (z, axis 2, is up).  Each particle stands for a
+    cube of edge dx/2 of density ``rho``: volume (dx/2)^3, mass rho times
+    that.  Material: Young's modulus E and Poisson ratio nu, given as the
+    Lame parameters mu = E / (2 (1 + nu)), lambda = E nu / ((1 + nu)(1 - 2 nu)).
+    Walls 1/32 of the domain from each side (``bound`` = n/32 nodes).
+
+    Seeded: each lattice point moves by U(-jitter, jitter) of the spacing per
+    axis (so the B-spline weights take generic values) and the cube centre by
+    U(-0.5, 0.5) cells in x and y.  The paper's cube starts at rest with F = I
+    and C = 0; ``v_sigma``, ``c_sigma``, ``f_sigma`` > 0 draw v ~ N(0, v_sigma^2),
+    C ~ N(0, c_sigma^2) and F = I + N(0, f_sigma^2) per entry instead (test
+    states that exercise every term).  Order: blocks of 8^3 lattice points in
+    lexicographic block order, lexicographic inside a block."""
+    rng = np.random.default_rng([11, seed, n])
+    h = 0.5 / n
+    P = int(round(side / h))
+    centre = 0.5 + rng.uniform(-0.5, 0.5, 2) / n
+    lo = np.array([centre[0] - 0.5 * side + 0.5 * h, centre[1] - 0.5 * side + 0.5 * h, z_bottom])
+    idx = np.arange(P)
+    bsz = 8
+    nb = (P + bsz - 1) // bsz
+    order = []
+    for bi in range(nb):
+        for bj in range(nb):
+            for bk in range(nb):
+                ii, jj, kk = np.meshgrid(idx[bi * bsz:(bi + 1) * bsz], idx[bj * bsz:(bj + 1) * bsz],
+                                         idx[bk * bsz:(bk + 1) * bsz], indexing="ij")
+                order.append(np.stack([ii.ravel(), jj.ravel(), kk.ravel()]))
+    lat = np.concatenate(order, axis=1).astype(np.float64)
+    npart = lat.shape[1]
+    x = lo[:, None] + h * lat + h * rng.uniform(-jitter, jitter, (3, npart))
+    v = rng.normal(0.0, v_sigma, (3, npart)) if v_sigma > 0 else np.zeros((3, npart))
+    C = rng.normal(0.0, c_sigma, (9, npart)) if c_sigma > 0 else np.zeros((9, npart))
+    F = np.zeros((9, npart))
+    F[0] = F[4] = F[8] = 1.0
+    if f_sigma > 0:
+        F = F + rng.normal(0.0, f_sigma, (9, npart))
+    vol = h ** 3
+    params = {"dt": dt, "dx": 1.0 / n, "mass": rho * vol, "vol": vol,
+              "mu": E / (2.0 * (1.0 + nu)), "lam": E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu)),
+              "gravity": gravity, "bound": max(1, n // 32), "side": side, "lattice": P}
+    f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    return MpmWorkload("mpm_cube%d" % n, n, root_kind, f32(x), f32(v), f32(C), f32(F), params)
