@@ -711,8 +711,8 @@ int64_t og_mpm_p2g(og_grid *g, int ch_m, int ch_mv, int ch_abs, const REAL *x, c
                 }
     }
     for (int q = 0; q < 4; ++q) {
-        int ch = q == 0 ? ch_m : ch_mv + q - 1;
-        for (size_t t = 0; t < len; ++t) g->pool[ch][t] = (REAL)acc[q * len + t];
+        REAL *dst = g->pool[q == 0 ? ch_m : ch_mv + q - 1];
+        for (size_t t = 0; t < len; ++t) dst[t] = (REAL)acc[q * len + t];
         if (ch_abs >= 0)
             for (size_t t = 0; t < len; ++t) g->pool[ch_abs + q][t] = (REAL)acc[(4 + q) * len + t];
     }
@@ -727,10 +727,10 @@ int64_t og_mpm_p2g(og_grid *g, int ch_m, int ch_mv, int ch_abs, const REAL *x, c
  * Where m == 0, v = 0. */
 void og_mpm_grid(og_grid *g, int ch_m, int ch_mv, int ch_v, REAL dt, REAL gravity, int bound) {
     FOR_EACH_LISTED_VOXEL(g, {
-        REAL mm = rd(g, ch_m, i, j, k);
+        REAL mnode = rd(g, ch_m, i, j, k);
         REAL vv[3] = {(REAL)0, (REAL)0, (REAL)0};
-        if (mm > (REAL)0) {
-            for (int c = 0; c < 3; ++c) vv[c] = rd(g, ch_mv + c, i, j, k) / mm;
+        if (mnode > (REAL)0) {
+            for (int c = 0; c < 3; ++c) vv[c] = rd(g, ch_mv + c, i, j, k) / mnode;
             vv[2] = vv[2] - dt * gravity;
             int idx[3] = {i, j, k};
             for (int c = 0; c < 3; ++c) {
