@@ -189,9 +189,16 @@ at_status at_listgen(at_grid grid, hipStream_t stream);
                                 of I (as for AT_OP_ADVECT; sparse reads; far points
                                 moved as for AT_OP_ADVECT), fwd = ADVECT(q, dt) and
                                 bwd = ADVECT(fwd, -dt)                                     */
+#define AT_OP_MPM_GRID   12  /* ch {m, mv0, v0}; p {dt, g, bound}: the MLS-MPM grid
+                                update (Section 8.3): where m > 0, v = mv / m, then
+                                v_z = v_z - dt*g (z, axis 2, is up), then the walls: per
+                                axis c, a voxel with index I_c < bound loses a negative v_c
+                                and one with I_c > n - bound a positive v_c; where m == 0,
+                                v = 0.  v may not overlap m or mv                           */
 
 /* ch: host array of channel indices (meaning per op above); params: host
- * array of up to 4 floats.  check_activation != 0 keeps the per-write
+ * array of the op's parameters, in the order listed above (ADVECT and
+ * MACCORMACK: 2, MPM_GRID: 3, the others 1; NULL for none).  check_activation != 0 keeps the per-write
  * activation check of an eager task (activation on write); 0 is the
  * demoted form (Section 6.3). */
 at_status at_run_stencil(at_grid grid, int32_t op, const int32_t *ch, const float *params,
@@ -252,6 +259,39 @@ at_status at_p2g_static(at_grid grid, const float *d_x, const float *d_v, const 
 at_status at_g2p(at_grid grid, const float *d_x, float *d_v, int64_t np, float dx,
                  const int32_t *ch, hipStream_t stream);
 
+/* MLS-MPM transfers (the falling cube of Section 8.3: moving least squares
+ * MPM with APIC transfers and the fixed-corotated material).  Per-particle
+ * state, all device SoA fp32: x, v [3][np]; C (affine velocity) and F
+ * (deformation gradient) [9][np], row-major 3x3 per particle
+ * (M_rc at M[(3r + c) * np + p]).  Weights, base and node order as for
+ * at_p2g; fx = X - base per axis and the offset of node (a, b, d) from the
+ * particle is dpos = ((a, b, d) - fx) * dx.
+ *
+ * Scatter: per particle F <- (I + dt C) F (stored), R the rotation of the
+ * polar decomposition of F (Newton's iteration R <- (R + R^-T)/2 from F,
+ * which needs det F > 0; fp32), J = det F, Kirchhoff stress
+ * tau = 2 mu (F - R) F^T + lambda (J - 1) J I,
+ * A = -(dt vol 4 / dx^2) tau + mass C; node (a, b, d) receives
+ * m += w mass and mv += w (mass v + A dpos), with fp32 atomics in any order
+ * (results agree with an in-order sum within the summation bound),
+ * activating the blocks of the nodes written (AT_ACT_PER_NODE and
+ * AT_ACT_PER_BLOCK activate the same blocks, once per block and
+ * workgroup; AT_ACT_NONE drops contributions to inactive blocks).  Nodes
+ * outside the domain are skipped.  ch: {m, mv0}.  Particles are processed in
+ * chunks of 256 consecutive indices whose nodes are summed in an on-chip tile
+ * first when they fit in 1,024 nodes (so spatially ordered particle arrays
+ * scatter far faster; any order gives the same result). */
+at_status at_p2g_mls(at_grid grid, const float *d_x, const float *d_v, const float *d_C, float *d_F,
+                     int64_t np, float dx, float dt, float mass, float vol, float mu, float lambda,
+                     const int32_t *ch, int32_t activation, hipStream_t stream);
+
+/* Gather: v_p = sum of w v_node and C_p = (4 / dx^2) sum of w v_node dpos^T
+ * over the 27 nodes, accumulated in node order from 0 as
+ * wv = w * v_r; v_r = v_r + wv; B_rc = B_rc + wv * dpos_c, then C = (4/dx^2) B
+ * (nodes outside the domain or in inactive blocks read 0).  ch: {v0}. */
+at_status at_g2p_apic(at_grid grid, const float *d_x, float *d_v, float *d_C, int64_t np, float dx,
+                      const int32_t *ch, hipStream_t stream);
+
 /* Copy listed values between a grid and dense per-block arrays (setup and
  * inspection, not part of the optimized path).  cells: device int32 [n]
  * root cells; vals: device float [n][512].  at_scatter_blocks activates the
@@ -291,6 +331,19 @@ at_status at_gather_blocks(at_grid grid, int32_t ch, const int32_t *d_cells, flo
  *                     (an inactive coarse voxel reads 0; the coarse grid is
  *                     not written).  With RESTRICT, the transfers of the
  *                     multigrid solver of Section 8.4.
+ *   AT_TASK_P2G_MLS   range-for: grid (scatter target); op = AT_ACT_*; the
+ *                     MLS-MPM scatter of Section 8.3 (see at_p2g_mls):
+ *                     ext[0] = x, ext[1] = v, ext[2] = C (read),
+ *                     ext[3] = F (read and written); param = {dx, dt, mass,
+ *                     vol, mu, lambda}; ch[0] = m, ch[1] = mv0
+ *   AT_TASK_G2P_APIC  range-for: grid (gather source); the MLS-MPM gather
+ *                     (see at_g2p_apic): ext[0] = x, ext[1] = v and
+ *                     ext[2] = C (both written); param[0] = dx; ch[0] = v0.
+ *                     With the loop_unique hint, G2P_APIC, ADVECT and
+ *                     P2G_MLS over the same arrays fuse into one G2P2G task,
+ *                     in which the gathered v and C reach the scatter in
+ *                     registers, so dead store elimination can drop their
+ *                     stores (supplement Section 4.4).
  * Unused ch entries must be -1 and unused ext entries NULL; grid2 is NULL
  * except for the two-level tasks. */
 #define AT_TASK_ACTIVATE 1
@@ -301,6 +354,8 @@ at_status at_gather_blocks(at_grid grid, int32_t ch, const int32_t *d_cells, flo
 #define AT_TASK_G2P      6
 #define AT_TASK_RESTRICT 7
 #define AT_TASK_PROLONG  8
+#define AT_TASK_P2G_MLS  9
+#define AT_TASK_G2P_APIC 10
 
 /* The particle arrays of this task are indexed only at the loop index, and
  * the loop index is unique per iteration and covers the array (the paper's
@@ -316,7 +371,7 @@ typedef struct at_task {
     at_grid grid;
     at_grid grid2;        /* coarse level of RESTRICT / PROLONG; NULL otherwise */
     int32_t ch[8];        /* channels; unused entries -1 */
-    float param[4];
+    float param[8];       /* scalar parameters; unused entries 0 */
     void *ext[4];         /* device pointers of external arrays */
     int64_t n;            /* element count of a range-for (coordinates, particles) */
 } at_task;

@@ -636,8 +636,14 @@ void og_fcr_stress(const REAL *F, REAL mu, REAL lam, REAL *tau) {
  *   A  = -(dt * vol * 4 * inv_dx^2) tau(F) + mass * C
  *   node (a, b, d) receives  m  += w * mass
  *                            mv += w * (mass * v + A dpos)
- * with w and dpos as above.  Activation, accumulation in double and the
- * optional |term| sums (ch_abs .. ch_abs + 3) as in og_p2g.  Returns the
+ * with w and dpos as above.  Activation and accumulation in double as in
+ * og_p2g.  With ch_abs >= 0, channels ch_abs .. ch_abs + 3 receive the
+ * error scale of each node's sum: the sum over its terms of the magnitudes
+ * of the products each term is made of -- |w mass| for m and, for mv_c,
+ * |w| (|mass v_c| + sum_e |A_ce|' |dpos_e|), where |A_ce|' bounds the
+ * magnitudes inside A_ce: dt vol 4 inv_dx^2 (2 mu sum_k (|F_ck| + |R_ck|)
+ * |F_ek| + |lambda (J - 1) J|) + mass |C_ce| (the difference F - R cancels,
+ * so its rounding error is set by |F| and |R|, not by F - R).  Returns the
  * number of node writes outside the domain (skipped). */
 int64_t og_mpm_p2g(og_grid *g, int ch_m, int ch_mv, int ch_abs, const REAL *x, const REAL *v,
                    const REAL *C, REAL *F, int64_t np, REAL inv_dx, REAL dt, REAL mass, REAL vol,
@@ -681,6 +687,20 @@ int64_t og_mpm_p2g(og_grid *g, int ch_m, int ch_mv, int ch_abs, const REAL *x, c
         for (int q = 0; q < 9; ++q) F[q * np + p] = Fn[q];
         og_fcr_stress(Fn, mu, lam, tau);
         for (int q = 0; q < 9; ++q) A[q] = -(kstress * tau[q]) + mass * Cp[q];
+        REAL Aabs[9];
+        if (ch_abs >= 0) {
+            REAL Rn[9];
+            og_polar(Fn, Rn);
+            REAL J = det3(Fn);
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) {
+                    double sz = 0;
+                    for (int k = 0; k < 3; ++k)
+                        sz += (fabs((double)Fn[3 * r + k]) + fabs((double)Rn[3 * r + k])) * fabs((double)Fn[3 * c + k]);
+                    double t = 2.0 * fabs((double)mu) * sz + (r == c ? fabs((double)(lam * (J - 1) * J)) : 0.0);
+                    Aabs[3 * r + c] = (REAL)(fabs((double)kstress) * t + fabs((double)(mass * Cp[3 * r + c])));
+                }
+        }
         REAL w[3][3], fx[3];
         int base[3];
         for (int c = 0; c < 3; ++c) {
@@ -704,9 +724,14 @@ int64_t og_mpm_p2g(og_grid *g, int ch_m, int ch_mv, int ch_abs, const REAL *x, c
                         REAL ad = A[3 * c] * dpos[0] + A[3 * c + 1] * dpos[1] + A[3 * c + 2] * dpos[2];
                         term[1 + c] = wt * (mvp[c] + ad);
                     }
-                    for (int q = 0; q < 4; ++q) {
-                        acc[q * len + at] += (double)term[q];
-                        if (ch_abs >= 0) acc[(4 + q) * len + at] += fabs((double)term[q]);
+                    for (int q = 0; q < 4; ++q) acc[q * len + at] += (double)term[q];
+                    if (ch_abs >= 0) {
+                        acc[4 * len + at] += fabs((double)term[0]);
+                        for (int c = 0; c < 3; ++c) {
+                            double sz = fabs((double)mvp[c]);
+                            for (int e = 0; e < 3; ++e) sz += fabs((double)Aabs[3 * c + e]) * fabs((double)dpos[e]);
+                            acc[(5 + c) * len + at] += fabs((double)wt) * sz;
+                        }
                     }
                 }
     }

@@ -23,9 +23,11 @@ AT_OP_LAP_UPDATE, AT_OP_AXPY, AT_OP_JACOBI, AT_OP_COPY, AT_OP_FILL, AT_OP_INC = 
 AT_OP_DIFFUSE, AT_OP_DIFFUSE_ADJ, AT_OP_NORMALISE = 7, 8, 9
 AT_OP_ADVECT = 10
 AT_OP_MACCORMACK = 11
+AT_OP_MPM_GRID = 12
 AT_ACT_PER_NODE, AT_ACT_PER_BLOCK, AT_ACT_NONE = 0, 1, 2
 AT_TASK_ACTIVATE, AT_TASK_LISTGEN, AT_TASK_STENCIL, AT_TASK_ADVECT, AT_TASK_P2G, AT_TASK_G2P = 1, 2, 3, 4, 5, 6
 AT_TASK_RESTRICT, AT_TASK_PROLONG = 7, 8
+AT_TASK_P2G_MLS, AT_TASK_G2P_APIC = 9, 10
 AT_TASKF_LOOP_UNIQUE = 1
 AT_OPT_LGR, AT_OPT_AD, AT_OPT_FUSE, AT_OPT_DSE, AT_OPT_ALL = 1, 2, 4, 8, 15
 AT_PLAN_MAX_MEMBERS = 8
@@ -59,7 +61,7 @@ class AtGridInfo(ctypes.Structure):
 
 class AtTask(ctypes.Structure):
     _fields_ = [("kind", c_int32), ("op", c_int32), ("flags", c_uint32), ("reserved", c_int32),
-                ("grid", c_void_p), ("grid2", c_void_p), ("ch", c_int32 * 8), ("param", c_float * 4),
+                ("grid", c_void_p), ("grid2", c_void_p), ("ch", c_int32 * 8), ("param", c_float * 8),
                 ("ext", c_void_p * 4), ("n", c_int64)]
 
 
@@ -103,6 +105,9 @@ _SIGS = {
     "at_advect": (c_int32, [_P, _P, c_int64, c_float, _P]),
     "at_p2g": (c_int32, [_P, _P, _P, _P, c_int64, c_float, ctypes.POINTER(c_int32), c_int32, _P]),
     "at_p2g_static": (c_int32, [_P, _P, _P, _P, c_int64, c_float, ctypes.POINTER(c_int32), c_int32, _P]),
+    "at_p2g_mls": (c_int32, [_P, _P, _P, _P, _P, c_int64, c_float, c_float, c_float, c_float, c_float, c_float,
+                             ctypes.POINTER(c_int32), c_int32, _P]),
+    "at_g2p_apic": (c_int32, [_P, _P, _P, _P, c_int64, c_float, ctypes.POINTER(c_int32), _P]),
     "at_g2p": (c_int32, [_P, _P, _P, c_int64, c_float, ctypes.POINTER(c_int32), _P]),
     "at_scatter_blocks": (c_int32, [_P, c_int32, _P, _P, c_int64, _P]),
     "at_gather_blocks": (c_int32, [_P, c_int32, _P, _P, c_int64, _P]),

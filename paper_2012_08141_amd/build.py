@@ -21,10 +21,11 @@ CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__",
 
 SOURCES = {
     "kernels.hip": "hip",
+    "mpm.hip": "hip",
     "sfg.cpp": "cxx",
     "runtime.cpp": "cxx",
 }
-HEADERS = ["internal.hpp", "sfg.hpp"]
+HEADERS = ["internal.hpp", "sfg.hpp", "grid_device.hpp"]
 
 
 def _compile(name: str, kind: str, verbose: bool) -> str:

@@ -59,7 +59,8 @@ struct MicroOp {
     int32_t ch[7];    // channels, as in the public op table
     float p;          // parameter
     uint32_t keep;    // FILL: bit q keeps the store to ch[q]; NORMALISE: bit c keeps v_c
-    float p1;         // second parameter (ADVECT / MACCORMACK: 1 = RK3 back-trace)
+    float p1;         // second parameter (ADVECT / MACCORMACK: 1 = RK3 back-trace; MPM_GRID: gravity)
+    float p2;         // third parameter (MPM_GRID: wall thickness in nodes)
 };
 struct MicroProg {
     int32_t nops;
@@ -89,6 +90,28 @@ struct PartProg {
                            // of the same node updates their records first
     GridDev gbin_g;        // workspace holding the bins the gather goes through
     GridDev gbin_s;        // workspace holding the bins the scatter uses (gdst unless reusing)
+    GridDev gsrc, gdst;
+};
+
+// MLS-MPM particle program: any subset of gather (G2P_APIC), advection and
+// scatter (P2G_MLS), in that order, over the same particle arrays, as one
+// pass (the gathered v and C, and the advected x, reach the scatter in
+// registers).
+struct MpmProg {
+    uint32_t steps;        // PS_G2P | PS_ADVECT | PS_P2G
+    int32_t act_mode;      // AT_ACT_* for the scatter
+    int64_t np;
+    float *x;              // [3][np]
+    float *v;              // [3][np]
+    float *C;              // [9][np]
+    float *F;              // [9][np]
+    uint32_t keep;         // gather: bit 0 stores v, bit 1 stores C
+    float adv_dt;          // advection
+    float inv_dx_src;      // gather grid: 1 / dx
+    float inv_dx_dst;      // scatter grid: 1 / dx
+    float dt, mass, vol, mu, lam;   // scatter: F update and stress
+    int32_t ch_vsrc;       // gather: v0..v0+2 of gsrc
+    int32_t ch_m, ch_mv;   // scatter: m and mv0..mv0+2 of gdst
     GridDev gsrc, gdst;
 };
 
@@ -129,6 +152,8 @@ hipError_t launch_transfer(bool restrict_op, const GridDev &f, const GridDev &c,
 // Launches one particle task (1 dispatch, or 4 when its scatter is binned;
 // the count is stored in *dispatches).
 hipError_t launch_particles(const PartProg &prog, hipStream_t s, int *dispatches);
+// One MLS-MPM particle task (one dispatch).
+hipError_t launch_mpm(const MpmProg &prog, hipStream_t s);
 hipError_t launch_scatter_blocks(const GridDev &g, int ch, const int32_t *cells, const float *vals,
                                  int64_t n, hipStream_t s);
 hipError_t launch_gather_blocks(const GridDev &g, int ch, const int32_t *cells, float *vals,

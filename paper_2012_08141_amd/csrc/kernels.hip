@@ -19,76 +19,11 @@ namespace ats {
 namespace {
 
 constexpr int kSFThreads = 128;          // struct-for workgroup
-constexpr int kSpinLimit = 1 << 22;      // bounded wait on a pointer-root allocation
 int g_sf_grid_override = 0;
 int g_sf_kernel = 0;
 int g_batch_waves = 1;
 
-// -------------------------------------------------------------- root access
-
-__device__ __forceinline__ bool bit_set(const uint32_t *bits, int64_t c) {
-    return (bits[c >> 5] >> (c & 31)) & 1u;
-}
-
-// Slot of root cell c, or -1 when the block is inactive (no concurrent
-// activation of the same grid may be running).
-template <int KIND>
-__device__ __forceinline__ int32_t slot_of(const GridDev &g, int64_t c) {
-    if (KIND == AT_ROOT_BITMASK) return bit_set(g.bits, c) ? (int32_t)c : -1;
-    const int32_t s = g.ptr[c];
-    return s >= 0 ? s : -1;
-}
-
-// Activation on write: make root cell c active and return its slot (-1 if a
-// pointer pool is exhausted).  Inactive leaf storage is kept at zero (the
-// grid starts zeroed and leaves only become inactive through a clear that
-// zeroes them), so a newly activated block reads 0 without a fill here.
-//
-// Pointer root: the first thread to CAS the cell from NULL to LOCKED takes a
-// slot from the bump counter and publishes it; the others wait for the
-// publication.  The publish sits in an if-block that every lane of the wave
-// finishes before any lane reaches the wait loop after it, so a waiting lane
-// never blocks the lane it waits for.  The wait is bounded.
-template <int KIND>
-__device__ __forceinline__ int32_t activate_cell(const GridDev &g, int64_t c) {
-    const uint32_t m = 1u << (c & 31);
-    // A plain load may return a stale value; staleness only ever shows an
-    // active block as inactive (activity never reverts inside a kernel),
-    // which sends the thread down the atomic path below -- still correct.
-    if (KIND == AT_ROOT_BITMASK) {
-        if (!(g.bits[c >> 5] & m)) atomicOr(&g.bits[c >> 5], m);
-        return (int32_t)c;
-    }
-    int32_t s = g.ptr[c];
-    if (s == PTR_NULL) {
-        const int32_t old = atomicCAS(&g.ptr[c], PTR_NULL, PTR_LOCKED);
-        if (old == PTR_NULL) {
-            int32_t ns = atomicAdd(&g.hdr[HDR_BUMP], 1);
-            if (ns >= g.cap) {
-                atomicOr(&g.hdr[HDR_ERR], ERR_CAPACITY);
-                ns = PTR_FAILED;
-            } else {
-                atomicOr(&g.bits[c >> 5], m);
-            }
-            __hip_atomic_store(&g.ptr[c], ns, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            s = ns;
-        } else {
-            s = old;
-        }
-    }
-    for (int it = 0; s == PTR_LOCKED; ++it) {
-        if (it >= kSpinLimit) {
-            atomicOr(&g.hdr[HDR_ERR], ERR_SPIN);
-            s = PTR_FAILED;
-            break;
-        }
-        __builtin_amdgcn_s_sleep(2);
-        s = __hip_atomic_load(&g.ptr[c], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    return s >= 0 ? s : -1;
-}
-
-__device__ __forceinline__ float *chan(const GridDev &g, int c) { return g.chan + (int64_t)c * g.ch_stride; }
+#include "grid_device.hpp"
 
 // Range of list entries a workgroup walks.  Workgroups are dispatched to the
 // 8 XCDs round-robin; giving each XCD one contiguous slice of the (ascending)
@@ -106,12 +41,6 @@ __device__ __forceinline__ ListRange list_range(int count) {
     return {lo + local, hi, per};
 }
 
-__device__ __forceinline__ void cell_coords(const GridDev &g, int32_t cell, int &bi, int &bj, int &bk) {
-    bi = cell / g.R2;
-    const int r = cell - bi * g.R2;
-    bj = r / g.R;
-    bk = r - bj * g.R;
-}
 
 __device__ __forceinline__ int wave_incl_scan(int v) {
     const int lane = threadIdx.x & 63;
@@ -869,7 +798,7 @@ __global__ __launch_bounds__(64) void k_stencil_tail(GridDev g, const int32_t *_
 // block's inputs are loaded before this block's outputs are stored.
 template <int OP>
 struct Elem {
-    int32_t slot;
+    int32_t slot, cell;
     float4 a0, a1, b0, b1, c0, c1, d0, d1;   // up to 4 input rows
 };
 
@@ -878,6 +807,7 @@ __device__ __forceinline__ void fetch_elem(const GridDev &g, const int32_t *__re
                                            int e, int lane, Elem<OP> &E) {
     const int4 a = reinterpret_cast<const int4 *>(recs + (int64_t)e * kRec)[0];
     E.slot = a.y;
+    E.cell = a.x;
     const int64_t off = (int64_t)a.y * kBV + lane * 8;
     auto ld = [&](int ch, float4 &u, float4 &v) {
         const float *p = chan(g, ch) + off;
@@ -887,7 +817,7 @@ __device__ __forceinline__ void fetch_elem(const GridDev &g, const int32_t *__re
     if (OP == AT_OP_COPY) ld(op.ch[1], E.a0, E.a1);
     if (OP == AT_OP_AXPY) { ld(op.ch[0], E.a0, E.a1); ld(op.ch[1], E.b0, E.b1); }
     if (OP == AT_OP_INC) ld(op.ch[0], E.a0, E.a1);
-    if (OP == AT_OP_NORMALISE) {
+    if (OP == AT_OP_NORMALISE || OP == AT_OP_MPM_GRID) {
         ld(op.ch[0], E.a0, E.a1);
         ld(op.ch[1], E.b0, E.b1);
         ld(op.ch[1] + 1, E.c0, E.c1);
@@ -896,6 +826,29 @@ __device__ __forceinline__ void fetch_elem(const GridDev &g, const int32_t *__re
 }
 
 __device__ __forceinline__ float4 f4(float a, float b, float c, float d) { return make_float4(a, b, c, d); }
+
+// MLS-MPM grid update of one voxel (I, J, K) of an n^3 domain: velocity from
+// momentum where there is mass, gravity along -z (op.p = dt, op.p1 = g), and
+// the walls op.p2 nodes thick on every side (AT_OP_MPM_GRID).
+__device__ __forceinline__ void mpm_grid_voxel(const MicroOp &op, int n, int I, int J, int K, float m, float mv0,
+                                               float mv1, float mv2, float &v0, float &v1, float &v2) {
+    v0 = 0.f;
+    v1 = 0.f;
+    v2 = 0.f;
+    if (m > 0.f) {
+        v0 = mv0 / m;
+        v1 = mv1 / m;
+        v2 = mv2 / m;
+        v2 = v2 - op.p * op.p1;
+        const int bound = (int)op.p2;
+        if (I < bound && v0 < 0.f) v0 = 0.f;
+        if (I > n - bound && v0 > 0.f) v0 = 0.f;
+        if (J < bound && v1 < 0.f) v1 = 0.f;
+        if (J > n - bound && v1 > 0.f) v1 = 0.f;
+        if (K < bound && v2 < 0.f) v2 = 0.f;
+        if (K > n - bound && v2 > 0.f) v2 = 0.f;
+    }
+}
 
 template <int OP, int KIND, bool CHECK>
 __global__ __launch_bounds__(64) void k_elem(GridDev g, const int32_t *__restrict__ recs, MicroOp op) {
@@ -948,6 +901,20 @@ __global__ __launch_bounds__(64) void k_elem(GridDev g, const int32_t *__restric
                 for (int q = 0; q < 8; ++q) r[q] = m[q] > 0.f ? mv[cc][q] / m[q] : 0.f;
                 st(op.ch[2] + cc, f4(r[0], r[1], r[2], r[3]), f4(r[4], r[5], r[6], r[7]));
             }
+        } else if (OP == AT_OP_MPM_GRID) {
+            float m[8], mv[3][8], r[3][8];
+            put8(m, cur.a0, cur.a1);
+            put8(mv[0], cur.b0, cur.b1);
+            put8(mv[1], cur.c0, cur.c1);
+            put8(mv[2], cur.d0, cur.d1);
+            int bi, bj, bk;
+            cell_coords(g, cur.cell, bi, bj, bk);
+            const int I[2] = {bi * kBS + (lane >> 3), bj * kBS + (lane & 7)};
+#pragma unroll
+            for (int q = 0; q < 8; ++q) mpm_grid_voxel(op, g.R * kBS, I[0], I[1], bk * kBS + q, m[q], mv[0][q],
+                                                       mv[1][q], mv[2][q], r[0][q], r[1][q], r[2][q]);
+            for (int cc = 0; cc < 3; ++cc)
+                st(op.ch[2] + cc, f4(r[cc][0], r[cc][1], r[cc][2], r[cc][3]), f4(r[cc][4], r[cc][5], r[cc][6], r[cc][7]));
         }
         cur = nxt;
     }
@@ -1113,6 +1080,24 @@ __global__ __launch_bounds__(64) void k_micro(GridDev g, MicroProg prog) {
                         for (int q = 0; q < 4; ++q) r[q] = mm[q] > 0.f ? mvv[q] / mm[q] : 0.f;
                         *reinterpret_cast<float4 *>(chan(g, op.ch[2] + cc) + off) = make_float4(r[0], r[1], r[2], r[3]);
                     }
+                    break;
+                }
+                case AT_OP_MPM_GRID: {
+                    const float4 m = *reinterpret_cast<const float4 *>(chan(g, op.ch[0]) + off);
+                    const float4 a = *reinterpret_cast<const float4 *>(chan(g, op.ch[1]) + off);
+                    const float4 b = *reinterpret_cast<const float4 *>(chan(g, op.ch[1] + 1) + off);
+                    const float4 c = *reinterpret_cast<const float4 *>(chan(g, op.ch[1] + 2) + off);
+                    const float mm[4] = {m.x, m.y, m.z, m.w}, m0[4] = {a.x, a.y, a.z, a.w},
+                                m1[4] = {b.x, b.y, b.z, b.w}, m2[4] = {c.x, c.y, c.z, c.w};
+                    int bi, bj, bk;
+                    cell_coords(g, cell, bi, bj, bk);
+                    float r[3][4];
+                    for (int q = 0; q < 4; ++q)
+                        mpm_grid_voxel(op, g.R * kBS, bi * kBS + li, bj * kBS + lj, bk * kBS + k0 + q, mm[q], m0[q],
+                                       m1[q], m2[q], r[0][q], r[1][q], r[2][q]);
+                    for (int cc = 0; cc < 3; ++cc)
+                        *reinterpret_cast<float4 *>(chan(g, op.ch[2] + cc) + off) =
+                            make_float4(r[cc][0], r[cc][1], r[cc][2], r[cc][3]);
                     break;
                 }
                 case AT_OP_ADVECT: {
@@ -2333,6 +2318,9 @@ static bool launch_elem_k(const GridDev &g, const MicroOp &op, dim3 grid, hipStr
     case AT_OP_FILL: hipLaunchKernelGGL((k_elem<AT_OP_FILL, KIND, CHECK>), grid, dim3(64), 0, s, g, recs, op); return true;
     case AT_OP_NORMALISE:
         hipLaunchKernelGGL((k_elem<AT_OP_NORMALISE, KIND, CHECK>), grid, dim3(64), 0, s, g, recs, op);
+        return true;
+    case AT_OP_MPM_GRID:
+        hipLaunchKernelGGL((k_elem<AT_OP_MPM_GRID, KIND, CHECK>), grid, dim3(64), 0, s, g, recs, op);
         return true;
     default: return false;
     }

@@ -200,6 +200,7 @@ at_status execute_node(const Node &nd, const at_task *tasks, bool table, hipStre
                 op.p = t.param[0];
                 op.keep = nd.members[q].keep;
                 op.p1 = t.param[1];
+                op.p2 = t.param[2];
             }
             e = launch_stencil_tail(g->dev, t0.op, t0.ch, t0.param[0], prog, s);
         } else {
@@ -215,6 +216,7 @@ at_status execute_node(const Node &nd, const at_task *tasks, bool table, hipStre
                 op.p = t.param[0];
                 op.keep = nd.members[q].keep;
                 op.p1 = t.param[1];
+                op.p2 = t.param[2];
             }
             e = launch_micro(g->dev, prog, s);
         }
@@ -230,7 +232,53 @@ at_status execute_node(const Node &nd, const at_task *tasks, bool table, hipStre
     }
     case AT_TASK_ADVECT:
     case AT_TASK_P2G:
-    case AT_TASK_G2P: {
+    case AT_TASK_G2P:
+    case AT_TASK_P2G_MLS:
+    case AT_TASK_G2P_APIC: {
+        bool mpm = false;
+        for (const Member &m : nd.members) {
+            const int k = tasks[m.task].kind;
+            mpm |= k == AT_TASK_P2G_MLS || k == AT_TASK_G2P_APIC;
+        }
+        if (mpm) {
+            MpmProg mp{};
+            mp.act_mode = nd.act_mode;
+            mp.np = t0.n;
+            mp.keep = 3u;
+            for (const Member &m : nd.members) {
+                const at_task &t = tasks[m.task];
+                mp.x = (float *)t.ext[0];
+                mp.v = (float *)t.ext[1];
+                if (t.kind == AT_TASK_G2P_APIC) {
+                    mp.steps |= PS_G2P;
+                    mp.C = (float *)t.ext[2];
+                    mp.keep = m.keep & 3u;
+                    mp.gsrc = task_grid(t)->dev;
+                    mp.inv_dx_src = (float)(1.0 / (double)t.param[0]);
+                    mp.ch_vsrc = t.ch[0];
+                } else if (t.kind == AT_TASK_ADVECT) {
+                    mp.steps |= PS_ADVECT;
+                    mp.adv_dt = t.param[0];
+                } else {
+                    mp.steps |= PS_P2G;
+                    mp.C = (float *)t.ext[2];
+                    mp.F = (float *)t.ext[3];
+                    mp.gdst = task_grid(t)->dev;
+                    mp.inv_dx_dst = (float)(1.0 / (double)t.param[0]);
+                    mp.dt = t.param[1];
+                    mp.mass = t.param[2];
+                    mp.vol = t.param[3];
+                    mp.mu = t.param[4];
+                    mp.lam = t.param[5];
+                    mp.ch_m = t.ch[0];
+                    mp.ch_mv = t.ch[1];
+                }
+            }
+            if (mp.np == 0) return AT_OK;
+            if (mp.steps & PS_ADVECT) E().pos_writes[mp.x] += 1;
+            e = launch_mpm(mp, s);
+            break;
+        }
         PartProg pp{};
         pp.act_mode = nd.act_mode;
         pp.np = t0.n;
@@ -794,10 +842,13 @@ at_status at_run_stencil(at_grid grid, int32_t op, const int32_t *ch, const floa
     } else {
         const int nc = op == AT_OP_LAP_UPDATE || op == AT_OP_AXPY || op == AT_OP_COPY ? 2
                      : op == AT_OP_INC ? 1 : op == AT_OP_DIFFUSE_ADJ || op == AT_OP_MACCORMACK ? 5 : 3;
-        if (op < AT_OP_LAP_UPDATE || op > AT_OP_MACCORMACK) return fail(AT_E_INVALID, "unknown op %d", op);
+        if (op < AT_OP_LAP_UPDATE || op > AT_OP_MPM_GRID) return fail(AT_E_INVALID, "unknown op %d", op);
         for (int q = 0; q < nc; ++q) t.ch[q] = ch[q];
     }
-    if (params) t.param[0] = params[0];
+    if (params) {
+        const int np = op == AT_OP_ADVECT || op == AT_OP_MACCORMACK ? 2 : op == AT_OP_MPM_GRID ? 3 : 1;
+        for (int q = 0; q < np; ++q) t.param[q] = params[q];
+    }
     Engine &en = E();
     std::lock_guard<std::recursive_mutex> lk(en.mu);
     if (check_activation) return run_one(t, stream);
@@ -871,6 +922,43 @@ at_status at_p2g_static(at_grid grid, const float *d_x, const float *d_v, const 
     st = run_window(&t, 1, 0, nullptr, stream);
     en.static_ws = false;
     return st;
+}
+
+at_status at_p2g_mls(at_grid grid, const float *d_x, const float *d_v, const float *d_C, float *d_F, int64_t np,
+                     float dx, float dt, float mass, float vol, float mu, float lambda, const int32_t *ch,
+                     int32_t activation, hipStream_t stream) {
+    at_status st = check_grid(grid, true);
+    if (st != AT_OK) return st;
+    if (!ch) return fail(AT_E_INVALID, "null channel array");
+    at_task t = blank_task(AT_TASK_P2G_MLS, grid);
+    t.op = activation;
+    t.ext[0] = (void *)d_x;
+    t.ext[1] = (void *)d_v;
+    t.ext[2] = (void *)d_C;
+    t.ext[3] = d_F;
+    t.n = np;
+    const float prm[6] = {dx, dt, mass, vol, mu, lambda};
+    for (int q = 0; q < 6; ++q) t.param[q] = prm[q];
+    t.ch[0] = ch[0];
+    t.ch[1] = ch[1];
+    t.flags = AT_TASKF_LOOP_UNIQUE;
+    return run_one(t, stream);
+}
+
+at_status at_g2p_apic(at_grid grid, const float *d_x, float *d_v, float *d_C, int64_t np, float dx, const int32_t *ch,
+                      hipStream_t stream) {
+    at_status st = check_grid(grid, true);
+    if (st != AT_OK) return st;
+    if (!ch) return fail(AT_E_INVALID, "null channel array");
+    at_task t = blank_task(AT_TASK_G2P_APIC, grid);
+    t.ext[0] = (void *)d_x;
+    t.ext[1] = d_v;
+    t.ext[2] = d_C;
+    t.n = np;
+    t.param[0] = dx;
+    t.ch[0] = ch[0];
+    t.flags = AT_TASKF_LOOP_UNIQUE;
+    return run_one(t, stream);
 }
 
 at_status at_g2p(at_grid grid, const float *d_x, float *d_v, int64_t np, float dx, const int32_t *ch,

@@ -23,7 +23,12 @@ inline StateKey LIST(uint64_t g) { return {g, -1, ST_LIST}; }
 inline StateKey ALLOC(uint64_t g) { return {g, -1, ST_ALLOC}; }
 inline StateKey EXT(const void *p) { return {(uint64_t)(uintptr_t)p, -1, ST_EXT}; }
 
-bool is_particle_kind(int k) { return k == AT_TASK_ADVECT || k == AT_TASK_P2G || k == AT_TASK_G2P; }
+bool is_particle_kind(int k) {
+    return k == AT_TASK_ADVECT || k == AT_TASK_P2G || k == AT_TASK_G2P || k == AT_TASK_P2G_MLS ||
+           k == AT_TASK_G2P_APIC;
+}
+bool is_mpm_kind(int k) { return k == AT_TASK_P2G_MLS || k == AT_TASK_G2P_APIC; }
+bool is_scatter_kind(int k) { return k == AT_TASK_P2G || k == AT_TASK_P2G_MLS; }
 
 bool is_tiled_stencil(int op) {
     return op == AT_OP_LAP_UPDATE || op == AT_OP_JACOBI || op == AT_OP_DIFFUSE || op == AT_OP_DIFFUSE_ADJ;
@@ -42,6 +47,7 @@ int op_nch(int op) {
     case AT_OP_NORMALISE: return 3;
     case AT_OP_ADVECT: return 3;
     case AT_OP_MACCORMACK: return 5;
+    case AT_OP_MPM_GRID: return 3;
     default: return -1;
     }
 }
@@ -111,6 +117,11 @@ void member_accesses(const at_task &t, const Member &mb, bool check, int16_t mi,
             for (int q = 0; q < 3; ++q)
                 if ((mb.keep >> q) & 1u) wr(c[2] + q, true, false);
             break;
+        case AT_OP_MPM_GRID:
+            rd(c[0], false);
+            for (int q = 0; q < 3; ++q) rd(c[1] + q, false);
+            for (int q = 0; q < 3; ++q) wr(c[2] + q, true, false);
+            break;
         default: break;
         }
         if (stencil_read) add(MASK(gu), M_R, P_STENCIL, 0);
@@ -149,6 +160,33 @@ void member_accesses(const at_task &t, const Member &mb, bool check, int16_t mi,
         for (int q = 0; q < 3; ++q) add(VAL(gu, t.ch[0] + q), M_R, P_GATHER, 0);
         add(MASK(gu), M_R, P_GATHER, 0);
         add(EXT(t.ext[1]), M_W, P_ELEM, u | F_FULL);
+        break;
+    }
+    case AT_TASK_P2G_MLS: {
+        const uint8_t u = (t.flags & AT_TASKF_LOOP_UNIQUE) ? U : 0;
+        add(EXT(t.ext[0]), M_R, P_ELEM, u);
+        add(EXT(t.ext[1]), M_R, P_ELEM, u);
+        add(EXT(t.ext[2]), M_R, P_ELEM, u);
+        add(EXT(t.ext[3]), M_R | M_W, P_ELEM, u);
+        add(VAL(gu, t.ch[0]), M_R | M_W, P_SCATTER, 0);
+        for (int q = 0; q < 3; ++q) add(VAL(gu, t.ch[1] + q), M_R | M_W, P_SCATTER, 0);
+        if (t.op == AT_ACT_NONE) {
+            add(MASK(gu), M_R, P_GATHER, 0);
+        } else {
+            add(MASK(gu), M_R | M_W, P_SCATTER, F_ACTIVATING);
+            if (ptr_root) add(ALLOC(gu), M_R | M_W, P_SCATTER, F_ACTIVATING);
+        }
+        break;
+    }
+    case AT_TASK_G2P_APIC: {
+        // keep bit 0: the store of v; bit 1: the store of C (dead store
+        // elimination clears them; the gather itself always runs)
+        const uint8_t u = (t.flags & AT_TASKF_LOOP_UNIQUE) ? U : 0;
+        add(EXT(t.ext[0]), M_R, P_ELEM, u);
+        for (int q = 0; q < 3; ++q) add(VAL(gu, t.ch[0] + q), M_R, P_GATHER, 0);
+        add(MASK(gu), M_R, P_GATHER, 0);
+        if (mb.keep & 1u) add(EXT(t.ext[1]), M_W, P_ELEM, u | F_FULL);
+        if (mb.keep & 2u) add(EXT(t.ext[2]), M_W, P_ELEM, u | F_FULL);
         break;
     }
     case AT_TASK_RESTRICT: {
@@ -341,8 +379,8 @@ std::string validate_task(const at_task &t) {
     if (t.reserved != 0 || (t.grid2 != nullptr && !two_level)) return "reserved task fields must be zero";
     const at_grid_s *g = task_grid(t);
     const bool needs_grid = t.kind == AT_TASK_ACTIVATE || t.kind == AT_TASK_LISTGEN || t.kind == AT_TASK_STENCIL ||
-                            t.kind == AT_TASK_P2G || t.kind == AT_TASK_G2P || two_level;
-    if (t.kind < AT_TASK_ACTIVATE || t.kind > AT_TASK_PROLONG) return "unknown task kind";
+                            t.kind == AT_TASK_P2G || t.kind == AT_TASK_G2P || two_level || is_mpm_kind(t.kind);
+    if (t.kind < AT_TASK_ACTIVATE || t.kind > AT_TASK_G2P_APIC) return "unknown task kind";
     if (needs_grid && !g) return "task needs a grid";
     auto chan_ok = [&](int c, int span) { return g && c >= 0 && c + span <= g->desc.channels; };
     switch (t.kind) {
@@ -376,6 +414,11 @@ std::string validate_task(const at_task &t) {
             const int o = t.ch[4];
             if (o == t.ch[0] || o == t.ch[2] || o == t.ch[3] || (o >= t.ch[1] && o < t.ch[1] + 3))
                 return "maccormack: the output aliases an input";
+        } else if (t.op == AT_OP_MPM_GRID) {
+            if (!chan_ok(t.ch[0], 1) || !chan_ok(t.ch[1], 3) || !chan_ok(t.ch[2], 3)) return "mpm_grid: channel out of range";
+            if ((t.ch[0] >= t.ch[2] && t.ch[0] < t.ch[2] + 3) || (t.ch[2] > t.ch[1] - 3 && t.ch[2] < t.ch[1] + 3))
+                return "mpm_grid: the velocity channels overlap the mass or momentum channels";
+            if (!(t.param[2] >= 0.f) || t.param[2] != (float)(int)t.param[2]) return "mpm_grid: bound must be a whole number >= 0";
         } else if (t.op == AT_OP_NORMALISE) {
             if (!chan_ok(t.ch[0], 1) || !chan_ok(t.ch[1], 3) || !chan_ok(t.ch[2], 3)) return "normalise: channel out of range";
             // v may replace mv in place (each component reads its own mv before writing);
@@ -408,6 +451,19 @@ std::string validate_task(const at_task &t) {
         if (!chan_ok(t.ch[0], 3)) return "g2p: channel out of range";
         if (!(t.param[0] > 0.f)) return "g2p: dx must be positive";
         break;
+    case AT_TASK_P2G_MLS:
+        if (t.n < 0 || (t.n > 0 && (!t.ext[0] || !t.ext[1] || !t.ext[2] || !t.ext[3]))) return "p2g_mls: bad arrays";
+        if (!chan_ok(t.ch[0], 1) || !chan_ok(t.ch[1], 3)) return "p2g_mls: channel out of range";
+        if (!(t.param[0] > 0.f)) return "p2g_mls: dx must be positive";
+        if (t.op != AT_ACT_PER_NODE && t.op != AT_ACT_PER_BLOCK && t.op != AT_ACT_NONE)
+            return "p2g_mls: bad activation mode";
+        break;
+    case AT_TASK_G2P_APIC:
+        if (t.n < 0 || (t.n > 0 && (!t.ext[0] || !t.ext[1] || !t.ext[2]))) return "g2p_apic: bad arrays";
+        if (t.ext[1] == t.ext[2] || t.ext[0] == t.ext[1] || t.ext[0] == t.ext[2]) return "g2p_apic: arrays alias";
+        if (!chan_ok(t.ch[0], 3)) return "g2p_apic: channel out of range";
+        if (!(t.param[0] > 0.f)) return "g2p_apic: dx must be positive";
+        break;
     case AT_TASK_RESTRICT:
     case AT_TASK_PROLONG: {
         const at_grid_s *c = reinterpret_cast<const at_grid_s *>(t.grid2);
@@ -439,6 +495,37 @@ void derive(Node &nd, const at_task *tasks) {
     nd.acc.clear();
     for (size_t m = 0; m < nd.members.size(); ++m)
         member_accesses(tasks[nd.members[m].task], nd.members[m], nd.check_activation, (int16_t)m, nd.acc);
+    // A fused MLS-MPM node runs as one pass over the particles: what a member
+    // produces at the loop index (the gather's v and C, stored or not, and the
+    // advected x) reaches the later members in registers.  Their reads of
+    // those arrays are internal to the node and leave its access list.
+    bool mpm = false;
+    for (const Member &mb : nd.members) mpm |= is_mpm_kind(tasks[mb.task].kind);
+    if (!mpm || nd.members.size() < 2) return;
+    std::vector<std::pair<StateKey, int>> produced;   // array, producing member
+    for (size_t m = 0; m < nd.members.size(); ++m) {
+        const at_task &t = tasks[nd.members[m].task];
+        if (t.kind == AT_TASK_G2P_APIC) {
+            produced.push_back({EXT(t.ext[1]), (int)m});
+            produced.push_back({EXT(t.ext[2]), (int)m});
+        } else if (t.kind == AT_TASK_ADVECT) {
+            produced.push_back({EXT(t.ext[0]), (int)m});
+        }
+    }
+    std::vector<Access> kept;
+    kept.reserve(nd.acc.size());
+    for (Access a : nd.acc) {
+        if ((a.mode & M_R) && a.s.kind == ST_EXT && a.pattern == P_ELEM && (a.flags & F_UNIQUE)) {
+            bool internal = false;
+            for (const auto &pr : produced) internal |= pr.first == a.s && pr.second < a.member;
+            if (internal) {
+                a.mode &= (uint8_t)~M_R;
+                if (!a.mode) continue;
+            }
+        }
+        kept.push_back(a);
+    }
+    nd.acc.swap(kept);
 }
 
 uint64_t hash_window(const at_task *tasks, int n, uint32_t flags, int max_fuse) {
@@ -454,7 +541,7 @@ uint64_t hash_window(const at_task *tasks, int n, uint32_t flags, int max_fuse) 
         const at_grid_s *g2 = reinterpret_cast<const at_grid_s *>(t.grid2);
         h = mix(h, g2 ? g2->uid : 0);
         for (int q = 0; q < 8; ++q) h = mix(h, (uint64_t)(uint32_t)t.ch[q]);
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < 8; ++q) {
             uint32_t b;
             std::memcpy(&b, &t.param[q], 4);
             h = mix(h, b);
@@ -477,7 +564,7 @@ void Planner::build_eager() {
         Node nd;
         nd.members.push_back({i, ~0u});
         nd.check_activation = true;
-        nd.act_mode = tasks_[i].kind == AT_TASK_P2G ? tasks_[i].op : AT_ACT_PER_NODE;
+        nd.act_mode = is_scatter_kind(tasks_[i].kind) ? tasks_[i].op : AT_ACT_PER_NODE;
         derive(nd, tasks_);
         nodes.push_back(std::move(nd));
     }
@@ -504,7 +591,8 @@ bool Planner::pass_ad(const Persist &start) {
             derive(nd, tasks_);
             changed = true;
         }
-        if (nd.act_mode == AT_ACT_PER_NODE && node_has_kind(nd, tasks_, AT_TASK_P2G)) {
+        if (nd.act_mode == AT_ACT_PER_NODE &&
+            (node_has_kind(nd, tasks_, AT_TASK_P2G) || node_has_kind(nd, tasks_, AT_TASK_P2G_MLS))) {
             nd.act_mode = AT_ACT_PER_BLOCK;
             counters.activations_demoted += 1;
             changed = true;
@@ -689,6 +777,19 @@ bool Planner::pass_dse(const Persist &start) {
             bool any = false;
             for (int q = 0; q < 7; ++q) any |= t.ch[q] >= 0 && ((mb.keep >> q) & 1u);
             if (!any) mb.task = -1;
+        } else if (t.kind == AT_TASK_G2P_APIC) {
+            // the stores of v (keep bit 0) and C (bit 1) are dropped one by
+            // one; the gather stays while a later member of its node uses
+            // its results in registers
+            for (int q = 0; q < 2; ++q) {
+                const StateKey sk = EXT(t.ext[1 + q]);
+                if (((mb.keep >> q) & 1u) && std::find(dead[p].begin(), dead[p].end(), sk) != dead[p].end()) {
+                    mb.keep &= ~(1u << q);
+                    counters.stores_eliminated += 1;
+                    changed = true;
+                }
+            }
+            if ((mb.keep & 3u) == 0 && ops[p].member == (int)nd.members.size() - 1) mb.task = -1;
         } else if (t.kind == AT_TASK_STENCIL && t.op == AT_OP_NORMALISE) {
             for (int q = 0; q < 3; ++q)
                 if (((mb.keep >> q) & 1u) && is_dead_ch(t.ch[2] + q)) {
@@ -739,19 +840,31 @@ bool executable_pair(const Node &A, const Node &B, const at_task *tasks) {
         return true;
     }
     if (A.loop == LT_RANGE) {
-        int rank_prev = -1;
-        const void *x = nullptr, *v = nullptr;
+        // PIC members (G2P, P2G) and MLS-MPM members (G2P_APIC, P2G_MLS,
+        // sharing C as well) do not mix; ADVECT joins either
+        int rank_prev = -1, family = 0;
+        const void *x = nullptr, *v = nullptr, *C = nullptr;
         for (const Node *N : {&A, &B})
             for (const Member &m : N->members) {
                 const at_task &t = tasks[m.task];
                 if (!is_particle_kind(t.kind) || !(t.flags & AT_TASKF_LOOP_UNIQUE)) return false;
-                const int rank = t.kind == AT_TASK_G2P ? 0 : t.kind == AT_TASK_ADVECT ? 1 : 2;
+                const int rank = (t.kind == AT_TASK_G2P || t.kind == AT_TASK_G2P_APIC) ? 0
+                               : t.kind == AT_TASK_ADVECT ? 1 : 2;
                 if (rank <= rank_prev) return false;
                 rank_prev = rank;
+                if (t.kind != AT_TASK_ADVECT) {
+                    const int fam = is_mpm_kind(t.kind) ? 2 : 1;
+                    if (family && fam != family) return false;
+                    family = fam;
+                }
                 const void *tx = t.ext[0], *tv = t.ext[1];
                 if ((x && tx != x) || (v && tv != v)) return false;
                 x = tx;
                 v = tv;
+                if (is_mpm_kind(t.kind)) {
+                    if (C && t.ext[2] != C) return false;
+                    C = t.ext[2];
+                }
             }
         return true;
     }
@@ -848,7 +961,8 @@ bool Planner::pass_fuse_round(const Persist &start) {
                 const int fb = partner[i];
                 Node AB = nodes[i];
                 for (const Member &m : nodes[fb].members) AB.members.push_back(m);
-                if (node_has_kind(nodes[fb], tasks_, AT_TASK_P2G)) AB.act_mode = nodes[fb].act_mode;
+                if (node_has_kind(nodes[fb], tasks_, AT_TASK_P2G) || node_has_kind(nodes[fb], tasks_, AT_TASK_P2G_MLS))
+                    AB.act_mode = nodes[fb].act_mode;
                 derive(AB, tasks_);
                 pool.push_back(std::move(AB));
                 fcnt.push_back(std::max(fused[i], fused[fb]) + 1);
@@ -995,10 +1109,16 @@ std::vector<uint8_t> Planner::fingerprint(const at_task *tasks, int n, const Per
             auto ev = extv.find(key);
             extv[key] = (ev != extv.end() ? ev->second : p.ver(EXT(t.ext[0]))) + 1;
         }
-        if (t.kind == AT_TASK_G2P) {
+        if (t.kind == AT_TASK_G2P || t.kind == AT_TASK_G2P_APIC) {
             const uint64_t key = (uint64_t)(uintptr_t)t.ext[1];
             auto ev = extv.find(key);
             extv[key] = (ev != extv.end() ? ev->second : p.ver(EXT(t.ext[1]))) + 1;
+        }
+        if (t.kind == AT_TASK_G2P_APIC || t.kind == AT_TASK_P2G_MLS) {
+            void *w = t.kind == AT_TASK_G2P_APIC ? t.ext[2] : t.ext[3];
+            const uint64_t key = (uint64_t)(uintptr_t)w;
+            auto ev = extv.find(key);
+            extv[key] = (ev != extv.end() ? ev->second : p.ver(EXT(w))) + 1;
         }
     }
     return fp;

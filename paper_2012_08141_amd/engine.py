@@ -18,11 +18,12 @@ OPT_LGR, OPT_AD, OPT_FUSE, OPT_DSE, OPT_ALL = L.AT_OPT_LGR, L.AT_OPT_AD, L.AT_OP
 
 KIND_NAMES = {L.AT_TASK_ACTIVATE: "activate", L.AT_TASK_LISTGEN: "listgen", L.AT_TASK_STENCIL: "struct_for",
               L.AT_TASK_ADVECT: "advect", L.AT_TASK_P2G: "p2g", L.AT_TASK_G2P: "g2p",
-              L.AT_TASK_RESTRICT: "restrict", L.AT_TASK_PROLONG: "prolong"}
+              L.AT_TASK_RESTRICT: "restrict", L.AT_TASK_PROLONG: "prolong", L.AT_TASK_P2G_MLS: "p2g_mls",
+              L.AT_TASK_G2P_APIC: "g2p_apic"}
 OP_NAMES = {L.AT_OP_LAP_UPDATE: "lap_update", L.AT_OP_AXPY: "axpy", L.AT_OP_JACOBI: "jacobi",
             L.AT_OP_COPY: "copy", L.AT_OP_FILL: "fill", L.AT_OP_INC: "inc", L.AT_OP_DIFFUSE: "diffuse",
             L.AT_OP_DIFFUSE_ADJ: "diffuse_adj", L.AT_OP_NORMALISE: "normalise", L.AT_OP_ADVECT: "advect_sl",
-            L.AT_OP_MACCORMACK: "maccormack"}
+            L.AT_OP_MACCORMACK: "maccormack", L.AT_OP_MPM_GRID: "mpm_grid"}
 
 
 @dataclass
@@ -126,6 +127,15 @@ def maccormack(grid, q, v0, fwd, bwd, out, dt, rk3=False):
     return T
 
 
+def mpm_grid(grid, m, mv0, v0, dt, gravity, bound):
+    """MLS-MPM grid update: v = mv / m where m > 0, gravity along -z, walls
+    ``bound`` nodes thick."""
+    T = struct_for(grid, L.AT_OP_MPM_GRID, [m, mv0, v0], dt)
+    T.c.param[1] = gravity
+    T.c.param[2] = float(bound)
+    return T
+
+
 # ---- two-level transfers (struct-fors over the fine grid) ----------------------
 def restrict(fine, coarse, src, dst, weight) -> Task:
     """coarse[dst][I/2] += weight * fine[src][I] over the fine grid's list,
@@ -177,6 +187,33 @@ def g2p(grid, x, v, dx, ch_v, unique=True) -> Task:
     T.c.ch[0] = ch_v
     T.c.flags = L.AT_TASKF_LOOP_UNIQUE if unique else 0
     T.keep += [x, v]
+    return T
+
+
+def p2g_mls(grid, x, v, C, F, dx, dt, mass, vol, mu, lam, ch_m, ch_mv, activation=L.AT_ACT_PER_NODE,
+            unique=True) -> Task:
+    """MLS-MPM scatter: F <- (I + dt C) F, fixed-corotated stress, mass and
+    APIC momentum onto the grid (activating)."""
+    T = _task(L.AT_TASK_P2G_MLS, grid, activation)
+    T.c.ext[0], T.c.ext[1], T.c.ext[2], T.c.ext[3] = _ptr(x), _ptr(v), _ptr(C), _ptr(F)
+    T.c.n = x.shape[-1]
+    for q, val in enumerate((dx, dt, mass, vol, mu, lam)):
+        T.c.param[q] = val
+    T.c.ch[0], T.c.ch[1] = ch_m, ch_mv
+    T.c.flags = L.AT_TASKF_LOOP_UNIQUE if unique else 0
+    T.keep += [x, v, C, F]
+    return T
+
+
+def g2p_apic(grid, x, v, C, dx, ch_v, unique=True) -> Task:
+    """MLS-MPM gather of v and the APIC affine matrix C."""
+    T = _task(L.AT_TASK_G2P_APIC, grid)
+    T.c.ext[0], T.c.ext[1], T.c.ext[2] = _ptr(x), _ptr(v), _ptr(C)
+    T.c.n = x.shape[-1]
+    T.c.param[0] = dx
+    T.c.ch[0] = ch_v
+    T.c.flags = L.AT_TASKF_LOOP_UNIQUE if unique else 0
+    T.keep += [x, v, C]
     return T
 
 

@@ -172,3 +172,32 @@ def maccormack_step(g: SparseGrid, dt: float, rk3: bool = False):
                   E.listgen(g), E.maccormack(g, q, MAC["v"], f, b, o, dt, rk3),
                   E.listgen(g), E.copy(g, q, o)]
     return tasks
+
+
+# ----------------------------------------------------------- MLS-MPM workload
+MPM = {"m": 0, "mv": 1, "v": 4}            # m; mv0..2; v0..2  (7 channels)
+
+
+def mpm_grids(w: inputs.MpmWorkload, stream=None):
+    """The two grids the substeps alternate between (Section 8.3: two grids,
+    swapped before each substep), empty."""
+    cap = (w.n // 8) ** 3 if w.root_kind == "pointer" else 0
+    return [SparseGrid(w.n, 7, w.root_kind, cap, stream=stream) for _ in range(2)]
+
+
+def device_mpm(w: inputs.MpmWorkload):
+    """x, v, C, F as contiguous device arrays."""
+    return tuple(torch.as_tensor(a, device="cuda").contiguous() for a in (w.x, w.v, w.C, w.F))
+
+
+def mpm_step(grids, t: int, x, v, C, F, params: dict):
+    """Substep t on grid G = grids[t % 2]: listgen(G) -> fill(G: m, mv = 0) ->
+    p2g_mls(G) (F updated, activating) -> listgen(G) -> mpm_grid(G) (v,
+    gravity, walls) -> g2p_apic(G) (v and C) -> advect (x += dt v)."""
+    G = grids[t % 2]
+    p = params
+    dt, dx = p["dt"], p["dx"]
+    return [E.listgen(G), E.fill(G, [MPM["m"], MPM["mv"], MPM["mv"] + 1, MPM["mv"] + 2], 0.0),
+            E.p2g_mls(G, x, v, C, F, dx, dt, p["mass"], p["vol"], p["mu"], p["lam"], MPM["m"], MPM["mv"]),
+            E.listgen(G), E.mpm_grid(G, MPM["m"], MPM["mv"], MPM["v"], dt, p["gravity"], p["bound"]),
+            E.g2p_apic(G, x, v, C, dx, MPM["v"]), E.advect(x, v, dt)]

@@ -30,8 +30,8 @@ def test_constants_match_header():
 
 
 def test_struct_layouts():
-    # at_task: 4 int32, 2 pointers, 8 int32, 4 float, 4 pointers, int64
-    assert ctypes.sizeof(L.AtTask) == 16 + 16 + 32 + 16 + 32 + 8
+    # at_task: 4 int32, 2 pointers, 8 int32, 8 float, 4 pointers, int64
+    assert ctypes.sizeof(L.AtTask) == 16 + 16 + 32 + 32 + 32 + 8
     assert ctypes.sizeof(L.AtStats) == 8 * 9
     assert ctypes.sizeof(L.AtGridDesc) == 28
 
