@@ -14,8 +14,9 @@ included) bracketed by device synchronisation.
 Other workloads (--workload): shell (64^3 activate/lap_update/axpy),
 particles (2M-particle PIC), serving (256 Poisson-arriving 128^3 Jacobi
 requests, continuous batching), diffusion (128^3 forward + adjoint) and
-multigrid (V-cycles over a 256^3 band and its coarse levels) and advection
-(three scalar fields on a 256^3 tube).
+multigrid (V-cycles over a 256^3 band and its coarse levels), advection
+(three scalar fields on a 256^3 tube) and mpm (the MLS-MPM falling cube,
+16.7M particles on a 256^3 grid).
 
 Prints one JSON line.
 """
@@ -32,6 +33,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3      # MI355X dense fp32 vector peak
+
+# Algorithmic fp32 operations of one MLS-MPM particle-substep (gather of v
+# and C over 27 nodes, advection, F update, polar decomposition by two Newton
+# iterations, fixed-corotated stress, scatter of mass and APIC momentum over
+# 27 nodes); the count is derived term by term in the design notes.
+MPM_FLOPS_PER_PARTICLE = 2034
 
 # HBM bytes per launch of the Jacobi stencil on band512 (seed 0), from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE), each scaled by the reading
@@ -407,6 +415,95 @@ def bench_particles(args, torch):
     return out
 
 
+# ------------------------------------------------------------------------ mpm
+def bench_mpm(args, torch):
+    """The paper's MLS-MPM falling cube (256^3 grid, 16,777,216 particles):
+    a step is one substep (listgen, fill, p2g_mls, listgen, mpm_grid,
+    g2p_apic, advect; optimized: the G2P2G node with the stores of v and C
+    dropped)."""
+    import gc
+    from paper_2012_08141_amd import _lib as L
+    from paper_2012_08141_amd import engine as E
+    from paper_2012_08141_amd import inputs, programs as PR
+    mp = inputs.mpm_cube(args.seed, 256, side=0.5)
+    prm = mp.params
+    K, W = args.steps, args.warmup
+    W += W % 2          # keep the grid alternation in phase, so the timed window's plan is cached
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {}
+    runs = [("optimized", E.OPT_ALL), ("eager", 0)] + ([] if args.profile else _ablations())
+    for name, opt in runs:
+        E.reset()
+        grids = PR.mpm_grids(mp)
+        x, v, C, F = PR.device_mpm(mp)
+        step = lambda t: PR.mpm_step(grids, t, x, v, C, F, prm)
+        for t0 in range(0, W, K):
+            E.run_sequence(sum((step(t) for t in range(t0, min(t0 + K, W))), []), opt)
+        tasks = E.prepare(sum((step(t) for t in range(W, W + K)), []))
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        st = E.run_sequence(tasks, opt)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        vox = sum(len(g.active_cells()) for g in grids) * 512 // 2
+        res[name] = (ev0.elapsed_time(ev1) * 1e-3, st, vox)
+        if name == "optimized":
+            keep = (grids, x, v, C, F)
+        else:
+            del grids, x, v, C, F
+        gc.collect()
+        torch.cuda.empty_cache()
+    t, st, vox = res["optimized"]
+    npart = mp.nparticles
+    out = _base(K, W, vox * K / t, t / K * 1e3,
+                {"workload": "mpm256: MLS-MPM falling cube, 16,777,216 fixed-corotated particles (2 per cell per "
+                             "axis, block-ordered lattice), 256^3 grid, two alternating bitmask-rooted grids, "
+                             "dt 1e-4", "seed": args.seed, "particles": npart})
+    out.update({"particle_steps_per_s": npart * K / t,
+                "launches_per_step": {"optimized": st["dispatches"] / K, "eager": res["eager"][1]["dispatches"] / K},
+                "eager": {"value": res["eager"][2] * K / res["eager"][0], "ms_per_step": res["eager"][0] / K * 1e3,
+                          "particle_steps_per_s": npart * K / res["eager"][0]},
+                "speedup_vs_eager": res["eager"][0] / t, "fusions": st["fusions"],
+                "stores_eliminated": st["stores_eliminated"], "plan_cache_hits": st["plan_cache_hits"],
+                "optimizer_us_per_window": st["optimizer_us"],
+                "ablations": {name: {"launches_per_step": res[name][1]["dispatches"] / K,
+                                     "ms_per_step": res[name][0] / K * 1e3,
+                                     "stores_eliminated": res[name][1]["stores_eliminated"]}
+                              for name, _ in runs[2:]}})
+    # dominant launch: the fused G2P2G node, timed between HIP events around
+    # each launch over two more windows of the timed shape (plan cached)
+    grids, x, v, C, F = keep
+    tasks = E.prepare(sum((PR.mpm_step(grids, t_, x, v, C, F, prm) for t_ in range(W + K, W + 2 * K)), []))
+    E.run_sequence(tasks, E.OPT_ALL)
+    ents = window_kernel_means(E, tasks, E.OPT_ALL, 2)
+    out["kernels"] = {"%s/%d" % (e["name"], e["members"]): {"launches": e["launches"], "mean_us": e["mean_us"]}
+                      for e in ents}
+    dom = max(ents, key=lambda e: e["launches"] * e["mean_us"])
+    if dom["kind"] == L.AT_TASK_G2P_APIC and dom["members"] == 3:
+        tf = MPM_FLOPS_PER_PARTICLE * npart / (dom["mean_us"] * 1e-6) / 1e12
+        out["roofline"] = {"bound": "alu", "achieved": tf, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": tf / FP32_PEAK_TFLOPS, "traffic": None,
+                           "kernel": "k_mpm<G2P|ADVECT|P2G> (fused G2P2G node): %d algorithmic fp32 operations "
+                                     "per particle; mean over %d launches, each between its own HIP events"
+                                     % (MPM_FLOPS_PER_PARTICLE, dom["launches"]),
+                           "algorithmic_flops_per_launch": MPM_FLOPS_PER_PARTICLE * npart,
+                           "hbm_GBs_algorithmic": 96.0 * npart / (dom["mean_us"] * 1e-6) / 1e9,
+                           "hbm_note": "96 B per particle (x and F read and written)"}
+    del keep, grids, x, v, C, F
+    if not args.no_cpu_baseline and not args.profile:
+        from oracle import programs as OP
+        sample = 1 << 18     # the first 262,144 particles: 512 whole blocks of the lattice
+        sx, sv, sC, sF = (a[:, :sample].copy() for a in (mp.x, mp.v, mp.C, mp.F))
+        calls, dt, core = cpu_leg(lambda _: OP.mpm_program(256, sx, sv, sC, sF, 1, prm["dt"], prm["mass"],
+                                                            prm["vol"], prm["mu"], prm["lam"], prm["gravity"],
+                                                            prm["bound"], "f64"), 10.0, 200)
+        out["cpu_baseline"] = cpu_baseline(sample * calls / dt, "particle-steps/s",
+                                           "%d substeps of the first %d particles of the mpm256 cube (fp64 oracle), "
+                                           "seed %d" % (calls, sample, args.seed), dt, core)
+    return out
+
+
 # --------------------------------------------------------------------- serving
 def bench_serving(args, torch):
     import numpy as np
@@ -712,7 +809,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--workload", default="band512", choices=["band512", "shell", "particles", "serving", "diffusion",
-                                                           "multigrid", "advection", "maccormack"])
+                                                           "multigrid", "advection", "maccormack", "mpm"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=90)
     ap.add_argument("--requests", type=int, default=256)
@@ -732,7 +829,7 @@ def main():
     # reported beside the result)
     defaults = {"band512": (100, 100), "shell": (100, 100), "particles": (20, 40), "serving": (256, 0),
                 "diffusion": (40, 5), "multigrid": (20, 5), "advection": (50, 5),
-                "maccormack": (30, 5)}
+                "maccormack": (30, 5), "mpm": (16, 32)}
     d = defaults[args.workload]
     args.steps = d[0] if args.steps is None else args.steps
     args.warmup = d[1] if args.warmup is None else args.warmup
@@ -744,7 +841,7 @@ def main():
     fn = {"band512": bench_band, "shell": bench_shell, "particles": bench_particles, "serving": bench_serving,
           "diffusion": bench_diffusion, "multigrid": bench_multigrid,
           "advection": bench_advection,
-          "maccormack": lambda a, t: bench_advection(a, t, mac=True)}[args.workload]
+          "maccormack": lambda a, t: bench_advection(a, t, mac=True), "mpm": bench_mpm}[args.workload]
     out = fn(args, torch)
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib << 18
