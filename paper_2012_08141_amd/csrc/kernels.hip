@@ -1216,6 +1216,273 @@ __global__ __launch_bounds__(64) void k_micro(GridDev g, MicroProg prog) {
     }
 }
 
+// ------------------------------------------- advection over staged tiles
+// A fused (or single) struct-for whose ops sample channels at back-traced
+// points (ADVECT, MACCORMACK), possibly with element-wise ops: one
+// workgroup of 512 threads per listed block stages, in LDS, the block plus a
+// 2-voxel halo (12^3 voxels; this workload's back-traces reach 1.34 voxels)
+// of every channel the node samples and, for RK3 back-traces, of the three
+// velocity channels -- coalesced rows, one root lookup per neighbour block
+// for the whole tile -- and then runs the ops per voxel in program order.
+// A trilinear sample whose 8 corners lie in the tile reads LDS, in the same
+// corner order and arithmetic as sample_point, so results are bit-identical
+// to the per-voxel interpreter; a point outside the tile reads the grid as
+// before.  Fusion legality guarantees that no op of the node writes a
+// channel another op samples, so the staged tiles stay valid for the whole
+// node.
+constexpr int kTE = 12, kT3 = kTE * kTE * kTE;   // tile edge and voxels (block + 2 each side)
+constexpr int kTileCh = 4;                        // sampled channels staged per node
+constexpr int kTT = 512;                          // threads per workgroup: one voxel each
+
+struct TileProg {
+    MicroProg prog;
+    int32_t nt;              // staged sampled channels
+    int32_t tch[kTileCh];    // their grid channels
+    int32_t vstage;          // stage the tile of v0 .. v0 + 2 (RK3 back-traces)
+    int32_t v0;              // the velocity of every sampling op (else -1: read per voxel)
+};
+
+// Tile position of a point coordinate's lower corner: the corner pair
+// (b0, b0 + 1) lies in the tile when 0 <= b0 - origin <= kTE - 2.
+__device__ __forceinline__ float tile_sample(const float *T, const int lb[3], const float w[3][2]) {
+    float acc = 0.f;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 2; ++c) {
+                const float wt = (w[0][a] * w[1][b]) * w[2][c];
+                acc = acc + wt * T[((lb[0] + a) * kTE + (lb[1] + b)) * kTE + (lb[2] + c)];
+            }
+    return acc;
+}
+
+// The rare sample outside the staged tile, out of line so that its root
+// lookups do not hold registers in the staged path.
+template <int KIND>
+__device__ __noinline__ float sample_far(const GridDev &g, const float *base, int64_t cell, int32_t slot,
+                                         float p0, float p1, float p2, int n) {
+    const float p[3] = {p0, p1, p2};
+    return sample_point<KIND>(g, base, cell, slot, p, n);
+}
+
+template <int KIND>
+__device__ __noinline__ void corners_far(const GridDev &g, const float *Q, int64_t cell, int32_t slot, int b0, int b1,
+                                         int b2, int n, float &lo, float &hi) {
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 2; ++c) {
+                const float x = sample_voxel<KIND>(g, Q, cell, slot, b0 + a, b1 + b, b2 + c, n);
+                if (a + b + c == 0) {
+                    lo = x;
+                    hi = x;
+                } else {
+                    lo = x < lo ? x : lo;
+                    hi = x > hi ? x : hi;
+                }
+            }
+}
+
+// Trilinear sample of channel ch at p: from the staged tile T (origin o,
+// the block's first voxel minus 2) when all corners lie in it, else from the
+// grid (sample_point).  Same clamp, weights, corner order and arithmetic.
+template <int KIND>
+__device__ __forceinline__ float sample_staged(const GridDev &g, const float *T, const int o[3], const float *base,
+                                               int64_t cell, int32_t slot, const float p[3], int n) {
+    float w[3][2];
+    int lb[3];
+    bool in = T != nullptr;
+    for (int d = 0; d < 3; ++d) {
+        const float pd = clamp_coord(p[d], n);
+        const float bd = floorf(pd);
+        const float f = pd - bd;
+        lb[d] = (int)bd - o[d];
+        in = in && lb[d] >= 0 && lb[d] <= kTE - 2;
+        w[d][0] = 1.0f - f;
+        w[d][1] = f;
+    }
+    if (in) return tile_sample(T, lb, w);
+    return sample_far<KIND>(g, base, cell, slot, p[0], p[1], p[2], n);
+}
+
+template <int KIND>
+__device__ __forceinline__ const float *staged(const TileProg &tp, const float *tiles, int ch) {
+    for (int q = 0; q < tp.nt; ++q)
+        if (tp.tch[q] == ch) return tiles + q * kT3;
+    return nullptr;
+}
+
+// LDS layout (dynamic): the nt sampled tiles, then the velocity: three
+// tiles when staged for RK3 back-traces, else the block's own 512 voxels of
+// each component when every sampling op shares one velocity (v0 >= 0).
+__host__ __device__ inline int tile_lds_floats(const TileProg &tp) {
+    return tp.nt * kT3 + (tp.vstage ? 3 * kT3 : (tp.v0 >= 0 ? 3 * kBV : 0));
+}
+
+template <int KIND, int NT, bool VS>
+__global__ __launch_bounds__(kTT) void k_tile_micro(GridDev g, TileProg tp) {
+    extern __shared__ float s_t[];
+    __shared__ int32_t s_nb[27];
+    const int tid = threadIdx.x;
+    const int n = g.R * kBS;
+    float *vs = s_t + tp.nt * kT3;                       // velocity: tiles or the block's voxels
+    const float *vt = tp.vstage ? vs : nullptr;
+    const ListRange lr = list_range(g.hdr[HDR_COUNT]);
+    for (int e = lr.lo; e < lr.hi; e += lr.step) {
+        const int4 rec0 = reinterpret_cast<const int4 *>(g.list + (int64_t)e * kRec)[0];
+        const int32_t cell = rec0.x, slot = rec0.y;
+        int bi, bj, bk;
+        cell_coords(g, cell, bi, bj, bk);
+        if (tid < 27) {
+            const int ni = bi + tid / 9 - 1, nj = bj + (tid / 3) % 3 - 1, nk = bk + tid % 3 - 1;
+            int32_t sl = -1;
+            if (ni >= 0 && nj >= 0 && nk >= 0 && ni < g.R && nj < g.R && nk < g.R)
+                sl = tid == 13 ? slot : slot_of<KIND>(g, ((int64_t)ni * g.R + nj) * g.R + nk);
+            s_nb[tid] = sl;
+        }
+        __syncthreads();
+        // every load of the tile first (a valid dummy address where the voxel
+        // is outside the domain or inactive, zeroed by a select), then the
+        // LDS stores, so the loads overlap instead of each waiting for the
+        // store after it
+        constexpr int NIT = (kT3 + kTT - 1) / kTT, NC = NT + (VS ? 3 : 0);
+        float val[NIT][NC];
+        bool ok[NIT];
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int t = tid + it * kTT < kT3 ? tid + it * kTT : 0;
+            const int ti = t / (kTE * kTE) - 2, tj = (t / kTE) % kTE - 2, tk = t % kTE - 2;   // block-local
+            const int gi = bi * kBS + ti, gj = bj * kBS + tj, gk = bk * kBS + tk;
+            int32_t sl = -1;
+            if (gi >= 0 && gj >= 0 && gk >= 0 && gi < n && gj < n && gk < n)
+                sl = s_nb[((ti >> 3) + 1) * 9 + ((tj >> 3) + 1) * 3 + ((tk >> 3) + 1)];
+            ok[it] = sl >= 0;
+            const int64_t o = (int64_t)(sl >= 0 ? sl : slot) * kBV + (ti & 7) * 64 + (tj & 7) * 8 + (tk & 7);
+#pragma unroll
+            for (int q = 0; q < NT; ++q) val[it][q] = chan(g, tp.tch[q])[o];
+#pragma unroll
+            for (int d = 0; d < (VS ? 3 : 0); ++d) val[it][NT + d] = chan(g, tp.v0 + d)[o];
+        }
+        constexpr int NV = kBV / kTT;
+        float vown[NV][3];
+        if (!VS && tp.v0 >= 0)
+#pragma unroll
+            for (int it = 0; it < NV; ++it)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) vown[it][d] = chan(g, tp.v0 + d)[(int64_t)slot * kBV + tid + it * kTT];
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int t = tid + it * kTT;
+            if (t < kT3) {
+#pragma unroll
+                for (int q = 0; q < NT; ++q) s_t[q * kT3 + t] = ok[it] ? val[it][q] : 0.f;
+#pragma unroll
+                for (int d = 0; d < (VS ? 3 : 0); ++d) vs[d * kT3 + t] = ok[it] ? val[it][NT + d] : 0.f;
+            }
+        }
+        if (!VS && tp.v0 >= 0)
+#pragma unroll
+            for (int it = 0; it < NV; ++it)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) vs[d * kBV + tid + it * kTT] = vown[it][d];
+        __syncthreads();
+        const int org[3] = {bi * kBS - 2, bj * kBS - 2, bk * kBS - 2};
+        for (int vx = tid; vx < kBV; vx += kTT) {
+            const int li = vx >> 6, lj = (vx >> 3) & 7, lk = vx & 7;
+            const int I[3] = {bi * kBS + li, bj * kBS + lj, bk * kBS + lk};
+            const int64_t off = (int64_t)slot * kBV + vx;
+            // the back-traced point of the last (velocity, dt, rk3) used
+            float pt[3] = {0.f, 0.f, 0.f}, pdt = 0.f, prk = -1.f;
+            int pv = -1;
+            for (int oi = 0; oi < tp.prog.nops; ++oi) {
+                const MicroOp &op = tp.prog.ops[oi];
+                if (op.op == AT_OP_ADVECT || op.op == AT_OP_MACCORMACK) {
+                    if (!(op.ch[1] == pv && op.p == pdt && op.p1 == prk)) {
+                        float v1[3];
+                        if (op.ch[1] == tp.v0 && tp.vstage) {
+                            const int c = ((li + 2) * kTE + (lj + 2)) * kTE + (lk + 2);
+                            for (int d = 0; d < 3; ++d) v1[d] = vs[d * kT3 + c];
+                        } else if (op.ch[1] == tp.v0) {
+                            for (int d = 0; d < 3; ++d) v1[d] = vs[d * kBV + vx];
+                        } else {
+                            for (int d = 0; d < 3; ++d) v1[d] = chan(g, op.ch[1] + d)[off];
+                        }
+                        if (!VS || op.p1 == 0.f) {   // (every RK3 op stages velocity tiles)
+                            for (int d = 0; d < 3; ++d) pt[d] = (float)I[d] - op.p * v1[d];
+                        } else {
+                            const float *vtile = op.ch[1] == tp.v0 ? vt : nullptr;
+                            const float h1 = 0.5f * op.p, h2 = 0.75f * op.p;
+                            float p1[3], v2[3], p2[3], v3[3];
+                            for (int d = 0; d < 3; ++d) p1[d] = (float)I[d] - h1 * v1[d];
+                            for (int d = 0; d < 3; ++d)
+                                v2[d] = sample_staged<KIND>(g, vtile ? vtile + d * kT3 : nullptr, org,
+                                                            chan(g, op.ch[1] + d), cell, slot, p1, n);
+                            for (int d = 0; d < 3; ++d) p2[d] = (float)I[d] - h2 * v2[d];
+                            for (int d = 0; d < 3; ++d)
+                                v3[d] = sample_staged<KIND>(g, vtile ? vtile + d * kT3 : nullptr, org,
+                                                            chan(g, op.ch[1] + d), cell, slot, p2, n);
+                            const float c1 = (float)(2.0 / 9.0), c2 = (float)(1.0 / 3.0), c3 = (float)(4.0 / 9.0);
+                            for (int d = 0; d < 3; ++d) {
+                                float sv = c1 * v1[d];
+                                sv = sv + c2 * v2[d];
+                                sv = sv + c3 * v3[d];
+                                pt[d] = (float)I[d] - op.p * sv;
+                            }
+                        }
+                        pdt = op.p;
+                        prk = op.p1;
+                        pv = op.ch[1];
+                    }
+                    const float *Q = chan(g, op.ch[0]);
+                    const float *qt = staged<KIND>(tp, s_t, op.ch[0]);
+                    if (op.op == AT_OP_ADVECT) {
+                        chan(g, op.ch[2])[off] = sample_staged<KIND>(g, qt, org, Q, cell, slot, pt, n);
+                    } else {
+                        int b0[3], lb[3];
+                        bool in = qt != nullptr;
+                        for (int d = 0; d < 3; ++d) {
+                            b0[d] = (int)floorf(clamp_coord(pt[d], n));
+                            lb[d] = b0[d] - org[d];
+                            in = in && lb[d] >= 0 && lb[d] <= kTE - 2;
+                        }
+                        float lo = 0.f, hi = 0.f;
+                        if (in) {
+                            for (int a = 0; a < 2; ++a)
+                                for (int b = 0; b < 2; ++b)
+                                    for (int c = 0; c < 2; ++c) {
+                                        const float x = qt[((lb[0] + a) * kTE + (lb[1] + b)) * kTE + (lb[2] + c)];
+                                        if (a + b + c == 0) {
+                                            lo = x;
+                                            hi = x;
+                                        } else {
+                                            lo = x < lo ? x : lo;
+                                            hi = x > hi ? x : hi;
+                                        }
+                                    }
+                        } else {
+                            corners_far<KIND>(g, Q, cell, slot, b0[0], b0[1], b0[2], n, lo, hi);
+                        }
+                        const float dq = Q[off] - chan(g, op.ch[3])[off];
+                        const float h2 = 0.5f * dq;
+                        const float val = chan(g, op.ch[2])[off] + h2;
+                        chan(g, op.ch[4])[off] = val < lo ? lo : (val > hi ? hi : val);
+                    }
+                } else if (op.op == AT_OP_COPY) {
+                    chan(g, op.ch[0])[off] = chan(g, op.ch[1])[off];
+                } else if (op.op == AT_OP_AXPY) {
+                    float *y = chan(g, op.ch[0]) + off;
+                    *y = *y + op.p * chan(g, op.ch[1])[off];
+                } else if (op.op == AT_OP_INC) {
+                    float *x = chan(g, op.ch[0]) + off;
+                    *x = *x + op.p;
+                } else if (op.op == AT_OP_FILL) {
+                    for (int q = 0; q < 7; ++q)
+                        if (op.ch[q] >= 0 && ((op.keep >> q) & 1u)) chan(g, op.ch[q])[off] = op.p;
+                }
+            }
+        }
+        __syncthreads();   // the next block restages the tiles
+    }
+}
+
 // ---------------------------------------------------- two-level transfers
 // A coarse grid has half the fine domain edge, so fine block (bi, bj, bk)
 // lies under coarse block (bi/2, bj/2, bk/2), in its octant
@@ -2200,12 +2467,13 @@ int struct_for_grid_size(const GridDev &g) {
 }
 
 // Wavefront-per-block kernels.  The software-pipelined forms want several
-// blocks per wavefront (8 resident wavefronts per CU measured best on the
-// 13k-block band); the direct forms hide latency with occupancy instead.
+// blocks per wavefront (7 resident wavefronts per CU measured best on the
+// 13k-block band: 4, 5, 6, 8, 12 and 16 were slower); the direct forms hide
+// latency with occupancy instead.
 int wave_grid_size(const GridDev &g, bool pipelined) {
     if (g_sf_grid_override > 0) return g_sf_grid_override;
     const int64_t cap = g.cap < g.ncells ? g.cap : g.ncells;
-    int64_t wg = pipelined ? 256 * 8 : 256 * 28;
+    int64_t wg = pipelined ? 256 * 7 : 256 * 28;
     if (cap < wg) wg = ((cap + 7) / 8) * 8;
     if (wg < 8) wg = 8;
     return (int)wg;
@@ -2365,7 +2633,72 @@ hipError_t launch_stencil_tail(const GridDev &g, int op, const int32_t *ch, floa
     return hipGetLastError();
 }
 
+template <int KIND, int NT>
+static void launch_tile_nt(const GridDev &g, const TileProg &tp, dim3 grid, size_t lds, hipStream_t s) {
+    if (tp.vstage) hipLaunchKernelGGL((k_tile_micro<KIND, NT, true>), grid, dim3(kTT), lds, s, g, tp);
+    else hipLaunchKernelGGL((k_tile_micro<KIND, NT, false>), grid, dim3(kTT), lds, s, g, tp);
+}
+
+template <int KIND>
+static void launch_tile_k(const GridDev &g, const TileProg &tp, dim3 grid, size_t lds, hipStream_t s) {
+    switch (tp.nt) {
+    case 1: launch_tile_nt<KIND, 1>(g, tp, grid, lds, s); break;
+    case 2: launch_tile_nt<KIND, 2>(g, tp, grid, lds, s); break;
+    case 3: launch_tile_nt<KIND, 3>(g, tp, grid, lds, s); break;
+    default: launch_tile_nt<KIND, 4>(g, tp, grid, lds, s); break;
+    }
+}
+
+// A node for k_tile_micro: no activation check; sampling ops (ADVECT,
+// MACCORMACK) with element-wise ops it implements (COPY, AXPY, INC, FILL);
+// at most kTileCh distinct sampled channels; RK3 ops sharing one velocity.
+static bool tile_prog(const MicroProg &prog, TileProg &tp) {
+    if (prog.check || g_sf_kernel != 0) return false;
+    tp = TileProg{};
+    tp.prog = prog;
+    tp.v0 = -1;
+    bool sampling = false, shared_v = true;
+    for (int o = 0; o < prog.nops; ++o) {
+        const MicroOp &op = prog.ops[o];
+        if (op.op == AT_OP_ADVECT || op.op == AT_OP_MACCORMACK) {
+            bool have = false;
+            for (int q = 0; q < tp.nt; ++q) have |= tp.tch[q] == op.ch[0];
+            if (!have) {
+                if (tp.nt == kTileCh) return false;
+                tp.tch[tp.nt++] = op.ch[0];
+            }
+            if (sampling && op.ch[1] != tp.v0) shared_v = false;
+            if (!sampling) tp.v0 = op.ch[1];
+            if (op.p1 != 0.f) tp.vstage = 1;
+            sampling = true;
+        } else if (op.op != AT_OP_COPY && op.op != AT_OP_AXPY && op.op != AT_OP_INC && op.op != AT_OP_FILL) {
+            return false;
+        }
+    }
+    // RK3 back-traces sample one staged velocity; else each op reads its own
+    if (!shared_v) {
+        if (tp.vstage) return false;
+        tp.v0 = -1;
+    }
+    return sampling;
+}
+
 hipError_t launch_micro(const GridDev &g, const MicroProg &prog, hipStream_t s) {
+    TileProg tp;
+    if (tile_prog(prog, tp)) {
+        const int64_t cap = g.cap < g.ncells ? g.cap : g.ncells;
+        const size_t lds = (size_t)tile_lds_floats(tp) * sizeof(float);
+        // as many resident workgroups as the CU's 160 KiB of LDS holds (at most 8)
+        int64_t per_cu = (int64_t)(160 * 1024) / (int64_t)(lds + 256);
+        if (per_cu > 8) per_cu = 8;
+        if (per_cu < 1) per_cu = 1;
+        int64_t wgs = 256 * per_cu;
+        if (cap < wgs) wgs = ((cap + 7) / 8) * 8;
+        const dim3 grid((unsigned)wgs);
+        if (g.kind == AT_ROOT_BITMASK) launch_tile_k<AT_ROOT_BITMASK>(g, tp, grid, lds, s);
+        else launch_tile_k<AT_ROOT_POINTER>(g, tp, grid, lds, s);
+        return hipGetLastError();
+    }
     const dim3 grid(wave_grid_size(g, false)), block(64);
     if (prog.nops == 1 && g_sf_kernel == 0) {
         const dim3 pgrid(wave_grid_size(g, true));
