@@ -25,7 +25,7 @@ def _grads(w, steps, every, dt=0.1):
     loss = diffusion_loss(a0, k, tgt, prob)
     loss.backward()
     torch.cuda.synchronize()
-    return float(loss), a0.grad.cpu().numpy().astype(np.float64), k.grad.cpu().numpy().astype(np.float64), prob
+    return float(loss.detach()), a0.grad.cpu().numpy().astype(np.float64), k.grad.cpu().numpy().astype(np.float64), prob
 
 
 def _check(g, ref, what):

@@ -299,6 +299,58 @@ def test_diffusion_gradient_matches_central_differences():
             assert abs(grad.flat[p] - fd) <= 1e-4 * max(abs(fd), 1e-2 * np.abs(grad).max()), (which, p)
 
 
+_FD = {}
+
+
+def _fd_loss(case):
+    """Loss of the differentiation workload at (a0 + s h ua, k + s h uk), in a
+    worker process forked after _FD was filled."""
+    ua, uk, sign = case
+    d = _FD
+    aa = d["a0"] + sign * d["h"] * ua if ua is not None else d["a0"]
+    kk = d["k"] + sign * d["h"] * uk if uk is not None else d["k"]
+    return P.diffusion_loss(d["n"], d["blocks"], aa, kk, d["tgt"], d["dt"], d["T"])
+
+
+def test_diffusion_workload_gradient_matches_central_differences():
+    """The differentiation workload at full size (128^3, 355 active blocks, 20
+    steps): fp64 gradients from the reverse sweep against fp64 central
+    differences of the loss on 64 components of a0, 64 of k and 4 random
+    directions, at 1e-4 relative (h = 1e-3: the loss is quadratic in a0,
+    where central differences are exact up to rounding, and smooth in k;
+    at h = 1e-5 the rounding of the 2e5-term loss over 2h would exceed the
+    bar).  The device gradients are held to this adjoint element by element.
+    The 264 loss evaluations run in 8 forked worker processes."""
+    import multiprocessing as mp
+    w = I.diffusion(0)
+    _FD.update(n=w.n, blocks=w.blocks, a0=w.channels["a"].astype(np.float64), k=w.channels["k"].astype(np.float64),
+               tgt=w.channels["target"].astype(np.float64), dt=0.1, T=20, h=1e-3)
+    a0, k, h = _FD["a0"], _FD["k"], _FD["h"]
+    res = P.diffusion_grad(w.n, w.blocks, a0, k, _FD["tgt"], 0.1, 20, "f64")
+    rng = np.random.default_rng(11)
+    cases = []
+    for which, arr in (("a", a0), ("k", k)):
+        for p in rng.choice(arr.size, 64, replace=False):
+            e = np.zeros(arr.shape)
+            e.flat[p] = 1.0
+            cases.append((which, int(p), (e, None) if which == "a" else (None, e)))
+    for d in range(4):
+        cases.append(("dir", d, (rng.standard_normal(a0.shape), rng.standard_normal(k.shape))))
+    jobs = [(ua, uk, s) for _, _, (ua, uk) in cases for s in (1.0, -1.0)]
+    with mp.get_context("fork").Pool(8) as pool:
+        losses = pool.map(_fd_loss, jobs, chunksize=4)
+    _FD.clear()
+    ga, gk = res["grad_a0"], res["grad_k"]
+    for i, (which, p, (ua, uk)) in enumerate(cases):
+        fd = (losses[2 * i] - losses[2 * i + 1]) / (2 * h)
+        if which == "dir":
+            dot = float(np.sum(ga * ua) + np.sum(gk * uk))
+            assert abs(dot - fd) <= 1e-4 * abs(fd), (which, p, dot, fd)
+        else:
+            g = ga if which == "a" else gk
+            assert abs(g.flat[p] - fd) <= 1e-4 * max(abs(fd), 1e-2 * np.abs(g).max()), (which, p, g.flat[p], fd)
+
+
 # ----------------------------------------------------------------- particles
 @pytest.mark.parametrize("X", [5.0, 5.25, 5.5, 5.75, 6.4999, 100.0001, 17.3])
 def test_bspline_weights_moments(X):
