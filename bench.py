@@ -142,11 +142,12 @@ def window_kernel_means(E, tasks, opt, reps):
 
 def time_group(torch, E, group_fn, reps, opt, windows=3):
     """Like time_kernel, for a group of tasks that the optimizer turns into
-    one launch: a window of ``reps`` groups planned with ``opt``.  Returns
-    (seconds per group, launches per group)."""
+    one launch: a window of ``reps`` groups (``group_fn(r)`` for r = 0 ..
+    reps - 1, built so that consecutive groups cannot fuse) planned with
+    ``opt``.  Returns (seconds per group, launches per group)."""
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    tasks = E.prepare(sum((group_fn() for _ in range(reps)), []))
+    tasks = E.prepare(sum((group_fn(r) for r in range(reps)), []))
     E.run_sequence(tasks, opt)
     st = E.run_sequence(tasks, opt)
     torch.cuda.synchronize()
@@ -777,13 +778,18 @@ def bench_multigrid(args, torch):
                 "speedup_vs_eager": te / t})
     # dominant launch: the fine level's smoothing stencil, which the
     # optimizer fuses with the update after it (t = J(x); t -= x) into one
-    # k_stencil_tail launch: x, b read, t written (12 B per fine voxel)
+    # k_stencil_tail launch: x, b read, t written (12 B per fine voxel).
+    # Consecutive groups swap x and t, so each reads the previous group's
+    # output at neighbours and the groups cannot fuse with one another.
     E.reset()
     lv = PR.mg_levels(w, nl)
     g0 = lv[0]
-    t_fused, lpg = time_group(torch, E, lambda: [E.listgen(g0), E.jacobi(g0, PR.MG["x"], PR.MG["b"], PR.MG["t"]),
-                                                 E.listgen(g0), E.axpy(g0, PR.MG["t"], PR.MG["x"], -1.0)],
-                              100, E.OPT_ALL & ~E.OPT_DSE)    # (DSE would drop all but the last group's stores)
+
+    def group(r):
+        x, t = (PR.MG["x"], PR.MG["t"]) if r % 2 == 0 else (PR.MG["t"], PR.MG["x"])
+        return [E.listgen(g0), E.jacobi(g0, x, PR.MG["b"], t), E.listgen(g0), E.axpy(g0, t, x, -1.0)]
+
+    t_fused, lpg = time_group(torch, E, group, 100, E.OPT_ALL & ~E.OPT_DSE)    # (DSE would drop stores)
     out["kernels"] = {"fine_jacobi_tail_us": t_fused * 1e6, "launches_per_group": lpg}
     if lpg == 1:
         out["roofline"] = roofline(12.0 * w.active_voxels / t_fused / 1e9,

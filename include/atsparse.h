@@ -407,7 +407,7 @@ at_status at_run_sequence(const at_task *tasks, int32_t ntasks, uint32_t opt_fla
                           at_stats *stats, hipStream_t stream);
 
 /* One entry of an optimized plan: the input tasks it runs, in order. */
-#define AT_PLAN_MAX_MEMBERS 8
+#define AT_PLAN_MAX_MEMBERS 16   /* = the most tasks one fused launch runs */
 typedef struct at_plan_entry {
     int32_t kind;                 /* AT_TASK_* of the first member */
     int32_t nmembers;

@@ -30,7 +30,7 @@ AT_TASK_RESTRICT, AT_TASK_PROLONG = 7, 8
 AT_TASK_P2G_MLS, AT_TASK_G2P_APIC = 9, 10
 AT_TASKF_LOOP_UNIQUE = 1
 AT_OPT_LGR, AT_OPT_AD, AT_OPT_FUSE, AT_OPT_DSE, AT_OPT_ALL = 1, 2, 4, 8, 15
-AT_PLAN_MAX_MEMBERS = 8
+AT_PLAN_MAX_MEMBERS = 16
 AT_OPTION_MAX_FUSE_PER_TASK, AT_OPTION_FLUSH_PERIOD, AT_OPTION_OPT_FLAGS, AT_OPTION_PLAN_CACHE = 1, 2, 3, 4
 AT_OPTION_STRUCT_FOR_WORKGROUPS = 5
 AT_OPTION_STRUCT_FOR_KERNEL = 6

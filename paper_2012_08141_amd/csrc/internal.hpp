@@ -53,7 +53,7 @@ constexpr int kRec = 8;            // int32 words per list record
 
 // One op of a fused (or elementwise) struct-for program, applied per voxel
 // in program order.
-constexpr int kMaxOps = 8;
+constexpr int kMaxOps = 16;
 struct MicroOp {
     int32_t op;       // AT_OP_*
     int32_t ch[7];    // channels, as in the public op table

@@ -1057,6 +1057,7 @@ at_status at_plan_sequence(const at_task *tasks, int32_t ntasks, uint32_t opt_fl
         std::memset(&e, 0, sizeof e);
         e.kind = tasks[nd.members[0].task].kind;
         e.nmembers = (int32_t)nd.members.size();
+        static_assert(AT_PLAN_MAX_MEMBERS >= kMaxOps, "a plan entry holds every member of a fused launch");
         for (size_t m = 0; m < nd.members.size() && m < AT_PLAN_MAX_MEMBERS; ++m) {
             e.members[m] = nd.members[m].task;
             e.keep[m] = nd.members[m].keep;

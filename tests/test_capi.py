@@ -34,6 +34,7 @@ def test_struct_layouts():
     assert ctypes.sizeof(L.AtTask) == 16 + 16 + 32 + 32 + 32 + 8
     assert ctypes.sizeof(L.AtStats) == 8 * 9
     assert ctypes.sizeof(L.AtGridDesc) == 28
+    assert ctypes.sizeof(L.AtPlanEntry) == 4 * (2 + L.AT_PLAN_MAX_MEMBERS + 3 + L.AT_PLAN_MAX_MEMBERS)
 
 
 def _desc(n, kind=L.AT_ROOT_BITMASK, ch=2, cap=0):

@@ -46,6 +46,10 @@ def build(fx):
             tasks.append(E.fill(grids[op[1]], op[2], op[3]))
         elif k == "copy":
             tasks.append(E.copy(grids[op[1]], op[2], op[3]))
+        elif k == "axpy":
+            tasks.append(E.axpy(grids[op[1]], op[2], op[3], op[4]))
+        elif k == "restrict":
+            tasks.append(E.restrict(grids[op[1]], grids[op[2]], op[3], op[4], op[5]))
         elif k == "lap_update":
             tasks.append(E.lap_update(grids[op[1]], op[2], op[3], op[4]))
         elif k == "jacobi":
@@ -83,6 +87,9 @@ def test_golden_plan(path):
             mask = ent[0]["fill_channels"]
             chans = [c for q, c in enumerate(fx["program"][ti][2]) if (mask >> q) & 1]
             assert chans == kept
+        for ti, chk in case.get("check_activation", {}).items():
+            ent = [e for e in entries if e["members"][0] == int(ti)]
+            assert ent and ent[0]["check_activation"] == chk, (ti, ent)
         for a, b in case.get("separate", []):
             assert not any(a in m and b in m for m in plan), plan
         # every plan entry is a topological order of the eager program:
