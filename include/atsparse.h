@@ -535,6 +535,52 @@ at_status at_batch_get_views(at_batch batch, at_batch_views *views);
  * cannot check these.  An entry whose root cell holds no block is skipped. */
 at_status at_batch_jacobi(at_batch batch, int32_t iters, int32_t workgroups, hipStream_t stream);
 
+/* Library-managed admission and retirement for continuous batching (Section
+ * 7.1: the host enqueues and goes on while the device computes).  One call
+ * applies a replay boundary's changes in stream order: the retirements (each
+ * grid's x copied out when x_out is given, its pool slots returned, its root
+ * cells and window cleared), then the admissions (pool slots taken, b copied
+ * in, x and xn zeroed, the root cells pointed at the slots, the window set
+ * to [clock, clock + iters) from the device clock as it is when the update
+ * runs, i.e. after every launch enqueued before it), then the work list of
+ * every resident grid, in ascending grid id and each grid's cell order.
+ * The descriptors travel as kernel arguments: no host-to-device copy and no
+ * host synchronisation; 1 + ceil(nretire / 16) dispatches or more (one per
+ * 16 admissions or 64 resident grids).  The pool's free slots are a stack
+ * in device memory whose height the library tracks on the host.
+ * Ownership: cells ([nblocks] root cells, distinct, below R^3), b
+ * ([nblocks][512], block i for cells[i]) and slots ([nblocks], receives the
+ * grid's pool slots) are caller device arrays; cells and slots must stay
+ * valid until the grid is retired, b until the update has run; x_out
+ * ([nblocks][512], block i for cells[i]) until the update has run.
+ * Errors (nothing enqueued, state unchanged): AT_E_INVALID for a grid id
+ * out of range, retiring a grid that is not resident (or twice), admitting
+ * into a resident grid id (one retired in the same call may be reused),
+ * nblocks outside [1, pool_blocks], negative iters or null arrays;
+ * AT_E_CAPACITY when the admissions need more pool blocks than are free
+ * after the retirements.  Cells outside the root cannot be checked on the
+ * host: the device leaves them out of the roots and the sweep.  Grids made
+ * this way must not also be written through the views (root rows, windows,
+ * work list); reading x, xn and b through them is fine. */
+typedef struct at_batch_admit {
+    const int32_t *cells;
+    const float *b;
+    int32_t *slots;
+    int32_t gid;          /* a grid id below max_grids that is not resident */
+    int32_t nblocks;
+    int32_t iters;        /* iterations the grid stays active */
+    int32_t reserved;     /* must be 0 */
+} at_batch_admit;
+
+typedef struct at_batch_retire {
+    int32_t gid;          /* a resident grid admitted through at_batch_update */
+    int32_t reserved;     /* must be 0 */
+    float *x_out;         /* nullable */
+} at_batch_retire;
+
+at_status at_batch_update(at_batch batch, const at_batch_retire *retire, int32_t nretire,
+                          const at_batch_admit *admit, int32_t nadmit, hipStream_t stream);
+
 /* Total device dispatches issued by the library since load. */
 int64_t at_dispatch_count(void);
 

@@ -83,6 +83,15 @@ class AtBatchViews(ctypes.Structure):
                 ("work", c_void_p), ("x", c_void_p), ("xn", c_void_p), ("b", c_void_p)]
 
 
+class AtBatchAdmit(ctypes.Structure):
+    _fields_ = [("cells", c_void_p), ("b", c_void_p), ("slots", c_void_p), ("gid", c_int32), ("nblocks", c_int32),
+                ("iters", c_int32), ("reserved", c_int32)]
+
+
+class AtBatchRetire(ctypes.Structure):
+    _fields_ = [("gid", c_int32), ("reserved", c_int32), ("x_out", c_void_p)]
+
+
 class AtPlanEntry(ctypes.Structure):
     _fields_ = [("kind", c_int32), ("nmembers", c_int32), ("members", c_int32 * AT_PLAN_MAX_MEMBERS),
                 ("check_activation", c_int32), ("activation_mode", c_int32), ("dropped", c_uint32),
@@ -127,6 +136,8 @@ _SIGS = {
     "at_batch_destroy": (c_int32, [_P]),
     "at_batch_get_views": (c_int32, [_P, ctypes.POINTER(AtBatchViews)]),
     "at_batch_jacobi": (c_int32, [_P, c_int32, c_int32, _P]),
+    "at_batch_update": (c_int32, [_P, ctypes.POINTER(AtBatchRetire), c_int32, ctypes.POINTER(AtBatchAdmit), c_int32,
+                                  _P]),
     "at_dispatch_count": (c_int64, []),
     "at_last_error": (ctypes.c_char_p, []),
     "at_version": (ctypes.c_char_p, []),

@@ -4,10 +4,13 @@
 root row per resident grid (pool slot per root cell), a shared pool of
 leaves for x, xn and b, a work list of (grid, cell) entries and, per grid,
 the window of global iterations in which it is active.  Admission and
-retirement only edit those arrays (stream-ordered device copies); the
-iterations themselves are ``at_batch_jacobi`` launches -- the same Jacobi
-and copy arithmetic as the single-grid kernels -- which can be captured once
-in a HIP graph and replayed while grids come and go.
+retirement go through ``at_batch_update``, which applies one replay
+boundary's changes in two launches, in stream order, without host
+synchronisation: the host keeps only ids and counts, and a request's cells
+and right-hand side are already on the device.  The iterations themselves
+are ``at_batch_jacobi`` launches -- the same Jacobi and copy arithmetic as
+the single-grid kernels -- which can be captured once in a HIP graph and
+replayed while grids come and go.
 """
 from __future__ import annotations
 
@@ -18,6 +21,16 @@ import torch
 
 from . import _lib as L
 from .grid import current_stream
+
+
+def _dev_i32(x, dev):
+    t = x if isinstance(x, torch.Tensor) else torch.as_tensor(np.asarray(x, dtype=np.int32))
+    return t.to(device=dev, dtype=torch.int32).contiguous()
+
+
+def _dev_f32(x, dev, nb):
+    t = x if isinstance(x, torch.Tensor) else torch.as_tensor(np.asarray(x, dtype=np.float32))
+    return t.to(device=dev, dtype=torch.float32).reshape(nb, 512).contiguous()
 
 
 class BatchArena:
@@ -50,12 +63,11 @@ class BatchArena:
         self.x = view(v.x, pool_blocks * 2048, torch.float32, (pool_blocks, 512))
         self.xn = view(v.xn, pool_blocks * 2048, torch.float32, (pool_blocks, 512))
         self.b = view(v.b, pool_blocks * 2048, torch.float32, (pool_blocks, 512))
-        # host bookkeeping
+        # host bookkeeping: ids and counts only
         self.clock_host = 0
-        self.free_slots = list(range(pool_blocks - 1, -1, -1))
+        self.nfree = pool_blocks
         self.free_gids = list(range(max_grids - 1, -1, -1))
-        self.grids = {}            # gid -> (slots tensor, cells np, window)
-        self._dirty = False
+        self.grids = {}            # gid -> (cells, slots, b: device tensors kept alive; window)
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -73,62 +85,72 @@ class BatchArena:
         return nblocks * (3 * 2048 + 4)
 
     def free_blocks(self) -> int:
-        return len(self.free_slots)
+        return self.nfree
 
     def fits(self, nblocks: int) -> bool:
-        return bool(self.free_gids) and len(self.free_slots) >= nblocks
+        return bool(self.free_gids) and self.nfree >= nblocks
 
-    def admit(self, cells: np.ndarray, b, iters: int) -> int:
+    def update(self, retire=(), admit=(), stream=None):
+        """Apply one replay boundary's changes in stream order: retire the
+        grids ``retire`` (ids), then admit ``admit`` -- (cells, b, iters)
+        triples, cells ascending ([nb] int32) and b ([nb, 512] float32), on
+        the device already for a host-free update.  Returns (x of each
+        retired grid [nb, 512], valid in stream order; id of each admitted
+        grid)."""
+        dev = self.x.device
+        rets, outs = [], []
+        for gid in retire:
+            cells, slots, _, _ = self.grids[gid]
+            out = torch.empty((cells.numel(), 512), dtype=torch.float32, device=dev)
+            rets.append(L.AtBatchRetire(gid, 0, out.data_ptr()))
+            outs.append(out)
+        freed = sum(self.grids[g][0].numel() for g in retire)
+        need = 0
+        adms, gids, keep = [], [], []
+        free_gids = self.free_gids + list(retire)
+        for cells, b, iters in admit:
+            if not 0 <= int(iters) < (1 << 31):
+                raise ValueError("iterations must lie in [0, 2^31)")
+            cells_t = _dev_i32(cells, dev)
+            nb = cells_t.numel()
+            b_t = _dev_f32(b, dev, nb)
+            slots_t = torch.empty(nb, dtype=torch.int32, device=dev)
+            if not free_gids:
+                raise RuntimeError("batch arena has no free grid slot")
+            gid = free_gids.pop()
+            adms.append(L.AtBatchAdmit(cells_t.data_ptr(), b_t.data_ptr(), slots_t.data_ptr(), gid, nb, int(iters), 0))
+            gids.append(gid)
+            keep.append((cells_t, slots_t, b_t, (self.clock_host, self.clock_host + int(iters))))
+            need += nb
+        if need > self.nfree + freed:
+            raise RuntimeError("batch arena full")
+        ra = (L.AtBatchRetire * max(1, len(rets)))(*rets)
+        aa = (L.AtBatchAdmit * max(1, len(adms)))(*adms)
+        L.check(self._lib.at_batch_update(self.handle, ra, len(rets), aa, len(adms),
+                                          stream if stream is not None else current_stream()))
+        for gid in retire:
+            del self.grids[gid]
+        self.free_gids = free_gids
+        self.nfree += freed - need
+        for gid, k in zip(gids, keep):
+            self.grids[gid] = k
+        return outs, gids
+
+    def admit(self, cells, b, iters: int) -> int:
         """Make a grid with active root cells ``cells`` (ascending), right-hand
         side ``b`` ([nb, 512]) and x = 0 resident, active for the next
         ``iters`` global iterations.  Returns its grid id."""
-        nb = len(cells)
-        if not self.fits(nb):
+        if not self.fits(len(cells)):
             raise RuntimeError("batch arena full")
-        gid = self.free_gids.pop()
-        slots = np.array([self.free_slots.pop() for _ in range(nb)], dtype=np.int64)
-        dev = self.x.device
-        slots_t = torch.as_tensor(slots, device=dev)
-        cells_t = torch.as_tensor(np.asarray(cells, dtype=np.int64), device=dev)
-        row = torch.full((self.ncells,), -1, dtype=torch.int32, device=dev)
-        row[cells_t] = slots_t.to(torch.int32)
-        self.roots[gid].copy_(row)
-        bt = b if isinstance(b, torch.Tensor) else torch.as_tensor(np.asarray(b, np.float32))
-        self.b.index_copy_(0, slots_t, bt.to(device=dev, dtype=torch.float32).reshape(nb, 512))
-        z = torch.zeros((nb, 512), dtype=torch.float32, device=dev)
-        self.x.index_copy_(0, slots_t, z)
-        self.xn.index_copy_(0, slots_t, z)
-        win = (self.clock_host, self.clock_host + iters)
-        self.window[gid].copy_(torch.tensor(win, dtype=torch.int64))
-        self.grids[gid] = (slots_t, np.asarray(cells, dtype=np.int32), win)
-        self._dirty = True
-        return gid
+        return self.update((), [(cells, b, iters)])[1][0]
 
     def done(self, gid: int) -> bool:
-        return self.clock_host >= self.grids[gid][2][1]
+        return self.clock_host >= self.grids[gid][3][1]
 
     def retire(self, gid: int):
         """Remove a grid; returns its x values [nb, 512] (a device tensor,
         valid in stream order)."""
-        slots_t, cells, win = self.grids.pop(gid)
-        out = self.x.index_select(0, slots_t)
-        self.roots[gid].fill_(-1)
-        self.window[gid].zero_()
-        self.free_slots.extend(slots_t.cpu().tolist())
-        self.free_gids.append(gid)
-        self._dirty = True
-        return out
-
-    def sync_work_list(self):
-        """Upload the work list (ascending grid, then cell) if it changed."""
-        if not self._dirty:
-            return
-        parts = [gid * self.ncells + cells.astype(np.int64) for gid, (_, cells, _) in sorted(self.grids.items())]
-        w = np.concatenate(parts).astype(np.int32) if parts else np.zeros(0, np.int32)
-        if len(w):
-            self.work[:len(w)].copy_(torch.as_tensor(w))
-        self.count.copy_(torch.tensor([len(w)], dtype=torch.int32))
-        self._dirty = False
+        return self.update([gid], ())[0][0]
 
     # ---- iterations -------------------------------------------------------------
     def launch(self, iters: int, workgroups: int = 0, stream=None):
@@ -137,7 +159,6 @@ class BatchArena:
                                           stream if stream is not None else current_stream()))
 
     def step(self, iters: int, workgroups: int = 0):
-        self.sync_work_list()
         self.launch(iters, workgroups)
         self.clock_host += iters
 
@@ -182,6 +203,5 @@ class CapturedSteps:
             arena.launch(iters, workgroups, torch.cuda.current_stream().cuda_stream)
 
     def replay(self):
-        self.arena.sync_work_list()
         self.graph.replay()
         self.arena.clock_host += self.iters

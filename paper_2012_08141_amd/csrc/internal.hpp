@@ -127,6 +127,42 @@ struct BatchDev {
     int32_t *work;           // [pool]: grid * R^3 + cell
     int4 *rec;               // [pool][2]: per work entry {slot, grid, nb0, nb1}, {nb2, nb3, nb4, nb5}
     float *x, *xn, *b;       // [pool][512]
+    int32_t *free_slots;     // [pool]: stack of free pool slots (the host keeps its height)
+};
+
+// One batch update (at_batch_update) passes its descriptors by value, as
+// kernel arguments: no host-to-device copy, nothing for the host to wait on.
+constexpr int kUpdItems = 16;    // retirements or admissions per update launch
+constexpr int kUpdGrids = 64;    // resident grids whose work entries one update launch writes
+struct BatchRetireItem {
+    int32_t gid, nb;
+    int32_t q;                   // free-stack position its first slot is pushed to
+    int32_t first;               // its first workgroup in the launch
+    const int32_t *cells;        // [nb] root cells
+    const int32_t *slots;        // [nb] pool slots (written by the admission)
+    float *x_out;                // [nb][512] receives x, or null
+};
+struct BatchRetireArgs {
+    int32_t n, blocks;
+    BatchRetireItem it[kUpdItems];
+};
+struct BatchAdmitItem {
+    int32_t gid, nb;
+    int32_t p;                   // free-stack position of its first slot
+    int32_t first;               // its first workgroup in the launch
+    int32_t iters, pad;
+    const int32_t *cells;        // [nb] root cells
+    const float *b;              // [nb][512] right-hand side
+    int32_t *slots;              // [nb] receives the pool slots
+};
+struct BatchWorkItem {
+    int32_t gid, nb, off, pad;   // entries off .. off + nb - 1 of the work list
+    const int32_t *cells;
+};
+struct BatchAdmitArgs {
+    int32_t nadm, adm_blocks, nwork, count;
+    BatchAdmitItem it[kUpdItems];
+    BatchWorkItem w[kUpdGrids];
 };
 
 // Kernel launchers (kernels.hip).  Each enqueues exactly one dispatch on the
@@ -161,6 +197,9 @@ hipError_t launch_gather_blocks(const GridDev &g, int ch, const int32_t *cells, 
 hipError_t launch_popcount(const GridDev &g, hipStream_t s);   // into hdr[HDR_SCRATCH]
 // iters x (jacobi, copy) over the work list, then clock += iters (2*iters + 1 dispatches).
 hipError_t launch_batch_jacobi(const BatchDev &d, int iters, int workgroups, hipStream_t s);
+hipError_t launch_batch_init(const BatchDev &d, hipStream_t s);
+hipError_t launch_batch_retire(const BatchDev &d, const BatchRetireArgs &a, hipStream_t s);
+hipError_t launch_batch_admit(const BatchDev &d, const BatchAdmitArgs &a, hipStream_t s);
 int batch_waves();
 void set_batch_waves(int waves);          // 1, 2 or 4 wavefronts per batched workgroup
 // Binning workspace in the library's static device array (the scatter that

@@ -1581,6 +1581,11 @@ __global__ __launch_bounds__(256) void k_batch_records(BatchDev d) {
     const int n = *d.count;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
         const int32_t w = d.work[e];
+        if (w < 0) {                       // an entry without a block (see k_batch_admit)
+            d.rec[2 * e] = make_int4(-1, 0, -1, -1);
+            d.rec[2 * e + 1] = make_int4(-1, -1, -1, -1);
+            continue;
+        }
         const int gid = w / d.ncells;
         const int32_t cell = w - gid * d.ncells;
         const int32_t *root = d.roots + (int64_t)gid * d.ncells;
@@ -1649,6 +1654,78 @@ __global__ __launch_bounds__(64 * W) void k_batch(BatchDev d, int it) {
 
 __global__ void k_batch_tick(BatchDev d, int iters) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *d.clock += iters;
+}
+
+// Batch updates.  The pool's free slots are a stack in device memory whose
+// height only the host tracks, so the slots an admission takes and a
+// retirement returns never cross to the host.  One workgroup of 128 threads
+// per pool block (a float4 each); the descriptors come as kernel arguments.
+__global__ __launch_bounds__(256) void k_batch_init(BatchDev d) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d.pool; i += gridDim.x * blockDim.x)
+        d.free_slots[i] = i;
+}
+
+// Retirement: x of the grid's blocks out (when asked), its slots back on the
+// stack, its root cells and window cleared.
+__global__ __launch_bounds__(128) void k_batch_retire(BatchDev d, BatchRetireArgs a) {
+    const int w = blockIdx.x, t = threadIdx.x;
+    int k = 0;
+    while (k + 1 < a.n && w >= a.it[k + 1].first) ++k;
+    const BatchRetireItem &it = a.it[k];
+    const int i = w - it.first;
+    const int32_t s = it.slots[i];
+    if (it.x_out && s >= 0 && s < d.pool)
+        reinterpret_cast<float4 *>(it.x_out + (int64_t)i * kBV)[t] =
+            reinterpret_cast<const float4 *>(d.x + (int64_t)s * kBV)[t];
+    if (t == 0) {
+        d.free_slots[it.q + i] = s;
+        const int32_t c = it.cells[i];
+        if (c >= 0 && c < d.ncells) d.roots[(int64_t)it.gid * d.ncells + c] = -1;
+        if (i == 0) {
+            d.window[2 * it.gid] = 0;
+            d.window[2 * it.gid + 1] = 0;
+        }
+    }
+}
+
+// Admission (the first adm_blocks workgroups): a slot off the stack per
+// block, b copied in, x and xn zeroed, the root cell pointed at the slot,
+// and the window [clock, clock + iters) read from the device clock, i.e. in
+// stream order after every sweep enqueued before.  The other workgroups, one
+// per resident grid, write the work list: entries grid * R^3 + cell in the
+// order given (a cell outside the root gives an entry without a block).
+__global__ __launch_bounds__(128) void k_batch_admit(BatchDev d, BatchAdmitArgs a) {
+    const int w = blockIdx.x, t = threadIdx.x;
+    if (w == 0 && t == 0) *d.count = a.count;
+    if (w < a.adm_blocks) {
+        int k = 0;
+        while (k + 1 < a.nadm && w >= a.it[k + 1].first) ++k;
+        const BatchAdmitItem &it = a.it[k];
+        const int i = w - it.first;
+        const int32_t s = d.free_slots[it.p + i];
+        const int64_t o = (int64_t)s * kBV;
+        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+        reinterpret_cast<float4 *>(d.b + o)[t] = reinterpret_cast<const float4 *>(it.b + (int64_t)i * kBV)[t];
+        reinterpret_cast<float4 *>(d.x + o)[t] = z;
+        reinterpret_cast<float4 *>(d.xn + o)[t] = z;
+        if (t == 0) {
+            it.slots[i] = s;
+            const int32_t c = it.cells[i];
+            if (c >= 0 && c < d.ncells) d.roots[(int64_t)it.gid * d.ncells + c] = s;
+            if (i == 0) {
+                const int64_t now = *d.clock;
+                d.window[2 * it.gid] = now;
+                d.window[2 * it.gid + 1] = now + it.iters;
+            }
+        }
+        return;
+    }
+    if (w - a.adm_blocks >= a.nwork) return;          // the lone workgroup of an empty update
+    const BatchWorkItem &wi = a.w[w - a.adm_blocks];
+    for (int i = t; i < wi.nb; i += blockDim.x) {
+        const int32_t c = wi.cells[i];
+        d.work[wi.off + i] = (c >= 0 && c < d.ncells) ? wi.gid * d.ncells + c : -1;
+    }
 }
 
 // ---------------------------------------------------------------- particles
@@ -2901,6 +2978,22 @@ hipError_t launch_batch_jacobi(const BatchDev &d, int iters, int workgroups, hip
         }
     }
     hipLaunchKernelGGL(k_batch_tick, dim3(1), dim3(64), 0, s, d, iters);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_init(const BatchDev &d, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_init, dim3(256), dim3(256), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_retire(const BatchDev &d, const BatchRetireArgs &a, hipStream_t s) {
+    if (a.blocks > 0) hipLaunchKernelGGL(k_batch_retire, dim3(a.blocks), dim3(128), 0, s, d, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_admit(const BatchDev &d, const BatchAdmitArgs &a, hipStream_t s) {
+    const int wgs = a.adm_blocks + a.nwork;
+    hipLaunchKernelGGL(k_batch_admit, dim3(wgs > 0 ? wgs : 1), dim3(128), 0, s, d, a);
     return hipGetLastError();
 }
 

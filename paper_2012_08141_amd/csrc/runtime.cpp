@@ -1205,11 +1205,20 @@ struct at_batch_s {
     at_batch_desc desc;
     BatchDev dev;
     size_t bytes;
+    // admissions made through at_batch_update (host view)
+    struct Grid {
+        bool live = false;
+        int32_t nb = 0;
+        const int32_t *cells = nullptr;
+        int32_t *slots = nullptr;
+    };
+    std::vector<Grid> grids;
+    int32_t nfree = 0;       // height of the device free-slot stack
 };
 
 namespace {
 struct BatchLayout {
-    size_t clock, count, window, roots, work, rec, x, xn, b, total;
+    size_t clock, count, window, roots, work, rec, free_slots, x, xn, b, total;
 };
 at_status batch_layout(const at_batch_desc *d, BatchLayout &L, int32_t &R) {
     if (!d) return fail(AT_E_INVALID, "null batch description");
@@ -1227,6 +1236,7 @@ at_status batch_layout(const at_batch_desc *d, BatchLayout &L, int32_t &R) {
     L.roots = off; off += align256((size_t)d->max_grids * nc * sizeof(int32_t));
     L.work = off; off += align256((size_t)d->pool_blocks * sizeof(int32_t));
     L.rec = off; off += align256((size_t)d->pool_blocks * 8 * sizeof(int32_t));
+    L.free_slots = off; off += align256((size_t)d->pool_blocks * sizeof(int32_t));
     L.x = off; off += (size_t)d->pool_blocks * kBV * sizeof(float);
     L.xn = off; off += (size_t)d->pool_blocks * kBV * sizeof(float);
     L.b = off; off += (size_t)d->pool_blocks * kBV * sizeof(float);
@@ -1273,13 +1283,17 @@ at_status at_batch_create(const at_batch_desc *desc, void *dev_buf, size_t bytes
     d.x = (float *)(b + L.x);
     d.xn = (float *)(b + L.xn);
     d.b = (float *)(b + L.b);
+    d.free_slots = (int32_t *)(b + L.free_slots);
+    h->grids.resize(desc->max_grids);
+    h->nfree = desc->pool_blocks;
     hipError_t e = hipMemsetAsync(dev_buf, 0, L.total, stream);
     if (e == hipSuccess) e = hipMemsetAsync(d.roots, 0xff, (size_t)d.max_grids * d.ncells * sizeof(int32_t), stream);
+    if (e == hipSuccess) e = launch_batch_init(d, stream);
     if (e != hipSuccess) {
         delete h;
         return hip_fail(e, "batch initialisation");
     }
-    E().dispatches.fetch_add(2);
+    E().dispatches.fetch_add(3);
     *out = h;
     return AT_OK;
 }
@@ -1311,6 +1325,106 @@ at_status at_batch_jacobi(at_batch batch, int32_t iters, int32_t workgroups, hip
     hipError_t e = launch_batch_jacobi(batch->dev, iters, workgroups, stream);
     if (e != hipSuccess) return hip_fail(e, "batched jacobi launch");
     E().dispatches.fetch_add(2 * (int64_t)iters + 2);
+    return AT_OK;
+}
+
+at_status at_batch_update(at_batch batch, const at_batch_retire *retire, int32_t nretire, const at_batch_admit *admit,
+                          int32_t nadmit, hipStream_t stream) {
+    if (!batch) return fail(AT_E_INVALID, "null batch handle");
+    if (nretire < 0 || nadmit < 0) return fail(AT_E_INVALID, "negative retirement or admission count");
+    if ((nretire > 0 && !retire) || (nadmit > 0 && !admit)) return fail(AT_E_INVALID, "null descriptor array");
+    const int32_t G = batch->desc.max_grids, pool = batch->desc.pool_blocks;
+    auto &grids = batch->grids;
+    // validate everything before anything is enqueued
+    std::vector<char> out(G, 0), in(G, 0);
+    int64_t freed = 0, taken = 0;
+    for (int32_t r = 0; r < nretire; ++r) {
+        const int32_t g = retire[r].gid;
+        if (g < 0 || g >= G || !grids[g].live) return fail(AT_E_INVALID, "retirement %d: grid %d is not resident", r, g);
+        if (out[g]) return fail(AT_E_INVALID, "grid %d retired twice in one update", g);
+        if (retire[r].reserved != 0) return fail(AT_E_INVALID, "retirement %d: reserved field must be 0", r);
+        out[g] = 1;
+        freed += grids[g].nb;
+    }
+    for (int32_t a = 0; a < nadmit; ++a) {
+        const at_batch_admit &A = admit[a];
+        if (A.gid < 0 || A.gid >= G) return fail(AT_E_INVALID, "admission %d: grid id %d out of range", a, A.gid);
+        if ((grids[A.gid].live && !out[A.gid]) || in[A.gid])
+            return fail(AT_E_INVALID, "admission %d: grid %d is in use", a, A.gid);
+        if (A.nblocks < 1 || A.nblocks > pool) return fail(AT_E_INVALID, "admission %d: %d blocks", a, A.nblocks);
+        if (A.iters < 0) return fail(AT_E_INVALID, "admission %d: negative iteration count", a);
+        if (!A.cells || !A.b || !A.slots) return fail(AT_E_INVALID, "admission %d: null device array", a);
+        if (A.reserved != 0) return fail(AT_E_INVALID, "admission %d: reserved field must be 0", a);
+        in[A.gid] = 1;
+        taken += A.nblocks;
+    }
+    if (taken > (int64_t)batch->nfree + freed)
+        return fail(AT_E_CAPACITY, "admissions need %lld pool blocks, %lld free", (long long)taken,
+                    (long long)(batch->nfree + freed));
+    const BatchDev &d = batch->dev;
+    int64_t launches = 0;
+    hipError_t e = hipSuccess;
+    // retirements first: their slots go back on the stack, where the
+    // admissions below may take them
+    for (int32_t r0 = 0; r0 < nretire && e == hipSuccess; r0 += kUpdItems) {
+        BatchRetireArgs ra{};
+        for (int32_t r = r0; r < nretire && r < r0 + kUpdItems; ++r) {
+            at_batch_s::Grid &gr = grids[retire[r].gid];
+            BatchRetireItem &it = ra.it[ra.n++];
+            it.gid = retire[r].gid;
+            it.nb = gr.nb;
+            it.q = batch->nfree;
+            it.first = ra.blocks;
+            it.cells = gr.cells;
+            it.slots = gr.slots;
+            it.x_out = retire[r].x_out;
+            ra.blocks += gr.nb;
+            batch->nfree += gr.nb;
+            gr = at_batch_s::Grid{};
+        }
+        e = launch_batch_retire(d, ra, stream);
+        ++launches;
+    }
+    for (int32_t a = 0; a < nadmit; ++a) {
+        at_batch_s::Grid &gr = grids[admit[a].gid];
+        gr.live = true;
+        gr.nb = admit[a].nblocks;
+        gr.cells = admit[a].cells;
+        gr.slots = admit[a].slots;
+    }
+    // admissions, and the work list of every resident grid (ascending grid id)
+    std::vector<BatchWorkItem> work;
+    int32_t count = 0;
+    for (int32_t g = 0; g < G; ++g)
+        if (grids[g].live) {
+            work.push_back(BatchWorkItem{g, grids[g].nb, count, 0, grids[g].cells});
+            count += grids[g].nb;
+        }
+    const int64_t nl = std::max<int64_t>({(nadmit + kUpdItems - 1) / kUpdItems,
+                                          ((int64_t)work.size() + kUpdGrids - 1) / kUpdGrids, (int64_t)1});
+    for (int64_t l = 0; l < nl && e == hipSuccess; ++l) {
+        BatchAdmitArgs aa{};
+        aa.count = count;
+        for (int32_t a = (int32_t)(l * kUpdItems); a < nadmit && a < (l + 1) * kUpdItems; ++a) {
+            BatchAdmitItem &it = aa.it[aa.nadm++];
+            it.gid = admit[a].gid;
+            it.nb = admit[a].nblocks;
+            batch->nfree -= it.nb;
+            it.p = batch->nfree;
+            it.first = aa.adm_blocks;
+            it.iters = admit[a].iters;
+            it.cells = admit[a].cells;
+            it.b = admit[a].b;
+            it.slots = admit[a].slots;
+            aa.adm_blocks += it.nb;
+        }
+        for (size_t w = (size_t)(l * kUpdGrids); w < work.size() && w < (size_t)((l + 1) * kUpdGrids); ++w)
+            aa.w[aa.nwork++] = work[w];
+        e = launch_batch_admit(d, aa, stream);
+        ++launches;
+    }
+    E().dispatches.fetch_add(launches);
+    if (e != hipSuccess) return hip_fail(e, "batch update launch");
     return AT_OK;
 }
 

@@ -10,6 +10,12 @@ on the GPU join them -- and retires the requests whose iteration window has
 ended, freeing their pool space.  Latency is completion minus arrival; the
 completion time of a request is the device time at which the replay that ran
 its last iteration finished.
+
+The loop never waits for the device except to bound the replays in flight:
+a boundary's retirements and admissions are one ``at_batch_update`` (two
+launches, descriptors as kernel arguments), a request's cells and
+right-hand side are on the device from its creation (inputs resident in
+HBM), and completion times are read from events as they complete.
 """
 from __future__ import annotations
 
@@ -38,6 +44,8 @@ class Request:
     result: torch.Tensor = None
     gid: int = -1
     end_clock: int = -1
+    cells_dev: torch.Tensor = None    # the same on the device (uploaded at creation)
+    b_dev: torch.Tensor = None
 
     @property
     def nblocks(self) -> int:
@@ -48,11 +56,17 @@ class Request:
         return self.nblocks * 512 * self.iters
 
 
-def make_requests(seed: int, count: int, arrivals: np.ndarray, n: int = 128, iters: int = 50):
+def make_requests(seed: int, count: int, arrivals: np.ndarray, n: int = 128, iters: int = 50, device="cuda"):
+    """The seeded request stream; each request's cells and b are also put on
+    ``device`` (None: host only)."""
     reqs = []
     for i in range(count):
         w = inputs.batch_request(seed, i, n=n)
-        reqs.append(Request(i, float(arrivals[i]), w.cells, w.channels["b"], iters))
+        r = Request(i, float(arrivals[i]), w.cells, w.channels["b"], iters)
+        if device is not None:
+            r.cells_dev = torch.as_tensor(r.cells.astype(np.int32), device=device)
+            r.b_dev = torch.as_tensor(np.ascontiguousarray(r.b, dtype=np.float32), device=device)
+        reqs.append(r)
     return reqs
 
 
@@ -74,7 +88,7 @@ class ServeStats:
 
 class JacobiServer:
     def __init__(self, n: int = 128, budget_bytes: int = 256 << 20, max_grids: int = 64,
-                 iters_per_replay: int = 10, workgroups: int = 0, max_inflight: int = 2, waves: int = 0):
+                 iters_per_replay: int = 10, workgroups: int = 0, max_inflight: int = 8, waves: int = 0):
         pool = max(1, budget_bytes // BatchArena.footprint(1))
         self.arena = BatchArena(n, max_grids, pool)
         self.budget = budget_bytes
@@ -98,29 +112,49 @@ class JacobiServer:
         start_ev.record()
 
         def finish(ev, clock_after):
-            ev.synchronize()
             t_done = start_ev.elapsed_time(ev) * 1e-3
             for r in [r for r in unfinished.values() if r.end_clock <= clock_after]:
                 del unfinished[r.rid]
                 r.completed = t_done
                 st.latencies.append(t_done - (r.arrival if realtime else 0.0))
 
+        def drain(block_until):
+            # completed replays first, without waiting; then wait for the
+            # oldest while more than block_until are in flight
+            while inflight and inflight[0][0].query():
+                finish(*inflight.popleft())
+            while len(inflight) > block_until:
+                inflight[0][0].synchronize()
+                finish(*inflight.popleft())
+
         while pending or waiting or resident or unfinished:
             now = time.perf_counter() - t0
             while pending and (not realtime or pending[0].arrival <= now):
                 waiting.append(pending.popleft())
-            # retire grids whose last iteration is already enqueued
-            for r in [r for r in resident.values() if r.end_clock <= A.clock_host]:
-                r.result = A.retire(r.gid)
-                del resident[r.rid]
-            # admit FIFO while the footprint fits
-            while waiting and A.fits(waiting[0].nblocks):
+            # retire grids whose last iteration is already enqueued, admit
+            # FIFO while the footprint fits: one update
+            gone = [r for r in resident.values() if r.end_clock <= A.clock_host]
+            free_blocks = A.free_blocks() + sum(r.nblocks for r in gone)
+            free_ids = len(A.free_gids) + len(gone)
+            new = []
+            while waiting and free_ids > 0 and waiting[0].nblocks <= free_blocks:
                 r = waiting.popleft()
-                r.gid = A.admit(r.cells, r.b, r.iters)
-                r.end_clock = A.clock_host + r.iters
-                r.admitted = now
-                resident[r.rid] = r
-                unfinished[r.rid] = r
+                free_blocks -= r.nblocks
+                free_ids -= 1
+                new.append(r)
+            if gone or new:
+                outs, gids = A.update([r.gid for r in gone],
+                                      [(r.cells_dev if r.cells_dev is not None else r.cells,
+                                        r.b_dev if r.b_dev is not None else r.b, r.iters) for r in new])
+                for r, x in zip(gone, outs):
+                    r.result = x
+                    del resident[r.rid]
+                for r, gid in zip(new, gids):
+                    r.gid = gid
+                    r.end_clock = A.clock_host + r.iters
+                    r.admitted = now
+                    resident[r.rid] = r
+                    unfinished[r.rid] = r
             st.max_resident = max(st.max_resident, len(resident))
             if resident:
                 self.graph.replay()
@@ -128,11 +162,9 @@ class JacobiServer:
                 ev = torch.cuda.Event(enable_timing=True)
                 ev.record()
                 inflight.append((ev, A.clock_host))
-                while len(inflight) > self.max_inflight:
-                    finish(*inflight.popleft())
+                drain(self.max_inflight)
             else:
-                while inflight:
-                    finish(*inflight.popleft())
+                drain(0)
                 if waiting:
                     raise RuntimeError("a request of %d blocks can never fit the arena" % waiting[0].nblocks)
                 if pending and realtime:

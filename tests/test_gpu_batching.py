@@ -196,3 +196,58 @@ def test_full_size_requests_alone_mix_and_oracle():
         exp = ref["x"]
         tol = 1e-6 * np.maximum(np.abs(exp), 1e-3 * np.abs(exp).max())
         assert np.all(np.abs(got - exp) <= tol), r.rid
+
+
+def test_batch_update_validation_and_mixed_boundary():
+    """at_batch_update rejects bad descriptors before enqueueing anything
+    (the arena is unchanged afterwards), and one update that retires a grid
+    and admits two others into its slots gives the results of separate
+    calls: every result equals the request solved alone."""
+    import ctypes
+    from paper_2012_08141_amd import _lib as L
+    from paper_2012_08141_amd.batching import BatchArena
+    from paper_2012_08141_amd.grid import current_stream
+    from paper_2012_08141_amd.serving import solve_alone
+    say("batch update")
+    reqs = _requests(3, lo=40, hi=300, iters=10, seed=11)
+    pool = reqs[0].nblocks + max(reqs[1].nblocks + reqs[2].nblocks, 1)
+    arena = BatchArena(128, max_grids=2, pool_blocks=pool)
+    lib = L.lib()
+    cells = torch.as_tensor(reqs[0].cells.astype(np.int32), device="cuda")
+    b = torch.as_tensor(reqs[0].b, device="cuda")
+    slots = torch.empty(len(reqs[0].cells), dtype=torch.int32, device="cuda")
+
+    def adm(gid, nb=None, it=10, reserved=0):
+        return L.AtBatchAdmit(cells.data_ptr(), b.data_ptr(), slots.data_ptr(), gid,
+                              len(reqs[0].cells) if nb is None else nb, it, reserved)
+
+    def call(rets, adms):
+        ra = (L.AtBatchRetire * max(1, len(rets)))(*rets)
+        aa = (L.AtBatchAdmit * max(1, len(adms)))(*adms)
+        return lib.at_batch_update(arena.handle, ra, len(rets), aa, len(adms), current_stream())
+
+    assert call([L.AtBatchRetire(0, 0, None)], []) == L.AT_E_INVALID          # not resident
+    assert call([], [adm(2)]) == L.AT_E_INVALID                               # id out of range
+    assert call([], [adm(0), adm(0)]) == L.AT_E_INVALID                       # same id twice
+    assert call([], [adm(0, nb=0)]) == L.AT_E_INVALID                         # no blocks
+    assert call([], [adm(0, it=-1)]) == L.AT_E_INVALID
+    assert call([], [adm(0, reserved=1)]) == L.AT_E_INVALID
+    assert call([], [adm(0, nb=pool + 1)]) == L.AT_E_INVALID
+    assert call([], [adm(0), adm(1, nb=pool)]) == L.AT_E_CAPACITY
+    torch.cuda.synchronize()
+    assert int(arena.count.item()) == 0
+    # request 0 alone, then one boundary retires it and admits 1 and 2
+    g0 = arena.admit(reqs[0].cells, reqs[0].b, 10)
+    for _ in range(2):
+        arena.step(5)
+    outs, gids = arena.update([g0], [(reqs[1].cells, reqs[1].b, 10), (reqs[2].cells, reqs[2].b, 10)])
+    assert sorted(gids) == [0, 1]
+    res = {0: outs[0]}
+    for _ in range(2):
+        arena.step(5)
+    outs2, _ = arena.update(gids, [])
+    res[1], res[2] = outs2
+    torch.cuda.synchronize()
+    assert int(arena.count.item()) == 0 and arena.free_blocks() == pool
+    for i, r in enumerate(reqs):
+        assert torch.equal(res[i], solve_alone(r, 128, 0)), i
