@@ -478,11 +478,37 @@ at_status at_flush(at_stats *stats, hipStream_t stream);
 #define AT_OPTION_GRAPHS 11
 /* Read-only: the number of window graphs currently cached. */
 #define AT_OPTION_GRAPHS_CACHED 12
+/* Asynchronous flushes (Section 7: the engine's optimizer and launcher run
+ * beside the program): 1 hands every flushed window (at_flush, a periodic
+ * flush, at_run_sequence) to an optimizer thread, which plans the windows in
+ * flush order, and from it to a launcher thread, which launches them on
+ * their streams; the call returns once the window is queued, so the
+ * optimizer plans window k + 1 while window k is being launched and the
+ * caller goes on enqueueing.  Default 0 (planned and launched inside the
+ * call).  Plans, launches and results are those of the synchronous engine.
+ * While windows are in flight every other engine call (activation, list
+ * generation, grid creation and destruction, status reads, options, ...)
+ * first waits until they have all been launched.  at_engine_sync waits
+ * too and reports a failure of an asynchronous window; a failed window
+ * drops the windows after it until the failure is reported.  The stats a
+ * flush or at_run_sequence returns hold only tasks_in; at_engine_sync
+ * returns the counters summed over the windows launched since the last
+ * sync.  Launches happen on the launcher thread, with the device that was
+ * current when the window was flushed; a device synchronisation waits only
+ * for work launched, so call at_engine_sync first. */
+#define AT_OPTION_ASYNC 13
 at_status at_set_option(int32_t option, int64_t value);
 at_status at_get_option(int32_t option, int64_t *value);
 
 /* Forget all engine state (versions, owners, cached plans). */
 at_status at_engine_reset(void);
+
+/* Waits until every window flushed asynchronously (AT_OPTION_ASYNC) has
+ * been launched; stats (nullable) receives the counters summed over the
+ * windows launched since the last sync.  Returns the first failure of such
+ * a window since it was last reported (then cleared), else AT_OK.  A no-op
+ * returning AT_OK when nothing was flushed asynchronously. */
+at_status at_engine_sync(at_stats *stats);
 
 /* Tell the engine an external array was written outside its tasks (bumps
  * the array's state version so no earlier result is reused). */

@@ -40,6 +40,7 @@ AT_OPTION_BIN_REUSE = 9
 AT_OPTION_FUSE_BATCH = 10
 AT_OPTION_GRAPHS = 11
 AT_OPTION_GRAPHS_CACHED = 12
+AT_OPTION_ASYNC = 13
 AT_STATIC_MAX_PARTICLES, AT_STATIC_MAX_CELLS = 1048576, 262144
 
 
@@ -130,6 +131,7 @@ _SIGS = {
     "at_timing_collect": (c_int32, [ctypes.POINTER(AtTimingEntry), c_int32, ctypes.POINTER(c_int32)]),
     "at_get_option": (c_int32, [c_int32, ctypes.POINTER(c_int64)]),
     "at_engine_reset": (c_int32, []),
+    "at_engine_sync": (c_int32, [ctypes.POINTER(AtStats)]),
     "at_ext_modified": (c_int32, [_P]),
     "at_batch_footprint": (c_int32, [ctypes.POINTER(AtBatchDesc), ctypes.POINTER(c_size_t)]),
     "at_batch_create": (c_int32, [ctypes.POINTER(AtBatchDesc), _P, c_size_t, _P, ctypes.POINTER(_P)]),

@@ -13,11 +13,15 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -50,8 +54,37 @@ struct CacheEntry {
     PlanCounters counters;
 };
 
+// A flushed window on its way through the asynchronous pipeline
+// (AT_OPTION_ASYNC): the optimizer thread fills in the plan, the launcher
+// thread launches it.
+struct PendingWindow {
+    std::vector<at_task> tasks;
+    uint32_t flags = 0;
+    hipStream_t stream = nullptr;
+    int device = -1;
+    bool any_virt = false;
+    std::vector<Node> nodes;
+    std::vector<uint8_t> tables;
+    PlanCounters ctr{};
+    int64_t hits = 0;
+    double us = 0;
+};
+
+struct AsyncPipe {
+    std::mutex mu;
+    std::condition_variable cv;      // work arrived, or a worker finished some
+    std::deque<std::unique_ptr<PendingWindow>> to_plan, to_launch;
+    int busy = 0;                    // windows a worker has taken and not finished
+    at_status err = AT_OK;           // first failure since it was last reported
+    std::string msg;
+    at_stats sum{};                  // counters of the windows launched since the last sync
+    std::thread optimizer, launcher;
+};
+
 struct Engine {
     std::recursive_mutex mu;
+    bool async = false;                  // flushes go to the pipeline (AT_OPTION_ASYNC)
+    std::unique_ptr<AsyncPipe> pipe;     // started when async is first switched on
     Persist persist;
     std::unordered_map<uint64_t, CacheEntry> cache;
     int max_fuse = 1;
@@ -554,35 +587,30 @@ bool run_as_graph(const std::vector<Node> &nodes, const at_task *tasks, int ntas
     return true;
 }
 
-at_status run_window(const at_task *tasks, int ntasks, uint32_t flags, at_stats *stats, hipStream_t s) {
-    Engine &en = E();
-    std::lock_guard<std::recursive_mutex> lk(en.mu);
+// Checks a window shares between the synchronous and the asynchronous
+// path; any_virt: it holds planning handles (it then launches nothing).
+at_status check_window(const at_task *tasks, int ntasks, uint32_t flags, bool &any_virt) {
     if (ntasks < 0 || (ntasks > 0 && !tasks)) return fail(AT_E_INVALID, "bad task array");
     if (flags & ~AT_OPT_ALL) return fail(AT_E_INVALID, "unknown optimizer flags");
     // a window on planning handles only records engine state; its tasks
     // without a grid (advection) must not launch on their placeholder arrays
-    bool any_virt = false, any_dev = false;
+    bool any_dev = false;
+    any_virt = false;
     for (int i = 0; i < ntasks; ++i)
         for (const at_grid_s *g : {(const at_grid_s *)tasks[i].grid, (const at_grid_s *)tasks[i].grid2})
             if (g) (g->virt ? any_virt : any_dev) = true;
     if (any_virt && any_dev) return fail(AT_E_INVALID, "a window mixes planning handles and device grids");
-    const auto t0 = std::chrono::steady_clock::now();
-    std::vector<Node> nodes;
-    PlanCounters ctr;
-    int64_t hits = 0;
-    at_status st = plan_window(tasks, ntasks, flags, nodes, ctr, hits);
-    if (st != AT_OK) return st;
-    const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
-    const int64_t d0 = en.dispatches.load();
-    const std::vector<uint8_t> tables = neighbour_tables_valid(nodes, tasks, en.persist);
+    return AT_OK;
+}
+
+// The launch half of a window: its planned nodes in order on stream s.
+at_status launch_window(const std::vector<Node> &nodes, const at_task *tasks, int ntasks, uint32_t flags,
+                        const std::vector<uint8_t> &tables, int64_t hits, bool any_virt, hipStream_t s) {
+    Engine &en = E();
     ++en.window_seq;
     en.pos_writes.clear();
-    if (!any_virt && hits > 0 && run_as_graph(nodes, tasks, ntasks, flags, tables, s, st)) {
-        Planner::commit(nodes, tasks, en.persist);
-        if (st != AT_OK) return st;
-        fill_stats(stats, ntasks, nodes, ctr, en.dispatches.load() - d0, us, hits);
-        return AT_OK;
-    }
+    at_status st = AT_OK;
+    if (!any_virt && hits > 0 && run_as_graph(nodes, tasks, ntasks, flags, tables, s, st)) return st;
     for (size_t i = 0; i < nodes.size() && !any_virt; ++i) {
         const Node &nd = nodes[i];
         hipEvent_t ea = nullptr;
@@ -601,14 +629,200 @@ at_status run_window(const at_task *tasks, int ntasks, uint32_t flags, at_stats 
                 if (eb) en.ev_free.push_back(eb);
             }
         }
-        if (st != AT_OK) {
-            Planner::commit(nodes, tasks, en.persist);
-            return st;
-        }
+        if (st != AT_OK) return st;
     }
+    return AT_OK;
+}
+
+at_status run_window(const at_task *tasks, int ntasks, uint32_t flags, at_stats *stats, hipStream_t s) {
+    Engine &en = E();
+    std::lock_guard<std::recursive_mutex> lk(en.mu);
+    bool any_virt = false;
+    at_status st = check_window(tasks, ntasks, flags, any_virt);
+    if (st != AT_OK) return st;
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<Node> nodes;
+    PlanCounters ctr;
+    int64_t hits = 0;
+    st = plan_window(tasks, ntasks, flags, nodes, ctr, hits);
+    if (st != AT_OK) return st;
+    const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+    const int64_t d0 = en.dispatches.load();
+    const std::vector<uint8_t> tables = neighbour_tables_valid(nodes, tasks, en.persist);
+    st = launch_window(nodes, tasks, ntasks, flags, tables, hits, any_virt, s);
     Planner::commit(nodes, tasks, en.persist);
+    if (st != AT_OK) return st;
     fill_stats(stats, ntasks, nodes, ctr, en.dispatches.load() - d0, us, hits);
     return AT_OK;
+}
+
+// ------------------------------------------------- asynchronous pipeline
+// Flushed windows are planned by an optimizer thread, in flush order, and
+// launched by a launcher thread, so the optimizer plans a window while the
+// previous one is being launched and the caller goes on enqueueing (the
+// paper's asynchronous engine, Section 7).  Planning touches only the
+// persistent graph state and the plan cache; launching only the per-launch
+// state (bin reuse, graphs, timing).  Every other engine call first waits
+// for the pipeline to empty, so program order holds on every stream.
+
+void add_stats(at_stats &a, const at_stats &b) {
+    a.tasks_in += b.tasks_in;
+    a.tasks_launched += b.tasks_launched;
+    a.dispatches += b.dispatches;
+    a.listgens_removed += b.listgens_removed;
+    a.activations_demoted += b.activations_demoted;
+    a.fusions += b.fusions;
+    a.stores_eliminated += b.stores_eliminated;
+    a.plan_cache_hits += b.plan_cache_hits;
+    a.optimizer_us += b.optimizer_us;
+}
+
+void optimizer_loop(AsyncPipe *p) {
+    Engine &en = E();
+    for (;;) {
+        std::unique_ptr<PendingWindow> w;
+        bool failed;
+        {
+            std::unique_lock<std::mutex> lk(p->mu);
+            p->cv.wait(lk, [&] { return !p->to_plan.empty(); });
+            w = std::move(p->to_plan.front());
+            p->to_plan.pop_front();
+            ++p->busy;
+            failed = p->err != AT_OK;
+        }
+        at_status st = AT_OK;
+        if (!failed) {   // after a failure, windows are dropped until it is reported
+            const auto t0 = std::chrono::steady_clock::now();
+            st = plan_window(w->tasks.data(), (int)w->tasks.size(), w->flags, w->nodes, w->ctr, w->hits);
+            if (st == AT_OK) {
+                w->tables = neighbour_tables_valid(w->nodes, w->tasks.data(), en.persist);
+                Planner::commit(w->nodes, w->tasks.data(), en.persist);
+            }
+            w->us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+        }
+        std::lock_guard<std::mutex> lk(p->mu);
+        --p->busy;
+        if (st != AT_OK && p->err == AT_OK) {
+            p->err = st;
+            p->msg = at_last_error();
+        }
+        if (st == AT_OK && !failed) p->to_launch.push_back(std::move(w));
+        p->cv.notify_all();
+    }
+}
+
+void launcher_loop(AsyncPipe *p) {
+    Engine &en = E();
+    int device = -1;
+    for (;;) {
+        std::unique_ptr<PendingWindow> w;
+        bool failed;
+        {
+            std::unique_lock<std::mutex> lk(p->mu);
+            p->cv.wait(lk, [&] { return !p->to_launch.empty(); });
+            w = std::move(p->to_launch.front());
+            p->to_launch.pop_front();
+            ++p->busy;
+            failed = p->err != AT_OK;
+        }
+        at_status st = AT_OK;
+        at_stats one{};
+        if (!failed) {
+            if (w->device >= 0 && w->device != device) {
+                const hipError_t e = hipSetDevice(w->device);
+                if (e != hipSuccess) st = hip_fail(e, "launcher thread device");
+                else device = w->device;
+            }
+            if (st == AT_OK) {
+                const int64_t d0 = en.dispatches.load();
+                st = launch_window(w->nodes, w->tasks.data(), (int)w->tasks.size(), w->flags, w->tables, w->hits,
+                                   w->any_virt, w->stream);
+                fill_stats(&one, (int)w->tasks.size(), w->nodes, w->ctr, en.dispatches.load() - d0, w->us, w->hits);
+            }
+        }
+        std::lock_guard<std::mutex> lk(p->mu);
+        --p->busy;
+        if (st != AT_OK && p->err == AT_OK) {
+            p->err = st;
+            p->msg = at_last_error();
+        }
+        if (st == AT_OK && !failed) add_stats(p->sum, one);
+        p->cv.notify_all();
+    }
+}
+
+void start_pipe() {
+    Engine &en = E();
+    if (en.pipe) return;
+    en.pipe.reset(new AsyncPipe());
+    AsyncPipe *p = en.pipe.get();
+    p->optimizer = std::thread(optimizer_loop, p);
+    p->launcher = std::thread(launcher_loop, p);
+    p->optimizer.detach();
+    p->launcher.detach();
+}
+
+// Waits until every submitted window has been launched.  Returns (and
+// clears) the first failure of a window since the last report when
+// `report`; otherwise it stays for a later report.
+at_status drain_pipe(bool report) {
+    Engine &en = E();
+    AsyncPipe *p = en.pipe.get();
+    if (!p) return AT_OK;
+    std::unique_lock<std::mutex> lk(p->mu);
+    p->cv.wait(lk, [&] { return p->to_plan.empty() && p->to_launch.empty() && p->busy == 0; });
+    if (!report || p->err == AT_OK) return AT_OK;
+    const at_status e = p->err;
+    const std::string msg = p->msg;
+    p->err = AT_OK;
+    p->msg.clear();
+    return fail(e, "%s", msg.c_str());
+}
+
+// Hands a window to the pipeline (the caller holds en.mu).  A failure of an
+// earlier window is reported here first, and this window is then dropped.
+at_status submit_window(const at_task *tasks, int ntasks, uint32_t flags, at_stats *stats, hipStream_t s) {
+    Engine &en = E();
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    bool any_virt = false;
+    at_status st = check_window(tasks, ntasks, flags, any_virt);
+    if (st != AT_OK) return st;
+    for (int i = 0; i < ntasks; ++i) {
+        const std::string msg = validate_task(tasks[i]);
+        if (!msg.empty()) return fail(AT_E_INVALID, "task %d: %s", i, msg.c_str());
+    }
+    start_pipe();
+    AsyncPipe *p = en.pipe.get();
+    auto w = std::unique_ptr<PendingWindow>(new PendingWindow());
+    w->tasks.assign(tasks, tasks + ntasks);
+    w->flags = flags;
+    w->stream = s;
+    w->any_virt = any_virt;
+    int dev = -1;
+    if (!any_virt && hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        dev = -1;
+    }
+    w->device = dev;
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (p->err != AT_OK) {
+        const at_status e = p->err;
+        const std::string msg = p->msg;
+        p->err = AT_OK;
+        p->msg.clear();
+        return fail(e, "an earlier asynchronous window failed: %s", msg.c_str());
+    }
+    if (stats) stats->tasks_in = ntasks;
+    p->to_plan.push_back(std::move(w));
+    p->cv.notify_all();
+    return AT_OK;
+}
+
+// A window from the queue or a caller: through the pipeline when
+// asynchronous, else planned and launched here.
+at_status dispatch_window(const at_task *tasks, int ntasks, uint32_t flags, at_stats *stats, hipStream_t s) {
+    if (E().async) return submit_window(tasks, ntasks, flags, stats, s);
+    return run_window(tasks, ntasks, flags, stats, s);
 }
 
 at_status run_one(const at_task &t, hipStream_t s) {
@@ -616,10 +830,12 @@ at_status run_one(const at_task &t, hipStream_t s) {
     std::lock_guard<std::recursive_mutex> lk(en.mu);
     if (!en.queue.empty()) {
         // keep program order with queued work
-        at_status st = run_window(en.queue.data(), (int)en.queue.size(), en.opt_flags, nullptr, en.queue_stream);
+        at_status st = dispatch_window(en.queue.data(), (int)en.queue.size(), en.opt_flags, nullptr, en.queue_stream);
         en.queue.clear();
         if (st != AT_OK) return st;
     }
+    at_status st = drain_pipe(true);
+    if (st != AT_OK) return st;
     return run_window(&t, 1, 0, nullptr, s);
 }
 
@@ -700,6 +916,7 @@ at_status at_grid_create(const at_grid_desc *desc, void *dev_buf, size_t bytes, 
     }
     {
         std::lock_guard<std::recursive_mutex> lk(E().mu);
+        drain_pipe(false);   // the launcher reads the live-grid map
         g->uid = E().next_uid++;
         E().live[g->uid] = g;
     }
@@ -712,6 +929,7 @@ at_status at_grid_destroy(at_grid grid) {
     {
         Engine &en = E();
         std::lock_guard<std::recursive_mutex> lk(en.mu);
+        drain_pipe(false);
         for (const at_task &t : en.queue)
             if (t.grid == grid || t.grid2 == grid) return fail(AT_E_STATE, "grid has queued tasks; flush first");
         en.persist.forget_grid(grid->uid);
@@ -761,6 +979,7 @@ at_status at_grid_clear(at_grid grid, hipStream_t stream) {
     if (st != AT_OK) return st;
     Engine &en = E();
     std::lock_guard<std::recursive_mutex> lk(en.mu);
+    drain_pipe(false);
     if (!en.queue.empty()) {
         st = run_window(en.queue.data(), (int)en.queue.size(), en.opt_flags, nullptr, en.queue_stream);
         en.queue.clear();
@@ -786,6 +1005,10 @@ at_status at_grid_clear(at_grid grid, hipStream_t stream) {
 at_status at_device_status(at_grid grid, hipStream_t stream, int32_t clear, int32_t *bits) {
     at_status st = check_grid(grid, true);
     if (st != AT_OK) return st;
+    {
+        std::lock_guard<std::recursive_mutex> lk(E().mu);
+        drain_pipe(false);
+    }
     if (!bits) return fail(AT_E_INVALID, "null output");
     hipError_t e = hipMemcpyAsync(bits, grid->dev.hdr + HDR_ERR, sizeof(int32_t), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -800,6 +1023,10 @@ at_status at_device_status(at_grid grid, hipStream_t stream, int32_t clear, int3
 at_status at_active_count(at_grid grid, hipStream_t stream, int64_t *count) {
     at_status st = check_grid(grid, true);
     if (st != AT_OK) return st;
+    {
+        std::lock_guard<std::recursive_mutex> lk(E().mu);
+        drain_pipe(false);
+    }
     if (!count) return fail(AT_E_INVALID, "null output");
     hipError_t e = launch_popcount(grid->dev, stream);
     int32_t v = 0;
@@ -851,6 +1078,7 @@ at_status at_run_stencil(at_grid grid, int32_t op, const int32_t *ch, const floa
     }
     Engine &en = E();
     std::lock_guard<std::recursive_mutex> lk(en.mu);
+    drain_pipe(false);
     if (check_activation) return run_one(t, stream);
     // demoted form requested explicitly: plan with activation demotion only
     if (!en.queue.empty()) {
@@ -913,6 +1141,7 @@ at_status at_p2g_static(at_grid grid, const float *d_x, const float *d_v, const 
     t.flags = AT_TASKF_LOOP_UNIQUE;
     Engine &en = E();
     std::lock_guard<std::recursive_mutex> lk(en.mu);
+    drain_pipe(false);
     if (!en.queue.empty()) {
         st = run_window(en.queue.data(), (int)en.queue.size(), en.opt_flags, nullptr, en.queue_stream);
         en.queue.clear();
@@ -984,6 +1213,7 @@ at_status at_scatter_blocks(at_grid grid, int32_t ch, const int32_t *d_cells, co
     if (n < 0 || (n > 0 && (!d_cells || !d_vals))) return fail(AT_E_INVALID, "bad block arrays");
     Engine &en = E();
     std::lock_guard<std::recursive_mutex> lk(en.mu);
+    drain_pipe(false);
     if (!en.queue.empty()) {
         st = run_window(en.queue.data(), (int)en.queue.size(), en.opt_flags, nullptr, en.queue_stream);
         en.queue.clear();
@@ -1007,6 +1237,7 @@ at_status at_gather_blocks(at_grid grid, int32_t ch, const int32_t *d_cells, flo
     if (n < 0 || (n > 0 && (!d_cells || !d_vals))) return fail(AT_E_INVALID, "bad block arrays");
     Engine &en = E();
     std::lock_guard<std::recursive_mutex> lk(en.mu);
+    drain_pipe(false);
     if (!en.queue.empty()) {
         st = run_window(en.queue.data(), (int)en.queue.size(), en.opt_flags, nullptr, en.queue_stream);
         en.queue.clear();
@@ -1024,11 +1255,24 @@ at_status at_run_sequence(const at_task *tasks, int32_t ntasks, uint32_t opt_fla
     Engine &en = E();
     std::lock_guard<std::recursive_mutex> lk(en.mu);
     if (!en.queue.empty()) {
-        at_status st = run_window(en.queue.data(), (int)en.queue.size(), en.opt_flags, nullptr, en.queue_stream);
+        at_status st = dispatch_window(en.queue.data(), (int)en.queue.size(), en.opt_flags, nullptr, en.queue_stream);
         en.queue.clear();
         if (st != AT_OK) return st;
     }
-    return run_window(tasks, ntasks, opt_flags, stats, stream);
+    return dispatch_window(tasks, ntasks, opt_flags, stats, stream);
+}
+
+at_status at_engine_sync(at_stats *stats) {
+    Engine &en = E();
+    std::lock_guard<std::recursive_mutex> lk(en.mu);
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    at_status st = drain_pipe(true);
+    if (en.pipe) {
+        std::lock_guard<std::mutex> pl(en.pipe->mu);
+        if (stats) *stats = en.pipe->sum;
+        en.pipe->sum = at_stats{};
+    }
+    return st;
 }
 
 at_status at_plan_sequence(const at_task *tasks, int32_t ntasks, uint32_t opt_flags, at_plan_entry *out,
@@ -1043,6 +1287,7 @@ at_status at_plan_sequence(const at_task *tasks, int32_t ntasks, uint32_t opt_fl
     PlanCounters ctr;
     int64_t hits = 0;
     // planning must not populate the cache with a plan that was never run
+    drain_pipe(false);
     const bool cache = en.plan_cache;
     en.plan_cache = false;
     at_status st = plan_window(tasks, ntasks, opt_flags, nodes, ctr, hits);
@@ -1077,14 +1322,14 @@ at_status at_enqueue(const at_task *task, hipStream_t stream) {
     Engine &en = E();
     std::lock_guard<std::recursive_mutex> lk(en.mu);
     if (!en.queue.empty() && stream != en.queue_stream) {
-        at_status st = run_window(en.queue.data(), (int)en.queue.size(), en.opt_flags, nullptr, en.queue_stream);
+        at_status st = dispatch_window(en.queue.data(), (int)en.queue.size(), en.opt_flags, nullptr, en.queue_stream);
         en.queue.clear();
         if (st != AT_OK) return st;
     }
     en.queue.push_back(*task);
     en.queue_stream = stream;
     if (en.flush_period > 0 && (int64_t)en.queue.size() >= en.flush_period) {
-        at_status st = run_window(en.queue.data(), (int)en.queue.size(), en.opt_flags, nullptr, en.queue_stream);
+        at_status st = dispatch_window(en.queue.data(), (int)en.queue.size(), en.opt_flags, nullptr, en.queue_stream);
         en.queue.clear();
         return st;
     }
@@ -1099,7 +1344,7 @@ at_status at_flush(at_stats *stats, hipStream_t stream) {
         return AT_OK;
     }
     (void)stream;
-    at_status st = run_window(en.queue.data(), (int)en.queue.size(), en.opt_flags, stats, en.queue_stream);
+    at_status st = dispatch_window(en.queue.data(), (int)en.queue.size(), en.opt_flags, stats, en.queue_stream);
     en.queue.clear();
     return st;
 }
@@ -1107,7 +1352,12 @@ at_status at_flush(at_stats *stats, hipStream_t stream) {
 at_status at_set_option(int32_t option, int64_t value) {
     Engine &en = E();
     std::lock_guard<std::recursive_mutex> lk(en.mu);
+    drain_pipe(false);
     switch (option) {
+    case AT_OPTION_ASYNC:
+        if (value != 0 && value != 1) return fail(AT_E_INVALID, "async must be 0 or 1");
+        en.async = value != 0;
+        return AT_OK;
     case AT_OPTION_MAX_FUSE_PER_TASK:
         if (value < 1 || value > 64) return fail(AT_E_INVALID, "max_fuse_per_task must be in 1..64");
         en.max_fuse = (int)value;
@@ -1177,6 +1427,7 @@ at_status at_get_option(int32_t option, int64_t *value) {
     case AT_OPTION_FUSE_BATCH: *value = en.fuse_batch ? 1 : 0; return AT_OK;
     case AT_OPTION_GRAPHS: *value = en.graphs ? 1 : 0; return AT_OK;
     case AT_OPTION_GRAPHS_CACHED: *value = (int64_t)en.graph_cache.size(); return AT_OK;
+    case AT_OPTION_ASYNC: *value = en.async ? 1 : 0; return AT_OK;
     default: return fail(AT_E_INVALID, "unknown option %d", option);
     }
 }
@@ -1184,6 +1435,13 @@ at_status at_get_option(int32_t option, int64_t *value) {
 at_status at_engine_reset(void) {
     Engine &en = E();
     std::lock_guard<std::recursive_mutex> lk(en.mu);
+    drain_pipe(false);
+    if (en.pipe) {
+        std::lock_guard<std::mutex> pl(en.pipe->mu);
+        en.pipe->err = AT_OK;
+        en.pipe->msg.clear();
+        en.pipe->sum = at_stats{};
+    }
     en.persist = Persist{};
     en.cache.clear();
     en.queue.clear();
@@ -1195,6 +1453,7 @@ at_status at_ext_modified(const void *ptr) {
     if (!ptr) return fail(AT_E_INVALID, "null pointer");
     Engine &en = E();
     std::lock_guard<std::recursive_mutex> lk(en.mu);
+    drain_pipe(false);
     en.persist.version[StateKey{(uint64_t)(uintptr_t)ptr, -1, ST_EXT}] += 1;
     return AT_OK;
 }
@@ -1433,6 +1692,7 @@ int64_t at_dispatch_count(void) { return E().dispatches.load(); }
 at_status at_timing_enable(int32_t on) {
     Engine &en = E();
     std::lock_guard<std::recursive_mutex> lk(en.mu);
+    drain_pipe(false);
     en.timing = on != 0;
     return AT_OK;
 }
@@ -1441,6 +1701,7 @@ at_status at_timing_collect(at_timing_entry *out, int32_t cap, int32_t *n) {
     if (cap < 0 || (cap > 0 && !out) || !n) return fail(AT_E_INVALID, "bad output array");
     Engine &en = E();
     std::lock_guard<std::recursive_mutex> lk(en.mu);
+    drain_pipe(false);
     std::vector<at_timing_entry> acc;
     hipError_t err = hipSuccess;
     for (const Engine::Timed &t : en.timed) {

@@ -282,6 +282,22 @@ def flush(stream=None) -> dict:
     return st.as_dict()
 
 
+def sync() -> dict:
+    """Wait until every window flushed asynchronously (AT_OPTION_ASYNC) has
+    been launched; returns their counters summed since the last sync, and
+    raises the first failure of such a window.  Call it before a device
+    synchronisation or before reading results."""
+    st = L.AtStats()
+    L.check(L.lib().at_engine_sync(ctypes.byref(st)))
+    return st.as_dict()
+
+
+def set_async(on: bool = True):
+    """Hand flushed windows to the optimizer and launcher threads (True) or
+    plan and launch them inside each call (False, the default)."""
+    set_option(L.AT_OPTION_ASYNC, 1 if on else 0)
+
+
 def set_option(option: int, value: int):
     L.check(L.lib().at_set_option(option, value))
 
