@@ -850,6 +850,8 @@ def main():
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--load", type=float, default=0.8)
     ap.add_argument("--budget-mib", type=int, default=256)
+    ap.add_argument("--no-variants", action="store_true",
+                    help="run fused element-wise nodes in the interpreter, not their compiled variants")
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (no CPU baseline)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, one plain torch copy of this many MiB (the known-size kernel that "
@@ -872,6 +874,13 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench needs a HIP device"
     torch.cuda.set_device(0)
+    from paper_2012_08141_amd import _lib as L
+    from paper_2012_08141_amd import engine as E
+    # fused element-wise struct-fors run their compiled variants, built at
+    # first use (inside the untimed warm-up windows); unfused (eager) tasks
+    # never use them
+    if not args.no_variants:
+        E.set_option(L.AT_OPTION_VARIANTS, 2)
     settle_host()
     fn = {"band512": bench_band, "shell": bench_shell, "particles": bench_particles, "serving": bench_serving,
           "diffusion": bench_diffusion, "multigrid": bench_multigrid,
@@ -886,6 +895,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = 4 * n
+    out["compiled_variants"] = E.get_option(L.AT_OPTION_VARIANTS_LOADED)
     print(json.dumps(out), flush=True)
 
 

@@ -497,11 +497,34 @@ at_status at_flush(at_stats *stats, hipStream_t stream);
  * current when the window was flushed; a device synchronisation waits only
  * for work launched, so call at_engine_sync first. */
 #define AT_OPTION_ASYNC 13
+/* Runtime-compiled variants (Sections 5 and 7.2: fused kernels compiled in
+ * parallel with the program and kept in a cache): a fused struct-for of two
+ * or more COPY, AXPY, INC, FILL and NORMALISE ops with no activation check
+ * runs a kernel generated for its exact op sequence, compiled with hiprtc
+ * for gfx950 and kept in memory and in $XDG_CACHE_HOME/atsparse/variants
+ * (else ~/.cache/atsparse/variants), instead of the per-voxel interpreter.
+ * It keeps each channel's value in registers from op to op and stores each
+ * written channel once: same results, bit for bit.  0 (default): off; 1:
+ * the first use queues the compilation on a worker thread and the node runs
+ * the interpreter until the variant is loaded; 2: the first use compiles
+ * (or reads the disk cache) before launching.  At most 256 variants. */
+#define AT_OPTION_VARIANTS 14
+/* Read-only: variants loaded on a device so far. */
+#define AT_OPTION_VARIANTS_LOADED 15
 at_status at_set_option(int32_t option, int64_t value);
 at_status at_get_option(int32_t option, int64_t *value);
 
 /* Forget all engine state (versions, owners, cached plans). */
 at_status at_engine_reset(void);
+
+/* Generates and compiles, ahead of any launch, the variant
+ * (AT_OPTION_VARIANTS) of a fused struct-for made of `tasks` in order (2 ..
+ * 16 struct-for tasks of one grid, all stores kept), storing it in the
+ * cache; no device is needed.  src (cap bytes, nullable when cap is 0)
+ * receives the generated source, NUL-terminated and truncated to cap - 1,
+ * and len (nullable) its full length.  AT_E_UNSUPPORTED when an op has no
+ * variant form or the compilation failed; AT_E_INVALID for bad tasks. */
+at_status at_variant_prepare(const at_task *tasks, int32_t ntasks, char *src, size_t cap, size_t *len);
 
 /* Waits until every window flushed asynchronously (AT_OPTION_ASYNC) has
  * been launched; stats (nullable) receives the counters summed over the

@@ -41,6 +41,8 @@ AT_OPTION_FUSE_BATCH = 10
 AT_OPTION_GRAPHS = 11
 AT_OPTION_GRAPHS_CACHED = 12
 AT_OPTION_ASYNC = 13
+AT_OPTION_VARIANTS = 14
+AT_OPTION_VARIANTS_LOADED = 15
 AT_STATIC_MAX_PARTICLES, AT_STATIC_MAX_CELLS = 1048576, 262144
 
 
@@ -132,6 +134,8 @@ _SIGS = {
     "at_get_option": (c_int32, [c_int32, ctypes.POINTER(c_int64)]),
     "at_engine_reset": (c_int32, []),
     "at_engine_sync": (c_int32, [ctypes.POINTER(AtStats)]),
+    "at_variant_prepare": (c_int32, [ctypes.POINTER(AtTask), c_int32, ctypes.c_char_p, c_size_t,
+                                     ctypes.POINTER(c_size_t)]),
     "at_ext_modified": (c_int32, [_P]),
     "at_batch_footprint": (c_int32, [ctypes.POINTER(AtBatchDesc), ctypes.POINTER(c_size_t)]),
     "at_batch_create": (c_int32, [ctypes.POINTER(AtBatchDesc), _P, c_size_t, _P, ctypes.POINTER(_P)]),

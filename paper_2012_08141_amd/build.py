@@ -24,6 +24,7 @@ SOURCES = {
     "mpm.hip": "hip",
     "sfg.cpp": "cxx",
     "runtime.cpp": "cxx",
+    "jit.cpp": "cxx",
 }
 HEADERS = ["internal.hpp", "sfg.hpp", "grid_device.hpp"]
 
@@ -50,7 +51,7 @@ def build(verbose: bool = False) -> str:
         objs = list(ex.map(lambda kv: _compile(kv[0], kv[1], verbose), SOURCES.items()))
     tmp = LIB + ".tmp"
     cmd = [os.path.join(ROCM, "bin", "hipcc"), "-shared", "-fPIC", "--offload-arch=gfx950", *objs,
-           "-o", tmp, "-Wl,-soname,libatsparse.so"]
+           "-o", tmp, "-Wl,-soname,libatsparse.so", "-L" + os.path.join(ROCM, "lib"), "-lhiprtc"]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

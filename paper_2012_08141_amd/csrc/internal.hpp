@@ -4,6 +4,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <string>
 
 #include "atsparse.h"
 
@@ -173,6 +174,18 @@ hipError_t launch_listgen(const GridDev &g, uint64_t *flags, uint32_t epoch, hip
 hipError_t launch_stencil(const GridDev &g, int op, const int32_t *ch, float p, int check, int table,
                           hipStream_t s);
 hipError_t launch_micro(const GridDev &g, const MicroProg &prog, hipStream_t s);
+int wave_grid_size(const GridDev &g, bool pipelined);   // workgroups of the one-wavefront-per-block kernels
+
+// Runtime-compiled variants of fused element-wise programs (jit.cpp).
+// variant_launch: launches the program through its compiled variant when
+// one is loaded (true; err has the launch status), else false (the caller
+// runs the interpreter), queueing or doing the compilation per the mode.
+bool variant_eligible(const MicroProg &prog);
+bool variant_launch(const GridDev &g, const MicroProg &prog, hipStream_t s, hipError_t &err);
+bool variant_prepare(const MicroProg &prog, std::string &src);   // generate and compile now (no device needed)
+void set_variant_mode(int mode);   // 0 off, 1 compile in the background, 2 compile at first use
+int variant_mode();
+int64_t variants_loaded();
 // A fused node whose first member is a single-output stencil op (LAP_UPDATE,
 // JACOBI, DIFFUSE, channels ch) and whose other members are element-wise ops
 // accepted by tail_op_supported (tail); neighbour slots from the list

@@ -251,7 +251,7 @@ at_status execute_node(const Node &nd, const at_task *tasks, bool table, hipStre
                 op.p1 = t.param[1];
                 op.p2 = t.param[2];
             }
-            e = launch_micro(g->dev, prog, s);
+            if (!variant_launch(g->dev, prog, s, e)) e = launch_micro(g->dev, prog, s);
         }
         break;
     }
@@ -1262,6 +1262,37 @@ at_status at_run_sequence(const at_task *tasks, int32_t ntasks, uint32_t opt_fla
     return dispatch_window(tasks, ntasks, opt_flags, stats, stream);
 }
 
+at_status at_variant_prepare(const at_task *tasks, int32_t ntasks, char *src, size_t cap, size_t *len) {
+    if (ntasks < 2 || ntasks > kMaxOps || !tasks) return fail(AT_E_INVALID, "a variant takes 2 .. %d tasks", kMaxOps);
+    if (cap > 0 && !src) return fail(AT_E_INVALID, "null source buffer");
+    MicroProg prog{};
+    prog.nops = ntasks;
+    for (int32_t i = 0; i < ntasks; ++i) {
+        const at_task &t = tasks[i];
+        const std::string msg = validate_task(t);
+        if (!msg.empty()) return fail(AT_E_INVALID, "task %d: %s", i, msg.c_str());
+        if (t.kind != AT_TASK_STENCIL || t.grid != tasks[0].grid)
+            return fail(AT_E_UNSUPPORTED, "task %d: variants cover struct-for tasks of one grid", i);
+        MicroOp &op = prog.ops[i];
+        op.op = t.op;
+        for (int c = 0; c < 7; ++c) op.ch[c] = t.ch[c];
+        op.p = t.param[0];
+        op.keep = ~0u;
+        op.p1 = t.param[1];
+        op.p2 = t.param[2];
+    }
+    if (!variant_eligible(prog)) return fail(AT_E_UNSUPPORTED, "variants cover copy, axpy, inc, fill and normalise");
+    std::string s;
+    if (!variant_prepare(prog, s)) return fail(AT_E_UNSUPPORTED, "the variant did not compile");
+    if (len) *len = s.size();
+    if (cap > 0) {
+        const size_t n = s.size() < cap - 1 ? s.size() : cap - 1;
+        std::memcpy(src, s.data(), n);
+        src[n] = 0;
+    }
+    return AT_OK;
+}
+
 at_status at_engine_sync(at_stats *stats) {
     Engine &en = E();
     std::lock_guard<std::recursive_mutex> lk(en.mu);
@@ -1358,6 +1389,11 @@ at_status at_set_option(int32_t option, int64_t value) {
         if (value != 0 && value != 1) return fail(AT_E_INVALID, "async must be 0 or 1");
         en.async = value != 0;
         return AT_OK;
+    case AT_OPTION_VARIANTS:
+        if (value < 0 || value > 2) return fail(AT_E_INVALID, "variants must be 0, 1 or 2");
+        set_variant_mode((int)value);
+        return AT_OK;
+    case AT_OPTION_VARIANTS_LOADED: return fail(AT_E_INVALID, "the number of loaded variants is read-only");
     case AT_OPTION_MAX_FUSE_PER_TASK:
         if (value < 1 || value > 64) return fail(AT_E_INVALID, "max_fuse_per_task must be in 1..64");
         en.max_fuse = (int)value;
@@ -1428,6 +1464,8 @@ at_status at_get_option(int32_t option, int64_t *value) {
     case AT_OPTION_GRAPHS: *value = en.graphs ? 1 : 0; return AT_OK;
     case AT_OPTION_GRAPHS_CACHED: *value = (int64_t)en.graph_cache.size(); return AT_OK;
     case AT_OPTION_ASYNC: *value = en.async ? 1 : 0; return AT_OK;
+    case AT_OPTION_VARIANTS: *value = variant_mode(); return AT_OK;
+    case AT_OPTION_VARIANTS_LOADED: *value = variants_loaded(); return AT_OK;
     default: return fail(AT_E_INVALID, "unknown option %d", option);
     }
 }

@@ -14,6 +14,23 @@ def pytest_configure(config):
 
 
 @pytest.fixture(scope="session", autouse=True)
+def private_caches(tmp_path_factory):
+    """Caches the library and the compiler write (the autotuner's choices,
+    compiled variants, the code-object compiler's own cache) go to a
+    temporary directory for the session, not to the user's home."""
+    d = str(tmp_path_factory.mktemp("cache"))
+    old = {k: os.environ.get(k) for k in ("XDG_CACHE_HOME", "AMD_COMGR_CACHE_DIR")}
+    os.environ["XDG_CACHE_HOME"] = d
+    os.environ["AMD_COMGR_CACHE_DIR"] = os.path.join(d, "comgr")
+    yield d
+    for k, v in old.items():
+        if v is None:
+            os.environ.pop(k, None)
+        else:
+            os.environ[k] = v
+
+
+@pytest.fixture(scope="session", autouse=True)
 def library_built():
     """Build libatsparse.so (host cross-compile) if the tree has none at all;
     an existing build is used as is (rebuilding after a source change is the

@@ -1,0 +1,86 @@
+"""Runtime-compiled variants of fused element-wise struct-fors (host only:
+generation and compilation need no device).
+
+The generated kernel keeps each channel's value in registers from op to op:
+a channel is loaded at most once (before its first use, and only when an
+op reads it before anything writes it) and stored once at the end when
+written.  The device tests compare it with the interpreter bit for bit."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2012_08141_amd import _lib as L
+from paper_2012_08141_amd import engine as E
+from paper_2012_08141_amd.grid import SparseGrid
+
+
+def prepare(tasks):
+    arr = E._array(tasks)
+    buf = ctypes.create_string_buffer(1 << 16)
+    n = ctypes.c_size_t()
+    st = L.lib().at_variant_prepare(arr, len(tasks), buf, len(buf), ctypes.byref(n))
+    return st, buf.value.decode(), n.value
+
+
+def loads_stores(src):
+    loads = sorted(int(c) for c in re.findall(r"= \*reinterpret_cast<const float4 \*>\(ch \+ (\d+)LL", src))
+    stores = sorted(int(c) for c in re.findall(r"\*reinterpret_cast<float4 \*>\(ch \+ (\d+)LL \* stride \+ off\) =", src))
+    return loads, stores
+
+
+@pytest.fixture
+def grid():
+    return SparseGrid(64, 8, "bitmask", device=None)
+
+
+def test_seed_program_compiles_with_one_load_and_store_per_channel(grid, private_caches):
+    g = grid
+    # the differentiation seed: grad_k = 0; lam = a_T; lam += a_T; lam += -2 target
+    st, src, n = prepare([E.fill(g, [3], 0.0), E.copy(g, 1, 0), E.axpy(g, 1, 0, 1.0), E.axpy(g, 1, 2, -2.0)])
+    assert st == L.AT_OK, L.lib().at_last_error()
+    assert n == len(src) and "extern \"C\" __global__" in src
+    loads, stores = loads_stores(src)
+    assert loads == [0, 2] and stores == [1, 3]
+    # the code object is in the disk cache
+    d = os.path.join(private_caches, "atsparse", "variants")
+    assert any(f.endswith(".co") for f in os.listdir(d))
+    # a second prepare finds it (same source, no new file)
+    before = set(os.listdir(d))
+    assert prepare([E.fill(g, [3], 0.0), E.copy(g, 1, 0), E.axpy(g, 1, 0, 1.0), E.axpy(g, 1, 2, -2.0)])[0] == L.AT_OK
+    assert set(os.listdir(d)) == before
+
+
+def test_fill_array_and_chains(grid):
+    g = grid
+    st, src, _ = prepare([E.fill(g, [0], 7.0) for _ in range(10)])
+    assert st == L.AT_OK
+    assert loads_stores(src) == ([], [0])
+    # chain_copy: y = x + 1, z = y + 4
+    st, src, _ = prepare([E.copy(g, 1, 0), E.inc(g, 1, 1.0), E.copy(g, 2, 1), E.inc(g, 2, 4.0)])
+    assert st == L.AT_OK
+    assert loads_stores(src) == ([0], [1, 2])
+    # normalise (m, mv -> v) after clearing another grid's channels
+    st, src, _ = prepare([E.normalise(g, 0, 1, 4), E.fill(g, [0, 1, 2, 3], 0.0)])
+    assert st == L.AT_OK
+    assert loads_stores(src) == ([0, 1, 2, 3], [0, 1, 2, 3, 4, 5, 6])
+
+
+def test_unsupported_programs(grid):
+    g = grid
+    assert prepare([E.jacobi(g, 0, 1, 2), E.copy(g, 0, 2)])[0] == L.AT_E_UNSUPPORTED
+    assert prepare([E.copy(g, 0, 1)])[0] == L.AT_E_INVALID          # one task: no fusion
+    other = SparseGrid(64, 8, "bitmask", device=None)
+    assert prepare([E.copy(g, 0, 1), E.copy(other, 0, 1)])[0] == L.AT_E_UNSUPPORTED
+
+
+def test_variant_options():
+    assert E.get_option(L.AT_OPTION_VARIANTS) == 0
+    for m in (1, 2, 0):
+        E.set_option(L.AT_OPTION_VARIANTS, m)
+        assert E.get_option(L.AT_OPTION_VARIANTS) == m
+    with pytest.raises(L.AtError):
+        E.set_option(L.AT_OPTION_VARIANTS, 3)
+    with pytest.raises(L.AtError):
+        E.set_option(L.AT_OPTION_VARIANTS_LOADED, 1)
