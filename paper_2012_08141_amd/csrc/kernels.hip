@@ -709,6 +709,131 @@ __global__ __launch_bounds__(64) void k_stencil_pipe(GridDev g, const int32_t *_
     }
 }
 
+// ------------------------------------- pipelined stencil, LDS-staged rows
+// The one-input ops (LAP_UPDATE, JACOBI) with the rows a lane needs from the
+// rest of its block, and from the four lateral neighbour faces, taken from
+// LDS instead of being loaded again through the vector memory path: per
+// block and lane the loads are the own row (2 x 16 B), a quarter-row of one
+// lateral neighbour face (16 B: lanes 16f .. 16f + 15 load face f), the two
+// k-end values and, for JACOBI, b (2 x 16 B) -- 7 loads instead of 14.  The
+// wave (one per workgroup) writes its block's rows and the faces to LDS,
+// split into the first and second float4 of every row so that the 16-byte
+// reads of 64 lanes fall on distinct banks, then reads the i -+ 1 and j -+ 1
+// rows from there.  Software-pipelined as k_stencil_pipe: the next block's
+// loads are in flight while the current block is computed; a wave-scope
+// fence keeps the LDS writes and reads in program order across lanes (LDS
+// operations of one wave execute in order).  Same values, same arithmetic.
+constexpr bool kStencilLds = true;
+
+template <bool HAS_E>
+struct BlkL {
+    int32_t slot;
+    float4 c0, c1;       // own row
+    float4 face;         // this lane's piece of a lateral face (zero when absent)
+    float km, kp;        // k-1 / k+1 beyond the row
+    float4 e0, e1;       // elementwise input
+};
+
+template <bool HAS_E>
+__device__ __forceinline__ void fetch_blk_lds(const StencilCh &c, const int32_t *__restrict__ recs, int e, int lane,
+                                              BlkL<HAS_E> &B) {
+    const int4 *r = reinterpret_cast<const int4 *>(recs + (int64_t)e * kRec);
+    const int4 a = r[0], b = r[1];
+    const int32_t slot = a.y;
+    B.slot = slot;
+    const int64_t own = (int64_t)slot * kBV;
+    const float *ch = c.tin[0];
+    B.c0 = *reinterpret_cast<const float4 *>(ch + own + lane * 8);
+    B.c1 = *reinterpret_cast<const float4 *>(ch + own + lane * 8 + 4);
+    // face f of the neighbour across it: i-1 (its plane i = 7), i+1 (i = 0),
+    // j-1 (j = 7), j+1 (j = 0); piece q = 2 * row + half
+    const int f = lane >> 4, q = lane & 15, row = q >> 1, h = q & 1;
+    const int32_t nf = f == 0 ? a.z : f == 1 ? a.w : f == 2 ? b.x : b.y;
+    const int fo = f == 0 ? 7 * 64 + row * 8 : f == 1 ? row * 8 : f == 2 ? row * 64 + 7 * 8 : row * 64;
+    const float4 fv = *reinterpret_cast<const float4 *>(ch + (nf >= 0 ? (int64_t)nf * kBV : own) + fo + 4 * h);
+    B.face = nf >= 0 ? fv : make_float4(0.f, 0.f, 0.f, 0.f);
+    const int64_t kmb = (b.z >= 0 ? (int64_t)b.z * kBV : own) + lane * 8 + 7;
+    const int64_t kpb = (b.w >= 0 ? (int64_t)b.w * kBV : own) + lane * 8;
+    const float km = ch[kmb], kp = ch[kpb];
+    B.km = b.z >= 0 ? km : 0.f;
+    B.kp = b.w >= 0 ? kp : 0.f;
+    if (HAS_E) {
+        B.e0 = *reinterpret_cast<const float4 *>(c.ein + own + lane * 8);
+        B.e1 = *reinterpret_cast<const float4 *>(c.ein + own + lane * 8 + 4);
+    }
+}
+
+template <int OP, bool CHECK, int KIND>
+__global__ __launch_bounds__(64) void k_stencil_lds(GridDev g, const int32_t *__restrict__ recs, StencilCh c, float p) {
+    constexpr bool HAS_E = OP == AT_OP_JACOBI;
+    __shared__ float4 s_own[2][64];       // [half][row]: float4 h of row (i, j) = lane
+    __shared__ float4 s_face[2][4][8];    // [half][face][row]
+    const int lane = threadIdx.x;
+    const int li = lane >> 3, lj = lane & 7;
+    const int f = lane >> 4, frow = (lane & 15) >> 1, fh = lane & 1;
+    // LDS sources of this lane's i-1, i+1, j-1, j+1 rows: the own block's
+    // row, or row lj (i faces) / li (j faces) of a face
+    const float4 *src[4] = {li > 0 ? &s_own[0][lane - 8] : &s_face[0][0][lj],
+                            li < 7 ? &s_own[0][lane + 8] : &s_face[0][1][lj],
+                            lj > 0 ? &s_own[0][lane - 1] : &s_face[0][2][li],
+                            lj < 7 ? &s_own[0][lane + 1] : &s_face[0][3][li]};
+    const int hstride[4] = {li > 0 ? 64 : 32, li < 7 ? 64 : 32, lj > 0 ? 64 : 32, lj < 7 ? 64 : 32};
+    const ListRange lr = list_range(g.hdr[HDR_COUNT]);
+    if (lr.lo >= lr.hi) return;
+    BlkL<HAS_E> cur, nxt;
+    fetch_blk_lds<HAS_E>(c, recs, __builtin_amdgcn_readfirstlane(lr.lo), lane, cur);
+    for (int e = lr.lo; e < lr.hi; e += lr.step) {
+        const int en = e + lr.step < lr.hi ? e + lr.step : e;
+        fetch_blk_lds<HAS_E>(c, recs, __builtin_amdgcn_readfirstlane(en), lane, nxt);
+        int32_t wslot = cur.slot;
+        if (CHECK) {
+            const int32_t cell = recs[(int64_t)e * kRec];
+            int32_t a = 0;
+            if (lane == 0) a = activate_cell<KIND>(g, cell);
+            wslot = __builtin_amdgcn_readfirstlane(a);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");   // the last block's reads come first
+        s_own[0][lane] = cur.c0;
+        s_own[1][lane] = cur.c1;
+        s_face[fh][f][frow] = cur.face;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");   // then this block's writes
+        Row X;
+        put8(X.c, cur.c0, cur.c1);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) put8(X.f[d], src[d][0], src[d][hstride[d]]);
+        X.f[4][0] = cur.km;
+        X.f[5][7] = cur.kp;
+#pragma unroll
+        for (int q = 1; q < 8; ++q) X.f[4][q] = X.c[q - 1];
+#pragma unroll
+        for (int q = 0; q < 7; ++q) X.f[5][q] = X.c[q + 1];
+        const int64_t off = (int64_t)wslot * kBV + lane * 8;
+        float r0[8];
+        if (OP == AT_OP_LAP_UPDATE) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const float sum = nbsum(X, q);
+                const float six_a = 6.0f * X.c[q];
+                const float d = sum - six_a;
+                const float tq = p * d;
+                r0[q] = X.c[q] + tq;
+            }
+        } else {
+            float bb[8];
+            put8(bb, cur.e0, cur.e1);
+            const float sixth = 0x1.555556p-3f;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const float sum = nbsum(X, q);
+                const float tq = sum + bb[q];
+                r0[q] = tq * sixth;
+            }
+        }
+        store8(c.out0 + off, r0);
+        cur = nxt;
+    }
+}
+
 // A fused struct-for whose first member is a single-output stencil op
 // (LAP_UPDATE, JACOBI, DIFFUSE) followed by element-wise ops (AXPY, INC,
 // COPY, FILL): the stencil runs pipelined as above and the element-wise ops
@@ -2607,7 +2732,9 @@ hipError_t launch_listgen(const GridDev &g, uint64_t *flags, uint32_t epoch, hip
 template <int OP, int KIND, bool CHECK>
 static void launch_stencil_c(const GridDev &g, const StencilCh &c, float p, int table, hipStream_t s) {
     const dim3 grid(wave_grid_size(g, table && g_sf_kernel == 0)), block(64);
-    if (table && g_sf_kernel == 0)
+    if (table && g_sf_kernel == 0 && kStencilLds && (OP == AT_OP_LAP_UPDATE || OP == AT_OP_JACOBI))
+        hipLaunchKernelGGL((k_stencil_lds<OP, CHECK, KIND>), grid, block, 0, s, g, (const int32_t *)g.list, c, p);
+    else if (table && g_sf_kernel == 0)
         hipLaunchKernelGGL((k_stencil_pipe<OP, KIND, CHECK>), grid, block, 0, s, g, (const int32_t *)g.list, c, p);
     else if (table && g_sf_kernel == 1)
         hipLaunchKernelGGL((k_stencil<OP, KIND, CHECK, true>), grid, block, 0, s, g, c, p);
