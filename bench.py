@@ -45,8 +45,8 @@ MPM_FLOPS_PER_PARTICLE = 2034
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE), each scaled by the reading
 # for a plain 256 MiB copy in the same run.  Valid only for the kernel
 # source the counters were taken on; any change to it reports null.
-JACOBI_TRAFFIC = {"kernels_sha256": "5b37adcb6311c3fd0120fdaf3271d047a8ec6e7c6d44b2c9788de71607dd4394",
-                  "bytes_per_launch": 83358104, "profile": "profiles/band512_jacobi_traffic.md"}
+JACOBI_TRAFFIC = {"kernels_sha256": "fcac9b0250c9cc84a34464a4cdbd0763220d39a3f74ab66b6334f00c06e6b522",
+                  "bytes_per_launch": 83314333, "profile": "profiles/band512_jacobi_traffic.md"}
 
 
 def _jacobi_traffic():
