@@ -240,7 +240,7 @@ def test_particle_program_reduced(opt, binned, reuse, bin_reuse):
     else:
         assert st["dispatches"] == st["tasks_launched"] + _binning_extra(20, reuse)
     ref = OP.particle_program(p.n, p.x, p.v, p.m, 20, p.params["dt"], "f32")
-    sx, sv = 0.1 * np.abs(p.x).max(), 0.1 * np.abs(p.v).max()
+    sx, sv = 0.1 * np.abs(ref["x"]).max(), 0.1 * np.abs(ref["v"]).max()     # 0.1 |o|_inf
     close_state(x.cpu().numpy(), ref["x"], "x", sx)
     close_state(v.cpu().numpy(), ref["v"], "v", sv)
     for gi in (0, 1):
@@ -262,7 +262,7 @@ def test_particle_program_bin_reuse_with_drift(reuse, root, bin_reuse):
     p = dataclasses.replace(p0, v=(p0.v * 10).astype(np.float32), params=dict(p0.params, dt=2e-3), root_kind=root)
     steps = 12
     ref = OP.particle_program(p.n, p.x, p.v, p.m, steps, p.params["dt"], "f32")
-    sx, sv = 0.1 * np.abs(p.x).max(), 0.1 * np.abs(p.v).max()
+    sx, sv = 0.1 * np.abs(ref["x"]).max(), 0.1 * np.abs(ref["v"]).max()     # 0.1 |o|_inf
     out = {}
     for k in (reuse, 0):
         bin_reuse(k)
@@ -324,7 +324,10 @@ def test_particle_full_size_three_steps_and_eager_vs_optimized():
     say("particles full size")
     p = I.particles(0)
     ref = OP.particle_program(p.n, p.x, p.v, p.m, 3, p.params["dt"], "f32")
-    sx, sv = 0.1 * np.abs(p.x).max(), 0.1 * np.abs(p.v).max()
+    # at 2M particles the reordered fp32 momentum sums differ by up to about
+    # 1.3e-7 in v, above 1e-5 * 0.1 |o|_inf of the grid-averaged velocity:
+    # the scale is that of the scattered terms, 0.1 max|v0|
+    sx, sv = 0.1 * np.abs(ref["x"]).max(), 0.1 * np.abs(p.v).max()
     grids, x, v, st = _particle_run(p, 3, 15)
     assert st["dispatches"] == st["tasks_launched"] + _binning_extra(3, 8)
     close_state(x.cpu().numpy(), ref["x"], "x", sx)
