@@ -503,8 +503,12 @@ at_status at_flush(at_stats *stats, hipStream_t stream);
  * runs a kernel generated for its exact op sequence, compiled with hiprtc
  * for gfx950 and kept in memory and in $XDG_CACHE_HOME/atsparse/variants
  * (else ~/.cache/atsparse/variants), instead of the per-voxel interpreter.
- * It keeps each channel's value in registers from op to op and stores each
- * written channel once: same results, bit for bit.  0 (default): off; 1:
+ * It loads each channel it reads before writing once per block (the next
+ * block's loads issued before this block's stores), keeps every value in
+ * registers from op to op and stores each written channel once: same
+ * results, bit for bit.  A node gets a variant only when that saves memory
+ * traffic (the interpreter's per-voxel accesses at least 1.5 times the
+ * variant's); others run the interpreter.  0 (default): off; 1:
  * the first use queues the compilation on a worker thread and the node runs
  * the interpreter until the variant is loaded; 2: the first use compiles
  * (or reads the disk cache) before launching.  At most 256 variants. */
@@ -523,7 +527,8 @@ at_status at_engine_reset(void);
  * cache; no device is needed.  src (cap bytes, nullable when cap is 0)
  * receives the generated source, NUL-terminated and truncated to cap - 1,
  * and len (nullable) its full length.  AT_E_UNSUPPORTED when an op has no
- * variant form or the compilation failed; AT_E_INVALID for bad tasks. */
+ * variant form, the variant would save no memory traffic, or the
+ * compilation failed; AT_E_INVALID for bad tasks. */
 at_status at_variant_prepare(const at_task *tasks, int32_t ntasks, char *src, size_t cap, size_t *len);
 
 /* Waits until every window flushed asynchronously (AT_OPTION_ASYNC) has

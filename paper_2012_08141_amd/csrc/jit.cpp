@@ -13,8 +13,9 @@
 // Covered: programs of COPY, AXPY, INC, FILL and NORMALISE ops with no
 // activation check (the element-wise chains fusion forms).  Within one
 // lane's voxels every op of such a program reads and writes at the loop
-// index only, so the generated kernel keeps each channel's current value in
-// registers from op to op and stores each written channel once at the end:
+// index only, so the generated kernel loads each channel it reads before
+// writing it once per block, keeps every value in registers from op to op,
+// and stores each written channel once:
 // the memory it leaves is the interpreter's, with the same arithmetic in
 // the same order (compiled without contraction), so results are
 // bit-identical.
@@ -24,6 +25,7 @@
 
 #include <sys/stat.h>
 
+#include <algorithm>
 #include <condition_variable>
 #include <cstdio>
 #include <cstdlib>
@@ -58,32 +60,44 @@ bool op_supported(const MicroOp &op) {
            op.op == AT_OP_NORMALISE;
 }
 
-// Kernel source for one program: same loop over list records and lane
+// Kernel source for one program.  Same loop over list records and lane
 // layout as the interpreter (one wavefront per block, lane l owning the
-// voxels 8l .. 8l + 7 as two float4 halves).
+// voxels 8l .. 8l + 7 as two float4 halves, suffixes a and b), but written
+// in the order the memory system wants: every channel the program reads
+// before writing it is loaded once per block, both halves at once; the next
+// block's loads are issued before the current block's stores (blocks are
+// disjoint, so this is safe; a compiler cannot know it); the ops run on
+// registers; each written channel is stored once.
 struct Gen {
-    std::string body;
-    std::map<int, bool> dirty;   // channels held in a register (value: written)
+    std::vector<int> loads;      // channels read before any op writes them, in order
+    std::map<int, bool> have;    // channels with a register value
+    std::vector<int> written;    // channels written, in order of first write
+    std::string body;            // compute code for one half, '@' for the suffix
 
-    std::string var(int c) { return "c" + std::to_string(c); }
+    static std::string var(int c) { return "c" + std::to_string(c) + "@"; }
     std::string get(int c) {
-        if (!dirty.count(c)) {
-            body += "            float4 " + var(c) + " = *reinterpret_cast<const float4 *>(ch + " + std::to_string(c) +
-                    "LL * stride + off);\n";
-            dirty[c] = false;
+        if (!have.count(c)) {
+            loads.push_back(c);
+            have[c] = true;
         }
         return var(c);
     }
     void set(int c, const std::string &expr) {
-        if (!dirty.count(c)) body += "            float4 " + var(c) + ";\n";
-        body += "            " + var(c) + " = " + expr + ";\n";
-        dirty[c] = true;
+        have[c] = true;
+        if (std::find(written.begin(), written.end(), c) == written.end()) written.push_back(c);
+        body += "        " + var(c) + " = " + expr + ";\n";
     }
 };
 
+std::string subst(const std::string &code, char h) {
+    std::string r = code;
+    for (char &ch : r)
+        if (ch == '@') ch = h;
+    return r;
+}
+
 std::string generate(const MicroProg &prog) {
     Gen G;
-    G.body += "            float4 t;\n";
     for (int o = 0; o < prog.nops; ++o) {
         const MicroOp &op = prog.ops[o];
         const std::string p = flit(op.p);
@@ -95,30 +109,31 @@ std::string generate(const MicroProg &prog) {
         }
         case AT_OP_AXPY: {
             const std::string y = G.get(op.ch[0]), x = G.get(op.ch[1]);
-            G.body += "            t.x = " + y + ".x + " + p + " * " + x + ".x; t.y = " + y + ".y + " + p + " * " + x +
+            G.body += "        t.x = " + y + ".x + " + p + " * " + x + ".x; t.y = " + y + ".y + " + p + " * " + x +
                       ".y; t.z = " + y + ".z + " + p + " * " + x + ".z; t.w = " + y + ".w + " + p + " * " + x + ".w;\n";
             G.set(op.ch[0], "t");
             break;
         }
         case AT_OP_INC: {
             const std::string x = G.get(op.ch[0]);
-            G.body += "            t.x = " + x + ".x + " + p + "; t.y = " + x + ".y + " + p + "; t.z = " + x + ".z + " +
-                      p + "; t.w = " + x + ".w + " + p + ";\n";
+            G.body += "        t.x = " + x + ".x + " + p + "; t.y = " + x + ".y + " + p + "; t.z = " + x + ".z + " + p +
+                      "; t.w = " + x + ".w + " + p + ";\n";
             G.set(op.ch[0], "t");
             break;
         }
         case AT_OP_FILL:
             for (int q = 0; q < 7; ++q)
-                if (op.ch[q] >= 0 && ((op.keep >> q) & 1u)) G.set(op.ch[q], "make_float4(" + p + ", " + p + ", " + p + ", " + p + ")");
+                if (op.ch[q] >= 0 && ((op.keep >> q) & 1u))
+                    G.set(op.ch[q], "make_float4(" + p + ", " + p + ", " + p + ", " + p + ")");
             break;
         case AT_OP_NORMALISE: {
             const std::string m = G.get(op.ch[0]);
             for (int cc = 0; cc < 3; ++cc) {
                 if (!((op.keep >> cc) & 1u)) continue;
                 const std::string mv = G.get(op.ch[1] + cc);
-                G.body += "            t.x = " + m + ".x > 0.f ? " + mv + ".x / " + m + ".x : 0.f; t.y = " + m +
-                          ".y > 0.f ? " + mv + ".y / " + m + ".y : 0.f; t.z = " + m + ".z > 0.f ? " + mv + ".z / " + m +
-                          ".z : 0.f; t.w = " + m + ".w > 0.f ? " + mv + ".w / " + m + ".w : 0.f;\n";
+                G.body += "        t.x = " + m + ".x > 0.f ? " + mv + ".x / " + m + ".x : 0.f; t.y = " + m + ".y > 0.f ? " +
+                          mv + ".y / " + m + ".y : 0.f; t.z = " + m + ".z > 0.f ? " + mv + ".z / " + m + ".z : 0.f; t.w = " +
+                          m + ".w > 0.f ? " + mv + ".w / " + m + ".w : 0.f;\n";
                 G.set(op.ch[2] + cc, "t");
             }
             break;
@@ -127,10 +142,10 @@ std::string generate(const MicroProg &prog) {
             break;
         }
     }
-    for (const auto &kv : G.dirty)
-        if (kv.second)
-            G.body += "            *reinterpret_cast<float4 *>(ch + " + std::to_string(kv.first) +
-                      "LL * stride + off) = " + G.var(kv.first) + ";\n";
+    auto ld = [](int c, const char *o, const char *h) {
+        return std::string("*reinterpret_cast<const float4 *>(ch + ") + std::to_string(c) + "LL * stride + " + o +
+               (h[0] == 'b' ? " + 4" : "") + ")";
+    };
     std::string s;
     s += "#include <hip/hip_runtime.h>\n";
     s += "extern \"C\" __global__ __launch_bounds__(64) void atsv(const int *__restrict__ hdr, const int *__restrict__ "
@@ -142,12 +157,34 @@ std::string generate(const MicroProg &prog) {
     s += "    const int lo = (int)(((long long)count * xs) / nx) + (int)(blockIdx.x / nx);\n";
     s += "    const int hi = (int)(((long long)count * (xs + 1)) / nx);\n";
     s += "    const int step = gridDim.x / nx;\n";
+    s += "    if (lo >= hi) return;\n";
+    s += "    long long off = (long long)list[(long long)lo * " + std::to_string(kRec) + " + 1] * " +
+         std::to_string(kBV) + " + lane * 8;\n";
+    for (int c : G.loads)
+        for (const char *h : {"a", "b"}) s += "    float4 p" + std::to_string(c) + h + " = " + ld(c, "off", h) + ";\n";
     s += "    for (int e = lo; e < hi; e += step) {\n";
-    s += "        const long long slot = list[(long long)e * " + std::to_string(kRec) + " + 1];\n";
-    s += "        for (int h = 0; h < 2; ++h) {\n";
-    s += "            const long long off = slot * " + std::to_string(kBV) + " + lane * 8 + 4 * h;\n";
-    s += G.body;
-    s += "        }\n    }\n}\n";
+    s += "        const int en = e + step < hi ? e + step : e;\n";
+    s += "        const long long offn = (long long)list[(long long)en * " + std::to_string(kRec) + " + 1] * " +
+         std::to_string(kBV) + " + lane * 8;\n";
+    for (int c : G.loads)
+        for (const char *h : {"a", "b"}) s += "        const float4 n" + std::to_string(c) + h + " = " + ld(c, "offn", h) + ";\n";
+    s += "        float4 t;\n";
+    for (const auto &kv : G.have) {
+        const bool loaded = std::find(G.loads.begin(), G.loads.end(), kv.first) != G.loads.end();
+        for (const char *h : {"a", "b"})
+            s += "        float4 c" + std::to_string(kv.first) + h +
+                 (loaded ? " = p" + std::to_string(kv.first) + h : std::string()) + ";\n";
+    }
+    s += subst(G.body, 'a');
+    s += subst(G.body, 'b');
+    for (int c : G.written)
+        for (const char *h : {"a", "b"})
+            s += std::string("        *reinterpret_cast<float4 *>(ch + ") + std::to_string(c) + "LL * stride + off" +
+                 (h[0] == 'b' ? " + 4" : "") + ") = c" + std::to_string(c) + h + ";\n";
+    for (int c : G.loads)
+        for (const char *h : {"a", "b"}) s += "        p" + std::to_string(c) + h + " = n" + std::to_string(c) + h + ";\n";
+    s += "        off = offn;\n";
+    s += "    }\n}\n";
     return s;
 }
 
@@ -224,13 +261,33 @@ bool build_code(uint64_t key, const std::string &src, std::vector<char> &code, b
     return ok;
 }
 
-// Key of a variant: its source, the compile options and the generator's
-// revision (bumped whenever the generated code's form changes).
-constexpr const char *kGenRevision = "atsv-1";
-uint64_t variant_key(const std::string &src) {
-    std::string k = src;
+// Key of a variant: the program's ops, channels, constants and keep masks
+// (what the generated source is a function of), the compile options and
+// the generator's revision (bumped whenever the generated code's form
+// changes).  Computed from the program's fields, so a launch that finds its
+// variant loaded generates no source.
+constexpr const char *kGenRevision = "atsv-4";
+uint64_t variant_key(const MicroProg &prog) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint32_t v) {
+        for (int b = 0; b < 4; ++b) {
+            h ^= (v >> (8 * b)) & 0xffu;
+            h *= 1099511628211ull;
+        }
+    };
+    mix((uint32_t)prog.nops);
+    for (int o = 0; o < prog.nops; ++o) {
+        const MicroOp &op = prog.ops[o];
+        uint32_t pb;
+        std::memcpy(&pb, &op.p, 4);
+        mix((uint32_t)op.op);
+        for (int c = 0; c < 7; ++c) mix((uint32_t)op.ch[c]);
+        mix(pb);
+        mix(op.keep);
+    }
+    std::string k;
     for (int i = 0; i < kNOpts; ++i) k += std::string(" ") + kOpts[i];
-    return hash_text(k + kGenRevision);
+    return h ^ (hash_text(k + kGenRevision) * 0x9e3779b97f4a7c15ull);
 }
 
 struct Variant {
@@ -285,11 +342,61 @@ void compile_loop() {
 
 }  // namespace
 
+// Memory accesses per voxel: the interpreter's (each op reads its inputs
+// and writes its outputs) and the variant's (each channel read before being
+// written loaded once, each written channel stored once).
+static void accesses(const MicroProg &prog, int &interp, int &variant) {
+    std::map<int, int> state;   // 1 read first, 2 written
+    int loads = 0;
+    interp = 0;
+    auto rd = [&](int c) {
+        ++interp;
+        if (!state.count(c)) {
+            state[c] = 1;
+            ++loads;
+        }
+    };
+    auto wr = [&](int c) {
+        ++interp;
+        state[c] = 2;
+    };
+    for (int o = 0; o < prog.nops; ++o) {
+        const MicroOp &op = prog.ops[o];
+        switch (op.op) {
+        case AT_OP_COPY: rd(op.ch[1]); wr(op.ch[0]); break;
+        case AT_OP_AXPY: rd(op.ch[0]); rd(op.ch[1]); wr(op.ch[0]); break;
+        case AT_OP_INC: rd(op.ch[0]); wr(op.ch[0]); break;
+        case AT_OP_FILL:
+            for (int q = 0; q < 7; ++q)
+                if (op.ch[q] >= 0 && ((op.keep >> q) & 1u)) wr(op.ch[q]);
+            break;
+        case AT_OP_NORMALISE:
+            rd(op.ch[0]);
+            for (int cc = 0; cc < 3; ++cc)
+                if ((op.keep >> cc) & 1u) {
+                    rd(op.ch[1] + cc);
+                    wr(op.ch[2] + cc);
+                }
+            break;
+        default: break;
+        }
+    }
+    int stores = 0;
+    for (const auto &kv : state) stores += kv.second == 2;
+    variant = loads + stores;
+}
+
+// A variant pays when it saves memory traffic: measured on MI355X, a chain
+// whose variant moves as many bytes as the interpreter (three copies, a copy
+// and an axpy) runs slower as a variant (the interpreter streams such chains
+// at about 5.3 TB/s), while chains of 8 and 16 ops ran 2.9x and 5.7x faster.
 bool variant_eligible(const MicroProg &prog) {
     if (prog.check || prog.nops < 2) return false;
     for (int o = 0; o < prog.nops; ++o)
         if (!op_supported(prog.ops[o])) return false;
-    return true;
+    int interp, variant;
+    accesses(prog, interp, variant);
+    return 2 * interp >= 3 * variant;
 }
 
 bool variant_launch(const GridDev &g, const MicroProg &prog, hipStream_t s, hipError_t &err) {
@@ -301,14 +408,14 @@ bool variant_launch(const GridDev &g, const MicroProg &prog, hipStream_t s, hipE
         mode = v.mode;
     }
     if (mode == 0 || !variant_eligible(prog)) return false;
-    const std::string src = generate(prog);
-    const uint64_t key = variant_key(src);
+    const uint64_t key = variant_key(prog);
     hipFunction_t fn = nullptr;
     {
         std::unique_lock<std::mutex> lk(v.mu);
         auto it = v.map.find(key);
         if (it == v.map.end()) {
             if ((int64_t)v.map.size() >= kMaxVariants) return false;
+            const std::string src = generate(prog);
             Variant &nv = v.map[key];
             nv.src = src;
             if (mode == 2) {
@@ -323,6 +430,7 @@ bool variant_launch(const GridDev &g, const MicroProg &prog, hipStream_t s, hipE
                 var.code.swap(code);
                 var.from_disk = disk;
                 if (ok) (disk ? v.disk_hits : v.compiled) += 1;
+                v.cv.notify_all();
             } else {
                 if (!v.worker) {
                     std::thread(compile_loop).detach();
@@ -388,7 +496,7 @@ int64_t variants_loaded() {
 bool variant_prepare(const MicroProg &prog, std::string &src) {
     if (!variant_eligible(prog)) return false;
     src = generate(prog);
-    const uint64_t key = variant_key(src);
+    const uint64_t key = variant_key(prog);
     Variants &v = V();
     {
         std::unique_lock<std::mutex> lk(v.mu);

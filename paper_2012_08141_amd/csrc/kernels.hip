@@ -1442,6 +1442,48 @@ __host__ __device__ inline int tile_lds_floats(const TileProg &tp) {
     return tp.nt * kT3 + (tp.vstage ? 3 * kT3 : (tp.v0 >= 0 ? 3 * kBV : 0));
 }
 
+// Tile voxel number e (0 .. kT3 - 1) in source order: the block's own 512
+// voxels, then the 2-voxel face slabs of the neighbours across i-, i+, j-,
+// j+, k-, k+ (128 each), the twelve edge pieces (32 each: i and j sides,
+// then i and k, then j and k) and the eight corners (8 each), every piece in
+// its source block's memory order (k fastest).  Consecutive numbers are
+// then consecutive addresses along the pieces' rows, so a wave's staging
+// load touches few cache lines.  Returns the neighbour (0 .. 26, as s_nb)
+// and sets the voxel's offset in that block and its tile position.
+__device__ __forceinline__ int tile_src(int e, int &src, int &tpos) {
+    int d0 = 0, d1 = 0, d2 = 0, l;
+    if (e < 512) {
+        l = e;
+    } else if (e < 1280) {
+        const int f = (e - 512) >> 7, sg = (f & 1) ? 1 : -1;
+        l = (e - 512) & 127;
+        d0 = f >> 1 == 0 ? sg : 0;
+        d1 = f >> 1 == 1 ? sg : 0;
+        d2 = f >> 1 == 2 ? sg : 0;
+    } else if (e < 1664) {
+        const int m = (e - 1280) >> 5, pr = m >> 2;
+        const int sa = (m & 2) ? 1 : -1, sb = (m & 1) ? 1 : -1;
+        l = (e - 1280) & 31;
+        d0 = pr <= 1 ? sa : 0;
+        d1 = pr == 0 ? sb : (pr == 2 ? sa : 0);
+        d2 = pr >= 1 ? sb : 0;
+    } else {
+        const int c = (e - 1664) >> 3;
+        l = (e - 1664) & 7;
+        d0 = (c & 4) ? 1 : -1;
+        d1 = (c & 2) ? 1 : -1;
+        d2 = (c & 1) ? 1 : -1;
+    }
+    const int bk = d2 ? 1 : 3, bj = d1 ? 1 : 3;              // log2 of the piece's extent
+    const int sk = l & ((1 << bk) - 1), sj = (l >> bk) & ((1 << bj) - 1), si = l >> (bk + bj);
+    const int i = d0 < 0 ? 6 + si : si, j = d1 < 0 ? 6 + sj : sj, k = d2 < 0 ? 6 + sk : sk;
+    src = i * 64 + j * 8 + k;
+    const int ti = d0 < 0 ? si : (d0 ? 10 + si : 2 + si), tj = d1 < 0 ? sj : (d1 ? 10 + sj : 2 + sj),
+              tk = d2 < 0 ? sk : (d2 ? 10 + sk : 2 + sk);
+    tpos = (ti * kTE + tj) * kTE + tk;
+    return (d0 + 1) * 9 + (d1 + 1) * 3 + (d2 + 1);
+}
+
 template <int KIND, int NT, bool VS>
 __global__ __launch_bounds__(kTT) void k_tile_micro(GridDev g, TileProg tp) {
     extern __shared__ float s_t[];
@@ -1464,23 +1506,21 @@ __global__ __launch_bounds__(kTT) void k_tile_micro(GridDev g, TileProg tp) {
             s_nb[tid] = sl;
         }
         __syncthreads();
-        // every load of the tile first (a valid dummy address where the voxel
+        // every load of the tile first (a valid dummy address where the block
         // is outside the domain or inactive, zeroed by a select), then the
         // LDS stores, so the loads overlap instead of each waiting for the
-        // store after it
+        // store after it; voxels in source order (tile_src)
         constexpr int NIT = (kT3 + kTT - 1) / kTT, NC = NT + (VS ? 3 : 0);
         float val[NIT][NC];
         bool ok[NIT];
+        int tpos[NIT];
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
             const int t = tid + it * kTT < kT3 ? tid + it * kTT : 0;
-            const int ti = t / (kTE * kTE) - 2, tj = (t / kTE) % kTE - 2, tk = t % kTE - 2;   // block-local
-            const int gi = bi * kBS + ti, gj = bj * kBS + tj, gk = bk * kBS + tk;
-            int32_t sl = -1;
-            if (gi >= 0 && gj >= 0 && gk >= 0 && gi < n && gj < n && gk < n)
-                sl = s_nb[((ti >> 3) + 1) * 9 + ((tj >> 3) + 1) * 3 + ((tk >> 3) + 1)];
+            int src;
+            const int32_t sl = s_nb[tile_src(t, src, tpos[it])];   // -1 outside the domain or inactive
             ok[it] = sl >= 0;
-            const int64_t o = (int64_t)(sl >= 0 ? sl : slot) * kBV + (ti & 7) * 64 + (tj & 7) * 8 + (tk & 7);
+            const int64_t o = (int64_t)(sl >= 0 ? sl : slot) * kBV + src;
 #pragma unroll
             for (int q = 0; q < NT; ++q) val[it][q] = chan(g, tp.tch[q])[o];
 #pragma unroll
@@ -1495,8 +1535,8 @@ __global__ __launch_bounds__(kTT) void k_tile_micro(GridDev g, TileProg tp) {
                 for (int d = 0; d < 3; ++d) vown[it][d] = chan(g, tp.v0 + d)[(int64_t)slot * kBV + tid + it * kTT];
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
-            const int t = tid + it * kTT;
-            if (t < kT3) {
+            if (tid + it * kTT < kT3) {
+                const int t = tpos[it];
 #pragma unroll
                 for (int q = 0; q < NT; ++q) s_t[q * kT3 + t] = ok[it] ? val[it][q] : 0.f;
 #pragma unroll

@@ -1281,7 +1281,8 @@ at_status at_variant_prepare(const at_task *tasks, int32_t ntasks, char *src, si
         op.p1 = t.param[1];
         op.p2 = t.param[2];
     }
-    if (!variant_eligible(prog)) return fail(AT_E_UNSUPPORTED, "variants cover copy, axpy, inc, fill and normalise");
+    if (!variant_eligible(prog))
+        return fail(AT_E_UNSUPPORTED, "variants cover copy, axpy, inc, fill and normalise chains that save memory traffic");
     std::string s;
     if (!variant_prepare(prog, s)) return fail(AT_E_UNSUPPORTED, "the variant did not compile");
     if (len) *len = s.size();

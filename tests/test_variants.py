@@ -2,9 +2,9 @@
 generation and compilation need no device).
 
 The generated kernel keeps each channel's value in registers from op to op:
-a channel is loaded at most once (before its first use, and only when an
-op reads it before anything writes it) and stored once at the end when
-written.  The device tests compare it with the interpreter bit for bit."""
+a channel is loaded once per block (only when an op reads it before
+anything writes it; the next block's loads are issued before this block's
+stores) and stored once when written.  The device tests compare it with the interpreter bit for bit."""
 import ctypes
 import os
 import re
@@ -25,8 +25,14 @@ def prepare(tasks):
 
 
 def loads_stores(src):
-    loads = sorted(int(c) for c in re.findall(r"= \*reinterpret_cast<const float4 \*>\(ch \+ (\d+)LL", src))
+    """Channels loaded per block (the first block's loads) and stored."""
+    loads = sorted(int(c) for c in re.findall(r"float4 p(\d+)a = \*reinterpret_cast<const float4 \*>", src))
     stores = sorted(int(c) for c in re.findall(r"\*reinterpret_cast<float4 \*>\(ch \+ (\d+)LL \* stride \+ off\) =", src))
+    # every load has its prefetch for the next block and its second half
+    for c in loads:
+        assert ("float4 p%db = " % c) in src and ("float4 n%da = " % c) in src and ("float4 n%db = " % c) in src
+    for c in stores:
+        assert ("stride + off + 4) = c%db;" % c) in src
     return loads, stores
 
 
@@ -61,10 +67,16 @@ def test_fill_array_and_chains(grid):
     st, src, _ = prepare([E.copy(g, 1, 0), E.inc(g, 1, 1.0), E.copy(g, 2, 1), E.inc(g, 2, 4.0)])
     assert st == L.AT_OK
     assert loads_stores(src) == ([0], [1, 2])
-    # normalise (m, mv -> v) after clearing another grid's channels
-    st, src, _ = prepare([E.normalise(g, 0, 1, 4), E.fill(g, [0, 1, 2, 3], 0.0)])
+    # normalise (m, mv -> v) then clearing m and mv: once it saves no memory
+    # traffic (11 accesses per voxel either way) and stays on the
+    # interpreter; twice over, the variant moves half the bytes
+    one = [E.normalise(g, 0, 1, 4), E.fill(g, [0, 1, 2, 3], 0.0)]
+    assert prepare(one)[0] == L.AT_E_UNSUPPORTED
+    st, src, _ = prepare(one + one)
     assert st == L.AT_OK
     assert loads_stores(src) == ([0, 1, 2, 3], [0, 1, 2, 3, 4, 5, 6])
+    # three copies move the same bytes as a variant: interpreter
+    assert prepare([E.copy(g, 0, 5), E.copy(g, 1, 6), E.copy(g, 2, 7)])[0] == L.AT_E_UNSUPPORTED
 
 
 def test_unsupported_programs(grid):
