@@ -45,8 +45,8 @@ MPM_FLOPS_PER_PARTICLE = 2034
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE), each scaled by the reading
 # for a plain 256 MiB copy in the same run.  Valid only for the kernel
 # source the counters were taken on; any change to it reports null.
-JACOBI_TRAFFIC = {"kernels_sha256": "fcac9b0250c9cc84a34464a4cdbd0763220d39a3f74ab66b6334f00c06e6b522",
-                  "bytes_per_launch": 83314333, "profile": "profiles/band512_jacobi_traffic.md"}
+JACOBI_TRAFFIC = {"kernels_sha256": "9b077b4fc0bdf2fb9114f9d1d172ae901b8a030580876b1ae8cb8655ad097cf9",
+                  "bytes_per_launch": 83343938, "profile": "profiles/band512_jacobi_traffic.md"}
 
 
 def _jacobi_traffic():
@@ -261,7 +261,7 @@ def bench_band(args, torch):
                     "step_GBs_algorithmic": 20.0 * voxels / (t_opt / K) / 1e9},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": _jacobi_traffic() if args.seed == 0 else None,
-                     "kernel": "k_stencil_pipe<JACOBI> (12 B per active voxel: x, b read; xn written); mean of "
+                     "kernel": "k_stencil_lds<JACOBI> (12 B per active voxel: x, b read; xn written); mean of "
                                "%d back-to-back launches over the workload's list between two HIP events on the "
                                "launch stream, median of 3 such windows (plan cached)" % reps,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
@@ -317,7 +317,7 @@ def bench_shell(args, torch):
     E.run_sequence(PR.shell_setup(g, coords), E.OPT_ALL)
     t_lap = time_kernel(torch, E, lambda: E.lap_update(g, PR.SHELL["a"], PR.SHELL["out"], 0.1), 100)
     t_axpy = time_kernel(torch, E, lambda: E.axpy(g, PR.SHELL["a"], PR.SHELL["out"], 0.5), 100)
-    name, tk, per = max((("k_stencil_pipe<LAP_UPDATE>", t_lap, 8), ("k_elem<AXPY>", t_axpy, 12)), key=lambda e: e[1])
+    name, tk, per = max((("k_stencil_lds<LAP_UPDATE>", t_lap, 8), ("k_elem<AXPY>", t_axpy, 12)), key=lambda e: e[1])
     out["kernels"] = {"lap_update_us": t_lap * 1e6, "axpy_us": t_axpy * 1e6}
     out["roofline"] = roofline(per * w.active_voxels / tk / 1e9,
                                "%s (%d B per active voxel), mean of 100 back-to-back launches between two HIP events "

@@ -126,7 +126,9 @@ at_status at_grid_clear(at_grid grid, hipStream_t stream);
  * (waits for the stream).  Activation allocates leaves from the grid's pool
  * (Section 3.2, pointer nodes); the pool's fixed capacity is this library's,
  * so running out is reported here instead of growing memory.  bit 0: the pointer pool overflowed
- * (AT_E_CAPACITY); bit 1: an allocation wait exceeded its spin limit.
+ * (AT_E_CAPACITY); bit 1: an allocation wait exceeded its spin limit; bit 2:
+ * a write whose activation check was demoted found its block inactive
+ * (only with AT_OPTION_VERIFY_DEMOTED).
  * Returns AT_OK and stores the bits; `clear` != 0 also resets them. */
 at_status at_device_status(at_grid grid, hipStream_t stream, int32_t clear, int32_t *bits);
 
@@ -515,6 +517,15 @@ at_status at_flush(at_stats *stats, hipStream_t stream);
 #define AT_OPTION_VARIANTS 14
 /* Read-only: variants loaded on a device so far. */
 #define AT_OPTION_VARIANTS_LOADED 15
+/* Debug mode for activation demotion (Section 6.3): 1 makes every launched
+ * node whose activating writes the optimizer demoted verify them: a
+ * struct-for (run in the general interpreter, not the faster forms) checks
+ * that each listed block is still active, and a restriction or
+ * prolongation that each block it writes is active.  A block that is not
+ * is skipped and sets bit 2 of the grid's sticky status (at_device_status).
+ * A correct plan never sets it; the bit reports a demotion that was wrong,
+ * or a mask changed behind the engine's back.  Default 0. */
+#define AT_OPTION_VERIFY_DEMOTED 16
 at_status at_set_option(int32_t option, int64_t value);
 at_status at_get_option(int32_t option, int64_t *value);
 

@@ -43,6 +43,7 @@ AT_OPTION_GRAPHS_CACHED = 12
 AT_OPTION_ASYNC = 13
 AT_OPTION_VARIANTS = 14
 AT_OPTION_VARIANTS_LOADED = 15
+AT_OPTION_VERIFY_DEMOTED = 16
 AT_STATIC_MAX_PARTICLES, AT_STATIC_MAX_CELLS = 1048576, 262144
 
 

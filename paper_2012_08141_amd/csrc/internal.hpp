@@ -19,7 +19,7 @@ enum : int {
     HDR_NOUT_ACC = 6,   // outliers listed so far by the scatter's first pass
     HDR_NOUT = 7        // outliers of the last binned scatter (pout[0..NOUT))
 };
-enum : int32_t { ERR_CAPACITY = 1, ERR_SPIN = 2 };
+enum : int32_t { ERR_CAPACITY = 1, ERR_SPIN = 2, ERR_DEMOTED = 4 };
 
 // Pointer-root cell states besides a valid slot (>= 0).
 enum : int32_t { PTR_NULL = -1, PTR_LOCKED = -2, PTR_FAILED = -3 };
@@ -67,6 +67,7 @@ struct MicroProg {
     int32_t nops;
     int32_t check;    // eager activation check on writes
     int32_t table;    // neighbour slots from the list records (mask unchanged since listgen)
+    int32_t verify;   // (no check) verify each listed block is still active; else flag ERR_DEMOTED, skip it
     MicroOp ops[kMaxOps];
 };
 
@@ -195,9 +196,10 @@ hipError_t launch_stencil_tail(const GridDev &g, int op, const int32_t *ch, floa
                                hipStream_t s);
 // Restriction (restrict_op; coarse[chc][I/2] += w * fine[chf][I]) or
 // prolongation (fine[chf][I] += coarse[chc][I/2]) over the fine grid's list;
-// check: activation on write of the blocks written.
+// check: activation on write of the blocks written; verify (without the
+// check): a written block found inactive sets ERR_DEMOTED and is skipped.
 hipError_t launch_transfer(bool restrict_op, const GridDev &f, const GridDev &c, int chf, int chc, float w,
-                           int check, hipStream_t s);
+                           int check, int verify, hipStream_t s);
 // Launches one particle task (1 dispatch, or 4 when its scatter is binned;
 // the count is stored in *dispatches).
 hipError_t launch_particles(const PartProg &prog, hipStream_t s, int *dispatches);

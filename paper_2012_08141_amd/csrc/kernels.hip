@@ -1148,6 +1148,10 @@ __global__ __launch_bounds__(64) void k_micro(GridDev g, MicroProg prog) {
         const int4 rec0 = reinterpret_cast<const int4 *>(g.list + (int64_t)e * kRec)[0];
         const int32_t cell = rec0.x;
         int32_t slot = rec0.y;
+        if (prog.verify && !prog.check && __builtin_amdgcn_readfirstlane(slot_of<KIND>(g, cell)) != slot) {
+            if (lane == 0) atomicOr(g.hdr + HDR_ERR, ERR_DEMOTED);   // the listed block is no longer active
+            continue;
+        }
         int32_t nbs[6] = {-1, -1, -1, -1, -1, -1};
         if (STENCIL) {
             Nbs n;
@@ -1661,7 +1665,7 @@ __global__ __launch_bounds__(kTT) void k_tile_micro(GridDev g, TileProg tp) {
 // coarse block is activated by lane 0 first (CHECK) or looked up.
 template <int KF, int KC, bool CHECK>
 __global__ __launch_bounds__(64) void k_restrict(GridDev f, GridDev c, const float *__restrict__ x, float *y,
-                                                 float w) {
+                                                 float w, int verify) {
     const int lane = threadIdx.x;
     const ListRange lr = list_range(f.hdr[HDR_COUNT]);
     const int ci = lane >> 4, cj = (lane >> 2) & 3, ck = lane & 3;
@@ -1677,6 +1681,8 @@ __global__ __launch_bounds__(64) void k_restrict(GridDev f, GridDev c, const flo
             cs = __builtin_amdgcn_readfirstlane(a);
         } else {
             cs = __builtin_amdgcn_readfirstlane(slot_of<KC>(c, cc));
+            // a demoted check whose block is not active: an optimizer error
+            if (verify && cs < 0 && lane == 0) atomicOr(c.hdr + HDR_ERR, ERR_DEMOTED);
         }
         if (cs < 0) continue;
         const float *xp = x + (int64_t)r.y * kBV + (2 * ci) * 64 + (2 * cj) * 8 + 2 * ck;
@@ -1700,7 +1706,8 @@ __global__ __launch_bounds__(64) void k_restrict(GridDev f, GridDev c, const flo
 // (l>>3, l&7, 0..7), which reads 4 consecutive coarse voxels (one float4);
 // an inactive coarse block reads as zeros.
 template <int KF, int KC, bool CHECK>
-__global__ __launch_bounds__(64) void k_prolong(GridDev f, GridDev c, const float *__restrict__ y, float *x) {
+__global__ __launch_bounds__(64) void k_prolong(GridDev f, GridDev c, const float *__restrict__ y, float *x,
+                                                int verify) {
     const int lane = threadIdx.x;
     const ListRange lr = list_range(f.hdr[HDR_COUNT]);
     const int li = lane >> 3, lj = lane & 7;
@@ -1716,6 +1723,9 @@ __global__ __launch_bounds__(64) void k_prolong(GridDev f, GridDev c, const floa
             if (lane == 0) a = activate_cell<KF>(f, r.x);
             fs = __builtin_amdgcn_readfirstlane(a);
             if (fs < 0) continue;
+        } else if (verify && __builtin_amdgcn_readfirstlane(slot_of<KF>(f, r.x)) != fs) {
+            if (lane == 0) atomicOr(f.hdr + HDR_ERR, ERR_DEMOTED);   // the listed block is no longer active
+            continue;
         }
         float4 yv = make_float4(0.f, 0.f, 0.f, 0.f);
         if (cs >= 0)
@@ -2897,7 +2907,7 @@ static void launch_tile_k(const GridDev &g, const TileProg &tp, dim3 grid, size_
 // MACCORMACK) with element-wise ops it implements (COPY, AXPY, INC, FILL);
 // at most kTileCh distinct sampled channels; RK3 ops sharing one velocity.
 static bool tile_prog(const MicroProg &prog, TileProg &tp) {
-    if (prog.check || g_sf_kernel != 0) return false;
+    if (prog.check || prog.verify || g_sf_kernel != 0) return false;
     tp = TileProg{};
     tp.prog = prog;
     tp.v0 = -1;
@@ -2944,7 +2954,7 @@ hipError_t launch_micro(const GridDev &g, const MicroProg &prog, hipStream_t s) 
         return hipGetLastError();
     }
     const dim3 grid(wave_grid_size(g, false)), block(64);
-    if (prog.nops == 1 && g_sf_kernel == 0) {
+    if (prog.nops == 1 && g_sf_kernel == 0 && !prog.verify) {
         const dim3 pgrid(wave_grid_size(g, true));
         // a single element-wise op runs the pipelined kernel
         bool done;
@@ -3102,26 +3112,26 @@ hipError_t launch_gather_blocks(const GridDev &g, int ch, const int32_t *cells, 
 
 template <int KF, int KC>
 static void launch_transfer_k(bool restrict_op, const GridDev &f, const GridDev &c, int chf, int chc, float w,
-                              bool check, hipStream_t s) {
+                              bool check, int verify, hipStream_t s) {
     const dim3 grid(wave_grid_size(f, false)), block(64);
     float *xf = f.chan + (int64_t)chf * f.ch_stride;
     float *yc = c.chan + (int64_t)chc * c.ch_stride;
     if (restrict_op) {
-        if (check) hipLaunchKernelGGL((k_restrict<KF, KC, true>), grid, block, 0, s, f, c, xf, yc, w);
-        else hipLaunchKernelGGL((k_restrict<KF, KC, false>), grid, block, 0, s, f, c, xf, yc, w);
+        if (check) hipLaunchKernelGGL((k_restrict<KF, KC, true>), grid, block, 0, s, f, c, xf, yc, w, verify);
+        else hipLaunchKernelGGL((k_restrict<KF, KC, false>), grid, block, 0, s, f, c, xf, yc, w, verify);
     } else {
-        if (check) hipLaunchKernelGGL((k_prolong<KF, KC, true>), grid, block, 0, s, f, c, yc, xf);
-        else hipLaunchKernelGGL((k_prolong<KF, KC, false>), grid, block, 0, s, f, c, yc, xf);
+        if (check) hipLaunchKernelGGL((k_prolong<KF, KC, true>), grid, block, 0, s, f, c, yc, xf, verify);
+        else hipLaunchKernelGGL((k_prolong<KF, KC, false>), grid, block, 0, s, f, c, yc, xf, verify);
     }
 }
 
 hipError_t launch_transfer(bool restrict_op, const GridDev &f, const GridDev &c, int chf, int chc, float w,
-                           int check, hipStream_t s) {
+                           int check, int verify, hipStream_t s) {
     const bool fb = f.kind == AT_ROOT_BITMASK, cb = c.kind == AT_ROOT_BITMASK;
-    if (fb && cb) launch_transfer_k<AT_ROOT_BITMASK, AT_ROOT_BITMASK>(restrict_op, f, c, chf, chc, w, check, s);
-    else if (fb) launch_transfer_k<AT_ROOT_BITMASK, AT_ROOT_POINTER>(restrict_op, f, c, chf, chc, w, check, s);
-    else if (cb) launch_transfer_k<AT_ROOT_POINTER, AT_ROOT_BITMASK>(restrict_op, f, c, chf, chc, w, check, s);
-    else launch_transfer_k<AT_ROOT_POINTER, AT_ROOT_POINTER>(restrict_op, f, c, chf, chc, w, check, s);
+    if (fb && cb) launch_transfer_k<AT_ROOT_BITMASK, AT_ROOT_BITMASK>(restrict_op, f, c, chf, chc, w, check, verify, s);
+    else if (fb) launch_transfer_k<AT_ROOT_BITMASK, AT_ROOT_POINTER>(restrict_op, f, c, chf, chc, w, check, verify, s);
+    else if (cb) launch_transfer_k<AT_ROOT_POINTER, AT_ROOT_BITMASK>(restrict_op, f, c, chf, chc, w, check, verify, s);
+    else launch_transfer_k<AT_ROOT_POINTER, AT_ROOT_POINTER>(restrict_op, f, c, chf, chc, w, check, verify, s);
     return hipGetLastError();
 }
 

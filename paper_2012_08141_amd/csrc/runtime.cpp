@@ -84,6 +84,7 @@ struct AsyncPipe {
 struct Engine {
     std::recursive_mutex mu;
     bool async = false;                  // flushes go to the pipeline (AT_OPTION_ASYNC)
+    bool verify_demoted = false;         // AT_OPTION_VERIFY_DEMOTED
     std::unique_ptr<AsyncPipe> pipe;     // started when async is first switched on
     Persist persist;
     std::unordered_map<uint64_t, CacheEntry> cache;
@@ -220,7 +221,10 @@ at_status execute_node(const Node &nd, const at_task *tasks, bool table, hipStre
                     !nd.check_activation && table && struct_for_kernel() == 0 &&
                     nd.members.size() - 1 <= (size_t)kMaxOps;
         for (size_t q = 1; tail && q < nd.members.size(); ++q) tail = tail_op_supported(tasks[nd.members[q].task].op);
-        if (nd.members.size() == 1 && tiled && m0.keep == ~0u) {
+        // verification of demoted writes runs every such node in the interpreter
+        const bool verify = E().verify_demoted && !nd.check_activation;
+        if (verify) tail = false;
+        if (nd.members.size() == 1 && tiled && m0.keep == ~0u && !verify) {
             e = launch_stencil(g->dev, t0.op, t0.ch, t0.param[0], nd.check_activation ? 1 : 0, table ? 1 : 0, s);
         } else if (tail) {
             MicroProg prog{};
@@ -241,6 +245,7 @@ at_status execute_node(const Node &nd, const at_task *tasks, bool table, hipStre
             prog.nops = (int32_t)nd.members.size();
             prog.check = nd.check_activation ? 1 : 0;
             prog.table = table ? 1 : 0;
+            prog.verify = verify ? 1 : 0;
             for (size_t q = 0; q < nd.members.size(); ++q) {
                 const at_task &t = tasks[nd.members[q].task];
                 MicroOp &op = prog.ops[q];
@@ -251,7 +256,7 @@ at_status execute_node(const Node &nd, const at_task *tasks, bool table, hipStre
                 op.p1 = t.param[1];
                 op.p2 = t.param[2];
             }
-            if (!variant_launch(g->dev, prog, s, e)) e = launch_micro(g->dev, prog, s);
+            if (verify || !variant_launch(g->dev, prog, s, e)) e = launch_micro(g->dev, prog, s);
         }
         break;
     }
@@ -260,7 +265,7 @@ at_status execute_node(const Node &nd, const at_task *tasks, bool table, hipStre
         const at_grid_s *c = reinterpret_cast<const at_grid_s *>(t0.grid2);
         const bool r = t0.kind == AT_TASK_RESTRICT;
         e = launch_transfer(r, g->dev, c->dev, r ? t0.ch[0] : t0.ch[1], r ? t0.ch[1] : t0.ch[0], t0.param[0],
-                            nd.check_activation ? 1 : 0, s);
+                            nd.check_activation ? 1 : 0, E().verify_demoted && !nd.check_activation ? 1 : 0, s);
         break;
     }
     case AT_TASK_ADVECT:
@@ -1395,6 +1400,12 @@ at_status at_set_option(int32_t option, int64_t value) {
         set_variant_mode((int)value);
         return AT_OK;
     case AT_OPTION_VARIANTS_LOADED: return fail(AT_E_INVALID, "the number of loaded variants is read-only");
+    case AT_OPTION_VERIFY_DEMOTED:
+        if (value != 0 && value != 1) return fail(AT_E_INVALID, "verify demoted must be 0 or 1");
+        // a captured graph holds the kernels of the other setting
+        if (en.verify_demoted != (value != 0)) drop_graphs(true);
+        en.verify_demoted = value != 0;
+        return AT_OK;
     case AT_OPTION_MAX_FUSE_PER_TASK:
         if (value < 1 || value > 64) return fail(AT_E_INVALID, "max_fuse_per_task must be in 1..64");
         en.max_fuse = (int)value;
@@ -1467,6 +1478,7 @@ at_status at_get_option(int32_t option, int64_t *value) {
     case AT_OPTION_ASYNC: *value = en.async ? 1 : 0; return AT_OK;
     case AT_OPTION_VARIANTS: *value = variant_mode(); return AT_OK;
     case AT_OPTION_VARIANTS_LOADED: *value = variants_loaded(); return AT_OK;
+    case AT_OPTION_VERIFY_DEMOTED: *value = en.verify_demoted ? 1 : 0; return AT_OK;
     default: return fail(AT_E_INVALID, "unknown option %d", option);
     }
 }
