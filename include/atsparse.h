@@ -510,7 +510,12 @@ at_status at_flush(at_stats *stats, hipStream_t stream);
  * registers from op to op and stores each written channel once: same
  * results, bit for bit.  A node gets a variant only when that saves memory
  * traffic (the interpreter's per-voxel accesses at least 1.5 times the
- * variant's); others run the interpreter.  0 (default): off; 1:
+ * variant's); others run the interpreter.  A node of semi-Lagrangian or
+ * MacCormack ops (Section 8.2) with element-wise ops beside them, which runs
+ * one workgroup per block over an LDS tile of the block and its 2-voxel
+ * halo, gets a variant with its ops written out in place of the tile
+ * kernel's op interpreter: same staging and arithmetic, same results bit
+ * for bit.  0 (default): off; 1:
  * the first use queues the compilation on a worker thread and the node runs
  * the interpreter until the variant is loaded; 2: the first use compiles
  * (or reads the disk cache) before launching.  At most 256 variants. */
@@ -537,9 +542,10 @@ at_status at_engine_reset(void);
  * 16 struct-for tasks of one grid, all stores kept), storing it in the
  * cache; no device is needed.  src (cap bytes, nullable when cap is 0)
  * receives the generated source, NUL-terminated and truncated to cap - 1,
- * and len (nullable) its full length.  AT_E_UNSUPPORTED when an op has no
- * variant form, the variant would save no memory traffic, or the
- * compilation failed; AT_E_INVALID for bad tasks. */
+ * and len (nullable) its full length.  AT_E_UNSUPPORTED when the program is
+ * neither an element-wise chain whose variant saves memory traffic nor an
+ * advection tile program, or the compilation failed; AT_E_INVALID for bad
+ * tasks. */
 at_status at_variant_prepare(const at_task *tasks, int32_t ntasks, char *src, size_t cap, size_t *len);
 
 /* Waits until every window flushed asynchronously (AT_OPTION_ASYNC) has

@@ -177,13 +177,30 @@ hipError_t launch_stencil(const GridDev &g, int op, const int32_t *ch, float p, 
 hipError_t launch_micro(const GridDev &g, const MicroProg &prog, hipStream_t s);
 int wave_grid_size(const GridDev &g, bool pipelined);   // workgroups of the one-wavefront-per-block kernels
 
+// A struct-for node of sampling ops (ADVECT, MACCORMACK) with element-wise
+// ops beside them, run one workgroup of kTT threads per listed block with
+// the block and a 2-voxel halo of every sampled channel staged in LDS.
+constexpr int kTE = 12, kT3 = kTE * kTE * kTE;   // tile edge and voxels (block + 2 each side)
+constexpr int kTileCh = 4;                        // sampled channels staged per node
+constexpr int kTT = 512;                          // threads per workgroup
+struct TileProg {
+    MicroProg prog;
+    int32_t nt;              // staged sampled channels
+    int32_t tch[kTileCh];    // their grid channels
+    int32_t vstage;          // stage the tile of v0 .. v0 + 2 (RK3 back-traces)
+    int32_t v0;              // the velocity of every sampling op (else -1: read per voxel)
+};
+bool tile_prog(const MicroProg &prog, TileProg &tp);   // false: the node is not a tile program
+size_t tile_lds_bytes(const TileProg &tp);             // dynamic LDS of one workgroup
+unsigned tile_grid_size(const GridDev &g, size_t lds);  // workgroups of a tile launch
+
 // Runtime-compiled variants of fused element-wise programs (jit.cpp).
 // variant_launch: launches the program through its compiled variant when
 // one is loaded (true; err has the launch status), else false (the caller
 // runs the interpreter), queueing or doing the compilation per the mode.
 bool variant_eligible(const MicroProg &prog);
 bool variant_launch(const GridDev &g, const MicroProg &prog, hipStream_t s, hipError_t &err);
-bool variant_prepare(const MicroProg &prog, std::string &src);   // generate and compile now (no device needed)
+bool variant_prepare(const MicroProg &prog, int kind, std::string &src);   // generate and compile now (no device needed)
 void set_variant_mode(int mode);   // 0 off, 1 compile in the background, 2 compile at first use
 int variant_mode();
 int64_t variants_loaded();

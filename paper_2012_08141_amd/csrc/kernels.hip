@@ -1359,17 +1359,7 @@ __global__ __launch_bounds__(64) void k_micro(GridDev g, MicroProg prog) {
 // before.  Fusion legality guarantees that no op of the node writes a
 // channel another op samples, so the staged tiles stay valid for the whole
 // node.
-constexpr int kTE = 12, kT3 = kTE * kTE * kTE;   // tile edge and voxels (block + 2 each side)
-constexpr int kTileCh = 4;                        // sampled channels staged per node
-constexpr int kTT = 512;                          // threads per workgroup: one voxel each
-
-struct TileProg {
-    MicroProg prog;
-    int32_t nt;              // staged sampled channels
-    int32_t tch[kTileCh];    // their grid channels
-    int32_t vstage;          // stage the tile of v0 .. v0 + 2 (RK3 back-traces)
-    int32_t v0;              // the velocity of every sampling op (else -1: read per voxel)
-};
+constexpr int kTC = 4;                            // tile voxels a thread loads before storing them
 
 // Tile position of a point coordinate's lower corner: the corner pair
 // (b0, b0 + 1) lies in the tile when 0 <= b0 - origin <= kTE - 2.
@@ -1384,30 +1374,47 @@ __device__ __forceinline__ float tile_sample(const float *T, const int lb[3], co
     return acc;
 }
 
-// The rare sample outside the staged tile, out of line so that its root
-// lookups do not hold registers in the staged path.
+// The rare sample outside the staged tile, inline but one corner at a time
+// (no unrolling, so it adds few registers to the staged path): the
+// arithmetic of sample_point, corner for corner.
 template <int KIND>
-__device__ __noinline__ float sample_far(const GridDev &g, const float *base, int64_t cell, int32_t slot,
-                                         float p0, float p1, float p2, int n) {
-    const float p[3] = {p0, p1, p2};
-    return sample_point<KIND>(g, base, cell, slot, p, n);
+__device__ __forceinline__ float sample_far(const GridDev &g, const float *base, int64_t cell, int32_t slot,
+                                            const float p[3], int n) {
+    float w0[3], w1[3];
+    int b0[3];
+    for (int d = 0; d < 3; ++d) {
+        const float pd = clamp_coord(p[d], n);
+        const float bd = floorf(pd);
+        const float f = pd - bd;
+        b0[d] = (int)bd;
+        w0[d] = 1.0f - f;
+        w1[d] = f;
+    }
+    float acc = 0.f;
+#pragma nounroll
+    for (int q = 0; q < 8; ++q) {
+        const int a = q >> 2, b = (q >> 1) & 1, c = q & 1;
+        const float wt = ((a ? w1[0] : w0[0]) * (b ? w1[1] : w0[1])) * (c ? w1[2] : w0[2]);
+        acc = acc + wt * sample_voxel<KIND>(g, base, cell, slot, b0[0] + a, b0[1] + b, b0[2] + c, n);
+    }
+    return acc;
 }
 
+// Range (lo, hi) of the 8 corners from (b0, b1, b2), outside the tile.
 template <int KIND>
-__device__ __noinline__ void corners_far(const GridDev &g, const float *Q, int64_t cell, int32_t slot, int b0, int b1,
-                                         int b2, int n, float &lo, float &hi) {
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b)
-            for (int c = 0; c < 2; ++c) {
-                const float x = sample_voxel<KIND>(g, Q, cell, slot, b0 + a, b1 + b, b2 + c, n);
-                if (a + b + c == 0) {
-                    lo = x;
-                    hi = x;
-                } else {
-                    lo = x < lo ? x : lo;
-                    hi = x > hi ? x : hi;
-                }
-            }
+__device__ __forceinline__ void corners_far(const GridDev &g, const float *Q, int64_t cell, int32_t slot, int b0,
+                                            int b1, int b2, int n, float &lo, float &hi) {
+#pragma nounroll
+    for (int q = 0; q < 8; ++q) {
+        const float x = sample_voxel<KIND>(g, Q, cell, slot, b0 + (q >> 2), b1 + ((q >> 1) & 1), b2 + (q & 1), n);
+        if (q == 0) {
+            lo = x;
+            hi = x;
+        } else {
+            lo = x < lo ? x : lo;
+            hi = x > hi ? x : hi;
+        }
+    }
 }
 
 // Trilinear sample of channel ch at p: from the staged tile T (origin o,
@@ -1429,7 +1436,7 @@ __device__ __forceinline__ float sample_staged(const GridDev &g, const float *T,
         w[d][1] = f;
     }
     if (in) return tile_sample(T, lb, w);
-    return sample_far<KIND>(g, base, cell, slot, p[0], p[1], p[2], n);
+    return sample_far<KIND>(g, base, cell, slot, p, n);
 }
 
 template <int KIND>
@@ -1437,6 +1444,38 @@ __device__ __forceinline__ const float *staged(const TileProg &tp, const float *
     for (int q = 0; q < tp.nt; ++q)
         if (tp.tch[q] == ch) return tiles + q * kT3;
     return nullptr;
+}
+
+// The sampling state of a back-traced point p shared by every field sampled
+// there: the 8 corner weights (w0 * w1) * w2 in corner order, and the tile
+// index of the lower corner, or -1 when a corner lies outside the tile.
+// Same clamp, floor and products as sample_staged.
+__device__ __forceinline__ int trace_tile(const float p[3], const int o[3], int n, float wt[8]) {
+    float w[3][2];
+    int lb[3];
+    bool in = true;
+    for (int d = 0; d < 3; ++d) {
+        const float pd = clamp_coord(p[d], n);
+        const float bd = floorf(pd);
+        const float f = pd - bd;
+        lb[d] = (int)bd - o[d];
+        in = in && lb[d] >= 0 && lb[d] <= kTE - 2;
+        w[d][0] = 1.0f - f;
+        w[d][1] = f;
+    }
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 2; ++c) wt[(a * 2 + b) * 2 + c] = (w[0][a] * w[1][b]) * w[2][c];
+    return in ? (lb[0] * kTE + lb[1]) * kTE + lb[2] : -1;
+}
+
+// tile_sample with the weights of trace_tile; T points at the lower corner.
+__device__ __forceinline__ float tile_sum(const float *T, const float wt[8]) {
+    float acc = 0.f;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 2; ++c) acc = acc + wt[(a * 2 + b) * 2 + c] * T[(a * kTE + b) * kTE + c];
+    return acc;
 }
 
 // LDS layout (dynamic): the nt sampled tiles, then the velocity: three
@@ -1514,46 +1553,48 @@ __global__ __launch_bounds__(kTT) void k_tile_micro(GridDev g, TileProg tp) {
         // is outside the domain or inactive, zeroed by a select), then the
         // LDS stores, so the loads overlap instead of each waiting for the
         // store after it; voxels in source order (tile_src)
+        // (in chunks of kTC voxels per thread, which bounds the registers)
         constexpr int NIT = (kT3 + kTT - 1) / kTT, NC = NT + (VS ? 3 : 0);
-        float val[NIT][NC];
-        bool ok[NIT];
-        int tpos[NIT];
 #pragma unroll
-        for (int it = 0; it < NIT; ++it) {
-            const int t = tid + it * kTT < kT3 ? tid + it * kTT : 0;
-            int src;
-            const int32_t sl = s_nb[tile_src(t, src, tpos[it])];   // -1 outside the domain or inactive
-            ok[it] = sl >= 0;
-            const int64_t o = (int64_t)(sl >= 0 ? sl : slot) * kBV + src;
+        for (int c0 = 0; c0 < NIT; c0 += kTC) {
+            float val[kTC][NC];
+            bool ok[kTC];
+            int tpos[kTC];
 #pragma unroll
-            for (int q = 0; q < NT; ++q) val[it][q] = chan(g, tp.tch[q])[o];
+            for (int u = 0; u < kTC; ++u) {
+                const int it = c0 + u;
+                if (it >= NIT) break;
+                const int t = tid + it * kTT < kT3 ? tid + it * kTT : 0;
+                int src;
+                const int32_t sl = s_nb[tile_src(t, src, tpos[u])];   // -1 outside the domain or inactive
+                ok[u] = sl >= 0;
+                const int64_t o = (int64_t)(sl >= 0 ? sl : slot) * kBV + src;
 #pragma unroll
-            for (int d = 0; d < (VS ? 3 : 0); ++d) val[it][NT + d] = chan(g, tp.v0 + d)[o];
-        }
-        constexpr int NV = kBV / kTT;
-        float vown[NV][3];
-        if (!VS && tp.v0 >= 0)
+                for (int q = 0; q < NT; ++q) val[u][q] = chan(g, tp.tch[q])[o];
 #pragma unroll
-            for (int it = 0; it < NV; ++it)
-#pragma unroll
-                for (int d = 0; d < 3; ++d) vown[it][d] = chan(g, tp.v0 + d)[(int64_t)slot * kBV + tid + it * kTT];
-#pragma unroll
-        for (int it = 0; it < NIT; ++it) {
-            if (tid + it * kTT < kT3) {
-                const int t = tpos[it];
-#pragma unroll
-                for (int q = 0; q < NT; ++q) s_t[q * kT3 + t] = ok[it] ? val[it][q] : 0.f;
-#pragma unroll
-                for (int d = 0; d < (VS ? 3 : 0); ++d) vs[d * kT3 + t] = ok[it] ? val[it][NT + d] : 0.f;
+                for (int d = 0; d < (VS ? 3 : 0); ++d) val[u][NT + d] = chan(g, tp.v0 + d)[o];
             }
+#pragma unroll
+            for (int u = 0; u < kTC; ++u) {
+                const int it = c0 + u;
+                if (it >= NIT) break;
+                if (tid + it * kTT < kT3) {
+                    const int t = tpos[u];
+#pragma unroll
+                    for (int q = 0; q < NT; ++q) s_t[q * kT3 + t] = ok[u] ? val[u][q] : 0.f;
+#pragma unroll
+                    for (int d = 0; d < (VS ? 3 : 0); ++d) vs[d * kT3 + t] = ok[u] ? val[u][NT + d] : 0.f;
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);   // the next chunk's loads after these stores
         }
         if (!VS && tp.v0 >= 0)
+            for (int vx = tid; vx < kBV; vx += kTT)
 #pragma unroll
-            for (int it = 0; it < NV; ++it)
-#pragma unroll
-                for (int d = 0; d < 3; ++d) vs[d * kBV + tid + it * kTT] = vown[it][d];
+                for (int d = 0; d < 3; ++d) vs[d * kBV + vx] = chan(g, tp.v0 + d)[(int64_t)slot * kBV + vx];
         __syncthreads();
         const int org[3] = {bi * kBS - 2, bj * kBS - 2, bk * kBS - 2};
+#pragma nounroll
         for (int vx = tid; vx < kBV; vx += kTT) {
             const int li = vx >> 6, lj = (vx >> 3) & 7, lk = vx & 7;
             const int I[3] = {bi * kBS + li, bj * kBS + lj, bk * kBS + lk};
@@ -1561,6 +1602,9 @@ __global__ __launch_bounds__(kTT) void k_tile_micro(GridDev g, TileProg tp) {
             // the back-traced point of the last (velocity, dt, rk3) used
             float pt[3] = {0.f, 0.f, 0.f}, pdt = 0.f, prk = -1.f;
             int pv = -1;
+            // its sampling state (trace_tile), shared by the fields sampled there
+            float wt[8];
+            int lbase = -1;
             for (int oi = 0; oi < tp.prog.nops; ++oi) {
                 const MicroOp &op = tp.prog.ops[oi];
                 if (op.op == AT_OP_ADVECT || op.op == AT_OP_MACCORMACK) {
@@ -1599,25 +1643,22 @@ __global__ __launch_bounds__(kTT) void k_tile_micro(GridDev g, TileProg tp) {
                         pdt = op.p;
                         prk = op.p1;
                         pv = op.ch[1];
+                        lbase = trace_tile(pt, org, n, wt);
                     }
                     const float *Q = chan(g, op.ch[0]);
                     const float *qt = staged<KIND>(tp, s_t, op.ch[0]);
+                    const bool in = qt != nullptr && lbase >= 0;
                     if (op.op == AT_OP_ADVECT) {
-                        chan(g, op.ch[2])[off] = sample_staged<KIND>(g, qt, org, Q, cell, slot, pt, n);
+                        chan(g, op.ch[2])[off] =
+                            in ? tile_sum(qt + lbase, wt) : sample_far<KIND>(g, Q, cell, slot, pt, n);
                     } else {
-                        int b0[3], lb[3];
-                        bool in = qt != nullptr;
-                        for (int d = 0; d < 3; ++d) {
-                            b0[d] = (int)floorf(clamp_coord(pt[d], n));
-                            lb[d] = b0[d] - org[d];
-                            in = in && lb[d] >= 0 && lb[d] <= kTE - 2;
-                        }
                         float lo = 0.f, hi = 0.f;
                         if (in) {
+                            const float *T = qt + lbase;
                             for (int a = 0; a < 2; ++a)
                                 for (int b = 0; b < 2; ++b)
                                     for (int c = 0; c < 2; ++c) {
-                                        const float x = qt[((lb[0] + a) * kTE + (lb[1] + b)) * kTE + (lb[2] + c)];
+                                        const float x = T[(a * kTE + b) * kTE + c];
                                         if (a + b + c == 0) {
                                             lo = x;
                                             hi = x;
@@ -1627,6 +1668,8 @@ __global__ __launch_bounds__(kTT) void k_tile_micro(GridDev g, TileProg tp) {
                                         }
                                     }
                         } else {
+                            int b0[3];
+                            for (int d = 0; d < 3; ++d) b0[d] = (int)floorf(clamp_coord(pt[d], n));
                             corners_far<KIND>(g, Q, cell, slot, b0[0], b0[1], b0[2], n, lo, hi);
                         }
                         const float dq = Q[off] - chan(g, op.ch[3])[off];
@@ -2906,7 +2949,7 @@ static void launch_tile_k(const GridDev &g, const TileProg &tp, dim3 grid, size_
 // A node for k_tile_micro: no activation check; sampling ops (ADVECT,
 // MACCORMACK) with element-wise ops it implements (COPY, AXPY, INC, FILL);
 // at most kTileCh distinct sampled channels; RK3 ops sharing one velocity.
-static bool tile_prog(const MicroProg &prog, TileProg &tp) {
+bool tile_prog(const MicroProg &prog, TileProg &tp) {
     if (prog.check || prog.verify || g_sf_kernel != 0) return false;
     tp = TileProg{};
     tp.prog = prog;
@@ -2937,18 +2980,24 @@ static bool tile_prog(const MicroProg &prog, TileProg &tp) {
     return sampling;
 }
 
+size_t tile_lds_bytes(const TileProg &tp) { return (size_t)tile_lds_floats(tp) * sizeof(float); }
+
+unsigned tile_grid_size(const GridDev &g, size_t lds) {
+    const int64_t cap = g.cap < g.ncells ? g.cap : g.ncells;
+    // as many resident workgroups as the CU's 160 KiB of LDS holds (at most 8)
+    int64_t per_cu = (int64_t)(160 * 1024) / (int64_t)(lds + 256);
+    if (per_cu > 8) per_cu = 8;
+    if (per_cu < 1) per_cu = 1;
+    int64_t wgs = 256 * per_cu;
+    if (cap < wgs) wgs = ((cap + 7) / 8) * 8;
+    return (unsigned)wgs;
+}
+
 hipError_t launch_micro(const GridDev &g, const MicroProg &prog, hipStream_t s) {
     TileProg tp;
     if (tile_prog(prog, tp)) {
-        const int64_t cap = g.cap < g.ncells ? g.cap : g.ncells;
-        const size_t lds = (size_t)tile_lds_floats(tp) * sizeof(float);
-        // as many resident workgroups as the CU's 160 KiB of LDS holds (at most 8)
-        int64_t per_cu = (int64_t)(160 * 1024) / (int64_t)(lds + 256);
-        if (per_cu > 8) per_cu = 8;
-        if (per_cu < 1) per_cu = 1;
-        int64_t wgs = 256 * per_cu;
-        if (cap < wgs) wgs = ((cap + 7) / 8) * 8;
-        const dim3 grid((unsigned)wgs);
+        const size_t lds = tile_lds_bytes(tp);
+        const dim3 grid(tile_grid_size(g, lds));
         if (g.kind == AT_ROOT_BITMASK) launch_tile_k<AT_ROOT_BITMASK>(g, tp, grid, lds, s);
         else launch_tile_k<AT_ROOT_POINTER>(g, tp, grid, lds, s);
         return hipGetLastError();

@@ -1286,10 +1286,13 @@ at_status at_variant_prepare(const at_task *tasks, int32_t ntasks, char *src, si
         op.p1 = t.param[1];
         op.p2 = t.param[2];
     }
-    if (!variant_eligible(prog))
-        return fail(AT_E_UNSUPPORTED, "variants cover copy, axpy, inc, fill and normalise chains that save memory traffic");
+    TileProg tp;
+    if (!variant_eligible(prog) && !tile_prog(prog, tp))
+        return fail(AT_E_UNSUPPORTED, "variants cover copy, axpy, inc, fill and normalise chains that save memory "
+                                      "traffic, and advection tile programs");
+    const at_grid_s *g0 = reinterpret_cast<const at_grid_s *>(tasks[0].grid);
     std::string s;
-    if (!variant_prepare(prog, s)) return fail(AT_E_UNSUPPORTED, "the variant did not compile");
+    if (!variant_prepare(prog, g0->desc.root_kind, s)) return fail(AT_E_UNSUPPORTED, "the variant did not compile");
     if (len) *len = s.size();
     if (cap > 0) {
         const size_t n = s.size() < cap - 1 ? s.size() : cap - 1;

@@ -149,3 +149,82 @@ def test_maccormack_program(opt, rk3):
     for c in range(3):
         assert np.array_equal(g.read_blocks(c, ref["cells"]), ref["q"][c]), c
     E.reset()
+
+
+# ---- the tile programs through their compiled variants (AT_OPTION_VARIANTS)
+
+def _variants(mode):
+    from paper_2012_08141_amd import engine as E
+    E.set_option(L.AT_OPTION_VARIANTS, mode)
+
+
+@pytest.mark.parametrize("root", ["bitmask", "pointer"])
+@pytest.mark.parametrize("rk3", [False, True])
+def test_compiled_tile_program_far_traces(root, rk3):
+    """A fused node of two semi-Lagrangian ops, a MacCormack correction and
+    element-wise ops, compiled for its op sequence: back-traces up to ~8
+    voxels leave the staged tile (sampled from the grid instead), reach
+    inactive and absent blocks; bit-exact against the oracle run op by op."""
+    from paper_2012_08141_amd import engine as E
+    from paper_2012_08141_amd.grid import SparseGrid
+    say("compiled tile program", root, "rk3" if rk3 else "euler")
+    n = 64
+    w = I.random_blocks(35, n, 0.3, root, channels=("q0", "q1", "v0", "v1", "v2", "f", "b"))
+    for c in ("v0", "v1", "v2"):
+        w.channels[c] = (w.channels[c] * 9.0).astype(np.float32)
+    names = {"q0": 0, "q1": 1, "v0": 2, "v1": 3, "v2": 4, "f": 5, "b": 6}
+    try:
+        E.reset()
+        _variants(2)
+        g = SparseGrid(n, 10, root, w.R ** 3 if root == "pointer" else 0)
+        o = oracle.OracleGrid(n, 10)
+        for name, vals in w.channels.items():
+            g.load_blocks(names[name], w.cells, vals)
+        o.load(w.blocks, w.channels, names)
+        extra = I.random_blocks(36, n, 0.1, root).blocks      # listed blocks holding zeros
+        g.activate(extra)
+        o.activate(extra); o.listgen()
+        loaded = E.get_option(L.AT_OPTION_VARIANTS_LOADED)
+        prog = [E.listgen(g), E.advect_sl(g, 0, 2, 7, 0.6, rk3), E.advect_sl(g, 1, 2, 8, 0.6, rk3),
+                E.maccormack(g, 0, 2, 5, 6, 9, 0.6, rk3), E.copy(g, 5, 9), E.inc(g, 6, 0.25)]
+        st = E.run_sequence(prog, E.OPT_ALL)
+        assert st["dispatches"] == 2, st          # the list generation and one fused node
+        assert E.get_option(L.AT_OPTION_VARIANTS_LOADED) > loaded
+        o.advect_sl(0, 2, 7, 0.6, rk3); o.advect_sl(1, 2, 8, 0.6, rk3)
+        o.maccormack(0, 2, 5, 6, 9, 0.6, rk3); o.copy(5, 9); o.inc(6, 0.25)
+        torch.cuda.synchronize()
+        cells = o.list()
+        assert np.array_equal(np.sort(g.list_cells()), np.sort(cells))
+        for q in range(10):
+            assert np.array_equal(g.read_blocks(q, cells), o.read_blocks(q, cells)), q
+    finally:
+        _variants(0)
+        E.reset()
+
+
+@pytest.mark.parametrize("mac", [False, True])
+def test_compiled_tile_programs_match_oracle(mac):
+    """The three-field advection and RK3 MacCormack programs on a 64^3 tube,
+    optimized, with their fused nodes compiled: bit-exact against the
+    oracle."""
+    from paper_2012_08141_amd import engine as E, programs as PR
+    say("compiled tube programs", "maccormack" if mac else "advection")
+    w = I.tube(3, n=64)
+    dt = w.params["dt"]
+    try:
+        E.reset()
+        _variants(2)
+        loaded = E.get_option(L.AT_OPTION_VARIANTS_LOADED)
+        g = PR.load_workload(w, {"q0": 0, "q1": 1, "q2": 2, "v0": 3, "v1": 4, "v2": 5}, 15 if mac else 9)
+        step = E.prepare(PR.maccormack_step(g, dt, rk3=True) if mac else PR.advection_step(g, dt))
+        for _ in range(2):
+            E.run_sequence(step, E.OPT_ALL)
+        assert E.get_option(L.AT_OPTION_VARIANTS_LOADED) > loaded
+        ref = (OP.maccormack_program(w.n, w.blocks, w.channels, dt, 2, rk3=True) if mac else
+               OP.advection_program(w.n, w.blocks, w.channels, dt, 2))
+        torch.cuda.synchronize()
+        for c in range(3):
+            assert np.array_equal(g.read_blocks(c, ref["cells"]), ref["q"][c]), c
+    finally:
+        _variants(0)
+        E.reset()
