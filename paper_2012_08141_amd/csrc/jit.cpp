@@ -355,18 +355,29 @@ extern "C" __global__ __launch_bounds__(kTT) void atst(const unsigned *bits, con
     const int lo = (int)(((long long)count * xs) / nx) + (int)(blockIdx.x / nx);
     const int hi = (int)(((long long)count * (xs + 1)) / nx);
     const int step = gridDim.x / nx;
+    static_assert(kTT == kBV, "one voxel per thread");
+    // slot of neighbour t (0 .. 26) of the block listed at e, -1 outside the
+    // domain or inactive
+    auto nb_slot = [&](int e, int t) {
+        const int2 r = *reinterpret_cast<const int2 *>(list + (long long)e * kRec);
+        const int b0 = r.x / g.R2, b1 = (r.x - b0 * g.R2) / R, b2 = r.x - b0 * g.R2 - b1 * R;
+        const int ni = b0 + t / 9 - 1, nj = b1 + (t / 3) % 3 - 1, nk = b2 + t % 3 - 1;
+        int sl = -1;
+        if (ni >= 0 && nj >= 0 && nk >= 0 && ni < R && nj < R && nk < R)
+            sl = t == 13 ? r.y : slot_of(g, ((long long)ni * R + nj) * R + nk);
+        return sl;
+    };
+    if (lo < hi && tid < 27) s_nb[tid] = nb_slot(lo, tid);
+    __syncthreads();
     for (int e = lo; e < hi; e += step) {
         const int4 rec0 = *reinterpret_cast<const int4 *>(list + (long long)e * kRec);
         const int cell = rec0.x, slot = rec0.y;
         const int bi = cell / g.R2, rr = cell - bi * g.R2, bj = rr / R, bk = rr - bj * R;
-        if (tid < 27) {
-            const int ni = bi + tid / 9 - 1, nj = bj + (tid / 3) % 3 - 1, nk = bk + tid % 3 - 1;
-            int sl = -1;
-            if (ni >= 0 && nj >= 0 && nk >= 0 && ni < R && nj < R && nk < R)
-                sl = tid == 13 ? slot : slot_of(g, ((long long)ni * R + nj) * R + nk);
-            s_nb[tid] = sl;
-        }
-        __syncthreads();
+        // the block's own velocity, loaded with the first staging chunk
+#if VOWN
+        float vo[3];
+        for (int d = 0; d < 3; ++d) vo[d] = chan(g, V0 + d)[(long long)slot * kBV + tid];
+#endif
         constexpr int NIT = (kT3 + kTT - 1) / kTT;
 #pragma unroll
         for (int c0 = 0; c0 < NIT; c0 += kTC) {
@@ -397,11 +408,14 @@ extern "C" __global__ __launch_bounds__(kTT) void atst(const unsigned *bits, con
             __builtin_amdgcn_sched_barrier(0);
         }
 #if VOWN
-        for (int vx = tid; vx < kBV; vx += kTT)
-#pragma unroll
-            for (int d = 0; d < 3; ++d) vs[d * kBV + vx] = chan(g, V0 + d)[(long long)slot * kBV + vx];
+        for (int d = 0; d < 3; ++d) vs[d * kBV + tid] = vo[d];
 #endif
         __syncthreads();
+        // the next block's neighbour slots, looked up while this block computes
+        // (the staging above was their last reader)
+        const int en = e + step;
+        int nbn = -1;
+        if (tid < 27 && en < hi) nbn = nb_slot(en, tid);
         const int org[3] = {bi * kBS - 2, bj * kBS - 2, bk * kBS - 2};
 #pragma nounroll
         for (int vx = tid; vx < kBV; vx += kTT) {
@@ -533,7 +547,7 @@ std::string generate_tile(const TileProg &tp, int kind) {
         }
     }
     s += b;
-    s += "        }\n        __syncthreads();\n    }\n}\n";
+    s += "        }\n        if (tid < 27 && en < hi) s_nb[tid] = nbn;\n        __syncthreads();\n    }\n}\n";
     return s;
 }
 
@@ -641,7 +655,7 @@ uint64_t variant_key(const MicroProg &prog) {
 
 // Key of a tile program's variant: every field of its ops (the trace
 // parameters included), the root kind and the workgroup size.
-constexpr const char *kTileRevision = "atst-1";
+constexpr const char *kTileRevision = "atst-2";
 uint64_t tile_key(const MicroProg &prog, int kind) {
     uint64_t h = 1469598103934665603ull;
     auto mix = [&](uint32_t v) {
