@@ -87,6 +87,35 @@ def test_unsupported_programs(grid):
     assert prepare([E.copy(g, 0, 1), E.copy(other, 0, 1)])[0] == L.AT_E_UNSUPPORTED
 
 
+@pytest.mark.parametrize("root", ["bitmask", "pointer"])
+def test_tile_program_variant(root):
+    """A fused advection node (two semi-Lagrangian ops sharing one Euler
+    back-trace, a MacCormack correction, element-wise ops) compiles to a tile
+    kernel with its ops written out: one back-trace computed once (the
+    MacCormack op shares it), each op's channels and constants in the code,
+    the root kind's lookup; an RK3 program stages the velocity tiles."""
+    cap = 512 if root == "pointer" else 0
+    g = SparseGrid(64, 10, root, cap, device=None)
+    prog = [E.advect_sl(g, 0, 2, 7, 0.6), E.advect_sl(g, 1, 2, 8, 0.6), E.maccormack(g, 0, 2, 5, 6, 9, 0.6),
+            E.copy(g, 5, 9), E.inc(g, 6, 0.25)]
+    st, src, n = prepare(prog)
+    assert st == L.AT_OK, L.lib().at_last_error()
+    assert n == len(src) and 'void atst(' in src
+    assert ("#define KIND %d" % (0 if root == "bitmask" else 1)) in src
+    assert src.count("trace_tile(") == 2             # the helper and one shared back-trace
+    assert "chan(g, 7)[off] = " in src and "chan(g, 8)[off] = " in src and "chan(g, 9)[off] = " in src
+    assert "chan(g, 5)[off] = chan(g, 9)[off];" in src
+    assert "chan(g, 6)[off] = chan(g, 6)[off] + 0x1p-2f;" in src
+    assert "constexpr int NT = 2;" in src and "#define VOWN 1" in src
+    # RK3 back-traces sample the velocity: three velocity tiles staged
+    st, src, _ = prepare([E.advect_sl(g, 0, 2, 7, 0.6, rk3=True), E.advect_sl(g, 1, 2, 8, 0.6, rk3=True)])
+    assert st == L.AT_OK
+    assert "constexpr int NC = 5;" in src and "#define VOWN 0" in src and src.count("sample_staged(g, vs") == 2
+    # two back-traces (different dt): two trace blocks
+    st, src, _ = prepare([E.advect_sl(g, 0, 2, 7, 0.6), E.advect_sl(g, 1, 2, 8, -0.6)])
+    assert st == L.AT_OK and src.count("trace_tile(") == 3
+
+
 def test_variant_options():
     assert E.get_option(L.AT_OPTION_VARIANTS) == 0
     for m in (1, 2, 0):
