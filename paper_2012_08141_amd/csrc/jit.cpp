@@ -419,9 +419,12 @@ extern "C" __global__ __launch_bounds__(kTT) void atst(const unsigned *bits, con
         const int org[3] = {bi * kBS - 2, bj * kBS - 2, bk * kBS - 2};
 #pragma nounroll
         for (int vx = tid; vx < kBV; vx += kTT) {
-            const int li = vx >> 6, lj = (vx >> 3) & 7, lk = vx & 7;
+            // lanes permuted within the wave's 8x8 plane (rows 0, 2, 4, 6 in the first half, 1, 3, 5, 7
+            // in the second), so that its corner reads at a common offset fall in distinct LDS banks
+            const int li = vx >> 6, lj = ((vx >> 3) & 3) * 2 + ((vx >> 5) & 1), lk = vx & 7;
+            const int vm = li * 64 + lj * 8 + lk;
             const int I[3] = {bi * kBS + li, bj * kBS + lj, bk * kBS + lk};
-            const long long off = (long long)slot * kBV + vx;
+            const long long off = (long long)slot * kBV + vm;
             (void)I;
             (void)org;
 )";
@@ -465,7 +468,7 @@ std::string generate_tile(const TileProg &tp, int kind) {
                 b += "            float " + T + "v1[3], " + T + "pt[3], " + T + "wt[8];\n";
                 b += "            for (int d = 0; d < 3; ++d) " + T + "v1[d] = ";
                 if (op.ch[1] == tp.v0 && tp.vstage) b += "vs[d * kT3 + ((li + 2) * kTE + (lj + 2)) * kTE + (lk + 2)];\n";
-                else if (op.ch[1] == tp.v0) b += "vs[d * kBV + vx];\n";
+                else if (op.ch[1] == tp.v0) b += "vs[d * kBV + vm];\n";
                 else b += "chan(g, " + std::to_string(op.ch[1]) + " + d)[off];\n";
                 if (!tp.vstage || op.p1 == 0.f) {
                     b += "            for (int d = 0; d < 3; ++d) " + T + "pt[d] = (float)I[d] - " + P + " * " + T + "v1[d];\n";
@@ -655,7 +658,7 @@ uint64_t variant_key(const MicroProg &prog) {
 
 // Key of a tile program's variant: every field of its ops (the trace
 // parameters included), the root kind and the workgroup size.
-constexpr const char *kTileRevision = "atst-2";
+constexpr const char *kTileRevision = "atst-3";
 uint64_t tile_key(const MicroProg &prog, int kind) {
     uint64_t h = 1469598103934665603ull;
     auto mix = [&](uint32_t v) {
