@@ -202,14 +202,15 @@ def test_compiled_tile_program_far_traces(root, rk3):
         E.reset()
 
 
+@pytest.mark.parametrize("root", ["bitmask", "pointer"])
 @pytest.mark.parametrize("mac", [False, True])
-def test_compiled_tile_programs_match_oracle(mac):
+def test_compiled_tile_programs_match_oracle(mac, root):
     """The three-field advection and RK3 MacCormack programs on a 64^3 tube,
     optimized, with their fused nodes compiled: bit-exact against the
-    oracle."""
+    oracle, on both root kinds."""
     from paper_2012_08141_amd import engine as E, programs as PR
-    say("compiled tube programs", "maccormack" if mac else "advection")
-    w = I.tube(3, n=64)
+    say("compiled tube programs", "maccormack" if mac else "advection", root)
+    w = I.tube(3, n=64, root_kind=root)
     dt = w.params["dt"]
     try:
         E.reset()
@@ -225,6 +226,52 @@ def test_compiled_tile_programs_match_oracle(mac):
         torch.cuda.synchronize()
         for c in range(3):
             assert np.array_equal(g.read_blocks(c, ref["cells"]), ref["q"][c]), c
+    finally:
+        _variants(0)
+        E.reset()
+
+
+def test_compiled_tile_program_background():
+    """Mode 1: the fused node runs the interpreted tile kernel while its
+    variant compiles on the worker thread, then through the variant; both
+    leave the oracle's result (the node rewrites its outputs from unchanged
+    inputs, so every run gives the same values)."""
+    import time
+    from paper_2012_08141_amd import engine as E
+    from paper_2012_08141_amd.grid import SparseGrid
+    say("compiled tile program, background")
+    n = 64
+    w = I.random_blocks(37, n, 0.3, "bitmask", channels=("q0", "q1", "v0", "v1", "v2"))
+    for c in ("v0", "v1", "v2"):
+        w.channels[c] = (w.channels[c] * 3.0).astype(np.float32)
+    names = {"q0": 0, "q1": 1, "v0": 2, "v1": 3, "v2": 4}
+    try:
+        E.reset()
+        _variants(1)
+        g = SparseGrid(n, 7, "bitmask")
+        o = oracle.OracleGrid(n, 7)
+        for name, vals in w.channels.items():
+            g.load_blocks(names[name], w.cells, vals)
+        o.load(w.blocks, w.channels, names)
+        o.listgen()
+        o.advect_sl(0, 2, 5, 0.45); o.advect_sl(1, 2, 6, 0.45)
+        cells = o.list()
+        prog = [E.listgen(g), E.advect_sl(g, 0, 2, 5, 0.45), E.advect_sl(g, 1, 2, 6, 0.45)]
+        loaded0 = E.get_option(L.AT_OPTION_VARIANTS_LOADED)
+        E.run_sequence(prog, E.OPT_ALL)
+        torch.cuda.synchronize()
+        for q in (5, 6):                                # the interpreted tile kernel's result
+            assert np.array_equal(g.read_blocks(q, cells), o.read_blocks(q, cells)), q
+        t0 = time.time()
+        while E.get_option(L.AT_OPTION_VARIANTS_LOADED) == loaded0 and time.time() - t0 < 60:
+            E.run_sequence(prog, E.OPT_ALL)
+            time.sleep(0.02)
+        assert E.get_option(L.AT_OPTION_VARIANTS_LOADED) == loaded0 + 1, "variant never loaded"
+        g.load_blocks(5, w.cells, np.zeros((len(w.cells), 512), np.float32))
+        E.run_sequence(prog, E.OPT_ALL)                 # through the variant
+        torch.cuda.synchronize()
+        for q in range(7):
+            assert np.array_equal(g.read_blocks(q, cells), o.read_blocks(q, cells)), q
     finally:
         _variants(0)
         E.reset()
