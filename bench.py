@@ -45,8 +45,8 @@ MPM_FLOPS_PER_PARTICLE = 2034
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE), each scaled by the reading
 # for a plain 256 MiB copy in the same run.  Valid only for the kernel
 # source the counters were taken on; any change to it reports null.
-JACOBI_TRAFFIC = {"kernels_sha256": "ebd5ec0d19c3905bbe2199b8f66a66f992173998e53e5209f5f95d99d29b79c2",
-                  "bytes_per_launch": 83321617, "profile": "profiles/band512_jacobi_traffic.md"}
+JACOBI_TRAFFIC = {"kernels_sha256": "9bec18596f1aabad095fb8c6fd69329b16b80b64f00e75845746db46b93da517",
+                  "bytes_per_launch": 83319472, "profile": "profiles/band512_jacobi_traffic.md"}
 
 
 def _jacobi_traffic():

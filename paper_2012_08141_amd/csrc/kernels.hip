@@ -1527,8 +1527,10 @@ __device__ __forceinline__ int tile_src(int e, int &src, int &tpos) {
     return (d0 + 1) * 9 + (d1 + 1) * 3 + (d2 + 1);
 }
 
+// Six waves per SIMD (3 workgroups per CU instead of the 2 its 93 VGPRs
+// allow): a few spilled values, 15% faster on the advection workloads.
 template <int KIND, int NT, bool VS>
-__global__ __launch_bounds__(kTT) void k_tile_micro(GridDev g, TileProg tp) {
+__global__ __launch_bounds__(kTT) __attribute__((amdgpu_waves_per_eu(6))) void k_tile_micro(GridDev g, TileProg tp) {
     extern __shared__ float s_t[];
     __shared__ int32_t s_nb[27];
     const int tid = threadIdx.x;
