@@ -240,7 +240,10 @@ def test_particle_program_reduced(opt, binned, reuse, bin_reuse):
     else:
         assert st["dispatches"] == st["tasks_launched"] + _binning_extra(20, reuse)
     ref = OP.particle_program(p.n, p.x, p.v, p.m, 20, p.params["dt"], "f32")
-    sx, sv = 0.1 * np.abs(ref["x"]).max(), 0.1 * np.abs(ref["v"]).max()     # 0.1 |o|_inf
+    # positions at 0.1 |o|_inf; velocities at the scale of the scattered
+    # terms (the particles' own speeds), which sets the rounding of the
+    # momentum sums that fp32 atomics add in a varying order
+    sx, sv = 0.1 * np.abs(ref["x"]).max(), 0.1 * np.abs(p.v).max()
     close_state(x.cpu().numpy(), ref["x"], "x", sx)
     close_state(v.cpu().numpy(), ref["v"], "v", sv)
     for gi in (0, 1):
@@ -262,7 +265,7 @@ def test_particle_program_bin_reuse_with_drift(reuse, root, bin_reuse):
     p = dataclasses.replace(p0, v=(p0.v * 10).astype(np.float32), params=dict(p0.params, dt=2e-3), root_kind=root)
     steps = 12
     ref = OP.particle_program(p.n, p.x, p.v, p.m, steps, p.params["dt"], "f32")
-    sx, sv = 0.1 * np.abs(ref["x"]).max(), 0.1 * np.abs(ref["v"]).max()     # 0.1 |o|_inf
+    sx, sv = 0.1 * np.abs(ref["x"]).max(), 0.1 * np.abs(p.v).max()     # as in the reduced program
     out = {}
     for k in (reuse, 0):
         bin_reuse(k)
