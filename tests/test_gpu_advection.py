@@ -275,3 +275,53 @@ def test_compiled_tile_program_background():
     finally:
         _variants(0)
         E.reset()
+
+
+@pytest.mark.parametrize("case", ["empty", "corner-block", "ragged"])
+def test_compiled_tile_program_edge_cases(case):
+    """Compiled tile programs on an empty list (no block: nothing written),
+    on one block at the domain's corner (most of its halo outside the
+    domain), and on a 40^3-voxel domain (R = 5, not a multiple of the
+    workgroup slicing); bit-exact against the oracle."""
+    from paper_2012_08141_amd import engine as E
+    from paper_2012_08141_amd.grid import SparseGrid
+    say("compiled tile program edge case", case)
+    n = 40 if case == "ragged" else 32
+    if case == "empty":
+        blocks = np.zeros((0, 3), np.int32)
+    elif case == "corner-block":
+        blocks = np.array([[0, 0, 0]], np.int32)
+    else:
+        blocks = I.random_blocks(38, n, 0.5, "bitmask").blocks
+    rng = np.random.default_rng(7)
+    nb = len(blocks)
+    chans = {k: rng.uniform(-1, 1, (nb, 512)).astype(np.float32) for k in ("q0", "q1")}
+    for k in ("v0", "v1", "v2"):
+        chans[k] = rng.uniform(-4, 4, (nb, 512)).astype(np.float32)
+    names = {"q0": 0, "q1": 1, "v0": 2, "v1": 3, "v2": 4}
+    try:
+        E.reset()
+        _variants(2)
+        g = SparseGrid(n, 8, "bitmask")
+        o = oracle.OracleGrid(n, 8)
+        if nb:
+            g.activate(blocks)
+            cells = ((blocks[:, 0].astype(np.int64) * (n // 8) + blocks[:, 1]) * (n // 8) + blocks[:, 2])
+            for k, q in names.items():
+                g.load_blocks(q, cells, chans[k])
+            o.load(blocks, chans, names)
+        o.listgen()
+        prog = [E.listgen(g), E.advect_sl(g, 0, 2, 5, 0.7, True), E.advect_sl(g, 1, 2, 6, 0.7, True),
+                E.maccormack(g, 0, 2, 5, 1, 7, 0.7, True)]
+        st = E.run_sequence(prog, E.OPT_ALL)
+        assert st["dispatches"] == 2, st
+        o.advect_sl(0, 2, 5, 0.7, True); o.advect_sl(1, 2, 6, 0.7, True); o.maccormack(0, 2, 5, 1, 7, 0.7, True)
+        torch.cuda.synchronize()
+        cl = o.list()
+        assert np.array_equal(np.sort(g.list_cells()), np.sort(cl))
+        for q in range(8):
+            assert np.array_equal(g.read_blocks(q, cl), o.read_blocks(q, cl)), q
+        assert g.device_status() == 0
+    finally:
+        _variants(0)
+        E.reset()
