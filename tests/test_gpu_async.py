@@ -2,8 +2,8 @@
 optimizer and launcher threads give the same device results, bit for bit,
 and the same counters as the synchronous engine -- on the narrow-band
 Jacobi (one window per iteration), the multigrid V-cycle (activating
-restrictions across levels) and the MacCormack step (fused sampling nodes),
-all deterministic."""
+restrictions across levels) and the MacCormack step (fused sampling nodes,
+interpreted or compiled), all deterministic."""
 import numpy as np
 import pytest
 
@@ -22,14 +22,20 @@ def engine():
     from paper_2012_08141_amd import engine as E
     E.reset()
     yield
+    from paper_2012_08141_amd import _lib as L
     E.set_async(False)
+    E.set_option(L.AT_OPTION_VARIANTS, 0)
     E.reset()
 
 
 def _run(kind, async_on):
     from paper_2012_08141_amd import engine as E
     from paper_2012_08141_amd import programs as PR
+    from paper_2012_08141_amd import _lib as L
     E.reset()
+    # the compiled form: the fused sampling nodes run their compiled tile
+    # programs, compiled and loaded on the launching thread
+    E.set_option(L.AT_OPTION_VARIANTS, 2 if kind == "maccormack-compiled" else 0)
     E.set_async(async_on)
     tot = {"dispatches": 0, "tasks_launched": 0}
     if kind == "jacobi":
@@ -58,10 +64,11 @@ def _run(kind, async_on):
     torch.cuda.synchronize()
     res = [o.clone() for o in outs()]
     E.set_async(False)
+    E.set_option(L.AT_OPTION_VARIANTS, 0)
     return res, tot
 
 
-@pytest.mark.parametrize("kind", ["jacobi", "multigrid", "maccormack"])
+@pytest.mark.parametrize("kind", ["jacobi", "multigrid", "maccormack", "maccormack-compiled"])
 def test_async_equals_sync(kind):
     say("async", kind)
     a, ta = _run(kind, True)
