@@ -116,6 +116,23 @@ def test_tile_program_variant(root):
     assert st == L.AT_OK and src.count("trace_tile(") == 3
 
 
+def test_tile_program_limits():
+    """Which fused sampling nodes get a tile program: Euler back-traces by
+    different velocities read each op's velocity at the voxel (no velocity
+    staged); RK3 back-traces must share one velocity (its tiles are staged);
+    at most four sampled fields are staged."""
+    g = SparseGrid(64, 16, "bitmask", device=None)
+    st, src, _ = prepare([E.advect_sl(g, 0, 2, 7, 0.5), E.advect_sl(g, 1, 10, 8, 0.5)])
+    assert st == L.AT_OK and "#define V0 -1" in src and "#define VOWN 0" in src
+    assert "chan(g, 10 + d)[off]" in src and "chan(g, 2 + d)[off]" in src
+    st, _, _ = prepare([E.advect_sl(g, 0, 2, 7, 0.5, rk3=True), E.advect_sl(g, 1, 10, 8, 0.5, rk3=True)])
+    assert st == L.AT_E_UNSUPPORTED
+    four = [E.advect_sl(g, q, 5, 8 + q, 0.5) for q in range(4)]
+    assert prepare(four)[0] == L.AT_OK
+    five = four + [E.advect_sl(g, 4, 5, 12, 0.5)]
+    assert prepare(five)[0] == L.AT_E_UNSUPPORTED
+
+
 def test_variant_options():
     assert E.get_option(L.AT_OPTION_VARIANTS) == 0
     for m in (1, 2, 0):
