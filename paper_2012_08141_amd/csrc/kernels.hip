@@ -734,11 +734,11 @@ struct BlkL {
     float4 e0, e1;       // elementwise input
 };
 
+// Loads of one block from its record: a = {cell, slot, i-1, i+1}, b = {j-1,
+// j+1, k-1, k+1} (neighbour slots, -1 when absent); slot must be valid.
 template <bool HAS_E>
-__device__ __forceinline__ void fetch_blk_lds(const StencilCh &c, const int32_t *__restrict__ recs, int e, int lane,
+__device__ __forceinline__ void fetch_rec_lds(const StencilCh &c, const int4 a, const int4 b, int lane,
                                               BlkL<HAS_E> &B) {
-    const int4 *r = reinterpret_cast<const int4 *>(recs + (int64_t)e * kRec);
-    const int4 a = r[0], b = r[1];
     const int32_t slot = a.y;
     B.slot = slot;
     const int64_t own = (int64_t)slot * kBV;
@@ -761,6 +761,13 @@ __device__ __forceinline__ void fetch_blk_lds(const StencilCh &c, const int32_t 
         B.e0 = *reinterpret_cast<const float4 *>(c.ein + own + lane * 8);
         B.e1 = *reinterpret_cast<const float4 *>(c.ein + own + lane * 8 + 4);
     }
+}
+
+template <bool HAS_E>
+__device__ __forceinline__ void fetch_blk_lds(const StencilCh &c, const int32_t *__restrict__ recs, int e, int lane,
+                                              BlkL<HAS_E> &B) {
+    const int4 *r = reinterpret_cast<const int4 *>(recs + (int64_t)e * kRec);
+    fetch_rec_lds<HAS_E>(c, r[0], r[1], lane, B);
 }
 
 template <int OP, bool CHECK, int KIND>
@@ -1869,6 +1876,79 @@ __global__ __launch_bounds__(64 * W) void k_batch(BatchDev d, int it) {
             r[q] = tq * sixth;
         }
         store8(d.xn + off, r);
+    }
+}
+
+// The batched Jacobi sweep in the form of k_stencil_lds: each wavefront
+// keeps its own LDS rows and faces, loads the next entry's block while it
+// computes this one (records, window and slots included), and stages the
+// block's rows and lateral faces through LDS.  Same arithmetic and order as
+// k_batch, so the same results bit for bit.
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_batch_lds(BatchDev d, int it) {
+    __shared__ float4 s_own_w[W][2][64];
+    __shared__ float4 s_face_w[W][2][4][8];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    float4 (*s_own)[64] = s_own_w[wv];
+    float4 (*s_face)[4][8] = s_face_w[wv];
+    const int li = lane >> 3, lj = lane & 7;
+    const int f = lane >> 4, frow = (lane & 15) >> 1, fh = lane & 1;
+    const float4 *src[4] = {li > 0 ? &s_own[0][lane - 8] : &s_face[0][0][lj],
+                            li < 7 ? &s_own[0][lane + 8] : &s_face[0][1][lj],
+                            lj > 0 ? &s_own[0][lane - 1] : &s_face[0][2][li],
+                            lj < 7 ? &s_own[0][lane + 1] : &s_face[0][3][li]};
+    const int hstride[4] = {li > 0 ? 64 : 32, li < 7 ? 64 : 32, lj > 0 ? 64 : 32, lj < 7 ? 64 : 32};
+    const int64_t now = *d.clock + it;
+    const ListRange lr = wave_range<W>(*d.count);
+    if (lr.lo >= lr.hi) return;
+    StencilCh c{};
+    c.tin[0] = d.x;
+    c.ein = d.b;
+    c.out0 = d.xn;
+    // entry e's block (a dummy valid slot when it has none), and whether its
+    // grid sweeps at this iteration
+    auto fetch = [&](int e, BlkL<true> &B) {
+        const int4 r0 = d.rec[2 * e], r1 = d.rec[2 * e + 1];
+        const int gid = r0.y;
+        bool on = r0.x >= 0 && gid >= 0 && gid < d.max_grids;
+        if (on) on = now >= d.window[2 * gid] && now < d.window[2 * gid + 1];
+        fetch_rec_lds<true>(c, make_int4(0, r0.x >= 0 ? r0.x : 0, r0.z, r0.w), r1, lane, B);
+        return on;
+    };
+    BlkL<true> cur, nxt;
+    bool on_cur = fetch(__builtin_amdgcn_readfirstlane(lr.lo), cur);
+    for (int e = lr.lo; e < lr.hi; e += lr.step) {
+        const int en = e + lr.step < lr.hi ? e + lr.step : e;
+        const bool on_nxt = fetch(__builtin_amdgcn_readfirstlane(en), nxt);
+        if (on_cur) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");   // the last block's reads come first
+            s_own[0][lane] = cur.c0;
+            s_own[1][lane] = cur.c1;
+            s_face[fh][f][frow] = cur.face;
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");   // then this block's writes
+            Row X;
+            put8(X.c, cur.c0, cur.c1);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) put8(X.f[q], src[q][0], src[q][hstride[q]]);
+            X.f[4][0] = cur.km;
+            X.f[5][7] = cur.kp;
+#pragma unroll
+            for (int q = 1; q < 8; ++q) X.f[4][q] = X.c[q - 1];
+#pragma unroll
+            for (int q = 0; q < 7; ++q) X.f[5][q] = X.c[q + 1];
+            float bb[8], r0[8];
+            put8(bb, cur.e0, cur.e1);
+            const float sixth = 0x1.555556p-3f;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const float sum = nbsum(X, q);
+                const float tq = sum + bb[q];
+                r0[q] = tq * sixth;
+            }
+            store8(d.xn + (int64_t)cur.slot * kBV + lane * 8, r0);
+        }
+        cur = nxt;
+        on_cur = on_nxt;
     }
 }
 
@@ -3195,13 +3275,13 @@ hipError_t launch_batch_jacobi(const BatchDev &d, int iters, int workgroups, hip
     const int W = g_batch_waves;
     for (int it = 0; it < iters; ++it) {
         if (W == 4) {
-            hipLaunchKernelGGL((k_batch<false, 4>), dim3(wgs), dim3(256), 0, s, d, it);
+            hipLaunchKernelGGL((k_batch_lds<4>), dim3(wgs), dim3(256), 0, s, d, it);
             hipLaunchKernelGGL((k_batch<true, 4>), dim3(wgs), dim3(256), 0, s, d, it);
         } else if (W == 2) {
-            hipLaunchKernelGGL((k_batch<false, 2>), dim3(wgs), dim3(128), 0, s, d, it);
+            hipLaunchKernelGGL((k_batch_lds<2>), dim3(wgs), dim3(128), 0, s, d, it);
             hipLaunchKernelGGL((k_batch<true, 2>), dim3(wgs), dim3(128), 0, s, d, it);
         } else {
-            hipLaunchKernelGGL((k_batch<false, 1>), dim3(wgs), dim3(64), 0, s, d, it);
+            hipLaunchKernelGGL((k_batch_lds<1>), dim3(wgs), dim3(64), 0, s, d, it);
             hipLaunchKernelGGL((k_batch<true, 1>), dim3(wgs), dim3(64), 0, s, d, it);
         }
     }
