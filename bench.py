@@ -45,8 +45,8 @@ MPM_FLOPS_PER_PARTICLE = 2034
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE), each scaled by the reading
 # for a plain 256 MiB copy in the same run.  Valid only for the kernel
 # source the counters were taken on; any change to it reports null.
-JACOBI_TRAFFIC = {"kernels_sha256": "9bec18596f1aabad095fb8c6fd69329b16b80b64f00e75845746db46b93da517",
-                  "bytes_per_launch": 83319472, "profile": "profiles/band512_jacobi_traffic.md"}
+JACOBI_TRAFFIC = {"kernels_sha256": "c2da6a0189683806bfd4205bec60e123079c87de05a0bd77ddf2dc2a25a3cc30",
+                  "bytes_per_launch": 83315400, "profile": "profiles/band512_jacobi_traffic.md"}
 
 
 def _jacobi_traffic():
@@ -574,7 +574,7 @@ def bench_serving(args, torch):
     vox = nb * 512
     out["closed_batch_iteration_all_resident_s"] = tune["s_per_iter"]
     out["roofline"] = roofline(20.0 * vox / s_iter / 1e9,
-                               "one batched Jacobi iteration (k_batch jacobi + copy launches, 20 B per active voxel) "
+                               "one batched Jacobi iteration (k_batch_lds jacobi + k_batch copy launches, 20 B per active voxel) "
                                "over the %d requests (%d blocks) the %d MiB budget admits first; mean per iteration "
                                "over 20 replays of the captured %d-iteration graph between two HIP events; the "
                                "working set is near the 256 MiB last-level cache" % (len(first), nb, args.budget_mib, K),
