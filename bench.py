@@ -822,7 +822,7 @@ def bench_multigrid(args, torch):
     out["kernels"] = {"fine_jacobi_tail_us": t_fused * 1e6, "launches_per_group": lpg}
     if lpg == 1:
         out["roofline"] = roofline(12.0 * w.active_voxels / t_fused / 1e9,
-                                   "k_stencil_tail (fine-level jacobi fused with t -= x; 12 B per fine active voxel), "
+                                   "k_stencil_tail_lds (fine-level jacobi fused with t -= x; 12 B per fine active voxel), "
                                    "mean of 100 back-to-back launches between two HIP events on the launch stream, "
                                    "median of 3 windows", 12 * w.active_voxels)
     del lv, g0

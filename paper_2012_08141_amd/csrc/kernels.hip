@@ -841,6 +841,69 @@ __global__ __launch_bounds__(64) void k_stencil_lds(GridDev g, const int32_t *__
     }
 }
 
+// The element-wise tail of a fused stencil node, applied per voxel in
+// program order to the lane's 8 voxels: the stencil's output (out_ch) stays
+// in r0 until the caller stores it, the centre row of its first input
+// (in_ch) is cin, other channels are read and written at the voxel.
+__device__ __forceinline__ void apply_tail(const GridDev &g, const MicroProg &tail, int64_t off, int out_ch, int in_ch,
+                                           float r0[8], float cin[8]) {
+    auto get = [&](int ch, float v[8]) {
+        if (ch == out_ch) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = r0[q];
+        } else if (ch == in_ch) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = cin[q];
+        } else {
+            const float *src = chan(g, ch) + off;
+            put8(v, reinterpret_cast<const float4 *>(src)[0], reinterpret_cast<const float4 *>(src)[1]);
+        }
+    };
+    auto set = [&](int ch, const float v[8]) {
+        if (ch == out_ch) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) r0[q] = v[q];
+        } else {
+            store8(chan(g, ch) + off, v);
+            if (ch == in_ch) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) cin[q] = v[q];
+            }
+        }
+    };
+    for (int o = 0; o < tail.nops; ++o) {
+        const MicroOp &op = tail.ops[o];
+        float y[8], x[8];
+        switch (op.op) {
+        case AT_OP_AXPY:
+            get(op.ch[0], y);
+            get(op.ch[1], x);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) y[q] = y[q] + op.p * x[q];
+            set(op.ch[0], y);
+            break;
+        case AT_OP_INC:
+            get(op.ch[0], y);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) y[q] = y[q] + op.p;
+            set(op.ch[0], y);
+            break;
+        case AT_OP_COPY:
+            get(op.ch[1], y);
+            set(op.ch[0], y);
+            break;
+        case AT_OP_FILL:
+#pragma unroll
+            for (int q = 0; q < 8; ++q) y[q] = op.p;
+            for (int k = 0; k < 7; ++k)
+                if (op.ch[k] >= 0 && ((op.keep >> k) & 1u)) set(op.ch[k], y);
+            break;
+        default:
+            break;
+        }
+    }
+}
+
 // A fused struct-for whose first member is a single-output stencil op
 // (LAP_UPDATE, JACOBI, DIFFUSE) followed by element-wise ops (AXPY, INC,
 // COPY, FILL): the stencil runs pipelined as above and the element-wise ops
@@ -865,61 +928,76 @@ __global__ __launch_bounds__(64) void k_stencil_tail(GridDev g, const int32_t *_
         const int64_t off = (int64_t)cur.slot * kBV + lane * 8;
         float r0[8], r1[8], cin[8];
         pipe_compute<OP, NT, HAS_E>(cur, p, r0, r1, cin);
-        auto get = [&](int ch, float v[8]) {
-            if (ch == out_ch) {
+        apply_tail(g, tail, off, out_ch, in_ch, r0, cin);
+        store8(c.out0 + off, r0);
+        cur = nxt;
+    }
+}
+
+// The same for a Jacobi or lap_update head in the form of k_stencil_lds:
+// the block's rows and lateral faces staged through LDS, the next block's
+// loads issued before this block computes.  Same arithmetic, same results.
+template <int OP>
+__global__ __launch_bounds__(64) void k_stencil_tail_lds(GridDev g, const int32_t *__restrict__ recs, StencilCh c,
+                                                         float p, MicroProg tail, int out_ch, int in_ch) {
+    constexpr bool HAS_E = OP == AT_OP_JACOBI;
+    __shared__ float4 s_own[2][64];
+    __shared__ float4 s_face[2][4][8];
+    const int lane = threadIdx.x;
+    const int li = lane >> 3, lj = lane & 7;
+    const int f = lane >> 4, frow = (lane & 15) >> 1, fh = lane & 1;
+    const float4 *src[4] = {li > 0 ? &s_own[0][lane - 8] : &s_face[0][0][lj],
+                            li < 7 ? &s_own[0][lane + 8] : &s_face[0][1][lj],
+                            lj > 0 ? &s_own[0][lane - 1] : &s_face[0][2][li],
+                            lj < 7 ? &s_own[0][lane + 1] : &s_face[0][3][li]};
+    const int hstride[4] = {li > 0 ? 64 : 32, li < 7 ? 64 : 32, lj > 0 ? 64 : 32, lj < 7 ? 64 : 32};
+    const ListRange lr = list_range(g.hdr[HDR_COUNT]);
+    if (lr.lo >= lr.hi) return;
+    BlkL<HAS_E> cur, nxt;
+    fetch_blk_lds<HAS_E>(c, recs, __builtin_amdgcn_readfirstlane(lr.lo), lane, cur);
+    for (int e = lr.lo; e < lr.hi; e += lr.step) {
+        const int en = e + lr.step < lr.hi ? e + lr.step : e;
+        fetch_blk_lds<HAS_E>(c, recs, __builtin_amdgcn_readfirstlane(en), lane, nxt);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");   // the last block's reads come first
+        s_own[0][lane] = cur.c0;
+        s_own[1][lane] = cur.c1;
+        s_face[fh][f][frow] = cur.face;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");   // then this block's writes
+        Row X;
+        put8(X.c, cur.c0, cur.c1);
 #pragma unroll
-                for (int q = 0; q < 8; ++q) v[q] = r0[q];
-            } else if (ch == in_ch) {
+        for (int d = 0; d < 4; ++d) put8(X.f[d], src[d][0], src[d][hstride[d]]);
+        X.f[4][0] = cur.km;
+        X.f[5][7] = cur.kp;
 #pragma unroll
-                for (int q = 0; q < 8; ++q) v[q] = cin[q];
-            } else {
-                const float *src = chan(g, ch) + off;
-                put8(v, reinterpret_cast<const float4 *>(src)[0], reinterpret_cast<const float4 *>(src)[1]);
+        for (int q = 1; q < 8; ++q) X.f[4][q] = X.c[q - 1];
+#pragma unroll
+        for (int q = 0; q < 7; ++q) X.f[5][q] = X.c[q + 1];
+        const int64_t off = (int64_t)cur.slot * kBV + lane * 8;
+        float r0[8], cin[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) cin[q] = X.c[q];
+        if (OP == AT_OP_LAP_UPDATE) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const float sum = nbsum(X, q);
+                const float six_a = 6.0f * X.c[q];
+                const float d = sum - six_a;
+                const float tq = p * d;
+                r0[q] = X.c[q] + tq;
             }
-        };
-        auto set = [&](int ch, const float v[8]) {
-            if (ch == out_ch) {
+        } else {
+            float bb[8];
+            put8(bb, cur.e0, cur.e1);
+            const float sixth = 0x1.555556p-3f;
 #pragma unroll
-                for (int q = 0; q < 8; ++q) r0[q] = v[q];
-            } else {
-                store8(chan(g, ch) + off, v);
-                if (ch == in_ch) {
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) cin[q] = v[q];
-                }
-            }
-        };
-        for (int o = 0; o < tail.nops; ++o) {
-            const MicroOp &op = tail.ops[o];
-            float y[8], x[8];
-            switch (op.op) {
-            case AT_OP_AXPY:
-                get(op.ch[0], y);
-                get(op.ch[1], x);
-#pragma unroll
-                for (int q = 0; q < 8; ++q) y[q] = y[q] + op.p * x[q];
-                set(op.ch[0], y);
-                break;
-            case AT_OP_INC:
-                get(op.ch[0], y);
-#pragma unroll
-                for (int q = 0; q < 8; ++q) y[q] = y[q] + op.p;
-                set(op.ch[0], y);
-                break;
-            case AT_OP_COPY:
-                get(op.ch[1], y);
-                set(op.ch[0], y);
-                break;
-            case AT_OP_FILL:
-#pragma unroll
-                for (int q = 0; q < 8; ++q) y[q] = op.p;
-                for (int k = 0; k < 7; ++k)
-                    if (op.ch[k] >= 0 && ((op.keep >> k) & 1u)) set(op.ch[k], y);
-                break;
-            default:
-                break;
+            for (int q = 0; q < 8; ++q) {
+                const float sum = nbsum(X, q);
+                const float tq = sum + bb[q];
+                r0[q] = tq * sixth;
             }
         }
+        apply_tail(g, tail, off, out_ch, in_ch, r0, cin);
         store8(c.out0 + off, r0);
         cur = nxt;
     }
@@ -2981,6 +3059,13 @@ template <int OP>
 static void launch_tail_k(const GridDev &g, const StencilCh &c, float p, const MicroProg &tail, int out_ch,
                           int in_ch, hipStream_t s) {
     const dim3 grid(wave_grid_size(g, true)), block(64);
+    if constexpr (OP == AT_OP_JACOBI || OP == AT_OP_LAP_UPDATE) {
+        if (kStencilLds) {
+            hipLaunchKernelGGL((k_stencil_tail_lds<OP>), grid, block, 0, s, g, (const int32_t *)g.list, c, p, tail,
+                               out_ch, in_ch);
+            return;
+        }
+    }
     if (g.kind == AT_ROOT_BITMASK)
         hipLaunchKernelGGL((k_stencil_tail<OP, AT_ROOT_BITMASK>), grid, block, 0, s, g, (const int32_t *)g.list, c, p,
                            tail, out_ch, in_ch);
