@@ -45,8 +45,8 @@ MPM_FLOPS_PER_PARTICLE = 2034
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE), each scaled by the reading
 # for a plain 256 MiB copy in the same run.  Valid only for the kernel
 # source the counters were taken on; any change to it reports null.
-JACOBI_TRAFFIC = {"kernels_sha256": "c2da6a0189683806bfd4205bec60e123079c87de05a0bd77ddf2dc2a25a3cc30",
-                  "bytes_per_launch": 83315400, "profile": "profiles/band512_jacobi_traffic.md"}
+JACOBI_TRAFFIC = {"kernels_sha256": "11365eaf2afa2c621385c717f524a0962c2d0f848257d1f4f2934948910f1bf9",
+                  "bytes_per_launch": 83327291, "profile": "profiles/band512_jacobi_traffic.md"}
 
 
 def _jacobi_traffic():
